@@ -103,10 +103,25 @@ def dipole(comp, X, Y, Z, dx, dy, dz):
 COMPONENTS = ("xx", "yy", "zz", "xy", "xz", "yz")
 
 
+_PARITY_AXES = {"xx": (), "yy": (), "zz": (), "xy": (0, 1), "xz": (0, 2),
+                "yz": (1, 2)}
+
+
 def demag_tensor(comp, X, Y, Z, dx, dy, dz, rc_cells=30.0):
-    """N_comp at displacements (X, Y, Z) [m]: Newell inside rc, dipole outside."""
+    """N_comp at displacements (X, Y, Z) [m]: Newell inside rc, dipole outside.
+
+    Each component has a definite parity in every coordinate (diagonal terms
+    even, N_ab odd in a and b), so it is evaluated at (|X|, |Y|, |Z|) and
+    multiplied by the parity sign.  This is an identity of the tensor; it
+    makes the float64 values exactly symmetric, which the near-field
+    cancellation would otherwise break at the 1e-7 level.
+    """
     X, Y, Z = np.broadcast_arrays(*(np.asarray(v, dtype=np.float64)
                                     for v in (X, Y, Z)))
+    sign = np.ones(X.shape)
+    for ax in _PARITY_AXES[comp]:
+        sign = sign * np.sign((X, Y, Z)[ax])
+    X, Y, Z = np.abs(X), np.abs(Y), np.abs(Z)
     rmax = rc_cells * max(dx, dy, dz)
     far = (X * X + Y * Y + Z * Z) >= rmax * rmax
     out = np.zeros(X.shape)
@@ -115,7 +130,7 @@ def demag_tensor(comp, X, Y, Z, dx, dy, dz, rc_cells=30.0):
         out[near] = newell_exact(comp, X[near], Y[near], Z[near], dx, dy, dz)
     if far.any():
         out[far] = dipole(comp, X[far], Y[far], Z[far], dx, dy, dz)
-    return out
+    return sign * out
 
 
 def tensor_matrix(X, Y, Z, dx, dy, dz, rc_cells=30.0):
