@@ -1,0 +1,174 @@
+"""Benchmark: cell-updates/s of the two-film hot path on one MI355X.
+
+One step = one classic RK4 step of both films (4 effective-field
+evaluations: x transforms, y pass with the kernel multiplication, fused row
+kernel with the spline, local terms, LLG stage and force) plus the slider's
+equation of motion.  Workload: the stick-slip films, 2 x 512 x 128 cells of
+2 nm, float32, spring drive, seeded synthetic +/-z domain states.
+
+Prints one JSON line (see README of the contract in the design doc).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "cell-updates/s per LLG step; surrogate+batched vs plain at ≤1e-3 H error"
+
+# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# (profiles/), keyed by the source hash of the kernels it was taken on.
+TRAFFIC = {}
+
+
+def kernel_bytes(desc, lx, ly):
+    """Algorithmic bytes per launch of each kernel (float32, direct mode).
+
+    x transform: read m, write the row spectra of the ny non-zero rows.
+    y pass:      read those spectra and each kernel channel once, write every
+                 output row of every channel.
+    row kernel:  read every output row, m of the stage, m at the step start,
+                 the RK accumulator (3 of 4 stages), write the next stage m and
+                 the accumulator (3 of 4 stages).
+    """
+    r = 4 if desc.precision == 32 else 8
+    c = 2 * r
+    nf, nx, ny = desc.n_films, desc.nx, desc.ny
+    kx = lx // 2 + 1
+    kyh = ly // 2 + 1
+    cells = nf * nx * ny
+    spec1 = 3 * nf * ny * kx * c
+    rows = 3 * nf * ny
+    nkern = 4
+    if nf == 2:
+        rows += 3 * (ny + 2) + 2 * ny + 3 * ny
+        nkern += 6 + 3 + 3
+    spec2 = rows * kx * c
+    kern = nkern * kx * kyh * r
+    return {
+        "row_fwd": 3 * cells * r + spec1,
+        "col": spec1 + kern + spec2,
+        "row_stage": spec2 + cells * 3 * r * (1 + 1 + 0.75 + 1 + 0.75),
+    }, cells
+
+
+def cpu_baseline(cfg, m, budget_s=12.0):
+    """The float64 oracle, as it stands, on a bounded sample of the workload."""
+    from threadpoolctl import threadpool_limits
+    from oracle.sim import System
+    d = cfg["desc"]
+    with threadpool_limits(limits=1):
+        s = System(d, cfg["drive"], m)
+        s.field_terms()            # build the kernel windows outside the clock
+        t0 = time.perf_counter()
+        n = 0
+        while n < 2 or (time.perf_counter() - t0 < budget_s and n < 50):
+            s.step(cfg["dt"])
+            n += 1
+        dt = time.perf_counter() - t0
+    return {"value": d.cells * n / dt, "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{n} RK4 steps of the same 2x{d.nx}x{d.ny} workload, float64 "
+                      f"NumPy/SciPy oracle, 1 thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--config", default="stickslip")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; the multi-GPU sharding "
+              "is described in DESIGN.md and not implemented", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1801_04181_amd as mmv
+    from workloads import get_config, initial_state
+
+    cfg = get_config(args.config)
+    d, drv, dt = cfg["desc"], cfg["drive"], cfg["dt"]
+    m = initial_state(cfg)
+    print(f"bench: {args.config} 2x{d.nx}x{d.ny} fp{d.precision}, warmup {args.warmup}, "
+          f"steps {args.steps}", file=sys.stderr, flush=True)
+    mesh = mmv.Mesh(d, drv, m)
+    lx, ly, _ = mesh.fft_lengths()
+    per_launch, cells = kernel_bytes(d, lx, ly)
+    stream = mesh.stream
+
+    mesh.step(dt, args.warmup)
+    torch.cuda.synchronize()
+
+    # which kernel dominates: a short timed pass per kernel (outside the clock)
+    probe = {}
+    for k in ("row_fwd", "col", "row_stage"):
+        mmv.profile_begin(mesh.h, k)
+        mesh.step(dt, 20)
+        ms, n = mmv.profile_end(mesh.h)
+        probe[k] = (ms, n)
+    dom = max(probe, key=lambda k: probe[k][0])
+
+    # timed region
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    t0 = time.perf_counter()
+    mesh.step(dt, args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    ms_per_step = ms_total / args.steps
+    value = cells * args.steps / (ms_total * 1e-3)
+
+    # the dominant kernel over a second region of the same length, timed with
+    # HIP events recorded by the library around each of its launches
+    mmv.profile_begin(mesh.h, dom)
+    mesh.step(dt, args.steps)
+    kms, kn = mmv.profile_end(mesh.h)
+    avg_s = kms * 1e-3 / kn
+    achieved = per_launch[dom] / avg_s / 1e9
+    st = mesh.state()
+    mesh.close()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if d.precision == 32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: 2 films {d.nx}x{d.ny}x1 cells of "
+                               f"{d.dx*1e9:g} nm, RK4 dt {dt:g} s, spring drive, direct spline mode",
+                   "cells": cells, "fft": [lx, ly], "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": TRAFFIC.get(dom), "bytes_per_launch": per_launch[dom],
+                     "avg_launch_us": avg_s * 1e6, "launches": kn},
+        "kernel_share": {k: v[0] / sum(p[0] for p in probe.values()) for k, v in probe.items()},
+        "wall_s": wall,
+        "slider_x_nm": st["x"] * 1e9,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg, m)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,163 @@
+/*
+ * mmv.h -- C ABI of the moving-magnet micromagnetic hot path on MI355X.
+ *
+ * Two thin magnetic films on finite-difference lattices: film 0 (the base)
+ * is fixed, film 1 (the slider) sits gap_cells empty layers above it and
+ * moves rigidly along x (Rissanen & Laurson, Sec. II and III).  Per RK4
+ * stage the library evaluates the effective field (exchange, uniaxial
+ * anisotropy, uniform Zeeman, the demagnetising convolution of Eq. (6) and
+ * the stray field of the other film sampled at the sub-cell offset by
+ * prefiltered cubic B-splines, Sec. II.A and III.A), the LLG torque of
+ * Eq. (1), the force of Eq. (3) and the slider equation of motion Eq. (15).
+ *
+ * Conventions shared by every call
+ *   - Return value: MMV_OK (0) or a negative MMV_E* code; nothing throws.
+ *     mmv_last_error() returns a thread-local text for the last failure.
+ *   - Arguments are validated on the host before any HIP call; a call that
+ *     fails validation has no effect.
+ *   - Device pointers are owned by the caller (e.g. torch tensors) and must
+ *     stay valid until the call's work on the handle's stream completes.
+ *     The library owns its internal buffers and frees them in destroy_mesh.
+ *   - Magnetisation and field buffers are structure-of-arrays
+ *     [3][nz][ny][nx] (component, z, y, x; x fastest) of the mesh's
+ *     precision: float for precision 32, double for precision 64.
+ *   - Work is enqueued on the stream given to init_mesh and is
+ *     asynchronous, except stray_force and get_state, which synchronise
+ *     that stream.  A handle is not thread-safe.
+ *   - Units are SI, except offsets given in cells where stated.
+ */
+#ifndef MMV_H
+#define MMV_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MMV_OK = 0,
+  MMV_EINVAL = -1,   /* bad argument or descriptor                         */
+  MMV_ENOMEM = -2,   /* device allocation failed                           */
+  MMV_EHIP = -3,     /* a HIP runtime call failed                          */
+  MMV_ERANGE = -4,   /* slider offset outside the window the FFT was sized for */
+  MMV_ENUMERIC = -5, /* non-finite magnetisation detected                  */
+  MMV_ESTATE = -6    /* call not valid in the handle's current state       */
+};
+
+/* Field terms for eval_heff (bit mask). */
+enum {
+  MMV_TERM_EXCHANGE = 1,
+  MMV_TERM_ANISOTROPY = 2,
+  MMV_TERM_ZEEMAN = 4,
+  MMV_TERM_DEMAG_SELF = 8,   /* the film's own demagnetising field, Eq. (6) */
+  MMV_TERM_DEMAG_CROSS = 16, /* the other film's interpolated stray field   */
+  MMV_TERM_EDDY = 32,        /* eddy-current field (Sec. III.B)             */
+  MMV_TERM_ALL = 63
+};
+
+/* Slider drive (Sec. III; Eqs. 14-15). */
+enum { MMV_DRIVE_FROZEN = 0, MMV_DRIVE_VELOCITY = 1, MMV_DRIVE_SPRING = 2 };
+
+typedef struct mmv_mesh* mmv_handle;
+
+typedef struct {
+  int n_films;          /* 1: one magnet; 2: base (film 0) + slider (film 1) */
+  int nx, ny, nz;       /* cells per film; two films need nz == 1            */
+  double dx, dy, dz;    /* cell edges [m]                                     */
+  int gap_cells;        /* empty layers between the films (>= 0)              */
+  int max_travel_cells; /* |floor(x_s/dx)| allowed; sizes the FFT window      */
+  double Ms;            /* saturation magnetisation [A/m]                     */
+  double Aex;           /* exchange stiffness [J/m]                           */
+  double alpha;         /* Gilbert damping                                    */
+  double Ku;            /* first-order uniaxial anisotropy [J/m^3]            */
+  double u[3];          /* anisotropy axis (normalised by the library)        */
+  double Hext[3];       /* uniform applied field [A/m]                        */
+  double sigma;         /* conductivity [S/m]; 0 = no eddy currents           */
+  int precision;        /* 32 or 64                                           */
+  int cross_mode;       /* 0: direct field spline; 1: scalar potential        */
+  int halo;             /* spline window extension along x in cells (>= 2)    */
+  double rc_cells;      /* Newell / point-dipole switch radius in cells (> 0) */
+  int sor_sweeps;       /* eddy SOR sweeps per step (0: library default)      */
+  double sor_omega;     /* eddy SOR factor (0: 2/(1+sin(pi/n_max)))           */
+  int fft_lx, fft_ly, fft_lz; /* FFT lengths; 0 = smallest admissible       */
+} mmv_mesh_desc;
+
+typedef struct {
+  int mode;          /* MMV_DRIVE_*                                           */
+  double v_d;        /* anchor (spring) or slider (velocity) speed [m/s]      */
+  double k;          /* spring constant [N/m]                                 */
+  double mass;       /* slider mass [kg] (> 0 for the spring drive)           */
+  double gamma_v;    /* viscous damping coefficient [1/s], Eq. (14)           */
+  double x_anchor0;  /* spring anchor position at t = 0 [m]                   */
+  double x0, v0;     /* slider position [m] and velocity [m/s] set now        */
+} mmv_drive;
+
+/* Create a mesh.  Validates d, chooses FFT lengths (x: even and
+ * {2,3,5,7}-smooth with Lx >= 2 (nx + halo + max_travel_cells); y:
+ * {2,3,5,7}-smooth with Ly >= 2 (ny + 1) for the direct mode, 2 (ny + 3)
+ * for the potential mode), allocates device buffers and builds the kernel
+ * spectra on the GPU in float64 (Sec. III.A: the tensor is computed once,
+ * Fourier transformed and kept on the GPU).  hip_stream is a hipStream_t
+ * (NULL = default stream).  Magnetisation starts at +z, slider at x = 0,
+ * drive frozen, t = 0.  On success *out receives the handle.           */
+int init_mesh(const mmv_mesh_desc* d, void* hip_stream, mmv_handle* out);
+
+/* Copy a film's magnetisation from / to a caller device buffer
+ * (SoA [3][nz][ny][nx], mesh precision).  set_m does not renormalise.   */
+int set_m(mmv_handle h, int film, const void* m_dev);
+int get_m(mmv_handle h, int film, void* m_dev);
+
+/* Place the slider at x_s = x_cells * dx (Fig. 3: x_s = (s_int + x_p) dx
+ * with s_int = floor(x_cells)).  MMV_ERANGE if |s_int| exceeds
+ * max_travel_cells.  Enqueued on the stream.                            */
+int set_offset(mmv_handle h, double x_cells);
+
+/* Set the drive and the slider's position and velocity (x0, v0; for the
+ * velocity drive v0 is replaced by v_d).                                */
+int set_drive(mmv_handle h, const mmv_drive* drv);
+
+/* Effective field of one film at the current state: the sum of the terms
+ * in term_mask (MMV_TERM_*), in A/m, written to h_dev (SoA, mesh
+ * precision).  The cross term is the other film's stray field sampled at
+ * the current slider offset (Sec. II.A).                               */
+int eval_heff(mmv_handle h, int film, int term_mask, void* h_dev);
+
+/* Advance nsteps classic RK4 steps of size dt [s] for (m_base, m_slider,
+ * x_s, v_s) (Eq. 1 with Eq. 15); every stage evaluates the full field at
+ * its own magnetisation, offset and time; m is renormalised after each
+ * step and s_int re-seated to floor(x_s / dx) (Sec. III).  Asynchronous.
+ * A slider leaving the sized window sets a flag reported as MMV_ERANGE by
+ * the next get_state / stray_force.                                      */
+int llg_step(mmv_handle h, double dt, int nsteps);
+
+/* Force of Eq. (3) exerted by the base on the slider [N] at the current
+ * state, all three components, accumulated in float64 in a fixed order.
+ * Synchronises the stream.  MMV_ESTATE for a single-film mesh.          */
+int stray_force(mmv_handle h, double F_out[3]);
+
+/* Time [s], slider position [m] and velocity [m/s] and step count.
+ * Synchronises the stream; reports a pending MMV_ERANGE / MMV_ENUMERIC. */
+int get_state(mmv_handle h, double* t, double* x_s, double* v_s, long* step);
+
+/* Diagnostics: time every launch of one kernel with HIP events recorded on
+ * the handle's stream around that launch.  kernel: 1 = x transform,
+ * 2 = y pass with kernel multiplication, 3 = row kernel (inverse x
+ * transform, spline, local terms, LLG stage, force).  profile_end
+ * synchronises the stream, returns the summed duration [ms] and the number
+ * of timed launches since profile_begin, and stops timing.               */
+int profile_begin(mmv_handle h, int kernel);
+int profile_end(mmv_handle h, double* total_ms, long* launches);
+
+/* Chosen FFT lengths (diagnostics). */
+int get_fft_lengths(mmv_handle h, int* lx, int* ly, int* lz);
+
+/* Release every device buffer of the handle.  NULL is accepted.         */
+int destroy_mesh(mmv_handle h);
+
+/* Thread-local message for the most recent failing call ("" if none).   */
+const char* mmv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MMV_H */

@@ -1,0 +1,260 @@
+"""Python binding of libmmv (the moving-magnet micromagnetic hot path).
+
+Argument marshalling only: every call forwards to the C ABI declared in
+include/mmv.h, and every step of the computation runs in the HIP kernels of
+libmmv.so.  Device buffers are torch tensors on the GPU; the library only
+sees their pointers and the current HIP stream.  If libmmv.so is missing the
+first call raises -- there is no fallback implementation.
+"""
+import ctypes
+import os
+
+__all__ = ["MMVError", "lib_path", "load", "MeshDesc", "DriveDesc", "init_mesh",
+           "set_m", "get_m", "set_offset", "set_drive", "eval_heff", "llg_step",
+           "stray_force", "get_state", "get_fft_lengths", "destroy_mesh",
+           "profile_begin", "profile_end",
+           "last_error", "Mesh", "TERM", "EXPORTS"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libmmv.so")
+
+TERM = dict(exchange=1, anisotropy=2, zeeman=4, demag_self=8, demag_cross=16,
+            eddy=32, all=63)
+ERRORS = {-1: "MMV_EINVAL", -2: "MMV_ENOMEM", -3: "MMV_EHIP", -4: "MMV_ERANGE",
+          -5: "MMV_ENUMERIC", -6: "MMV_ESTATE"}
+EXPORTS = ("init_mesh", "set_m", "get_m", "set_offset", "set_drive", "eval_heff",
+           "llg_step", "stray_force", "get_state", "profile_begin", "profile_end",
+           "get_fft_lengths", "destroy_mesh", "mmv_last_error")
+
+
+class MMVError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("n_films", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("nz", ctypes.c_int), ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("dz", ctypes.c_double), ("gap_cells", ctypes.c_int),
+                ("max_travel_cells", ctypes.c_int), ("Ms", ctypes.c_double),
+                ("Aex", ctypes.c_double), ("alpha", ctypes.c_double), ("Ku", ctypes.c_double),
+                ("u", ctypes.c_double * 3), ("Hext", ctypes.c_double * 3),
+                ("sigma", ctypes.c_double), ("precision", ctypes.c_int),
+                ("cross_mode", ctypes.c_int), ("halo", ctypes.c_int),
+                ("rc_cells", ctypes.c_double), ("sor_sweeps", ctypes.c_int),
+                ("sor_omega", ctypes.c_double), ("fft_lx", ctypes.c_int),
+                ("fft_ly", ctypes.c_int), ("fft_lz", ctypes.c_int)]
+
+
+class DriveDesc(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("v_d", ctypes.c_double), ("k", ctypes.c_double),
+                ("mass", ctypes.c_double), ("gamma_v", ctypes.c_double),
+                ("x_anchor0", ctypes.c_double), ("x0", ctypes.c_double),
+                ("v0", ctypes.c_double)]
+
+
+_LIB = None
+
+
+def load():
+    """Load libmmv.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(lib_path):
+            raise ImportError(f"{lib_path} is missing: build it with "
+                              "`python -m paper_1801_04181_amd.build` (no fallback exists)")
+        lib = ctypes.CDLL(lib_path)
+        vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+        pd = ctypes.POINTER(ctypes.c_double)
+        lib.init_mesh.argtypes = [ctypes.POINTER(MeshDesc), vp, ctypes.POINTER(vp)]
+        lib.set_m.argtypes = [vp, i, vp]
+        lib.get_m.argtypes = [vp, i, vp]
+        lib.set_offset.argtypes = [vp, d]
+        lib.set_drive.argtypes = [vp, ctypes.POINTER(DriveDesc)]
+        lib.eval_heff.argtypes = [vp, i, i, vp]
+        lib.llg_step.argtypes = [vp, d, i]
+        lib.stray_force.argtypes = [vp, pd]
+        lib.get_state.argtypes = [vp, pd, pd, pd, ctypes.POINTER(ctypes.c_long)]
+        lib.get_fft_lengths.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
+        lib.destroy_mesh.argtypes = [vp]
+        lib.profile_begin.argtypes = [vp, i]
+        lib.profile_end.argtypes = [vp, pd, ctypes.POINTER(ctypes.c_long)]
+        lib.mmv_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS[:-1]:
+            getattr(lib, name).restype = ctypes.c_int
+        _LIB = lib
+    return _LIB
+
+
+def last_error():
+    return load().mmv_last_error().decode()
+
+
+def _check(rc):
+    if rc != 0:
+        raise MMVError(rc, last_error())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def to_desc(desc):
+    """workloads.Desc (or any object with the same attributes) -> MeshDesc."""
+    c = MeshDesc()
+    for name, _ in MeshDesc._fields_:
+        if name in ("u", "Hext"):
+            arr = (ctypes.c_double * 3)(*[float(v) for v in getattr(desc, name)])
+            setattr(c, name, arr)
+        elif name in ("fft_lx", "fft_ly", "fft_lz"):
+            setattr(c, name, int(getattr(desc, name, 0)))
+        else:
+            setattr(c, name, getattr(desc, name))
+    return c
+
+
+def to_drive(drv):
+    c = DriveDesc()
+    c.mode, c.v_d, c.k, c.mass = drv.mode, drv.v_d, drv.k, drv.mass
+    c.gamma_v, c.x_anchor0, c.x0, c.v0 = drv.gamma_v, drv.x_anchor0, drv.x0, drv.v0
+    return c
+
+
+def init_mesh(desc, stream=None):
+    h = ctypes.c_void_p()
+    cd = desc if isinstance(desc, MeshDesc) else to_desc(desc)
+    _check(load().init_mesh(ctypes.byref(cd), _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def set_m(h, film, m):
+    _check(load().set_m(h, film, _ptr(m)))
+
+
+def get_m(h, film, out):
+    _check(load().get_m(h, film, _ptr(out)))
+    return out
+
+
+def set_offset(h, x_cells):
+    _check(load().set_offset(h, float(x_cells)))
+
+
+def set_drive(h, drv):
+    cd = drv if isinstance(drv, DriveDesc) else to_drive(drv)
+    _check(load().set_drive(h, ctypes.byref(cd)))
+
+
+def eval_heff(h, film, term_mask, out):
+    _check(load().eval_heff(h, film, int(term_mask), _ptr(out)))
+    return out
+
+
+def llg_step(h, dt, nsteps=1):
+    _check(load().llg_step(h, float(dt), int(nsteps)))
+
+
+def stray_force(h):
+    F = (ctypes.c_double * 3)()
+    _check(load().stray_force(h, F))
+    return [F[0], F[1], F[2]]
+
+
+def get_state(h):
+    t, x, v = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    n = ctypes.c_long()
+    _check(load().get_state(h, ctypes.byref(t), ctypes.byref(x), ctypes.byref(v), ctypes.byref(n)))
+    return dict(t=t.value, x=x.value, v=v.value, step=n.value)
+
+
+def get_fft_lengths(h):
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load().get_fft_lengths(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+KERNELS = {"row_fwd": 1, "col": 2, "row_stage": 3}
+
+
+def profile_begin(h, kernel):
+    _check(load().profile_begin(h, KERNELS.get(kernel, kernel)))
+
+
+def profile_end(h):
+    ms, n = ctypes.c_double(), ctypes.c_long()
+    _check(load().profile_end(h, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def destroy_mesh(h):
+    _check(load().destroy_mesh(h))
+
+
+class Mesh:
+    """Owns one handle; torch tensors supply device memory and the stream."""
+
+    def __init__(self, desc, drive=None, m=None, stream=None, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.desc = desc
+        self.device = torch.device(device)
+        self.dtype = torch.float64 if desc.precision == 64 else torch.float32
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h = init_mesh(desc, self.stream)
+        self.shape = (3, desc.nz, desc.ny, desc.nx)
+        if drive is not None:
+            set_drive(self.h, drive)
+        if m is not None:
+            for f, mf in enumerate(m):
+                self.set_m(f, mf)
+
+    def set_m(self, film, m):
+        t = self.torch.as_tensor(m, dtype=self.dtype).to(self.device).contiguous()
+        assert tuple(t.shape) == self.shape, (t.shape, self.shape)
+        set_m(self.h, film, t)
+        self.torch.cuda.current_stream(self.device).synchronize()
+
+    def get_m(self, film):
+        out = self.torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        get_m(self.h, film, out)
+        return out
+
+    def eval_heff(self, film, mask=63):
+        out = self.torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        eval_heff(self.h, film, mask, out)
+        return out
+
+    def step(self, dt, n=1):
+        llg_step(self.h, dt, n)
+
+    def force(self):
+        return stray_force(self.h)
+
+    def state(self):
+        return get_state(self.h)
+
+    def set_offset(self, x_cells):
+        set_offset(self.h, x_cells)
+
+    def fft_lengths(self):
+        return get_fft_lengths(self.h)
+
+    def close(self):
+        if self.h is not None:
+            destroy_mesh(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,710 @@
+// C ABI of the two-film hot path: descriptor validation, FFT plans, device
+// buffers, one-time kernel construction and the per-step launch sequence.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+#include <string>
+#include <vector>
+#include "mmv.h"
+#include "mmv_internal.h"
+#include "mmv_kernels.h"
+
+using namespace mmv;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) return fail(MMV_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr double MU0 = 4e-7 * M_PI;
+constexpr double GAMMA0 = MU0 * 1.7595e11;  // gamma_e = 1.7595e11 rad/(s T)
+
+bool smooth2357(int n) {
+  if (n < 1) return false;
+  for (int p : {2, 3, 5, 7})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+int next_smooth(int n, bool even) {
+  for (int m = n < 1 ? 1 : n;; ++m)
+    if (smooth2357(m) && (!even || m % 2 == 0)) return m;
+}
+bool make_plan(int L, FftPlan& P) {
+  P.L = L;
+  P.np = 0;
+  int n = L;
+  for (int r : {7, 5, 3}) {
+    while (n % r == 0) {
+      if (P.np >= MAX_PASSES) return false;
+      P.r[P.np++] = r;
+      n /= r;
+    }
+  }
+  while (n % 4 == 0) {
+    if (P.np >= MAX_PASSES) return false;
+    P.r[P.np++] = 4;
+    n /= 4;
+  }
+  while (n % 2 == 0) {
+    if (P.np >= MAX_PASSES) return false;
+    P.r[P.np++] = 2;
+    n /= 2;
+  }
+  return n == 1;
+}
+
+// Kernel component order: xx yy zz xy xz yz; parities in (x, y).
+const int PX[6] = {0, 0, 0, 1, 1, 0};
+const int PY[6] = {0, 0, 0, 1, 0, 1};
+int comp_index(int a, int b) {
+  static const int t[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+  return t[a][b];
+}
+
+struct LayerSet {
+  int kc[6];  // kernel channel per component, -1 = identically zero
+};
+
+}  // namespace
+
+struct mmv_mesh {
+  mmv_mesh_desc d;
+  hipStream_t st = nullptr;
+  int esz = 4;  // bytes per real
+  int nfilm = 2, nx = 0, ny = 0;
+  int Lx = 0, Ly = 0, N2x = 0, Kx = 0, Kyh = 0, CB = 1, M = 0;
+  FftPlan px{}, py{};
+  void* m0 = nullptr;
+  void* mb[2] = {nullptr, nullptr};
+  void* acc = nullptr;
+  void* spec1 = nullptr;
+  void* spec2 = nullptr;
+  void* kern = nullptr;
+  void* twx = nullptr;
+  void* twp = nullptr;
+  void* twy = nullptr;
+  RigidState* rigid = nullptr;
+  double* partial = nullptr;
+  unsigned* counter = nullptr;
+  int nkc = 0;
+  LayerSet self{}, cross{}, fp{}, fm{};
+  OutTable tab_hot{}, tab_force{};
+  RowParams rp_hot{}, rp_force{};
+  DriveP drive{};
+  std::vector<void*> allocs;
+  // launch timing (diagnostics)
+  int prof_kernel = 0;
+  size_t prof_used = 0;
+  std::vector<hipEvent_t> prof_ev;
+};
+
+namespace {
+
+template <typename T>
+size_t rsz() {
+  return sizeof(T);
+}
+
+int dalloc(mmv_mesh* h, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) return fail(MMV_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  h->allocs.push_back(*p);
+  return MMV_OK;
+}
+
+void free_all(mmv_mesh* h) {
+  for (void* p : h->allocs) hipFree(p);
+  h->allocs.clear();
+}
+
+int validate(const mmv_mesh_desc* d) {
+  if (!d) return fail(MMV_EINVAL, "descriptor is NULL");
+  if (d->n_films != 1 && d->n_films != 2) return fail(MMV_EINVAL, "n_films must be 1 or 2");
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(MMV_EINVAL, "nx, ny, nz must be >= 1");
+  if (d->nx > 8192 || d->ny > 8192) return fail(MMV_EINVAL, "nx, ny must be <= 8192");
+  if (d->nz != 1) return fail(MMV_EINVAL, "this build supports films one cell thick (nz == 1)");
+  auto pos = [](double v) { return isfinite(v) && v > 0; };
+  if (!pos(d->dx) || !pos(d->dy) || !pos(d->dz)) return fail(MMV_EINVAL, "cell edges must be finite and > 0");
+  if (!pos(d->Ms)) return fail(MMV_EINVAL, "Ms must be finite and > 0");
+  if (!isfinite(d->Aex) || d->Aex < 0) return fail(MMV_EINVAL, "Aex must be finite and >= 0");
+  if (!isfinite(d->alpha) || d->alpha < 0) return fail(MMV_EINVAL, "alpha must be finite and >= 0");
+  if (!isfinite(d->Ku)) return fail(MMV_EINVAL, "Ku must be finite");
+  for (int i = 0; i < 3; ++i)
+    if (!isfinite(d->u[i]) || !isfinite(d->Hext[i])) return fail(MMV_EINVAL, "u and Hext must be finite");
+  if (d->precision != 32 && d->precision != 64) return fail(MMV_EINVAL, "precision must be 32 or 64");
+  if (d->cross_mode != 0) return fail(MMV_EINVAL, "cross_mode 1 (scalar potential) is not available in this build");
+  if (d->sigma != 0.0)
+    return fail(MMV_EINVAL, "eddy currents need magnets more than one cell thick (sigma must be 0 for nz == 1)");
+  if (d->gap_cells < 0) return fail(MMV_EINVAL, "gap_cells must be >= 0");
+  if (d->max_travel_cells < 0 || d->max_travel_cells > 4096)
+    return fail(MMV_EINVAL, "max_travel_cells must be in [0, 4096]");
+  if (d->n_films == 2 && (d->halo < 2 || d->halo > 64)) return fail(MMV_EINVAL, "halo must be in [2, 64]");
+  if (!pos(d->rc_cells)) return fail(MMV_EINVAL, "rc_cells must be finite and > 0");
+  if (d->fft_lx < 0 || d->fft_ly < 0 || d->fft_lz < 0) return fail(MMV_EINVAL, "FFT lengths must be >= 0");
+  return MMV_OK;
+}
+
+void host_twiddles(int L, int count, std::vector<double>& re, std::vector<double>& im) {
+  re.resize(count);
+  im.resize(count);
+  for (int t = 0; t < count; ++t) {
+    const double a = -2.0 * M_PI * (double)t / (double)L;
+    re[t] = cos(a);
+    im[t] = sin(a);
+  }
+}
+
+int upload_tw(mmv_mesh* h, void** dst, int L, int count, bool dbl) {
+  std::vector<double> re, im;
+  host_twiddles(L, count, re, im);
+  const size_t es = dbl ? 8 : 4;
+  std::vector<unsigned char> buf(2 * es * count);
+  for (int t = 0; t < count; ++t) {
+    if (dbl) {
+      double v[2] = {re[t], im[t]};
+      memcpy(&buf[2 * es * t], v, 2 * es);
+    } else {
+      float v[2] = {(float)re[t], (float)im[t]};
+      memcpy(&buf[2 * es * t], v, 2 * es);
+    }
+  }
+  int rc = dalloc(h, dst, buf.size());
+  if (rc) return rc;
+  HIPCHK(hipMemcpy(*dst, buf.data(), buf.size(), hipMemcpyHostToDevice));
+  return MMV_OK;
+}
+
+// Output channel for component a of the field of film `src` through layer set L.
+OutCh make_out(const LayerSet& L, int src, int a, int zsign, int row0, int nrows) {
+  OutCh o{};
+  o.src = src;
+  for (int b = 0; b < 3; ++b) {
+    const int c = comp_index(a, b);
+    o.kc[b] = L.kc[c];
+    const int imag = (PX[c] + PY[c]) & 1;
+    const int oddy = PY[c];
+    const int neg = (zsign < 0 && (c == 4 || c == 5)) ? 1 : 0;  // xz, yz are odd in z
+    o.fl[b] = imag | (oddy << 1) | (neg << 2);
+  }
+  o.row0 = row0;
+  o.nrows = nrows;
+  o.off = 0;
+  return o;
+}
+
+// Column-pass table and the matching row-kernel offsets.
+void build_tables(mmv_mesh* h, bool full_force, OutTable& tab, RowParams& rp, long long& total) {
+  const int ny = h->ny;
+  tab.n = 0;
+  long long off = 0;
+  auto add = [&](OutCh o) -> long long {
+    o.off = off;
+    off += (long long)o.nrows * h->Kx;
+    tab.ch[tab.n++] = o;
+    return o.off;
+  };
+  for (int f = 0; f < h->nfilm; ++f)
+    for (int a = 0; a < 3; ++a) rp.off_self[f][a] = add(make_out(h->self, f, a, +1, 0, ny));
+  if (h->nfilm == 2) {
+    for (int a = 0; a < 3; ++a) rp.off_cross[1][a] = add(make_out(h->cross, 0, a, +1, -1, ny + 2));
+    rp.cross_row0[1] = -1;
+    const int nfc = full_force ? 3 : 1;
+    for (int a = 0; a < nfc; ++a) rp.off_fp[a] = add(make_out(h->fp, 0, a, +1, 0, ny));
+    for (int a = 0; a < nfc; ++a) rp.off_fm[a] = add(make_out(h->fm, 0, a, +1, 0, ny));
+    for (int a = 0; a < 3; ++a) rp.off_cross[0][a] = add(make_out(h->cross, 1, a, -1, 0, ny));
+    rp.cross_row0[0] = 0;
+  }
+  total = off;
+}
+
+// Kernel-channel numbering: the film's own layer (xz, yz vanish in the film
+// plane), the other film's layer z_s and the force layers z_s +/- 1.
+void assign_channels(mmv_mesh* h) {
+  int n = 0;
+  for (int c = 0; c < 6; ++c) h->self.kc[c] = (c < 4) ? n++ : -1;
+  if (h->nfilm == 2) {
+    for (int c = 0; c < 6; ++c) h->cross.kc[c] = n++;
+    for (int c = 0; c < 6; ++c) h->fp.kc[c] = n++;
+    for (int c = 0; c < 6; ++c) h->fm.kc[c] = n++;
+  }
+  h->nkc = n;
+}
+
+template <typename T>
+int build_kernels(mmv_mesh* h) {
+  const mmv_mesh_desc& d = h->d;
+  const int n = h->nkc;
+  int rc = dalloc(h, &h->kern, sizeof(T) * (size_t)n * h->Kx * h->Kyh);
+  if (rc) return rc;
+  void *tmp = nullptr, *tspec = nullptr, *twxd = nullptr, *twpd = nullptr, *twyd = nullptr;
+  HIPCHK(hipMalloc(&tmp, sizeof(double) * (size_t)h->Lx * h->Ly));
+  HIPCHK(hipMalloc(&tspec, 2 * sizeof(double) * (size_t)h->Kx * h->Ly));
+  mmv_mesh tmp_owner;
+  rc = upload_tw(&tmp_owner, &twxd, h->N2x, h->N2x, true);
+  if (!rc) rc = upload_tw(&tmp_owner, &twpd, h->Lx, h->N2x + 1, true);
+  if (!rc) rc = upload_tw(&tmp_owner, &twyd, h->Ly, h->Ly, true);
+  if (rc) {
+    hipFree(tmp);
+    hipFree(tspec);
+    free_all(&tmp_owner);
+    return rc;
+  }
+  const double scale = -d.Ms / ((double)h->Lx * (double)h->Ly);
+  struct Job {
+    int kc, comp;
+    double dzc;
+  };
+  std::vector<Job> jobs;
+  const int zs = d.nz + d.gap_cells;
+  for (int c = 0; c < 6; ++c) {
+    if (h->self.kc[c] >= 0) jobs.push_back({h->self.kc[c], c, 0.0});
+    if (h->nfilm == 2) {
+      jobs.push_back({h->cross.kc[c], c, (double)zs});
+      jobs.push_back({h->fp.kc[c], c, (double)(zs + 1)});
+      jobs.push_back({h->fm.kc[c], c, (double)(zs - 1)});
+    }
+  }
+  hipError_t err = hipSuccess;
+  for (const Job& j : jobs) {
+    err = launch_kernel_real((double*)tmp, h->Lx, h->Ly, 0, j.comp, j.dzc, d.dx, d.dy, d.dz, d.rc_cells, scale,
+                             h->st);
+    if (err != hipSuccess) break;
+    err = launch_row_fwd<double>((const double*)tmp, tspec, h->Ly, h->Lx, h->N2x, h->Kx, h->px, twxd, twpd, h->st);
+    if (err != hipSuccess) break;
+    const int imag = (PX[j.comp] + PY[j.comp]) & 1;
+    err = launch_colpack<T>(tspec, (T*)h->kern + (size_t)j.kc * h->Kx * h->Kyh, h->Kx, h->Ly, h->Kyh, h->py, twyd,
+                            imag, h->st);
+    if (err != hipSuccess) break;
+  }
+  if (err == hipSuccess) err = hipStreamSynchronize(h->st);
+  hipFree(tmp);
+  hipFree(tspec);
+  free_all(&tmp_owner);
+  if (err != hipSuccess) return fail(MMV_EHIP, std::string("kernel construction: ") + hipGetErrorString(err));
+  return MMV_OK;
+}
+
+template <typename T>
+int init_typed(mmv_mesh* h) {
+  const mmv_mesh_desc& d = h->d;
+  h->esz = sizeof(T);
+  const size_t ncell = (size_t)h->nfilm * h->nx * h->ny;
+  int rc;
+  if ((rc = dalloc(h, &h->m0, 3 * ncell * sizeof(T)))) return rc;
+  if ((rc = dalloc(h, &h->mb[0], 3 * ncell * sizeof(T)))) return rc;
+  if ((rc = dalloc(h, &h->mb[1], 3 * ncell * sizeof(T)))) return rc;
+  if ((rc = dalloc(h, &h->acc, 3 * ncell * sizeof(T)))) return rc;
+  if ((rc = dalloc(h, &h->spec1, 2 * sizeof(T) * 3 * (size_t)h->nfilm * h->ny * h->Kx))) return rc;
+  long long n_hot = 0, n_force = 0;
+  assign_channels(h);
+  build_tables(h, false, h->tab_hot, h->rp_hot, n_hot);
+  build_tables(h, true, h->tab_force, h->rp_force, n_force);
+  const long long n2 = n_hot > n_force ? n_hot : n_force;
+  if ((rc = dalloc(h, &h->spec2, 2 * sizeof(T) * (size_t)n2))) return rc;
+  if ((rc = upload_tw(h, &h->twx, h->N2x, h->N2x, sizeof(T) == 8))) return rc;
+  if ((rc = upload_tw(h, &h->twp, h->Lx, h->N2x + 1, sizeof(T) == 8))) return rc;
+  if ((rc = upload_tw(h, &h->twy, h->Ly, h->Ly, sizeof(T) == 8))) return rc;
+  const int ntask_max = h->nfilm * h->ny + 2;
+  if ((rc = dalloc(h, (void**)&h->partial, sizeof(double) * 3 * (size_t)ntask_max))) return rc;
+  if ((rc = dalloc(h, (void**)&h->counter, sizeof(unsigned) * 4))) return rc;
+  if ((rc = dalloc(h, (void**)&h->rigid, sizeof(RigidState)))) return rc;
+  HIPCHK(hipMemsetAsync(h->counter, 0, sizeof(unsigned) * 4, h->st));
+  RigidState r{};
+  HIPCHK(hipMemcpyAsync(h->rigid, &r, sizeof(r), hipMemcpyHostToDevice, h->st));
+  // m = +z
+  std::vector<T> mz(3 * ncell, T(0));
+  for (int f = 0; f < h->nfilm; ++f)
+    for (size_t i = 0; i < (size_t)h->nx * h->ny; ++i) mz[(size_t)f * 3 * h->nx * h->ny + 2 * h->nx * h->ny + i] = T(1);
+  HIPCHK(hipMemcpy(h->m0, mz.data(), mz.size() * sizeof(T), hipMemcpyHostToDevice));
+  if ((rc = build_kernels<T>(h))) return rc;
+
+  // row-kernel parameters common to both tables
+  for (RowParams* rp : {&h->rp_hot, &h->rp_force}) {
+    rp->nfilm = h->nfilm;
+    rp->nx = h->nx;
+    rp->ny = h->ny;
+    rp->N2x = h->N2x;
+    rp->Kx = h->Kx;
+    rp->halo = d.halo;
+    rp->M = h->M;
+    rp->travel = d.max_travel_cells;
+    rp->dx = d.dx;
+    rp->dy = d.dy;
+    rp->dz = d.dz;
+    rp->pref_ex = 2.0 * d.Aex / (MU0 * d.Ms);
+    rp->pref_an = 2.0 * d.Ku / (MU0 * d.Ms);
+    const double un = sqrt(d.u[0] * d.u[0] + d.u[1] * d.u[1] + d.u[2] * d.u[2]);
+    for (int i = 0; i < 3; ++i) {
+      rp->u[i] = un > 0 ? d.u[i] / un : 0.0;
+      rp->hext[i] = d.Hext[i];
+    }
+    rp->gam = GAMMA0 / (1.0 + d.alpha * d.alpha);
+    rp->alpha = d.alpha;
+    rp->force_scale = MU0 * d.Ms * d.dx * d.dy * d.dz;
+    rp->px = h->px;
+  }
+  // LDS limits
+  const size_t lds_limit = 160 * 1024;
+  RowParams probe = h->rp_force;
+  probe.full_force = 1;
+  if (row_lds_bytes<T>(probe) > lds_limit) return fail(MMV_EINVAL, "nx too large for the row kernel's LDS");
+  if (sizeof(T) * 2 * (4 * (size_t)h->N2x + 1) > lds_limit) return fail(MMV_EINVAL, "nx too large");
+  // columns per block of the y pass: largest CB with LDS <= 64 KiB (>= 1)
+  const int bufch = 3 * h->nfilm > 6 ? 3 * h->nfilm : 6;
+  h->CB = 1;
+  for (int cb : {8, 4, 2}) {
+    if (col_lds_bytes<T>(h->Ly, bufch, cb) <= 64 * 1024 && (h->Kx + cb - 1) / cb >= 256) {
+      h->CB = cb;
+      break;
+    }
+  }
+  if (col_lds_bytes<T>(h->Ly, bufch, h->CB) > lds_limit) return fail(MMV_EINVAL, "ny too large for the y pass");
+  return MMV_OK;
+}
+
+template <typename T>
+void* mptr(mmv_mesh* h, void* base, int film) {
+  return (char*)base + (size_t)film * 3 * h->nx * h->ny * sizeof(T);
+}
+
+int check_handle(mmv_handle h) {
+  if (!h) return fail(MMV_EINVAL, "handle is NULL");
+  return MMV_OK;
+}
+
+// Record a timing event before (begin = true) or after a launch of `kernel`.
+int prof_mark(mmv_mesh* h, int kernel) {
+  if (h->prof_kernel != kernel) return MMV_OK;
+  if (h->prof_used == h->prof_ev.size()) {
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    h->prof_ev.push_back(e);
+  }
+  HIPCHK(hipEventRecord(h->prof_ev[h->prof_used++], h->st));
+  return MMV_OK;
+}
+
+#define PROF(k)                      \
+  do {                               \
+    int rc_ = prof_mark(h, (k));     \
+    if (rc_) return rc_;             \
+  } while (0)
+
+template <typename T>
+int run_fields(mmv_mesh* h, const void* m_in, const OutTable& tab) {
+  PROF(1);
+  HIPCHK(launch_row_fwd<T>((const T*)m_in, h->spec1, 3 * h->nfilm * h->ny, h->nx, h->N2x, h->Kx, h->px, h->twx,
+                           h->twp, h->st));
+  PROF(1);
+  PROF(2);
+  HIPCHK(launch_col<T>(h->spec1, h->spec2, (const T*)h->kern, h->Kx, h->Ly, h->Kyh, h->ny, 3 * h->nfilm, h->CB,
+                       h->py, h->twy, tab, h->st));
+  PROF(2);
+  return MMV_OK;
+}
+
+template <typename T>
+int step_typed(mmv_mesh* h, double dt, int nsteps) {
+  RowParams rp = h->rp_hot;
+  rp.mode = MODE_STAGE;
+  rp.term_mask = MMV_TERM_ALL;
+  rp.dt = dt;
+  rp.drive = h->drive;
+  rp.with_force = (h->nfilm == 2 && h->drive.mode == MMV_DRIVE_SPRING) ? 1 : 0;
+  rp.full_force = 0;
+  rp.ntask = h->nfilm * h->ny + (rp.with_force ? 2 : 0);
+  T* m0 = (T*)h->m0;
+  T* b1 = (T*)h->mb[0];
+  T* b2 = (T*)h->mb[1];
+  for (int n = 0; n < nsteps; ++n) {
+    for (int s = 0; s < 4; ++s) {
+      T* in = s == 0 ? m0 : (s == 1 ? b1 : (s == 2 ? b2 : b1));
+      T* out = s == 0 ? b1 : (s == 1 ? b2 : (s == 2 ? b1 : m0));
+      int rc = run_fields<T>(h, in, h->tab_hot);
+      if (rc) return rc;
+      rp.stage = s;
+      PROF(3);
+      HIPCHK(launch_row_stage<T>(rp, h->spec2, in, m0, out, (T*)h->acc, nullptr, h->twx, h->twp, h->rigid,
+                                 h->partial, h->counter, h->st));
+      PROF(3);
+    }
+  }
+  return MMV_OK;
+}
+
+template <typename T>
+int eval_typed(mmv_mesh* h, int film, int mask, void* hout) {
+  if (mask & (MMV_TERM_DEMAG_SELF | MMV_TERM_DEMAG_CROSS)) {
+    int rc = run_fields<T>(h, h->m0, h->tab_hot);
+    if (rc) return rc;
+  }
+  RowParams rp = h->rp_hot;
+  rp.mode = MODE_EVAL;
+  rp.eval_film = film;
+  rp.term_mask = mask & 31;
+  rp.with_force = 0;
+  rp.full_force = 0;
+  rp.ntask = h->ny;
+  rp.drive = h->drive;
+  HIPCHK(launch_row_stage<T>(rp, h->spec2, (const T*)h->m0, (const T*)h->m0, nullptr, nullptr, (T*)hout, h->twx,
+                             h->twp, h->rigid, h->partial, h->counter, h->st));
+  return MMV_OK;
+}
+
+template <typename T>
+int force_typed(mmv_mesh* h) {
+  int rc = run_fields<T>(h, h->m0, h->tab_force);
+  if (rc) return rc;
+  RowParams rp = h->rp_force;
+  rp.mode = MODE_FORCE;
+  rp.term_mask = 0;
+  rp.with_force = 1;
+  rp.full_force = 1;
+  rp.ntask = h->ny + 2;
+  rp.drive = h->drive;
+  HIPCHK(launch_row_stage<T>(rp, h->spec2, (const T*)h->m0, (const T*)h->m0, nullptr, nullptr, nullptr, h->twx,
+                             h->twp, h->rigid, h->partial, h->counter, h->st));
+  return MMV_OK;
+}
+
+int read_rigid(mmv_mesh* h, RigidState& r) {
+  HIPCHK(hipMemcpyAsync(&r, h->rigid, sizeof(r), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return MMV_OK;
+}
+
+int write_rigid(mmv_mesh* h, const RigidState& r) {
+  HIPCHK(hipMemcpyAsync(h->rigid, &r, sizeof(r), hipMemcpyHostToDevice, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return MMV_OK;
+}
+
+int report_flags(mmv_mesh* h, RigidState& r) {
+  if (r.flags == 0) return MMV_OK;
+  const int f = r.flags;
+  r.flags = 0;
+  int rc = write_rigid(h, r);
+  if (rc) return rc;
+  if (f & FLAG_NUMERIC) return fail(MMV_ENUMERIC, "non-finite magnetisation or slider state");
+  return fail(MMV_ERANGE, "slider left the window the FFT lengths were sized for (max_travel_cells)");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mmv_last_error(void) { return g_err.c_str(); }
+
+int init_mesh(const mmv_mesh_desc* d, void* hip_stream, mmv_handle* out) {
+  g_err.clear();
+  if (!out) return fail(MMV_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(d);
+  if (rc) return rc;
+  mmv_mesh* h = new mmv_mesh();
+  h->d = *d;
+  h->st = (hipStream_t)hip_stream;
+  h->nfilm = d->n_films;
+  h->nx = d->nx;
+  h->ny = d->ny;
+  const int hx = d->n_films == 2 ? d->halo : 0;
+  const int T = d->n_films == 2 ? d->max_travel_cells : 0;
+  const int lx_min = d->n_films == 2 ? 2 * (d->nx + hx + T) : 2 * d->nx;
+  const int ly_min = d->n_films == 2 ? 2 * (d->ny + (d->cross_mode == 1 ? 3 : 1)) : 2 * d->ny;
+  if (d->fft_lx) {
+    if (d->fft_lx < lx_min || d->fft_lx % 2 || !smooth2357(d->fft_lx)) {
+      delete h;
+      return fail(MMV_EINVAL, "fft_lx must be even, {2,3,5,7}-smooth and >= " + std::to_string(lx_min));
+    }
+    h->Lx = d->fft_lx;
+  } else {
+    h->Lx = next_smooth(lx_min, true);
+  }
+  if (d->fft_ly) {
+    if (d->fft_ly < ly_min || !smooth2357(d->fft_ly)) {
+      delete h;
+      return fail(MMV_EINVAL, "fft_ly must be {2,3,5,7}-smooth and >= " + std::to_string(ly_min));
+    }
+    h->Ly = d->fft_ly;
+  } else {
+    h->Ly = next_smooth(ly_min, false);
+  }
+  h->N2x = h->Lx / 2;
+  h->Kx = h->N2x + 1;
+  h->Kyh = h->Ly / 2 + 1;
+  h->M = d->nx + 2 * hx;
+  if (!make_plan(h->N2x, h->px) || !make_plan(h->Ly, h->py)) {
+    delete h;
+    return fail(MMV_EINVAL, "FFT length has too many factors");
+  }
+  rc = d->precision == 64 ? init_typed<double>(h) : init_typed<float>(h);
+  if (rc) {
+    free_all(h);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return MMV_OK;
+}
+
+int profile_begin(mmv_handle h, int kernel) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (kernel < 1 || kernel > 3) return fail(MMV_EINVAL, "kernel must be 1, 2 or 3");
+  h->prof_kernel = kernel;
+  h->prof_used = 0;
+  return MMV_OK;
+}
+
+int profile_end(mmv_handle h, double* total_ms, long* launches) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(h->st));
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < h->prof_used; i += 2) {
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, h->prof_ev[i], h->prof_ev[i + 1]));
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = (long)(h->prof_used / 2);
+  h->prof_kernel = 0;
+  h->prof_used = 0;
+  return MMV_OK;
+}
+
+int destroy_mesh(mmv_handle h) {
+  if (!h) return MMV_OK;
+  hipStreamSynchronize(h->st);
+  for (hipEvent_t e : h->prof_ev) hipEventDestroy(e);
+  free_all(h);
+  delete h;
+  return MMV_OK;
+}
+
+int set_m(mmv_handle h, int film, const void* m_dev) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (film < 0 || film >= h->nfilm) return fail(MMV_EINVAL, "film out of range");
+  if (!m_dev) return fail(MMV_EINVAL, "m_dev is NULL");
+  const size_t bytes = (size_t)3 * h->nx * h->ny * h->esz;
+  HIPCHK(hipMemcpyAsync((char*)h->m0 + film * bytes, m_dev, bytes, hipMemcpyDeviceToDevice, h->st));
+  return MMV_OK;
+}
+
+int get_m(mmv_handle h, int film, void* m_dev) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (film < 0 || film >= h->nfilm) return fail(MMV_EINVAL, "film out of range");
+  if (!m_dev) return fail(MMV_EINVAL, "m_dev is NULL");
+  const size_t bytes = (size_t)3 * h->nx * h->ny * h->esz;
+  HIPCHK(hipMemcpyAsync(m_dev, (char*)h->m0 + film * bytes, bytes, hipMemcpyDeviceToDevice, h->st));
+  return MMV_OK;
+}
+
+int set_offset(mmv_handle h, double x_cells) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (h->nfilm != 2) return fail(MMV_ESTATE, "set_offset needs two films");
+  if (!isfinite(x_cells)) return fail(MMV_EINVAL, "offset must be finite");
+  const double s = floor(x_cells);
+  if (fabs(s) > h->d.max_travel_cells)
+    return fail(MMV_ERANGE, "offset outside the window sized by max_travel_cells");
+  RigidState r;
+  if ((rc = read_rigid(h, r))) return rc;
+  r.x0 = r.xs = x_cells * h->d.dx;
+  r.s_int = (int)s;
+  return write_rigid(h, r);
+}
+
+int set_drive(mmv_handle h, const mmv_drive* drv) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!drv) return fail(MMV_EINVAL, "drive is NULL");
+  if (drv->mode < 0 || drv->mode > 2) return fail(MMV_EINVAL, "unknown drive mode");
+  if (drv->mode != MMV_DRIVE_FROZEN && h->nfilm != 2) return fail(MMV_ESTATE, "a moving drive needs two films");
+  if (drv->mode == MMV_DRIVE_SPRING && !(drv->mass > 0 && isfinite(drv->mass)))
+    return fail(MMV_EINVAL, "spring drive needs mass > 0");
+  if (!isfinite(drv->v_d) || !isfinite(drv->k) || !isfinite(drv->gamma_v) || !isfinite(drv->x_anchor0) ||
+      !isfinite(drv->x0) || !isfinite(drv->v0))
+    return fail(MMV_EINVAL, "drive parameters must be finite");
+  const double s = floor(drv->x0 / h->d.dx);
+  if (fabs(s) > h->d.max_travel_cells) return fail(MMV_ERANGE, "x0 outside the window sized by max_travel_cells");
+  RigidState r;
+  if ((rc = read_rigid(h, r))) return rc;
+  r.x0 = r.xs = drv->x0;
+  r.v0 = r.vs = (drv->mode == MMV_DRIVE_VELOCITY) ? drv->v_d : (drv->mode == MMV_DRIVE_FROZEN ? 0.0 : drv->v0);
+  r.s_int = (int)s;
+  h->drive.mode = drv->mode;
+  h->drive.v_d = drv->v_d;
+  h->drive.k = drv->k;
+  h->drive.mass = drv->mode == MMV_DRIVE_SPRING ? drv->mass : 1.0;
+  h->drive.gamma_v = drv->gamma_v;
+  h->drive.xa0 = drv->x_anchor0;
+  return write_rigid(h, r);
+}
+
+int eval_heff(mmv_handle h, int film, int term_mask, void* h_dev) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (film < 0 || film >= h->nfilm) return fail(MMV_EINVAL, "film out of range");
+  if (!h_dev) return fail(MMV_EINVAL, "h_dev is NULL");
+  if (term_mask & ~MMV_TERM_ALL) return fail(MMV_EINVAL, "unknown term bits");
+  return h->esz == 8 ? eval_typed<double>(h, film, term_mask, h_dev) : eval_typed<float>(h, film, term_mask, h_dev);
+}
+
+int llg_step(mmv_handle h, double dt, int nsteps) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!(dt > 0) || !isfinite(dt)) return fail(MMV_EINVAL, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(MMV_EINVAL, "nsteps must be >= 0");
+  return h->esz == 8 ? step_typed<double>(h, dt, nsteps) : step_typed<float>(h, dt, nsteps);
+}
+
+int stray_force(mmv_handle h, double F_out[3]) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!F_out) return fail(MMV_EINVAL, "F_out is NULL");
+  if (h->nfilm != 2) return fail(MMV_ESTATE, "stray_force needs two films");
+  rc = h->esz == 8 ? force_typed<double>(h) : force_typed<float>(h);
+  if (rc) return rc;
+  RigidState r;
+  if ((rc = read_rigid(h, r))) return rc;
+  for (int a = 0; a < 3; ++a) F_out[a] = r.F[a];
+  return report_flags(h, r);
+}
+
+int get_state(mmv_handle h, double* t, double* x_s, double* v_s, long* step) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  RigidState r;
+  if ((rc = read_rigid(h, r))) return rc;
+  if (t) *t = r.t0;
+  if (x_s) *x_s = r.x0;
+  if (v_s) *v_s = r.v0;
+  if (step) *step = (long)r.step;
+  return report_flags(h, r);
+}
+
+int get_fft_lengths(mmv_handle h, int* lx, int* ly, int* lz) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (lx) *lx = h->Lx;
+  if (ly) *ly = h->Ly;
+  if (lz) *lz = 1;
+  return MMV_OK;
+}
+
+}  // extern "C"

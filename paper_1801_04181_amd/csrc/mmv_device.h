@@ -1,0 +1,196 @@
+// Device-side building blocks: complex arithmetic, mixed-radix Stockham FFT
+// passes in LDS, XCD-aware block remapping.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "mmv_internal.h"
+
+namespace mmv {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> mk(T a, T b) {
+  cpx<T> r;
+  r.x = a;
+  r.y = b;
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
+  return mk(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> scale(cpx<T> a, T s) { return mk(a.x * s, a.y * s); }
+
+// Blocks are dispatched round-robin over the 8 XCDs.  Map the hardware block
+// id to a logical id so that each XCD works on one contiguous range of
+// logical ids (neighbouring columns / rows then share that XCD's L2).
+__device__ __forceinline__ int xcd_remap(int b, int G) {
+  const int nx = 8;
+  int per = G / nx, rem = G % nx;
+  int x = b % nx, local = b / nx;
+  return (x < rem) ? x * (per + 1) + local : rem * (per + 1) + (x - rem) * per + local;
+}
+
+// ---------------------------------------------------------------- small DFTs
+// cos / sin of 2 pi m / R for m = 1..(R-1)/2.
+template <int R> struct Roots;
+template <> struct Roots<3> {
+  static __device__ __forceinline__ double c(int m) { return -0.5; }
+  static __device__ __forceinline__ double s(int m) { return 0.86602540378443864676; }
+};
+template <> struct Roots<5> {
+  static __device__ __forceinline__ double c(int m) {
+    return m == 1 ? 0.3090169943749474241 : -0.8090169943749474241;
+  }
+  static __device__ __forceinline__ double s(int m) {
+    return m == 1 ? 0.95105651629515357212 : 0.58778525229247312917;
+  }
+};
+template <> struct Roots<7> {
+  static __device__ __forceinline__ double c(int m) {
+    return m == 1 ? 0.62348980185873353053 : (m == 2 ? -0.22252093395631440429 : -0.90096886790241912624);
+  }
+  static __device__ __forceinline__ double s(int m) {
+    return m == 1 ? 0.78183148246802980871 : (m == 2 ? 0.97492791218182360702 : 0.43388373911755812048);
+  }
+};
+
+// In-register DFT of odd length R, forward (e^{-2 pi i rq/R}) or inverse.
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_odd(cpx<T>* v) {
+  constexpr int H = (R - 1) / 2;
+  cpx<T> s[H], d[H];
+#pragma unroll
+  for (int r = 1; r <= H; ++r) {
+    s[r - 1] = v[r] + v[R - r];
+    d[r - 1] = v[r] - v[R - r];
+  }
+  cpx<T> out[R];
+  cpx<T> o0 = v[0];
+#pragma unroll
+  for (int r = 0; r < H; ++r) o0 = o0 + s[r];
+  out[0] = o0;
+#pragma unroll
+  for (int q = 1; q <= H; ++q) {
+    cpx<T> A = v[0];
+    cpx<T> B = mk<T>(0, 0);
+#pragma unroll
+    for (int r = 1; r <= H; ++r) {
+      int m = (r * q) % R;
+      T c, sn;
+      if (m <= H) {
+        c = (T)Roots<R>::c(m);
+        sn = (T)Roots<R>::s(m);
+      } else {
+        c = (T)Roots<R>::c(R - m);
+        sn = -(T)Roots<R>::s(R - m);
+      }
+      A = A + scale(s[r - 1], c);
+      B = B + scale(d[r - 1], sn);
+    }
+    if (!INV) {
+      out[q] = mk(A.x + B.y, A.y - B.x);
+      out[R - q] = mk(A.x - B.y, A.y + B.x);
+    } else {
+      out[q] = mk(A.x - B.y, A.y + B.x);
+      out[R - q] = mk(A.x + B.y, A.y - B.x);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = out[r];
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft(cpx<T>* v) {
+  if constexpr (R == 2) {
+    cpx<T> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+  } else if constexpr (R == 4) {
+    cpx<T> t0 = v[0] + v[2], t1 = v[0] - v[2];
+    cpx<T> t2 = v[1] + v[3], d = v[1] - v[3];
+    // forward: t3 = -i d ; inverse: t3 = +i d
+    cpx<T> t3 = INV ? mk(-d.y, d.x) : mk(d.y, -d.x);
+    v[0] = t0 + t2;
+    v[2] = t0 - t2;
+    v[1] = t1 + t3;
+    v[3] = t1 - t3;
+  } else {
+    dft_odd<T, R, INV>(v);
+  }
+}
+
+// One radix-R Stockham butterfly: reads src[j + r*nb], twiddles, DFT_R,
+// writes dst[(j - k) R + k + r Ns] with k = j mod Ns.  tw[t] = exp(-2 pi i t / L).
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void butterfly(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
+                                          const cpx<T>* __restrict__ tw, int j, int nb, int Ns,
+                                          int tws) {
+  int k = j % Ns;
+  cpx<T> v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
+  if (k) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      cpx<T> w = tw[r * k * tws];
+      v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
+    }
+  }
+  dft<T, R, INV>(v);
+  int base = (j - k) * R + k;
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+}
+
+// Batched in-LDS FFT of `batch` transforms of length P.L, transform t at
+// a + t*stride.  Ping-pongs between a and b; returns the buffer holding the
+// result.  Unnormalised.  Must be entered by the whole block after the data
+// are in place and visible (a __syncthreads() before the call); ends with
+// a __syncthreads().
+template <typename T, bool INV>
+__device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, const FftPlan& P, int batch, int stride,
+                           const cpx<T>* __restrict__ tw) {
+  const int L = P.L;
+  int Ns = 1;
+  for (int p = 0; p < P.np; ++p) {
+    const int R = P.r[p];
+    const int nb = L / R;
+    const int tws = L / (Ns * R);
+    const int total = nb * batch;
+    for (int w = threadIdx.x; w < total; w += blockDim.x) {
+      int t = w / nb;
+      int j = w - t * nb;
+      const cpx<T>* s = a + t * stride;
+      cpx<T>* d = b + t * stride;
+      switch (R) {
+        case 2: butterfly<T, 2, INV>(s, d, tw, j, nb, Ns, tws); break;
+        case 3: butterfly<T, 3, INV>(s, d, tw, j, nb, Ns, tws); break;
+        case 4: butterfly<T, 4, INV>(s, d, tw, j, nb, Ns, tws); break;
+        case 5: butterfly<T, 5, INV>(s, d, tw, j, nb, Ns, tws); break;
+        default: butterfly<T, 7, INV>(s, d, tw, j, nb, Ns, tws); break;
+      }
+    }
+    __syncthreads();
+    cpx<T>* tmp = a;
+    a = b;
+    b = tmp;
+    Ns *= R;
+  }
+  return a;
+}
+
+}  // namespace mmv

@@ -1,0 +1,88 @@
+// Structures shared by the host runtime and the kernels (plain data).
+#pragma once
+#include <stdint.h>
+
+namespace mmv {
+
+constexpr int MAX_PASSES = 16;
+constexpr int MAX_OUT = 24;
+
+// Mixed-radix plan: L = r[0] * r[1] * ... * r[np-1], radices in {2,3,4,5,7}.
+struct FftPlan {
+  int L;
+  int np;
+  int r[MAX_PASSES];
+};
+
+// One output channel of the column pass:
+//   out(kx, ky) = sum_b K_{kc[b]}(kx, ky) * mhat_{src, b}(kx, ky)
+// followed by an inverse y-transform and the rows [row0, row0 + nrows)
+// (cyclic in Ly) written to spec2 at element offset `off` (row stride Kx).
+// Kernel spectra are stored as one real number per (kx, ky <= Ly/2):
+//   fl bit0: the spectrum is imaginary (value = i * stored)
+//   fl bit1: the kernel is odd in y (stored(Ly-ky) = -stored(ky))
+//   fl bit2: negate (the kernel of the mirrored layer -dz)
+struct OutCh {
+  int src;
+  int kc[3];
+  int fl[3];
+  int row0;
+  int nrows;
+  long long off;
+};
+
+struct OutTable {
+  int n;
+  OutCh ch[MAX_OUT];
+};
+
+// Rigid-body state of the slider, float64 on the device (Eq. 15).
+struct RigidState {
+  double x0, v0, t0;  // at the start of the step
+  double xs, vs, ts;  // at the current RK stage
+  double ax, av;      // RK accumulators
+  double F[3];        // last force [N]
+  long long step;
+  int s_int;          // floor(x / dx), fixed within a step
+  int flags;          // FLAG_* (sticky until read by the host)
+};
+
+enum { FLAG_RANGE = 1, FLAG_NUMERIC = 2 };
+
+struct DriveP {
+  int mode;
+  double v_d, k, mass, gamma_v, xa0;
+};
+
+enum { MODE_EVAL = 0, MODE_STAGE = 1, MODE_FORCE = 2 };
+
+// Parameters of the fused row kernel (inverse row transform, spline,
+// local fields, LLG stage, force partials).
+struct RowParams {
+  int mode;       // MODE_*
+  int stage;      // RK stage 0..3
+  int eval_film;  // MODE_EVAL: film written to hout
+  int term_mask;
+  int nfilm, nx, ny;
+  int N2x, Kx;
+  int halo, M, travel, kfir;
+  int ntask;
+  int with_force;  // MODE_STAGE: accumulate F_x partials
+  int full_force;  // MODE_FORCE: all three components
+  double dx, dy, dz;
+  double pref_ex;  // 2 A / (mu0 Ms)
+  double pref_an;  // 2 Ku / (mu0 Ms)
+  double u[3], hext[3];
+  double gam;      // gamma0 / (1 + alpha^2)
+  double alpha;
+  double dt;
+  double force_scale;  // mu0 Ms V
+  long long off_self[2][3];
+  long long off_cross[2][3];
+  int cross_row0[2];      // row stored first in the cross channel
+  long long off_fp[3], off_fm[3];  // G at z_s+1 and z_s-1 (force)
+  DriveP drive;
+  FftPlan px;
+};
+
+}  // namespace mmv

@@ -1,0 +1,806 @@
+// HIP kernels of the two-film hot path (gfx950).
+//
+//   k_row_fwd    forward real-to-complex transform of each row of m (the
+//                x pass of the zero-padded demagnetising convolution,
+//                Sec. III.A, Eq. 6), one row per block.
+//   k_col        per kx column: y transform of the six magnetisation
+//                channels, multiplication by the kernel spectra (tensor N of
+//                Eq. 6 or potential kernel S of Eq. 8), inverse y transform
+//                of each requested output channel.
+//   k_row_stage  per film row: inverse x transforms, prefiltered cubic
+//                B-spline sampling of the other film's field at the sub-cell
+//                offset (Sec. II.A, III.A), exchange / anisotropy / Zeeman
+//                terms, LLG torque (Eq. 1) and RK4 stage update, partial sums
+//                of the force of Eq. (3); the last block to finish reduces the
+//                partials in float64 and advances the slider (Eq. 15).
+//   k_kernel_real, k_colpack
+//                one-time float64 construction of the kernel spectra.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include "mmv_device.h"
+#include "mmv_kernels.h"
+
+namespace mmv {
+
+// ------------------------------------------------------------ x transform
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_row_fwd(const T* __restrict__ src, cpx<T>* __restrict__ dst, int nrows, int nin, int N2x,
+              int Kx, FftPlan P, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* stp = stw + N2x;
+  cpx<T>* a = stp + N2x + 1;
+  cpx<T>* b = a + N2x;
+  const int row = blockIdx.x;
+  if (row >= nrows) return;
+  for (int t = threadIdx.x; t < N2x; t += blockDim.x) stw[t] = tw[t];
+  for (int t = threadIdx.x; t <= N2x; t += blockDim.x) stp[t] = twp[t];
+  const T* s = src + (size_t)row * nin;
+  for (int n = threadIdx.x; n < N2x; n += blockDim.x) {
+    const int i0 = 2 * n, i1 = 2 * n + 1;
+    a[n] = mk<T>(i0 < nin ? s[i0] : T(0), i1 < nin ? s[i1] : T(0));
+  }
+  __syncthreads();
+  cpx<T>* Z = fft_lds<T, false>(a, b, P, 1, N2x, stw);
+  cpx<T>* out = dst + (size_t)row * Kx;
+  for (int k = threadIdx.x; k <= N2x; k += blockDim.x) {
+    cpx<T> zk = Z[k == N2x ? 0 : k];
+    cpx<T> zm = Z[k == 0 ? 0 : N2x - k];
+    zm.y = -zm.y;
+    cpx<T> e = zk + zm;
+    cpx<T> p = cmul(stp[k], zk - zm);
+    out[k] = mk<T>(T(0.5) * (e.x + p.y), T(0.5) * (e.y - p.x));
+  }
+}
+
+// ------------------------------------------------------------ y pass
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_col(const cpx<T>* __restrict__ spec1, cpx<T>* __restrict__ spec2, const T* __restrict__ kern,
+          int Kx, int Ly, int Kyh, int ny, int nin_ch, int CB, int bufch, FftPlan P,
+          const cpx<T>* __restrict__ twy, OutTable tab) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* A = stw + Ly;
+  cpx<T>* B = A + (size_t)bufch * CB * Ly;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int kx0 = blk * CB;
+  if (kx0 >= Kx) return;
+  const int ncol = min(CB, Kx - kx0);
+  for (int t = threadIdx.x; t < Ly; t += blockDim.x) stw[t] = twy[t];
+  const int nload = nin_ch * ncol * Ly;
+  for (int t = threadIdx.x; t < nload; t += blockDim.x) {
+    const int c = t % ncol;
+    const int rest = t / ncol;
+    const int y = rest % Ly;
+    const int ch = rest / Ly;
+    cpx<T> v = mk<T>(0, 0);
+    if (y < ny) v = spec1[((size_t)ch * ny + y) * Kx + kx0 + c];
+    A[(ch * ncol + c) * Ly + y] = v;
+  }
+  __syncthreads();
+  cpx<T>* X = fft_lds<T, false>(A, B, P, nin_ch * ncol, Ly, stw);
+  cpx<T>* W0 = (X == A) ? B : A;
+  cpx<T>* W1 = W0 + 3 * ncol * Ly;
+  for (int og = 0; og < tab.n; og += 3) {
+    const int ng = min(3, tab.n - og);
+    const int nprod = ng * ncol * Ly;
+    for (int t = threadIdx.x; t < nprod; t += blockDim.x) {
+      const int ky = t % Ly;
+      const int rest = t / Ly;
+      const int c = rest % ncol;
+      const int o = rest / ncol;
+      const OutCh& oc = tab.ch[og + o];
+      const bool upper = ky >= Kyh;
+      const int kyr = upper ? Ly - ky : ky;
+      cpx<T> acc = mk<T>(0, 0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const int kc = oc.kc[b];
+        if (kc < 0) continue;
+        const int fl = oc.fl[b];
+        T s = kern[((size_t)kc * Kx + kx0 + c) * Kyh + kyr];
+        const bool neg = ((fl & 4) != 0) != (upper && (fl & 2));
+        if (neg) s = -s;
+        const cpx<T> mh = X[((oc.src * 3 + b) * ncol + c) * Ly + ky];
+        if (fl & 1)
+          acc = acc + mk<T>(-s * mh.y, s * mh.x);
+        else
+          acc = acc + mk<T>(s * mh.x, s * mh.y);
+      }
+      W0[(o * ncol + c) * Ly + ky] = acc;
+    }
+    __syncthreads();
+    cpx<T>* Y = fft_lds<T, true>(W0, W1, P, ng * ncol, Ly, stw);
+    for (int o = 0; o < ng; ++o) {
+      const OutCh& oc = tab.ch[og + o];
+      const int nw = oc.nrows * ncol;
+      for (int t = threadIdx.x; t < nw; t += blockDim.x) {
+        const int c = t % ncol;
+        const int r = t / ncol;
+        int yy = (oc.row0 + r) % Ly;
+        if (yy < 0) yy += Ly;
+        spec2[oc.off + (size_t)r * Kx + kx0 + c] = Y[(o * ncol + c) * Ly + yy];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ row kernel
+template <typename T> struct FirHalf { static constexpr int K = 16; };
+template <> struct FirHalf<double> { static constexpr int K = 30; };
+
+__device__ __forceinline__ int reflect_idx(int k, int M) {
+  if (M == 1) return 0;
+  const int P = 2 * M - 2;
+  k %= P;
+  if (k < 0) k += P;
+  return k > M - 1 ? P - k : k;
+}
+
+__device__ __forceinline__ double beta3(double t) {
+  double a = fabs(t);
+  if (a <= 1.0) return 2.0 / 3.0 - a * a + 0.5 * a * a * a;
+  if (a <= 2.0) {
+    double b = 2.0 - a;
+    return b * b * b / 6.0;
+  }
+  return 0.0;
+}
+
+// Inverse real transform of nb rows (Hermitian halves X[0..N2x] at rowp[b])
+// into LDS; result buffer viewed as T* holds x[0..Lx) of each row at stride
+// 2*N2x reals.
+template <typename T>
+__device__ cpx<T>* c2r_rows(const cpx<T>* const* rowp, int nb, cpx<T>* fa, cpx<T>* fb, int N2x,
+                            const FftPlan& P, const cpx<T>* stw, const cpx<T>* stp) {
+  const int tot = nb * N2x;
+  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+    const int b = t / N2x;
+    const int k = t - b * N2x;
+    const cpx<T>* X = rowp[b];
+    cpx<T> xk = X[k];
+    cpx<T> xm = X[N2x - k];
+    xm.y = -xm.y;
+    cpx<T> s = xk + xm;
+    cpx<T> d = cmulc(xk - xm, stp[k]);
+    fa[b * N2x + k] = mk<T>(s.x - d.y, s.y + d.x);
+  }
+  __syncthreads();
+  return fft_lds<T, true>(fa, fb, P, nb, N2x, stw);
+}
+
+// Copy the spline window of one real row into ext[E + k], k in [-E, M+E),
+// with whole-sample mirror extension; W0 = lattice index of window sample 0.
+template <typename T>
+__device__ void load_window(const T* __restrict__ xr, T* ext, int W0, int M, int E, int Lx) {
+  for (int k = threadIdx.x; k < M + 2 * E; k += blockDim.x) {
+    int w = reflect_idx(k - E, M);
+    int X = (W0 + w) % Lx;
+    if (X < 0) X += Lx;
+    ext[k] = xr[X];
+  }
+}
+
+// Spline value at window coordinate u = k0 + frac: sum_q g_q ext(k0 + q).
+template <typename T, int K>
+__device__ __forceinline__ T fir_eval(const T* ext, const T* g, int k0, int E) {
+  const T* p = ext + E + k0 - K - 1;
+  T acc = 0;
+#pragma unroll
+  for (int q = 0; q < 2 * K + 4; ++q) acc += g[q] * p[q];
+  return acc;
+}
+
+__device__ void rigid_stage(RigidState* R, const DriveP& d, int stage, double F, double h,
+                            double dxc, int travel) {
+  const double x = R->xs, v = R->vs, t = R->ts;
+  double dxdt = 0.0, dvdt = 0.0;
+  if (d.mode == 1) {
+    dxdt = d.v_d;
+  } else if (d.mode == 2) {
+    dxdt = v;
+    dvdt = (d.k * (d.v_d * t + d.xa0 - x) - d.gamma_v * d.mass * v + F) / d.mass;
+  }
+  R->F[0] = F;
+  if (stage == 0) {
+    R->ax = dxdt;
+    R->av = dvdt;
+    R->xs = R->x0 + 0.5 * h * dxdt;
+    R->vs = R->v0 + 0.5 * h * dvdt;
+    R->ts = R->t0 + 0.5 * h;
+  } else if (stage == 1) {
+    R->ax += 2.0 * dxdt;
+    R->av += 2.0 * dvdt;
+    R->xs = R->x0 + 0.5 * h * dxdt;
+    R->vs = R->v0 + 0.5 * h * dvdt;
+    R->ts = R->t0 + 0.5 * h;
+  } else if (stage == 2) {
+    R->ax += 2.0 * dxdt;
+    R->av += 2.0 * dvdt;
+    R->xs = R->x0 + h * dxdt;
+    R->vs = R->v0 + h * dvdt;
+    R->ts = R->t0 + h;
+  } else {
+    const double xn = R->x0 + h / 6.0 * (R->ax + dxdt);
+    const double vn = R->v0 + h / 6.0 * (R->av + dvdt);
+    R->t0 = R->t0 + h;
+    R->ts = R->t0;
+    R->x0 = R->xs = xn;
+    R->v0 = R->vs = vn;
+    R->step += 1;
+    if (isfinite(xn)) {
+      const double s = floor(xn / dxc);
+      if (fabs(s) > (double)travel) {
+        R->flags |= FLAG_RANGE;
+      } else {
+        R->s_int = (int)s;
+      }
+    } else {
+      R->flags |= FLAG_NUMERIC;
+    }
+  }
+}
+
+// Block layout: tasks [film 0 rows][film 1 rows][film 1 rows -1 and ny]
+// (MODE_STAGE), [eval_film rows] (MODE_EVAL), [film 1 rows -1..ny]
+// (MODE_FORCE).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_row_stage(RowParams p, const cpx<T>* __restrict__ spec2, const T* __restrict__ mst,
+                const T* m0, T* mnext, T* __restrict__ acc,
+                T* __restrict__ hout, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp,
+                RigidState* __restrict__ rigid, double* __restrict__ partial,
+                unsigned int* __restrict__ counter) {
+  constexpr int K = FirHalf<T>::K;
+  constexpr int NQ = 2 * K + 4;
+  constexpr int E = K + 4;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nx = p.nx, ny = p.ny, N2x = p.N2x, M = p.M, Lx = 2 * N2x;
+  const int nfc = p.full_force ? 3 : 1;
+  cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* stp = stw + N2x;
+  cpx<T>* fa = stp + N2x + 1;
+  cpx<T>* fb = fa + 3 * N2x;
+  T* ext = reinterpret_cast<T*>(fb + 3 * N2x);
+  T* gs = ext + M + 2 * E;   // weights, slider samples base field
+  T* gb = gs + NQ;           // weights, base samples slider field
+  T* H = gb + NQ;            // [3][nx] demag accumulation
+  T* gc = H + 3 * nx;        // [3][nx+2] slider cross field at i = -1..nx
+  T* gp = gc + 3 * (nx + 2); // [nfc][nx] force layer z_s+1
+  T* gm = gp + nfc * nx;     // [nfc][nx] force layer z_s-1
+  double* red = reinterpret_cast<double*>(gm + nfc * nx + 2);
+  red = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(red) + 15) & ~uintptr_t(15));
+  __shared__ const cpx<T>* rowp[6];
+  __shared__ int s_last;
+  __shared__ int s_bad;
+
+  const int task = blockIdx.x;
+  int film, y;
+  if (p.mode == MODE_STAGE) {
+    if (task < p.nfilm * ny) {
+      film = task / ny;
+      y = task - film * ny;
+    } else {
+      film = 1;
+      y = (task == p.nfilm * ny) ? -1 : ny;
+    }
+  } else if (p.mode == MODE_EVAL) {
+    film = p.eval_film;
+    y = task;
+  } else {
+    film = 1;
+    y = task - 1;
+  }
+  const bool cell_row = (y >= 0 && y < ny);
+  const bool two = (p.nfilm == 2);
+  const bool need_force =
+      two && film == 1 && ((p.mode == MODE_STAGE && p.with_force) || p.mode == MODE_FORCE);
+  const bool need_cross = two && ((p.term_mask & 16) || need_force);
+
+  for (int t = threadIdx.x; t < N2x; t += blockDim.x) stw[t] = tw[t];
+  for (int t = threadIdx.x; t <= N2x; t += blockDim.x) stp[t] = twp[t];
+  if (threadIdx.x == 0) s_bad = 0;
+
+  // slider offset of this stage
+  const double xs = rigid->xs;
+  const int s_int = rigid->s_int;
+  double xp = xs / p.dx - (double)s_int;
+  bool xp_bad = !(xp >= -1.0 && xp < 2.0);
+  if (xp_bad) xp = 0.0;
+  const double fls = floor(xp), flb = floor(-xp);
+  const double frs = xp - fls, frb = -xp - flb;
+  for (int tq = threadIdx.x; tq < 2 * NQ; tq += blockDim.x) {
+    const int q = (tq % NQ) - K - 1;
+    const double fr = tq < NQ ? frs : frb;
+    const double z1 = -0.26794919243112270647;  // sqrt(3) - 2, pole of the cubic B-spline prefilter
+    double g = 0.0;
+    for (int t = -1; t <= 2; ++t) {
+      const int j = t - q;
+      if (j >= -K && j <= K) g += beta3(fr - t) * 1.7320508075688772935 * pow(-z1, (double)abs(j)) *
+                                   ((abs(j) & 1) ? -1.0 : 1.0);
+    }
+    (tq < NQ ? gs : gb)[tq % NQ] = (T)g;
+  }
+  for (int t = threadIdx.x; t < 3 * nx; t += blockDim.x) H[t] = T(0);
+  __syncthreads();
+
+  // --- own demagnetising field
+  if (cell_row && (p.term_mask & 8)) {
+    for (int c = threadIdx.x; c < 3; c += blockDim.x) rowp[c] = spec2 + p.off_self[film][c] + (size_t)y * p.Kx;
+    __syncthreads();
+    cpx<T>* Z = c2r_rows<T>(rowp, 3, fa, fb, N2x, p.px, stw, stp);
+    const T* xr = reinterpret_cast<const T*>(Z);
+    for (int t = threadIdx.x; t < 3 * nx; t += blockDim.x) {
+      const int c = t / nx, i = t - c * nx;
+      H[t] = xr[(size_t)c * Lx + i];
+    }
+    __syncthreads();
+  }
+
+  // --- the other film's field, sampled at the shifted lattice
+  const int h = p.halo;
+  if (need_cross) {
+    const int ncomp = (cell_row || p.full_force) ? 3 : 1;
+    const int stored = y - p.cross_row0[film];
+    for (int c = threadIdx.x; c < ncomp; c += blockDim.x)
+      rowp[c] = spec2 + p.off_cross[film][c] + (size_t)stored * p.Kx;
+    __syncthreads();
+    cpx<T>* Z = c2r_rows<T>(rowp, ncomp, fa, fb, N2x, p.px, stw, stp);
+    const T* xr = reinterpret_cast<const T*>(Z);
+    const int W0 = (film == 1) ? s_int - h : -s_int - h;
+    const int fl = (int)((film == 1) ? fls : flb);
+    const T* g = (film == 1) ? gs : gb;
+    for (int c = 0; c < ncomp; ++c) {
+      load_window<T>(xr + (size_t)c * Lx, ext, W0, M, E, Lx);
+      __syncthreads();
+      if (film == 1) {
+        for (int i = threadIdx.x - 1; i <= nx; i += blockDim.x) {
+          const T v = fir_eval<T, K>(ext, g, i + h + fl, E);
+          gc[c * (nx + 2) + i + 1] = v;
+          if (cell_row && i >= 0 && i < nx && (p.term_mask & 16)) H[c * nx + i] += v;
+        }
+      } else {
+        for (int i = threadIdx.x; i < nx; i += blockDim.x)
+          H[c * nx + i] += fir_eval<T, K>(ext, g, i + h + fl, E);
+      }
+      __syncthreads();
+    }
+  }
+  // --- force layers z_s +/- 1
+  if (need_force && cell_row) {
+    const int nb = 2 * nfc;
+    for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+      const int a = t % nfc;
+      const long long off = t < nfc ? p.off_fp[a] : p.off_fm[a];
+      rowp[t] = spec2 + off + (size_t)y * p.Kx;
+    }
+    __syncthreads();
+    // up to six rows: two batches of three
+    for (int b0 = 0; b0 < nb; b0 += 3) {
+      const int bn = min(3, nb - b0);
+      cpx<T>* Z = c2r_rows<T>(rowp + b0, bn, fa, fb, N2x, p.px, stw, stp);
+      const T* xr = reinterpret_cast<const T*>(Z);
+      for (int c = 0; c < bn; ++c) {
+        const int idx = b0 + c;
+        T* dstp = idx < nfc ? gp + idx * nx : gm + (idx - nfc) * nx;
+        load_window<T>(xr + (size_t)c * Lx, ext, s_int - h, M, E, Lx);
+        __syncthreads();
+        for (int i = threadIdx.x; i < nx; i += blockDim.x)
+          dstp[i] = fir_eval<T, K>(ext, gs, i + h + (int)fls, E);
+        __syncthreads();
+      }
+    }
+  }
+
+  // --- per cell: local terms, LLG stage, force partials
+  const size_t plane = (size_t)ny * nx;
+  double fpart[3] = {0.0, 0.0, 0.0};
+  const T* ms = mst + (size_t)film * 3 * plane;
+  const T idx2 = T(1.0 / (p.dx * p.dx)), idy2 = T(1.0 / (p.dy * p.dy));
+  const T pex = (T)p.pref_ex, pan = (T)p.pref_an;
+  const T u0 = (T)p.u[0], u1 = (T)p.u[1], u2 = (T)p.u[2];
+  const T gam = (T)p.gam, alp = (T)p.alpha;
+  const T hdt = (T)p.dt;
+  bool bad = false;
+  if (cell_row && p.mode != MODE_FORCE) {
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+      const size_t id = (size_t)y * nx + i;
+      const T mx = ms[id], my = ms[plane + id], mz = ms[2 * plane + id];
+      T hx = H[i], hy = H[nx + i], hz = H[2 * nx + i];
+      if (p.term_mask & 1) {
+        T ex = 0, ey = 0, ez = 0;
+        if (i > 0) {
+          ex += (ms[id - 1] - mx) * idx2;
+          ey += (ms[plane + id - 1] - my) * idx2;
+          ez += (ms[2 * plane + id - 1] - mz) * idx2;
+        }
+        if (i < nx - 1) {
+          ex += (ms[id + 1] - mx) * idx2;
+          ey += (ms[plane + id + 1] - my) * idx2;
+          ez += (ms[2 * plane + id + 1] - mz) * idx2;
+        }
+        if (y > 0) {
+          ex += (ms[id - nx] - mx) * idy2;
+          ey += (ms[plane + id - nx] - my) * idy2;
+          ez += (ms[2 * plane + id - nx] - mz) * idy2;
+        }
+        if (y < ny - 1) {
+          ex += (ms[id + nx] - mx) * idy2;
+          ey += (ms[plane + id + nx] - my) * idy2;
+          ez += (ms[2 * plane + id + nx] - mz) * idy2;
+        }
+        hx += pex * ex;
+        hy += pex * ey;
+        hz += pex * ez;
+      }
+      if (p.term_mask & 2) {
+        const T mu = mx * u0 + my * u1 + mz * u2;
+        hx += pan * mu * u0;
+        hy += pan * mu * u1;
+        hz += pan * mu * u2;
+      }
+      if (p.term_mask & 4) {
+        hx += (T)p.hext[0];
+        hy += (T)p.hext[1];
+        hz += (T)p.hext[2];
+      }
+      if (p.mode == MODE_EVAL) {
+        hout[id] = hx;
+        hout[plane + id] = hy;
+        hout[2 * plane + id] = hz;
+        continue;
+      }
+      // LLG right-hand side, Landau-Lifshitz form of Eq. (1)
+      const T cx = my * hz - mz * hy, cy = mz * hx - mx * hz, cz = mx * hy - my * hx;
+      const T dx_ = my * cz - mz * cy, dy_ = mz * cx - mx * cz, dz_ = mx * cy - my * cx;
+      const T kx = -gam * (cx + alp * dx_), ky = -gam * (cy + alp * dy_), kz = -gam * (cz + alp * dz_);
+      const size_t fo = (size_t)film * 3 * plane + id;
+      const T ox = m0[fo], oy = m0[fo + plane], oz = m0[fo + 2 * plane];
+      if (p.stage == 0) {
+        acc[fo] = kx;
+        acc[fo + plane] = ky;
+        acc[fo + 2 * plane] = kz;
+        const T c = T(0.5) * hdt;
+        mnext[fo] = ox + c * kx;
+        mnext[fo + plane] = oy + c * ky;
+        mnext[fo + 2 * plane] = oz + c * kz;
+      } else if (p.stage < 3) {
+        acc[fo] += T(2) * kx;
+        acc[fo + plane] += T(2) * ky;
+        acc[fo + 2 * plane] += T(2) * kz;
+        const T c = (p.stage == 1) ? T(0.5) * hdt : hdt;
+        mnext[fo] = ox + c * kx;
+        mnext[fo + plane] = oy + c * ky;
+        mnext[fo + 2 * plane] = oz + c * kz;
+      } else {
+        const T c = hdt / T(6);
+        T nx_ = ox + c * (acc[fo] + kx);
+        T ny_ = oy + c * (acc[fo + plane] + ky);
+        T nz_ = oz + c * (acc[fo + 2 * plane] + kz);
+        const T nrm = sqrt(nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
+        if (!(nrm > T(0)) || !isfinite(nrm)) bad = true;
+        const T inv = T(1) / nrm;
+        mnext[fo] = nx_ * inv;
+        mnext[fo + plane] = ny_ * inv;
+        mnext[fo + 2 * plane] = nz_ * inv;
+      }
+    }
+  }
+  if (need_force) {
+    // Eq. (3), component a: sum_i m_x d_x G_a + m_y d_y G_a + m_z d_z G_a,
+    // the y term summed by parts over rows -1..ny.
+    const double i2dx = 1.0 / (2.0 * p.dx), i2dy = 1.0 / (2.0 * p.dy), i2dz = 1.0 / (2.0 * p.dz);
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+      const double myl = (y - 1 >= 0 && y - 1 < ny) ? (double)ms[plane + (size_t)(y - 1) * nx + i] : 0.0;
+      const double myh = (y + 1 >= 0 && y + 1 < ny) ? (double)ms[plane + (size_t)(y + 1) * nx + i] : 0.0;
+      double mx = 0, mz = 0;
+      if (cell_row) {
+        mx = ms[(size_t)y * nx + i];
+        mz = ms[2 * plane + (size_t)y * nx + i];
+      }
+      for (int a = 0; a < nfc; ++a) {
+        const T* ga = gc + a * (nx + 2);
+        double v = (double)ga[i + 1] * (myl - myh) * i2dy;
+        if (cell_row) {
+          v += mx * ((double)ga[i + 2] - (double)ga[i]) * i2dx;
+          v += mz * ((double)gp[a * nx + i] - (double)gm[a * nx + i]) * i2dz;
+        }
+        fpart[a] += v;
+      }
+    }
+  }
+  if (bad) atomicOr(&s_bad, 1);
+  // block reduction of the force partials, fixed order
+  for (int a = 0; a < 3; ++a) red[a * blockDim.x + threadIdx.x] = fpart[a];
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int a = 0; a < 3; ++a) red[a * blockDim.x + threadIdx.x] += red[a * blockDim.x + threadIdx.x + s];
+    __syncthreads();
+  }
+  if (p.mode == MODE_EVAL) return;
+  if (threadIdx.x == 0) {
+    for (int a = 0; a < 3; ++a) partial[(size_t)task * 3 + a] = red[a * blockDim.x];
+    if (s_bad || xp_bad) atomicOr(&rigid->flags, s_bad ? (int)FLAG_NUMERIC : (int)FLAG_RANGE);
+    __threadfence();
+    const unsigned prev = atomicAdd(counter, 1u);
+    s_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  double sum[3] = {0.0, 0.0, 0.0};
+  for (int t = threadIdx.x; t < (int)gridDim.x; t += blockDim.x)
+    for (int a = 0; a < 3; ++a)
+      sum[a] += __hip_atomic_load(&partial[(size_t)t * 3 + a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int a = 0; a < 3; ++a) red[a * blockDim.x + threadIdx.x] = sum[a];
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int a = 0; a < 3; ++a) red[a * blockDim.x + threadIdx.x] += red[a * blockDim.x + threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double F0 = p.force_scale * red[0];
+    if (p.mode == MODE_FORCE) {
+      for (int a = 0; a < 3; ++a) rigid->F[a] = p.force_scale * red[a * blockDim.x];
+    } else {
+      rigid_stage(rigid, p.drive, p.stage, F0, p.dt, p.dx, p.travel);
+    }
+    __threadfence();
+    atomicExch(counter, 0u);
+  }
+}
+
+// ------------------------------------------------------------ kernel init (float64)
+__device__ double f_newell(double x, double y, double z) {
+  x = fabs(x);
+  y = fabs(y);
+  z = fabs(z);
+  const double x2 = x * x, y2 = y * y, z2 = z * z;
+  const double R = sqrt(x2 + y2 + z2);
+  const double rxz = sqrt(x2 + z2), rxy = sqrt(x2 + y2);
+  double t = 0.0;
+  if (rxz > 0) t += 0.5 * y * (z2 - x2) * asinh(y / rxz);
+  if (rxy > 0) t += 0.5 * z * (y2 - x2) * asinh(z / rxy);
+  if (x * R > 0) t -= x * y * z * atan(y * z / (x * R));
+  return t + (2.0 * x2 - y2 - z2) * R / 6.0;
+}
+
+__device__ double g_newell(double x, double y, double z) {
+  const double sg = (x > 0 ? 1.0 : (x < 0 ? -1.0 : 0.0)) * (y > 0 ? 1.0 : (y < 0 ? -1.0 : 0.0));
+  x = fabs(x);
+  y = fabs(y);
+  z = fabs(z);
+  const double x2 = x * x, y2 = y * y, z2 = z * z;
+  const double R = sqrt(x2 + y2 + z2);
+  const double rxy = sqrt(x2 + y2), ryz = sqrt(y2 + z2), rxz = sqrt(x2 + z2);
+  double t = 0.0;
+  if (rxy > 0) t += x * y * z * asinh(z / rxy);
+  if (ryz > 0) t += y / 6.0 * (3.0 * z2 - y2) * asinh(x / ryz);
+  if (rxz > 0) t += x / 6.0 * (3.0 * z2 - x2) * asinh(y / rxz);
+  if (z * R > 0) t -= z * z * z / 6.0 * atan(x * y / (z * R));
+  if (y * R > 0) t -= z * y2 / 2.0 * atan(x * z / (y * R));
+  if (x * R > 0) t -= z * x2 / 2.0 * atan(y * z / (x * R));
+  t -= x * y * R / 3.0;
+  return sg * t;
+}
+
+// 27-point difference of Newell's f (use_g = 0) or g (use_g = 1); the
+// first argument triple is already permuted for the requested component.
+__device__ double newell_diff(int use_g, double X, double Y, double Z, double a, double b, double c) {
+  const double w[3] = {-1.0, 2.0, -1.0};
+  double acc = 0.0;
+  for (int e1 = -1; e1 <= 1; ++e1)
+    for (int e2 = -1; e2 <= 1; ++e2)
+      for (int e3 = -1; e3 <= 1; ++e3) {
+        const double ww = w[e1 + 1] * w[e2 + 1] * w[e3 + 1];
+        const double xx = X + e1 * a, yy = Y + e2 * b, zz = Z + e3 * c;
+        acc += ww * (use_g ? g_newell(xx, yy, zz) : f_newell(xx, yy, zz));
+      }
+  return acc / (4.0 * M_PI * a * b * c);
+}
+
+// comp: 0 xx, 1 yy, 2 zz, 3 xy, 4 xz, 5 yz.  Evaluated at |r| with the
+// component's parity sign; point dipole beyond rc * max(dx, dy, dz).
+__device__ double tensor_comp(int comp, double X, double Y, double Z, double dx, double dy, double dz,
+                              double rc) {
+  double sign = 1.0;
+  auto sgn = [](double v) { return v > 0 ? 1.0 : (v < 0 ? -1.0 : 0.0); };
+  if (comp == 3) sign = sgn(X) * sgn(Y);
+  if (comp == 4) sign = sgn(X) * sgn(Z);
+  if (comp == 5) sign = sgn(Y) * sgn(Z);
+  if (sign == 0.0) return 0.0;
+  X = fabs(X);
+  Y = fabs(Y);
+  Z = fabs(Z);
+  const double r2 = X * X + Y * Y + Z * Z;
+  const double rmax = rc * fmax(dx, fmax(dy, dz));
+  if (r2 >= rmax * rmax) {
+    const double r[3] = {X, Y, Z};
+    const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+    const double v = dx * dy * dz / (4.0 * M_PI * r2 * sqrt(r2)) *
+                     ((comp < 3 ? 1.0 : 0.0) - 3.0 * r[ia[comp]] * r[ib[comp]] / r2);
+    return sign * v;
+  }
+  double v;
+  switch (comp) {
+    case 0: v = newell_diff(0, X, Y, Z, dx, dy, dz); break;
+    case 1: v = newell_diff(0, Y, X, Z, dy, dx, dz); break;
+    case 2: v = newell_diff(0, Z, Y, X, dz, dy, dx); break;
+    case 3: v = newell_diff(1, X, Y, Z, dx, dy, dz); break;
+    case 4: v = newell_diff(1, X, Z, Y, dx, dz, dy); break;
+    default: v = newell_diff(1, Y, Z, X, dy, dz, dx); break;
+  }
+  return sign * v;
+}
+
+// Potential-kernel helpers (Eq. 8 by the divergence theorem).
+__device__ double face_F(double u, double v, double w) {
+  const double u2 = u * u, v2 = v * v, w2 = w * w;
+  const double R = sqrt(u2 + v2 + w2);
+  const double ruw = sqrt(u2 + w2), rvw = sqrt(v2 + w2);
+  double t = 0.0;
+  if (ruw > 0) t += u * asinh(v / ruw);
+  if (rvw > 0) t += v * asinh(u / rvw);
+  if (w != 0.0 && R > 0) t -= w * atan(u * v / (w * R));
+  return t;
+}
+__device__ double face_rect(double u1, double u2, double v1, double v2, double w) {
+  return face_F(u2, v2, w) - face_F(u1, v2, w) - face_F(u2, v1, w) + face_F(u1, v1, w);
+}
+__device__ double s_axis(double A, double B, double C, double a, double b, double c) {
+  const double f1 = face_rect(-b / 2 - B, b / 2 - B, -c / 2 - C, c / 2 - C, A - a / 2);
+  const double f2 = face_rect(-b / 2 - B, b / 2 - B, -c / 2 - C, c / 2 - C, A + a / 2);
+  return (f1 - f2) / (4.0 * M_PI);
+}
+__device__ double s_comp(int comp, double X, double Y, double Z, double dx, double dy, double dz) {
+  if (comp == 0) return s_axis(X, Y, Z, dx, dy, dz);
+  if (comp == 1) return s_axis(Y, X, Z, dy, dx, dz);
+  return s_axis(Z, X, Y, dz, dx, dy);
+}
+
+// Real kernel on the cyclic Lx x Ly grid of one layer (dzc cells apart):
+// displacement index r maps to r (r <= L/2) or r - L; odd components are
+// zeroed on the Nyquist index of an even length so that every spectrum is
+// purely real or imaginary.
+__global__ void k_kernel_real(double* __restrict__ out, int Lx, int Ly, int kind, int comp, double dzc,
+                              double dx, double dy, double dz, double rc, double scale) {
+  const int ry = blockIdx.y;
+  if (ry >= Ly) return;
+  for (int rx = blockIdx.x * blockDim.x + threadIdx.x; rx < Lx; rx += gridDim.x * blockDim.x) {
+  const int ix = rx <= Lx / 2 ? rx : rx - Lx;
+  const int iy = ry <= Ly / 2 ? ry : ry - Ly;
+  int oddx, oddy;
+  double v;
+  if (kind == 0) {
+    const int px[6] = {0, 0, 0, 1, 1, 0}, py[6] = {0, 0, 0, 1, 0, 1};
+    oddx = px[comp];
+    oddy = py[comp];
+    v = tensor_comp(comp, ix * dx, iy * dy, dzc * dz, dx, dy, dz, rc);
+  } else {
+    oddx = (comp == 0);
+    oddy = (comp == 1);
+    v = s_comp(comp, ix * dx, iy * dy, dzc * dz, dx, dy, dz);
+  }
+  if ((Lx % 2 == 0 && rx == Lx / 2 && oddx) || (Ly % 2 == 0 && ry == Ly / 2 && oddy)) v = 0.0;
+  out[(size_t)ry * Lx + rx] = scale * v;
+  }
+}
+
+// y transform of the row spectra of a real kernel, keeping the real or
+// imaginary part for ky in [0, Kyh).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_colpack(const cpx<double>* __restrict__ spec, T* __restrict__ out, int Kx, int Ly, int Kyh,
+              FftPlan P, const cpx<double>* __restrict__ twy, int imag) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<double>* stw = reinterpret_cast<cpx<double>*>(smem_raw);
+  cpx<double>* a = stw + Ly;
+  cpx<double>* b = a + Ly;
+  const int kx = blockIdx.x;
+  for (int t = threadIdx.x; t < Ly; t += blockDim.x) {
+    stw[t] = twy[t];
+    a[t] = spec[(size_t)t * Kx + kx];
+  }
+  __syncthreads();
+  cpx<double>* Y = fft_lds<double, false>(a, b, P, 1, Ly, stw);
+  for (int t = threadIdx.x; t < Kyh; t += blockDim.x) out[(size_t)kx * Kyh + t] = (T)(imag ? Y[t].y : Y[t].x);
+}
+
+// ------------------------------------------------------------ launchers
+template <typename T>
+hipError_t launch_row_fwd(const T* src, void* dst, int nrows, int nin, int N2x, int Kx, const FftPlan& P,
+                          const void* tw, const void* twp, hipStream_t st) {
+  const size_t lds = sizeof(cpx<T>) * (4 * (size_t)N2x + 1);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_row_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_row_fwd<T>, dim3(nrows), dim3(256), lds, st, src, (cpx<T>*)dst, nrows, nin, N2x, Kx,
+                     P, (const cpx<T>*)tw, (const cpx<T>*)twp);
+  return hipGetLastError();
+}
+
+template <typename T>
+size_t col_lds_bytes(int Ly, int bufch, int CB) {
+  return sizeof(cpx<T>) * ((size_t)Ly + 2 * (size_t)bufch * CB * Ly);
+}
+
+template <typename T>
+hipError_t launch_col(const void* spec1, void* spec2, const T* kern, int Kx, int Ly, int Kyh, int ny,
+                      int nin_ch, int CB, const FftPlan& P, const void* twy, const OutTable& tab,
+                      hipStream_t st) {
+  const int bufch = nin_ch > 6 ? nin_ch : 6;
+  const size_t lds = col_lds_bytes<T>(Ly, bufch, CB);
+  const int nblk = (Kx + CB - 1) / CB;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_col<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_col<T>, dim3(nblk), dim3(256), lds, st, (const cpx<T>*)spec1, (cpx<T>*)spec2, kern, Kx,
+                     Ly, Kyh, ny, nin_ch, CB, bufch, P, (const cpx<T>*)twy, tab);
+  return hipGetLastError();
+}
+
+template <typename T>
+size_t row_lds_bytes(const RowParams& p) {
+  const int K = FirHalf<T>::K, NQ = 2 * K + 4, E = K + 4;
+  const int nfc = p.full_force ? 3 : 1;
+  size_t b = sizeof(cpx<T>) * (size_t)(p.N2x + p.N2x + 1 + 6 * p.N2x);
+  b += sizeof(T) * (size_t)(p.M + 2 * E + 2 * NQ + 3 * p.nx + 3 * (p.nx + 2) + 2 * nfc * p.nx + 2);
+  b = (b + 15) & ~size_t(15);
+  b += sizeof(double) * 3 * 256 + 16;
+  return b;
+}
+
+template <typename T>
+hipError_t launch_row_stage(const RowParams& p, const void* spec2, const T* mst, const T* m0, T* mnext, T* acc,
+                            T* hout, const void* tw, const void* twp, RigidState* rigid, double* partial,
+                            unsigned* counter, hipStream_t st) {
+  const size_t lds = row_lds_bytes<T>(p);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_row_stage<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_row_stage<T>, dim3(p.ntask), dim3(256), lds, st, p, (const cpx<T>*)spec2, mst, m0, mnext,
+                     acc, hout, (const cpx<T>*)tw, (const cpx<T>*)twp, rigid, partial, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_kernel_real(double* out, int Lx, int Ly, int kind, int comp, double dzc, double dx, double dy,
+                              double dz, double rc, double scale, hipStream_t st) {
+  dim3 grid((Lx + 127) / 128, Ly);
+  hipLaunchKernelGGL(k_kernel_real, grid, dim3(128), 0, st, out, Lx, Ly, kind, comp, dzc, dx, dy, dz, rc, scale);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_colpack(const void* spec, T* out, int Kx, int Ly, int Kyh, const FftPlan& P, const void* twy,
+                          int imag, hipStream_t st) {
+  const size_t lds = sizeof(cpx<double>) * 3 * (size_t)Ly;
+  hipLaunchKernelGGL(k_colpack<T>, dim3(Kx), dim3(256), lds, st, (const cpx<double>*)spec, out, Kx, Ly, Kyh, P,
+                     (const cpx<double>*)twy, imag);
+  return hipGetLastError();
+}
+
+#define MMV_INST(T)                                                                                             \
+  template hipError_t launch_row_fwd<T>(const T*, void*, int, int, int, int, const FftPlan&, const void*,      \
+                                        const void*, hipStream_t);                                             \
+  template hipError_t launch_col<T>(const void*, void*, const T*, int, int, int, int, int, int, const FftPlan&, \
+                                    const void*, const OutTable&, hipStream_t);                                \
+  template hipError_t launch_row_stage<T>(const RowParams&, const void*, const T*, const T*, T*, T*, T*,       \
+                                          const void*, const void*, RigidState*, double*, unsigned*,           \
+                                          hipStream_t);                                                        \
+  template hipError_t launch_colpack<T>(const void*, T*, int, int, int, const FftPlan&, const void*, int,      \
+                                        hipStream_t);                                                          \
+  template size_t row_lds_bytes<T>(const RowParams&);                                                           \
+  template size_t col_lds_bytes<T>(int, int, int);
+
+MMV_INST(float)
+MMV_INST(double)
+
+}  // namespace mmv

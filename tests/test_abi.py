@@ -1,0 +1,62 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol of
+include/mmv.h, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+import pytest
+import paper_1801_04181_amd as mmv
+from workloads import Desc, get_config
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "mmv.h")
+
+
+def header_functions():
+    txt = open(HDR).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_header_lists_north_star_calls():
+    fns = header_functions()
+    for name in ("init_mesh", "set_offset", "eval_heff", "llg_step", "stray_force"):
+        assert name in fns
+
+
+def test_library_exports_every_header_symbol():
+    lib = mmv.load()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+    assert set(header_functions()) == set(mmv.EXPORTS)
+
+
+def test_struct_layout_matches_header():
+    # offsets the C compiler assigns (x86-64 SysV): checked against ctypes
+    assert ctypes.sizeof(mmv.MeshDesc) == 192
+    assert ctypes.sizeof(mmv.DriveDesc) == 64
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("n_films", 3, "n_films"), ("nx", 0, "nx"), ("dx", 0.0, "cell edges"),
+    ("dz", float("nan"), "cell edges"), ("Ms", -1.0, "Ms"), ("precision", 16, "precision"),
+    ("halo", 1, "halo"), ("gap_cells", -1, "gap_cells"), ("nz", 2, "nz == 1"),
+    ("sigma", 1e6, "eddy"), ("rc_cells", 0.0, "rc_cells"), ("max_travel_cells", -1, "max_travel"),
+    ("fft_lx", 71, "fft_lx"), ("fft_ly", 11, "fft_ly"),
+])
+def test_init_rejects_bad_descriptors(field, value, msg):
+    d = get_config("tiny")["desc"]
+    c = mmv.to_desc(d)
+    setattr(c, field, value)
+    with pytest.raises(mmv.MMVError) as e:
+        mmv.init_mesh(c)
+    assert e.value.code == -1
+    assert msg in str(e.value)
+
+
+def test_null_handle_and_pointers():
+    lib = mmv.load()
+    assert lib.destroy_mesh(None) == 0
+    assert lib.llg_step(None, 1e-13, 1) == -1
+    assert "handle" in mmv.last_error()
+    assert lib.init_mesh(None, None, None) == -1
+    F = (ctypes.c_double * 3)()
+    assert lib.stray_force(None, F) == -1

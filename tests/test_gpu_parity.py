@@ -1,0 +1,120 @@
+"""GPU parity: the HIP path through the C ABI vs the float64 oracle."""
+import math
+import numpy as np
+import pytest
+
+from workloads import Desc, Drive, get_config, initial_state
+from workloads.states import random_unit, domain_state
+from gpu_common import TERMS, TOL, rel, oracle_system
+
+pytestmark = pytest.mark.gpu
+
+
+def _mmv():
+    import paper_1801_04181_amd as mmv
+    return mmv
+
+
+def check_fields(desc, drive, m, x_cells=None, tol=None):
+    mmv = _mmv()
+    tol = tol or TOL[desc.precision]
+    print(f"fields: n_films={desc.n_films} {desc.nx}x{desc.ny} p{desc.precision} x={x_cells}", flush=True)
+    mesh = mmv.Mesh(desc, drive, m)
+    if x_cells is not None:
+        mesh.set_offset(x_cells)
+    s = oracle_system(desc, drive, m, x_cells)
+    terms, F = s.field_terms()
+    worst = {}
+    for f in range(desc.n_films):
+        for name, bit in TERMS:
+            ref = terms[f][name]
+            got = mesh.eval_heff(f, bit).cpu().numpy()
+            if not np.any(ref):
+                assert np.abs(got).max() == 0.0, (f, name)
+                continue
+            e = rel(got, ref)
+            worst[(f, name)] = e
+            assert e <= tol, (f, name, e)
+        tot = sum(terms[f][k] for k, _ in TERMS)
+        e = rel(mesh.eval_heff(f, 63).cpu().numpy(), tot)
+        worst[(f, "total")] = e
+        assert e <= tol, (f, "total", e)
+    print("  worst rel err", max(worst.values()), flush=True)
+    if desc.n_films == 2:
+        Fg = np.array(mesh.force())
+        eF = np.linalg.norm(Fg - F) / np.linalg.norm(F)
+        print(f"  force gpu {Fg} oracle {F} rel {eF:.2e}", flush=True)
+        assert eF <= 10 * tol
+    mesh.close()
+    return worst
+
+
+def test_tiny_fp64_fields():
+    cfg = get_config("tiny")
+    check_fields(cfg["desc"], cfg["drive"], initial_state(cfg), x_cells=0.37)
+
+
+@pytest.mark.parametrize("x_cells", [0.37, 3.6, -2.25])
+def test_stickslip_fp32_fields_full_size(x_cells):
+    cfg = get_config("stickslip")
+    check_fields(cfg["desc"], cfg["drive"], initial_state(cfg), x_cells=x_cells)
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+@pytest.mark.parametrize("shape", [(37, 23), (5, 1), (1, 6), (70, 3)])
+def test_ragged_shapes(prec, shape):
+    nx, ny = shape
+    d = Desc(n_films=2, nx=nx, ny=ny, nz=1, dx=2e-9, dy=3e-9, dz=2.5e-9, gap_cells=2,
+             max_travel_cells=3, Ms=9e5, Aex=1.2e-11, alpha=0.2, Ku=3e5, u=(0.3, -0.2, 0.9),
+             Hext=(1e4, -2e4, 5e3), precision=prec)
+    rng = np.random.default_rng(nx * 100 + ny)
+    m = [random_unit((1, ny, nx), rng) for _ in range(2)]
+    check_fields(d, Drive(), m, x_cells=1.3)
+    check_fields(d, Drive(), m, x_cells=-2.9)
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_gap_zero_and_single_film(prec):
+    d = Desc(n_films=2, nx=24, ny=17, nz=1, dx=2e-9, dy=2e-9, dz=2e-9, gap_cells=0,
+             max_travel_cells=2, Ms=1.1e6, Aex=1.5e-11, alpha=0.1, Ku=8e5, precision=prec)
+    m = [domain_state((1, 17, 24), 3), domain_state((1, 17, 24), 4)]
+    check_fields(d, Drive(), m, x_cells=0.5)
+    d1 = d.replace(n_films=1)
+    check_fields(d1, Drive(), m[:1])
+
+
+def run_steps(desc, drive, m, dt, n):
+    mmv = _mmv()
+    import torch
+    mesh = mmv.Mesh(desc, drive, m)
+    s = oracle_system(desc, drive, m)
+    mesh.step(dt, n)
+    torch.cuda.synchronize()
+    s.run(dt, n)
+    st = mesh.state()
+    dm = max(np.abs(mesh.get_m(f).cpu().numpy() - s.m[f]).max() for f in range(desc.n_films))
+    mesh.close()
+    return dm, st, s
+
+
+def test_tiny_fp64_100_steps():
+    cfg = get_config("tiny")
+    dm, st, s = run_steps(cfg["desc"], cfg["drive"], initial_state(cfg), cfg["dt"], 100)
+    print("tiny 100 steps max|dm|", dm, flush=True)
+    assert st["step"] == 100
+    assert st["t"] == pytest.approx(s.t, rel=1e-15)
+    assert dm < 1e-9
+
+
+def test_spring_fp32_steps():
+    d = Desc(n_films=2, nx=96, ny=40, nz=1, dx=2e-9, dy=2e-9, dz=2e-9, gap_cells=1,
+             max_travel_cells=4, Ms=1.1e6, Aex=1.5e-11, alpha=0.1, Ku=8e5, precision=32)
+    from workloads import slider_mass_damping
+    mass, gv = slider_mass_damping(96, 40, 1e-3)
+    drv = Drive(mode=2, v_d=5.0, k=1e-3, mass=mass, gamma_v=gv, x0=0.9 * 2e-9)
+    m = [domain_state((1, 40, 96), 7), domain_state((1, 40, 96), 8)]
+    dm, st, s = run_steps(d, drv, m, 1e-13, 60)
+    print("spring 60 steps max|dm|", dm, "x gpu", st["x"], "oracle", s.x, flush=True)
+    assert dm < 1e-4
+    assert abs(st["x"] - s.x) < 1e-4 * d.dx
+    assert abs(st["v"] - s.v) < 1e-4 * max(abs(s.v), 1e-3)
