@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 #include <string>
 #include <vector>
@@ -83,7 +84,7 @@ struct mmv_mesh {
   hipStream_t st = nullptr;
   int esz = 4;  // bytes per real
   int nfilm = 2, nx = 0, ny = 0;
-  int Lx = 0, Ly = 0, N2x = 0, Kx = 0, Kyh = 0, CB = 1, M = 0;
+  int Lx = 0, Ly = 0, N2x = 0, Kx = 0, Kyh = 0, ngroup = 1, M = 0;
   FftPlan px{}, py{};
   void* m0 = nullptr;
   void* mb[2] = {nullptr, nullptr};
@@ -357,20 +358,34 @@ int init_typed(mmv_mesh* h) {
   }
   // LDS limits
   const size_t lds_limit = 160 * 1024;
-  RowParams probe = h->rp_force;
-  probe.full_force = 1;
-  if (row_lds_bytes<T>(probe) > lds_limit) return fail(MMV_EINVAL, "nx too large for the row kernel's LDS");
-  if (sizeof(T) * 2 * (4 * (size_t)h->N2x + 1) > lds_limit) return fail(MMV_EINVAL, "nx too large");
-  // columns per block of the y pass: largest CB with LDS <= 64 KiB (>= 1)
-  const int bufch = 3 * h->nfilm > 6 ? 3 * h->nfilm : 6;
-  h->CB = 1;
-  for (int cb : {8, 4, 2}) {
-    if (col_lds_bytes<T>(h->Ly, bufch, cb) <= 64 * 1024 && (h->Kx + cb - 1) / cb >= 256) {
-      h->CB = cb;
+  // inverse row transforms per batch of the row kernel: as many as fit
+  int nbr = 0;
+  for (int b : {8, 6, 4, 3, 2, 1}) {
+    RowParams probe = h->rp_force;
+    probe.full_force = 1;
+    probe.nbr = b;
+    if (row_lds_bytes<T>(probe) <= lds_limit) {
+      nbr = b;
       break;
     }
   }
-  if (col_lds_bytes<T>(h->Ly, bufch, h->CB) > lds_limit) return fail(MMV_EINVAL, "ny too large for the y pass");
+  if (!nbr) return fail(MMV_EINVAL, "nx too large for the row kernel's LDS");
+  h->rp_hot.nbr = h->rp_force.nbr = nbr;
+  if (sizeof(T) * 2 * (4 * (size_t)h->N2x + 1) > lds_limit) return fail(MMV_EINVAL, "nx too large");
+  // output groups per column of the y pass: enough blocks to fill the chip
+  // (each group recomputes the column's forward transforms, an L2 hit)
+  h->ngroup = (1536 + h->Kx - 1) / h->Kx;
+  if (h->ngroup < 1) h->ngroup = 1;
+  if (h->ngroup > 4) h->ngroup = 4;
+  if (const char* e = getenv("MMV_COL_GROUPS")) {
+    const int v = atoi(e);
+    if (v >= 1 && v <= 8) h->ngroup = v;
+  }
+  const int nin = 3 * h->nfilm;
+  const int nmax = h->tab_force.n > h->tab_hot.n ? h->tab_force.n : h->tab_hot.n;
+  const int per = (nmax + h->ngroup - 1) / h->ngroup;
+  if (col_lds_bytes<T>(h->Ly, nin > per ? nin : per) > lds_limit)
+    return fail(MMV_EINVAL, "ny too large for the y pass");
   return MMV_OK;
 }
 
@@ -409,7 +424,7 @@ int run_fields(mmv_mesh* h, const void* m_in, const OutTable& tab) {
                            h->twp, h->st));
   PROF(1);
   PROF(2);
-  HIPCHK(launch_col<T>(h->spec1, h->spec2, (const T*)h->kern, h->Kx, h->Ly, h->Kyh, h->ny, 3 * h->nfilm, h->CB,
+  HIPCHK(launch_col<T>(h->spec1, h->spec2, (const T*)h->kern, h->Kx, h->Ly, h->Kyh, h->ny, 3 * h->nfilm, h->ngroup,
                        h->py, h->twy, tab, h->st));
   PROF(2);
   return MMV_OK;

@@ -133,27 +133,46 @@ __device__ __forceinline__ void dft(cpx<T>* v) {
   }
 }
 
-// One radix-R Stockham butterfly: reads src[j + r*nb], twiddles, DFT_R,
-// writes dst[(j - k) R + k + r Ns] with k = j mod Ns.  tw[t] = exp(-2 pi i t / L).
+// Exact quotient floor(n / d) for 0 <= n < 2^20, 1 <= d < 2^20 from a float
+// reciprocal: (n + 1/2) / d lies at least 1/(2d) from an integer, far more
+// than the float rounding of the product.
+__device__ __forceinline__ int fdiv(int n, float inv_d) { return (int)(((float)n + 0.5f) * inv_d); }
+
+// One radix-R Stockham pass over `batch` transforms of length L at stride
+// `stride`: reads src[j + r*nb], twiddles by exp(-+2 pi i r k / (Ns R)),
+// DFT_R, writes dst[(j - k) R + k + r Ns] with k = j mod Ns.
+// tw[t] = exp(-2 pi i t / L).
 template <typename T, int R, bool INV>
-__device__ __forceinline__ void butterfly(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
-                                          const cpx<T>* __restrict__ tw, int j, int nb, int Ns,
-                                          int tws) {
-  int k = j % Ns;
-  cpx<T> v[R];
+__device__ __forceinline__ void stockham_pass(const cpx<T>* __restrict__ a, cpx<T>* __restrict__ b, int L,
+                                              int Ns, int batch, int stride,
+                                              const cpx<T>* __restrict__ tw) {
+  const int nb = L / R;
+  const int tws = L / (Ns * R);
+  const float inb = 1.0f / (float)nb;
+  const float ins = 1.0f / (float)Ns;
+  const int total = nb * batch;
+  for (int w = threadIdx.x; w < total; w += blockDim.x) {
+    const int t = fdiv(w, inb);
+    const int j = w - t * nb;
+    const int q = fdiv(j, ins);
+    const int k = j - q * Ns;
+    const cpx<T>* s = a + t * stride + j;
+    cpx<T>* d = b + t * stride + q * Ns * R + k;
+    cpx<T> v[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) v[r] = src[j + r * nb];
-  if (k) {
+    for (int r = 0; r < R; ++r) v[r] = s[r * nb];
+    if (k) {
+      const int kt = k * tws;
 #pragma unroll
-    for (int r = 1; r < R; ++r) {
-      cpx<T> w = tw[r * k * tws];
-      v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
+      for (int r = 1; r < R; ++r) {
+        cpx<T> wv = tw[r * kt];
+        v[r] = INV ? cmulc(v[r], wv) : cmul(v[r], wv);
+      }
     }
-  }
-  dft<T, R, INV>(v);
-  int base = (j - k) * R + k;
+    dft<T, R, INV>(v);
 #pragma unroll
-  for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+    for (int r = 0; r < R; ++r) d[r * Ns] = v[r];
+  }
 }
 
 // Batched in-LDS FFT of `batch` transforms of length P.L, transform t at
@@ -168,21 +187,12 @@ __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, const FftPlan& P, int batch, in
   int Ns = 1;
   for (int p = 0; p < P.np; ++p) {
     const int R = P.r[p];
-    const int nb = L / R;
-    const int tws = L / (Ns * R);
-    const int total = nb * batch;
-    for (int w = threadIdx.x; w < total; w += blockDim.x) {
-      int t = w / nb;
-      int j = w - t * nb;
-      const cpx<T>* s = a + t * stride;
-      cpx<T>* d = b + t * stride;
-      switch (R) {
-        case 2: butterfly<T, 2, INV>(s, d, tw, j, nb, Ns, tws); break;
-        case 3: butterfly<T, 3, INV>(s, d, tw, j, nb, Ns, tws); break;
-        case 4: butterfly<T, 4, INV>(s, d, tw, j, nb, Ns, tws); break;
-        case 5: butterfly<T, 5, INV>(s, d, tw, j, nb, Ns, tws); break;
-        default: butterfly<T, 7, INV>(s, d, tw, j, nb, Ns, tws); break;
-      }
+    switch (R) {
+      case 2: stockham_pass<T, 2, INV>(a, b, L, Ns, batch, stride, tw); break;
+      case 3: stockham_pass<T, 3, INV>(a, b, L, Ns, batch, stride, tw); break;
+      case 4: stockham_pass<T, 4, INV>(a, b, L, Ns, batch, stride, tw); break;
+      case 5: stockham_pass<T, 5, INV>(a, b, L, Ns, batch, stride, tw); break;
+      default: stockham_pass<T, 7, INV>(a, b, L, Ns, batch, stride, tw); break;
     }
     __syncthreads();
     cpx<T>* tmp = a;

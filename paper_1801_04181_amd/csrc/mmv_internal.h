@@ -66,6 +66,7 @@ struct RowParams {
   int nfilm, nx, ny;
   int N2x, Kx;
   int halo, M, travel, kfir;
+  int nbr;        // inverse row transforms per batch
   int ntask;
   int with_force;  // MODE_STAGE: accumulate F_x partials
   int full_force;  // MODE_FORCE: all three components

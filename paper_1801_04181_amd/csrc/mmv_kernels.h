@@ -11,7 +11,7 @@ hipError_t launch_row_fwd(const T* src, void* dst, int nrows, int nin, int N2x, 
                           const void* tw, const void* twp, hipStream_t st);
 template <typename T>
 hipError_t launch_col(const void* spec1, void* spec2, const T* kern, int Kx, int Ly, int Kyh, int ny, int nin_ch,
-                      int CB, const FftPlan& P, const void* twy, const OutTable& tab, hipStream_t st);
+                      int ngroup, const FftPlan& P, const void* twy, const OutTable& tab, hipStream_t st);
 template <typename T>
 hipError_t launch_row_stage(const RowParams& p, const void* spec2, const T* mst, const T* m0, T* mnext, T* acc,
                             T* hout, const void* tw, const void* twp, RigidState* rigid, double* partial,
@@ -24,6 +24,6 @@ hipError_t launch_colpack(const void* spec, T* out, int Kx, int Ly, int Kyh, con
 template <typename T>
 size_t row_lds_bytes(const RowParams& p);
 template <typename T>
-size_t col_lds_bytes(int Ly, int bufch, int CB);
+size_t col_lds_bytes(int Ly, int nbuf);
 
 }  // namespace mmv

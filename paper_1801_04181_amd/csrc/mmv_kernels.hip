@@ -55,76 +55,82 @@ __global__ void __launch_bounds__(256)
 }
 
 // ------------------------------------------------------------ y pass
+// One block per (kx column, output group): the column's nin_ch magnetisation
+// spectra are y-transformed (recomputed by each group, an L2 hit), multiplied
+// by the kernel spectra into the group's output channels, inverse
+// y-transformed and the requested rows written.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_col(const cpx<T>* __restrict__ spec1, cpx<T>* __restrict__ spec2, const T* __restrict__ kern,
-          int Kx, int Ly, int Kyh, int ny, int nin_ch, int CB, int bufch, FftPlan P,
+          int Kx, int Ly, int Kyh, int ny, int nin_ch, int ngroup, int nbuf, FftPlan P,
           const cpx<T>* __restrict__ twy, OutTable tab) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* A = stw + Ly;
-  cpx<T>* B = A + (size_t)bufch * CB * Ly;
+  cpx<T>* B = A + (size_t)nbuf * Ly;
+  // this group's output channels, staged in LDS: per (output, source comp)
+  // the kernel offset and flags, per output the source film
+  __shared__ long long s_koff[MAX_OUT][3];
+  __shared__ int s_fl[MAX_OUT][3];
+  __shared__ int s_src[MAX_OUT];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int kx0 = blk * CB;
-  if (kx0 >= Kx) return;
-  const int ncol = min(CB, Kx - kx0);
+  const int kx = blk / ngroup;
+  const int g = blk - kx * ngroup;
+  if (kx >= Kx) return;
+  const int o0 = (g * tab.n) / ngroup;
+  const int o1 = ((g + 1) * tab.n) / ngroup;
+  const int no = o1 - o0;
+  for (int t = threadIdx.x; t < 3 * no; t += blockDim.x) {
+    const int o = t / 3, b = t - 3 * o;
+    const int kc = tab.ch[o0 + o].kc[b];
+    s_koff[o][b] = kc < 0 ? -1 : ((long long)kc * Kx + kx) * Kyh;
+    s_fl[o][b] = tab.ch[o0 + o].fl[b];
+    if (b == 0) s_src[o] = tab.ch[o0 + o].src;
+  }
   for (int t = threadIdx.x; t < Ly; t += blockDim.x) stw[t] = twy[t];
-  const int nload = nin_ch * ncol * Ly;
+  const int nload = nin_ch * Ly;
+  const float invLy = 1.0f / (float)Ly;
   for (int t = threadIdx.x; t < nload; t += blockDim.x) {
-    const int c = t % ncol;
-    const int rest = t / ncol;
-    const int y = rest % Ly;
-    const int ch = rest / Ly;
-    cpx<T> v = mk<T>(0, 0);
-    if (y < ny) v = spec1[((size_t)ch * ny + y) * Kx + kx0 + c];
-    A[(ch * ncol + c) * Ly + y] = v;
+    const int ch = fdiv(t, invLy);
+    const int y = t - ch * Ly;
+    A[t] = (y < ny) ? spec1[((size_t)ch * ny + y) * Kx + kx] : mk<T>(0, 0);
   }
   __syncthreads();
-  cpx<T>* X = fft_lds<T, false>(A, B, P, nin_ch * ncol, Ly, stw);
-  cpx<T>* W0 = (X == A) ? B : A;
-  cpx<T>* W1 = W0 + 3 * ncol * Ly;
-  for (int og = 0; og < tab.n; og += 3) {
-    const int ng = min(3, tab.n - og);
-    const int nprod = ng * ncol * Ly;
-    for (int t = threadIdx.x; t < nprod; t += blockDim.x) {
-      const int ky = t % Ly;
-      const int rest = t / Ly;
-      const int c = rest % ncol;
-      const int o = rest / ncol;
-      const OutCh& oc = tab.ch[og + o];
-      const bool upper = ky >= Kyh;
-      const int kyr = upper ? Ly - ky : ky;
-      cpx<T> acc = mk<T>(0, 0);
+  cpx<T>* X = fft_lds<T, false>(A, B, P, nin_ch, Ly, stw);
+  cpx<T>* W = (X == A) ? B : A;
+  const int nprod = no * Ly;
+  for (int t = threadIdx.x; t < nprod; t += blockDim.x) {
+    const int o = fdiv(t, invLy);
+    const int ky = t - o * Ly;
+    const bool upper = ky >= Kyh;
+    const int kyr = upper ? Ly - ky : ky;
+    const int src = s_src[o];
+    cpx<T> acc = mk<T>(0, 0);
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const int kc = oc.kc[b];
-        if (kc < 0) continue;
-        const int fl = oc.fl[b];
-        T s = kern[((size_t)kc * Kx + kx0 + c) * Kyh + kyr];
-        const bool neg = ((fl & 4) != 0) != (upper && (fl & 2));
-        if (neg) s = -s;
-        const cpx<T> mh = X[((oc.src * 3 + b) * ncol + c) * Ly + ky];
-        if (fl & 1)
-          acc = acc + mk<T>(-s * mh.y, s * mh.x);
-        else
-          acc = acc + mk<T>(s * mh.x, s * mh.y);
-      }
-      W0[(o * ncol + c) * Ly + ky] = acc;
+    for (int b = 0; b < 3; ++b) {
+      const long long ko = s_koff[o][b];
+      if (ko < 0) continue;
+      const int fl = s_fl[o][b];
+      T s = kern[ko + kyr];
+      const bool neg = ((fl & 4) != 0) != (upper && (fl & 2));
+      if (neg) s = -s;
+      const cpx<T> mh = X[(src * 3 + b) * Ly + ky];
+      if (fl & 1)
+        acc = acc + mk<T>(-s * mh.y, s * mh.x);
+      else
+        acc = acc + mk<T>(s * mh.x, s * mh.y);
     }
-    __syncthreads();
-    cpx<T>* Y = fft_lds<T, true>(W0, W1, P, ng * ncol, Ly, stw);
-    for (int o = 0; o < ng; ++o) {
-      const OutCh& oc = tab.ch[og + o];
-      const int nw = oc.nrows * ncol;
-      for (int t = threadIdx.x; t < nw; t += blockDim.x) {
-        const int c = t % ncol;
-        const int r = t / ncol;
-        int yy = (oc.row0 + r) % Ly;
-        if (yy < 0) yy += Ly;
-        spec2[oc.off + (size_t)r * Kx + kx0 + c] = Y[(o * ncol + c) * Ly + yy];
-      }
+    W[t] = acc;
+  }
+  __syncthreads();
+  cpx<T>* Y = fft_lds<T, true>(W, X, P, no, Ly, stw);
+  for (int o = 0; o < no; ++o) {
+    const OutCh& oc = tab.ch[o0 + o];
+    for (int r = threadIdx.x; r < oc.nrows; r += blockDim.x) {
+      int yy = (oc.row0 + r) % Ly;
+      if (yy < 0) yy += Ly;
+      spec2[oc.off + (size_t)r * Kx + kx] = Y[o * Ly + yy];
     }
-    __syncthreads();
   }
 }
 
@@ -157,8 +163,9 @@ template <typename T>
 __device__ cpx<T>* c2r_rows(const cpx<T>* const* rowp, int nb, cpx<T>* fa, cpx<T>* fb, int N2x,
                             const FftPlan& P, const cpx<T>* stw, const cpx<T>* stp) {
   const int tot = nb * N2x;
+  const float inv = 1.0f / (float)N2x;
   for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-    const int b = t / N2x;
+    const int b = fdiv(t, inv);
     const int k = t - b * N2x;
     const cpx<T>* X = rowp[b];
     cpx<T> xk = X[k];
@@ -244,11 +251,15 @@ __device__ void rigid_stage(RigidState* R, const DriveP& d, int stage, double F,
   }
 }
 
+// Row kinds of the fused row kernel.
+enum { RK_SELF = 0, RK_CROSS = 3, RK_FP = 6, RK_FM = 9 };
+
 // Block layout: tasks [film 0 rows][film 1 rows][film 1 rows -1 and ny]
 // (MODE_STAGE), [eval_film rows] (MODE_EVAL), [film 1 rows -1..ny]
-// (MODE_FORCE).
+// (MODE_FORCE).  All inverse row transforms of a task run as one batch (or
+// batches of p.nbr rows); every spline window is filtered in parallel.
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
     k_row_stage(RowParams p, const cpx<T>* __restrict__ spec2, const T* __restrict__ mst,
                 const T* m0, T* mnext, T* __restrict__ acc,
                 T* __restrict__ hout, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp,
@@ -258,22 +269,25 @@ __global__ void __launch_bounds__(256)
   constexpr int NQ = 2 * K + 4;
   constexpr int E = K + 4;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int nx = p.nx, ny = p.ny, N2x = p.N2x, M = p.M, Lx = 2 * N2x;
+  const int nx = p.nx, ny = p.ny, N2x = p.N2x, M = p.M, Lx = 2 * N2x, nbr = p.nbr;
+  const int MW = M + 2 * E;
   const int nfc = p.full_force ? 3 : 1;
   cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* stp = stw + N2x;
   cpx<T>* fa = stp + N2x + 1;
-  cpx<T>* fb = fa + 3 * N2x;
-  T* ext = reinterpret_cast<T*>(fb + 3 * N2x);
-  T* gs = ext + M + 2 * E;   // weights, slider samples base field
-  T* gb = gs + NQ;           // weights, base samples slider field
-  T* H = gb + NQ;            // [3][nx] demag accumulation
-  T* gc = H + 3 * nx;        // [3][nx+2] slider cross field at i = -1..nx
-  T* gp = gc + 3 * (nx + 2); // [nfc][nx] force layer z_s+1
-  T* gm = gp + nfc * nx;     // [nfc][nx] force layer z_s-1
+  cpx<T>* fb = fa + (size_t)nbr * N2x;
+  T* ext = reinterpret_cast<T*>(fb + (size_t)nbr * N2x);  // [nbr][MW]
+  T* gs = ext + (size_t)nbr * MW;  // weights, slider samples base field
+  T* gb = gs + NQ;                 // weights, base samples slider field
+  T* H = gb + NQ;                  // [3][nx] demag accumulation
+  T* gc = H + 3 * nx;              // [3][nx+2] slider cross field at i = -1..nx
+  T* gp = gc + 3 * (nx + 2);       // [nfc][nx] force layer z_s+1
+  T* gm = gp + nfc * nx;           // [nfc][nx] force layer z_s-1
   double* red = reinterpret_cast<double*>(gm + nfc * nx + 2);
   red = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(red) + 15) & ~uintptr_t(15));
-  __shared__ const cpx<T>* rowp[6];
+  __shared__ const cpx<T>* rowp[12];
+  __shared__ int rowkind[12];
+  __shared__ int s_nrow;
   __shared__ int s_last;
   __shared__ int s_bad;
 
@@ -299,19 +313,46 @@ __global__ void __launch_bounds__(256)
   const bool need_force =
       two && film == 1 && ((p.mode == MODE_STAGE && p.with_force) || p.mode == MODE_FORCE);
   const bool need_cross = two && ((p.term_mask & 16) || need_force);
+  const int h = p.halo;
 
   for (int t = threadIdx.x; t < N2x; t += blockDim.x) stw[t] = tw[t];
   for (int t = threadIdx.x; t <= N2x; t += blockDim.x) stp[t] = twp[t];
-  if (threadIdx.x == 0) s_bad = 0;
+  for (int t = threadIdx.x; t < 3 * nx; t += blockDim.x) H[t] = T(0);
+  if (threadIdx.x == 0) {
+    s_bad = 0;
+    int n = 0;
+    if (cell_row && (p.term_mask & 8))
+      for (int c = 0; c < 3; ++c) {
+        rowp[n] = spec2 + p.off_self[film][c] + (size_t)y * p.Kx;
+        rowkind[n++] = RK_SELF + c;
+      }
+    if (need_cross) {
+      const int ncomp = (cell_row || p.full_force) ? 3 : 1;
+      const int stored = y - p.cross_row0[film];
+      for (int c = 0; c < ncomp; ++c) {
+        rowp[n] = spec2 + p.off_cross[film][c] + (size_t)stored * p.Kx;
+        rowkind[n++] = RK_CROSS + c;
+      }
+    }
+    if (need_force && cell_row)
+      for (int c = 0; c < nfc; ++c) {
+        rowp[n] = spec2 + p.off_fp[c] + (size_t)y * p.Kx;
+        rowkind[n++] = RK_FP + c;
+        rowp[n] = spec2 + p.off_fm[c] + (size_t)y * p.Kx;
+        rowkind[n++] = RK_FM + c;
+      }
+    s_nrow = n;
+  }
 
   // slider offset of this stage
   const double xs = rigid->xs;
   const int s_int = rigid->s_int;
   double xp = xs / p.dx - (double)s_int;
-  bool xp_bad = !(xp >= -1.0 && xp < 2.0);
+  const bool xp_bad = !(xp >= -1.0 && xp < 2.0);
   if (xp_bad) xp = 0.0;
   const double fls = floor(xp), flb = floor(-xp);
   const double frs = xp - fls, frb = -xp - flb;
+  const int ifs = (int)fls, ifb = (int)flb;
   for (int tq = threadIdx.x; tq < 2 * NQ; tq += blockDim.x) {
     const int q = (tq % NQ) - K - 1;
     const double fr = tq < NQ ? frs : frb;
@@ -319,80 +360,63 @@ __global__ void __launch_bounds__(256)
     double g = 0.0;
     for (int t = -1; t <= 2; ++t) {
       const int j = t - q;
-      if (j >= -K && j <= K) g += beta3(fr - t) * 1.7320508075688772935 * pow(-z1, (double)abs(j)) *
-                                   ((abs(j) & 1) ? -1.0 : 1.0);
+      if (j >= -K && j <= K)
+        g += beta3(fr - t) * 1.7320508075688772935 * pow(-z1, (double)abs(j)) * ((abs(j) & 1) ? -1.0 : 1.0);
     }
     (tq < NQ ? gs : gb)[tq % NQ] = (T)g;
   }
-  for (int t = threadIdx.x; t < 3 * nx; t += blockDim.x) H[t] = T(0);
   __syncthreads();
+  const int nrow = s_nrow;
+  const int W0c = (film == 1) ? s_int - h : -s_int - h;  // cross window start
+  const int W0f = s_int - h;                              // force windows (base field)
 
-  // --- own demagnetising field
-  if (cell_row && (p.term_mask & 8)) {
-    for (int c = threadIdx.x; c < 3; c += blockDim.x) rowp[c] = spec2 + p.off_self[film][c] + (size_t)y * p.Kx;
-    __syncthreads();
-    cpx<T>* Z = c2r_rows<T>(rowp, 3, fa, fb, N2x, p.px, stw, stp);
+  for (int b0 = 0; b0 < nrow; b0 += nbr) {
+    const int bn = min(nbr, nrow - b0);
+    cpx<T>* Z = c2r_rows<T>(rowp + b0, bn, fa, fb, N2x, p.px, stw, stp);
     const T* xr = reinterpret_cast<const T*>(Z);
-    for (int t = threadIdx.x; t < 3 * nx; t += blockDim.x) {
-      const int c = t / nx, i = t - c * nx;
-      H[t] = xr[(size_t)c * Lx + i];
+    // self rows -> H, spline rows -> windows with mirror extension
+    const float invMW = 1.0f / (float)MW;
+    for (int t = threadIdx.x; t < bn * MW; t += blockDim.x) {
+      const int r = fdiv(t, invMW);
+      const int k = t - r * MW;
+      const int kind = rowkind[b0 + r];
+      const T* row = xr + (size_t)r * Lx;
+      if (kind < RK_CROSS) {
+        if (k < nx) H[kind * nx + k] = row[k];
+      } else {
+        const int w = reflect_idx(k - E, M);
+        int X = ((kind < RK_FP) ? W0c : W0f) + w;
+        X %= Lx;
+        if (X < 0) X += Lx;
+        ext[(size_t)r * MW + k] = row[X];
+      }
     }
     __syncthreads();
-  }
-
-  // --- the other film's field, sampled at the shifted lattice
-  const int h = p.halo;
-  if (need_cross) {
-    const int ncomp = (cell_row || p.full_force) ? 3 : 1;
-    const int stored = y - p.cross_row0[film];
-    for (int c = threadIdx.x; c < ncomp; c += blockDim.x)
-      rowp[c] = spec2 + p.off_cross[film][c] + (size_t)stored * p.Kx;
-    __syncthreads();
-    cpx<T>* Z = c2r_rows<T>(rowp, ncomp, fa, fb, N2x, p.px, stw, stp);
-    const T* xr = reinterpret_cast<const T*>(Z);
-    const int W0 = (film == 1) ? s_int - h : -s_int - h;
-    const int fl = (int)((film == 1) ? fls : flb);
-    const T* g = (film == 1) ? gs : gb;
-    for (int c = 0; c < ncomp; ++c) {
-      load_window<T>(xr + (size_t)c * Lx, ext, W0, M, E, Lx);
-      __syncthreads();
-      if (film == 1) {
-        for (int i = threadIdx.x - 1; i <= nx; i += blockDim.x) {
-          const T v = fir_eval<T, K>(ext, g, i + h + fl, E);
+    const float invNX2 = 1.0f / (float)(nx + 2);
+    for (int t = threadIdx.x; t < bn * (nx + 2); t += blockDim.x) {
+      const int r = fdiv(t, invNX2);
+      const int i = t - r * (nx + 2) - 1;
+      const int kind = rowkind[b0 + r];
+      if (kind < RK_CROSS) continue;
+      const T* e = ext + (size_t)r * MW;
+      if (kind < RK_FP) {
+        const int c = kind - RK_CROSS;
+        if (film == 1) {
+          const T v = fir_eval<T, K>(e, gs, i + h + ifs, E);
           gc[c * (nx + 2) + i + 1] = v;
           if (cell_row && i >= 0 && i < nx && (p.term_mask & 16)) H[c * nx + i] += v;
+        } else if (i >= 0 && i < nx) {
+          H[c * nx + i] += fir_eval<T, K>(e, gb, i + h + ifb, E);
         }
-      } else {
-        for (int i = threadIdx.x; i < nx; i += blockDim.x)
-          H[c * nx + i] += fir_eval<T, K>(ext, g, i + h + fl, E);
+      } else if (i >= 0 && i < nx) {
+        const T v = fir_eval<T, K>(e, gs, i + h + ifs, E);
+        if (kind < RK_FM)
+          gp[(kind - RK_FP) * nx + i] = v;
+        else
+          gm[(kind - RK_FM) * nx + i] = v;
       }
-      __syncthreads();
-    }
-  }
-  // --- force layers z_s +/- 1
-  if (need_force && cell_row) {
-    const int nb = 2 * nfc;
-    for (int t = threadIdx.x; t < nb; t += blockDim.x) {
-      const int a = t % nfc;
-      const long long off = t < nfc ? p.off_fp[a] : p.off_fm[a];
-      rowp[t] = spec2 + off + (size_t)y * p.Kx;
     }
     __syncthreads();
-    // up to six rows: two batches of three
-    for (int b0 = 0; b0 < nb; b0 += 3) {
-      const int bn = min(3, nb - b0);
-      cpx<T>* Z = c2r_rows<T>(rowp + b0, bn, fa, fb, N2x, p.px, stw, stp);
-      const T* xr = reinterpret_cast<const T*>(Z);
-      for (int c = 0; c < bn; ++c) {
-        const int idx = b0 + c;
-        T* dstp = idx < nfc ? gp + idx * nx : gm + (idx - nfc) * nx;
-        load_window<T>(xr + (size_t)c * Lx, ext, s_int - h, M, E, Lx);
-        __syncthreads();
-        for (int i = threadIdx.x; i < nx; i += blockDim.x)
-          dstp[i] = fir_eval<T, K>(ext, gs, i + h + (int)fls, E);
-        __syncthreads();
-      }
-    }
   }
 
   // --- per cell: local terms, LLG stage, force partials
@@ -726,34 +750,37 @@ hipError_t launch_row_fwd(const T* src, void* dst, int nrows, int nin, int N2x, 
 }
 
 template <typename T>
-size_t col_lds_bytes(int Ly, int bufch, int CB) {
-  return sizeof(cpx<T>) * ((size_t)Ly + 2 * (size_t)bufch * CB * Ly);
+size_t col_lds_bytes(int Ly, int nbuf) {
+  return sizeof(cpx<T>) * ((size_t)Ly + 2 * (size_t)nbuf * Ly);
 }
 
 template <typename T>
 hipError_t launch_col(const void* spec1, void* spec2, const T* kern, int Kx, int Ly, int Kyh, int ny,
-                      int nin_ch, int CB, const FftPlan& P, const void* twy, const OutTable& tab,
+                      int nin_ch, int ngroup, const FftPlan& P, const void* twy, const OutTable& tab,
                       hipStream_t st) {
-  const int bufch = nin_ch > 6 ? nin_ch : 6;
-  const size_t lds = col_lds_bytes<T>(Ly, bufch, CB);
-  const int nblk = (Kx + CB - 1) / CB;
+  const int per = (tab.n + ngroup - 1) / ngroup;
+  const int nbuf = nin_ch > per ? nin_ch : per;
+  const size_t lds = col_lds_bytes<T>(Ly, nbuf);
+  const int nblk = Kx * ngroup;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_col<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_col<T>, dim3(nblk), dim3(256), lds, st, (const cpx<T>*)spec1, (cpx<T>*)spec2, kern, Kx,
-                     Ly, Kyh, ny, nin_ch, CB, bufch, P, (const cpx<T>*)twy, tab);
+                     Ly, Kyh, ny, nin_ch, ngroup, nbuf, P, (const cpx<T>*)twy, tab);
   return hipGetLastError();
 }
+
+constexpr int ROW_THREADS = 512;
 
 template <typename T>
 size_t row_lds_bytes(const RowParams& p) {
   const int K = FirHalf<T>::K, NQ = 2 * K + 4, E = K + 4;
   const int nfc = p.full_force ? 3 : 1;
-  size_t b = sizeof(cpx<T>) * (size_t)(p.N2x + p.N2x + 1 + 6 * p.N2x);
-  b += sizeof(T) * (size_t)(p.M + 2 * E + 2 * NQ + 3 * p.nx + 3 * (p.nx + 2) + 2 * nfc * p.nx + 2);
+  size_t b = sizeof(cpx<T>) * (size_t)(2 * p.N2x + 1 + 2 * (size_t)p.nbr * p.N2x);
+  b += sizeof(T) * ((size_t)p.nbr * (p.M + 2 * E) + 2 * NQ + 3 * p.nx + 3 * (p.nx + 2) + 2 * nfc * p.nx + 2);
   b = (b + 15) & ~size_t(15);
-  b += sizeof(double) * 3 * 256 + 16;
+  b += sizeof(double) * 3 * ROW_THREADS + 16;
   return b;
 }
 
@@ -766,8 +793,8 @@ hipError_t launch_row_stage(const RowParams& p, const void* spec2, const T* mst,
     hipError_t e = hipFuncSetAttribute((const void*)k_row_stage<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_row_stage<T>, dim3(p.ntask), dim3(256), lds, st, p, (const cpx<T>*)spec2, mst, m0, mnext,
-                     acc, hout, (const cpx<T>*)tw, (const cpx<T>*)twp, rigid, partial, counter);
+  hipLaunchKernelGGL(k_row_stage<T>, dim3(p.ntask), dim3(ROW_THREADS), lds, st, p, (const cpx<T>*)spec2, mst, m0,
+                     mnext, acc, hout, (const cpx<T>*)tw, (const cpx<T>*)twp, rigid, partial, counter);
   return hipGetLastError();
 }
 
@@ -798,7 +825,7 @@ hipError_t launch_colpack(const void* spec, T* out, int Kx, int Ly, int Kyh, con
   template hipError_t launch_colpack<T>(const void*, T*, int, int, int, const FftPlan&, const void*, int,      \
                                         hipStream_t);                                                          \
   template size_t row_lds_bytes<T>(const RowParams&);                                                           \
-  template size_t col_lds_bytes<T>(int, int, int);
+  template size_t col_lds_bytes<T>(int, int);
 
 MMV_INST(float)
 MMV_INST(double)
