@@ -100,6 +100,7 @@ struct mmv_mesh {
   unsigned* counter = nullptr;
   int nkc = 0;
   LayerSet self{}, cross{}, fp{}, fm{};
+  int pot_kc[7][3];  // potential kernel S at dz = z_s + d (d = -3..3), components x, y, z
   OutTable tab_hot{}, tab_force{};
   RowParams rp_hot{}, rp_force{};
   DriveP drive{};
@@ -145,7 +146,8 @@ int validate(const mmv_mesh_desc* d) {
   for (int i = 0; i < 3; ++i)
     if (!isfinite(d->u[i]) || !isfinite(d->Hext[i])) return fail(MMV_EINVAL, "u and Hext must be finite");
   if (d->precision != 32 && d->precision != 64) return fail(MMV_EINVAL, "precision must be 32 or 64");
-  if (d->cross_mode != 0) return fail(MMV_EINVAL, "cross_mode 1 (scalar potential) is not available in this build");
+  if (d->cross_mode != 0 && d->cross_mode != 1) return fail(MMV_EINVAL, "cross_mode must be 0 or 1");
+  if (d->cross_mode == 1 && d->n_films != 2) return fail(MMV_EINVAL, "cross_mode 1 needs two films");
   if (d->sigma != 0.0)
     return fail(MMV_EINVAL, "eddy currents need magnets more than one cell thick (sigma must be 0 for nz == 1)");
   if (d->gap_cells < 0) return fail(MMV_EINVAL, "gap_cells must be >= 0");
@@ -205,6 +207,44 @@ OutCh make_out(const LayerSet& L, int src, int a, int zsign, int row0, int nrows
   return o;
 }
 
+// Kernel-channel numbering: the film's own layer (xz, yz vanish in the film
+// plane), the other film's layer z_s and the force layers z_s +/- 1.
+void assign_channels(mmv_mesh* h) {
+  int n = 0;
+  for (int c = 0; c < 6; ++c) h->self.kc[c] = (c < 4) ? n++ : -1;
+  for (int c = 0; c < 6; ++c) h->cross.kc[c] = h->fp.kc[c] = h->fm.kc[c] = -1;
+  for (int d = 0; d < 7; ++d)
+    for (int c = 0; c < 3; ++c) h->pot_kc[d][c] = -1;
+  if (h->nfilm == 2 && h->d.cross_mode == 0) {
+    for (int c = 0; c < 6; ++c) h->cross.kc[c] = n++;
+    for (int c = 0; c < 6; ++c) h->fp.kc[c] = n++;
+    for (int c = 0; c < 6; ++c) h->fm.kc[c] = n++;
+  }
+  if (h->nfilm == 2 && h->d.cross_mode == 1)
+    for (int d = 0; d < 7; ++d)
+      for (int c = 0; c < 3; ++c) h->pot_kc[d][c] = n++;
+  h->nkc = n;
+}
+
+// Potential channel of film `src` sampled on the layer zsign * z_s + d of
+// the other film: phi = sum_b S_b * m_b with S at dz = zsign (z_s + zsign d).
+// S_x and S_y have imaginary spectra, S_y is odd in y, S_z flips with dz.
+OutCh make_phi(const mmv_mesh* h, int src, int zsign, int d, int row0, int nrows) {
+  OutCh o{};
+  o.src = src;
+  const int layer = zsign > 0 ? d : -d;  // index into S at dz = z_s + layer
+  for (int b = 0; b < 3; ++b) {
+    o.kc[b] = h->pot_kc[layer + 3][b];
+    const int imag = (b < 2) ? 1 : 0;
+    const int oddy = (b == 1) ? 1 : 0;
+    const int neg = (zsign < 0 && b == 2) ? 1 : 0;
+    o.fl[b] = imag | (oddy << 1) | (neg << 2);
+  }
+  o.row0 = row0;
+  o.nrows = nrows;
+  return o;
+}
+
 // Column-pass table and the matching row-kernel offsets.
 void build_tables(mmv_mesh* h, bool full_force, OutTable& tab, RowParams& rp, long long& total) {
   const int ny = h->ny;
@@ -216,6 +256,39 @@ void build_tables(mmv_mesh* h, bool full_force, OutTable& tab, RowParams& rp, lo
     tab.ch[tab.n++] = o;
     return o.off;
   };
+  rp.pot = h->d.cross_mode == 1;
+  if (rp.pot) {
+    // potential rows each task reads: the stage / eval table carries layers
+    // d = -2..2 (rows y-2..y+2 on the film's own layer), the force table
+    // d = -3..3 with the extra rows of the y and z differences of H.
+    if (!full_force)
+      for (int f = 0; f < 2; ++f)
+        for (int a = 0; a < 3; ++a) rp.off_self[f][a] = add(make_out(h->self, f, a, +1, 0, ny));
+    for (int tgt = 1; tgt >= 0; --tgt) {
+      if (full_force && tgt == 0) break;
+      const int src = 1 - tgt, zsign = tgt == 1 ? +1 : -1;
+      for (int d = -3; d <= 3; ++d) {
+        int r0, r1;
+        if (full_force) {
+          const int ext = 3 - (d < 0 ? -d : d);
+          r0 = -ext;
+          r1 = ny - 1 + ext;
+        } else {
+          if (d < -2 || d > 2) {
+            rp.off_phi[tgt][d + 3] = 0;
+            rp.phi_row0[tgt][d + 3] = 0;
+            continue;
+          }
+          r0 = d == 0 ? -2 : 0;
+          r1 = d == 0 ? ny + 1 : ny - 1;
+        }
+        rp.off_phi[tgt][d + 3] = add(make_phi(h, src, zsign, d, r0, r1 - r0 + 1));
+        rp.phi_row0[tgt][d + 3] = r0;
+      }
+    }
+    total = off;
+    return;
+  }
   for (int f = 0; f < h->nfilm; ++f)
     for (int a = 0; a < 3; ++a) rp.off_self[f][a] = add(make_out(h->self, f, a, +1, 0, ny));
   if (h->nfilm == 2) {
@@ -228,19 +301,6 @@ void build_tables(mmv_mesh* h, bool full_force, OutTable& tab, RowParams& rp, lo
     rp.cross_row0[0] = 0;
   }
   total = off;
-}
-
-// Kernel-channel numbering: the film's own layer (xz, yz vanish in the film
-// plane), the other film's layer z_s and the force layers z_s +/- 1.
-void assign_channels(mmv_mesh* h) {
-  int n = 0;
-  for (int c = 0; c < 6; ++c) h->self.kc[c] = (c < 4) ? n++ : -1;
-  if (h->nfilm == 2) {
-    for (int c = 0; c < 6; ++c) h->cross.kc[c] = n++;
-    for (int c = 0; c < 6; ++c) h->fp.kc[c] = n++;
-    for (int c = 0; c < 6; ++c) h->fm.kc[c] = n++;
-  }
-  h->nkc = n;
 }
 
 template <typename T>
@@ -262,29 +322,34 @@ int build_kernels(mmv_mesh* h) {
     free_all(&tmp_owner);
     return rc;
   }
-  const double scale = -d.Ms / ((double)h->Lx * (double)h->Ly);
+  // tensor spectra carry -Ms (Eq. 6), potential spectra +Ms (Eq. 7); both
+  // the 1/(Lx Ly) of the unnormalised inverse transforms
+  const double scale = d.Ms / ((double)h->Lx * (double)h->Ly);
   struct Job {
-    int kc, comp;
+    int kc, kind, comp;
     double dzc;
   };
   std::vector<Job> jobs;
   const int zs = d.nz + d.gap_cells;
   for (int c = 0; c < 6; ++c) {
-    if (h->self.kc[c] >= 0) jobs.push_back({h->self.kc[c], c, 0.0});
-    if (h->nfilm == 2) {
-      jobs.push_back({h->cross.kc[c], c, (double)zs});
-      jobs.push_back({h->fp.kc[c], c, (double)(zs + 1)});
-      jobs.push_back({h->fm.kc[c], c, (double)(zs - 1)});
+    if (h->self.kc[c] >= 0) jobs.push_back({h->self.kc[c], 0, c, 0.0});
+    if (h->cross.kc[c] >= 0) {
+      jobs.push_back({h->cross.kc[c], 0, c, (double)zs});
+      jobs.push_back({h->fp.kc[c], 0, c, (double)(zs + 1)});
+      jobs.push_back({h->fm.kc[c], 0, c, (double)(zs - 1)});
     }
   }
+  for (int dd = -3; dd <= 3; ++dd)
+    for (int c = 0; c < 3; ++c)
+      if (h->pot_kc[dd + 3][c] >= 0) jobs.push_back({h->pot_kc[dd + 3][c], 1, c, (double)(zs + dd)});
   hipError_t err = hipSuccess;
   for (const Job& j : jobs) {
-    err = launch_kernel_real((double*)tmp, h->Lx, h->Ly, 0, j.comp, j.dzc, d.dx, d.dy, d.dz, d.rc_cells, scale,
-                             h->st);
+    err = launch_kernel_real((double*)tmp, h->Lx, h->Ly, j.kind, j.comp, j.dzc, d.dx, d.dy, d.dz, d.rc_cells,
+                             j.kind == 0 ? -scale : scale, h->st);
     if (err != hipSuccess) break;
     err = launch_row_fwd<double>((const double*)tmp, tspec, h->Ly, h->Lx, h->N2x, h->Kx, h->px, twxd, twpd, h->st);
     if (err != hipSuccess) break;
-    const int imag = (PX[j.comp] + PY[j.comp]) & 1;
+    const int imag = j.kind == 0 ? ((PX[j.comp] + PY[j.comp]) & 1) : (j.comp < 2 ? 1 : 0);
     err = launch_colpack<T>(tspec, (T*)h->kern + (size_t)j.kc * h->Kx * h->Kyh, h->Kx, h->Ly, h->Kyh, h->py, twyd,
                             imag, h->st);
     if (err != hipSuccess) break;
@@ -364,6 +429,7 @@ int init_typed(mmv_mesh* h) {
     RowParams probe = h->rp_force;
     probe.full_force = 1;
     probe.nbr = b;
+    probe.pot = h->d.cross_mode == 1;
     if (row_lds_bytes<T>(probe) <= lds_limit) {
       nbr = b;
       break;

@@ -82,6 +82,11 @@ struct RowParams {
   long long off_cross[2][3];
   int cross_row0[2];      // row stored first in the cross channel
   long long off_fp[3], off_fm[3];  // G at z_s+1 and z_s-1 (force)
+  // scalar-potential mode: potential of the other film on the target
+  // film's layers (z_target + d, d = -3..3): channel offset and first row
+  int pot;
+  long long off_phi[2][7];
+  int phi_row0[2][7];
   DriveP drive;
   FftPlan px;
 };

@@ -252,7 +252,8 @@ __device__ void rigid_stage(RigidState* R, const DriveP& d, int stage, double F,
 }
 
 // Row kinds of the fused row kernel.
-enum { RK_SELF = 0, RK_CROSS = 3, RK_FP = 6, RK_FM = 9 };
+enum { RK_SELF = 0, RK_CROSS = 3, RK_FP = 6, RK_FM = 9, RK_PHI = 12 };
+constexpr int MAX_ROWS = 24;
 
 // Block layout: tasks [film 0 rows][film 1 rows][film 1 rows -1 and ny]
 // (MODE_STAGE), [eval_film rows] (MODE_EVAL), [film 1 rows -1..ny]
@@ -283,10 +284,13 @@ __global__ void __launch_bounds__(512)
   T* gc = H + 3 * nx;              // [3][nx+2] slider cross field at i = -1..nx
   T* gp = gc + 3 * (nx + 2);       // [nfc][nx] force layer z_s+1
   T* gm = gp + nfc * nx;           // [nfc][nx] force layer z_s-1
-  double* red = reinterpret_cast<double*>(gm + nfc * nx + 2);
+  T* phit = gm + nfc * nx;         // [nslot][nx+6] potential at i = -3..nx+2
+  const int nslot_max = p.pot ? (p.full_force ? 19 : 9) : 0;
+  double* red = reinterpret_cast<double*>(phit + (size_t)nslot_max * (nx + 6) + 2);
   red = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(red) + 15) & ~uintptr_t(15));
-  __shared__ const cpx<T>* rowp[12];
-  __shared__ int rowkind[12];
+  __shared__ const cpx<T>* rowp[MAX_ROWS];
+  __shared__ int rowkind[MAX_ROWS];
+  __shared__ int slot_of[7][5];  // (layer d + 3, row offset + 2) -> slot, -1 if absent
   __shared__ int s_nrow;
   __shared__ int s_last;
   __shared__ int s_bad;
@@ -326,7 +330,37 @@ __global__ void __launch_bounds__(512)
         rowp[n] = spec2 + p.off_self[film][c] + (size_t)y * p.Kx;
         rowkind[n++] = RK_SELF + c;
       }
-    if (need_cross) {
+    for (int a = 0; a < 7; ++a)
+      for (int b = 0; b < 5; ++b) slot_of[a][b] = -1;
+    if (need_cross && p.pot) {
+      // potential rows needed by this task (layer offset d, row offset r)
+      int ns = 0;
+      auto add = [&](int d, int r) {
+        slot_of[d + 3][r + 2] = ns;
+        rowp[n] = spec2 + p.off_phi[film][d + 3] + (size_t)(y + r - p.phi_row0[film][d + 3]) * p.Kx;
+        rowkind[n++] = RK_PHI + ns;
+        ++ns;
+      };
+      const bool full = p.mode == MODE_FORCE;
+      if (cell_row || full) {
+        for (int r = -2; r <= 2; ++r) add(0, r);
+        if (full && cell_row) {
+          for (int r = -2; r <= 2; ++r) add(1, r);
+          for (int r = -2; r <= 2; ++r) add(-1, r);
+          add(2, 0);
+          add(-2, 0);
+          add(3, 0);
+          add(-3, 0);
+        } else {
+          add(1, 0);
+          add(-1, 0);
+          add(2, 0);
+          add(-2, 0);
+        }
+      } else {
+        add(0, 0);
+      }
+    } else if (need_cross) {
       const int ncomp = (cell_row || p.full_force) ? 3 : 1;
       const int stored = y - p.cross_row0[film];
       for (int c = 0; c < ncomp; ++c) {
@@ -334,7 +368,7 @@ __global__ void __launch_bounds__(512)
         rowkind[n++] = RK_CROSS + c;
       }
     }
-    if (need_force && cell_row)
+    if (need_force && cell_row && !p.pot)
       for (int c = 0; c < nfc; ++c) {
         rowp[n] = spec2 + p.off_fp[c] + (size_t)y * p.Kx;
         rowkind[n++] = RK_FP + c;
@@ -385,20 +419,27 @@ __global__ void __launch_bounds__(512)
         if (k < nx) H[kind * nx + k] = row[k];
       } else {
         const int w = reflect_idx(k - E, M);
-        int X = ((kind < RK_FP) ? W0c : W0f) + w;
+        int X = ((kind < RK_FP || kind >= RK_PHI) ? W0c : W0f) + w;
         X %= Lx;
         if (X < 0) X += Lx;
         ext[(size_t)r * MW + k] = row[X];
       }
     }
     __syncthreads();
-    const float invNX2 = 1.0f / (float)(nx + 2);
-    for (int t = threadIdx.x; t < bn * (nx + 2); t += blockDim.x) {
-      const int r = fdiv(t, invNX2);
-      const int i = t - r * (nx + 2) - 1;
+    const int NP = nx + 6;
+    const float invNP = 1.0f / (float)NP;
+    for (int t = threadIdx.x; t < bn * NP; t += blockDim.x) {
+      const int r = fdiv(t, invNP);
+      const int i = t - r * NP - 3;  // -3 .. nx+2
       const int kind = rowkind[b0 + r];
       if (kind < RK_CROSS) continue;
       const T* e = ext + (size_t)r * MW;
+      if (kind >= RK_PHI) {
+        const T v = (film == 1) ? fir_eval<T, K>(e, gs, i + h + ifs, E) : fir_eval<T, K>(e, gb, i + h + ifb, E);
+        phit[(size_t)(kind - RK_PHI) * NP + i + 3] = v;
+        continue;
+      }
+      if (i < -1 || i > nx) continue;
       if (kind < RK_FP) {
         const int c = kind - RK_CROSS;
         if (film == 1) {
@@ -415,6 +456,44 @@ __global__ void __launch_bounds__(512)
         else
           gm[(kind - RK_FM) * nx + i] = v;
       }
+    }
+    __syncthreads();
+  }
+
+  if (need_cross && p.pot) {
+    // H = -grad phi with the four-point central difference on the shifted
+    // lattice (far field from the scalar potential, Sec. III.A)
+    const int NP = nx + 6;
+    const T c1 = T(8.0 / 12.0), c2 = T(1.0 / 12.0);
+    const T ix = T(1.0 / p.dx), iy = T(1.0 / p.dy), iz = T(1.0 / p.dz);
+    auto ph = [&](int d, int r, int i) -> T { return phit[(size_t)slot_of[d + 3][r + 2] * NP + i + 3]; };
+    auto hcomp = [&](int a, int d, int i) -> T {
+      if (a == 0)
+        return -(c1 * (ph(d, 0, i + 1) - ph(d, 0, i - 1)) - c2 * (ph(d, 0, i + 2) - ph(d, 0, i - 2))) * ix;
+      if (a == 1)
+        return -(c1 * (ph(d, 1, i) - ph(d, -1, i)) - c2 * (ph(d, 2, i) - ph(d, -2, i))) * iy;
+      return -(c1 * (ph(d + 1, 0, i) - ph(d - 1, 0, i)) - c2 * (ph(d + 2, 0, i) - ph(d - 2, 0, i))) * iz;
+    };
+    const bool full = p.mode == MODE_FORCE;
+    if (cell_row) {
+      for (int t = threadIdx.x; t < 3 * nx; t += blockDim.x) {
+        const int c = t / nx, i = t - c * nx;
+        if (p.term_mask & 16) H[t] += hcomp(c, 0, i);
+      }
+    }
+    if (need_force) {
+      for (int t = threadIdx.x; t < nfc * (nx + 2); t += blockDim.x) {
+        const int a = t / (nx + 2), i = t - a * (nx + 2) - 1;
+        gc[a * (nx + 2) + i + 1] = hcomp(a, 0, i);
+      }
+      if (cell_row)
+        for (int t = threadIdx.x; t < nfc * nx; t += blockDim.x) {
+          const int a = t / nx, i = t - a * nx;
+          if (a == 0 || full) {
+            gp[a * nx + i] = hcomp(a, 1, i);
+            gm[a * nx + i] = hcomp(a, -1, i);
+          }
+        }
     }
     __syncthreads();
   }
@@ -778,7 +857,9 @@ size_t row_lds_bytes(const RowParams& p) {
   const int K = FirHalf<T>::K, NQ = 2 * K + 4, E = K + 4;
   const int nfc = p.full_force ? 3 : 1;
   size_t b = sizeof(cpx<T>) * (size_t)(2 * p.N2x + 1 + 2 * (size_t)p.nbr * p.N2x);
-  b += sizeof(T) * ((size_t)p.nbr * (p.M + 2 * E) + 2 * NQ + 3 * p.nx + 3 * (p.nx + 2) + 2 * nfc * p.nx + 2);
+  const int nslot = p.pot ? (p.full_force ? 19 : 9) : 0;
+  b += sizeof(T) * ((size_t)p.nbr * (p.M + 2 * E) + 2 * NQ + 3 * p.nx + 3 * (p.nx + 2) + 2 * nfc * p.nx +
+                    (size_t)nslot * (p.nx + 6) + 2);
   b = (b + 15) & ~size_t(15);
   b += sizeof(double) * 3 * ROW_THREADS + 16;
   return b;

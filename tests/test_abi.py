@@ -60,3 +60,10 @@ def test_null_handle_and_pointers():
     assert lib.init_mesh(None, None, None) == -1
     F = (ctypes.c_double * 3)()
     assert lib.stray_force(None, F) == -1
+
+
+def test_potential_mode_needs_two_films():
+    d = get_config("tiny_potential")["desc"].replace(n_films=1)
+    with pytest.raises(mmv.MMVError) as e:
+        mmv.init_mesh(mmv.to_desc(d))
+    assert e.value.code == -1 and "two films" in str(e.value)

@@ -118,3 +118,30 @@ def test_spring_fp32_steps():
     assert dm < 1e-4
     assert abs(st["x"] - s.x) < 1e-4 * d.dx
     assert abs(st["v"] - s.v) < 1e-4 * max(abs(s.v), 1e-3)
+
+
+# ---------------------------------------------------------------- scalar potential mode
+def test_tiny_potential_fp64_fields():
+    cfg = get_config("tiny_potential")
+    check_fields(cfg["desc"], cfg["drive"], initial_state(cfg), x_cells=0.37)
+    check_fields(cfg["desc"].replace(max_travel_cells=2), cfg["drive"], initial_state(cfg),
+                 x_cells=-1.6)
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+@pytest.mark.parametrize("shape", [(37, 23), (6, 2)])
+def test_potential_ragged(prec, shape):
+    nx, ny = shape
+    d = Desc(n_films=2, nx=nx, ny=ny, nz=1, dx=2e-9, dy=3e-9, dz=2.5e-9, gap_cells=3,
+             max_travel_cells=3, Ms=9e5, Aex=1.2e-11, alpha=0.2, Ku=3e5, u=(0.3, -0.2, 0.9),
+             precision=prec, cross_mode=1)
+    rng = np.random.default_rng(nx + 7 * ny)
+    m = [random_unit((1, ny, nx), rng) for _ in range(2)]
+    check_fields(d, Drive(), m, x_cells=1.3)
+
+
+def test_tiny_potential_fp64_100_steps():
+    cfg = get_config("tiny_potential")
+    dm, st, s = run_steps(cfg["desc"], cfg["drive"], initial_state(cfg), cfg["dt"], 100)
+    print("tiny potential 100 steps max|dm|", dm, flush=True)
+    assert dm < 1e-9
