@@ -1,0 +1,182 @@
+"""Eddy-current field of a conducting magnet (Sec. III.B, Eqs. 9-12).
+
+Per time step, from the magnetisation at the start of the step:
+
+1. B = mu0 (H_d + H_ext + Ms m) on the cells; dB/dt by the backward
+   difference over the previous step, (B_n - B_{n-1}) / dt (the first step
+   takes B_{-1} = B_0, i.e. no induced field before the first update).
+2. Solenoidal field, Eq. (9): E_sol(r_i) = -sum_j dB_j/dt x S(r_i - r_j)
+   = sum_j S(r_i - r_j) x dB_j/dt, with S the scalar-potential kernel of
+   Eq. (8) (the integral of Eq. 10).  Eq. (11) as printed drops the minus
+   sign of Eq. (9); the sign here is the one for which the discrete curl of
+   E_sol is -dB/dt (Faraday), pinned in tests/test_oracle_eddy.py.
+3. Irrotational field, Eq. (12): Laplace's equation for phi_E inside the
+   magnet with d phi_E / dn = E_sol . n on its surface, E_irrot = -grad phi_E,
+   so that J . n = 0.  Finite volumes on the cells: an interior face
+   contributes (phi_j - phi_i) / d^2, a surface face s E_sol,a(i) / d with s
+   the sign of its outward normal; the right-hand side is projected onto
+   zero mean (compatibility of the pure Neumann problem) and phi has zero
+   mean (gauge).  Solved by red-black successive over-relaxation (colour
+   (i + j + k) mod 2, red first), omega = 2 / (1 + sin(pi / n_max)), a fixed
+   number of sweeps per step from the previous step's phi.
+   E_irrot,a(i) = -(g+ + g-) / 2 with g the face gradients, a surface face
+   taking E_sol,a(i).
+4. J = sigma (E_sol + E_irrot) and H_eddy(r_i) = sum_j J_j x S(r_i - r_j)
+   (Biot-Savart with the same kernel), held through the step's RK stages.
+
+Pins (tests/test_oracle_eddy.py): the window sums equal brute-force sums;
+Faraday's law for a divergence-free dB/dt; the converged SOR equals a direct
+sparse solve of the same system; the discrete surface flux J . n vanishes;
+Lenz's law (the eddy field opposes a growing uniform dB/dt).
+"""
+import numpy as np
+from .constants import MU0
+from .convolution import displacement_grid, WindowSum
+from .potential_kernel import potential_kernel
+
+EPS = {(0, 1, 2): 1.0, (1, 2, 0): 1.0, (2, 0, 1): 1.0,
+       (0, 2, 1): -1.0, (2, 1, 0): -1.0, (1, 0, 2): -1.0}
+
+
+def cross_kernels(desc, sign):
+    """Kernels of out_a = sign * sum_c (S x v_c)_a, i.e. sign * eps_abc S_b v_c."""
+    box = (0, desc.nx, 0, desc.ny, 0, desc.nz)
+    X, Y, Z = displacement_grid(desc, box)
+    S = potential_kernel(X, Y, Z, desc.dx, desc.dy, desc.dz)
+    ker = {}
+    for (a, b, c), e in EPS.items():
+        ker[(a, c)] = ker.get((a, c), 0.0) + sign * e * S[b]
+    return WindowSum(ker, (desc.nz, desc.ny, desc.nx), 3)
+
+
+def default_sweeps(desc):
+    return desc.sor_sweeps if desc.sor_sweeps > 0 else 40
+
+
+def default_omega(desc):
+    if desc.sor_omega > 0:
+        return desc.sor_omega
+    n = max(desc.nx, desc.ny, desc.nz)
+    return 2.0 / (1.0 + np.sin(np.pi / n))
+
+
+def neumann_rhs(desc, Esol):
+    """Right-hand side r of sum_interior (phi_j - phi_i)/d^2 = r_i."""
+    r = np.zeros(Esol.shape[1:])
+    for a, (axis, d) in enumerate(((2, desc.dx), (1, desc.dy), (0, desc.dz))):
+        n = r.shape[axis]
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[axis] = slice(0, 1)
+        hi[axis] = slice(n - 1, n)
+        # + surface face: outward normal +a; - surface face: -a
+        r[tuple(hi)] -= Esol[a][tuple(hi)] / d
+        r[tuple(lo)] += Esol[a][tuple(lo)] / d
+    return r - r.mean()
+
+
+def laplacian(desc, phi):
+    out = np.zeros_like(phi)
+    for axis, d in ((2, desc.dx), (1, desc.dy), (0, desc.dz)):
+        n = phi.shape[axis]
+        if n < 2:
+            continue
+        lo = [slice(None)] * 3
+        hi = [slice(None)] * 3
+        lo[axis] = slice(0, n - 1)
+        hi[axis] = slice(1, n)
+        diff = (phi[tuple(hi)] - phi[tuple(lo)]) / (d * d)
+        out[tuple(lo)] += diff
+        out[tuple(hi)] -= diff
+    return out
+
+
+def neighbour_weight(desc, shape):
+    """sum over interior faces of 1/d^2, per cell."""
+    w = np.zeros(shape)
+    for axis, d in ((2, desc.dx), (1, desc.dy), (0, desc.dz)):
+        n = shape[axis]
+        cnt = np.full(n, 2.0)
+        cnt[0] -= 1
+        cnt[-1] -= 1
+        sh = [1, 1, 1]
+        sh[axis] = n
+        w = w + cnt.reshape(sh) / (d * d)
+    return w
+
+
+def sor(desc, phi, r, sweeps, omega):
+    """Red-black SOR sweeps (red = (i+j+k) even first), then zero mean."""
+    nz, ny, nx = phi.shape
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    colour = (i + j + k) % 2
+    W = neighbour_weight(desc, phi.shape)
+    phi = phi.copy()
+    for _ in range(sweeps):
+        for c in (0, 1):
+            # sum of neighbour values / d^2 over interior faces
+            nb = laplacian(desc, phi) + W * phi
+            upd = (nb - r) / W
+            mask = colour == c
+            phi[mask] = (1 - omega) * phi[mask] + omega * upd[mask]
+    return phi - phi.mean()
+
+
+def irrotational(desc, phi, Esol):
+    """E_irrot = -(g+ + g-)/2 per axis; a surface face gradient is E_sol,a."""
+    E = np.zeros_like(Esol)
+    for a, (axis, d) in enumerate(((2, desc.dx), (1, desc.dy), (0, desc.dz))):
+        n = phi.shape[axis]
+        gp = np.array(Esol[a], copy=True)
+        gm = np.array(Esol[a], copy=True)
+        if n >= 2:
+            lo = [slice(None)] * 3
+            hi = [slice(None)] * 3
+            lo[axis] = slice(0, n - 1)
+            hi[axis] = slice(1, n)
+            g = (phi[tuple(hi)] - phi[tuple(lo)]) / d
+            gp[tuple(lo)] = g
+            gm[tuple(hi)] = g
+        E[a] = -0.5 * (gp + gm)
+    return E
+
+
+class EddyState:
+    """Held eddy field and the history it needs (single conducting magnet)."""
+
+    def __init__(self, desc):
+        self.desc = desc
+        shape = (3, desc.nz, desc.ny, desc.nx)
+        self.H_eddy = np.zeros(shape)
+        self.B_prev = None
+        self.phi = np.zeros(shape[1:])
+        self.E_sol = np.zeros(shape)
+        self.J = np.zeros(shape)
+        self._esol = None
+        self._heddy = None
+
+    def ops(self):
+        if self._esol is None:
+            self._esol = cross_kernels(self.desc, +1.0)   # E_sol = S x dB/dt
+            self._heddy = cross_kernels(self.desc, -1.0)  # H = J x S = -S x J
+        return self._esol, self._heddy
+
+    def b_field(self, system, m):
+        d = self.desc
+        Hd = system.self_op()(m)
+        h = np.asarray(d.Hext, dtype=np.float64)[:, None, None, None]
+        return MU0 * (Hd + h + d.Ms * m)
+
+    def update(self, system, dt):
+        d = self.desc
+        B = self.b_field(system, system.m[0])
+        if self.B_prev is None:
+            self.B_prev = B
+        dB = (B - self.B_prev) / dt
+        self.B_prev = B
+        esol_op, heddy_op = self.ops()
+        self.E_sol = esol_op(dB)
+        r = neumann_rhs(d, self.E_sol)
+        self.phi = sor(d, self.phi, r, default_sweeps(d), default_omega(d))
+        self.J = d.sigma * (self.E_sol + irrotational(d, self.phi, self.E_sol))
+        self.H_eddy = heddy_op(self.J)
