@@ -105,6 +105,19 @@ struct mmv_mesh {
   RowParams rp_hot{}, rp_force{};
   DriveP drive{};
   std::vector<void*> allocs;
+  // single-magnet three-dimensional path
+  bool cube = false;
+  int nz = 1, Lz = 1;
+  FftPlan pz{};
+  void* twz = nullptr;
+  void* specB = nullptr;
+  void* kern_s = nullptr;  // potential kernel S (eddy currents)
+  void *hd = nullptr, *he = nullptr, *bprev = nullptr, *bdot = nullptr, *es = nullptr, *phi = nullptr, *rr = nullptr;
+  double* red = nullptr;   // reduction partials + mean
+  CubeLaunch cl{};
+  bool eddy_first = true;
+  int sor_sweeps = 40;
+  double sor_omega = 1.0;
   // launch timing (diagnostics)
   int prof_kernel = 0;
   size_t prof_used = 0;
@@ -136,7 +149,9 @@ int validate(const mmv_mesh_desc* d) {
   if (d->n_films != 1 && d->n_films != 2) return fail(MMV_EINVAL, "n_films must be 1 or 2");
   if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(MMV_EINVAL, "nx, ny, nz must be >= 1");
   if (d->nx > 8192 || d->ny > 8192) return fail(MMV_EINVAL, "nx, ny must be <= 8192");
-  if (d->nz != 1) return fail(MMV_EINVAL, "this build supports films one cell thick (nz == 1)");
+  if (d->nz > 8192) return fail(MMV_EINVAL, "nz must be <= 8192");
+  if (d->nz != 1 && d->n_films != 1)
+    return fail(MMV_EINVAL, "two films must be one cell thick (nz == 1); nz > 1 is the single-magnet path");
   auto pos = [](double v) { return isfinite(v) && v > 0; };
   if (!pos(d->dx) || !pos(d->dy) || !pos(d->dz)) return fail(MMV_EINVAL, "cell edges must be finite and > 0");
   if (!pos(d->Ms)) return fail(MMV_EINVAL, "Ms must be finite and > 0");
@@ -148,8 +163,12 @@ int validate(const mmv_mesh_desc* d) {
   if (d->precision != 32 && d->precision != 64) return fail(MMV_EINVAL, "precision must be 32 or 64");
   if (d->cross_mode != 0 && d->cross_mode != 1) return fail(MMV_EINVAL, "cross_mode must be 0 or 1");
   if (d->cross_mode == 1 && d->n_films != 2) return fail(MMV_EINVAL, "cross_mode 1 needs two films");
-  if (d->sigma != 0.0)
-    return fail(MMV_EINVAL, "eddy currents need magnets more than one cell thick (sigma must be 0 for nz == 1)");
+  if (!isfinite(d->sigma) || d->sigma < 0) return fail(MMV_EINVAL, "sigma must be finite and >= 0");
+  if (d->sigma != 0.0 && !(d->n_films == 1 && d->nz > 1 && d->ny > 1 && d->nx > 1))
+    return fail(MMV_EINVAL,
+                "eddy currents need a single magnet more than one cell thick in every direction (sigma must be 0)");
+  if (d->sor_sweeps < 0 || d->sor_sweeps > 100000) return fail(MMV_EINVAL, "sor_sweeps must be in [0, 100000]");
+  if (!isfinite(d->sor_omega) || d->sor_omega < 0 || d->sor_omega >= 2) return fail(MMV_EINVAL, "sor_omega must be in [0, 2)");
   if (d->gap_cells < 0) return fail(MMV_EINVAL, "gap_cells must be >= 0");
   if (d->max_travel_cells < 0 || d->max_travel_cells > 4096)
     return fail(MMV_EINVAL, "max_travel_cells must be in [0, 4096]");
@@ -455,16 +474,6 @@ int init_typed(mmv_mesh* h) {
   return MMV_OK;
 }
 
-template <typename T>
-void* mptr(mmv_mesh* h, void* base, int film) {
-  return (char*)base + (size_t)film * 3 * h->nx * h->ny * sizeof(T);
-}
-
-int check_handle(mmv_handle h) {
-  if (!h) return fail(MMV_EINVAL, "handle is NULL");
-  return MMV_OK;
-}
-
 // Record a timing event before (begin = true) or after a launch of `kernel`.
 int prof_mark(mmv_mesh* h, int kernel) {
   if (h->prof_kernel != kernel) return MMV_OK;
@@ -482,6 +491,188 @@ int prof_mark(mmv_mesh* h, int kernel) {
     int rc_ = prof_mark(h, (k));     \
     if (rc_) return rc_;             \
   } while (0)
+
+// ---------------------------------------------------------------- single magnet, 3-D
+template <typename T>
+int build_kernels_cube(mmv_mesh* h) {
+  const mmv_mesh_desc& d = h->d;
+  const size_t nk = (size_t)h->Kx * (h->Ly / 2 + 1) * (h->Lz / 2 + 1);
+  int rc = dalloc(h, &h->kern, sizeof(T) * 6 * nk);
+  if (rc) return rc;
+  if (d.sigma > 0 && (rc = dalloc(h, &h->kern_s, sizeof(T) * 3 * nk))) return rc;
+  mmv_mesh tmp_owner;
+  void *grid = nullptr, *s1 = nullptr, *s2 = nullptr, *twxd = nullptr, *twpd = nullptr, *twyd = nullptr, *twzd = nullptr;
+  const size_t ng = (size_t)h->Lx * h->Ly * h->Lz;
+  const size_t ns = (size_t)h->Kx * h->Ly * h->Lz;
+  rc = dalloc(&tmp_owner, &grid, sizeof(double) * ng);
+  if (!rc) rc = dalloc(&tmp_owner, &s1, 2 * sizeof(double) * ns);
+  if (!rc) rc = dalloc(&tmp_owner, &s2, 2 * sizeof(double) * ns);
+  if (!rc) rc = upload_tw(&tmp_owner, &twxd, h->N2x, h->N2x, true);
+  if (!rc) rc = upload_tw(&tmp_owner, &twpd, h->Lx, h->N2x + 1, true);
+  if (!rc) rc = upload_tw(&tmp_owner, &twyd, h->Ly, h->Ly, true);
+  if (!rc) rc = upload_tw(&tmp_owner, &twzd, h->Lz, h->Lz, true);
+  if (rc) {
+    free_all(&tmp_owner);
+    return rc;
+  }
+  const double inv = 1.0 / ((double)h->Lx * h->Ly * h->Lz);
+  hipError_t err = hipSuccess;
+  const int nkind = d.sigma > 0 ? 2 : 1;
+  for (int kind = 0; kind < nkind && err == hipSuccess; ++kind) {
+    for (int comp = 0; comp < (kind == 0 ? 6 : 3) && err == hipSuccess; ++comp) {
+      // tensor spectra carry -Ms (Eq. 6); S spectra enter the eddy sums bare
+      const double scale = kind == 0 ? -d.Ms * inv : inv;
+      err = launch_kernel_real3((double*)grid, h->Lx, h->Ly, h->Lz, kind, comp, d.dx, d.dy, d.dz, d.rc_cells, scale,
+                                h->st);
+      if (err == hipSuccess)
+        err = launch_row_fwd<double>((const double*)grid, s1, h->Ly * h->Lz, h->Lx, h->N2x, h->Kx, h->px, twxd, twpd,
+                                     h->st);
+      if (err == hipSuccess)
+        err = launch_fft_axis<double>(s1, s2, h->Lz, h->Kx, 0, h->Ly, (long long)h->Ly * h->Kx, h->Ly,
+                                      (long long)h->Ly * h->Kx, h->py, twyd, false, h->st);
+      if (err == hipSuccess)
+        err = launch_fft_axis<double>(s2, s1, 1, h->Ly * h->Kx, 0, h->Lz, 0, h->Lz, 0, h->pz, twzd, false, h->st);
+      T* dst = (T*)(kind == 0 ? h->kern : h->kern_s) + (size_t)comp * nk;
+      if (err == hipSuccess) err = launch_pack3<T>(s1, dst, h->Kx, h->Ly, h->Lz, kind == 1 ? 1 : 0, h->st);
+    }
+  }
+  if (err == hipSuccess) err = hipStreamSynchronize(h->st);
+  free_all(&tmp_owner);
+  if (err != hipSuccess) return fail(MMV_EHIP, std::string("kernel construction: ") + hipGetErrorString(err));
+  return MMV_OK;
+}
+
+template <typename T>
+int init_cube(mmv_mesh* h) {
+  const mmv_mesh_desc& d = h->d;
+  h->esz = sizeof(T);
+  const size_t N = (size_t)h->nx * h->ny * h->nz;
+  int rc;
+  void** bufs3[] = {&h->m0, &h->mb[0], &h->mb[1], &h->acc, &h->hd, &h->he};
+  for (void** b : bufs3)
+    if ((rc = dalloc(h, b, 3 * N * sizeof(T)))) return rc;
+  if ((rc = dalloc(h, &h->spec1, 2 * sizeof(T) * 3 * (size_t)h->nz * h->ny * h->Kx))) return rc;
+  if ((rc = dalloc(h, &h->specB, 2 * sizeof(T) * 3 * (size_t)h->nz * h->Ly * h->Kx))) return rc;
+  if (d.sigma > 0) {
+    void** e3[] = {&h->bprev, &h->bdot, &h->es};
+    for (void** b : e3)
+      if ((rc = dalloc(h, b, 3 * N * sizeof(T)))) return rc;
+    if ((rc = dalloc(h, &h->phi, N * sizeof(T)))) return rc;
+    if ((rc = dalloc(h, &h->rr, N * sizeof(T)))) return rc;
+    HIPCHK(hipMemsetAsync(h->phi, 0, N * sizeof(T), h->st));
+  }
+  if ((rc = dalloc(h, (void**)&h->red, sizeof(double) * (N / 256 + 4)))) return rc;
+  HIPCHK(hipMemsetAsync(h->he, 0, 3 * N * sizeof(T), h->st));
+  if ((rc = upload_tw(h, &h->twx, h->N2x, h->N2x, sizeof(T) == 8))) return rc;
+  if ((rc = upload_tw(h, &h->twp, h->Lx, h->N2x + 1, sizeof(T) == 8))) return rc;
+  if ((rc = upload_tw(h, &h->twy, h->Ly, h->Ly, sizeof(T) == 8))) return rc;
+  if ((rc = upload_tw(h, &h->twz, h->Lz, h->Lz, sizeof(T) == 8))) return rc;
+  if ((rc = dalloc(h, (void**)&h->rigid, sizeof(RigidState)))) return rc;
+  RigidState r{};
+  HIPCHK(hipMemcpyAsync(h->rigid, &r, sizeof(r), hipMemcpyHostToDevice, h->st));
+  std::vector<T> mz(3 * N, T(0));
+  for (size_t i = 0; i < N; ++i) mz[2 * N + i] = T(1);
+  HIPCHK(hipMemcpyAsync(h->m0, mz.data(), mz.size() * sizeof(T), hipMemcpyHostToDevice, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  if ((rc = build_kernels_cube<T>(h))) return rc;
+  CubeLaunch& c = h->cl;
+  c.nx = h->nx;
+  c.ny = h->ny;
+  c.nz = h->nz;
+  c.dx = d.dx;
+  c.dy = d.dy;
+  c.dz = d.dz;
+  c.pref_ex = 2.0 * d.Aex / (MU0 * d.Ms);
+  c.pref_an = 2.0 * d.Ku / (MU0 * d.Ms);
+  const double un = sqrt(d.u[0] * d.u[0] + d.u[1] * d.u[1] + d.u[2] * d.u[2]);
+  for (int i = 0; i < 3; ++i) {
+    c.u[i] = un > 0 ? d.u[i] / un : 0.0;
+    c.hext[i] = d.Hext[i];
+  }
+  c.gam = GAMMA0 / (1.0 + d.alpha * d.alpha);
+  c.alpha = d.alpha;
+  h->sor_sweeps = d.sor_sweeps > 0 ? d.sor_sweeps : 40;
+  const int nmax = std::max(h->nx, std::max(h->ny, h->nz));
+  h->sor_omega = d.sor_omega > 0 ? d.sor_omega : 2.0 / (1.0 + sin(M_PI / nmax));
+  return MMV_OK;
+}
+
+// Demagnetising-type convolution of a three-channel cell field:
+// x transform, y transform, z pencils with the kernel, inverse y, inverse x.
+template <typename T>
+int conv3(mmv_mesh* h, const void* src, void* dst, const T* kern, int mode, double sgn) {
+  const int nrow = 3 * h->nz * h->ny;
+  HIPCHK(launch_row_fwd<T>((const T*)src, h->spec1, nrow, h->nx, h->N2x, h->Kx, h->px, h->twx, h->twp, h->st));
+  HIPCHK(launch_fft_axis<T>(h->spec1, h->specB, 3 * h->nz, h->Kx, 0, h->ny, (long long)h->ny * h->Kx, h->Ly,
+                            (long long)h->Ly * h->Kx, h->py, h->twy, false, h->st));
+  const int CBz = sizeof(T) == 4 ? 8 : 4;
+  HIPCHK(launch_zmul<T>(h->specB, kern, h->Kx, h->Ly, h->nz, CBz, mode, sgn, h->pz, h->twz, h->st));
+  HIPCHK(launch_fft_axis<T>(h->specB, h->spec1, 3 * h->nz, h->Kx, 0, h->Ly, (long long)h->Ly * h->Kx, h->ny,
+                            (long long)h->ny * h->Kx, h->py, h->twy, true, h->st));
+  HIPCHK(launch_row_inv<T>(h->spec1, (T*)dst, nrow, h->nx, h->N2x, h->Kx, h->px, h->twx, h->twp, h->st));
+  return MMV_OK;
+}
+
+// Eddy-current update at the start of a step (field held through its stages).
+template <typename T>
+int eddy_update(mmv_mesh* h, double dt) {
+  const size_t N = (size_t)h->nx * h->ny * h->nz;
+  const double* part = h->red;
+  double* mean = h->red + (N / 256 + 2);
+  HIPCHK(launch_eddy_bdot<T>(N, (const T*)h->m0, (const T*)h->hd, (T*)h->bprev, (T*)h->bdot, MU0, h->d.Ms,
+                             h->d.Hext, 1.0 / dt, h->eddy_first ? 1 : 0, h->st));
+  h->eddy_first = false;
+  int rc = conv3<T>(h, h->bdot, h->es, (const T*)h->kern_s, 1, +1.0);
+  if (rc) return rc;
+  HIPCHK(launch_sor_rhs<T>(h->cl, (const T*)h->es, (T*)h->rr, h->red, mean, h->st));
+  HIPCHK(launch_sor<T>(h->cl, (T*)h->phi, (const T*)h->rr, h->sor_omega, h->sor_sweeps, h->red, mean, h->st));
+  HIPCHK(launch_current<T>(h->cl, (const T*)h->phi, (const T*)h->es, (T*)h->bdot, h->d.sigma, h->st));
+  (void)part;
+  return conv3<T>(h, h->bdot, h->he, (const T*)h->kern_s, 1, -1.0);
+}
+
+template <typename T>
+int step_cube(mmv_mesh* h, double dt, int nsteps) {
+  T* m0 = (T*)h->m0;
+  T* b1 = (T*)h->mb[0];
+  T* b2 = (T*)h->mb[1];
+  for (int n = 0; n < nsteps; ++n) {
+    for (int s = 0; s < 4; ++s) {
+      T* in = s == 0 ? m0 : (s == 1 ? b1 : (s == 2 ? b2 : b1));
+      T* out = s == 0 ? b1 : (s == 1 ? b2 : (s == 2 ? b1 : m0));
+      int rc = conv3<T>(h, in, h->hd, (const T*)h->kern, 0, 1.0);
+      if (rc) return rc;
+      if (s == 0 && h->d.sigma > 0 && (rc = eddy_update<T>(h, dt))) return rc;
+      PROF(3);
+      HIPCHK(launch_stage3<T>(h->cl, MODE_STAGE, s, MMV_TERM_ALL, dt, in, m0, out, (T*)h->acc, (const T*)h->hd,
+                              (const T*)h->he, nullptr, &h->rigid->flags, h->st));
+      PROF(3);
+    }
+    HIPCHK(launch_rigid_tick(h->rigid, dt, h->st));
+  }
+  return MMV_OK;
+}
+
+template <typename T>
+int eval_cube(mmv_mesh* h, int mask, void* hout) {
+  if (mask & MMV_TERM_DEMAG_SELF) {
+    int rc = conv3<T>(h, h->m0, h->hd, (const T*)h->kern, 0, 1.0);
+    if (rc) return rc;
+  }
+  HIPCHK(launch_stage3<T>(h->cl, MODE_EVAL, 0, mask & (1 | 2 | 4 | 8 | 32), 0.0, (const T*)h->m0, (const T*)h->m0,
+                          nullptr, nullptr, (const T*)h->hd, (const T*)h->he, (T*)hout, &h->rigid->flags, h->st));
+  return MMV_OK;
+}
+
+template <typename T>
+void* mptr(mmv_mesh* h, void* base, int film) {
+  return (char*)base + (size_t)film * 3 * h->nx * h->ny * sizeof(T);
+}
+
+int check_handle(mmv_handle h) {
+  if (!h) return fail(MMV_EINVAL, "handle is NULL");
+  return MMV_OK;
+}
 
 template <typename T>
 int run_fields(mmv_mesh* h, const void* m_in, const OutTable& tab) {
@@ -600,6 +791,37 @@ int init_mesh(const mmv_mesh_desc* d, void* hip_stream, mmv_handle* out) {
   h->nfilm = d->n_films;
   h->nx = d->nx;
   h->ny = d->ny;
+  if (d->n_films == 1 && d->nz > 1) {
+    h->cube = true;
+    h->nz = d->nz;
+    h->Lx = d->fft_lx ? d->fft_lx : next_smooth(2 * d->nx - 1, true);
+    h->Ly = d->fft_ly ? d->fft_ly : next_smooth(2 * d->ny - 1, false);
+    h->Lz = d->fft_lz ? d->fft_lz : next_smooth(2 * d->nz - 1, false);
+    if (h->Lx < 2 * d->nx - 1 || h->Lx % 2 || !smooth2357(h->Lx) || h->Ly < 2 * d->ny - 1 || !smooth2357(h->Ly) ||
+        h->Lz < 2 * d->nz - 1 || !smooth2357(h->Lz)) {
+      delete h;
+      return fail(MMV_EINVAL, "FFT lengths must be {2,3,5,7}-smooth and >= 2n-1 per axis (Lx even)");
+    }
+    h->N2x = h->Lx / 2;
+    h->Kx = h->N2x + 1;
+    h->Kyh = h->Ly / 2 + 1;
+    if (!make_plan(h->N2x, h->px) || !make_plan(h->Ly, h->py) || !make_plan(h->Lz, h->pz)) {
+      delete h;
+      return fail(MMV_EINVAL, "FFT length has too many factors");
+    }
+    if (sizeof(double) * 2 * (4 * (size_t)h->N2x + 1) > 160 * 1024 || h->Ly > 4096 || h->Lz > 2048) {
+      delete h;
+      return fail(MMV_EINVAL, "mesh too large for the three-dimensional path");
+    }
+    rc = d->precision == 64 ? init_cube<double>(h) : init_cube<float>(h);
+    if (rc) {
+      free_all(h);
+      delete h;
+      return rc;
+    }
+    *out = h;
+    return MMV_OK;
+  }
   const int hx = d->n_films == 2 ? d->halo : 0;
   const int T = d->n_films == 2 ? d->max_travel_cells : 0;
   const int lx_min = d->n_films == 2 ? 2 * (d->nx + hx + T) : 2 * d->nx;
@@ -680,8 +902,9 @@ int set_m(mmv_handle h, int film, const void* m_dev) {
   if (rc) return rc;
   if (film < 0 || film >= h->nfilm) return fail(MMV_EINVAL, "film out of range");
   if (!m_dev) return fail(MMV_EINVAL, "m_dev is NULL");
-  const size_t bytes = (size_t)3 * h->nx * h->ny * h->esz;
+  const size_t bytes = (size_t)3 * h->nx * h->ny * h->nz * h->esz;
   HIPCHK(hipMemcpyAsync((char*)h->m0 + film * bytes, m_dev, bytes, hipMemcpyDeviceToDevice, h->st));
+  h->eddy_first = true;
   return MMV_OK;
 }
 
@@ -690,7 +913,7 @@ int get_m(mmv_handle h, int film, void* m_dev) {
   if (rc) return rc;
   if (film < 0 || film >= h->nfilm) return fail(MMV_EINVAL, "film out of range");
   if (!m_dev) return fail(MMV_EINVAL, "m_dev is NULL");
-  const size_t bytes = (size_t)3 * h->nx * h->ny * h->esz;
+  const size_t bytes = (size_t)3 * h->nx * h->ny * h->nz * h->esz;
   HIPCHK(hipMemcpyAsync(m_dev, (char*)h->m0 + film * bytes, bytes, hipMemcpyDeviceToDevice, h->st));
   return MMV_OK;
 }
@@ -743,6 +966,7 @@ int eval_heff(mmv_handle h, int film, int term_mask, void* h_dev) {
   if (film < 0 || film >= h->nfilm) return fail(MMV_EINVAL, "film out of range");
   if (!h_dev) return fail(MMV_EINVAL, "h_dev is NULL");
   if (term_mask & ~MMV_TERM_ALL) return fail(MMV_EINVAL, "unknown term bits");
+  if (h->cube) return h->esz == 8 ? eval_cube<double>(h, term_mask, h_dev) : eval_cube<float>(h, term_mask, h_dev);
   return h->esz == 8 ? eval_typed<double>(h, film, term_mask, h_dev) : eval_typed<float>(h, film, term_mask, h_dev);
 }
 
@@ -751,6 +975,7 @@ int llg_step(mmv_handle h, double dt, int nsteps) {
   if (rc) return rc;
   if (!(dt > 0) || !isfinite(dt)) return fail(MMV_EINVAL, "dt must be finite and > 0");
   if (nsteps < 0) return fail(MMV_EINVAL, "nsteps must be >= 0");
+  if (h->cube) return h->esz == 8 ? step_cube<double>(h, dt, nsteps) : step_cube<float>(h, dt, nsteps);
   return h->esz == 8 ? step_typed<double>(h, dt, nsteps) : step_typed<float>(h, dt, nsteps);
 }
 
@@ -784,7 +1009,7 @@ int get_fft_lengths(mmv_handle h, int* lx, int* ly, int* lz) {
   if (rc) return rc;
   if (lx) *lx = h->Lx;
   if (ly) *ly = h->Ly;
-  if (lz) *lz = 1;
+  if (lz) *lz = h->cube ? h->Lz : 1;
   return MMV_OK;
 }
 

@@ -23,6 +23,40 @@ hipError_t launch_colpack(const void* spec, T* out, int Kx, int Ly, int Kyh, con
                           int imag, hipStream_t st);
 template <typename T>
 size_t row_lds_bytes(const RowParams& p);
+
+// single-magnet three-dimensional path
+struct CubeLaunch {
+  int nx, ny, nz;
+  double dx, dy, dz;
+  double pref_ex, pref_an, u[3], hext[3], gam, alpha;
+};
+template <typename T>
+hipError_t launch_fft_axis(const void* in, void* out, int nplanes, int ncols, int CB, int n_in, long long in_ps,
+                           int n_out, long long out_ps, const FftPlan& P, const void* tw, bool inv, hipStream_t st);
+template <typename T>
+hipError_t launch_zmul(void* buf, const T* kern, int Kx, int Ly, int nz, int CB, int mode, double sgn,
+                       const FftPlan& P, const void* twz, hipStream_t st);
+template <typename T>
+hipError_t launch_row_inv(const void* spec, T* out, int nrows, int nx, int N2x, int Kx, const FftPlan& P,
+                          const void* tw, const void* twp, hipStream_t st);
+template <typename T>
+hipError_t launch_stage3(const CubeLaunch& c, int mode, int stage, int mask, double dt, const T* ms, const T* m0,
+                         T* mnext, T* acc, const T* hd, const T* he, T* hout, int* flags, hipStream_t st);
+template <typename T>
+hipError_t launch_eddy_bdot(size_t N, const T* m, const T* hd, T* bprev, T* bdot, double mu0, double Ms,
+                            const double* hext, double idt, int first, hipStream_t st);
+template <typename T>
+hipError_t launch_sor_rhs(const CubeLaunch& c, const T* es, T* r, double* part, double* mean, hipStream_t st);
+template <typename T>
+hipError_t launch_sor(const CubeLaunch& c, T* phi, const T* r, double omega, int sweeps, double* part, double* mean,
+                      hipStream_t st);
+template <typename T>
+hipError_t launch_current(const CubeLaunch& c, const T* phi, const T* es, T* J, double sigma, hipStream_t st);
+hipError_t launch_rigid_tick(RigidState* r, double dt, hipStream_t st);
+hipError_t launch_kernel_real3(double* out, int Lx, int Ly, int Lz, int kind, int comp, double dx, double dy,
+                               double dz, double rc, double scale, hipStream_t st);
+template <typename T>
+hipError_t launch_pack3(const void* spec, T* out, int Kx, int Ly, int Lz, int imag, hipStream_t st);
 template <typename T>
 size_t col_lds_bytes(int Ly, int nbuf);
 

@@ -38,7 +38,7 @@ def test_struct_layout_matches_header():
 @pytest.mark.parametrize("field,value,msg", [
     ("n_films", 3, "n_films"), ("nx", 0, "nx"), ("dx", 0.0, "cell edges"),
     ("dz", float("nan"), "cell edges"), ("Ms", -1.0, "Ms"), ("precision", 16, "precision"),
-    ("halo", 1, "halo"), ("gap_cells", -1, "gap_cells"), ("nz", 2, "nz == 1"),
+    ("halo", 1, "halo"), ("gap_cells", -1, "gap_cells"), ("nz", 2, "one cell thick"),
     ("sigma", 1e6, "eddy"), ("rc_cells", 0.0, "rc_cells"), ("max_travel_cells", -1, "max_travel"),
     ("fft_lx", 71, "fft_lx"), ("fft_ly", 11, "fft_ly"),
 ])
@@ -67,3 +67,13 @@ def test_potential_mode_needs_two_films():
     with pytest.raises(mmv.MMVError) as e:
         mmv.init_mesh(mmv.to_desc(d))
     assert e.value.code == -1 and "two films" in str(e.value)
+
+
+def test_eddy_needs_a_thick_single_magnet():
+    d = get_config("stickslip")["desc"].replace(sigma=1e6)
+    with pytest.raises(mmv.MMVError) as e:
+        mmv.init_mesh(mmv.to_desc(d))
+    assert "eddy" in str(e.value)
+    d = get_config("cube_eddy")["desc"].replace(sor_omega=2.5)
+    with pytest.raises(mmv.MMVError):
+        mmv.init_mesh(mmv.to_desc(d))
