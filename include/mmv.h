@@ -150,6 +150,29 @@ int profile_end(mmv_handle h, double* total_ms, long* launches);
 /* Chosen FFT lengths (diagnostics). */
 int get_fft_lengths(mmv_handle h, int* lx, int* ly, int* lz);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent two-film meshes of uneven sizes advanced
+ * together, one launch per pass covering every instance (per-instance
+ * descriptors live in device memory), optionally replayed from a captured
+ * HIP graph.  Instances of equal geometry share their kernel spectra.
+ * flags: MMV_BATCH_AUTOTUNE times the y-pass grouping per mesh size at
+ * set-up and keeps the fastest; MMV_BATCH_GRAPH captures 8 steps into a
+ * graph (on an internal stream ordered after the caller's) and replays it.
+ * All instances must have two films, the same precision and nz == 1.     */
+enum { MMV_BATCH_AUTOTUNE = 1, MMV_BATCH_GRAPH = 2 };
+typedef struct mmv_batch* mmv_batch_handle;
+
+int init_batch(const mmv_mesh_desc* descs, int n, void* hip_stream, int flags, mmv_batch_handle* out);
+/* Per-instance handle (owned by the batch; do not destroy): set_m, get_m,
+ * set_drive, set_offset, eval_heff, stray_force and get_state act on that
+ * instance.                                                              */
+int batch_instance(mmv_batch_handle b, int i, mmv_handle* out);
+/* Advance every instance nsteps RK4 steps of size dt (llg_step semantics). */
+int batch_step(mmv_batch_handle b, double dt, int nsteps);
+/* Chosen y-pass grouping of instance i (diagnostics).                   */
+int batch_tuning(mmv_batch_handle b, int i, int* col_groups);
+int destroy_batch(mmv_batch_handle b);
+
 /* Release every device buffer of the handle.  NULL is accepted.         */
 int destroy_mesh(mmv_handle h);
 

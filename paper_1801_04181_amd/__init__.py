@@ -12,7 +12,8 @@ import os
 __all__ = ["MMVError", "lib_path", "load", "MeshDesc", "DriveDesc", "init_mesh",
            "set_m", "get_m", "set_offset", "set_drive", "eval_heff", "llg_step",
            "stray_force", "get_state", "get_fft_lengths", "destroy_mesh",
-           "profile_begin", "profile_end",
+           "profile_begin", "profile_end", "init_batch", "batch_instance", "batch_step",
+           "batch_tuning", "destroy_batch", "Batch",
            "last_error", "Mesh", "TERM", "EXPORTS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -24,7 +25,9 @@ ERRORS = {-1: "MMV_EINVAL", -2: "MMV_ENOMEM", -3: "MMV_EHIP", -4: "MMV_ERANGE",
           -5: "MMV_ENUMERIC", -6: "MMV_ESTATE"}
 EXPORTS = ("init_mesh", "set_m", "get_m", "set_offset", "set_drive", "eval_heff",
            "llg_step", "stray_force", "get_state", "profile_begin", "profile_end",
-           "get_fft_lengths", "destroy_mesh", "mmv_last_error")
+           "get_fft_lengths", "init_batch", "batch_instance", "batch_step", "batch_tuning",
+           "destroy_batch", "destroy_mesh", "mmv_last_error")
+BATCH_AUTOTUNE, BATCH_GRAPH = 1, 2
 
 
 class MMVError(RuntimeError):
@@ -79,6 +82,11 @@ def load():
         lib.get_fft_lengths.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
         lib.destroy_mesh.argtypes = [vp]
         lib.profile_begin.argtypes = [vp, i]
+        lib.init_batch.argtypes = [ctypes.POINTER(MeshDesc), i, vp, i, ctypes.POINTER(vp)]
+        lib.batch_instance.argtypes = [vp, i, ctypes.POINTER(vp)]
+        lib.batch_step.argtypes = [vp, d, i]
+        lib.batch_tuning.argtypes = [vp, i, ctypes.POINTER(i)]
+        lib.destroy_batch.argtypes = [vp]
         lib.profile_end.argtypes = [vp, pd, ctypes.POINTER(ctypes.c_long)]
         lib.mmv_last_error.restype = ctypes.c_char_p
         for name in EXPORTS[:-1]:
@@ -197,6 +205,81 @@ def profile_end(h):
 
 def destroy_mesh(h):
     _check(load().destroy_mesh(h))
+
+
+def init_batch(descs, stream=None, flags=0):
+    arr = (MeshDesc * len(descs))(*[d if isinstance(d, MeshDesc) else to_desc(d) for d in descs])
+    h = ctypes.c_void_p()
+    _check(load().init_batch(arr, len(descs), _stream(stream), int(flags), ctypes.byref(h)))
+    return h
+
+
+def batch_instance(b, i):
+    h = ctypes.c_void_p()
+    _check(load().batch_instance(b, int(i), ctypes.byref(h)))
+    return h
+
+
+def batch_step(b, dt, nsteps=1):
+    _check(load().batch_step(b, float(dt), int(nsteps)))
+
+
+def batch_tuning(b, i):
+    g = ctypes.c_int()
+    _check(load().batch_tuning(b, int(i), ctypes.byref(g)))
+    return g.value
+
+
+def destroy_batch(b):
+    _check(load().destroy_batch(b))
+
+
+class Batch:
+    """Many film pairs advanced together (torch tensors for device memory)."""
+
+    def __init__(self, descs, drives=None, ms=None, flags=0, stream=None, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.descs = list(descs)
+        self.dtype = torch.float64 if self.descs[0].precision == 64 else torch.float32
+        self.b = init_batch(self.descs, self.stream, flags)
+        self.h = [batch_instance(self.b, i) for i in range(len(self.descs))]
+        for i, d in enumerate(self.descs):
+            if drives is not None:
+                set_drive(self.h[i], drives[i])
+            if ms is not None:
+                for f, mf in enumerate(ms[i]):
+                    t = torch.as_tensor(mf, dtype=self.dtype).to(self.device).contiguous()
+                    set_m(self.h[i], f, t)
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def step(self, dt, n=1):
+        batch_step(self.b, dt, n)
+
+    def get_m(self, i, film):
+        d = self.descs[i]
+        out = self.torch.empty((3, d.nz, d.ny, d.nx), dtype=self.dtype, device=self.device)
+        get_m(self.h[i], film, out)
+        return out
+
+    def state(self, i):
+        return get_state(self.h[i])
+
+    def tuning(self, i):
+        return batch_tuning(self.b, i)
+
+    def close(self):
+        if self.b is not None:
+            destroy_batch(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Mesh:

@@ -7,6 +7,7 @@
 #include <string.h>
 #include <string>
 #include <vector>
+#include <algorithm>
 #include "mmv.h"
 #include "mmv_internal.h"
 #include "mmv_kernels.h"
@@ -116,6 +117,7 @@ struct mmv_mesh {
   double* red = nullptr;   // reduction partials + mean
   CubeLaunch cl{};
   bool eddy_first = true;
+  bool in_batch = false;  // owned by a batch: destroy_mesh refuses it
   int sor_sweeps = 40;
   double sor_omega = 1.0;
   // launch timing (diagnostics)
@@ -775,6 +777,270 @@ int report_flags(mmv_mesh* h, RigidState& r) {
 
 }  // namespace
 
+
+// ---------------------------------------------------------------- batches
+struct mmv_batch {
+  std::vector<mmv_mesh*> inst;
+  hipStream_t st = nullptr;
+  hipStream_t gst = nullptr;
+  int esz = 4;
+  int flags = 0;
+  std::vector<void*> allocs;
+  RowFwdDesc* d_fwd[4] = {};
+  ColDesc* d_col = nullptr;
+  RowStageDesc* d_stage[4] = {};
+  int *s_fwd = nullptr, *s_col = nullptr, *s_stage = nullptr;
+  int nblk_fwd = 0, nblk_col = 0, nblk_stage = 0;
+  size_t lds_fwd = 0, lds_col = 0, lds_stage = 0;
+  std::vector<int> drive_sig;  // drive modes the stage descriptors were built for
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  double g_dt = 0.0;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+namespace {
+
+int balloc(mmv_batch* b, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+  if (e != hipSuccess) return fail(MMV_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  b->allocs.push_back(*p);
+  return MMV_OK;
+}
+
+RowParams stage_params(mmv_mesh* h) {
+  RowParams rp = h->rp_hot;
+  rp.mode = MODE_STAGE;
+  rp.term_mask = MMV_TERM_ALL;
+  rp.drive = h->drive;
+  rp.with_force = (h->drive.mode == MMV_DRIVE_SPRING) ? 1 : 0;
+  rp.full_force = 0;
+  rp.ntask = h->nfilm * h->ny + (rp.with_force ? 2 : 0);
+  return rp;
+}
+
+// (Re)build the per-instance descriptors and block tables.
+template <typename T>
+int batch_build(mmv_batch* b) {
+  const int n = (int)b->inst.size();
+  std::vector<RowFwdDesc> fwd[4];
+  std::vector<RowStageDesc> stg[4];
+  std::vector<ColDesc> col(n);
+  std::vector<int> sf(n + 1, 0), sc(n + 1, 0), ss(n + 1, 0);
+  b->lds_fwd = b->lds_col = b->lds_stage = 0;
+  b->drive_sig.assign(n, 0);
+  for (int i = 0; i < n; ++i) {
+    mmv_mesh* h = b->inst[i];
+    b->drive_sig[i] = h->drive.mode;
+    T* m0 = (T*)h->m0;
+    T* b1 = (T*)h->mb[0];
+    T* b2 = (T*)h->mb[1];
+    const RowParams rp = stage_params(h);
+    for (int s = 0; s < 4; ++s) {
+      T* in = s == 0 ? m0 : (s == 1 ? b1 : (s == 2 ? b2 : b1));
+      T* out = s == 0 ? b1 : (s == 1 ? b2 : (s == 2 ? b1 : m0));
+      RowFwdDesc f{};
+      f.src = in;
+      f.dst = h->spec1;
+      f.nin = h->nx;
+      f.N2x = h->N2x;
+      f.Kx = h->Kx;
+      f.P = h->px;
+      f.tw = h->twx;
+      f.twp = h->twp;
+      fwd[s].push_back(f);
+      RowStageDesc r{};
+      r.p = rp;
+      r.spec2 = h->spec2;
+      r.mst = in;
+      r.m0 = m0;
+      r.mnext = out;
+      r.acc = h->acc;
+      r.tw = h->twx;
+      r.twp = h->twp;
+      r.rigid = h->rigid;
+      r.partial = h->partial;
+      r.counter = h->counter;
+      stg[s].push_back(r);
+    }
+    ColDesc& c = col[i];
+    c.spec1 = h->spec1;
+    c.spec2 = h->spec2;
+    c.kern = h->kern;
+    c.Kx = h->Kx;
+    c.Ly = h->Ly;
+    c.Kyh = h->Kyh;
+    c.ny = h->ny;
+    c.nin_ch = 3 * h->nfilm;
+    c.ngroup = h->ngroup;
+    const int per = (h->tab_hot.n + h->ngroup - 1) / h->ngroup;
+    c.nbuf = c.nin_ch > per ? c.nin_ch : per;
+    c.P = h->py;
+    c.twy = h->twy;
+    c.tab = h->tab_hot;
+    sf[i + 1] = sf[i] + 3 * h->nfilm * h->ny;
+    sc[i + 1] = sc[i] + h->Kx * h->ngroup;
+    ss[i + 1] = ss[i] + rp.ntask;
+    b->lds_fwd = std::max(b->lds_fwd, row_fwd_lds_bytes(h->N2x, sizeof(T)));
+    b->lds_col = std::max(b->lds_col, col_lds_bytes<T>(h->Ly, c.nbuf));
+    b->lds_stage = std::max(b->lds_stage, row_lds_bytes<T>(rp));
+  }
+  b->nblk_fwd = sf[n];
+  b->nblk_col = sc[n];
+  b->nblk_stage = ss[n];
+  int rc;
+  if (!b->d_col) {
+    for (int s = 0; s < 4; ++s) {
+      if ((rc = balloc(b, (void**)&b->d_fwd[s], sizeof(RowFwdDesc) * n))) return rc;
+      if ((rc = balloc(b, (void**)&b->d_stage[s], sizeof(RowStageDesc) * n))) return rc;
+    }
+    if ((rc = balloc(b, (void**)&b->d_col, sizeof(ColDesc) * n))) return rc;
+    if ((rc = balloc(b, (void**)&b->s_fwd, sizeof(int) * (n + 1)))) return rc;
+    if ((rc = balloc(b, (void**)&b->s_col, sizeof(int) * (n + 1)))) return rc;
+    if ((rc = balloc(b, (void**)&b->s_stage, sizeof(int) * (n + 1)))) return rc;
+  }
+  for (int s = 0; s < 4; ++s) {
+    HIPCHK(hipMemcpyAsync(b->d_fwd[s], fwd[s].data(), sizeof(RowFwdDesc) * n, hipMemcpyHostToDevice, b->st));
+    HIPCHK(hipMemcpyAsync(b->d_stage[s], stg[s].data(), sizeof(RowStageDesc) * n, hipMemcpyHostToDevice, b->st));
+  }
+  HIPCHK(hipMemcpyAsync(b->d_col, col.data(), sizeof(ColDesc) * n, hipMemcpyHostToDevice, b->st));
+  HIPCHK(hipMemcpyAsync(b->s_fwd, sf.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, b->st));
+  HIPCHK(hipMemcpyAsync(b->s_col, sc.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, b->st));
+  HIPCHK(hipMemcpyAsync(b->s_stage, ss.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, b->st));
+  HIPCHK(prepare_batch_kernels<T>(b->lds_fwd, b->lds_col, b->lds_stage));
+  HIPCHK(hipStreamSynchronize(b->st));
+  if (b->exec) {
+    hipGraphExecDestroy(b->exec);
+    hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+  }
+  return MMV_OK;
+}
+
+template <typename T>
+int batch_launch_steps(mmv_batch* b, hipStream_t st, double dt, int nsteps) {
+  const int n = (int)b->inst.size();
+  mmv_mesh* h0 = b->inst[0];  // timing events of the first instance's profile slot
+  for (int k = 0; k < nsteps; ++k)
+    for (int s = 0; s < 4; ++s) {
+      mmv_mesh* h = h0;
+      PROF(1);
+      HIPCHK(launch_row_fwd_batch<T>(b->d_fwd[s], b->s_fwd, n, b->nblk_fwd, b->lds_fwd, st));
+      PROF(1);
+      PROF(2);
+      HIPCHK(launch_col_batch<T>(b->d_col, b->s_col, n, b->nblk_col, b->lds_col, st));
+      PROF(2);
+      PROF(3);
+      HIPCHK(launch_row_stage_batch<T>(b->d_stage[s], b->s_stage, n, b->nblk_stage, b->lds_stage, s, dt, st));
+      PROF(3);
+    }
+  return MMV_OK;
+}
+
+constexpr int GRAPH_STEPS = 8;
+
+template <typename T>
+int batch_step_typed(mmv_batch* b, double dt, int nsteps) {
+  for (size_t i = 0; i < b->inst.size(); ++i)
+    if (b->inst[i]->drive.mode != b->drive_sig[i]) {
+      int rc = batch_build<T>(b);
+      if (rc) return rc;
+      break;
+    }
+  const bool graph = (b->flags & MMV_BATCH_GRAPH) && b->inst[0]->prof_kernel == 0;
+  if (!graph) return batch_launch_steps<T>(b, b->st, dt, nsteps);
+  int done = 0;
+  if (nsteps >= GRAPH_STEPS) {
+    if (!b->exec || b->g_dt != dt) {
+      if (b->exec) {
+        hipGraphExecDestroy(b->exec);
+        hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+      }
+      HIPCHK(hipStreamBeginCapture(b->gst, hipStreamCaptureModeThreadLocal));
+      int rc = batch_launch_steps<T>(b, b->gst, dt, GRAPH_STEPS);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(b->gst, &g);
+      if (rc) return rc;
+      if (e != hipSuccess) return fail(MMV_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+      b->graph = g;
+      HIPCHK(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+      b->g_dt = dt;
+    }
+    HIPCHK(hipEventRecord(b->ev_in, b->st));
+    HIPCHK(hipStreamWaitEvent(b->gst, b->ev_in, 0));
+    for (; done + GRAPH_STEPS <= nsteps; done += GRAPH_STEPS) HIPCHK(hipGraphLaunch(b->exec, b->gst));
+    HIPCHK(hipEventRecord(b->ev_out, b->gst));
+    HIPCHK(hipStreamWaitEvent(b->st, b->ev_out, 0));
+  }
+  return batch_launch_steps<T>(b, b->st, dt, nsteps - done);
+}
+
+// Autotuner: per mesh size, time the batched y pass for each grouping of
+// that size's instances (others fixed) and keep the fastest.
+template <typename T>
+int batch_autotune(mmv_batch* b) {
+  std::vector<std::pair<int, int>> sizes;
+  for (mmv_mesh* h : b->inst) {
+    std::pair<int, int> k(h->Kx, h->Ly);
+    if (std::find(sizes.begin(), sizes.end(), k) == sizes.end()) sizes.push_back(k);
+  }
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int n = (int)b->inst.size();
+  for (auto& sz : sizes) {
+    int best = b->inst[0]->ngroup;
+    float best_ms = 1e30f;
+    for (int g : {1, 2, 3, 4}) {
+      for (mmv_mesh* h : b->inst)
+        if (h->Kx == sz.first && h->Ly == sz.second) h->ngroup = g;
+      int rc = batch_build<T>(b);
+      if (rc) return rc;
+      HIPCHK(launch_col_batch<T>(b->d_col, b->s_col, n, b->nblk_col, b->lds_col, b->st));
+      HIPCHK(hipEventRecord(e0, b->st));
+      for (int r = 0; r < 5; ++r) HIPCHK(launch_col_batch<T>(b->d_col, b->s_col, n, b->nblk_col, b->lds_col, b->st));
+      HIPCHK(hipEventRecord(e1, b->st));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = g;
+      }
+    }
+    for (mmv_mesh* h : b->inst)
+      if (h->Kx == sz.first && h->Ly == sz.second) h->ngroup = best;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return batch_build<T>(b);
+}
+
+bool same_kernel(const mmv_mesh_desc& a, const mmv_mesh_desc& c) {
+  return a.nx == c.nx && a.ny == c.ny && a.dx == c.dx && a.dy == c.dy && a.dz == c.dz && a.gap_cells == c.gap_cells &&
+         a.Ms == c.Ms && a.rc_cells == c.rc_cells && a.cross_mode == c.cross_mode && a.halo == c.halo &&
+         a.max_travel_cells == c.max_travel_cells && a.fft_lx == c.fft_lx && a.fft_ly == c.fft_ly;
+}
+
+void batch_free(mmv_batch* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  for (void* p : b->allocs) hipFree(p);
+  for (mmv_mesh* h : b->inst) {
+    for (hipEvent_t e : h->prof_ev) hipEventDestroy(e);
+    free_all(h);
+    delete h;
+  }
+  if (b->gst) hipStreamDestroy(b->gst);
+  if (b->ev_in) hipEventDestroy(b->ev_in);
+  if (b->ev_out) hipEventDestroy(b->ev_out);
+  delete b;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* mmv_last_error(void) { return g_err.c_str(); }
@@ -888,8 +1154,89 @@ int profile_end(mmv_handle h, double* total_ms, long* launches) {
   return MMV_OK;
 }
 
+int init_batch(const mmv_mesh_desc* descs, int n, void* hip_stream, int flags, mmv_batch_handle* out) {
+  g_err.clear();
+  if (!out) return fail(MMV_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!descs || n < 1 || n > 4096) return fail(MMV_EINVAL, "need 1..4096 descriptors");
+  for (int i = 0; i < n; ++i) {
+    int rc = validate(&descs[i]);
+    if (rc) return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
+    if (descs[i].n_films != 2 || descs[i].nz != 1) return fail(MMV_EINVAL, "batch instances need two films, nz == 1");
+    if (descs[i].precision != descs[0].precision) return fail(MMV_EINVAL, "batch instances need one precision");
+  }
+  mmv_batch* b = new mmv_batch();
+  b->st = (hipStream_t)hip_stream;
+  b->flags = flags;
+  b->esz = descs[0].precision == 64 ? 8 : 4;
+  for (int i = 0; i < n; ++i) {
+    mmv_handle h = nullptr;
+    // reuse the kernel spectra of an earlier instance of the same geometry
+    int rc = init_mesh(&descs[i], hip_stream, &h);
+    if (rc) {
+      batch_free(b);
+      return fail(rc, "instance " + std::to_string(i) + ": " + g_err);
+    }
+    h->in_batch = true;
+    for (int j = 0; j < i; ++j)
+      if (same_kernel(descs[i], descs[j])) {
+        auto it = std::find(h->allocs.begin(), h->allocs.end(), h->kern);
+        if (it != h->allocs.end()) {
+          hipFree(*it);
+          h->allocs.erase(it);
+        }
+        h->kern = b->inst[j]->kern;
+        break;
+      }
+    b->inst.push_back(h);
+  }
+  int rc = hipStreamCreateWithFlags(&b->gst, hipStreamNonBlocking) == hipSuccess ? MMV_OK
+                                                                                   : fail(MMV_EHIP, "stream create");
+  if (!rc && (hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess))
+    rc = fail(MMV_EHIP, "event create");
+  if (!rc) rc = b->esz == 8 ? batch_build<double>(b) : batch_build<float>(b);
+  if (!rc && (flags & MMV_BATCH_AUTOTUNE)) rc = b->esz == 8 ? batch_autotune<double>(b) : batch_autotune<float>(b);
+  if (rc) {
+    batch_free(b);
+    return rc;
+  }
+  *out = b;
+  return MMV_OK;
+}
+
+int batch_instance(mmv_batch_handle b, int i, mmv_handle* out) {
+  if (!b || !out) return fail(MMV_EINVAL, "NULL argument");
+  if (i < 0 || i >= (int)b->inst.size()) return fail(MMV_EINVAL, "instance out of range");
+  *out = b->inst[i];
+  return MMV_OK;
+}
+
+int batch_step(mmv_batch_handle b, double dt, int nsteps) {
+  if (!b) return fail(MMV_EINVAL, "batch is NULL");
+  if (!(dt > 0) || !isfinite(dt)) return fail(MMV_EINVAL, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(MMV_EINVAL, "nsteps must be >= 0");
+  return b->esz == 8 ? batch_step_typed<double>(b, dt, nsteps) : batch_step_typed<float>(b, dt, nsteps);
+}
+
+int batch_tuning(mmv_batch_handle b, int i, int* col_groups) {
+  if (!b || !col_groups) return fail(MMV_EINVAL, "NULL argument");
+  if (i < 0 || i >= (int)b->inst.size()) return fail(MMV_EINVAL, "instance out of range");
+  *col_groups = b->inst[i]->ngroup;
+  return MMV_OK;
+}
+
+int destroy_batch(mmv_batch_handle b) {
+  if (!b) return MMV_OK;
+  hipStreamSynchronize(b->st);
+  if (b->gst) hipStreamSynchronize(b->gst);
+  batch_free(b);
+  return MMV_OK;
+}
+
 int destroy_mesh(mmv_handle h) {
   if (!h) return MMV_OK;
+  if (h->in_batch) return fail(MMV_ESTATE, "instance handles are owned by their batch");
   hipStreamSynchronize(h->st);
   for (hipEvent_t e : h->prof_ev) hipEventDestroy(e);
   free_all(h);

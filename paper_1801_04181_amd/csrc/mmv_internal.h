@@ -91,4 +91,38 @@ struct RowParams {
   FftPlan px;
 };
 
+// Per-instance descriptors of the batched launches (device memory).
+struct RowFwdDesc {
+  const void* src;
+  void* dst;
+  int nin, N2x, Kx;
+  FftPlan P;
+  const void* tw;
+  const void* twp;
+};
+
+struct ColDesc {
+  const void* spec1;
+  void* spec2;
+  const void* kern;
+  int Kx, Ly, Kyh, ny, nin_ch, ngroup, nbuf;
+  FftPlan P;
+  const void* twy;
+  OutTable tab;
+};
+
+struct RowStageDesc {
+  RowParams p;
+  const void* spec2;
+  const void* mst;
+  const void* m0;
+  void* mnext;
+  void* acc;
+  const void* tw;
+  const void* twp;
+  RigidState* rigid;
+  double* partial;
+  unsigned* counter;
+};
+
 }  // namespace mmv

@@ -24,6 +24,18 @@ hipError_t launch_colpack(const void* spec, T* out, int Kx, int Ly, int Kyh, con
 template <typename T>
 size_t row_lds_bytes(const RowParams& p);
 
+// batched launches over many film pairs
+template <typename T>
+hipError_t launch_row_fwd_batch(const RowFwdDesc* d, const int* start, int n, int nblk, size_t lds, hipStream_t st);
+template <typename T>
+hipError_t launch_col_batch(const ColDesc* d, const int* start, int n, int nblk, size_t lds, hipStream_t st);
+template <typename T>
+hipError_t launch_row_stage_batch(const RowStageDesc* d, const int* start, int n, int nblk, size_t lds, int stage,
+                                  double dt, hipStream_t st);
+size_t row_fwd_lds_bytes(int N2x, int esz);
+template <typename T>
+hipError_t prepare_batch_kernels(size_t lds_fwd, size_t lds_col, size_t lds_stage);
+
 // single-magnet three-dimensional path
 struct CubeLaunch {
   int nx, ny, nz;

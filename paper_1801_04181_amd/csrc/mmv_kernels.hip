@@ -25,16 +25,14 @@ namespace mmv {
 
 // ------------------------------------------------------------ x transform
 template <typename T>
-__global__ void __launch_bounds__(256)
-    k_row_fwd(const T* __restrict__ src, cpx<T>* __restrict__ dst, int nrows, int nin, int N2x,
-              int Kx, FftPlan P, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp) {
+__device__ __forceinline__ void row_fwd_body(int row, const T* __restrict__ src, cpx<T>* __restrict__ dst, int nin,
+                                             int N2x, int Kx, const FftPlan& P, const cpx<T>* __restrict__ tw,
+                                             const cpx<T>* __restrict__ twp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* stp = stw + N2x;
   cpx<T>* a = stp + N2x + 1;
   cpx<T>* b = a + N2x;
-  const int row = blockIdx.x;
-  if (row >= nrows) return;
   for (int t = threadIdx.x; t < N2x; t += blockDim.x) stw[t] = tw[t];
   for (int t = threadIdx.x; t <= N2x; t += blockDim.x) stp[t] = twp[t];
   const T* s = src + (size_t)row * nin;
@@ -55,16 +53,43 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_row_fwd(const T* __restrict__ src, cpx<T>* __restrict__ dst, int nrows, int nin, int N2x,
+              int Kx, FftPlan P, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp) {
+  if ((int)blockIdx.x >= nrows) return;
+  row_fwd_body<T>(blockIdx.x, src, dst, nin, N2x, Kx, P, tw, twp);
+}
+
+// Instance of a batched launch owning block b: start[i] <= b < start[i+1].
+__device__ __forceinline__ int find_instance(const int* __restrict__ start, int n, int b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_row_fwd_batch(const RowFwdDesc* __restrict__ d, const int* __restrict__ start,
+                                                       int n) {
+  const int i = find_instance(start, n, blockIdx.x);
+  const RowFwdDesc& q = d[i];
+  row_fwd_body<T>(blockIdx.x - start[i], (const T*)q.src, (cpx<T>*)q.dst, q.nin, q.N2x, q.Kx, q.P,
+                  (const cpx<T>*)q.tw, (const cpx<T>*)q.twp);
+}
+
 // ------------------------------------------------------------ y pass
 // One block per (kx column, output group): the column's nin_ch magnetisation
 // spectra are y-transformed (recomputed by each group, an L2 hit), multiplied
 // by the kernel spectra into the group's output channels, inverse
 // y-transformed and the requested rows written.
 template <typename T>
-__global__ void __launch_bounds__(256)
-    k_col(const cpx<T>* __restrict__ spec1, cpx<T>* __restrict__ spec2, const T* __restrict__ kern,
-          int Kx, int Ly, int Kyh, int ny, int nin_ch, int ngroup, int nbuf, FftPlan P,
-          const cpx<T>* __restrict__ twy, OutTable tab) {
+__device__ __forceinline__ void col_body(int blk, const cpx<T>* __restrict__ spec1, cpx<T>* __restrict__ spec2,
+                                         const T* __restrict__ kern, int Kx, int Ly, int Kyh, int ny, int nin_ch,
+                                         int ngroup, int nbuf, const FftPlan& P, const cpx<T>* __restrict__ twy,
+                                         const OutTable& tab) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* A = stw + Ly;
@@ -74,7 +99,6 @@ __global__ void __launch_bounds__(256)
   __shared__ long long s_koff[MAX_OUT][3];
   __shared__ int s_fl[MAX_OUT][3];
   __shared__ int s_src[MAX_OUT];
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int kx = blk / ngroup;
   const int g = blk - kx * ngroup;
   if (kx >= Kx) return;
@@ -133,6 +157,25 @@ __global__ void __launch_bounds__(256)
       spec2[oc.off + (size_t)r * Kx + kx] = Y[o * Ly + yy];
     }
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_col(const cpx<T>* __restrict__ spec1, cpx<T>* __restrict__ spec2, const T* __restrict__ kern,
+          int Kx, int Ly, int Kyh, int ny, int nin_ch, int ngroup, int nbuf, FftPlan P,
+          const cpx<T>* __restrict__ twy, OutTable tab) {
+  col_body<T>(xcd_remap(blockIdx.x, gridDim.x), spec1, spec2, kern, Kx, Ly, Kyh, ny, nin_ch, ngroup, nbuf, P, twy,
+              tab);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_col_batch(const ColDesc* __restrict__ d, const int* __restrict__ start,
+                                                   int n) {
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int i = find_instance(start, n, b);
+  const ColDesc& q = d[i];
+  col_body<T>(b - start[i], (const cpx<T>*)q.spec1, (cpx<T>*)q.spec2, (const T*)q.kern, q.Kx, q.Ly, q.Kyh, q.ny,
+              q.nin_ch, q.ngroup, q.nbuf, q.P, (const cpx<T>*)q.twy, q.tab);
 }
 
 // ------------------------------------------------------------ row kernel
@@ -261,12 +304,12 @@ constexpr int MAX_ROWS = 24;
 // (MODE_FORCE).  All inverse row transforms of a task run as one batch (or
 // batches of p.nbr rows); every spline window is filtered in parallel.
 template <typename T>
-__global__ void __launch_bounds__(512)
-    k_row_stage(RowParams p, const cpx<T>* __restrict__ spec2, const T* __restrict__ mst,
-                const T* m0, T* mnext, T* __restrict__ acc,
-                T* __restrict__ hout, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp,
-                RigidState* __restrict__ rigid, double* __restrict__ partial,
-                unsigned int* __restrict__ counter) {
+__device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, double dt, int task, int ntask,
+                                               const cpx<T>* __restrict__ spec2, const T* __restrict__ mst,
+                                               const T* m0, T* mnext, T* __restrict__ acc, T* __restrict__ hout,
+                                               const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp,
+                                               RigidState* __restrict__ rigid, double* __restrict__ partial,
+                                               unsigned int* __restrict__ counter) {
   constexpr int K = FirHalf<T>::K;
   constexpr int NQ = 2 * K + 4;
   constexpr int E = K + 4;
@@ -296,7 +339,6 @@ __global__ void __launch_bounds__(512)
   __shared__ int s_last;
   __shared__ int s_bad;
 
-  const int task = blockIdx.x;
   int film, y;
   if (p.mode == MODE_STAGE) {
     if (task < p.nfilm * ny) {
@@ -507,7 +549,7 @@ __global__ void __launch_bounds__(512)
   const T pex = (T)p.pref_ex, pan = (T)p.pref_an;
   const T u0 = (T)p.u[0], u1 = (T)p.u[1], u2 = (T)p.u[2];
   const T gam = (T)p.gam, alp = (T)p.alpha;
-  const T hdt = (T)p.dt;
+  const T hdt = (T)dt;
   bool bad = false;
   if (cell_row && p.mode != MODE_FORCE) {
     for (int i = threadIdx.x; i < nx; i += blockDim.x) {
@@ -563,7 +605,7 @@ __global__ void __launch_bounds__(512)
       const T kx = -gam * (cx + alp * dx_), ky = -gam * (cy + alp * dy_), kz = -gam * (cz + alp * dz_);
       const size_t fo = (size_t)film * 3 * plane + id;
       const T ox = m0[fo], oy = m0[fo + plane], oz = m0[fo + 2 * plane];
-      if (p.stage == 0) {
+      if (stage == 0) {
         acc[fo] = kx;
         acc[fo + plane] = ky;
         acc[fo + 2 * plane] = kz;
@@ -571,11 +613,11 @@ __global__ void __launch_bounds__(512)
         mnext[fo] = ox + c * kx;
         mnext[fo + plane] = oy + c * ky;
         mnext[fo + 2 * plane] = oz + c * kz;
-      } else if (p.stage < 3) {
+      } else if (stage < 3) {
         acc[fo] += T(2) * kx;
         acc[fo + plane] += T(2) * ky;
         acc[fo + 2 * plane] += T(2) * kz;
-        const T c = (p.stage == 1) ? T(0.5) * hdt : hdt;
+        const T c = (stage == 1) ? T(0.5) * hdt : hdt;
         mnext[fo] = ox + c * kx;
         mnext[fo + plane] = oy + c * ky;
         mnext[fo + 2 * plane] = oz + c * kz;
@@ -631,13 +673,13 @@ __global__ void __launch_bounds__(512)
     if (s_bad || xp_bad) atomicOr(&rigid->flags, s_bad ? (int)FLAG_NUMERIC : (int)FLAG_RANGE);
     __threadfence();
     const unsigned prev = atomicAdd(counter, 1u);
-    s_last = (prev == gridDim.x - 1);
+    s_last = (prev == (unsigned)ntask - 1);
   }
   __syncthreads();
   if (!s_last) return;
   __threadfence();
   double sum[3] = {0.0, 0.0, 0.0};
-  for (int t = threadIdx.x; t < (int)gridDim.x; t += blockDim.x)
+  for (int t = threadIdx.x; t < ntask; t += blockDim.x)
     for (int a = 0; a < 3; ++a)
       sum[a] += __hip_atomic_load(&partial[(size_t)t * 3 + a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (int a = 0; a < 3; ++a) red[a * blockDim.x + threadIdx.x] = sum[a];
@@ -652,11 +694,31 @@ __global__ void __launch_bounds__(512)
     if (p.mode == MODE_FORCE) {
       for (int a = 0; a < 3; ++a) rigid->F[a] = p.force_scale * red[a * blockDim.x];
     } else {
-      rigid_stage(rigid, p.drive, p.stage, F0, p.dt, p.dx, p.travel);
+      rigid_stage(rigid, p.drive, stage, F0, dt, p.dx, p.travel);
     }
     __threadfence();
     atomicExch(counter, 0u);
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512)
+    k_row_stage(RowParams p, const cpx<T>* __restrict__ spec2, const T* __restrict__ mst, const T* m0, T* mnext,
+                T* __restrict__ acc, T* __restrict__ hout, const cpx<T>* __restrict__ tw,
+                const cpx<T>* __restrict__ twp, RigidState* __restrict__ rigid, double* __restrict__ partial,
+                unsigned int* __restrict__ counter) {
+  row_stage_body<T>(p, p.stage, p.dt, blockIdx.x, gridDim.x, spec2, mst, m0, mnext, acc, hout, tw, twp, rigid,
+                    partial, counter);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_row_stage_batch(const RowStageDesc* __restrict__ d,
+                                                         const int* __restrict__ start, int n, int stage, double dt) {
+  const int i = find_instance(start, n, blockIdx.x);
+  const RowStageDesc& q = d[i];
+  row_stage_body<T>(q.p, stage, dt, blockIdx.x - start[i], start[i + 1] - start[i], (const cpx<T>*)q.spec2,
+                    (const T*)q.mst, (const T*)q.m0, (T*)q.mnext, (T*)q.acc, nullptr, (const cpx<T>*)q.tw,
+                    (const cpx<T>*)q.twp, q.rigid, q.partial, q.counter);
 }
 
 // ------------------------------------------------------------ kernel init (float64)
@@ -773,6 +835,41 @@ hipError_t launch_row_stage(const RowParams& p, const void* spec2, const T* mst,
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_row_fwd_batch(const RowFwdDesc* d, const int* start, int n, int nblk, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL(k_row_fwd_batch<T>, dim3(nblk), dim3(256), lds, st, d, start, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_col_batch(const ColDesc* d, const int* start, int n, int nblk, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL(k_col_batch<T>, dim3(nblk), dim3(256), lds, st, d, start, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_row_stage_batch(const RowStageDesc* d, const int* start, int n, int nblk, size_t lds, int stage,
+                                  double dt, hipStream_t st) {
+  hipLaunchKernelGGL(k_row_stage_batch<T>, dim3(nblk), dim3(ROW_THREADS), lds, st, d, start, n, stage, dt);
+  return hipGetLastError();
+}
+
+// Dynamic-LDS limits of the batched kernels, set outside any graph capture.
+template <typename T>
+hipError_t prepare_batch_kernels(size_t lds_fwd, size_t lds_col, size_t lds_stage) {
+  hipError_t e = hipSuccess;
+  if (lds_fwd > 65536)
+    e = hipFuncSetAttribute((const void*)k_row_fwd_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_fwd);
+  if (e == hipSuccess && lds_col > 65536)
+    e = hipFuncSetAttribute((const void*)k_col_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_col);
+  if (e == hipSuccess && lds_stage > 65536)
+    e = hipFuncSetAttribute((const void*)k_row_stage_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds_stage);
+  return e;
+}
+
+size_t row_fwd_lds_bytes(int N2x, int esz) { return (size_t)2 * esz * (4 * (size_t)N2x + 1); }
+
 hipError_t launch_kernel_real(double* out, int Lx, int Ly, int kind, int comp, double dzc, double dx, double dy,
                               double dz, double rc, double scale, hipStream_t st) {
   dim3 grid((Lx + 127) / 128, Ly);
@@ -800,7 +897,12 @@ hipError_t launch_colpack(const void* spec, T* out, int Kx, int Ly, int Kyh, con
   template hipError_t launch_colpack<T>(const void*, T*, int, int, int, const FftPlan&, const void*, int,      \
                                         hipStream_t);                                                          \
   template size_t row_lds_bytes<T>(const RowParams&);                                                           \
-  template size_t col_lds_bytes<T>(int, int);
+  template size_t col_lds_bytes<T>(int, int);                                                                    \
+  template hipError_t prepare_batch_kernels<T>(size_t, size_t, size_t);                                         \
+  template hipError_t launch_row_fwd_batch<T>(const RowFwdDesc*, const int*, int, int, size_t, hipStream_t);      \
+  template hipError_t launch_col_batch<T>(const ColDesc*, const int*, int, int, size_t, hipStream_t);             \
+  template hipError_t launch_row_stage_batch<T>(const RowStageDesc*, const int*, int, int, size_t, int, double,   \
+                                                hipStream_t);
 
 MMV_INST(float)
 MMV_INST(double)
