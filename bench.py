@@ -78,6 +78,46 @@ def cpu_baseline(cfg, m, budget_s=12.0):
                       f"NumPy/SciPy oracle, 1 thread, {dt:.1f} s"}
 
 
+def batched_vs_plain(steps_batch=200, steps_plain=50):
+    """64 uneven pairs: per-instance launches vs one batched, graph-replayed launch per pass."""
+    import torch
+    import paper_1801_04181_amd as mmv
+    from workloads import initial_state
+    from workloads.configs import batch_pairs
+    pairs = batch_pairs(64)
+    descs = [p["desc"] for p in pairs]
+    drives = [p["drive"] for p in pairs]
+    ms = [initial_state(p) for p in pairs]
+    dt = pairs[0]["dt"]
+    cells = sum(d.cells for d in descs)
+    meshes = [mmv.Mesh(d, drv, m) for d, drv, m in zip(descs, drives, ms)]
+    for me in meshes:
+        me.step(dt, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for me in meshes:
+        me.step(dt, steps_plain)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    for me in meshes:
+        me.close()
+    B = mmv.Batch(descs, drives, ms, flags=mmv.BATCH_AUTOTUNE | mmv.BATCH_GRAPH)
+    B.step(dt, 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.step(dt, steps_batch)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    groups = sorted(set(B.tuning(i) for i in range(len(descs))))
+    B.close()
+    plain = cells * steps_plain / t_plain
+    batched = cells * steps_batch / t_batch
+    return {"workload": "64 uneven pairs nx {64,128,256,512} x ny {64,128}, 2 nm, f32, spring drives",
+            "cells": cells, "plain_cell_updates_per_s": plain,
+            "batched_cell_updates_per_s": batched, "speedup": batched / plain,
+            "ms_per_step_batched": t_batch / steps_batch * 1e3, "autotuned_groups": groups}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +125,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--config", default="stickslip")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU sharding "
@@ -165,6 +206,8 @@ def main():
         "wall_s": wall,
         "slider_x_nm": st["x"] * 1e9,
     }
+    if not args.no_batch:
+        out["batched"] = batched_vs_plain()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, m)
     print(json.dumps(out), flush=True)

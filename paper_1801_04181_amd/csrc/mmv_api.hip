@@ -680,7 +680,7 @@ template <typename T>
 int run_fields(mmv_mesh* h, const void* m_in, const OutTable& tab) {
   PROF(1);
   HIPCHK(launch_row_fwd<T>((const T*)m_in, h->spec1, 3 * h->nfilm * h->ny, h->nx, h->N2x, h->Kx, h->px, h->twx,
-                           h->twp, h->st));
+                           h->twp, h->st, h->ny));
   PROF(1);
   PROF(2);
   HIPCHK(launch_col<T>(h->spec1, h->spec2, (const T*)h->kern, h->Kx, h->Ly, h->Kyh, h->ny, 3 * h->nfilm, h->ngroup,
@@ -845,6 +845,7 @@ int batch_build(mmv_batch* b) {
       f.nin = h->nx;
       f.N2x = h->N2x;
       f.Kx = h->Kx;
+      f.ny = h->ny;
       f.P = h->px;
       f.tw = h->twx;
       f.twp = h->twp;
@@ -878,7 +879,7 @@ int batch_build(mmv_batch* b) {
     c.P = h->py;
     c.twy = h->twy;
     c.tab = h->tab_hot;
-    sf[i + 1] = sf[i] + 3 * h->nfilm * h->ny;
+    sf[i + 1] = sf[i] + h->nfilm * h->ny;
     sc[i + 1] = sc[i] + h->Kx * h->ngroup;
     ss[i + 1] = ss[i] + rp.ntask;
     b->lds_fwd = std::max(b->lds_fwd, row_fwd_lds_bytes(h->N2x, sizeof(T)));

@@ -141,37 +141,48 @@ __device__ __forceinline__ int fdiv(int n, float inv_d) { return (int)(((float)n
 // One radix-R Stockham pass over `batch` transforms of length L at stride
 // `stride`: reads src[j + r*nb], twiddles by exp(-+2 pi i r k / (Ns R)),
 // DFT_R, writes dst[(j - k) R + k + r Ns] with k = j mod Ns.
-// tw[t] = exp(-2 pi i t / L).
+// tw[t] = exp(-2 pi i t / L).  Threads are spread over (butterfly j,
+// transform group g); a thread reuses its index arithmetic and twiddles for
+// every transform t = g, g + G, ... of its group.
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void stockham_pass(const cpx<T>* __restrict__ a, cpx<T>* __restrict__ b, int L,
                                               int Ns, int batch, int stride,
                                               const cpx<T>* __restrict__ tw) {
   const int nb = L / R;
   const int tws = L / (Ns * R);
+  int G = (int)blockDim.x / nb;
+  if (G < 1) G = 1;
+  if (G > batch) G = batch;
   const float inb = 1.0f / (float)nb;
   const float ins = 1.0f / (float)Ns;
-  const int total = nb * batch;
+  const int total = nb * G;
   for (int w = threadIdx.x; w < total; w += blockDim.x) {
-    const int t = fdiv(w, inb);
-    const int j = w - t * nb;
+    const int g = fdiv(w, inb);
+    const int j = w - g * nb;
     const int q = fdiv(j, ins);
     const int k = j - q * Ns;
-    const cpx<T>* s = a + t * stride + j;
-    cpx<T>* d = b + t * stride + q * Ns * R + k;
-    cpx<T> v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = s[r * nb];
+    cpx<T> wv[R];
     if (k) {
       const int kt = k * tws;
 #pragma unroll
-      for (int r = 1; r < R; ++r) {
-        cpx<T> wv = tw[r * kt];
-        v[r] = INV ? cmulc(v[r], wv) : cmul(v[r], wv);
-      }
+      for (int r = 1; r < R; ++r) wv[r] = tw[r * kt];
     }
-    dft<T, R, INV>(v);
+    const int din = j;
+    const int dout = q * Ns * R + k;
+    for (int t = g; t < batch; t += G) {
+      const cpx<T>* s = a + t * stride + din;
+      cpx<T>* d = b + t * stride + dout;
+      cpx<T> v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) d[r * Ns] = v[r];
+      for (int r = 0; r < R; ++r) v[r] = s[r * nb];
+      if (k) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], wv[r]) : cmul(v[r], wv[r]);
+      }
+      dft<T, R, INV>(v);
+#pragma unroll
+      for (int r = 0; r < R; ++r) d[r * Ns] = v[r];
+    }
   }
 }
 

@@ -95,7 +95,7 @@ struct RowParams {
 struct RowFwdDesc {
   const void* src;
   void* dst;
-  int nin, N2x, Kx;
+  int nin, N2x, Kx, ny;
   FftPlan P;
   const void* tw;
   const void* twp;

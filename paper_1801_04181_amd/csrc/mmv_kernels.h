@@ -8,7 +8,7 @@ namespace mmv {
 
 template <typename T>
 hipError_t launch_row_fwd(const T* src, void* dst, int nrows, int nin, int N2x, int Kx, const FftPlan& P,
-                          const void* tw, const void* twp, hipStream_t st);
+                          const void* tw, const void* twp, hipStream_t st, int ny3 = 0);
 template <typename T>
 hipError_t launch_col(const void* spec1, void* spec2, const T* kern, int Kx, int Ly, int Kyh, int ny, int nin_ch,
                       int ngroup, const FftPlan& P, const void* twy, const OutTable& tab, hipStream_t st);

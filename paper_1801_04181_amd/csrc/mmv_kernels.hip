@@ -24,41 +24,58 @@
 namespace mmv {
 
 // ------------------------------------------------------------ x transform
+// Rows handled by one block of the x pass: `nb` rows at `row0`, `rstride`
+// rows apart (the three components of one film row, or one row).
 template <typename T>
-__device__ __forceinline__ void row_fwd_body(int row, const T* __restrict__ src, cpx<T>* __restrict__ dst, int nin,
-                                             int N2x, int Kx, const FftPlan& P, const cpx<T>* __restrict__ tw,
-                                             const cpx<T>* __restrict__ twp) {
+__device__ __forceinline__ void row_fwd_body(int row0, int nb, int rstride, const T* __restrict__ src,
+                                             cpx<T>* __restrict__ dst, int nin, int N2x, int Kx, const FftPlan& P,
+                                             const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* stp = stw + N2x;
   cpx<T>* a = stp + N2x + 1;
-  cpx<T>* b = a + N2x;
+  cpx<T>* b = a + (size_t)nb * N2x;
   for (int t = threadIdx.x; t < N2x; t += blockDim.x) stw[t] = tw[t];
   for (int t = threadIdx.x; t <= N2x; t += blockDim.x) stp[t] = twp[t];
-  const T* s = src + (size_t)row * nin;
-  for (int n = threadIdx.x; n < N2x; n += blockDim.x) {
+  const float inv = 1.0f / (float)N2x;
+  for (int t = threadIdx.x; t < nb * N2x; t += blockDim.x) {
+    const int r = fdiv(t, inv);
+    const int n = t - r * N2x;
+    const T* s = src + (size_t)(row0 + r * rstride) * nin;
     const int i0 = 2 * n, i1 = 2 * n + 1;
-    a[n] = mk<T>(i0 < nin ? s[i0] : T(0), i1 < nin ? s[i1] : T(0));
+    a[t] = mk<T>(i0 < nin ? s[i0] : T(0), i1 < nin ? s[i1] : T(0));
   }
   __syncthreads();
-  cpx<T>* Z = fft_lds<T, false>(a, b, P, 1, N2x, stw);
-  cpx<T>* out = dst + (size_t)row * Kx;
-  for (int k = threadIdx.x; k <= N2x; k += blockDim.x) {
-    cpx<T> zk = Z[k == N2x ? 0 : k];
-    cpx<T> zm = Z[k == 0 ? 0 : N2x - k];
+  cpx<T>* Z = fft_lds<T, false>(a, b, P, nb, N2x, stw);
+  const int K1 = N2x + 1;
+  const float ink = 1.0f / (float)K1;
+  for (int t = threadIdx.x; t < nb * K1; t += blockDim.x) {
+    const int r = fdiv(t, ink);
+    const int k = t - r * K1;
+    const cpx<T>* z = Z + (size_t)r * N2x;
+    cpx<T> zk = z[k == N2x ? 0 : k];
+    cpx<T> zm = z[k == 0 ? 0 : N2x - k];
     zm.y = -zm.y;
     cpx<T> e = zk + zm;
     cpx<T> p = cmul(stp[k], zk - zm);
-    out[k] = mk<T>(T(0.5) * (e.x + p.y), T(0.5) * (e.y - p.x));
+    dst[(size_t)(row0 + r * rstride) * Kx + k] = mk<T>(T(0.5) * (e.x + p.y), T(0.5) * (e.y - p.x));
   }
 }
 
+// Block b transforms rows b of a (rows / 3) x 3 arrangement when `three`
+// (the x, y, z components of one film row, ny rows apart), else row b.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_row_fwd(const T* __restrict__ src, cpx<T>* __restrict__ dst, int nrows, int nin, int N2x,
-              int Kx, FftPlan P, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp) {
-  if ((int)blockIdx.x >= nrows) return;
-  row_fwd_body<T>(blockIdx.x, src, dst, nin, N2x, Kx, P, tw, twp);
+              int Kx, FftPlan P, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp, int ny3) {
+  if (ny3 > 0) {
+    // rows are [film][comp][y]; block = (film, y)
+    const int f = blockIdx.x / ny3, y = blockIdx.x - f * ny3;
+    row_fwd_body<T>(f * 3 * ny3 + y, 3, ny3, src, dst, nin, N2x, Kx, P, tw, twp);
+  } else {
+    if ((int)blockIdx.x >= nrows) return;
+    row_fwd_body<T>(blockIdx.x, 1, 0, src, dst, nin, N2x, Kx, P, tw, twp);
+  }
 }
 
 // Instance of a batched launch owning block b: start[i] <= b < start[i+1].
@@ -76,7 +93,9 @@ __global__ void __launch_bounds__(256) k_row_fwd_batch(const RowFwdDesc* __restr
                                                        int n) {
   const int i = find_instance(start, n, blockIdx.x);
   const RowFwdDesc& q = d[i];
-  row_fwd_body<T>(blockIdx.x - start[i], (const T*)q.src, (cpx<T>*)q.dst, q.nin, q.N2x, q.Kx, q.P,
+  const int b = blockIdx.x - start[i];
+  const int f = b / q.ny, y = b - f * q.ny;
+  row_fwd_body<T>(f * 3 * q.ny + y, 3, q.ny, (const T*)q.src, (cpx<T>*)q.dst, q.nin, q.N2x, q.Kx, q.P,
                   (const cpx<T>*)q.tw, (const cpx<T>*)q.twp);
 }
 
@@ -773,14 +792,16 @@ __global__ void __launch_bounds__(256)
 // ------------------------------------------------------------ launchers
 template <typename T>
 hipError_t launch_row_fwd(const T* src, void* dst, int nrows, int nin, int N2x, int Kx, const FftPlan& P,
-                          const void* tw, const void* twp, hipStream_t st) {
-  const size_t lds = sizeof(cpx<T>) * (4 * (size_t)N2x + 1);
+                          const void* tw, const void* twp, hipStream_t st, int ny3) {
+  const int nb = ny3 > 0 ? 3 : 1;
+  const size_t lds = sizeof(cpx<T>) * (2 * (size_t)N2x + 1 + 2 * (size_t)nb * N2x);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_row_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_row_fwd<T>, dim3(nrows), dim3(256), lds, st, src, (cpx<T>*)dst, nrows, nin, N2x, Kx,
-                     P, (const cpx<T>*)tw, (const cpx<T>*)twp);
+  const int nblk = ny3 > 0 ? nrows / 3 : nrows;
+  hipLaunchKernelGGL(k_row_fwd<T>, dim3(nblk), dim3(256), lds, st, src, (cpx<T>*)dst, nrows, nin, N2x, Kx,
+                     P, (const cpx<T>*)tw, (const cpx<T>*)twp, ny3);
   return hipGetLastError();
 }
 
@@ -868,7 +889,7 @@ hipError_t prepare_batch_kernels(size_t lds_fwd, size_t lds_col, size_t lds_stag
   return e;
 }
 
-size_t row_fwd_lds_bytes(int N2x, int esz) { return (size_t)2 * esz * (4 * (size_t)N2x + 1); }
+size_t row_fwd_lds_bytes(int N2x, int esz) { return (size_t)2 * esz * (8 * (size_t)N2x + 1); }
 
 hipError_t launch_kernel_real(double* out, int Lx, int Ly, int kind, int comp, double dzc, double dx, double dy,
                               double dz, double rc, double scale, hipStream_t st) {
@@ -888,7 +909,7 @@ hipError_t launch_colpack(const void* spec, T* out, int Kx, int Ly, int Kyh, con
 
 #define MMV_INST(T)                                                                                             \
   template hipError_t launch_row_fwd<T>(const T*, void*, int, int, int, int, const FftPlan&, const void*,      \
-                                        const void*, hipStream_t);                                             \
+                                        const void*, hipStream_t, int);                                             \
   template hipError_t launch_col<T>(const void*, void*, const T*, int, int, int, int, int, int, const FftPlan&, \
                                     const void*, const OutTable&, hipStream_t);                                \
   template hipError_t launch_row_stage<T>(const RowParams&, const void*, const T*, const T*, T*, T*, T*,       \
