@@ -6,7 +6,8 @@ kernel with the spline, local terms, LLG stage and force) plus the slider's
 equation of motion.  Workload: the stick-slip films, 2 x 512 x 128 cells of
 2 nm, float32, spring drive, seeded synthetic +/-z domain states.
 
-Prints one JSON line (see README of the contract in the design doc).
+Prints one JSON line: metric, value, unit, timing, roofline of the dominant
+kernel and the float64 CPU reference's rate on a bounded sample.
 """
 import argparse
 import json
@@ -198,8 +199,8 @@ def main():
         print(json.dumps({"precision_report": precision_report()}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU sharding "
-              "is described in DESIGN.md and not implemented", file=sys.stderr)
+        print("bench.py: runs on one GPU only; sharding the films over several "
+              "GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -176,6 +176,69 @@ int destroy_batch(mmv_batch_handle b);
 /* Release every device buffer of the handle.  NULL is accepted.         */
 int destroy_mesh(mmv_handle h);
 
+/* ------------------------------------------------------------------------
+ * Learned stray-field operator (a Fourier neural operator standing in for
+ * the cross term of Eqs. (6)-(8) sampled at the slider offset, Sec. III.A).
+ *
+ * Input  a [B][4][H][W] float32 (device): m_x, m_y, m_z of the slider film
+ *        and, as the fourth channel, its offset in cells (x_p) at every
+ *        pixel.  Output [B][3][H][W] float32 (device): the stray field on the
+ *        base film, in the units the training targets carry.
+ * Network: pointwise lift 4 -> width; `layers` blocks
+ *        v <- GELU( IDFT2[ R(k) DFT2[v](k) ] + Wp v + bp ) keeping the modes
+ *        kx in [0, modes_x), ky in [0, modes_y/2) U [H - modes_y/2, H) with a
+ *        complex width x width matrix R(k) per mode; pointwise projection
+ *        width -> 3.  Products run on the BF16 matrix cores with float32
+ *        accumulation; parameters, gradients and Adam state are float32.
+ * Parameter vector (float32, sur_param_count entries): wl [width][4],
+ *        bl [width], then per layer R [modes_x*modes_y][2][width][width]
+ *        (real, imaginary planes; mode index ky_slot*modes_x + kx with
+ *        ky_slot < modes_y/2 for ky = ky_slot and H - modes_y + ky_slot
+ *        otherwise), Wp [width][width], bp [width]; then wq [3][width],
+ *        bq [3].  sur_param_offsets returns those start offsets in order.
+ * The DFT convention is numpy's: forward exp(-i 2 pi k x / W) unnormalised,
+ * inverse normalised by 1/(H W), with the real part kept after doubling the
+ * kx > 0 modes (Hermitian completion of the half spectrum).
+ * All pointers are device pointers; calls are ordered on the handle's stream.
+ * Errors: MMV_EINVAL for bad sizes or NULL pointers, MMV_ENOMEM, MMV_EHIP. */
+typedef struct {
+  int H, W;        /* grid of the base film (rows, columns)              */
+  int width;       /* channels C (1..256)                                 */
+  int modes_x;     /* kept kx modes (1..W/2)                              */
+  int modes_y;     /* kept ky modes, even, split over both ends (<= H)   */
+  int layers;      /* spectral blocks (1..16)                             */
+  int max_batch;   /* largest B any call may pass (1..256)                */
+  int reserved[9];
+} mmv_sur_desc;
+typedef struct mmv_sur* mmv_sur_handle;
+
+/* Allocate parameters (zeroed), Adam state and activations for max_batch. */
+int sur_create(const mmv_sur_desc* d, void* hip_stream, mmv_sur_handle* out);
+long long sur_param_count(mmv_sur_handle h);
+/* Start offsets of wl, bl, (R, Wp, bp) per layer, wq, bq: n >= 4 + 3 layers. */
+int sur_param_offsets(mmv_sur_handle h, long long* offs, int n);
+/* Copy the parameter vector in (resets Adam's moments and step) or out.  */
+int sur_set_params(mmv_sur_handle h, const float* w_dev);
+int sur_get_params(mmv_sur_handle h, float* w_dev);
+/* out = network(a) for B samples.                                         */
+int sur_forward(mmv_sur_handle h, const float* a_dev, int B, float* out_dev);
+/* Gradient of the mean over all B*3*H*W outputs of (out - target)^2 with
+ * respect to the parameter vector (written to grad_dev if not NULL);
+ * *loss receives that mean (blocks until it is known).                    */
+int sur_gradient(mmv_sur_handle h, const float* a_dev, const float* target_dev, int B, float* grad_dev,
+                 double* loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on that
+ * loss; *loss and *rel_err (||out - target|| / ||target||) are of the
+ * parameters before the step.                                             */
+int sur_train_step(mmv_sur_handle h, const float* a_dev, const float* target_dev, int B, float lr, double* loss,
+                   double* rel_err);
+/* The matrix-core product on its own: C = alpha A B + beta C with
+ * A(m,k) = A[m*am + k*ak], B(k,n) = B[k*bk + n*bn], C(m,n) = C[m*cm + n*cn]
+ * (float32 in memory, BF16 operands, float32 accumulation).              */
+int sur_gemm_bf16(const float* A, long long am, long long ak, const float* B, long long bk, long long bn, float* C,
+                  long long cm, long long cn, int M, int N, int K, float alpha, float beta, void* hip_stream);
+int sur_destroy(mmv_sur_handle h);
+
 /* Thread-local message for the most recent failing call ("" if none).   */
 const char* mmv_last_error(void);
 

@@ -19,12 +19,15 @@ framework") step by step:
   sim.py               two-film system: cross fields, force Eq. (3),
                        RK4 with the slider equation of motion Eq. (15),
                        diagnostics incl. P_diss Eq. (4)
+  fno.py               learned stray-field operator (Fourier neural
+                       operator standing in for the cross term), float64
+                       torch with autograd gradients
 
 Parity status of each function is stated in its docstring; functions with
 no independent pin say "parity unpinned".
 """
 from .constants import MU0, GAMMA_E, GAMMA0
-from . import newell, potential_kernel, convolution, spline, fields, llg, sim
+from . import newell, potential_kernel, convolution, spline, fields, llg, sim, fno
 
 __all__ = ["MU0", "GAMMA_E", "GAMMA0", "newell", "potential_kernel",
-           "convolution", "spline", "fields", "llg", "sim"]
+           "convolution", "spline", "fields", "llg", "sim", "fno"]

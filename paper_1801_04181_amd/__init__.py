@@ -13,7 +13,9 @@ __all__ = ["MMVError", "lib_path", "load", "MeshDesc", "DriveDesc", "init_mesh",
            "set_m", "get_m", "set_offset", "set_drive", "eval_heff", "llg_step",
            "stray_force", "get_state", "get_fft_lengths", "destroy_mesh",
            "profile_begin", "profile_end", "init_batch", "batch_instance", "batch_step",
-           "batch_tuning", "destroy_batch", "Batch",
+           "batch_tuning", "destroy_batch", "Batch", "SurDesc", "sur_create", "sur_param_count",
+           "sur_param_offsets", "sur_set_params", "sur_get_params", "sur_forward", "sur_gradient",
+           "sur_train_step", "sur_gemm_bf16", "sur_destroy", "Surrogate",
            "last_error", "Mesh", "TERM", "EXPORTS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -26,7 +28,9 @@ ERRORS = {-1: "MMV_EINVAL", -2: "MMV_ENOMEM", -3: "MMV_EHIP", -4: "MMV_ERANGE",
 EXPORTS = ("init_mesh", "set_m", "get_m", "set_offset", "set_drive", "eval_heff",
            "llg_step", "stray_force", "get_state", "profile_begin", "profile_end",
            "get_fft_lengths", "init_batch", "batch_instance", "batch_step", "batch_tuning",
-           "destroy_batch", "destroy_mesh", "mmv_last_error")
+           "destroy_batch", "destroy_mesh", "sur_create", "sur_param_count", "sur_param_offsets",
+           "sur_set_params", "sur_get_params", "sur_forward", "sur_gradient", "sur_train_step",
+           "sur_gemm_bf16", "sur_destroy", "mmv_last_error")
 BATCH_AUTOTUNE, BATCH_GRAPH = 1, 2
 
 
@@ -55,6 +59,12 @@ class DriveDesc(ctypes.Structure):
                 ("mass", ctypes.c_double), ("gamma_v", ctypes.c_double),
                 ("x_anchor0", ctypes.c_double), ("x0", ctypes.c_double),
                 ("v0", ctypes.c_double)]
+
+
+class SurDesc(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int), ("W", ctypes.c_int), ("width", ctypes.c_int),
+                ("modes_x", ctypes.c_int), ("modes_y", ctypes.c_int), ("layers", ctypes.c_int),
+                ("max_batch", ctypes.c_int), ("reserved", ctypes.c_int * 9)]
 
 
 _LIB = None
@@ -88,9 +98,21 @@ def load():
         lib.batch_tuning.argtypes = [vp, i, ctypes.POINTER(i)]
         lib.destroy_batch.argtypes = [vp]
         lib.profile_end.argtypes = [vp, pd, ctypes.POINTER(ctypes.c_long)]
+        ll, f = ctypes.c_longlong, ctypes.c_float
+        lib.sur_create.argtypes = [ctypes.POINTER(SurDesc), vp, ctypes.POINTER(vp)]
+        lib.sur_param_count.argtypes = [vp]
+        lib.sur_param_offsets.argtypes = [vp, ctypes.POINTER(ll), i]
+        lib.sur_set_params.argtypes = [vp, vp]
+        lib.sur_get_params.argtypes = [vp, vp]
+        lib.sur_forward.argtypes = [vp, vp, i, vp]
+        lib.sur_gradient.argtypes = [vp, vp, vp, i, vp, pd]
+        lib.sur_train_step.argtypes = [vp, vp, vp, i, f, pd, pd]
+        lib.sur_gemm_bf16.argtypes = [vp, ll, ll, vp, ll, ll, vp, ll, ll, i, i, i, f, f, vp]
+        lib.sur_destroy.argtypes = [vp]
         lib.mmv_last_error.restype = ctypes.c_char_p
         for name in EXPORTS[:-1]:
             getattr(lib, name).restype = ctypes.c_int
+        lib.sur_param_count.restype = ll
         _LIB = lib
     return _LIB
 
@@ -334,6 +356,110 @@ class Mesh:
     def close(self):
         if self.h is not None:
             destroy_mesh(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sur_create(H, W, width=32, modes_x=16, modes_y=32, layers=4, max_batch=8, stream=None):
+    d = SurDesc(H, W, width, modes_x, modes_y, layers, max_batch)
+    h = ctypes.c_void_p()
+    _check(load().sur_create(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def sur_param_count(h):
+    return int(load().sur_param_count(h))
+
+
+def sur_param_offsets(h, layers):
+    n = 4 + 3 * layers
+    arr = (ctypes.c_longlong * n)()
+    _check(load().sur_param_offsets(h, arr, n))
+    return list(arr)
+
+
+def sur_set_params(h, w):
+    _check(load().sur_set_params(h, _ptr(w)))
+
+
+def sur_get_params(h, out):
+    _check(load().sur_get_params(h, _ptr(out)))
+
+
+def sur_forward(h, a, B, out):
+    _check(load().sur_forward(h, _ptr(a), B, _ptr(out)))
+
+
+def sur_gradient(h, a, target, B, grad=None):
+    loss = ctypes.c_double()
+    g = _ptr(grad) if grad is not None else None
+    _check(load().sur_gradient(h, _ptr(a), _ptr(target), B, g, ctypes.byref(loss)))
+    return loss.value
+
+
+def sur_train_step(h, a, target, B, lr):
+    loss, rel = ctypes.c_double(), ctypes.c_double()
+    _check(load().sur_train_step(h, _ptr(a), _ptr(target), B, ctypes.c_float(lr),
+                                 ctypes.byref(loss), ctypes.byref(rel)))
+    return loss.value, rel.value
+
+
+def sur_gemm_bf16(A, am, ak, B, bk, bn, C, cm, cn, M, N, K, alpha=1.0, beta=0.0, stream=None):
+    _check(load().sur_gemm_bf16(_ptr(A), am, ak, _ptr(B), bk, bn, _ptr(C), cm, cn, M, N, K,
+                                ctypes.c_float(alpha), ctypes.c_float(beta), _stream(stream)))
+
+
+def sur_destroy(h):
+    _check(load().sur_destroy(h))
+
+
+class Surrogate:
+    """Learned stray-field operator; torch tensors supply device memory."""
+
+    def __init__(self, H, W, width=32, modes_x=16, modes_y=32, layers=4, max_batch=8,
+                 stream=None, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.H, self.W, self.layers = H, W, layers
+        self.h = sur_create(H, W, width, modes_x, modes_y, layers, max_batch, self.stream)
+        self.n = sur_param_count(self.h)
+        self.offsets = sur_param_offsets(self.h, layers)
+
+    def set_params(self, w):
+        w = self.torch.as_tensor(w, dtype=self.torch.float32).to(self.device).contiguous()
+        assert w.numel() == self.n
+        sur_set_params(self.h, w)
+        self.torch.cuda.current_stream(self.device).synchronize()
+
+    def get_params(self):
+        out = self.torch.empty(self.n, dtype=self.torch.float32, device=self.device)
+        sur_get_params(self.h, out)
+        return out
+
+    def forward(self, a):
+        B = a.shape[0]
+        out = self.torch.empty((B, 3, self.H, self.W), dtype=self.torch.float32, device=self.device)
+        sur_forward(self.h, a.contiguous(), B, out)
+        return out
+
+    def gradient(self, a, target):
+        g = self.torch.empty(self.n, dtype=self.torch.float32, device=self.device)
+        loss = sur_gradient(self.h, a.contiguous(), target.contiguous(), a.shape[0], g)
+        return loss, g
+
+    def train_step(self, a, target, lr):
+        return sur_train_step(self.h, a.contiguous(), target.contiguous(), a.shape[0], lr)
+
+    def close(self):
+        if self.h is not None:
+            sur_destroy(self.h)
             self.h = None
 
     def __del__(self):

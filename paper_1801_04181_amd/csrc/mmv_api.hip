@@ -80,6 +80,10 @@ struct LayerSet {
 
 }  // namespace
 
+namespace mmv {
+int report_error(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace mmv
+
 struct mmv_mesh {
   mmv_mesh_desc d;
   hipStream_t st = nullptr;

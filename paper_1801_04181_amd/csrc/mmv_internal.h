@@ -1,6 +1,7 @@
 // Structures shared by the host runtime and the kernels (plain data).
 #pragma once
 #include <stdint.h>
+#include <string>
 
 namespace mmv {
 
@@ -124,5 +125,9 @@ struct RowStageDesc {
   double* partial;
   unsigned* counter;
 };
+
+// Records msg as the thread's last error (returned by mmv_last_error) and
+// returns code.
+int report_error(int code, const std::string& msg);
 
 }  // namespace mmv

@@ -5,7 +5,7 @@ import numpy as np
 TERMS = (("exchange", 1), ("anisotropy", 2), ("zeeman", 4), ("demag_self", 8),
          ("demag_cross", 16))
 
-# Relative L2 bars.  float32: the spec bar.  float64: FFT rounding of the
+# Relative L2 bars.  float32: 1e-5, the bar set for the float32 path.  float64: FFT rounding of the
 # float64 path is ~1e-15; the bar is set by the Newell kernel near the switch
 # radius, where the independent float64 evaluations (device libm vs host
 # libm) differ by ~1e-7 of entries that carry ~1e-4 of the field.

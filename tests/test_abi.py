@@ -13,10 +13,10 @@ HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 
 def header_functions():
     txt = open(HDR).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|long long|const char\*)\s+(\w+)\s*\(", txt, flags=re.M)))
 
 
-def test_header_lists_north_star_calls():
+def test_header_lists_the_path_calls():
     fns = header_functions()
     for name in ("init_mesh", "set_offset", "eval_heff", "llg_step", "stray_force"):
         assert name in fns
@@ -33,6 +33,7 @@ def test_struct_layout_matches_header():
     # offsets the C compiler assigns (x86-64 SysV): checked against ctypes
     assert ctypes.sizeof(mmv.MeshDesc) == 192
     assert ctypes.sizeof(mmv.DriveDesc) == 64
+    assert ctypes.sizeof(mmv.SurDesc) == 64
 
 
 @pytest.mark.parametrize("field,value,msg", [
@@ -77,3 +78,14 @@ def test_eddy_needs_a_thick_single_magnet():
     d = get_config("cube_eddy")["desc"].replace(sor_omega=2.5)
     with pytest.raises(mmv.MMVError):
         mmv.init_mesh(mmv.to_desc(d))
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(H=4), "H, W"), (dict(width=0), "width"), (dict(modes_x=200), "modes_x"),
+    (dict(modes_y=3), "modes_y"), (dict(layers=0), "layers"), (dict(max_batch=0), "max_batch")])
+def test_surrogate_rejects_bad_shapes(kw, msg):
+    args = dict(H=64, W=64, width=8, modes_x=8, modes_y=8, layers=2, max_batch=2)
+    args.update(kw)
+    with pytest.raises(mmv.MMVError) as e:
+        mmv.sur_create(**args)
+    assert e.value.code == -1 and msg in str(e.value)
