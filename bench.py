@@ -185,6 +185,87 @@ def precision_report(steps_cube=6, steps_film=50):
     return out
 
 
+def surrogate_report(train_steps=3000, B=8, steps=200, log=None):
+    """Learned stray-field operator on the 2 x 256 x 256 films: train on fresh
+    exact pairs, held-out error, then LLG steps with the operator attached
+    (judge every 10 steps) against plain exact steps and the batched exact path."""
+    import numpy as np
+    import torch
+    import paper_1801_04181_amd as mmv
+    from paper_1801_04181_amd.surrogate import PairSource, train, held_out_error
+    from workloads import get_config, initial_state
+    from workloads.states import domain_state
+    from workloads.fno_inputs import init_params
+    log = log or (lambda msg: print(msg, file=sys.stderr, flush=True))
+    cfg = get_config("learned")
+    d, drv, dt = cfg["desc"], cfg["drive"], cfg["dt"]
+    C, Mx, My, L = 32, 16, 32, 4
+    pool = [domain_state((1, d.ny, d.nx), 1000 + k)[:, 0] for k in range(64)]
+    src = PairSource(d, pool, seed=1)
+    sur = mmv.Surrogate(d.ny, d.nx, C, Mx, My, L, max_batch=B)
+    sur.set_params(torch.from_numpy(init_params(C, Mx, My, L, seed=2)).float())
+    t0 = time.perf_counter()
+    hist = train(sur, src, train_steps, B=B, log=log)
+    t_train = time.perf_counter() - t0
+    held = held_out_error(sur, PairSource(d, pool, seed=99), n=64, B=B)
+    log(f"held-out relative error {held:.4f}")
+    a = src.batch(B)[0]
+    times = {}
+    for nb in (1, B):
+        for _ in range(3):
+            sur.forward(a[:nb])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            sur.forward(a[:nb])
+        torch.cuda.synchronize()
+        times[nb] = (time.perf_counter() - t0) / 20 * 1e3
+    m = initial_state(cfg)
+
+    def run(attach=None):
+        me = mmv.Mesh(d, drv, m)
+        if attach is not None:
+            mmv.sur_attach(me.h, sur.h, 10, attach)
+        me.step(dt, 10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        me.step(dt, steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = mmv.sur_status(me.h) if attach is not None else None
+        me.close()
+        return d.cells * steps / el, el / steps * 1e3, st
+
+    plain, ms_plain, _ = run()
+    sur_rate, ms_sur, st_free = run(1e30)          # judge runs, never falls back
+    strict_rate, ms_strict, st_strict = run(1e-3)
+    descs = [d] * B
+    bt = mmv.Batch(descs, [drv] * B, [m] * B, flags=mmv.BATCH_AUTOTUNE | mmv.BATCH_GRAPH)
+    bt.step(dt, 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.step(dt, steps)
+    torch.cuda.synchronize()
+    batched = d.cells * B * steps / (time.perf_counter() - t0)
+    bt.close()
+    sur.close()
+    return {
+        "workload": f"2x{d.nx}x{d.ny} films, f32, spring drive; operator width {C}, "
+                    f"{Mx}x{My} modes, {L} layers, BF16 matrix cores",
+        "train_steps": train_steps, "train_batch": B, "train_s": t_train,
+        "train_rel_err_last100": float(np.mean(hist[-100:])),
+        "held_out_rel_err": held,
+        "forward_ms": {str(k): v for k, v in times.items()},
+        "plain_cell_updates_per_s": plain, "plain_ms_per_step": ms_plain,
+        "surrogate_cell_updates_per_s": sur_rate, "surrogate_ms_per_step": ms_sur,
+        "surrogate_judged_rel_err": st_free[0],
+        "strict_tol_1e-3": {"fell_back": st_strict[1], "judged": st_strict[2],
+                            "rel_err": st_strict[0], "cell_updates_per_s": strict_rate},
+        "batched_exact_8_pairs_cell_updates_per_s": batched,
+        "meets_1e-3": bool(held <= 1e-3),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,10 +274,14 @@ def main():
     ap.add_argument("--config", default="stickslip")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--report", choices=["precision"], default=None)
+    ap.add_argument("--report", choices=["precision", "surrogate"], default=None)
+    ap.add_argument("--train-steps", type=int, default=3000)
     args = ap.parse_args()
     if args.report == "precision":
         print(json.dumps({"precision_report": precision_report()}), flush=True)
+        return
+    if args.report == "surrogate":
+        print(json.dumps({"surrogate_report": surrogate_report(args.train_steps)}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: runs on one GPU only; sharding the films over several "

@@ -239,6 +239,23 @@ int sur_gemm_bf16(const float* A, long long am, long long ak, const float* B, lo
                   long long cm, long long cn, int M, int N, int K, float alpha, float beta, void* hip_stream);
 int sur_destroy(mmv_sur_handle h);
 
+/* Use the operator for film 0's cross field inside llg_step: at every RK
+ * stage the network reads the stage's slider magnetisation and offset
+ * x_s / dx and its output, times Ms, replaces the interpolated stray field
+ * of film 1 on film 0 (the film-0 cross channels are then not computed).
+ * Every judge_every steps, before the step, the exact cross field is
+ * computed as well and compared (relative L2 over the film); above tol the
+ * mesh falls back to the exact path for good (until attached again).  The
+ * network must have been created with H = ny, W = nx and be trained on
+ * targets in units of Ms.  Needs two films, nz = 1, precision 32 and
+ * cross_mode 0, on a mesh that is not part of a batch (MMV_ESTATE
+ * otherwise).  The operator is not owned; s = NULL detaches.  Each judge
+ * blocks the host until its error is known.                            */
+int sur_attach(mmv_handle h, mmv_sur_handle s, int judge_every, double tol);
+/* Error at the last judge (-1 before the first), whether the mesh has
+ * fallen back to the exact path, and how many judges ran.               */
+int sur_status(mmv_handle h, double* last_rel_err, int* fallback, long* judged);
+
 /* Thread-local message for the most recent failing call ("" if none).   */
 const char* mmv_last_error(void);
 

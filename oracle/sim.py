@@ -72,6 +72,9 @@ class System:
         self.step_count = 0
         self._ops = {}
         self.eddy = None
+        # optional replacement of the base film's cross field: a callable
+        # (m_slider, x_s) -> H [A/m] (used to compose with the learned operator)
+        self.base_cross = None
         if desc.sigma > 0:
             from .eddy import EddyState
             self.eddy = EddyState(desc)
@@ -205,6 +208,8 @@ class System:
                                           want_force)
             out[0]["demag_cross"] = Hb
             out[1]["demag_cross"] = Hs
+            if self.base_cross is not None:
+                out[0]["demag_cross"] = self.base_cross(m_list[1], x)
         if self.eddy is not None:
             out[0]["eddy"] = self.eddy.H_eddy.copy()
         return out, F

@@ -15,7 +15,7 @@ __all__ = ["MMVError", "lib_path", "load", "MeshDesc", "DriveDesc", "init_mesh",
            "profile_begin", "profile_end", "init_batch", "batch_instance", "batch_step",
            "batch_tuning", "destroy_batch", "Batch", "SurDesc", "sur_create", "sur_param_count",
            "sur_param_offsets", "sur_set_params", "sur_get_params", "sur_forward", "sur_gradient",
-           "sur_train_step", "sur_gemm_bf16", "sur_destroy", "Surrogate",
+           "sur_train_step", "sur_gemm_bf16", "sur_destroy", "sur_attach", "sur_status", "Surrogate",
            "last_error", "Mesh", "TERM", "EXPORTS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -30,7 +30,7 @@ EXPORTS = ("init_mesh", "set_m", "get_m", "set_offset", "set_drive", "eval_heff"
            "get_fft_lengths", "init_batch", "batch_instance", "batch_step", "batch_tuning",
            "destroy_batch", "destroy_mesh", "sur_create", "sur_param_count", "sur_param_offsets",
            "sur_set_params", "sur_get_params", "sur_forward", "sur_gradient", "sur_train_step",
-           "sur_gemm_bf16", "sur_destroy", "mmv_last_error")
+           "sur_gemm_bf16", "sur_destroy", "sur_attach", "sur_status", "mmv_last_error")
 BATCH_AUTOTUNE, BATCH_GRAPH = 1, 2
 
 
@@ -109,6 +109,8 @@ def load():
         lib.sur_train_step.argtypes = [vp, vp, vp, i, f, pd, pd]
         lib.sur_gemm_bf16.argtypes = [vp, ll, ll, vp, ll, ll, vp, ll, ll, i, i, i, f, f, vp]
         lib.sur_destroy.argtypes = [vp]
+        lib.sur_attach.argtypes = [vp, vp, i, d]
+        lib.sur_status.argtypes = [vp, pd, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_long)]
         lib.mmv_last_error.restype = ctypes.c_char_p
         for name in EXPORTS[:-1]:
             getattr(lib, name).restype = ctypes.c_int
@@ -416,6 +418,16 @@ def sur_gemm_bf16(A, am, ak, B, bk, bn, C, cm, cn, M, N, K, alpha=1.0, beta=0.0,
 
 def sur_destroy(h):
     _check(load().sur_destroy(h))
+
+
+def sur_attach(h, s, judge_every=10, tol=1e-3):
+    _check(load().sur_attach(h, s, judge_every, tol))
+
+
+def sur_status(h):
+    e, f, n = ctypes.c_double(), ctypes.c_int(), ctypes.c_long()
+    _check(load().sur_status(h, ctypes.byref(e), ctypes.byref(f), ctypes.byref(n)))
+    return e.value, bool(f.value), n.value
 
 
 class Surrogate:

@@ -122,6 +122,16 @@ struct mmv_mesh {
   CubeLaunch cl{};
   bool eddy_first = true;
   bool in_batch = false;  // owned by a batch: destroy_mesh refuses it
+  // learned operator for film 0's cross field (not owned)
+  mmv_sur* sur = nullptr;
+  int sur_every = 10;
+  double sur_tol = 1e-3;
+  int sur_fallback = 0;
+  double sur_err = -1.0;
+  long sur_judged = 0, sur_steps = 0;
+  float* sur_in = nullptr;
+  float* sur_exact = nullptr;
+  OutTable tab_sur{};
   int sor_sweeps = 40;
   double sor_omega = 1.0;
   // launch timing (diagnostics)
@@ -694,6 +704,27 @@ int run_fields(mmv_mesh* h, const void* m_in, const OutTable& tab) {
 }
 
 template <typename T>
+int eval_typed(mmv_mesh* h, int film, int mask, void* hout);
+
+// Error judge of the learned operator: exact cross field on film 0 against
+// the network's, at the state at the start of the step.
+template <typename T>
+int sur_judge(mmv_mesh* h) {
+  int rc = eval_typed<T>(h, 0, MMV_TERM_DEMAG_CROSS, h->sur_exact);
+  if (rc) return rc;
+  const size_t plane = (size_t)h->ny * h->nx;
+  HIPCHK(launch_sur_input((const float*)h->m0 + 3 * plane, h->rigid, 1.0 / h->d.dx, h->ny, h->nx, h->sur_in, h->st));
+  const float* pred = nullptr;
+  if ((rc = sur_infer(h->sur, h->sur_in, 1, h->st, &pred))) return rc;
+  double e = 0.0;
+  if ((rc = sur_rel_err(h->sur, pred, h->sur_exact, (long long)3 * plane, h->d.Ms, h->st, &e))) return rc;
+  h->sur_err = e;
+  h->sur_judged += 1;
+  if (!(e <= h->sur_tol)) h->sur_fallback = 1;
+  return MMV_OK;
+}
+
+template <typename T>
 int step_typed(mmv_mesh* h, double dt, int nsteps) {
   RowParams rp = h->rp_hot;
   rp.mode = MODE_STAGE;
@@ -706,11 +737,30 @@ int step_typed(mmv_mesh* h, double dt, int nsteps) {
   T* m0 = (T*)h->m0;
   T* b1 = (T*)h->mb[0];
   T* b2 = (T*)h->mb[1];
+  const size_t plane = (size_t)h->ny * h->nx;
   for (int n = 0; n < nsteps; ++n) {
+    if (h->sur && !h->sur_fallback && h->sur_steps % h->sur_every == 0) {
+      int rc = sur_judge<T>(h);
+      if (rc) return rc;
+    }
+    const bool use_sur = h->sur && !h->sur_fallback;
     for (int s = 0; s < 4; ++s) {
       T* in = s == 0 ? m0 : (s == 1 ? b1 : (s == 2 ? b2 : b1));
       T* out = s == 0 ? b1 : (s == 1 ? b2 : (s == 2 ? b1 : m0));
-      int rc = run_fields<T>(h, in, h->tab_hot);
+      int rc;
+      if (use_sur) {
+        // film 0's cross field from the network at this stage's slider state
+        HIPCHK(launch_sur_input((const float*)in + 3 * plane, h->rigid, 1.0 / h->d.dx, h->ny, h->nx, h->sur_in,
+                                h->st));
+        const float* pred = nullptr;
+        if ((rc = sur_infer(h->sur, h->sur_in, 1, h->st, &pred))) return rc;
+        rp.hsur = pred;
+        rp.sur_scale = h->d.Ms;
+        rc = run_fields<T>(h, in, h->tab_sur);
+      } else {
+        rp.hsur = nullptr;
+        rc = run_fields<T>(h, in, h->tab_hot);
+      }
       if (rc) return rc;
       rp.stage = s;
       PROF(3);
@@ -718,6 +768,7 @@ int step_typed(mmv_mesh* h, double dt, int nsteps) {
                                  h->partial, h->counter, h->st));
       PROF(3);
     }
+    if (h->sur) h->sur_steps += 1;
   }
   return MMV_OK;
 }
@@ -1329,6 +1380,49 @@ int llg_step(mmv_handle h, double dt, int nsteps) {
   if (nsteps < 0) return fail(MMV_EINVAL, "nsteps must be >= 0");
   if (h->cube) return h->esz == 8 ? step_cube<double>(h, dt, nsteps) : step_cube<float>(h, dt, nsteps);
   return h->esz == 8 ? step_typed<double>(h, dt, nsteps) : step_typed<float>(h, dt, nsteps);
+}
+
+int sur_attach(mmv_handle h, mmv_sur_handle s, int judge_every, double tol) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!s) {
+    h->sur = nullptr;
+    return MMV_OK;
+  }
+  if (h->cube || h->nfilm != 2 || h->nz != 1) return fail(MMV_ESTATE, "the learned operator needs two films, nz = 1");
+  if (h->in_batch) return fail(MMV_ESTATE, "batch instances cannot use the learned operator");
+  if (h->esz != 4) return fail(MMV_ESTATE, "the learned operator runs with precision 32");
+  if (h->d.cross_mode != 0) return fail(MMV_ESTATE, "the learned operator replaces the direct cross term (cross_mode 0)");
+  int H = 0, W = 0;
+  sur_shape(s, &H, &W);
+  if (H != h->ny || W != h->nx) return fail(MMV_EINVAL, "operator grid differs from the film grid");
+  if (judge_every < 1) return fail(MMV_EINVAL, "judge_every must be >= 1");
+  if (!(tol > 0) || !isfinite(tol)) return fail(MMV_EINVAL, "tol must be finite and > 0");
+  // the film-0 cross channels are the last three of the stage table
+  const OutTable& t = h->tab_hot;
+  if (t.n < 3 || t.ch[t.n - 3].off != h->rp_hot.off_cross[0][0]) return fail(MMV_ESTATE, "unexpected channel table");
+  const size_t plane = (size_t)h->ny * h->nx;
+  if (!h->sur_in && (rc = dalloc(h, (void**)&h->sur_in, sizeof(float) * 4 * plane))) return rc;
+  if (!h->sur_exact && (rc = dalloc(h, (void**)&h->sur_exact, sizeof(float) * 3 * plane))) return rc;
+  h->tab_sur = t;
+  h->tab_sur.n = t.n - 3;
+  h->sur = s;
+  h->sur_every = judge_every;
+  h->sur_tol = tol;
+  h->sur_fallback = 0;
+  h->sur_err = -1.0;
+  h->sur_judged = 0;
+  h->sur_steps = 0;
+  return MMV_OK;
+}
+
+int sur_status(mmv_handle h, double* last_rel_err, int* fallback, long* judged) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (last_rel_err) *last_rel_err = h->sur_err;
+  if (fallback) *fallback = h->sur_fallback;
+  if (judged) *judged = h->sur_judged;
+  return MMV_OK;
 }
 
 int stray_force(mmv_handle h, double F_out[3]) {

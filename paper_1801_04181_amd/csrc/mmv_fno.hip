@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <string>
+#include <algorithm>
 #include <vector>
 #include "mmv.h"
 #include "mmv_internal.h"
@@ -283,7 +284,64 @@ void host_bases(mmv_sur* h, std::vector<float>& Dx, std::vector<float>& Cy, std:
   }
 }
 
+__global__ void k_sur_input(const float* __restrict__ m, const RigidState* __restrict__ rigid, double inv_dx,
+                            long long plane, float* __restrict__ a) {
+  const float xp = (float)(rigid->xs * inv_dx);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < plane;
+       i += (long long)gridDim.x * blockDim.x) {
+    a[i] = m[i];
+    a[plane + i] = m[plane + i];
+    a[2 * plane + i] = m[2 * plane + i];
+    a[3 * plane + i] = xp;
+  }
+}
+
 }  // namespace
+
+namespace mmv {
+
+int sur_infer(mmv_sur* s, const float* a, int B, hipStream_t st, const float** out) {
+  if (B < 1 || B > s->Bmax) return sfail(MMV_EINVAL, "batch out of range");
+  hipStream_t keep = s->st;
+  s->st = st;
+  const int rc = forward(s, a, B);
+  s->st = keep;
+  *out = s->pred;
+  return rc;
+}
+
+void sur_shape(const mmv_sur* s, int* H, int* W) {
+  *H = s->H;
+  *W = s->W;
+}
+
+hipError_t launch_sur_input(const float* m_slider, const RigidState* rigid, double inv_dx, int ny, int nx, float* a,
+                            hipStream_t st) {
+  const long long plane = (long long)ny * nx;
+  const unsigned nb = (unsigned)std::min<long long>((plane + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_sur_input, dim3(nb), dim3(256), 0, st, m_slider, rigid, inv_dx, plane, a);
+  return hipGetLastError();
+}
+
+int sur_rel_err(mmv_sur* s, const float* pred, float* exact, long long n, double scale, hipStream_t st, double* rel) {
+  // compare in the network's units: exact / scale against pred
+  SCHK(launch_axpy(n, (float)(1.0 / scale), exact, nullptr, exact, st));
+  const int nb = mse_blocks(n);
+  if (2LL * nb > 2LL * mse_blocks((long long)s->Bmax * 3 * s->HW)) return sfail(MMV_EINVAL, "judge size");
+  SCHK(launch_mse(n, pred, exact, nullptr, s->mse_part, st));
+  std::vector<double> part(2 * (size_t)nb);
+  SCHK(hipMemcpyAsync(part.data(), s->mse_part, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost, st));
+  SCHK(hipStreamSynchronize(st));
+  double e = 0, q = 0;
+  for (int i = 0; i < nb; ++i) {
+    e += part[2 * i];
+    q += part[2 * i + 1];
+  }
+  *rel = q > 0 ? sqrt(e / q) : (e > 0 ? INFINITY : 0.0);
+  return MMV_OK;
+}
+
+}  // namespace mmv
 
 extern "C" {
 

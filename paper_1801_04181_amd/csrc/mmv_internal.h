@@ -1,7 +1,10 @@
 // Structures shared by the host runtime and the kernels (plain data).
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string>
+
+struct mmv_sur;
 
 namespace mmv {
 
@@ -90,6 +93,10 @@ struct RowParams {
   int phi_row0[2][7];
   DriveP drive;
   FftPlan px;
+  // learned operator: when set, film 0's cross field is read from this
+  // float32 [3][ny][nx] array (times sur_scale) instead of the spline rows
+  const float* hsur;
+  double sur_scale;
 };
 
 // Per-instance descriptors of the batched launches (device memory).
@@ -129,5 +136,17 @@ struct RowStageDesc {
 // Records msg as the thread's last error (returned by mmv_last_error) and
 // returns code.
 int report_error(int code, const std::string& msg);
+
+// Learned stray-field operator, as used inside the LLG step (mmv_fno.hip).
+// sur_infer runs the network on B samples on stream st; *out points at the
+// handle's own output buffer [B][3][H][W] (valid until its next call).
+int sur_infer(mmv_sur* s, const float* a, int B, hipStream_t st, const float** out);
+void sur_shape(const mmv_sur* s, int* H, int* W);
+// a[4][ny][nx] = (m_x, m_y, m_z of the slider, x_s / dx of the current stage)
+hipError_t launch_sur_input(const float* m_slider, const RigidState* rigid, double inv_dx, int ny, int nx, float* a,
+                            hipStream_t st);
+// relative L2 distance between scale * pred and exact (both n floats);
+// exact is overwritten; blocks on st
+int sur_rel_err(mmv_sur* s, const float* pred, float* exact, long long n, double scale, hipStream_t st, double* rel);
 
 }  // namespace mmv

@@ -378,7 +378,8 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   const bool two = (p.nfilm == 2);
   const bool need_force =
       two && film == 1 && ((p.mode == MODE_STAGE && p.with_force) || p.mode == MODE_FORCE);
-  const bool need_cross = two && ((p.term_mask & 16) || need_force);
+  const bool ext_cross = two && film == 0 && p.hsur != nullptr;
+  const bool need_cross = two && !ext_cross && ((p.term_mask & 16) || need_force);
   const int h = p.halo;
 
   for (int t = threadIdx.x; t < N2x; t += blockDim.x) stw[t] = tw[t];
@@ -562,6 +563,14 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
 
   // --- per cell: local terms, LLG stage, force partials
   const size_t plane = (size_t)ny * nx;
+  if (ext_cross && cell_row && (p.term_mask & 16)) {
+    const T sc = (T)p.sur_scale;
+    for (int t = threadIdx.x; t < 3 * nx; t += blockDim.x) {
+      const int c = t / nx, i = t - c * nx;
+      H[t] += sc * (T)p.hsur[(size_t)c * plane + (size_t)y * nx + i];
+    }
+    __syncthreads();
+  }
   double fpart[3] = {0.0, 0.0, 0.0};
   const T* ms = mst + (size_t)film * 3 * plane;
   const T idx2 = T(1.0 / (p.dx * p.dx)), idy2 = T(1.0 / (p.dy * p.dy));

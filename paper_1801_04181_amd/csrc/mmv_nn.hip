@@ -175,8 +175,8 @@ __global__ void k_adam(long long n, float* __restrict__ w, const float* __restri
 }
 
 // out = x + y (element-wise), or out = a x when y is null
-__global__ void k_axpy(long long n, float a, const float* __restrict__ x, const float* __restrict__ y,
-                       float* __restrict__ out) {
+// (out may alias x: each element is read before it is written by the same thread)
+__global__ void k_axpy(long long n, float a, const float* x, const float* y, float* out) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     out[i] = a * x[i] + (y ? y[i] : 0.0f);
 }
