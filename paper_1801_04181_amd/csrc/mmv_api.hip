@@ -122,6 +122,7 @@ struct mmv_mesh {
   CubeLaunch cl{};
   bool eddy_first = true;
   bool in_batch = false;  // owned by a batch: destroy_mesh refuses it
+  bool fuse_fwd = false;  // the row kernel x-transforms its new rows (nbr >= 3)
   // learned operator for film 0's cross field (not owned)
   mmv_sur* sur = nullptr;
   int sur_every = 10;
@@ -460,7 +461,7 @@ int init_typed(mmv_mesh* h) {
   const size_t lds_limit = 160 * 1024;
   // inverse row transforms per batch of the row kernel: as many as fit
   int nbr = 0;
-  for (int b : {8, 6, 4, 3, 2, 1}) {
+  for (int b : {9, 8, 6, 4, 3, 2, 1}) {
     RowParams probe = h->rp_force;
     probe.full_force = 1;
     probe.nbr = b;
@@ -472,18 +473,45 @@ int init_typed(mmv_mesh* h) {
   }
   if (!nbr) return fail(MMV_EINVAL, "nx too large for the row kernel's LDS");
   h->rp_hot.nbr = h->rp_force.nbr = nbr;
+  h->fuse_fwd = nbr >= 3;
   if (sizeof(T) * 2 * (4 * (size_t)h->N2x + 1) > lds_limit) return fail(MMV_EINVAL, "nx too large");
-  // output groups per column of the y pass: enough blocks to fill the chip
-  // (each group recomputes the column's forward transforms, an L2 hit)
-  h->ngroup = (1536 + h->Kx - 1) / h->Kx;
-  if (h->ngroup < 1) h->ngroup = 1;
-  if (h->ngroup > 4) h->ngroup = 4;
+  // output groups per column of the y pass.  Each group recomputes the
+  // column's forward transforms (an L2 hit); more groups give shorter blocks,
+  // and the launch should fit in one round of resident blocks.  Estimated
+  // cost: rounds x (fixed load/store overhead of ~4 transforms + forward and
+  // inverse transforms per block).
+  const int nin = 3 * h->nfilm;
+  const int nmax = h->tab_force.n > h->tab_hot.n ? h->tab_force.n : h->tab_hot.n;
+  if ((long long)h->nkc * h->Kx * h->Kyh >= (1LL << 31)) return fail(MMV_EINVAL, "kernel spectra too large");
+  int ncu = 0, dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  h->ngroup = 0;
+  double best = 0.0;
+  for (int g = 1; g <= 4; ++g) {
+    // LDS of the stage launches (the force table only has to fit)
+    const int pf = (nmax + g - 1) / g;
+    if (col_lds_bytes<T>(h->Ly, nin > pf ? nin : pf) > lds_limit) continue;
+    const int pg = (h->tab_hot.n + g - 1) / g;
+    const size_t lds = col_lds_bytes<T>(h->Ly, nin > pg ? nin : pg);
+    const int occ = col_blocks_per_cu<T>(lds);
+    if (occ < 1) continue;
+    const long long slots = (long long)ncu * occ;
+    const long long rounds = ((long long)h->Kx * g + slots - 1) / slots;
+    const double cost = (double)rounds * (4.0 + nin + (h->tab_hot.n + g - 1) / g);
+    if (getenv("MMV_VERBOSE"))
+      fprintf(stderr, "mmv: y pass groups %d: lds %zu, blocks/CU %d, CUs %d, rounds %lld, cost %.0f\n", g, lds, occ,
+              ncu, rounds, cost);
+    if (!h->ngroup || cost < best) {
+      h->ngroup = g;
+      best = cost;
+    }
+  }
+  if (!h->ngroup) h->ngroup = 1;
   if (const char* e = getenv("MMV_COL_GROUPS")) {
     const int v = atoi(e);
     if (v >= 1 && v <= 8) h->ngroup = v;
   }
-  const int nin = 3 * h->nfilm;
-  const int nmax = h->tab_force.n > h->tab_hot.n ? h->tab_force.n : h->tab_hot.n;
   const int per = (nmax + h->ngroup - 1) / h->ngroup;
   if (col_lds_bytes<T>(h->Ly, nin > per ? nin : per) > lds_limit)
     return fail(MMV_EINVAL, "ny too large for the y pass");
@@ -691,11 +719,13 @@ int check_handle(mmv_handle h) {
 }
 
 template <typename T>
-int run_fields(mmv_mesh* h, const void* m_in, const OutTable& tab) {
-  PROF(1);
-  HIPCHK(launch_row_fwd<T>((const T*)m_in, h->spec1, 3 * h->nfilm * h->ny, h->nx, h->N2x, h->Kx, h->px, h->twx,
-                           h->twp, h->st, h->ny));
-  PROF(1);
+int run_fields(mmv_mesh* h, const void* m_in, const OutTable& tab, bool fwd = true) {
+  if (fwd) {
+    PROF(1);
+    HIPCHK(launch_row_fwd<T>((const T*)m_in, h->spec1, 3 * h->nfilm * h->ny, h->nx, h->N2x, h->Kx, h->px, h->twx,
+                             h->twp, h->st, h->ny));
+    PROF(1);
+  }
   PROF(2);
   HIPCHK(launch_col<T>(h->spec1, h->spec2, (const T*)h->kern, h->Kx, h->Ly, h->Kyh, h->ny, 3 * h->nfilm, h->ngroup,
                        h->py, h->twy, tab, h->st));
@@ -733,7 +763,9 @@ int step_typed(mmv_mesh* h, double dt, int nsteps) {
   rp.drive = h->drive;
   rp.with_force = (h->nfilm == 2 && h->drive.mode == MMV_DRIVE_SPRING) ? 1 : 0;
   rp.full_force = 0;
-  rp.ntask = h->nfilm * h->ny + (rp.with_force ? 2 : 0);
+  rp.ntask = h->nfilm * h->ny + ((rp.with_force && rp.pot) ? 2 : 0);
+  // after the first stage the x-pass input comes from the row kernel
+  rp.spec1_out = h->fuse_fwd ? h->spec1 : nullptr;
   T* m0 = (T*)h->m0;
   T* b1 = (T*)h->mb[0];
   T* b2 = (T*)h->mb[1];
@@ -748,6 +780,7 @@ int step_typed(mmv_mesh* h, double dt, int nsteps) {
       T* in = s == 0 ? m0 : (s == 1 ? b1 : (s == 2 ? b2 : b1));
       T* out = s == 0 ? b1 : (s == 1 ? b2 : (s == 2 ? b1 : m0));
       int rc;
+      const bool fwd = !h->fuse_fwd || (n == 0 && s == 0);
       if (use_sur) {
         // film 0's cross field from the network at this stage's slider state
         HIPCHK(launch_sur_input((const float*)in + 3 * plane, h->rigid, 1.0 / h->d.dx, h->ny, h->nx, h->sur_in,
@@ -756,10 +789,10 @@ int step_typed(mmv_mesh* h, double dt, int nsteps) {
         if ((rc = sur_infer(h->sur, h->sur_in, 1, h->st, &pred))) return rc;
         rp.hsur = pred;
         rp.sur_scale = h->d.Ms;
-        rc = run_fields<T>(h, in, h->tab_sur);
+        rc = run_fields<T>(h, in, h->tab_sur, fwd);
       } else {
         rp.hsur = nullptr;
-        rc = run_fields<T>(h, in, h->tab_hot);
+        rc = run_fields<T>(h, in, h->tab_hot, fwd);
       }
       if (rc) return rc;
       rp.stage = s;
@@ -844,6 +877,7 @@ struct mmv_batch {
   RowFwdDesc* d_fwd[4] = {};
   ColDesc* d_col = nullptr;
   RowStageDesc* d_stage[4] = {};
+  bool fuse = false;  // every instance x-transforms its new rows in the row kernel
   int *s_fwd = nullptr, *s_col = nullptr, *s_stage = nullptr;
   int nblk_fwd = 0, nblk_col = 0, nblk_stage = 0;
   size_t lds_fwd = 0, lds_col = 0, lds_stage = 0;
@@ -863,14 +897,15 @@ int balloc(mmv_batch* b, void** p, size_t bytes) {
   return MMV_OK;
 }
 
-RowParams stage_params(mmv_mesh* h) {
+RowParams stage_params(mmv_mesh* h, bool fuse) {
   RowParams rp = h->rp_hot;
+  rp.spec1_out = fuse ? h->spec1 : nullptr;
   rp.mode = MODE_STAGE;
   rp.term_mask = MMV_TERM_ALL;
   rp.drive = h->drive;
   rp.with_force = (h->drive.mode == MMV_DRIVE_SPRING) ? 1 : 0;
   rp.full_force = 0;
-  rp.ntask = h->nfilm * h->ny + (rp.with_force ? 2 : 0);
+  rp.ntask = h->nfilm * h->ny + ((rp.with_force && rp.pot) ? 2 : 0);
   return rp;
 }
 
@@ -884,13 +919,15 @@ int batch_build(mmv_batch* b) {
   std::vector<int> sf(n + 1, 0), sc(n + 1, 0), ss(n + 1, 0);
   b->lds_fwd = b->lds_col = b->lds_stage = 0;
   b->drive_sig.assign(n, 0);
+  b->fuse = true;
+  for (int i = 0; i < n; ++i) b->fuse = b->fuse && b->inst[i]->fuse_fwd;
   for (int i = 0; i < n; ++i) {
     mmv_mesh* h = b->inst[i];
     b->drive_sig[i] = h->drive.mode;
     T* m0 = (T*)h->m0;
     T* b1 = (T*)h->mb[0];
     T* b2 = (T*)h->mb[1];
-    const RowParams rp = stage_params(h);
+    const RowParams rp = stage_params(h, b->fuse);
     for (int s = 0; s < 4; ++s) {
       T* in = s == 0 ? m0 : (s == 1 ? b1 : (s == 2 ? b2 : b1));
       T* out = s == 0 ? b1 : (s == 1 ? b2 : (s == 2 ? b1 : m0));
@@ -981,9 +1018,11 @@ int batch_launch_steps(mmv_batch* b, hipStream_t st, double dt, int nsteps) {
   for (int k = 0; k < nsteps; ++k)
     for (int s = 0; s < 4; ++s) {
       mmv_mesh* h = h0;
-      PROF(1);
-      HIPCHK(launch_row_fwd_batch<T>(b->d_fwd[s], b->s_fwd, n, b->nblk_fwd, b->lds_fwd, st));
-      PROF(1);
+      if (!b->fuse || (k == 0 && s == 0)) {
+        PROF(1);
+        HIPCHK(launch_row_fwd_batch<T>(b->d_fwd[s], b->s_fwd, n, b->nblk_fwd, b->lds_fwd, st));
+        PROF(1);
+      }
       PROF(2);
       HIPCHK(launch_col_batch<T>(b->d_col, b->s_col, n, b->nblk_col, b->lds_col, st));
       PROF(2);

@@ -143,11 +143,12 @@ __device__ __forceinline__ int fdiv(int n, float inv_d) { return (int)(((float)n
 // DFT_R, writes dst[(j - k) R + k + r Ns] with k = j mod Ns.
 // tw[t] = exp(-2 pi i t / L).  Threads are spread over (butterfly j,
 // transform group g); a thread reuses its index arithmetic and twiddles for
-// every transform t = g, g + G, ... of its group.
+// every transform t = g, g + G, ... of its group.  twh > 0: only tw[0..twh)
+// is stored (L = 2 twh) and tw[t + twh] = -tw[t].
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void stockham_pass(const cpx<T>* __restrict__ a, cpx<T>* __restrict__ b, int L,
                                               int Ns, int batch, int stride,
-                                              const cpx<T>* __restrict__ tw) {
+                                              const cpx<T>* __restrict__ tw, int twh) {
   const int nb = L / R;
   const int tws = L / (Ns * R);
   int G = (int)blockDim.x / nb;
@@ -165,7 +166,15 @@ __device__ __forceinline__ void stockham_pass(const cpx<T>* __restrict__ a, cpx<
     if (k) {
       const int kt = k * tws;
 #pragma unroll
-      for (int r = 1; r < R; ++r) wv[r] = tw[r * kt];
+      for (int r = 1; r < R; ++r) {
+        const int id = r * kt;
+        if (twh == 0 || id < twh) {
+          wv[r] = tw[id];
+        } else {
+          const cpx<T> w = tw[id - twh];
+          wv[r] = mk(-w.x, -w.y);
+        }
+      }
     }
     const int din = j;
     const int dout = q * Ns * R + k;
@@ -193,17 +202,17 @@ __device__ __forceinline__ void stockham_pass(const cpx<T>* __restrict__ a, cpx<
 // a __syncthreads().
 template <typename T, bool INV>
 __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, const FftPlan& P, int batch, int stride,
-                           const cpx<T>* __restrict__ tw) {
+                           const cpx<T>* __restrict__ tw, int twh = 0) {
   const int L = P.L;
   int Ns = 1;
   for (int p = 0; p < P.np; ++p) {
     const int R = P.r[p];
     switch (R) {
-      case 2: stockham_pass<T, 2, INV>(a, b, L, Ns, batch, stride, tw); break;
-      case 3: stockham_pass<T, 3, INV>(a, b, L, Ns, batch, stride, tw); break;
-      case 4: stockham_pass<T, 4, INV>(a, b, L, Ns, batch, stride, tw); break;
-      case 5: stockham_pass<T, 5, INV>(a, b, L, Ns, batch, stride, tw); break;
-      default: stockham_pass<T, 7, INV>(a, b, L, Ns, batch, stride, tw); break;
+      case 2: stockham_pass<T, 2, INV>(a, b, L, Ns, batch, stride, tw, twh); break;
+      case 3: stockham_pass<T, 3, INV>(a, b, L, Ns, batch, stride, tw, twh); break;
+      case 4: stockham_pass<T, 4, INV>(a, b, L, Ns, batch, stride, tw, twh); break;
+      case 5: stockham_pass<T, 5, INV>(a, b, L, Ns, batch, stride, tw, twh); break;
+      default: stockham_pass<T, 7, INV>(a, b, L, Ns, batch, stride, tw, twh); break;
     }
     __syncthreads();
     cpx<T>* tmp = a;

@@ -97,6 +97,10 @@ struct RowParams {
   // float32 [3][ny][nx] array (times sur_scale) instead of the spline rows
   const float* hsur;
   double sur_scale;
+  // MODE_STAGE: when set, each cell-row task also x-transforms the three
+  // components of its new magnetisation row into this spectrum array (the
+  // x-pass input of the next stage), [film][comp][y][Kx]
+  void* spec1_out;
 };
 
 // Per-instance descriptors of the batched launches (device memory).

@@ -71,5 +71,7 @@ template <typename T>
 hipError_t launch_pack3(const void* spec, T* out, int Kx, int Ly, int Lz, int imag, hipStream_t st);
 template <typename T>
 size_t col_lds_bytes(int Ly, int nbuf);
+template <typename T>
+int col_blocks_per_cu(size_t lds);
 
 }  // namespace mmv

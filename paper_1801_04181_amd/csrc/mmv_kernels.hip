@@ -17,6 +17,8 @@
 //                one-time float64 construction of the kernel spectra.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include "mmv_device.h"
 #include "mmv_kernels.h"
 #include "mmv_kernel_fn.h"
@@ -110,14 +112,16 @@ __device__ __forceinline__ void col_body(int blk, const cpx<T>* __restrict__ spe
                                          int ngroup, int nbuf, const FftPlan& P, const cpx<T>* __restrict__ twy,
                                          const OutTable& tab) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  // twiddles: half table for even Ly (tw[t + Ly/2] = -tw[t])
+  const int Lh = (Ly & 1) ? Ly : Ly / 2;
   cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* A = stw + Ly;
+  cpx<T>* A = stw + Lh;
   cpx<T>* B = A + (size_t)nbuf * Ly;
   // this group's output channels, staged in LDS: per (output, source comp)
-  // the kernel offset and flags, per output the source film
-  __shared__ long long s_koff[MAX_OUT][3];
-  __shared__ int s_fl[MAX_OUT][3];
-  __shared__ int s_src[MAX_OUT];
+  // the kernel offset (kc Kx + kx) Kyh and flags, per output the source film
+  __shared__ int s_koff[MAX_OUT][3];
+  __shared__ unsigned char s_fl[MAX_OUT][3];
+  __shared__ unsigned char s_src[MAX_OUT];
   const int kx = blk / ngroup;
   const int g = blk - kx * ngroup;
   if (kx >= Kx) return;
@@ -127,11 +131,11 @@ __device__ __forceinline__ void col_body(int blk, const cpx<T>* __restrict__ spe
   for (int t = threadIdx.x; t < 3 * no; t += blockDim.x) {
     const int o = t / 3, b = t - 3 * o;
     const int kc = tab.ch[o0 + o].kc[b];
-    s_koff[o][b] = kc < 0 ? -1 : ((long long)kc * Kx + kx) * Kyh;
+    s_koff[o][b] = kc < 0 ? -1 : (kc * Kx + kx) * Kyh;
     s_fl[o][b] = tab.ch[o0 + o].fl[b];
     if (b == 0) s_src[o] = tab.ch[o0 + o].src;
   }
-  for (int t = threadIdx.x; t < Ly; t += blockDim.x) stw[t] = twy[t];
+  for (int t = threadIdx.x; t < Lh; t += blockDim.x) stw[t] = twy[t];
   const int nload = nin_ch * Ly;
   const float invLy = 1.0f / (float)Ly;
   for (int t = threadIdx.x; t < nload; t += blockDim.x) {
@@ -140,7 +144,8 @@ __device__ __forceinline__ void col_body(int blk, const cpx<T>* __restrict__ spe
     A[t] = (y < ny) ? spec1[((size_t)ch * ny + y) * Kx + kx] : mk<T>(0, 0);
   }
   __syncthreads();
-  cpx<T>* X = fft_lds<T, false>(A, B, P, nin_ch, Ly, stw);
+  const int twh = (Ly & 1) ? 0 : Lh;
+  cpx<T>* X = fft_lds<T, false>(A, B, P, nin_ch, Ly, stw, twh);
   cpx<T>* W = (X == A) ? B : A;
   const int nprod = no * Ly;
   for (int t = threadIdx.x; t < nprod; t += blockDim.x) {
@@ -152,7 +157,7 @@ __device__ __forceinline__ void col_body(int blk, const cpx<T>* __restrict__ spe
     cpx<T> acc = mk<T>(0, 0);
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      const long long ko = s_koff[o][b];
+      const int ko = s_koff[o][b];
       if (ko < 0) continue;
       const int fl = s_fl[o][b];
       T s = kern[ko + kyr];
@@ -167,7 +172,7 @@ __device__ __forceinline__ void col_body(int blk, const cpx<T>* __restrict__ spe
     W[t] = acc;
   }
   __syncthreads();
-  cpx<T>* Y = fft_lds<T, true>(W, X, P, no, Ly, stw);
+  cpx<T>* Y = fft_lds<T, true>(W, X, P, no, Ly, stw, twh);
   for (int o = 0; o < no; ++o) {
     const OutCh& oc = tab.ch[o0 + o];
     for (int r = threadIdx.x; r < oc.nrows; r += blockDim.x) {
@@ -315,12 +320,16 @@ __device__ void rigid_stage(RigidState* R, const DriveP& d, int stage, double F,
 }
 
 // Row kinds of the fused row kernel.
-enum { RK_SELF = 0, RK_CROSS = 3, RK_FP = 6, RK_FM = 9, RK_PHI = 12 };
+enum { RK_SELF = 0, RK_CROSS = 3, RK_FP = 6, RK_FM = 9, RK_PHI = 12, RK_XB = 40 };
 constexpr int MAX_ROWS = 24;
 
-// Block layout: tasks [film 0 rows][film 1 rows][film 1 rows -1 and ny]
-// (MODE_STAGE), [eval_film rows] (MODE_EVAL), [film 1 rows -1..ny]
-// (MODE_FORCE).  All inverse row transforms of a task run as one batch (or
+// Block layout: tasks [film 0 rows][film 1 rows] (MODE_STAGE; in potential
+// mode with a spring drive also [film 1 rows -1 and ny]), [eval_film rows]
+// (MODE_EVAL), [film 1 rows -1..ny] (MODE_FORCE).  In direct mode the
+// force's boundary rows -1 and ny (the y term summed by parts needs the
+// x-component of the base field there) ride along with the tasks of film 1
+// rows 0 and ny-1, one more inverse transform each, so that a stage
+// launches exactly nfilm * ny blocks.  All inverse row transforms of a task run as one batch (or
 // batches of p.nbr rows); every spline window is filtered in parallel.
 template <typename T>
 __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, double dt, int task, int ntask,
@@ -349,7 +358,8 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   T* gm = gp + nfc * nx;           // [nfc][nx] force layer z_s-1
   T* phit = gm + nfc * nx;         // [nslot][nx+6] potential at i = -3..nx+2
   const int nslot_max = p.pot ? (p.full_force ? 19 : 9) : 0;
-  double* red = reinterpret_cast<double*>(phit + (size_t)nslot_max * (nx + 6) + 2);
+  T* gxb = phit + (size_t)nslot_max * (nx + 6);  // [2][nx] base field x at slider rows -1, ny
+  double* red = reinterpret_cast<double*>(gxb + 2 * nx + 2);
   red = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(red) + 15) & ~uintptr_t(15));
   __shared__ const cpx<T>* rowp[MAX_ROWS];
   __shared__ int rowkind[MAX_ROWS];
@@ -380,6 +390,9 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
       two && film == 1 && ((p.mode == MODE_STAGE && p.with_force) || p.mode == MODE_FORCE);
   const bool ext_cross = two && film == 0 && p.hsur != nullptr;
   const bool need_cross = two && !ext_cross && ((p.term_mask & 16) || need_force);
+  // boundary force rows carried by this task (direct mode, stage launches)
+  const bool xb_lo = p.mode == MODE_STAGE && need_force && !p.pot && y == 0;
+  const bool xb_hi = p.mode == MODE_STAGE && need_force && !p.pot && y == ny - 1;
   const int h = p.halo;
 
   for (int t = threadIdx.x; t < N2x; t += blockDim.x) stw[t] = tw[t];
@@ -438,6 +451,14 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
         rowp[n] = spec2 + p.off_fm[c] + (size_t)y * p.Kx;
         rowkind[n++] = RK_FM + c;
       }
+    if (xb_lo) {
+      rowp[n] = spec2 + p.off_cross[1][0] + (size_t)(-1 - p.cross_row0[1]) * p.Kx;
+      rowkind[n++] = RK_XB;
+    }
+    if (xb_hi) {
+      rowp[n] = spec2 + p.off_cross[1][0] + (size_t)(ny - p.cross_row0[1]) * p.Kx;
+      rowkind[n++] = RK_XB + 1;
+    }
     s_nrow = n;
   }
 
@@ -497,6 +518,10 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
       const int kind = rowkind[b0 + r];
       if (kind < RK_CROSS) continue;
       const T* e = ext + (size_t)r * MW;
+      if (kind >= RK_XB) {
+        if (i >= 0 && i < nx) gxb[(kind - RK_XB) * nx + i] = fir_eval<T, K>(e, gs, i + h + ifs, E);
+        continue;
+      }
       if (kind >= RK_PHI) {
         const T v = (film == 1) ? fir_eval<T, K>(e, gs, i + h + ifs, E) : fir_eval<T, K>(e, gb, i + h + ifb, E);
         phit[(size_t)(kind - RK_PHI) * NP + i + 3] = v;
@@ -579,6 +604,14 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   const T gam = (T)p.gam, alp = (T)p.alpha;
   const T hdt = (T)dt;
   bool bad = false;
+  // fused x transform of the new row: real rows packed in fa (Lx reals each)
+  const bool fuse = p.spec1_out != nullptr && p.mode == MODE_STAGE && cell_row;
+  T* fr = reinterpret_cast<T*>(fa);
+  if (fuse)
+    for (int t = threadIdx.x; t < 3 * (Lx - nx); t += blockDim.x) {
+      const int c = t / (Lx - nx);
+      fr[c * Lx + nx + (t - c * (Lx - nx))] = T(0);
+    }
   if (cell_row && p.mode != MODE_FORCE) {
     for (int i = threadIdx.x; i < nx; i += blockDim.x) {
       const size_t id = (size_t)y * nx + i;
@@ -641,6 +674,11 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
         mnext[fo] = ox + c * kx;
         mnext[fo + plane] = oy + c * ky;
         mnext[fo + 2 * plane] = oz + c * kz;
+        if (fuse) {
+          fr[i] = ox + c * kx;
+          fr[Lx + i] = oy + c * ky;
+          fr[2 * Lx + i] = oz + c * kz;
+        }
       } else if (stage < 3) {
         acc[fo] += T(2) * kx;
         acc[fo + plane] += T(2) * ky;
@@ -649,6 +687,11 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
         mnext[fo] = ox + c * kx;
         mnext[fo + plane] = oy + c * ky;
         mnext[fo + 2 * plane] = oz + c * kz;
+        if (fuse) {
+          fr[i] = ox + c * kx;
+          fr[Lx + i] = oy + c * ky;
+          fr[2 * Lx + i] = oz + c * kz;
+        }
       } else {
         const T c = hdt / T(6);
         T nx_ = ox + c * (acc[fo] + kx);
@@ -660,7 +703,30 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
         mnext[fo] = nx_ * inv;
         mnext[fo + plane] = ny_ * inv;
         mnext[fo + 2 * plane] = nz_ * inv;
+        if (fuse) {
+          fr[i] = nx_ * inv;
+          fr[Lx + i] = ny_ * inv;
+          fr[2 * Lx + i] = nz_ * inv;
+        }
       }
+    }
+  }
+  if (fuse) {
+    // forward real transform of the three rows (as the x pass computes it)
+    __syncthreads();
+    const cpx<T>* Z = fft_lds<T, false>(fa, fb, p.px, 3, N2x, stw);
+    cpx<T>* dst = reinterpret_cast<cpx<T>*>(p.spec1_out);
+    const int K1 = N2x + 1;
+    for (int t = threadIdx.x; t < 3 * K1; t += blockDim.x) {
+      const int r = t / K1;
+      const int k = t - r * K1;
+      const cpx<T>* z = Z + (size_t)r * N2x;
+      cpx<T> zk = z[k == N2x ? 0 : k];
+      cpx<T> zm = z[k == 0 ? 0 : N2x - k];
+      zm.y = -zm.y;
+      const cpx<T> e = zk + zm;
+      const cpx<T> q = cmul(stp[k], zk - zm);
+      dst[((size_t)(film * 3 + r) * ny + y) * p.Kx + k] = mk<T>(T(0.5) * (e.x + q.y), T(0.5) * (e.y - q.x));
     }
   }
   if (need_force) {
@@ -684,6 +750,9 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
         }
         fpart[a] += v;
       }
+      // rows -1 and ny: m_y is zero outside the film
+      if (xb_lo) fpart[0] -= (double)gxb[i] * (double)ms[plane + i] * i2dy;
+      if (xb_hi) fpart[0] += (double)gxb[nx + i] * (double)ms[plane + (size_t)(ny - 1) * nx + i] * i2dy;
     }
   }
   if (bad) atomicOr(&s_bad, 1);
@@ -816,7 +885,26 @@ hipError_t launch_row_fwd(const T* src, void* dst, int nrows, int nin, int N2x, 
 
 template <typename T>
 size_t col_lds_bytes(int Ly, int nbuf) {
-  return sizeof(cpx<T>) * ((size_t)Ly + 2 * (size_t)nbuf * Ly);
+  const size_t Lh = (Ly & 1) ? Ly : Ly / 2;
+  return sizeof(cpx<T>) * (Lh + 2 * (size_t)nbuf * Ly);
+}
+
+// Resident blocks per CU of the y-pass kernel (256 threads = 4 waves, one
+// per SIMD) at `lds` bytes of dynamic LDS on a CDNA CU: 160 KiB of LDS
+// (512-byte granules), 512 VGPRs per SIMD lane (8-register granules), at
+// most 8 waves per SIMD.
+template <typename T>
+int col_blocks_per_cu(size_t lds) {
+  hipFuncAttributes a{};
+  if (hipFuncGetAttributes(&a, (const void*)k_col<T>) != hipSuccess) return 0;
+  const size_t per = ((lds + a.sharedSizeBytes + 511) / 512) * 512;
+  const int by_lds = (int)((160 * 1024) / per);
+  if (getenv("MMV_VERBOSE"))
+    fprintf(stderr, "mmv: k_col registers %d, static LDS %zu\n", a.numRegs, (size_t)a.sharedSizeBytes);
+  const int vg = ((a.numRegs > 0 ? a.numRegs : 128) + 7) / 8 * 8;
+  int waves = 512 / vg;
+  if (waves > 8) waves = 8;
+  return by_lds < waves ? by_lds : waves;
 }
 
 template <typename T>
@@ -845,7 +933,7 @@ size_t row_lds_bytes(const RowParams& p) {
   size_t b = sizeof(cpx<T>) * (size_t)(2 * p.N2x + 1 + 2 * (size_t)p.nbr * p.N2x);
   const int nslot = p.pot ? (p.full_force ? 19 : 9) : 0;
   b += sizeof(T) * ((size_t)p.nbr * (p.M + 2 * E) + 2 * NQ + 3 * p.nx + 3 * (p.nx + 2) + 2 * nfc * p.nx +
-                    (size_t)nslot * (p.nx + 6) + 2);
+                    (size_t)nslot * (p.nx + 6) + 2 * (size_t)p.nx + 2);
   b = (b + 15) & ~size_t(15);
   b += sizeof(double) * 3 * ROW_THREADS + 16;
   return b;
@@ -928,6 +1016,7 @@ hipError_t launch_colpack(const void* spec, T* out, int Kx, int Ly, int Kyh, con
                                         hipStream_t);                                                          \
   template size_t row_lds_bytes<T>(const RowParams&);                                                           \
   template size_t col_lds_bytes<T>(int, int);                                                                    \
+  template int col_blocks_per_cu<T>(size_t);                                                                     \
   template hipError_t prepare_batch_kernels<T>(size_t, size_t, size_t);                                         \
   template hipError_t launch_row_fwd_batch<T>(const RowFwdDesc*, const int*, int, int, size_t, hipStream_t);      \
   template hipError_t launch_col_batch<T>(const ColDesc*, const int*, int, int, size_t, hipStream_t);             \
