@@ -23,9 +23,32 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 METRIC = "cell-updates/s per LLG step; surrogate+batched vs plain at ≤1e-3 H error"
 
-# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
-# (profiles/), keyed by the source hash of the kernels it was taken on.
-TRAFFIC = {}
+# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs
+# (summaries under profiles/), scaled by the same counters read on a plain
+# device copy of known size, keyed by kernel and by the hash of the kernel
+# sources they were taken on: a changed kernel reports null.
+TRAFFIC = {
+    "col": {"source": "94ba62dc1ba8", "bytes": 16675219},
+    "row_stage": {"source": "94ba62dc1ba8", "bytes": 21437514},
+}
+KERNEL_SOURCES = ("paper_1801_04181_amd/csrc/mmv_kernels.hip", "paper_1801_04181_amd/csrc/mmv_device.h",
+                  "paper_1801_04181_amd/csrc/mmv_internal.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
+def traffic_of(kernel):
+    t = TRAFFIC.get(kernel)
+    if t is None or t.get("source") != kernel_source_hash():
+        return None
+    return t["bytes"]
 
 
 def kernel_bytes(desc, lx, ly):
@@ -36,7 +59,8 @@ def kernel_bytes(desc, lx, ly):
                  output row of every channel.
     row kernel:  read every output row, m of the stage, m at the step start,
                  the RK accumulator (3 of 4 stages), write the next stage m and
-                 the accumulator (3 of 4 stages).
+                 the accumulator (3 of 4 stages), and write the next stage's
+                 row spectra (the x transform runs inside the row kernel).
     """
     r = 4 if desc.precision == 32 else 8
     c = 2 * r
@@ -55,7 +79,7 @@ def kernel_bytes(desc, lx, ly):
     return {
         "row_fwd": 3 * cells * r + spec1,
         "col": spec1 + kern + spec2,
-        "row_stage": spec2 + cells * 3 * r * (1 + 1 + 0.75 + 1 + 0.75),
+        "row_stage": spec2 + cells * 3 * r * (1 + 1 + 0.75 + 1 + 0.75) + spec1,
     }, cells
 
 
@@ -276,6 +300,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--report", choices=["precision", "surrogate"], default=None)
     ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the run, copy 256 MiB device to device 3 times (counter calibration)")
     args = ap.parse_args()
     if args.report == "precision":
         print(json.dumps({"precision_report": precision_report()}), flush=True)
@@ -356,7 +382,7 @@ def main():
                    "cells": cells, "fft": [lx, ly], "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
-                     "traffic": TRAFFIC.get(dom), "bytes_per_launch": per_launch[dom],
+                     "traffic": traffic_of(dom), "bytes_per_launch": per_launch[dom],
                      "avg_launch_us": avg_s * 1e6, "launches": kn},
         "kernel_share": {k: v[0] / sum(p[0] for p in probe.values()) for k, v in probe.items()},
         "wall_s": wall,
@@ -367,6 +393,13 @@ def main():
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, m)
     print(json.dumps(out), flush=True)
+    if args.calib_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print("calib copy: 268435456 bytes read and written per launch", file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":

@@ -138,6 +138,33 @@ __device__ __forceinline__ void dft(cpx<T>* v) {
 // than the float rounding of the product.
 __device__ __forceinline__ int fdiv(int n, float inv_d) { return (int)(((float)n + 0.5f) * inv_d); }
 
+// dst[t] = load(t) for t < n, block-strided, with U independent loads in
+// flight per thread before the first store (one global-memory latency per U
+// elements instead of one per element).
+template <int U, typename V, typename F>
+__device__ __forceinline__ void stage_copy(V* dst, int n, F load) {
+  for (int t0 = threadIdx.x; t0 < n; t0 += U * (int)blockDim.x) {
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * (int)blockDim.x;
+      if (t < n) v[u] = load(t);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * (int)blockDim.x;
+      if (t < n) dst[t] = v[u];
+    }
+  }
+}
+
+// Sum over the 64 lanes of a wave; the total is returned in lane 0.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
 // One radix-R Stockham pass over `batch` transforms of length L at stride
 // `stride`: reads src[j + r*nb], twiddles by exp(-+2 pi i r k / (Ns R)),
 // DFT_R, writes dst[(j - k) R + k + r Ns] with k = j mod Ns.

@@ -271,7 +271,9 @@ __device__ __forceinline__ T fir_eval(const T* ext, const T* g, int k0, int E) {
 
 __device__ void rigid_stage(RigidState* R, const DriveP& d, int stage, double F, double h,
                             double dxc, int travel) {
+  // every field is read before the first store, so the loads issue together
   const double x = R->xs, v = R->vs, t = R->ts;
+  const double x0 = R->x0, v0 = R->v0, t0 = R->t0, ax = R->ax, av = R->av;
   double dxdt = 0.0, dvdt = 0.0;
   if (d.mode == 1) {
     dxdt = d.v_d;
@@ -283,26 +285,26 @@ __device__ void rigid_stage(RigidState* R, const DriveP& d, int stage, double F,
   if (stage == 0) {
     R->ax = dxdt;
     R->av = dvdt;
-    R->xs = R->x0 + 0.5 * h * dxdt;
-    R->vs = R->v0 + 0.5 * h * dvdt;
-    R->ts = R->t0 + 0.5 * h;
+    R->xs = x0 + 0.5 * h * dxdt;
+    R->vs = v0 + 0.5 * h * dvdt;
+    R->ts = t0 + 0.5 * h;
   } else if (stage == 1) {
-    R->ax += 2.0 * dxdt;
-    R->av += 2.0 * dvdt;
-    R->xs = R->x0 + 0.5 * h * dxdt;
-    R->vs = R->v0 + 0.5 * h * dvdt;
-    R->ts = R->t0 + 0.5 * h;
+    R->ax = ax + 2.0 * dxdt;
+    R->av = av + 2.0 * dvdt;
+    R->xs = x0 + 0.5 * h * dxdt;
+    R->vs = v0 + 0.5 * h * dvdt;
+    R->ts = t0 + 0.5 * h;
   } else if (stage == 2) {
-    R->ax += 2.0 * dxdt;
-    R->av += 2.0 * dvdt;
-    R->xs = R->x0 + h * dxdt;
-    R->vs = R->v0 + h * dvdt;
-    R->ts = R->t0 + h;
+    R->ax = ax + 2.0 * dxdt;
+    R->av = av + 2.0 * dvdt;
+    R->xs = x0 + h * dxdt;
+    R->vs = v0 + h * dvdt;
+    R->ts = t0 + h;
   } else {
-    const double xn = R->x0 + h / 6.0 * (R->ax + dxdt);
-    const double vn = R->v0 + h / 6.0 * (R->av + dvdt);
-    R->t0 = R->t0 + h;
-    R->ts = R->t0;
+    const double xn = x0 + h / 6.0 * (ax + dxdt);
+    const double vn = v0 + h / 6.0 * (av + dvdt);
+    R->t0 = t0 + h;
+    R->ts = t0 + h;
     R->x0 = R->xs = xn;
     R->v0 = R->vs = vn;
     R->step += 1;
@@ -395,8 +397,12 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   const bool xb_hi = p.mode == MODE_STAGE && need_force && !p.pot && y == ny - 1;
   const int h = p.halo;
 
-  for (int t = threadIdx.x; t < N2x; t += blockDim.x) stw[t] = tw[t];
-  for (int t = threadIdx.x; t <= N2x; t += blockDim.x) stp[t] = twp[t];
+  // slider offset of this stage (issued first; the last block of the launch
+  // is the only writer and runs after every block has read it)
+  const double xs = rigid->xs;
+  const int s_int = rigid->s_int;
+  // twiddles: stw (N2x) and stp (N2x + 1) are contiguous
+  stage_copy<4>(stw, 2 * N2x + 1, [&](int t) { return t < N2x ? tw[t] : twp[t - N2x]; });
   for (int t = threadIdx.x; t < 3 * nx; t += blockDim.x) H[t] = T(0);
   if (threadIdx.x == 0) {
     s_bad = 0;
@@ -462,9 +468,6 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     s_nrow = n;
   }
 
-  // slider offset of this stage
-  const double xs = rigid->xs;
-  const int s_int = rigid->s_int;
   double xp = xs / p.dx - (double)s_int;
   const bool xp_bad = !(xp >= -1.0 && xp < 2.0);
   if (xp_bad) xp = 0.0;
@@ -478,8 +481,11 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     double g = 0.0;
     for (int t = -1; t <= 2; ++t) {
       const int j = t - q;
-      if (j >= -K && j <= K)
-        g += beta3(fr - t) * 1.7320508075688772935 * pow(-z1, (double)abs(j)) * ((abs(j) & 1) ? -1.0 : 1.0);
+      if (j >= -K && j <= K) {
+        double zp = 1.0;  // z1^|j|
+        for (int a = 0; a < abs(j); ++a) zp *= z1;
+        g += beta3(fr - t) * 1.7320508075688772935 * zp;
+      }
     }
     (tq < NQ ? gs : gb)[tq % NQ] = (T)g;
   }
@@ -756,17 +762,21 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     }
   }
   if (bad) atomicOr(&s_bad, 1);
-  // block reduction of the force partials, fixed order
-  for (int a = 0; a < 3; ++a) red[a * blockDim.x + threadIdx.x] = fpart[a];
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s)
-      for (int a = 0; a < 3; ++a) red[a * blockDim.x + threadIdx.x] += red[a * blockDim.x + threadIdx.x + s];
-    __syncthreads();
+  // block reduction of the force partials, fixed order: within each wave,
+  // then over the waves
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  for (int a = 0; a < 3; ++a) {
+    const double v = wave_sum(fpart[a]);
+    if (lane == 0) red[wv * 3 + a] = v;
   }
+  __syncthreads();
   if (p.mode == MODE_EVAL) return;
   if (threadIdx.x == 0) {
-    for (int a = 0; a < 3; ++a) partial[(size_t)task * 3 + a] = red[a * blockDim.x];
+    for (int a = 0; a < 3; ++a) {
+      double v = 0.0;
+      for (int w = 0; w < nw; ++w) v += red[w * 3 + a];
+      partial[(size_t)task * 3 + a] = v;
+    }
     if (s_bad || xp_bad) atomicOr(&rigid->flags, s_bad ? (int)FLAG_NUMERIC : (int)FLAG_RANGE);
     __threadfence();
     const unsigned prev = atomicAdd(counter, 1u);
@@ -779,17 +789,20 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   for (int t = threadIdx.x; t < ntask; t += blockDim.x)
     for (int a = 0; a < 3; ++a)
       sum[a] += __hip_atomic_load(&partial[(size_t)t * 3 + a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  for (int a = 0; a < 3; ++a) red[a * blockDim.x + threadIdx.x] = sum[a];
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s)
-      for (int a = 0; a < 3; ++a) red[a * blockDim.x + threadIdx.x] += red[a * blockDim.x + threadIdx.x + s];
-    __syncthreads();
+  for (int a = 0; a < 3; ++a) {
+    const double v = wave_sum(sum[a]);
+    if (lane == 0) red[48 + wv * 3 + a] = v;
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const double F0 = p.force_scale * red[0];
+    double tot[3];
+    for (int a = 0; a < 3; ++a) {
+      tot[a] = 0.0;
+      for (int w = 0; w < nw; ++w) tot[a] += red[48 + w * 3 + a];
+    }
+    const double F0 = p.force_scale * tot[0];
     if (p.mode == MODE_FORCE) {
-      for (int a = 0; a < 3; ++a) rigid->F[a] = p.force_scale * red[a * blockDim.x];
+      for (int a = 0; a < 3; ++a) rigid->F[a] = p.force_scale * tot[a];
     } else {
       rigid_stage(rigid, p.drive, stage, F0, dt, p.dx, p.travel);
     }
@@ -935,7 +948,7 @@ size_t row_lds_bytes(const RowParams& p) {
   b += sizeof(T) * ((size_t)p.nbr * (p.M + 2 * E) + 2 * NQ + 3 * p.nx + 3 * (p.nx + 2) + 2 * nfc * p.nx +
                     (size_t)nslot * (p.nx + 6) + 2 * (size_t)p.nx + 2);
   b = (b + 15) & ~size_t(15);
-  b += sizeof(double) * 3 * ROW_THREADS + 16;
+  b += sizeof(double) * 96 + 16;  // wave partials of the force reduction
   return b;
 }
 
