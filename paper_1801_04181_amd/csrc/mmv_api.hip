@@ -718,8 +718,23 @@ int check_handle(mmv_handle h) {
   return MMV_OK;
 }
 
+TickArgs tick_args(mmv_mesh* h, int ntask) {
+  TickArgs a{};
+  a.partial = h->partial;
+  a.rigid = h->rigid;
+  a.drive = h->drive;
+  a.force_scale = h->rp_hot.force_scale;
+  a.dx = h->d.dx;
+  a.ntask = ntask;
+  a.travel = h->rp_hot.travel;
+  return a;
+}
+
+// tick_stage >= 0: the y pass also applies the slider update of the row
+// launch of that stage (whose force partials are in h->partial)
 template <typename T>
-int run_fields(mmv_mesh* h, const void* m_in, const OutTable& tab, bool fwd = true) {
+int run_fields(mmv_mesh* h, const void* m_in, const OutTable& tab, bool fwd = true, int tick_stage = -1,
+               int tick_ntask = 0, double tick_dt = 0.0) {
   if (fwd) {
     PROF(1);
     HIPCHK(launch_row_fwd<T>((const T*)m_in, h->spec1, 3 * h->nfilm * h->ny, h->nx, h->N2x, h->Kx, h->px, h->twx,
@@ -727,8 +742,9 @@ int run_fields(mmv_mesh* h, const void* m_in, const OutTable& tab, bool fwd = tr
     PROF(1);
   }
   PROF(2);
+  const TickArgs ta = tick_args(h, tick_ntask);
   HIPCHK(launch_col<T>(h->spec1, h->spec2, (const T*)h->kern, h->Kx, h->Ly, h->Kyh, h->ny, 3 * h->nfilm, h->ngroup,
-                       h->py, h->twy, tab, h->st));
+                       h->py, h->twy, tab, h->st, tick_stage >= 0 ? &ta : nullptr, tick_stage, tick_dt));
   PROF(2);
   return MMV_OK;
 }
@@ -766,12 +782,19 @@ int step_typed(mmv_mesh* h, double dt, int nsteps) {
   rp.ntask = h->nfilm * h->ny + ((rp.with_force && rp.pot) ? 2 : 0);
   // after the first stage the x-pass input comes from the row kernel
   rp.spec1_out = h->fuse_fwd ? h->spec1 : nullptr;
+  // the slider update of each row launch is applied by the next y pass (or
+  // by a one-block kernel when something else must see it first)
+  rp.defer_tick = 1;
+  const TickArgs ta = tick_args(h, rp.ntask);
+  int pending = -1;
   T* m0 = (T*)h->m0;
   T* b1 = (T*)h->mb[0];
   T* b2 = (T*)h->mb[1];
   const size_t plane = (size_t)h->ny * h->nx;
   for (int n = 0; n < nsteps; ++n) {
     if (h->sur && !h->sur_fallback && h->sur_steps % h->sur_every == 0) {
+      if (pending >= 0) HIPCHK(launch_tick(ta, pending, dt, h->st));
+      pending = -1;
       int rc = sur_judge<T>(h);
       if (rc) return rc;
     }
@@ -782,6 +805,9 @@ int step_typed(mmv_mesh* h, double dt, int nsteps) {
       int rc;
       const bool fwd = !h->fuse_fwd || (n == 0 && s == 0);
       if (use_sur) {
+        // the network reads this stage's slider offset: apply the update first
+        if (pending >= 0) HIPCHK(launch_tick(ta, pending, dt, h->st));
+        pending = -1;
         // film 0's cross field from the network at this stage's slider state
         HIPCHK(launch_sur_input((const float*)in + 3 * plane, h->rigid, 1.0 / h->d.dx, h->ny, h->nx, h->sur_in,
                                 h->st));
@@ -792,7 +818,8 @@ int step_typed(mmv_mesh* h, double dt, int nsteps) {
         rc = run_fields<T>(h, in, h->tab_sur, fwd);
       } else {
         rp.hsur = nullptr;
-        rc = run_fields<T>(h, in, h->tab_hot, fwd);
+        rc = run_fields<T>(h, in, h->tab_hot, fwd, pending, rp.ntask, dt);
+        pending = -1;
       }
       if (rc) return rc;
       rp.stage = s;
@@ -800,9 +827,11 @@ int step_typed(mmv_mesh* h, double dt, int nsteps) {
       HIPCHK(launch_row_stage<T>(rp, h->spec2, in, m0, out, (T*)h->acc, nullptr, h->twx, h->twp, h->rigid,
                                  h->partial, h->counter, h->st));
       PROF(3);
+      pending = s;
     }
     if (h->sur) h->sur_steps += 1;
   }
+  if (pending >= 0) HIPCHK(launch_tick(ta, pending, dt, h->st));
   return MMV_OK;
 }
 
@@ -900,6 +929,7 @@ int balloc(mmv_batch* b, void** p, size_t bytes) {
 RowParams stage_params(mmv_mesh* h, bool fuse) {
   RowParams rp = h->rp_hot;
   rp.spec1_out = fuse ? h->spec1 : nullptr;
+  rp.defer_tick = 1;
   rp.mode = MODE_STAGE;
   rp.term_mask = MMV_TERM_ALL;
   rp.drive = h->drive;
@@ -971,6 +1001,7 @@ int batch_build(mmv_batch* b) {
     c.P = h->py;
     c.twy = h->twy;
     c.tab = h->tab_hot;
+    c.tick = tick_args(h, rp.ntask);
     sf[i + 1] = sf[i] + h->nfilm * h->ny;
     sc[i + 1] = sc[i] + h->Kx * h->ngroup;
     ss[i + 1] = ss[i] + rp.ntask;
@@ -1015,6 +1046,7 @@ template <typename T>
 int batch_launch_steps(mmv_batch* b, hipStream_t st, double dt, int nsteps) {
   const int n = (int)b->inst.size();
   mmv_mesh* h0 = b->inst[0];  // timing events of the first instance's profile slot
+  int pending = -1;           // stage whose slider update the next y pass applies
   for (int k = 0; k < nsteps; ++k)
     for (int s = 0; s < 4; ++s) {
       mmv_mesh* h = h0;
@@ -1024,12 +1056,14 @@ int batch_launch_steps(mmv_batch* b, hipStream_t st, double dt, int nsteps) {
         PROF(1);
       }
       PROF(2);
-      HIPCHK(launch_col_batch<T>(b->d_col, b->s_col, n, b->nblk_col, b->lds_col, st));
+      HIPCHK(launch_col_batch<T>(b->d_col, b->s_col, n, b->nblk_col, b->lds_col, st, pending, dt));
       PROF(2);
       PROF(3);
       HIPCHK(launch_row_stage_batch<T>(b->d_stage[s], b->s_stage, n, b->nblk_stage, b->lds_stage, s, dt, st));
       PROF(3);
+      pending = s;
     }
+  if (pending >= 0) HIPCHK(launch_tick_batch(b->d_col, n, pending, dt, st));
   return MMV_OK;
 }
 

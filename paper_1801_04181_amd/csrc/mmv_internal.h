@@ -60,6 +60,18 @@ struct DriveP {
 
 enum { MODE_EVAL = 0, MODE_STAGE = 1, MODE_FORCE = 2 };
 
+// The slider's stage update (Eq. 15 inside RK4) from the force partials of a
+// finished row launch: applied by the first block of the next y-pass launch
+// (or by a one-block kernel after the last stage of a call), so the row
+// kernel needs no device-wide fence.
+struct TickArgs {
+  const double* partial;  // [ntask][3], F_x partial sums per row task
+  RigidState* rigid;
+  DriveP drive;
+  double force_scale, dx;
+  int ntask, travel;
+};
+
 // Parameters of the fused row kernel (inverse row transform, spline,
 // local fields, LLG stage, force partials).
 struct RowParams {
@@ -97,6 +109,9 @@ struct RowParams {
   // float32 [3][ny][nx] array (times sur_scale) instead of the spline rows
   const float* hsur;
   double sur_scale;
+  // MODE_STAGE: blocks only write their force partials; the slider update
+  // is applied later (TickArgs) instead of by the launch's last block
+  int defer_tick;
   // MODE_STAGE: when set, each cell-row task also x-transforms the three
   // components of its new magnetisation row into this spectrum array (the
   // x-pass input of the next stage), [film][comp][y][Kx]
@@ -121,6 +136,7 @@ struct ColDesc {
   FftPlan P;
   const void* twy;
   OutTable tab;
+  TickArgs tick;
 };
 
 struct RowStageDesc {

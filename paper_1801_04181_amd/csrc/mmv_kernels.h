@@ -11,7 +11,11 @@ hipError_t launch_row_fwd(const T* src, void* dst, int nrows, int nin, int N2x, 
                           const void* tw, const void* twp, hipStream_t st, int ny3 = 0);
 template <typename T>
 hipError_t launch_col(const void* spec1, void* spec2, const T* kern, int Kx, int Ly, int Kyh, int ny, int nin_ch,
-                      int ngroup, const FftPlan& P, const void* twy, const OutTable& tab, hipStream_t st);
+                      int ngroup, const FftPlan& P, const void* twy, const OutTable& tab, hipStream_t st,
+                      const TickArgs* tick = nullptr, int tick_stage = -1, double tick_dt = 0.0);
+// the pending slider update alone (after the last row launch of a call)
+hipError_t launch_tick(const TickArgs& tick, int stage, double dt, hipStream_t st);
+hipError_t launch_tick_batch(const ColDesc* d, int n, int stage, double dt, hipStream_t st);
 template <typename T>
 hipError_t launch_row_stage(const RowParams& p, const void* spec2, const T* mst, const T* m0, T* mnext, T* acc,
                             T* hout, const void* tw, const void* twp, RigidState* rigid, double* partial,
@@ -28,7 +32,8 @@ size_t row_lds_bytes(const RowParams& p);
 template <typename T>
 hipError_t launch_row_fwd_batch(const RowFwdDesc* d, const int* start, int n, int nblk, size_t lds, hipStream_t st);
 template <typename T>
-hipError_t launch_col_batch(const ColDesc* d, const int* start, int n, int nblk, size_t lds, hipStream_t st);
+hipError_t launch_col_batch(const ColDesc* d, const int* start, int n, int nblk, size_t lds, hipStream_t st,
+                            int tick_stage = -1, double tick_dt = 0.0);
 template <typename T>
 hipError_t launch_row_stage_batch(const RowStageDesc* d, const int* start, int n, int nblk, size_t lds, int stage,
                                   double dt, hipStream_t st);

@@ -183,21 +183,49 @@ __device__ __forceinline__ void col_body(int blk, const cpx<T>* __restrict__ spe
   }
 }
 
+__device__ void rigid_stage(RigidState* R, const DriveP& d, int stage, double F, double h, double dxc, int travel);
+
+// Slider stage update from a finished row launch's force partials, by one
+// whole block: fixed-order float64 sum (strided per thread, then per wave,
+// then over the waves), then Eq. 15's RK4 stage.
+__device__ void tick_body(const TickArgs& a, int stage, double dt) {
+  __shared__ double s_red[16];
+  double v = 0.0;
+  for (int t = threadIdx.x; t < a.ntask; t += blockDim.x) v += a.partial[(size_t)t * 3];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double F = 0.0;
+    for (int w = 0; w < ((int)blockDim.x + 63) >> 6; ++w) F += s_red[w];
+    rigid_stage(a.rigid, a.drive, stage, a.force_scale * F, dt, a.dx, a.travel);
+  }
+  __syncthreads();
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_col(const cpx<T>* __restrict__ spec1, cpx<T>* __restrict__ spec2, const T* __restrict__ kern,
           int Kx, int Ly, int Kyh, int ny, int nin_ch, int ngroup, int nbuf, FftPlan P,
-          const cpx<T>* __restrict__ twy, OutTable tab) {
+          const cpx<T>* __restrict__ twy, OutTable tab, TickArgs tick, int tick_stage, double tick_dt) {
+  if (tick_stage >= 0 && blockIdx.x == 0) tick_body(tick, tick_stage, tick_dt);
   col_body<T>(xcd_remap(blockIdx.x, gridDim.x), spec1, spec2, kern, Kx, Ly, Kyh, ny, nin_ch, ngroup, nbuf, P, twy,
               tab);
 }
 
+__global__ void __launch_bounds__(256) k_tick(TickArgs tick, int stage, double dt) { tick_body(tick, stage, dt); }
+
+__global__ void __launch_bounds__(256) k_tick_batch(const ColDesc* __restrict__ d, int stage, double dt) {
+  tick_body(d[blockIdx.x].tick, stage, dt);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_col_batch(const ColDesc* __restrict__ d, const int* __restrict__ start,
-                                                   int n) {
+                                                   int n, int tick_stage, double tick_dt) {
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int i = find_instance(start, n, b);
   const ColDesc& q = d[i];
+  if (tick_stage >= 0 && b == start[i]) tick_body(q.tick, tick_stage, tick_dt);
   col_body<T>(b - start[i], (const cpx<T>*)q.spec1, (cpx<T>*)q.spec2, (const T*)q.kern, q.Kx, q.Ly, q.Kyh, q.ny,
               q.nin_ch, q.ngroup, q.nbuf, q.P, (const cpx<T>*)q.twy, q.tab);
 }
@@ -771,6 +799,18 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   }
   __syncthreads();
   if (p.mode == MODE_EVAL) return;
+  if (p.mode == MODE_STAGE && p.defer_tick) {
+    // partials only; the slider update runs after this launch
+    if (threadIdx.x == 0) {
+      for (int a = 0; a < 3; ++a) {
+        double v = 0.0;
+        for (int w = 0; w < nw; ++w) v += red[w * 3 + a];
+        partial[(size_t)task * 3 + a] = v;
+      }
+      if (s_bad || xp_bad) atomicOr(&rigid->flags, s_bad ? (int)FLAG_NUMERIC : (int)FLAG_RANGE);
+    }
+    return;
+  }
   if (threadIdx.x == 0) {
     for (int a = 0; a < 3; ++a) {
       double v = 0.0;
@@ -923,7 +963,7 @@ int col_blocks_per_cu(size_t lds) {
 template <typename T>
 hipError_t launch_col(const void* spec1, void* spec2, const T* kern, int Kx, int Ly, int Kyh, int ny,
                       int nin_ch, int ngroup, const FftPlan& P, const void* twy, const OutTable& tab,
-                      hipStream_t st) {
+                      hipStream_t st, const TickArgs* tick, int tick_stage, double tick_dt) {
   const int per = (tab.n + ngroup - 1) / ngroup;
   const int nbuf = nin_ch > per ? nin_ch : per;
   const size_t lds = col_lds_bytes<T>(Ly, nbuf);
@@ -932,8 +972,21 @@ hipError_t launch_col(const void* spec1, void* spec2, const T* kern, int Kx, int
     hipError_t e = hipFuncSetAttribute((const void*)k_col<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
+  TickArgs ta{};
+  if (tick) ta = *tick;
   hipLaunchKernelGGL(k_col<T>, dim3(nblk), dim3(256), lds, st, (const cpx<T>*)spec1, (cpx<T>*)spec2, kern, Kx,
-                     Ly, Kyh, ny, nin_ch, ngroup, nbuf, P, (const cpx<T>*)twy, tab);
+                     Ly, Kyh, ny, nin_ch, ngroup, nbuf, P, (const cpx<T>*)twy, tab, ta, tick ? tick_stage : -1,
+                     tick_dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_tick(const TickArgs& tick, int stage, double dt, hipStream_t st) {
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(256), 0, st, tick, stage, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_tick_batch(const ColDesc* d, int n, int stage, double dt, hipStream_t st) {
+  hipLaunchKernelGGL(k_tick_batch, dim3(n), dim3(256), 0, st, d, stage, dt);
   return hipGetLastError();
 }
 
@@ -973,8 +1026,9 @@ hipError_t launch_row_fwd_batch(const RowFwdDesc* d, const int* start, int n, in
 }
 
 template <typename T>
-hipError_t launch_col_batch(const ColDesc* d, const int* start, int n, int nblk, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL(k_col_batch<T>, dim3(nblk), dim3(256), lds, st, d, start, n);
+hipError_t launch_col_batch(const ColDesc* d, const int* start, int n, int nblk, size_t lds, hipStream_t st,
+                            int tick_stage, double tick_dt) {
+  hipLaunchKernelGGL(k_col_batch<T>, dim3(nblk), dim3(256), lds, st, d, start, n, tick_stage, tick_dt);
   return hipGetLastError();
 }
 
@@ -1021,7 +1075,7 @@ hipError_t launch_colpack(const void* spec, T* out, int Kx, int Ly, int Kyh, con
   template hipError_t launch_row_fwd<T>(const T*, void*, int, int, int, int, const FftPlan&, const void*,      \
                                         const void*, hipStream_t, int);                                             \
   template hipError_t launch_col<T>(const void*, void*, const T*, int, int, int, int, int, int, const FftPlan&, \
-                                    const void*, const OutTable&, hipStream_t);                                \
+                                    const void*, const OutTable&, hipStream_t, const TickArgs*, int, double);  \
   template hipError_t launch_row_stage<T>(const RowParams&, const void*, const T*, const T*, T*, T*, T*,       \
                                           const void*, const void*, RigidState*, double*, unsigned*,           \
                                           hipStream_t);                                                        \
@@ -1032,7 +1086,7 @@ hipError_t launch_colpack(const void* spec, T* out, int Kx, int Ly, int Kyh, con
   template int col_blocks_per_cu<T>(size_t);                                                                     \
   template hipError_t prepare_batch_kernels<T>(size_t, size_t, size_t);                                         \
   template hipError_t launch_row_fwd_batch<T>(const RowFwdDesc*, const int*, int, int, size_t, hipStream_t);      \
-  template hipError_t launch_col_batch<T>(const ColDesc*, const int*, int, int, size_t, hipStream_t);             \
+  template hipError_t launch_col_batch<T>(const ColDesc*, const int*, int, int, size_t, hipStream_t, int, double);             \
   template hipError_t launch_row_stage_batch<T>(const RowStageDesc*, const int*, int, int, size_t, int, double,   \
                                                 hipStream_t);
 
