@@ -68,6 +68,17 @@ template <> struct Roots<7> {
   }
 };
 
+template <> struct Roots<9> {
+  static __device__ __forceinline__ double c(int m) {
+    return m == 1 ? 0.766044443118978035202
+                  : (m == 2 ? 0.173648177666930348852 : (m == 3 ? -0.5 : -0.939692620785908384054));
+  }
+  static __device__ __forceinline__ double s(int m) {
+    return m == 1 ? 0.642787609686539326323
+                  : (m == 2 ? 0.984807753012208059367 : (m == 3 ? 0.866025403784438646764 : 0.342020143325668733044));
+  }
+};
+
 // In-register DFT of odd length R, forward (e^{-2 pi i rq/R}) or inverse.
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dft_odd(cpx<T>* v) {
@@ -91,7 +102,10 @@ __device__ __forceinline__ void dft_odd(cpx<T>* v) {
     for (int r = 1; r <= H; ++r) {
       int m = (r * q) % R;
       T c, sn;
-      if (m <= H) {
+      if (m == 0) {  // composite R (9): r q can be a multiple of R
+        c = T(1);
+        sn = T(0);
+      } else if (m <= H) {
         c = (T)Roots<R>::c(m);
         sn = (T)Roots<R>::s(m);
       } else {
@@ -128,6 +142,19 @@ __device__ __forceinline__ void dft(cpx<T>* v) {
     v[2] = t0 - t2;
     v[1] = t1 + t3;
     v[3] = t1 - t3;
+  } else if constexpr (R == 6) {
+    // prime-factor 2 x 3 (no twiddles): inputs n = (3 n1 + 2 n2) mod 6,
+    // outputs k = (3 k1 + 4 k2) mod 6
+    cpx<T> a[3] = {v[0], v[2], v[4]};
+    cpx<T> b[3] = {v[3], v[5], v[1]};
+    dft_odd<T, 3, INV>(a);
+    dft_odd<T, 3, INV>(b);
+    v[0] = a[0] + b[0];
+    v[3] = a[0] - b[0];
+    v[4] = a[1] + b[1];
+    v[1] = a[1] - b[1];
+    v[2] = a[2] + b[2];
+    v[5] = a[2] - b[2];
   } else {
     dft_odd<T, R, INV>(v);
   }
@@ -194,13 +221,11 @@ __device__ __forceinline__ void stockham_pass(const cpx<T>* __restrict__ a, cpx<
       const int kt = k * tws;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
+        // branch-free: one load from the stored half, sign by select
         const int id = r * kt;
-        if (twh == 0 || id < twh) {
-          wv[r] = tw[id];
-        } else {
-          const cpx<T> w = tw[id - twh];
-          wv[r] = mk(-w.x, -w.y);
-        }
+        const bool hi = twh != 0 && id >= twh;
+        const cpx<T> w = tw[hi ? id - twh : id];
+        wv[r] = hi ? mk(-w.x, -w.y) : w;
       }
     }
     const int din = j;
@@ -222,14 +247,104 @@ __device__ __forceinline__ void stockham_pass(const cpx<T>* __restrict__ a, cpx<
   }
 }
 
+// ---------------------------------------------------------------- compile-time plans
+// For the lengths the workloads use, the radix plan, butterfly counts, thread
+// mapping and LDS strides are compile-time constants: index arithmetic folds,
+// LDS accesses take immediate offsets.  Radices: 7, 5, then 3s paired into 9,
+// then 4s, and a remaining 2 paired with a 3 into 6.
+struct CPlan {
+  int np;
+  int r[12];
+};
+
+constexpr CPlan make_cplan(int L) {
+  CPlan p{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+  int n = L, n3 = 0, n2 = 0;
+  while (n % 7 == 0) { p.r[p.np++] = 7; n /= 7; }
+  while (n % 5 == 0) { p.r[p.np++] = 5; n /= 5; }
+  while (n % 3 == 0) { ++n3; n /= 3; }
+  while (n % 2 == 0) { ++n2; n /= 2; }
+  if (n2 % 2 == 1 && n3 > 0) { p.r[p.np++] = 6; --n3; --n2; }
+  while (n3 >= 2) { p.r[p.np++] = 9; n3 -= 2; }
+  if (n3 == 1) p.r[p.np++] = 3;
+  while (n2 >= 2) { p.r[p.np++] = 4; n2 -= 2; }
+  if (n2 == 1) p.r[p.np++] = 2;
+  return p;
+}
+
+// One radix-R pass of `batch` contiguous transforms of length L with NT
+// threads per block (any blockDim works: butterflies are block-strided).
+// HALF: only tw[0..L/2) is stored and tw[t + L/2] = -tw[t].
+template <typename T, int L, int NT, int R, int Ns, bool INV, bool HALF>
+__device__ __forceinline__ void stockham_ct(const cpx<T>* __restrict__ a, cpx<T>* __restrict__ b, int batch,
+                                            const cpx<T>* __restrict__ tw) {
+  constexpr int nb = L / R;
+  constexpr int G = NT / nb >= 1 ? NT / nb : 1;
+  constexpr int tws = L / (Ns * R);
+  for (int w = threadIdx.x; w < nb * G; w += blockDim.x) {
+    const int g = w / nb;
+    const int j = w - g * nb;
+    const int q = j / Ns;
+    const int k = j - q * Ns;
+    cpx<T> wv[R];
+    if constexpr (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const int id = r * k * tws;
+        if constexpr (HALF) {
+          const bool hi = id >= L / 2;
+          const cpx<T> x = tw[hi ? id - L / 2 : id];
+          wv[r] = hi ? mk(-x.x, -x.y) : x;
+        } else {
+          wv[r] = tw[id];
+        }
+      }
+    }
+    const cpx<T>* s0 = a + j;
+    cpx<T>* d0 = b + q * Ns * R + k;
+    for (int t = g; t < batch; t += G) {
+      const cpx<T>* s = s0 + t * L;
+      cpx<T>* d = d0 + t * L;
+      cpx<T> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = s[r * nb];
+      if constexpr (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = INV ? cmulc(v[r], wv[r]) : cmul(v[r], wv[r]);
+      }
+      dft<T, R, INV>(v);
+#pragma unroll
+      for (int r = 0; r < R; ++r) d[r * Ns] = v[r];
+    }
+  }
+}
+
+template <typename T, int L, int NT, bool INV, bool HALF, int P, int Ns>
+__device__ __forceinline__ cpx<T>* fft_ct_from(cpx<T>* a, cpx<T>* b, int batch, const cpx<T>* __restrict__ tw) {
+  constexpr CPlan pl = make_cplan(L);
+  if constexpr (P == pl.np) {
+    return a;
+  } else {
+    constexpr int R = pl.r[P];
+    stockham_ct<T, L, NT, R, Ns, INV, HALF>(a, b, batch, tw);
+    __syncthreads();
+    return fft_ct_from<T, L, NT, INV, HALF, P + 1, Ns * R>(b, a, batch, tw);
+  }
+}
+
+// Lengths with compiled plans (film x and y transforms of the workloads).
+__host__ __device__ constexpr bool has_cplan(int L) {
+  return L == 270 || L == 525 || L == 135 || L == 140 || L == 72;
+}
+
 // Batched in-LDS FFT of `batch` transforms of length P.L, transform t at
 // a + t*stride.  Ping-pongs between a and b; returns the buffer holding the
 // result.  Unnormalised.  Must be entered by the whole block after the data
 // are in place and visible (a __syncthreads() before the call); ends with
 // a __syncthreads().
 template <typename T, bool INV>
-__device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, const FftPlan& P, int batch, int stride,
-                           const cpx<T>* __restrict__ tw, int twh = 0) {
+__device__ cpx<T>* fft_lds_generic(cpx<T>* a, cpx<T>* b, const FftPlan& P, int batch, int stride,
+                                   const cpx<T>* __restrict__ tw, int twh) {
   const int L = P.L;
   int Ns = 1;
   for (int p = 0; p < P.np; ++p) {
@@ -248,6 +363,34 @@ __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, const FftPlan& P, int batch, in
     Ns *= R;
   }
   return a;
+}
+
+// Dispatch: compiled plan for contiguous transforms of a known length (NT =
+// the launch's block size the thread mapping is tuned for), else the generic
+// runtime-plan passes.
+template <typename T, bool INV, int NT = 256>
+__device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, const FftPlan& P, int batch, int stride,
+                           const cpx<T>* __restrict__ tw, int twh = 0) {
+  if (stride == P.L) {
+    if (twh == 0) {
+      switch (P.L) {
+        case 270: return fft_ct_from<T, 270, NT, INV, false, 0, 1>(a, b, batch, tw);
+        case 525: return fft_ct_from<T, 525, NT, INV, false, 0, 1>(a, b, batch, tw);
+        case 135: return fft_ct_from<T, 135, NT, INV, false, 0, 1>(a, b, batch, tw);
+        case 140: return fft_ct_from<T, 140, NT, INV, false, 0, 1>(a, b, batch, tw);
+        case 72: return fft_ct_from<T, 72, NT, INV, false, 0, 1>(a, b, batch, tw);
+        default: break;
+      }
+    } else if (twh * 2 == P.L) {
+      switch (P.L) {
+        case 270: return fft_ct_from<T, 270, NT, INV, true, 0, 1>(a, b, batch, tw);
+        case 140: return fft_ct_from<T, 140, NT, INV, true, 0, 1>(a, b, batch, tw);
+        case 72: return fft_ct_from<T, 72, NT, INV, true, 0, 1>(a, b, batch, tw);
+        default: break;
+      }
+    }
+  }
+  return fft_lds_generic<T, INV>(a, b, P, batch, stride, tw, twh);
 }
 
 }  // namespace mmv

@@ -138,38 +138,56 @@ __device__ __forceinline__ void col_body(int blk, const cpx<T>* __restrict__ spe
   for (int t = threadIdx.x; t < Lh; t += blockDim.x) stw[t] = twy[t];
   const int nload = nin_ch * Ly;
   const float invLy = 1.0f / (float)Ly;
-  for (int t = threadIdx.x; t < nload; t += blockDim.x) {
+  stage_copy<4>(A, nload, [&](int t) {
     const int ch = fdiv(t, invLy);
     const int y = t - ch * Ly;
-    A[t] = (y < ny) ? spec1[((size_t)ch * ny + y) * Kx + kx] : mk<T>(0, 0);
-  }
+    return (y < ny) ? spec1[((size_t)ch * ny + y) * Kx + kx] : mk<T>(0, 0);
+  });
   __syncthreads();
   const int twh = (Ly & 1) ? 0 : Lh;
   cpx<T>* X = fft_lds<T, false>(A, B, P, nin_ch, Ly, stw, twh);
   cpx<T>* W = (X == A) ? B : A;
   const int nprod = no * Ly;
-  for (int t = threadIdx.x; t < nprod; t += blockDim.x) {
-    const int o = fdiv(t, invLy);
-    const int ky = t - o * Ly;
-    const bool upper = ky >= Kyh;
-    const int kyr = upper ? Ly - ky : ky;
-    const int src = s_src[o];
-    cpx<T> acc = mk<T>(0, 0);
+  // kernel values of U elements are fetched before any is used
+  constexpr int U = 4;
+  for (int t0 = threadIdx.x; t0 < nprod; t0 += U * (int)blockDim.x) {
+    T kv[U][3];
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const int ko = s_koff[o][b];
-      if (ko < 0) continue;
-      const int fl = s_fl[o][b];
-      T s = kern[ko + kyr];
-      const bool neg = ((fl & 4) != 0) != (upper && (fl & 2));
-      if (neg) s = -s;
-      const cpx<T> mh = X[(src * 3 + b) * Ly + ky];
-      if (fl & 1)
-        acc = acc + mk<T>(-s * mh.y, s * mh.x);
-      else
-        acc = acc + mk<T>(s * mh.x, s * mh.y);
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * (int)blockDim.x;
+      const int o = fdiv(t, invLy);
+      const int ky = t - o * Ly;
+      const int kyr = ky >= Kyh ? Ly - ky : ky;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const int ko = t < nprod ? s_koff[o][b] : -1;
+        kv[u][b] = ko < 0 ? T(0) : kern[ko + kyr];
+      }
     }
-    W[t] = acc;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * (int)blockDim.x;
+      if (t >= nprod) break;
+      const int o = fdiv(t, invLy);
+      const int ky = t - o * Ly;
+      const bool upper = ky >= Kyh;
+      const int src = s_src[o];
+      cpx<T> acc = mk<T>(0, 0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if (s_koff[o][b] < 0) continue;
+        const int fl = s_fl[o][b];
+        T s = kv[u][b];
+        const bool neg = ((fl & 4) != 0) != (upper && (fl & 2));
+        if (neg) s = -s;
+        const cpx<T> mh = X[(src * 3 + b) * Ly + ky];
+        if (fl & 1)
+          acc = acc + mk<T>(-s * mh.y, s * mh.x);
+        else
+          acc = acc + mk<T>(s * mh.x, s * mh.y);
+      }
+      W[t] = acc;
+    }
   }
   __syncthreads();
   cpx<T>* Y = fft_lds<T, true>(W, X, P, no, Ly, stw, twh);
@@ -231,6 +249,8 @@ __global__ void __launch_bounds__(256) k_col_batch(const ColDesc* __restrict__ d
 }
 
 // ------------------------------------------------------------ row kernel
+constexpr int ROW_THREADS = 512;
+
 template <typename T> struct FirHalf { static constexpr int K = 16; };
 template <> struct FirHalf<double> { static constexpr int K = 30; };
 
@@ -260,19 +280,19 @@ __device__ cpx<T>* c2r_rows(const cpx<T>* const* rowp, int nb, cpx<T>* fa, cpx<T
                             const FftPlan& P, const cpx<T>* stw, const cpx<T>* stp) {
   const int tot = nb * N2x;
   const float inv = 1.0f / (float)N2x;
-  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+  stage_copy<4>(fa, tot, [&](int t) {
     const int b = fdiv(t, inv);
     const int k = t - b * N2x;
     const cpx<T>* X = rowp[b];
     cpx<T> xk = X[k];
     cpx<T> xm = X[N2x - k];
     xm.y = -xm.y;
-    cpx<T> s = xk + xm;
-    cpx<T> d = cmulc(xk - xm, stp[k]);
-    fa[b * N2x + k] = mk<T>(s.x - d.y, s.y + d.x);
-  }
+    const cpx<T> s = xk + xm;
+    const cpx<T> d = cmulc(xk - xm, stp[k]);
+    return mk<T>(s.x - d.y, s.y + d.x);
+  });
   __syncthreads();
-  return fft_lds<T, true>(fa, fb, P, nb, N2x, stw);
+  return fft_lds<T, true, ROW_THREADS>(fa, fb, P, nb, N2x, stw);
 }
 
 // Copy the spline window of one real row into ext[E + k], k in [-E, M+E),
@@ -536,10 +556,19 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
       if (kind < RK_CROSS) {
         if (k < nx) H[kind * nx + k] = row[k];
       } else {
-        const int w = reflect_idx(k - E, M);
+        // mirror only the 2E samples outside the window; the lattice index
+        // then lies within one period of [0, Lx)
+        int w = k - E;
+        if (w < 0 || w >= M) w = reflect_idx(w, M);
         int X = ((kind < RK_FP || kind >= RK_PHI) ? W0c : W0f) + w;
-        X %= Lx;
-        if (X < 0) X += Lx;
+        if (X < 0)
+          X += Lx;
+        else if (X >= Lx)
+          X -= Lx;
+        if (X < 0 || X >= Lx) {
+          X %= Lx;
+          if (X < 0) X += Lx;
+        }
         ext[(size_t)r * MW + k] = row[X];
       }
     }
@@ -748,7 +777,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   if (fuse) {
     // forward real transform of the three rows (as the x pass computes it)
     __syncthreads();
-    const cpx<T>* Z = fft_lds<T, false>(fa, fb, p.px, 3, N2x, stw);
+    const cpx<T>* Z = fft_lds<T, false, ROW_THREADS>(fa, fb, p.px, 3, N2x, stw);
     cpx<T>* dst = reinterpret_cast<cpx<T>*>(p.spec1_out);
     const int K1 = N2x + 1;
     for (int t = threadIdx.x; t < 3 * K1; t += blockDim.x) {
@@ -989,8 +1018,6 @@ hipError_t launch_tick_batch(const ColDesc* d, int n, int stage, double dt, hipS
   hipLaunchKernelGGL(k_tick_batch, dim3(n), dim3(256), 0, st, d, stage, dt);
   return hipGetLastError();
 }
-
-constexpr int ROW_THREADS = 512;
 
 template <typename T>
 size_t row_lds_bytes(const RowParams& p) {

@@ -61,6 +61,24 @@ def test_stickslip_fp32_fields_full_size(x_cells):
 
 
 @pytest.mark.parametrize("prec", [32, 64])
+@pytest.mark.parametrize("shape", [(60, 64), (128, 128), (256, 256)])
+def test_compiled_fft_lengths(prec, shape):
+    # transform lengths with compile-time plans (radices 5 6 9 / 6 3 4 / 5 9 3 /
+    # 7 5 4 / 7 5 5 3): x 144, 280, 540 (half lengths 72, 140, 270), y 135,
+    # 270, 525 -- odd, half-table and full-table twiddle variants
+    import paper_1801_04181_amd as mmv
+    nx, ny = shape
+    cfg = get_config("stickslip")
+    d = cfg["desc"].replace(nx=nx, ny=ny, precision=prec)
+    h = mmv.init_mesh(d)
+    lx, ly, _ = mmv.get_fft_lengths(h)
+    mmv.destroy_mesh(h)
+    assert (lx // 2, ly) in {(72, 135), (140, 270), (270, 525)}
+    print("compiled lengths", nx, ny, lx, ly, prec, flush=True)
+    check_fields(d, cfg["drive"], initial_state(dict(cfg, desc=d)), x_cells=1.37)
+
+
+@pytest.mark.parametrize("prec", [32, 64])
 @pytest.mark.parametrize("shape", [(37, 23), (5, 1), (1, 6), (70, 3)])
 def test_ragged_shapes(prec, shape):
     nx, ny = shape
