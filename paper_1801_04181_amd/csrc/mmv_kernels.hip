@@ -452,7 +452,39 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   // twiddles: stw (N2x) and stp (N2x + 1) are contiguous
   stage_copy<4>(stw, 2 * N2x + 1, [&](int t) { return t < N2x ? tw[t] : twp[t - N2x]; });
   for (int t = threadIdx.x; t < 3 * nx; t += blockDim.x) H[t] = T(0);
-  if (threadIdx.x == 0) {
+  if (!(need_cross && p.pot)) {
+    // direct mode: the row table in closed form, one entry per thread
+    const int n_self = (cell_row && (p.term_mask & 8)) ? 3 : 0;
+    const int n_cross = need_cross ? ((cell_row || p.full_force) ? 3 : 1) : 0;
+    const int n_frc = (need_force && cell_row) ? 2 * nfc : 0;
+    const int n_tot = n_self + n_cross + n_frc + (xb_lo ? 1 : 0) + (xb_hi ? 1 : 0);
+    for (int i = threadIdx.x; i < n_tot; i += blockDim.x) {
+      const cpx<T>* r;
+      int kind;
+      if (i < n_self) {
+        r = spec2 + p.off_self[film][i] + (size_t)y * p.Kx;
+        kind = RK_SELF + i;
+      } else if (i < n_self + n_cross) {
+        const int c = i - n_self;
+        r = spec2 + p.off_cross[film][c] + (size_t)(y - p.cross_row0[film]) * p.Kx;
+        kind = RK_CROSS + c;
+      } else if (i < n_self + n_cross + n_frc) {
+        const int j = i - n_self - n_cross, c = j >> 1;
+        r = spec2 + ((j & 1) ? p.off_fm[c] : p.off_fp[c]) + (size_t)y * p.Kx;
+        kind = ((j & 1) ? RK_FM : RK_FP) + c;
+      } else {
+        const bool lo = xb_lo && i == n_self + n_cross + n_frc;
+        r = spec2 + p.off_cross[1][0] + (size_t)((lo ? -1 : ny) - p.cross_row0[1]) * p.Kx;
+        kind = RK_XB + (lo ? 0 : 1);
+      }
+      rowp[i] = r;
+      rowkind[i] = kind;
+    }
+    if (threadIdx.x == 0) {
+      s_bad = 0;
+      s_nrow = n_tot;
+    }
+  } else if (threadIdx.x == 0) {
     s_bad = 0;
     int n = 0;
     if (cell_row && (p.term_mask & 8))
@@ -527,11 +559,16 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     const double fr = tq < NQ ? frs : frb;
     const double z1 = -0.26794919243112270647;  // sqrt(3) - 2, pole of the cubic B-spline prefilter
     double g = 0.0;
+#pragma unroll
     for (int t = -1; t <= 2; ++t) {
       const int j = t - q;
       if (j >= -K && j <= K) {
-        double zp = 1.0;  // z1^|j|
-        for (int a = 0; a < abs(j); ++a) zp *= z1;
+        // z1^|j| by binary exponentiation (|j| <= K)
+        double zp = 1.0, b = z1;
+        for (int e = abs(j); e; e >>= 1) {
+          if (e & 1) zp *= b;
+          b *= b;
+        }
         g += beta3(fr - t) * 1.7320508075688772935 * zp;
       }
     }
