@@ -249,7 +249,11 @@ __global__ void __launch_bounds__(256) k_col_batch(const ColDesc* __restrict__ d
 }
 
 // ------------------------------------------------------------ row kernel
-constexpr int ROW_THREADS = 512;
+// Threads per row block: 1024 for the float32 single-mesh kernel (four
+// waves per SIMD at its register count), 512 where more registers are needed
+// (float64, batched descriptors).
+template <typename T, bool BATCH>
+struct RowThreads { static constexpr int n = (sizeof(T) == 4 && !BATCH) ? 1024 : 512; };
 
 template <typename T> struct FirHalf { static constexpr int K = 16; };
 template <> struct FirHalf<double> { static constexpr int K = 30; };
@@ -275,7 +279,7 @@ __device__ __forceinline__ double beta3(double t) {
 // Inverse real transform of nb rows (Hermitian halves X[0..N2x] at rowp[b])
 // into LDS; result buffer viewed as T* holds x[0..Lx) of each row at stride
 // 2*N2x reals.
-template <typename T>
+template <typename T, int NT>
 __device__ cpx<T>* c2r_rows(const cpx<T>* const* rowp, int nb, cpx<T>* fa, cpx<T>* fb, int N2x,
                             const FftPlan& P, const cpx<T>* stw, const cpx<T>* stp) {
   const int tot = nb * N2x;
@@ -292,7 +296,7 @@ __device__ cpx<T>* c2r_rows(const cpx<T>* const* rowp, int nb, cpx<T>* fa, cpx<T
     return mk<T>(s.x - d.y, s.y + d.x);
   });
   __syncthreads();
-  return fft_lds<T, true, ROW_THREADS>(fa, fb, P, nb, N2x, stw);
+  return fft_lds<T, true, NT>(fa, fb, P, nb, N2x, stw);
 }
 
 // Copy the spline window of one real row into ext[E + k], k in [-E, M+E),
@@ -381,7 +385,7 @@ constexpr int MAX_ROWS = 24;
 // rows 0 and ny-1, one more inverse transform each, so that a stage
 // launches exactly nfilm * ny blocks.  All inverse row transforms of a task run as one batch (or
 // batches of p.nbr rows); every spline window is filtered in parallel.
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, double dt, int task, int ntask,
                                                const cpx<T>* __restrict__ spec2, const T* __restrict__ mst,
                                                const T* m0, T* mnext, T* __restrict__ acc, T* __restrict__ hout,
@@ -581,7 +585,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
 
   for (int b0 = 0; b0 < nrow; b0 += nbr) {
     const int bn = min(nbr, nrow - b0);
-    cpx<T>* Z = c2r_rows<T>(rowp + b0, bn, fa, fb, N2x, p.px, stw, stp);
+    cpx<T>* Z = c2r_rows<T, NT>(rowp + b0, bn, fa, fb, N2x, p.px, stw, stp);
     const T* xr = reinterpret_cast<const T*>(Z);
     // self rows -> H, spline rows -> windows with mirror extension
     const float invMW = 1.0f / (float)MW;
@@ -814,7 +818,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   if (fuse) {
     // forward real transform of the three rows (as the x pass computes it)
     __syncthreads();
-    const cpx<T>* Z = fft_lds<T, false, ROW_THREADS>(fa, fb, p.px, 3, N2x, stw);
+    const cpx<T>* Z = fft_lds<T, false, NT>(fa, fb, p.px, 3, N2x, stw);
     cpx<T>* dst = reinterpret_cast<cpx<T>*>(p.spec1_out);
     const int K1 = N2x + 1;
     for (int t = threadIdx.x; t < 3 * K1; t += blockDim.x) {
@@ -918,21 +922,21 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
 }
 
 template <typename T>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__((RowThreads<T, false>::n))
     k_row_stage(RowParams p, const cpx<T>* __restrict__ spec2, const T* __restrict__ mst, const T* m0, T* mnext,
                 T* __restrict__ acc, T* __restrict__ hout, const cpx<T>* __restrict__ tw,
                 const cpx<T>* __restrict__ twp, RigidState* __restrict__ rigid, double* __restrict__ partial,
                 unsigned int* __restrict__ counter) {
-  row_stage_body<T>(p, p.stage, p.dt, blockIdx.x, gridDim.x, spec2, mst, m0, mnext, acc, hout, tw, twp, rigid,
+  row_stage_body<T, RowThreads<T, false>::n>(p, p.stage, p.dt, blockIdx.x, gridDim.x, spec2, mst, m0, mnext, acc, hout, tw, twp, rigid,
                     partial, counter);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(512) k_row_stage_batch(const RowStageDesc* __restrict__ d,
+__global__ void __launch_bounds__((RowThreads<T, true>::n)) k_row_stage_batch(const RowStageDesc* __restrict__ d,
                                                          const int* __restrict__ start, int n, int stage, double dt) {
   const int i = find_instance(start, n, blockIdx.x);
   const RowStageDesc& q = d[i];
-  row_stage_body<T>(q.p, stage, dt, blockIdx.x - start[i], start[i + 1] - start[i], (const cpx<T>*)q.spec2,
+  row_stage_body<T, RowThreads<T, true>::n>(q.p, stage, dt, blockIdx.x - start[i], start[i + 1] - start[i], (const cpx<T>*)q.spec2,
                     (const T*)q.mst, (const T*)q.m0, (T*)q.mnext, (T*)q.acc, nullptr, (const cpx<T>*)q.tw,
                     (const cpx<T>*)q.twp, q.rigid, q.partial, q.counter);
 }
@@ -1078,7 +1082,7 @@ hipError_t launch_row_stage(const RowParams& p, const void* spec2, const T* mst,
     hipError_t e = hipFuncSetAttribute((const void*)k_row_stage<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_row_stage<T>, dim3(p.ntask), dim3(ROW_THREADS), lds, st, p, (const cpx<T>*)spec2, mst, m0,
+  hipLaunchKernelGGL(k_row_stage<T>, dim3(p.ntask), dim3(RowThreads<T, false>::n), lds, st, p, (const cpx<T>*)spec2, mst, m0,
                      mnext, acc, hout, (const cpx<T>*)tw, (const cpx<T>*)twp, rigid, partial, counter);
   return hipGetLastError();
 }
@@ -1099,7 +1103,7 @@ hipError_t launch_col_batch(const ColDesc* d, const int* start, int n, int nblk,
 template <typename T>
 hipError_t launch_row_stage_batch(const RowStageDesc* d, const int* start, int n, int nblk, size_t lds, int stage,
                                   double dt, hipStream_t st) {
-  hipLaunchKernelGGL(k_row_stage_batch<T>, dim3(nblk), dim3(ROW_THREADS), lds, st, d, start, n, stage, dt);
+  hipLaunchKernelGGL(k_row_stage_batch<T>, dim3(nblk), dim3(RowThreads<T, true>::n), lds, st, d, start, n, stage, dt);
   return hipGetLastError();
 }
 
