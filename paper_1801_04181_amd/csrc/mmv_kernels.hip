@@ -27,11 +27,14 @@ namespace mmv {
 
 // ------------------------------------------------------------ x transform
 // Rows handled by one block of the x pass: `nb` rows at `row0`, `rstride`
-// rows apart (the three components of one film row, or one row).
+// rows apart (the three components of one film row, or one row).  Output
+// layout: tny == 0, row-major [row][Kx]; tny > 0 (film spectra), column-major
+// [row / tny][Kx][row % tny], so the y pass reads each column contiguously.
 template <typename T>
 __device__ __forceinline__ void row_fwd_body(int row0, int nb, int rstride, const T* __restrict__ src,
                                              cpx<T>* __restrict__ dst, int nin, int N2x, int Kx, const FftPlan& P,
-                                             const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp) {
+                                             const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp,
+                                             int tny = 0) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* stp = stw + N2x;
@@ -60,7 +63,9 @@ __device__ __forceinline__ void row_fwd_body(int row0, int nb, int rstride, cons
     zm.y = -zm.y;
     cpx<T> e = zk + zm;
     cpx<T> p = cmul(stp[k], zk - zm);
-    dst[(size_t)(row0 + r * rstride) * Kx + k] = mk<T>(T(0.5) * (e.x + p.y), T(0.5) * (e.y - p.x));
+    const int row = row0 + r * rstride;
+    const size_t o = tny > 0 ? ((size_t)(row / tny) * Kx + k) * tny + (row % tny) : (size_t)row * Kx + k;
+    dst[o] = mk<T>(T(0.5) * (e.x + p.y), T(0.5) * (e.y - p.x));
   }
 }
 
@@ -71,9 +76,11 @@ __global__ void __launch_bounds__(256)
     k_row_fwd(const T* __restrict__ src, cpx<T>* __restrict__ dst, int nrows, int nin, int N2x,
               int Kx, FftPlan P, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp, int ny3) {
   if (ny3 > 0) {
-    // rows are [film][comp][y]; block = (film, y)
-    const int f = blockIdx.x / ny3, y = blockIdx.x - f * ny3;
-    row_fwd_body<T>(f * 3 * ny3 + y, 3, ny3, src, dst, nin, N2x, Kx, P, tw, twp);
+    // rows are [film][comp][y]; block = (film, y), XCD-contiguous in y so the
+    // column-major writes of neighbouring rows meet in one L2
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int f = b / ny3, y = b - f * ny3;
+    row_fwd_body<T>(f * 3 * ny3 + y, 3, ny3, src, dst, nin, N2x, Kx, P, tw, twp, ny3);
   } else {
     if ((int)blockIdx.x >= nrows) return;
     row_fwd_body<T>(blockIdx.x, 1, 0, src, dst, nin, N2x, Kx, P, tw, twp);
@@ -93,12 +100,13 @@ __device__ __forceinline__ int find_instance(const int* __restrict__ start, int 
 template <typename T>
 __global__ void __launch_bounds__(256) k_row_fwd_batch(const RowFwdDesc* __restrict__ d, const int* __restrict__ start,
                                                        int n) {
-  const int i = find_instance(start, n, blockIdx.x);
+  const int bl = xcd_remap(blockIdx.x, gridDim.x);
+  const int i = find_instance(start, n, bl);
   const RowFwdDesc& q = d[i];
-  const int b = blockIdx.x - start[i];
+  const int b = bl - start[i];
   const int f = b / q.ny, y = b - f * q.ny;
   row_fwd_body<T>(f * 3 * q.ny + y, 3, q.ny, (const T*)q.src, (cpx<T>*)q.dst, q.nin, q.N2x, q.Kx, q.P,
-                  (const cpx<T>*)q.tw, (const cpx<T>*)q.twp);
+                  (const cpx<T>*)q.tw, (const cpx<T>*)q.twp, q.ny);
 }
 
 // ------------------------------------------------------------ y pass
@@ -141,7 +149,7 @@ __device__ __forceinline__ void col_body(int blk, const cpx<T>* __restrict__ spe
   stage_copy<4>(A, nload, [&](int t) {
     const int ch = fdiv(t, invLy);
     const int y = t - ch * Ly;
-    return (y < ny) ? spec1[((size_t)ch * ny + y) * Kx + kx] : mk<T>(0, 0);
+    return (y < ny) ? spec1[((size_t)ch * Kx + kx) * ny + y] : mk<T>(0, 0);
   });
   __syncthreads();
   const int twh = (Ly & 1) ? 0 : Lh;
@@ -830,7 +838,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
       zm.y = -zm.y;
       const cpx<T> e = zk + zm;
       const cpx<T> q = cmul(stp[k], zk - zm);
-      dst[((size_t)(film * 3 + r) * ny + y) * p.Kx + k] = mk<T>(T(0.5) * (e.x + q.y), T(0.5) * (e.y - q.x));
+      dst[((size_t)(film * 3 + r) * p.Kx + k) * ny + y] = mk<T>(T(0.5) * (e.x + q.y), T(0.5) * (e.y - q.x));
     }
   }
   if (need_force) {
@@ -927,16 +935,19 @@ __global__ void __launch_bounds__((RowThreads<T, false>::n))
                 T* __restrict__ acc, T* __restrict__ hout, const cpx<T>* __restrict__ tw,
                 const cpx<T>* __restrict__ twp, RigidState* __restrict__ rigid, double* __restrict__ partial,
                 unsigned int* __restrict__ counter) {
-  row_stage_body<T, RowThreads<T, false>::n>(p, p.stage, p.dt, blockIdx.x, gridDim.x, spec2, mst, m0, mnext, acc, hout, tw, twp, rigid,
+  // XCD-contiguous tasks: the column-major spectrum writes of neighbouring
+  // rows meet in one L2
+  row_stage_body<T, RowThreads<T, false>::n>(p, p.stage, p.dt, xcd_remap(blockIdx.x, gridDim.x), gridDim.x, spec2, mst, m0, mnext, acc, hout, tw, twp, rigid,
                     partial, counter);
 }
 
 template <typename T>
 __global__ void __launch_bounds__((RowThreads<T, true>::n)) k_row_stage_batch(const RowStageDesc* __restrict__ d,
                                                          const int* __restrict__ start, int n, int stage, double dt) {
-  const int i = find_instance(start, n, blockIdx.x);
+  const int bl = xcd_remap(blockIdx.x, gridDim.x);
+  const int i = find_instance(start, n, bl);
   const RowStageDesc& q = d[i];
-  row_stage_body<T, RowThreads<T, true>::n>(q.p, stage, dt, blockIdx.x - start[i], start[i + 1] - start[i], (const cpx<T>*)q.spec2,
+  row_stage_body<T, RowThreads<T, true>::n>(q.p, stage, dt, bl - start[i], start[i + 1] - start[i], (const cpx<T>*)q.spec2,
                     (const T*)q.mst, (const T*)q.m0, (T*)q.mnext, (T*)q.acc, nullptr, (const cpx<T>*)q.tw,
                     (const cpx<T>*)q.twp, q.rigid, q.partial, q.counter);
 }
