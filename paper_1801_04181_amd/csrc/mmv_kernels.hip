@@ -155,47 +155,41 @@ __device__ __forceinline__ void col_body(int blk, const cpx<T>* __restrict__ spe
   const int twh = (Ly & 1) ? 0 : Lh;
   cpx<T>* X = fft_lds<T, false>(A, B, P, nin_ch, Ly, stw, twh);
   cpx<T>* W = (X == A) ? B : A;
-  const int nprod = no * Ly;
-  // kernel values of U elements are fetched before any is used
-  constexpr int U = 4;
-  for (int t0 = threadIdx.x; t0 < nprod; t0 += U * (int)blockDim.x) {
-    T kv[U][3];
+  // one thread per (output, |ky|): the kernel value at |ky| (the stored half)
+  // serves both ky and Ly - ky
+  const int npair = no * Kyh;
+  const float invK = 1.0f / (float)Kyh;
+  for (int t = threadIdx.x; t < npair; t += blockDim.x) {
+    const int o = fdiv(t, invK);
+    const int kyr = t - o * Kyh;
+    const int ky2 = Ly - kyr;
+    const bool two = kyr > 0 && ky2 > kyr;
+    const int src = s_src[o];
+    cpx<T> a1 = mk<T>(0, 0), a2 = mk<T>(0, 0);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int t = t0 + u * (int)blockDim.x;
-      const int o = fdiv(t, invLy);
-      const int ky = t - o * Ly;
-      const int kyr = ky >= Kyh ? Ly - ky : ky;
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const int ko = t < nprod ? s_koff[o][b] : -1;
-        kv[u][b] = ko < 0 ? T(0) : kern[ko + kyr];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int t = t0 + u * (int)blockDim.x;
-      if (t >= nprod) break;
-      const int o = fdiv(t, invLy);
-      const int ky = t - o * Ly;
-      const bool upper = ky >= Kyh;
-      const int src = s_src[o];
-      cpx<T> acc = mk<T>(0, 0);
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        if (s_koff[o][b] < 0) continue;
-        const int fl = s_fl[o][b];
-        T s = kv[u][b];
-        const bool neg = ((fl & 4) != 0) != (upper && (fl & 2));
-        if (neg) s = -s;
-        const cpx<T> mh = X[(src * 3 + b) * Ly + ky];
+    for (int b = 0; b < 3; ++b) {
+      const int ko = s_koff[o][b];
+      if (ko < 0) continue;
+      const int fl = s_fl[o][b];
+      const T s = kern[ko + kyr];
+      const T s1 = (fl & 4) ? -s : s;                                // ky <= Ly/2
+      const T s2 = (((fl & 4) != 0) != ((fl & 2) != 0)) ? -s : s;   // ky > Ly/2 (odd in ky)
+      const cpx<T>* xb = X + (src * 3 + b) * Ly;
+      const cpx<T> m1 = xb[kyr];
+      if (fl & 1)
+        a1 = a1 + mk<T>(-s1 * m1.y, s1 * m1.x);
+      else
+        a1 = a1 + mk<T>(s1 * m1.x, s1 * m1.y);
+      if (two) {
+        const cpx<T> m2 = xb[ky2];
         if (fl & 1)
-          acc = acc + mk<T>(-s * mh.y, s * mh.x);
+          a2 = a2 + mk<T>(-s2 * m2.y, s2 * m2.x);
         else
-          acc = acc + mk<T>(s * mh.x, s * mh.y);
+          a2 = a2 + mk<T>(s2 * m2.x, s2 * m2.y);
       }
-      W[t] = acc;
     }
+    W[o * Ly + kyr] = a1;
+    if (two) W[o * Ly + ky2] = a2;
   }
   __syncthreads();
   cpx<T>* Y = fft_lds<T, true>(W, X, P, no, Ly, stw, twh);
