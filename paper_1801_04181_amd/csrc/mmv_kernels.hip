@@ -449,6 +449,11 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   // boundary force rows carried by this task (direct mode, stage launches)
   const bool xb_lo = p.mode == MODE_STAGE && need_force && !p.pot && y == 0;
   const bool xb_hi = p.mode == MODE_STAGE && need_force && !p.pot && y == ny - 1;
+  // direct-mode stage launches: the force's z_s - 1 layer row of slider row y
+  // is transformed and filtered by the base-film task of row y, which adds
+  // that part of the z term (seven rows per task on both films)
+  const bool fm_split = p.mode == MODE_STAGE && p.with_force && !p.pot && two;
+  const bool fm_here = fm_split && film == 0 && cell_row;
   const int h = p.halo;
 
   // slider offset of this stage (issued first; the last block of the launch
@@ -462,7 +467,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     // direct mode: the row table in closed form, one entry per thread
     const int n_self = (cell_row && (p.term_mask & 8)) ? 3 : 0;
     const int n_cross = need_cross ? ((cell_row || p.full_force) ? 3 : 1) : 0;
-    const int n_frc = (need_force && cell_row) ? 2 * nfc : 0;
+    const int n_frc = (need_force && cell_row) ? (fm_split ? nfc : 2 * nfc) : (fm_here ? 1 : 0);
     const int n_tot = n_self + n_cross + n_frc + (xb_lo ? 1 : 0) + (xb_hi ? 1 : 0);
     for (int i = threadIdx.x; i < n_tot; i += blockDim.x) {
       const cpx<T>* r;
@@ -475,9 +480,18 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
         r = spec2 + p.off_cross[film][c] + (size_t)(y - p.cross_row0[film]) * p.Kx;
         kind = RK_CROSS + c;
       } else if (i < n_self + n_cross + n_frc) {
-        const int j = i - n_self - n_cross, c = j >> 1;
-        r = spec2 + ((j & 1) ? p.off_fm[c] : p.off_fp[c]) + (size_t)y * p.Kx;
-        kind = ((j & 1) ? RK_FM : RK_FP) + c;
+        const int j = i - n_self - n_cross;
+        if (fm_here) {
+          r = spec2 + p.off_fm[0] + (size_t)y * p.Kx;
+          kind = RK_FM;
+        } else if (fm_split) {
+          r = spec2 + p.off_fp[j] + (size_t)y * p.Kx;
+          kind = RK_FP + j;
+        } else {
+          const int c = j >> 1;
+          r = spec2 + ((j & 1) ? p.off_fm[c] : p.off_fp[c]) + (size_t)y * p.Kx;
+          kind = ((j & 1) ? RK_FM : RK_FP) + c;
+        }
       } else {
         const bool lo = xb_lo && i == n_self + n_cross + n_frc;
         r = spec2 + p.off_cross[1][0] + (size_t)((lo ? -1 : ny) - p.cross_row0[1]) * p.Kx;
@@ -852,7 +866,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
         double v = (double)ga[i + 1] * (myl - myh) * i2dy;
         if (cell_row) {
           v += mx * ((double)ga[i + 2] - (double)ga[i]) * i2dx;
-          v += mz * ((double)gp[a * nx + i] - (double)gm[a * nx + i]) * i2dz;
+          v += mz * ((double)gp[a * nx + i] - (fm_split ? 0.0 : (double)gm[a * nx + i])) * i2dz;
         }
         fpart[a] += v;
       }
@@ -860,6 +874,13 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
       if (xb_lo) fpart[0] -= (double)gxb[i] * (double)ms[plane + i] * i2dy;
       if (xb_hi) fpart[0] += (double)gxb[nx + i] * (double)ms[plane + (size_t)(ny - 1) * nx + i] * i2dy;
     }
+  }
+  if (fm_here) {
+    // the slider's m_z at row y times the base field's x component on the
+    // layer below it (the z_s - 1 half of the central difference)
+    const double i2dz = 1.0 / (2.0 * p.dz);
+    const T* mz1 = mst + (size_t)5 * plane + (size_t)y * nx;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) fpart[0] -= (double)mz1[i] * (double)gm[i] * i2dz;
   }
   if (bad) atomicOr(&s_bad, 1);
   // block reduction of the force partials, fixed order: within each wave,
