@@ -278,18 +278,19 @@ __device__ __forceinline__ double beta3(double t) {
   return 0.0;
 }
 
-// Inverse real transform of nb rows (Hermitian halves X[0..N2x] at rowp[b])
+// Inverse real transform of nb rows (Hermitian halves X[0..N2x] at base + rowo[b])
 // into LDS; result buffer viewed as T* holds x[0..Lx) of each row at stride
 // 2*N2x reals.
 template <typename T, int NT>
-__device__ cpx<T>* c2r_rows(const cpx<T>* const* rowp, int nb, cpx<T>* fa, cpx<T>* fb, int N2x,
+__device__ cpx<T>* c2r_rows(const cpx<T>* __restrict__ base, const long long* rowo, int nb, cpx<T>* fa, cpx<T>* fb,
+                            int N2x,
                             const FftPlan& P, const cpx<T>* stw, const cpx<T>* stp) {
   const int tot = nb * N2x;
   const float inv = 1.0f / (float)N2x;
   stage_copy<4>(fa, tot, [&](int t) {
     const int b = fdiv(t, inv);
     const int k = t - b * N2x;
-    const cpx<T>* X = rowp[b];
+    const cpx<T>* X = base + rowo[b];
     cpx<T> xk = X[k];
     cpx<T> xm = X[N2x - k];
     xm.y = -xm.y;
@@ -321,6 +322,27 @@ __device__ __forceinline__ T fir_eval(const T* ext, const T* g, int k0, int E) {
 #pragma unroll
   for (int q = 0; q < 2 * K + 4; ++q) acc += g[q] * p[q];
   return acc;
+}
+
+// Two consecutive spline values k0, k0+1 from one register window (same tap
+// order per output as fir_eval; neighbouring lanes read windows two samples
+// apart, which keeps the LDS reads free of bank conflicts).
+template <typename T, int K>
+__device__ __forceinline__ void fir_eval2(const T* ext, const T* g, int k0, int E, T& o0, T& o1) {
+  constexpr int NQ = 2 * K + 4;
+  const T* p = ext + E + k0 - K - 1;
+  T w[NQ + 1];
+#pragma unroll
+  for (int q = 0; q < NQ + 1; ++q) w[q] = p[q];
+  T a0 = 0, a1 = 0;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const T gq = g[q];
+    a0 += gq * w[q];
+    a1 += gq * w[q + 1];
+  }
+  o0 = a0;
+  o1 = a1;
 }
 
 __device__ void rigid_stage(RigidState* R, const DriveP& d, int stage, double F, double h,
@@ -400,13 +422,14 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nx = p.nx, ny = p.ny, N2x = p.N2x, M = p.M, Lx = 2 * N2x, nbr = p.nbr;
   const int MW = M + 2 * E;
+  const int MWS = MW + 4;  // row stride of the windows (slack for the paired FIR outputs)
   const int nfc = p.full_force ? 3 : 1;
   cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* stp = stw + N2x;
   cpx<T>* fa = stp + N2x + 1;
   cpx<T>* fb = fa + (size_t)nbr * N2x;
   T* ext = reinterpret_cast<T*>(fb + (size_t)nbr * N2x);  // [nbr][MW]
-  T* gs = ext + (size_t)nbr * MW;  // weights, slider samples base field
+  T* gs = ext + (size_t)nbr * MWS;  // weights, slider samples base field
   T* gb = gs + NQ;                 // weights, base samples slider field
   T* H = gb + NQ;                  // [3][nx] demag accumulation
   T* gc = H + 3 * nx;              // [3][nx+2] slider cross field at i = -1..nx
@@ -415,9 +438,10 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   T* phit = gm + nfc * nx;         // [nslot][nx+6] potential at i = -3..nx+2
   const int nslot_max = p.pot ? (p.full_force ? 19 : 9) : 0;
   T* gxb = phit + (size_t)nslot_max * (nx + 6);  // [2][nx] base field x at slider rows -1, ny
-  double* red = reinterpret_cast<double*>(gxb + 2 * nx + 2);
-  red = reinterpret_cast<double*>((reinterpret_cast<uintptr_t>(red) + 15) & ~uintptr_t(15));
-  __shared__ const cpx<T>* rowp[MAX_ROWS];
+  // (offset arithmetic from smem_raw keeps the LDS address space)
+  const size_t red_off = ((size_t)(reinterpret_cast<unsigned char*>(gxb + 2 * nx + 2) - smem_raw) + 15) & ~size_t(15);
+  double* red = reinterpret_cast<double*>(smem_raw + red_off);
+  __shared__ long long rowo[MAX_ROWS];  // element offsets of the rows in spec2
   __shared__ int rowkind[MAX_ROWS];
   __shared__ int slot_of[7][5];  // (layer d + 3, row offset + 2) -> slot, -1 if absent
   __shared__ int s_nrow;
@@ -470,34 +494,34 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     const int n_frc = (need_force && cell_row) ? (fm_split ? nfc : 2 * nfc) : (fm_here ? 1 : 0);
     const int n_tot = n_self + n_cross + n_frc + (xb_lo ? 1 : 0) + (xb_hi ? 1 : 0);
     for (int i = threadIdx.x; i < n_tot; i += blockDim.x) {
-      const cpx<T>* r;
+      long long r;
       int kind;
       if (i < n_self) {
-        r = spec2 + p.off_self[film][i] + (size_t)y * p.Kx;
+        r = p.off_self[film][i] + (size_t)y * p.Kx;
         kind = RK_SELF + i;
       } else if (i < n_self + n_cross) {
         const int c = i - n_self;
-        r = spec2 + p.off_cross[film][c] + (size_t)(y - p.cross_row0[film]) * p.Kx;
+        r = p.off_cross[film][c] + (size_t)(y - p.cross_row0[film]) * p.Kx;
         kind = RK_CROSS + c;
       } else if (i < n_self + n_cross + n_frc) {
         const int j = i - n_self - n_cross;
         if (fm_here) {
-          r = spec2 + p.off_fm[0] + (size_t)y * p.Kx;
+          r = p.off_fm[0] + (size_t)y * p.Kx;
           kind = RK_FM;
         } else if (fm_split) {
-          r = spec2 + p.off_fp[j] + (size_t)y * p.Kx;
+          r = p.off_fp[j] + (size_t)y * p.Kx;
           kind = RK_FP + j;
         } else {
           const int c = j >> 1;
-          r = spec2 + ((j & 1) ? p.off_fm[c] : p.off_fp[c]) + (size_t)y * p.Kx;
+          r = ((j & 1) ? p.off_fm[c] : p.off_fp[c]) + (size_t)y * p.Kx;
           kind = ((j & 1) ? RK_FM : RK_FP) + c;
         }
       } else {
         const bool lo = xb_lo && i == n_self + n_cross + n_frc;
-        r = spec2 + p.off_cross[1][0] + (size_t)((lo ? -1 : ny) - p.cross_row0[1]) * p.Kx;
+        r = p.off_cross[1][0] + (size_t)((lo ? -1 : ny) - p.cross_row0[1]) * p.Kx;
         kind = RK_XB + (lo ? 0 : 1);
       }
-      rowp[i] = r;
+      rowo[i] = r;
       rowkind[i] = kind;
     }
     if (threadIdx.x == 0) {
@@ -509,7 +533,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     int n = 0;
     if (cell_row && (p.term_mask & 8))
       for (int c = 0; c < 3; ++c) {
-        rowp[n] = spec2 + p.off_self[film][c] + (size_t)y * p.Kx;
+        rowo[n] = p.off_self[film][c] + (size_t)y * p.Kx;
         rowkind[n++] = RK_SELF + c;
       }
     for (int a = 0; a < 7; ++a)
@@ -519,7 +543,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
       int ns = 0;
       auto add = [&](int d, int r) {
         slot_of[d + 3][r + 2] = ns;
-        rowp[n] = spec2 + p.off_phi[film][d + 3] + (size_t)(y + r - p.phi_row0[film][d + 3]) * p.Kx;
+        rowo[n] = p.off_phi[film][d + 3] + (size_t)(y + r - p.phi_row0[film][d + 3]) * p.Kx;
         rowkind[n++] = RK_PHI + ns;
         ++ns;
       };
@@ -546,23 +570,23 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
       const int ncomp = (cell_row || p.full_force) ? 3 : 1;
       const int stored = y - p.cross_row0[film];
       for (int c = 0; c < ncomp; ++c) {
-        rowp[n] = spec2 + p.off_cross[film][c] + (size_t)stored * p.Kx;
+        rowo[n] = p.off_cross[film][c] + (size_t)stored * p.Kx;
         rowkind[n++] = RK_CROSS + c;
       }
     }
     if (need_force && cell_row && !p.pot)
       for (int c = 0; c < nfc; ++c) {
-        rowp[n] = spec2 + p.off_fp[c] + (size_t)y * p.Kx;
+        rowo[n] = p.off_fp[c] + (size_t)y * p.Kx;
         rowkind[n++] = RK_FP + c;
-        rowp[n] = spec2 + p.off_fm[c] + (size_t)y * p.Kx;
+        rowo[n] = p.off_fm[c] + (size_t)y * p.Kx;
         rowkind[n++] = RK_FM + c;
       }
     if (xb_lo) {
-      rowp[n] = spec2 + p.off_cross[1][0] + (size_t)(-1 - p.cross_row0[1]) * p.Kx;
+      rowo[n] = p.off_cross[1][0] + (size_t)(-1 - p.cross_row0[1]) * p.Kx;
       rowkind[n++] = RK_XB;
     }
     if (xb_hi) {
-      rowp[n] = spec2 + p.off_cross[1][0] + (size_t)(ny - p.cross_row0[1]) * p.Kx;
+      rowo[n] = p.off_cross[1][0] + (size_t)(ny - p.cross_row0[1]) * p.Kx;
       rowkind[n++] = RK_XB + 1;
     }
     s_nrow = n;
@@ -601,7 +625,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
 
   for (int b0 = 0; b0 < nrow; b0 += nbr) {
     const int bn = min(nbr, nrow - b0);
-    cpx<T>* Z = c2r_rows<T, NT>(rowp + b0, bn, fa, fb, N2x, p.px, stw, stp);
+    cpx<T>* Z = c2r_rows<T, NT>(spec2, rowo + b0, bn, fa, fb, N2x, p.px, stw, stp);
     const T* xr = reinterpret_cast<const T*>(Z);
     // self rows -> H, spline rows -> windows with mirror extension
     const float invMW = 1.0f / (float)MW;
@@ -626,43 +650,49 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
           X %= Lx;
           if (X < 0) X += Lx;
         }
-        ext[(size_t)r * MW + k] = row[X];
+        ext[(size_t)r * MWS + k] = row[X];
       }
     }
     __syncthreads();
-    const int NP = nx + 6;
-    const float invNP = 1.0f / (float)NP;
-    for (int t = threadIdx.x; t < bn * NP; t += blockDim.x) {
-      const int r = fdiv(t, invNP);
-      const int i = t - r * NP - 3;  // -3 .. nx+2
+    const int NP = nx + 6;  // outputs i = -3 .. nx+2
+    const int NB2 = (NP + 1) >> 1;
+    const float invNB = 1.0f / (float)NB2;
+    for (int t = threadIdx.x; t < bn * NB2; t += blockDim.x) {
+      const int r = fdiv(t, invNB);
+      const int i0 = (t - r * NB2) * 2 - 3;
       const int kind = rowkind[b0 + r];
       if (kind < RK_CROSS) continue;
-      const T* e = ext + (size_t)r * MW;
-      if (kind >= RK_XB) {
-        if (i >= 0 && i < nx) gxb[(kind - RK_XB) * nx + i] = fir_eval<T, K>(e, gs, i + h + ifs, E);
-        continue;
-      }
-      if (kind >= RK_PHI) {
-        const T v = (film == 1) ? fir_eval<T, K>(e, gs, i + h + ifs, E) : fir_eval<T, K>(e, gb, i + h + ifb, E);
-        phit[(size_t)(kind - RK_PHI) * NP + i + 3] = v;
-        continue;
-      }
-      if (i < -1 || i > nx) continue;
-      if (kind < RK_FP) {
-        const int c = kind - RK_CROSS;
-        if (film == 1) {
-          const T v = fir_eval<T, K>(e, gs, i + h + ifs, E);
-          gc[c * (nx + 2) + i + 1] = v;
-          if (cell_row && i >= 0 && i < nx && (p.term_mask & 16)) H[c * nx + i] += v;
+      const T* e = ext + (size_t)r * MWS;
+      // the base film samples the slider's field (and potential) at -x_p
+      const bool base = film == 0 && (kind < RK_FP || (kind >= RK_PHI && kind < RK_XB));
+      T v[2];
+      if (base)
+        fir_eval2<T, K>(e, gb, i0 + h + ifb, E, v[0], v[1]);
+      else
+        fir_eval2<T, K>(e, gs, i0 + h + ifs, E, v[0], v[1]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int i = i0 + j;
+        if (i > nx + 2) continue;
+        if (kind >= RK_XB) {
+          if (i >= 0 && i < nx) gxb[(kind - RK_XB) * nx + i] = v[j];
+        } else if (kind >= RK_PHI) {
+          phit[(size_t)(kind - RK_PHI) * NP + i + 3] = v[j];
+        } else if (kind < RK_FP) {
+          if (i < -1 || i > nx) continue;
+          const int c = kind - RK_CROSS;
+          if (film == 1) {
+            gc[c * (nx + 2) + i + 1] = v[j];
+            if (cell_row && i >= 0 && i < nx && (p.term_mask & 16)) H[c * nx + i] += v[j];
+          } else if (i >= 0 && i < nx) {
+            H[c * nx + i] += v[j];
+          }
         } else if (i >= 0 && i < nx) {
-          H[c * nx + i] += fir_eval<T, K>(e, gb, i + h + ifb, E);
+          if (kind < RK_FM)
+            gp[(kind - RK_FP) * nx + i] = v[j];
+          else
+            gm[(kind - RK_FM) * nx + i] = v[j];
         }
-      } else if (i >= 0 && i < nx) {
-        const T v = fir_eval<T, K>(e, gs, i + h + ifs, E);
-        if (kind < RK_FM)
-          gp[(kind - RK_FP) * nx + i] = v;
-        else
-          gm[(kind - RK_FM) * nx + i] = v;
       }
     }
     __syncthreads();
@@ -1092,7 +1122,7 @@ size_t row_lds_bytes(const RowParams& p) {
   const int nfc = p.full_force ? 3 : 1;
   size_t b = sizeof(cpx<T>) * (size_t)(2 * p.N2x + 1 + 2 * (size_t)p.nbr * p.N2x);
   const int nslot = p.pot ? (p.full_force ? 19 : 9) : 0;
-  b += sizeof(T) * ((size_t)p.nbr * (p.M + 2 * E) + 2 * NQ + 3 * p.nx + 3 * (p.nx + 2) + 2 * nfc * p.nx +
+  b += sizeof(T) * ((size_t)p.nbr * (p.M + 2 * E + 4) + 2 * NQ + 3 * p.nx + 3 * (p.nx + 2) + 2 * nfc * p.nx +
                     (size_t)nslot * (p.nx + 6) + 2 * (size_t)p.nx + 2);
   b = (b + 15) & ~size_t(15);
   b += sizeof(double) * 96 + 16;  // wave partials of the force reduction
