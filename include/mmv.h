@@ -146,6 +146,13 @@ int get_state(mmv_handle h, double* t, double* x_s, double* v_s, long* step);
  * of timed launches since profile_begin, and stops timing.               */
 int profile_begin(mmv_handle h, int kernel);
 int profile_end(mmv_handle h, double* total_ms, long* launches);
+/* Diagnostics: launch `kernel` (as above) reps times back to back with the
+ * inputs of an RK stage, bracketed by one pair of HIP events on the handle's
+ * stream, and return the mean time per launch (blocks).  The launches
+ * overwrite the stage buffers, spectra and force partials: the mesh state is
+ * undefined afterwards (set m, offset and drive again before stepping).
+ * Two-film meshes that are not part of a batch (MMV_ESTATE otherwise).   */
+int profile_repeat(mmv_handle h, int kernel, int reps, double* avg_ms);
 
 /* Chosen FFT lengths (diagnostics). */
 int get_fft_lengths(mmv_handle h, int* lx, int* ly, int* lz);

@@ -12,7 +12,7 @@ import os
 __all__ = ["MMVError", "lib_path", "load", "MeshDesc", "DriveDesc", "init_mesh",
            "set_m", "get_m", "set_offset", "set_drive", "eval_heff", "llg_step",
            "stray_force", "get_state", "get_fft_lengths", "destroy_mesh",
-           "profile_begin", "profile_end", "init_batch", "batch_instance", "batch_step",
+           "profile_begin", "profile_end", "profile_repeat", "init_batch", "batch_instance", "batch_step",
            "batch_tuning", "destroy_batch", "Batch", "SurDesc", "sur_create", "sur_param_count",
            "sur_param_offsets", "sur_set_params", "sur_get_params", "sur_forward", "sur_gradient",
            "sur_train_step", "sur_gemm_bf16", "sur_destroy", "sur_attach", "sur_status", "Surrogate",
@@ -27,7 +27,7 @@ ERRORS = {-1: "MMV_EINVAL", -2: "MMV_ENOMEM", -3: "MMV_EHIP", -4: "MMV_ERANGE",
           -5: "MMV_ENUMERIC", -6: "MMV_ESTATE"}
 EXPORTS = ("init_mesh", "set_m", "get_m", "set_offset", "set_drive", "eval_heff",
            "llg_step", "stray_force", "get_state", "profile_begin", "profile_end",
-           "get_fft_lengths", "init_batch", "batch_instance", "batch_step", "batch_tuning",
+           "get_fft_lengths", "profile_repeat", "init_batch", "batch_instance", "batch_step", "batch_tuning",
            "destroy_batch", "destroy_mesh", "sur_create", "sur_param_count", "sur_param_offsets",
            "sur_set_params", "sur_get_params", "sur_forward", "sur_gradient", "sur_train_step",
            "sur_gemm_bf16", "sur_destroy", "sur_attach", "sur_status", "mmv_last_error")
@@ -98,6 +98,7 @@ def load():
         lib.batch_tuning.argtypes = [vp, i, ctypes.POINTER(i)]
         lib.destroy_batch.argtypes = [vp]
         lib.profile_end.argtypes = [vp, pd, ctypes.POINTER(ctypes.c_long)]
+        lib.profile_repeat.argtypes = [vp, i, i, pd]
         ll, f = ctypes.c_longlong, ctypes.c_float
         lib.sur_create.argtypes = [ctypes.POINTER(SurDesc), vp, ctypes.POINTER(vp)]
         lib.sur_param_count.argtypes = [vp]
@@ -225,6 +226,15 @@ def profile_end(h):
     ms, n = ctypes.c_double(), ctypes.c_long()
     _check(load().profile_end(h, ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def profile_repeat(h, kernel, reps=200):
+    """Mean ms per launch of one kernel launched reps times back to back
+    (leaves the mesh state undefined)."""
+    k = {"row_fwd": 1, "col": 2, "row_stage": 3}.get(kernel, kernel)
+    v = ctypes.c_double()
+    _check(load().profile_repeat(h, k, reps, ctypes.byref(v)))
+    return v.value
 
 
 def destroy_mesh(h):

@@ -1283,6 +1283,65 @@ int profile_end(mmv_handle h, double* total_ms, long* launches) {
   return MMV_OK;
 }
 
+}  // extern "C"
+
+namespace {
+template <typename T>
+int repeat_typed(mmv_mesh* h, int kernel, int reps, double* avg_ms) {
+  RowParams rp = h->rp_hot;
+  rp.mode = MODE_STAGE;
+  rp.term_mask = MMV_TERM_ALL;
+  rp.stage = 1;
+  rp.dt = 0.0;
+  rp.drive = h->drive;
+  rp.with_force = (h->drive.mode == MMV_DRIVE_SPRING) ? 1 : 0;
+  rp.full_force = 0;
+  rp.ntask = h->nfilm * h->ny + ((rp.with_force && rp.pot) ? 2 : 0);
+  rp.spec1_out = h->fuse_fwd ? h->spec1 : nullptr;
+  rp.defer_tick = 1;
+  rp.hsur = nullptr;
+  T* b1 = (T*)h->mb[0];
+  T* b2 = (T*)h->mb[1];
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int rc = MMV_OK;
+  auto one = [&]() -> hipError_t {
+    if (kernel == 1)
+      return launch_row_fwd<T>((const T*)h->m0, h->spec1, 3 * h->nfilm * h->ny, h->nx, h->N2x, h->Kx, h->px, h->twx,
+                               h->twp, h->st, h->ny);
+    if (kernel == 2)
+      return launch_col<T>(h->spec1, h->spec2, (const T*)h->kern, h->Kx, h->Ly, h->Kyh, h->ny, 3 * h->nfilm,
+                           h->ngroup, h->py, h->twy, h->tab_hot, h->st);
+    return launch_row_stage<T>(rp, h->spec2, b1, (const T*)h->m0, b2, (T*)h->acc, nullptr, h->twx, h->twp, h->rigid,
+                               h->partial, h->counter, h->st);
+  };
+  hipError_t e = one();  // warm
+  if (e == hipSuccess) e = hipEventRecord(e0, h->st);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = one();
+  if (e == hipSuccess) e = hipEventRecord(e1, h->st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e != hipSuccess) rc = fail(MMV_EHIP, std::string("profile_repeat: ") + hipGetErrorString(e));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (!rc && avg_ms) *avg_ms = (double)ms / reps;
+  return rc;
+}
+}  // namespace
+
+extern "C" {
+
+int profile_repeat(mmv_handle h, int kernel, int reps, double* avg_ms) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (kernel < 1 || kernel > 3) return fail(MMV_EINVAL, "kernel must be 1, 2 or 3");
+  if (reps < 1 || reps > 100000) return fail(MMV_EINVAL, "reps must be in [1, 100000]");
+  if (h->cube || h->nfilm != 2 || h->in_batch) return fail(MMV_ESTATE, "profile_repeat needs a two-film mesh");
+  return h->esz == 8 ? repeat_typed<double>(h, kernel, reps, avg_ms) : repeat_typed<float>(h, kernel, reps, avg_ms);
+}
+
 int init_batch(const mmv_mesh_desc* descs, int n, void* hip_stream, int flags, mmv_batch_handle* out) {
   g_err.clear();
   if (!out) return fail(MMV_EINVAL, "out is NULL");

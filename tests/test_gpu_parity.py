@@ -163,3 +163,23 @@ def test_tiny_potential_fp64_100_steps():
     dm, st, s = run_steps(cfg["desc"], cfg["drive"], initial_state(cfg), cfg["dt"], 100)
     print("tiny potential 100 steps max|dm|", dm, flush=True)
     assert dm < 1e-9
+
+
+def test_profile_repeat_times_each_kernel_and_validates():
+    import paper_1801_04181_amd as mmv
+    cfg = get_config("tiny")
+    d = cfg["desc"].replace(precision=32)
+    mesh = mmv.Mesh(d, cfg["drive"], initial_state(cfg))
+    for k in ("row_fwd", "col", "row_stage"):
+        ms = mmv.profile_repeat(mesh.h, k, 5)
+        assert 0.0 < ms < 100.0, (k, ms)
+    for bad in (0, 4):
+        with pytest.raises(mmv.MMVError) as e:
+            mmv.profile_repeat(mesh.h, bad, 5)
+        assert e.value.code == -1
+    with pytest.raises(mmv.MMVError):
+        mmv.profile_repeat(mesh.h, 2, 0)
+    single = mmv.Mesh(d.replace(n_films=1), cfg["drive"])
+    with pytest.raises(mmv.MMVError) as e:
+        mmv.profile_repeat(single.h, 2, 5)
+    assert e.value.code == -6
