@@ -598,14 +598,17 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   const double fls = floor(xp), flb = floor(-xp);
   const double frs = xp - fls, frb = -xp - flb;
   const int ifs = (int)fls, ifb = (int)flb;
-  for (int tq = threadIdx.x; tq < 2 * NQ; tq += blockDim.x) {
-    const int q = (tq % NQ) - K - 1;
-    const double fr = tq < NQ ? frs : frb;
-    const double z1 = -0.26794919243112270647;  // sqrt(3) - 2, pole of the cubic B-spline prefilter
-    double g = 0.0;
-#pragma unroll
-    for (int t = -1; t <= 2; ++t) {
+  // spline weights: the four terms of each weight on their own threads,
+  // then summed in tap order
+  {
+    double* wterm = red + 96;  // [2 NQ][4]
+    for (int u = threadIdx.x; u < 8 * NQ; u += blockDim.x) {
+      const int tq = u >> 2, t = (u & 3) - 1;
+      const int q = (tq % NQ) - K - 1;
+      const double fr = tq < NQ ? frs : frb;
+      const double z1 = -0.26794919243112270647;  // sqrt(3) - 2, pole of the cubic B-spline prefilter
       const int j = t - q;
+      double v = 0.0;
       if (j >= -K && j <= K) {
         // z1^|j| by binary exponentiation (|j| <= K)
         double zp = 1.0, b = z1;
@@ -613,10 +616,16 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
           if (e & 1) zp *= b;
           b *= b;
         }
-        g += beta3(fr - t) * 1.7320508075688772935 * zp;
+        v = beta3(fr - t) * 1.7320508075688772935 * zp;
       }
+      wterm[u] = v;
     }
-    (tq < NQ ? gs : gb)[tq % NQ] = (T)g;
+    __syncthreads();
+    for (int tq = threadIdx.x; tq < 2 * NQ; tq += blockDim.x) {
+      double g = 0.0;
+      for (int t = 0; t < 4; ++t) g += wterm[tq * 4 + t];
+      (tq < NQ ? gs : gb)[tq % NQ] = (T)g;
+    }
   }
   __syncthreads();
   const int nrow = s_nrow;
@@ -1125,7 +1134,7 @@ size_t row_lds_bytes(const RowParams& p) {
   b += sizeof(T) * ((size_t)p.nbr * (p.M + 2 * E + 4) + 2 * NQ + 3 * p.nx + 3 * (p.nx + 2) + 2 * nfc * p.nx +
                     (size_t)nslot * (p.nx + 6) + 2 * (size_t)p.nx + 2);
   b = (b + 15) & ~size_t(15);
-  b += sizeof(double) * 96 + 16;  // wave partials of the force reduction
+  b += sizeof(double) * (96 + 8 * NQ) + 16;  // wave partials of the force reduction, spline-weight terms
   return b;
 }
 
