@@ -22,8 +22,12 @@
 namespace mmv {
 
 // ------------------------------------------------------------ strided column FFT
+// Block size of the LDS transform kernels (used as a compile-time constant
+// by the kernels and their helpers).
+constexpr int CUBE_THREADS = 256;
+
 template <typename T, bool INV>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(CUBE_THREADS)
     k_fft_axis(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int ncols, int CB, int n_in,
                long long in_ps, int n_out, long long out_ps, FftPlan P, const cpx<T>* __restrict__ tw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -37,16 +41,16 @@ __global__ void __launch_bounds__(256)
   const long long p = blockIdx.y;
   const cpx<T>* src = in + p * in_ps + c0;
   cpx<T>* dst = out + p * out_ps + c0;
-  for (int t = threadIdx.x; t < L; t += blockDim.x) stw[t] = tw[t];
+  for (int t = threadIdx.x; t < L; t += CUBE_THREADS) stw[t] = tw[t];
   const float inc = 1.0f / (float)nc;
-  for (int t = threadIdx.x; t < nc * L; t += blockDim.x) {
+  for (int t = threadIdx.x; t < nc * L; t += CUBE_THREADS) {
     const int r = fdiv(t, inc);
     const int c = t - r * nc;
     A[c * L + r] = r < n_in ? src[(size_t)r * ncols + c] : mk<T>(0, 0);
   }
   __syncthreads();
-  const cpx<T>* R = fft_lds<T, INV>(A, B, P, nc, L, stw);
-  for (int t = threadIdx.x; t < nc * n_out; t += blockDim.x) {
+  const cpx<T>* R = fft_lds<T, INV, CUBE_THREADS>(A, B, P, nc, L, stw);
+  for (int t = threadIdx.x; t < nc * n_out; t += CUBE_THREADS) {
     const int r = fdiv(t, inc);
     const int c = t - r * nc;
     dst[(size_t)r * ncols + c] = R[c * L + r];
@@ -60,7 +64,7 @@ __global__ void __launch_bounds__(256)
 // mode 0: out_a = sum_b N_ab v_b (six components xx yy zz xy xz yz)
 // mode 1: out = sgn * S x v (components Sx Sy Sz)
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(CUBE_THREADS)
     k_zmul(cpx<T>* __restrict__ buf, const T* __restrict__ kern, int Kx, int Ly, int nz, int CB, int mode,
            T sgn, FftPlan P, const cpx<T>* __restrict__ twz) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -74,23 +78,23 @@ __global__ void __launch_bounds__(256)
   const int nc = min(CB, Kx - kx0);
   const int ky = blockIdx.y;
   const long long cs = (long long)nz * Ly * Kx;  // channel stride
-  for (int t = threadIdx.x; t < Lz; t += blockDim.x) stw[t] = twz[t];
+  for (int t = threadIdx.x; t < Lz; t += CUBE_THREADS) stw[t] = twz[t];
   const float inc = 1.0f / (float)nc;
-  for (int t = threadIdx.x; t < 3 * nz * nc; t += blockDim.x) {
+  for (int t = threadIdx.x; t < 3 * nz * nc; t += CUBE_THREADS) {
     const int cz = fdiv(t, inc);  // c * nz + z
     const int cc = t - cz * nc;
     const int c = cz / nz, z = cz - c * nz;
     A[(c * nc + cc) * Lz + z] = buf[c * cs + ((long long)z * Ly + ky) * Kx + kx0 + cc];
   }
-  for (int t = threadIdx.x; t < 3 * nc * (Lz - nz); t += blockDim.x) {
+  for (int t = threadIdx.x; t < 3 * nc * (Lz - nz); t += CUBE_THREADS) {
     const int b = t / (Lz - nz), z = nz + t - b * (Lz - nz);
     A[b * Lz + z] = mk<T>(0, 0);
   }
   __syncthreads();
-  cpx<T>* X = fft_lds<T, false>(A, B, P, 3 * nc, Lz, stw);
+  cpx<T>* X = fft_lds<T, false, CUBE_THREADS>(A, B, P, 3 * nc, Lz, stw);
   const bool yup = ky >= Kyh;
   const int kyr = yup ? Ly - ky : ky;
-  for (int t = threadIdx.x; t < nc * Lz; t += blockDim.x) {
+  for (int t = threadIdx.x; t < nc * Lz; t += CUBE_THREADS) {
     const int cc = t / Lz, kz = t - cc * Lz;
     const bool zup = kz >= Kzh;
     const int kzr = zup ? Lz - kz : kz;
@@ -125,8 +129,8 @@ __global__ void __launch_bounds__(256)
     X[(2 * nc + cc) * Lz + kz] = o2;
   }
   __syncthreads();
-  cpx<T>* Y = fft_lds<T, true>(X, (X == A) ? B : A, P, 3 * nc, Lz, stw);
-  for (int t = threadIdx.x; t < 3 * nz * nc; t += blockDim.x) {
+  cpx<T>* Y = fft_lds<T, true, CUBE_THREADS>(X, (X == A) ? B : A, P, 3 * nc, Lz, stw);
+  for (int t = threadIdx.x; t < 3 * nz * nc; t += CUBE_THREADS) {
     const int cz = fdiv(t, inc);
     const int cc = t - cz * nc;
     const int c = cz / nz, z = cz - c * nz;
@@ -136,7 +140,7 @@ __global__ void __launch_bounds__(256)
 
 // ------------------------------------------------------------ inverse x transform
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(CUBE_THREADS)
     k_row_inv(const cpx<T>* __restrict__ spec, T* __restrict__ out, int nx, int N2x, int Kx, FftPlan P,
               const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -145,11 +149,11 @@ __global__ void __launch_bounds__(256)
   cpx<T>* a = stp + N2x + 1;
   cpx<T>* b = a + N2x;
   const size_t row = blockIdx.x;
-  for (int t = threadIdx.x; t < N2x; t += blockDim.x) stw[t] = tw[t];
-  for (int t = threadIdx.x; t <= N2x; t += blockDim.x) stp[t] = twp[t];
+  for (int t = threadIdx.x; t < N2x; t += CUBE_THREADS) stw[t] = tw[t];
+  for (int t = threadIdx.x; t <= N2x; t += CUBE_THREADS) stp[t] = twp[t];
   const cpx<T>* X = spec + row * Kx;
   __syncthreads();
-  for (int k = threadIdx.x; k < N2x; k += blockDim.x) {
+  for (int k = threadIdx.x; k < N2x; k += CUBE_THREADS) {
     cpx<T> xk = X[k];
     cpx<T> xm = X[N2x - k];
     xm.y = -xm.y;
@@ -158,8 +162,8 @@ __global__ void __launch_bounds__(256)
     a[k] = mk<T>(s.x - d.y, s.y + d.x);
   }
   __syncthreads();
-  const T* xr = reinterpret_cast<const T*>(fft_lds<T, true>(a, b, P, 1, N2x, stw));
-  for (int i = threadIdx.x; i < nx; i += blockDim.x) out[row * nx + i] = xr[i];
+  const T* xr = reinterpret_cast<const T*>(fft_lds<T, true, CUBE_THREADS>(a, b, P, 1, N2x, stw));
+  for (int i = threadIdx.x; i < nx; i += CUBE_THREADS) out[row * nx + i] = xr[i];
 }
 
 // ------------------------------------------------------------ cell kernels
@@ -454,10 +458,10 @@ hipError_t launch_fft_axis(const void* in, void* out, int nplanes, int ncols, in
   const size_t lds = sizeof(cpx<T>) * ((size_t)P.L + 2 * (size_t)CB * P.L);
   dim3 grid((ncols + CB - 1) / CB, nplanes);
   if (inv)
-    hipLaunchKernelGGL((k_fft_axis<T, true>), grid, dim3(256), lds, st, (const cpx<T>*)in, (cpx<T>*)out, ncols, CB,
+    hipLaunchKernelGGL((k_fft_axis<T, true>), grid, dim3(CUBE_THREADS), lds, st, (const cpx<T>*)in, (cpx<T>*)out, ncols, CB,
                        n_in, in_ps, n_out, out_ps, P, (const cpx<T>*)tw);
   else
-    hipLaunchKernelGGL((k_fft_axis<T, false>), grid, dim3(256), lds, st, (const cpx<T>*)in, (cpx<T>*)out, ncols, CB,
+    hipLaunchKernelGGL((k_fft_axis<T, false>), grid, dim3(CUBE_THREADS), lds, st, (const cpx<T>*)in, (cpx<T>*)out, ncols, CB,
                        n_in, in_ps, n_out, out_ps, P, (const cpx<T>*)tw);
   return hipGetLastError();
 }
@@ -471,7 +475,7 @@ hipError_t launch_zmul(void* buf, const T* kern, int Kx, int Ly, int nz, int CB,
     if (e != hipSuccess) return e;
   }
   dim3 grid((Kx + CB - 1) / CB, Ly);
-  hipLaunchKernelGGL(k_zmul<T>, grid, dim3(256), lds, st, (cpx<T>*)buf, kern, Kx, Ly, nz, CB, mode, (T)sgn, P,
+  hipLaunchKernelGGL(k_zmul<T>, grid, dim3(CUBE_THREADS), lds, st, (cpx<T>*)buf, kern, Kx, Ly, nz, CB, mode, (T)sgn, P,
                      (const cpx<T>*)twz);
   return hipGetLastError();
 }
@@ -480,7 +484,7 @@ template <typename T>
 hipError_t launch_row_inv(const void* spec, T* out, int nrows, int nx, int N2x, int Kx, const FftPlan& P,
                           const void* tw, const void* twp, hipStream_t st) {
   const size_t lds = sizeof(cpx<T>) * (4 * (size_t)N2x + 1);
-  hipLaunchKernelGGL(k_row_inv<T>, dim3(nrows), dim3(256), lds, st, (const cpx<T>*)spec, out, nx, N2x, Kx, P,
+  hipLaunchKernelGGL(k_row_inv<T>, dim3(nrows), dim3(CUBE_THREADS), lds, st, (const cpx<T>*)spec, out, nx, N2x, Kx, P,
                      (const cpx<T>*)tw, (const cpx<T>*)twp);
   return hipGetLastError();
 }

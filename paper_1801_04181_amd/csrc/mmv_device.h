@@ -165,24 +165,39 @@ __device__ __forceinline__ void dft(cpx<T>* v) {
 // than the float rounding of the product.
 __device__ __forceinline__ int fdiv(int n, float inv_d) { return (int)(((float)n + 0.5f) * inv_d); }
 
-// dst[t] = load(t) for t < n, block-strided, with U independent loads in
-// flight per thread before the first store (one global-memory latency per U
-// elements instead of one per element).
-template <int U, typename V, typename F>
+// dst[t] = load(t) for t < n, block-strided over the NT threads of the
+// block, with U independent loads in flight per thread before the first
+// store (one global-memory latency per U elements instead of one per
+// element).
+//
+// Every device helper takes the block size NT as a compile-time constant:
+// the runtime block size lives in the dispatch's hidden arguments, and the
+// compiler re-reads it with a vector load after each barrier.
+template <int U, int NT, typename V, typename F>
 __device__ __forceinline__ void stage_copy(V* dst, int n, F load) {
-  for (int t0 = threadIdx.x; t0 < n; t0 += U * (int)blockDim.x) {
+#pragma unroll 1
+  for (int t0 = threadIdx.x; t0 < n; t0 += U * NT) {
     V v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int t = t0 + u * (int)blockDim.x;
+      const int t = t0 + u * NT;
       if (t < n) v[u] = load(t);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int t = t0 + u * (int)blockDim.x;
+      const int t = t0 + u * NT;
       if (t < n) dst[t] = v[u];
     }
   }
+}
+
+// threadIdx.x, opaque to the optimiser: index arithmetic derived from it
+// is then recomputed where it is used instead of being hoisted out of an
+// enclosing loop and kept live (in registers or spilled) across it.
+__device__ __forceinline__ int local_tid() {
+  int t = (int)threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
 }
 
 // Sum over the 64 lanes of a wave; the total is returned in lane 0.
@@ -199,19 +214,20 @@ __device__ __forceinline__ double wave_sum(double v) {
 // transform group g); a thread reuses its index arithmetic and twiddles for
 // every transform t = g, g + G, ... of its group.  twh > 0: only tw[0..twh)
 // is stored (L = 2 twh) and tw[t + twh] = -tw[t].
-template <typename T, int R, bool INV>
+template <typename T, int R, bool INV, int NT>
 __device__ __forceinline__ void stockham_pass(const cpx<T>* __restrict__ a, cpx<T>* __restrict__ b, int L,
                                               int Ns, int batch, int stride,
                                               const cpx<T>* __restrict__ tw, int twh) {
   const int nb = L / R;
   const int tws = L / (Ns * R);
-  int G = (int)blockDim.x / nb;
+  int G = NT / nb;
   if (G < 1) G = 1;
   if (G > batch) G = batch;
   const float inb = 1.0f / (float)nb;
   const float ins = 1.0f / (float)Ns;
   const int total = nb * G;
-  for (int w = threadIdx.x; w < total; w += blockDim.x) {
+#pragma unroll 1
+  for (int w = local_tid(); w < total; w += NT) {
     const int g = fdiv(w, inb);
     const int j = w - g * nb;
     const int q = fdiv(j, ins);
@@ -273,7 +289,7 @@ constexpr CPlan make_cplan(int L) {
 }
 
 // One radix-R pass of `batch` contiguous transforms of length L with NT
-// threads per block (any blockDim works: butterflies are block-strided).
+// threads per block (butterflies are block-strided).
 // HALF: only tw[0..L/2) is stored and tw[t + L/2] = -tw[t].
 template <typename T, int L, int NT, int R, int Ns, bool INV, bool HALF>
 __device__ __forceinline__ void stockham_ct(const cpx<T>* __restrict__ a, cpx<T>* __restrict__ b, int batch,
@@ -281,7 +297,8 @@ __device__ __forceinline__ void stockham_ct(const cpx<T>* __restrict__ a, cpx<T>
   constexpr int nb = L / R;
   constexpr int G = NT / nb >= 1 ? NT / nb : 1;
   constexpr int tws = L / (Ns * R);
-  for (int w = threadIdx.x; w < nb * G; w += blockDim.x) {
+#pragma unroll 1
+  for (int w = local_tid(); w < nb * G; w += NT) {
     const int g = w / nb;
     const int j = w - g * nb;
     const int q = j / Ns;
@@ -342,19 +359,19 @@ __host__ __device__ constexpr bool has_cplan(int L) {
 // result.  Unnormalised.  Must be entered by the whole block after the data
 // are in place and visible (a __syncthreads() before the call); ends with
 // a __syncthreads().
-template <typename T, bool INV>
-__device__ cpx<T>* fft_lds_generic(cpx<T>* a, cpx<T>* b, const FftPlan& P, int batch, int stride,
+template <typename T, bool INV, int NT>
+__device__ __forceinline__ cpx<T>* fft_lds_generic(cpx<T>* a, cpx<T>* b, const FftPlan& P, int batch, int stride,
                                    const cpx<T>* __restrict__ tw, int twh) {
   const int L = P.L;
   int Ns = 1;
   for (int p = 0; p < P.np; ++p) {
     const int R = P.r[p];
     switch (R) {
-      case 2: stockham_pass<T, 2, INV>(a, b, L, Ns, batch, stride, tw, twh); break;
-      case 3: stockham_pass<T, 3, INV>(a, b, L, Ns, batch, stride, tw, twh); break;
-      case 4: stockham_pass<T, 4, INV>(a, b, L, Ns, batch, stride, tw, twh); break;
-      case 5: stockham_pass<T, 5, INV>(a, b, L, Ns, batch, stride, tw, twh); break;
-      default: stockham_pass<T, 7, INV>(a, b, L, Ns, batch, stride, tw, twh); break;
+      case 2: stockham_pass<T, 2, INV, NT>(a, b, L, Ns, batch, stride, tw, twh); break;
+      case 3: stockham_pass<T, 3, INV, NT>(a, b, L, Ns, batch, stride, tw, twh); break;
+      case 4: stockham_pass<T, 4, INV, NT>(a, b, L, Ns, batch, stride, tw, twh); break;
+      case 5: stockham_pass<T, 5, INV, NT>(a, b, L, Ns, batch, stride, tw, twh); break;
+      default: stockham_pass<T, 7, INV, NT>(a, b, L, Ns, batch, stride, tw, twh); break;
     }
     __syncthreads();
     cpx<T>* tmp = a;
@@ -365,11 +382,10 @@ __device__ cpx<T>* fft_lds_generic(cpx<T>* a, cpx<T>* b, const FftPlan& P, int b
   return a;
 }
 
-// Dispatch: compiled plan for contiguous transforms of a known length (NT =
-// the launch's block size the thread mapping is tuned for), else the generic
-// runtime-plan passes.
-template <typename T, bool INV, int NT = 256>
-__device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, const FftPlan& P, int batch, int stride,
+// Dispatch: compiled plan for contiguous transforms of a known length, else
+// the generic runtime-plan passes; NT = the launch's block size.
+template <typename T, bool INV, int NT>
+__device__ __forceinline__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, const FftPlan& P, int batch, int stride,
                            const cpx<T>* __restrict__ tw, int twh = 0) {
   if (stride == P.L) {
     if (twh == 0) {
@@ -390,7 +406,7 @@ __device__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, const FftPlan& P, int batch, in
       }
     }
   }
-  return fft_lds_generic<T, INV>(a, b, P, batch, stride, tw, twh);
+  return fft_lds_generic<T, INV, NT>(a, b, P, batch, stride, tw, twh);
 }
 
 }  // namespace mmv

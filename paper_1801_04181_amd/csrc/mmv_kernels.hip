@@ -25,6 +25,14 @@
 
 namespace mmv {
 
+// Block sizes of the launches.  Kernels and their helpers use these
+// compile-time values instead of blockDim.x.
+constexpr int FWD_THREADS = 256;      // x pass
+constexpr int COL_THREADS = 256;      // y pass (its block 0 also runs the slider tick)
+constexpr int TICK_THREADS = 256;     // slider tick
+constexpr int COLPACK_THREADS = 256;  // kernel-spectrum packing
+static_assert(TICK_THREADS == COL_THREADS, "the y pass runs the tick with its own block");
+
 // ------------------------------------------------------------ x transform
 // Rows handled by one block of the x pass: `nb` rows at `row0`, `rstride`
 // rows apart (the three components of one film row, or one row).  Output
@@ -40,10 +48,10 @@ __device__ __forceinline__ void row_fwd_body(int row0, int nb, int rstride, cons
   cpx<T>* stp = stw + N2x;
   cpx<T>* a = stp + N2x + 1;
   cpx<T>* b = a + (size_t)nb * N2x;
-  for (int t = threadIdx.x; t < N2x; t += blockDim.x) stw[t] = tw[t];
-  for (int t = threadIdx.x; t <= N2x; t += blockDim.x) stp[t] = twp[t];
+  for (int t = threadIdx.x; t < N2x; t += FWD_THREADS) stw[t] = tw[t];
+  for (int t = threadIdx.x; t <= N2x; t += FWD_THREADS) stp[t] = twp[t];
   const float inv = 1.0f / (float)N2x;
-  for (int t = threadIdx.x; t < nb * N2x; t += blockDim.x) {
+  for (int t = threadIdx.x; t < nb * N2x; t += FWD_THREADS) {
     const int r = fdiv(t, inv);
     const int n = t - r * N2x;
     const T* s = src + (size_t)(row0 + r * rstride) * nin;
@@ -51,10 +59,10 @@ __device__ __forceinline__ void row_fwd_body(int row0, int nb, int rstride, cons
     a[t] = mk<T>(i0 < nin ? s[i0] : T(0), i1 < nin ? s[i1] : T(0));
   }
   __syncthreads();
-  cpx<T>* Z = fft_lds<T, false>(a, b, P, nb, N2x, stw);
+  cpx<T>* Z = fft_lds<T, false, FWD_THREADS>(a, b, P, nb, N2x, stw);
   const int K1 = N2x + 1;
   const float ink = 1.0f / (float)K1;
-  for (int t = threadIdx.x; t < nb * K1; t += blockDim.x) {
+  for (int t = threadIdx.x; t < nb * K1; t += FWD_THREADS) {
     const int r = fdiv(t, ink);
     const int k = t - r * K1;
     const cpx<T>* z = Z + (size_t)r * N2x;
@@ -72,7 +80,7 @@ __device__ __forceinline__ void row_fwd_body(int row0, int nb, int rstride, cons
 // Block b transforms rows b of a (rows / 3) x 3 arrangement when `three`
 // (the x, y, z components of one film row, ny rows apart), else row b.
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(FWD_THREADS)
     k_row_fwd(const T* __restrict__ src, cpx<T>* __restrict__ dst, int nrows, int nin, int N2x,
               int Kx, FftPlan P, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp, int ny3) {
   if (ny3 > 0) {
@@ -98,7 +106,7 @@ __device__ __forceinline__ int find_instance(const int* __restrict__ start, int 
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_row_fwd_batch(const RowFwdDesc* __restrict__ d, const int* __restrict__ start,
+__global__ void __launch_bounds__(FWD_THREADS) k_row_fwd_batch(const RowFwdDesc* __restrict__ d, const int* __restrict__ start,
                                                        int n) {
   const int bl = xcd_remap(blockIdx.x, gridDim.x);
   const int i = find_instance(start, n, bl);
@@ -136,66 +144,84 @@ __device__ __forceinline__ void col_body(int blk, const cpx<T>* __restrict__ spe
   const int o0 = (g * tab.n) / ngroup;
   const int o1 = ((g + 1) * tab.n) / ngroup;
   const int no = o1 - o0;
-  for (int t = threadIdx.x; t < 3 * no; t += blockDim.x) {
+  for (int t = threadIdx.x; t < 3 * no; t += COL_THREADS) {
     const int o = t / 3, b = t - 3 * o;
     const int kc = tab.ch[o0 + o].kc[b];
     s_koff[o][b] = kc < 0 ? -1 : (kc * Kx + kx) * Kyh;
     s_fl[o][b] = tab.ch[o0 + o].fl[b];
     if (b == 0) s_src[o] = tab.ch[o0 + o].src;
   }
-  for (int t = threadIdx.x; t < Lh; t += blockDim.x) stw[t] = twy[t];
+  for (int t = threadIdx.x; t < Lh; t += COL_THREADS) stw[t] = twy[t];
   const int nload = nin_ch * Ly;
   const float invLy = 1.0f / (float)Ly;
-  stage_copy<4>(A, nload, [&](int t) {
+  stage_copy<4, COL_THREADS>(A, nload, [&](int t) {
     const int ch = fdiv(t, invLy);
     const int y = t - ch * Ly;
     return (y < ny) ? spec1[((size_t)ch * Kx + kx) * ny + y] : mk<T>(0, 0);
   });
   __syncthreads();
   const int twh = (Ly & 1) ? 0 : Lh;
-  cpx<T>* X = fft_lds<T, false>(A, B, P, nin_ch, Ly, stw, twh);
+  cpx<T>* X = fft_lds<T, false, COL_THREADS>(A, B, P, nin_ch, Ly, stw, twh);
   cpx<T>* W = (X == A) ? B : A;
   // one thread per (output, |ky|): the kernel value at |ky| (the stored half)
-  // serves both ky and Ly - ky
+  // serves both ky and Ly - ky.  The kernel values of PF pairs per thread
+  // are loaded before any is used, so their latencies overlap.
   const int npair = no * Kyh;
   const float invK = 1.0f / (float)Kyh;
-  for (int t = threadIdx.x; t < npair; t += blockDim.x) {
-    const int o = fdiv(t, invK);
-    const int kyr = t - o * Kyh;
-    const int ky2 = Ly - kyr;
-    const bool two = kyr > 0 && ky2 > kyr;
-    const int src = s_src[o];
-    cpx<T> a1 = mk<T>(0, 0), a2 = mk<T>(0, 0);
+  constexpr int PF = 4;
+  for (int t0 = 0; t0 < npair; t0 += PF * COL_THREADS) {
+    T kv[PF][3];
 #pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const int ko = s_koff[o][b];
-      if (ko < 0) continue;
-      const int fl = s_fl[o][b];
-      const T s = kern[ko + kyr];
-      const T s1 = (fl & 4) ? -s : s;                                // ky <= Ly/2
-      const T s2 = (((fl & 4) != 0) != ((fl & 2) != 0)) ? -s : s;   // ky > Ly/2 (odd in ky)
-      const cpx<T>* xb = X + (src * 3 + b) * Ly;
-      const cpx<T> m1 = xb[kyr];
-      if (fl & 1)
-        a1 = a1 + mk<T>(-s1 * m1.y, s1 * m1.x);
-      else
-        a1 = a1 + mk<T>(s1 * m1.x, s1 * m1.y);
-      if (two) {
-        const cpx<T> m2 = xb[ky2];
-        if (fl & 1)
-          a2 = a2 + mk<T>(-s2 * m2.y, s2 * m2.x);
-        else
-          a2 = a2 + mk<T>(s2 * m2.x, s2 * m2.y);
+    for (int u = 0; u < PF; ++u) {
+      const int t = t0 + u * COL_THREADS + (int)threadIdx.x;
+      const int o = fdiv(t, invK);
+      const int kyr = t - o * Kyh;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const int ko = t < npair ? s_koff[o][b] : -1;
+        kv[u][b] = ko < 0 ? T(0) : kern[ko + kyr];
       }
     }
-    W[o * Ly + kyr] = a1;
-    if (two) W[o * Ly + ky2] = a2;
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int t = t0 + u * COL_THREADS + (int)threadIdx.x;
+      if (t >= npair) break;
+      const int o = fdiv(t, invK);
+      const int kyr = t - o * Kyh;
+      const int ky2 = Ly - kyr;
+      const bool two = kyr > 0 && ky2 > kyr;
+      const int src = s_src[o];
+      cpx<T> a1 = mk<T>(0, 0), a2 = mk<T>(0, 0);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if (s_koff[o][b] < 0) continue;
+        const int fl = s_fl[o][b];
+        const T s = kv[u][b];
+        const T s1 = (fl & 4) ? -s : s;                                // ky <= Ly/2
+        const T s2 = (((fl & 4) != 0) != ((fl & 2) != 0)) ? -s : s;   // ky > Ly/2 (odd in ky)
+        const cpx<T>* xb = X + (src * 3 + b) * Ly;
+        const cpx<T> m1 = xb[kyr];
+        if (fl & 1)
+          a1 = a1 + mk<T>(-s1 * m1.y, s1 * m1.x);
+        else
+          a1 = a1 + mk<T>(s1 * m1.x, s1 * m1.y);
+        if (two) {
+          const cpx<T> m2 = xb[ky2];
+          if (fl & 1)
+            a2 = a2 + mk<T>(-s2 * m2.y, s2 * m2.x);
+          else
+            a2 = a2 + mk<T>(s2 * m2.x, s2 * m2.y);
+        }
+      }
+      W[o * Ly + kyr] = a1;
+      if (two) W[o * Ly + ky2] = a2;
+    }
   }
   __syncthreads();
-  cpx<T>* Y = fft_lds<T, true>(W, X, P, no, Ly, stw, twh);
+  cpx<T>* Y = fft_lds<T, true, COL_THREADS>(W, X, P, no, Ly, stw, twh);
   for (int o = 0; o < no; ++o) {
     const OutCh& oc = tab.ch[o0 + o];
-    for (int r = threadIdx.x; r < oc.nrows; r += blockDim.x) {
+    for (int r = threadIdx.x; r < oc.nrows; r += COL_THREADS) {
       int yy = (oc.row0 + r) % Ly;
       if (yy < 0) yy += Ly;
       spec2[oc.off + (size_t)r * Kx + kx] = Y[o * Ly + yy];
@@ -208,23 +234,23 @@ __device__ void rigid_stage(RigidState* R, const DriveP& d, int stage, double F,
 // Slider stage update from a finished row launch's force partials, by one
 // whole block: fixed-order float64 sum (strided per thread, then per wave,
 // then over the waves), then Eq. 15's RK4 stage.
-__device__ void tick_body(const TickArgs& a, int stage, double dt) {
+__device__ __forceinline__ void tick_body(const TickArgs& a, int stage, double dt) {
   __shared__ double s_red[16];
   double v = 0.0;
-  for (int t = threadIdx.x; t < a.ntask; t += blockDim.x) v += a.partial[(size_t)t * 3];
+  for (int t = threadIdx.x; t < a.ntask; t += TICK_THREADS) v += a.partial[(size_t)t * 3];
   v = wave_sum(v);
   if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     double F = 0.0;
-    for (int w = 0; w < ((int)blockDim.x + 63) >> 6; ++w) F += s_red[w];
+    for (int w = 0; w < (TICK_THREADS + 63) >> 6; ++w) F += s_red[w];
     rigid_stage(a.rigid, a.drive, stage, a.force_scale * F, dt, a.dx, a.travel);
   }
   __syncthreads();
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(COL_THREADS)
     k_col(const cpx<T>* __restrict__ spec1, cpx<T>* __restrict__ spec2, const T* __restrict__ kern,
           int Kx, int Ly, int Kyh, int ny, int nin_ch, int ngroup, int nbuf, FftPlan P,
           const cpx<T>* __restrict__ twy, OutTable tab, TickArgs tick, int tick_stage, double tick_dt) {
@@ -233,14 +259,14 @@ __global__ void __launch_bounds__(256)
               tab);
 }
 
-__global__ void __launch_bounds__(256) k_tick(TickArgs tick, int stage, double dt) { tick_body(tick, stage, dt); }
+__global__ void __launch_bounds__(TICK_THREADS) k_tick(TickArgs tick, int stage, double dt) { tick_body(tick, stage, dt); }
 
-__global__ void __launch_bounds__(256) k_tick_batch(const ColDesc* __restrict__ d, int stage, double dt) {
+__global__ void __launch_bounds__(TICK_THREADS) k_tick_batch(const ColDesc* __restrict__ d, int stage, double dt) {
   tick_body(d[blockIdx.x].tick, stage, dt);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_col_batch(const ColDesc* __restrict__ d, const int* __restrict__ start,
+__global__ void __launch_bounds__(COL_THREADS) k_col_batch(const ColDesc* __restrict__ d, const int* __restrict__ start,
                                                    int n, int tick_stage, double tick_dt) {
   const int b = xcd_remap(blockIdx.x, gridDim.x);
   const int i = find_instance(start, n, b);
@@ -278,40 +304,33 @@ __device__ __forceinline__ double beta3(double t) {
   return 0.0;
 }
 
+// Half-length complex input of the inverse real transform from the
+// Hermitian half: Z[k] = (X[k] + conj X[N2x-k]) + i conj(w_k) (X[k] - conj X[N2x-k]).
+template <typename T>
+__device__ __forceinline__ cpx<T> c2r_twist(cpx<T> xk, cpx<T> xm, cpx<T> w) {
+  xm.y = -xm.y;
+  const cpx<T> s = xk + xm;
+  const cpx<T> d = cmulc(xk - xm, w);
+  return mk<T>(s.x - d.y, s.y + d.x);
+}
+
 // Inverse real transform of nb rows (Hermitian halves X[0..N2x] at base + rowo[b])
 // into LDS; result buffer viewed as T* holds x[0..Lx) of each row at stride
 // 2*N2x reals.
 template <typename T, int NT>
-__device__ cpx<T>* c2r_rows(const cpx<T>* __restrict__ base, const long long* rowo, int nb, cpx<T>* fa, cpx<T>* fb,
+__device__ __forceinline__ cpx<T>* c2r_rows(const cpx<T>* __restrict__ base, const long long* rowo, int nb, cpx<T>* fa, cpx<T>* fb,
                             int N2x,
                             const FftPlan& P, const cpx<T>* stw, const cpx<T>* stp) {
   const int tot = nb * N2x;
   const float inv = 1.0f / (float)N2x;
-  stage_copy<4>(fa, tot, [&](int t) {
+  stage_copy<4, NT>(fa, tot, [&](int t) {
     const int b = fdiv(t, inv);
     const int k = t - b * N2x;
     const cpx<T>* X = base + rowo[b];
-    cpx<T> xk = X[k];
-    cpx<T> xm = X[N2x - k];
-    xm.y = -xm.y;
-    const cpx<T> s = xk + xm;
-    const cpx<T> d = cmulc(xk - xm, stp[k]);
-    return mk<T>(s.x - d.y, s.y + d.x);
+    return c2r_twist(X[k], X[N2x - k], stp[k]);
   });
   __syncthreads();
   return fft_lds<T, true, NT>(fa, fb, P, nb, N2x, stw);
-}
-
-// Copy the spline window of one real row into ext[E + k], k in [-E, M+E),
-// with whole-sample mirror extension; W0 = lattice index of window sample 0.
-template <typename T>
-__device__ void load_window(const T* __restrict__ xr, T* ext, int W0, int M, int E, int Lx) {
-  for (int k = threadIdx.x; k < M + 2 * E; k += blockDim.x) {
-    int w = reflect_idx(k - E, M);
-    int X = (W0 + w) % Lx;
-    if (X < 0) X += Lx;
-    ext[k] = xr[X];
-  }
 }
 
 // Spline value at window coordinate u = k0 + frac: sum_q g_q ext(k0 + q).
@@ -480,48 +499,55 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   const bool fm_here = fm_split && film == 0 && cell_row;
   const int h = p.halo;
 
-  // slider offset of this stage (issued first; the last block of the launch
-  // is the only writer and runs after every block has read it)
+  // direct mode: the row table in closed form (row i -> spec2 offset, kind)
+  const bool closed = !(need_cross && p.pot);
+  const int n_self = (cell_row && (p.term_mask & 8)) ? 3 : 0;
+  const int n_cross = need_cross ? ((cell_row || p.full_force) ? 3 : 1) : 0;
+  const int n_frc = (need_force && cell_row) ? (fm_split ? nfc : 2 * nfc) : (fm_here ? 1 : 0);
+  const int n_tot = n_self + n_cross + n_frc + (xb_lo ? 1 : 0) + (xb_hi ? 1 : 0);
+  auto row_entry = [&](int i, int& kind) -> long long {
+    long long r;
+    if (i < n_self) {
+      r = p.off_self[film][i] + (long long)y * p.Kx;
+      kind = RK_SELF + i;
+    } else if (i < n_self + n_cross) {
+      const int c = i - n_self;
+      r = p.off_cross[film][c] + (long long)(y - p.cross_row0[film]) * p.Kx;
+      kind = RK_CROSS + c;
+    } else if (i < n_self + n_cross + n_frc) {
+      const int j = i - n_self - n_cross;
+      if (fm_here) {
+        r = p.off_fm[0] + (long long)y * p.Kx;
+        kind = RK_FM;
+      } else if (fm_split) {
+        r = p.off_fp[j] + (long long)y * p.Kx;
+        kind = RK_FP + j;
+      } else {
+        const int c = j >> 1;
+        r = ((j & 1) ? p.off_fm[c] : p.off_fp[c]) + (long long)y * p.Kx;
+        kind = ((j & 1) ? RK_FM : RK_FP) + c;
+      }
+    } else {
+      const bool lo = xb_lo && i == n_self + n_cross + n_frc;
+      r = p.off_cross[1][0] + (long long)((lo ? -1 : ny) - p.cross_row0[1]) * p.Kx;
+      kind = RK_XB + (lo ? 0 : 1);
+    }
+    return r;
+  };
+
+  // slider offset of this stage (issued first; the slider state is written
+  // only after every block of the launch has read it)
   const double xs = rigid->xs;
   const int s_int = rigid->s_int;
   // twiddles: stw (N2x) and stp (N2x + 1) are contiguous
-  stage_copy<4>(stw, 2 * N2x + 1, [&](int t) { return t < N2x ? tw[t] : twp[t - N2x]; });
-  for (int t = threadIdx.x; t < 3 * nx; t += blockDim.x) H[t] = T(0);
-  if (!(need_cross && p.pot)) {
-    // direct mode: the row table in closed form, one entry per thread
-    const int n_self = (cell_row && (p.term_mask & 8)) ? 3 : 0;
-    const int n_cross = need_cross ? ((cell_row || p.full_force) ? 3 : 1) : 0;
-    const int n_frc = (need_force && cell_row) ? (fm_split ? nfc : 2 * nfc) : (fm_here ? 1 : 0);
-    const int n_tot = n_self + n_cross + n_frc + (xb_lo ? 1 : 0) + (xb_hi ? 1 : 0);
-    for (int i = threadIdx.x; i < n_tot; i += blockDim.x) {
-      long long r;
+  stage_copy<4, NT>(stw, 2 * N2x + 1, [&](int t) { return t < N2x ? tw[t] : twp[t - N2x]; });
+#pragma unroll 1
+  for (int t = threadIdx.x; t < 3 * nx; t += NT) H[t] = T(0);
+  if (closed) {
+#pragma unroll 1
+    for (int i = threadIdx.x; i < n_tot; i += NT) {
       int kind;
-      if (i < n_self) {
-        r = p.off_self[film][i] + (size_t)y * p.Kx;
-        kind = RK_SELF + i;
-      } else if (i < n_self + n_cross) {
-        const int c = i - n_self;
-        r = p.off_cross[film][c] + (size_t)(y - p.cross_row0[film]) * p.Kx;
-        kind = RK_CROSS + c;
-      } else if (i < n_self + n_cross + n_frc) {
-        const int j = i - n_self - n_cross;
-        if (fm_here) {
-          r = p.off_fm[0] + (size_t)y * p.Kx;
-          kind = RK_FM;
-        } else if (fm_split) {
-          r = p.off_fp[j] + (size_t)y * p.Kx;
-          kind = RK_FP + j;
-        } else {
-          const int c = j >> 1;
-          r = ((j & 1) ? p.off_fm[c] : p.off_fp[c]) + (size_t)y * p.Kx;
-          kind = ((j & 1) ? RK_FM : RK_FP) + c;
-        }
-      } else {
-        const bool lo = xb_lo && i == n_self + n_cross + n_frc;
-        r = p.off_cross[1][0] + (size_t)((lo ? -1 : ny) - p.cross_row0[1]) * p.Kx;
-        kind = RK_XB + (lo ? 0 : 1);
-      }
-      rowo[i] = r;
+      rowo[i] = row_entry(i, kind);
       rowkind[i] = kind;
     }
     if (threadIdx.x == 0) {
@@ -602,7 +628,8 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   // then summed in tap order
   {
     double* wterm = red + 96;  // [2 NQ][4]
-    for (int u = threadIdx.x; u < 8 * NQ; u += blockDim.x) {
+#pragma unroll 1
+    for (int u = threadIdx.x; u < 8 * NQ; u += NT) {
       const int tq = u >> 2, t = (u & 3) - 1;
       const int q = (tq % NQ) - K - 1;
       const double fr = tq < NQ ? frs : frb;
@@ -621,7 +648,8 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
       wterm[u] = v;
     }
     __syncthreads();
-    for (int tq = threadIdx.x; tq < 2 * NQ; tq += blockDim.x) {
+#pragma unroll 1
+    for (int tq = threadIdx.x; tq < 2 * NQ; tq += NT) {
       double g = 0.0;
       for (int t = 0; t < 4; ++t) g += wterm[tq * 4 + t];
       (tq < NQ ? gs : gb)[tq % NQ] = (T)g;
@@ -638,7 +666,8 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     const T* xr = reinterpret_cast<const T*>(Z);
     // self rows -> H, spline rows -> windows with mirror extension
     const float invMW = 1.0f / (float)MW;
-    for (int t = threadIdx.x; t < bn * MW; t += blockDim.x) {
+#pragma unroll 1
+    for (int t = threadIdx.x; t < bn * MW; t += NT) {
       const int r = fdiv(t, invMW);
       const int k = t - r * MW;
       const int kind = rowkind[b0 + r];
@@ -666,7 +695,8 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     const int NP = nx + 6;  // outputs i = -3 .. nx+2
     const int NB2 = (NP + 1) >> 1;
     const float invNB = 1.0f / (float)NB2;
-    for (int t = threadIdx.x; t < bn * NB2; t += blockDim.x) {
+#pragma unroll 1
+    for (int t = threadIdx.x; t < bn * NB2; t += NT) {
       const int r = fdiv(t, invNB);
       const int i0 = (t - r * NB2) * 2 - 3;
       const int kind = rowkind[b0 + r];
@@ -723,18 +753,21 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     };
     const bool full = p.mode == MODE_FORCE;
     if (cell_row) {
-      for (int t = threadIdx.x; t < 3 * nx; t += blockDim.x) {
+#pragma unroll 1
+      for (int t = threadIdx.x; t < 3 * nx; t += NT) {
         const int c = t / nx, i = t - c * nx;
         if (p.term_mask & 16) H[t] += hcomp(c, 0, i);
       }
     }
     if (need_force) {
-      for (int t = threadIdx.x; t < nfc * (nx + 2); t += blockDim.x) {
+#pragma unroll 1
+      for (int t = threadIdx.x; t < nfc * (nx + 2); t += NT) {
         const int a = t / (nx + 2), i = t - a * (nx + 2) - 1;
         gc[a * (nx + 2) + i + 1] = hcomp(a, 0, i);
       }
       if (cell_row)
-        for (int t = threadIdx.x; t < nfc * nx; t += blockDim.x) {
+#pragma unroll 1
+        for (int t = threadIdx.x; t < nfc * nx; t += NT) {
           const int a = t / nx, i = t - a * nx;
           if (a == 0 || full) {
             gp[a * nx + i] = hcomp(a, 1, i);
@@ -749,7 +782,8 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   const size_t plane = (size_t)ny * nx;
   if (ext_cross && cell_row && (p.term_mask & 16)) {
     const T sc = (T)p.sur_scale;
-    for (int t = threadIdx.x; t < 3 * nx; t += blockDim.x) {
+#pragma unroll 1
+    for (int t = threadIdx.x; t < 3 * nx; t += NT) {
       const int c = t / nx, i = t - c * nx;
       H[t] += sc * (T)p.hsur[(size_t)c * plane + (size_t)y * nx + i];
     }
@@ -767,12 +801,14 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   const bool fuse = p.spec1_out != nullptr && p.mode == MODE_STAGE && cell_row;
   T* fr = reinterpret_cast<T*>(fa);
   if (fuse)
-    for (int t = threadIdx.x; t < 3 * (Lx - nx); t += blockDim.x) {
+#pragma unroll 1
+    for (int t = threadIdx.x; t < 3 * (Lx - nx); t += NT) {
       const int c = t / (Lx - nx);
       fr[c * Lx + nx + (t - c * (Lx - nx))] = T(0);
     }
   if (cell_row && p.mode != MODE_FORCE) {
-    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+#pragma unroll 1
+    for (int i = threadIdx.x; i < nx; i += NT) {
       const size_t id = (size_t)y * nx + i;
       const T mx = ms[id], my = ms[plane + id], mz = ms[2 * plane + id];
       T hx = H[i], hy = H[nx + i], hz = H[2 * nx + i];
@@ -876,7 +912,8 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     const cpx<T>* Z = fft_lds<T, false, NT>(fa, fb, p.px, 3, N2x, stw);
     cpx<T>* dst = reinterpret_cast<cpx<T>*>(p.spec1_out);
     const int K1 = N2x + 1;
-    for (int t = threadIdx.x; t < 3 * K1; t += blockDim.x) {
+#pragma unroll 1
+    for (int t = threadIdx.x; t < 3 * K1; t += NT) {
       const int r = t / K1;
       const int k = t - r * K1;
       const cpx<T>* z = Z + (size_t)r * N2x;
@@ -892,7 +929,8 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     // Eq. (3), component a: sum_i m_x d_x G_a + m_y d_y G_a + m_z d_z G_a,
     // the y term summed by parts over rows -1..ny.
     const double i2dx = 1.0 / (2.0 * p.dx), i2dy = 1.0 / (2.0 * p.dy), i2dz = 1.0 / (2.0 * p.dz);
-    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+#pragma unroll 1
+    for (int i = threadIdx.x; i < nx; i += NT) {
       const double myl = (y - 1 >= 0 && y - 1 < ny) ? (double)ms[plane + (size_t)(y - 1) * nx + i] : 0.0;
       const double myh = (y + 1 >= 0 && y + 1 < ny) ? (double)ms[plane + (size_t)(y + 1) * nx + i] : 0.0;
       double mx = 0, mz = 0;
@@ -919,12 +957,13 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     // layer below it (the z_s - 1 half of the central difference)
     const double i2dz = 1.0 / (2.0 * p.dz);
     const T* mz1 = mst + (size_t)5 * plane + (size_t)y * nx;
-    for (int i = threadIdx.x; i < nx; i += blockDim.x) fpart[0] -= (double)mz1[i] * (double)gm[i] * i2dz;
+#pragma unroll 1
+    for (int i = threadIdx.x; i < nx; i += NT) fpart[0] -= (double)mz1[i] * (double)gm[i] * i2dz;
   }
   if (bad) atomicOr(&s_bad, 1);
   // block reduction of the force partials, fixed order: within each wave,
   // then over the waves
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (NT + 63) >> 6;
   for (int a = 0; a < 3; ++a) {
     const double v = wave_sum(fpart[a]);
     if (lane == 0) red[wv * 3 + a] = v;
@@ -958,7 +997,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   if (!s_last) return;
   __threadfence();
   double sum[3] = {0.0, 0.0, 0.0};
-  for (int t = threadIdx.x; t < ntask; t += blockDim.x)
+  for (int t = threadIdx.x; t < ntask; t += NT)
     for (int a = 0; a < 3; ++a)
       sum[a] += __hip_atomic_load(&partial[(size_t)t * 3 + a], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (int a = 0; a < 3; ++a) {
@@ -1038,7 +1077,7 @@ __global__ void k_kernel_real(double* __restrict__ out, int Lx, int Ly, int kind
 // y transform of the row spectra of a real kernel, keeping the real or
 // imaginary part for ky in [0, Kyh).
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(COLPACK_THREADS)
     k_colpack(const cpx<double>* __restrict__ spec, T* __restrict__ out, int Kx, int Ly, int Kyh,
               FftPlan P, const cpx<double>* __restrict__ twy, int imag) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1046,13 +1085,13 @@ __global__ void __launch_bounds__(256)
   cpx<double>* a = stw + Ly;
   cpx<double>* b = a + Ly;
   const int kx = blockIdx.x;
-  for (int t = threadIdx.x; t < Ly; t += blockDim.x) {
+  for (int t = threadIdx.x; t < Ly; t += COLPACK_THREADS) {
     stw[t] = twy[t];
     a[t] = spec[(size_t)t * Kx + kx];
   }
   __syncthreads();
-  cpx<double>* Y = fft_lds<double, false>(a, b, P, 1, Ly, stw);
-  for (int t = threadIdx.x; t < Kyh; t += blockDim.x) out[(size_t)kx * Kyh + t] = (T)(imag ? Y[t].y : Y[t].x);
+  cpx<double>* Y = fft_lds<double, false, COLPACK_THREADS>(a, b, P, 1, Ly, stw);
+  for (int t = threadIdx.x; t < Kyh; t += COLPACK_THREADS) out[(size_t)kx * Kyh + t] = (T)(imag ? Y[t].y : Y[t].x);
 }
 
 // ------------------------------------------------------------ launchers
@@ -1066,7 +1105,7 @@ hipError_t launch_row_fwd(const T* src, void* dst, int nrows, int nin, int N2x, 
     if (e != hipSuccess) return e;
   }
   const int nblk = ny3 > 0 ? nrows / 3 : nrows;
-  hipLaunchKernelGGL(k_row_fwd<T>, dim3(nblk), dim3(256), lds, st, src, (cpx<T>*)dst, nrows, nin, N2x, Kx,
+  hipLaunchKernelGGL(k_row_fwd<T>, dim3(nblk), dim3(FWD_THREADS), lds, st, src, (cpx<T>*)dst, nrows, nin, N2x, Kx,
                      P, (const cpx<T>*)tw, (const cpx<T>*)twp, ny3);
   return hipGetLastError();
 }
@@ -1109,19 +1148,19 @@ hipError_t launch_col(const void* spec1, void* spec2, const T* kern, int Kx, int
   }
   TickArgs ta{};
   if (tick) ta = *tick;
-  hipLaunchKernelGGL(k_col<T>, dim3(nblk), dim3(256), lds, st, (const cpx<T>*)spec1, (cpx<T>*)spec2, kern, Kx,
+  hipLaunchKernelGGL(k_col<T>, dim3(nblk), dim3(COL_THREADS), lds, st, (const cpx<T>*)spec1, (cpx<T>*)spec2, kern, Kx,
                      Ly, Kyh, ny, nin_ch, ngroup, nbuf, P, (const cpx<T>*)twy, tab, ta, tick ? tick_stage : -1,
                      tick_dt);
   return hipGetLastError();
 }
 
 hipError_t launch_tick(const TickArgs& tick, int stage, double dt, hipStream_t st) {
-  hipLaunchKernelGGL(k_tick, dim3(1), dim3(256), 0, st, tick, stage, dt);
+  hipLaunchKernelGGL(k_tick, dim3(1), dim3(TICK_THREADS), 0, st, tick, stage, dt);
   return hipGetLastError();
 }
 
 hipError_t launch_tick_batch(const ColDesc* d, int n, int stage, double dt, hipStream_t st) {
-  hipLaunchKernelGGL(k_tick_batch, dim3(n), dim3(256), 0, st, d, stage, dt);
+  hipLaunchKernelGGL(k_tick_batch, dim3(n), dim3(TICK_THREADS), 0, st, d, stage, dt);
   return hipGetLastError();
 }
 
@@ -1154,14 +1193,14 @@ hipError_t launch_row_stage(const RowParams& p, const void* spec2, const T* mst,
 
 template <typename T>
 hipError_t launch_row_fwd_batch(const RowFwdDesc* d, const int* start, int n, int nblk, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL(k_row_fwd_batch<T>, dim3(nblk), dim3(256), lds, st, d, start, n);
+  hipLaunchKernelGGL(k_row_fwd_batch<T>, dim3(nblk), dim3(FWD_THREADS), lds, st, d, start, n);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_col_batch(const ColDesc* d, const int* start, int n, int nblk, size_t lds, hipStream_t st,
                             int tick_stage, double tick_dt) {
-  hipLaunchKernelGGL(k_col_batch<T>, dim3(nblk), dim3(256), lds, st, d, start, n, tick_stage, tick_dt);
+  hipLaunchKernelGGL(k_col_batch<T>, dim3(nblk), dim3(COL_THREADS), lds, st, d, start, n, tick_stage, tick_dt);
   return hipGetLastError();
 }
 
@@ -1199,7 +1238,7 @@ template <typename T>
 hipError_t launch_colpack(const void* spec, T* out, int Kx, int Ly, int Kyh, const FftPlan& P, const void* twy,
                           int imag, hipStream_t st) {
   const size_t lds = sizeof(cpx<double>) * 3 * (size_t)Ly;
-  hipLaunchKernelGGL(k_colpack<T>, dim3(Kx), dim3(256), lds, st, (const cpx<double>*)spec, out, Kx, Ly, Kyh, P,
+  hipLaunchKernelGGL(k_colpack<T>, dim3(Kx), dim3(COLPACK_THREADS), lds, st, (const cpx<double>*)spec, out, Kx, Ly, Kyh, P,
                      (const cpx<double>*)twy, imag);
   return hipGetLastError();
 }
