@@ -48,7 +48,7 @@ __global__ void __launch_bounds__(CUBE_THREADS)
     const int c = t - r * nc;
     A[c * L + r] = r < n_in ? src[(size_t)r * ncols + c] : mk<T>(0, 0);
   }
-  __syncthreads();
+  lds_barrier();
   const cpx<T>* R = fft_lds<T, INV, CUBE_THREADS>(A, B, P, nc, L, stw);
   for (int t = threadIdx.x; t < nc * n_out; t += CUBE_THREADS) {
     const int r = fdiv(t, inc);
@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(CUBE_THREADS)
     const int b = t / (Lz - nz), z = nz + t - b * (Lz - nz);
     A[b * Lz + z] = mk<T>(0, 0);
   }
-  __syncthreads();
+  lds_barrier();
   cpx<T>* X = fft_lds<T, false, CUBE_THREADS>(A, B, P, 3 * nc, Lz, stw);
   const bool yup = ky >= Kyh;
   const int kyr = yup ? Ly - ky : ky;
@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(CUBE_THREADS)
     X[(1 * nc + cc) * Lz + kz] = o1;
     X[(2 * nc + cc) * Lz + kz] = o2;
   }
-  __syncthreads();
+  lds_barrier();
   cpx<T>* Y = fft_lds<T, true, CUBE_THREADS>(X, (X == A) ? B : A, P, 3 * nc, Lz, stw);
   for (int t = threadIdx.x; t < 3 * nz * nc; t += CUBE_THREADS) {
     const int cz = fdiv(t, inc);
@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(CUBE_THREADS)
   for (int t = threadIdx.x; t < N2x; t += CUBE_THREADS) stw[t] = tw[t];
   for (int t = threadIdx.x; t <= N2x; t += CUBE_THREADS) stp[t] = twp[t];
   const cpx<T>* X = spec + row * Kx;
-  __syncthreads();
+  lds_barrier();
   for (int k = threadIdx.x; k < N2x; k += CUBE_THREADS) {
     cpx<T> xk = X[k];
     cpx<T> xm = X[N2x - k];
@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(CUBE_THREADS)
     cpx<T> d = cmulc(xk - xm, stp[k]);
     a[k] = mk<T>(s.x - d.y, s.y + d.x);
   }
-  __syncthreads();
+  lds_barrier();
   const T* xr = reinterpret_cast<const T*>(fft_lds<T, true, CUBE_THREADS>(a, b, P, 1, N2x, stw));
   for (int i = threadIdx.x; i < nx; i += CUBE_THREADS) out[row * nx + i] = xr[i];
 }

@@ -191,6 +191,17 @@ __device__ __forceinline__ void stage_copy(V* dst, int n, F load) {
   }
 }
 
+// Block barrier for data exchanged through LDS only.  It waits for this
+// wave's LDS operations but not for its global loads: on this architecture
+// the workgroup fence of __syncthreads() waits for every outstanding
+// vector-memory operation, loads included, so a load issued ahead of its use
+// could not stay in flight across a barrier.  Not a fence for global memory.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // threadIdx.x, opaque to the optimiser: index arithmetic derived from it
 // is then recomputed where it is used instead of being hoisted out of an
 // enclosing loop and kept live (in registers or spilled) across it.
@@ -344,7 +355,7 @@ __device__ __forceinline__ cpx<T>* fft_ct_from(cpx<T>* a, cpx<T>* b, int batch, 
   } else {
     constexpr int R = pl.r[P];
     stockham_ct<T, L, NT, R, Ns, INV, HALF>(a, b, batch, tw);
-    __syncthreads();
+    lds_barrier();
     return fft_ct_from<T, L, NT, INV, HALF, P + 1, Ns * R>(b, a, batch, tw);
   }
 }
@@ -357,8 +368,8 @@ __host__ __device__ constexpr bool has_cplan(int L) {
 // Batched in-LDS FFT of `batch` transforms of length P.L, transform t at
 // a + t*stride.  Ping-pongs between a and b; returns the buffer holding the
 // result.  Unnormalised.  Must be entered by the whole block after the data
-// are in place and visible (a __syncthreads() before the call); ends with
-// a __syncthreads().
+// are in place and visible (an lds_barrier() before the call); ends with
+// an lds_barrier().
 template <typename T, bool INV, int NT>
 __device__ __forceinline__ cpx<T>* fft_lds_generic(cpx<T>* a, cpx<T>* b, const FftPlan& P, int batch, int stride,
                                    const cpx<T>* __restrict__ tw, int twh) {
@@ -373,7 +384,7 @@ __device__ __forceinline__ cpx<T>* fft_lds_generic(cpx<T>* a, cpx<T>* b, const F
       case 5: stockham_pass<T, 5, INV, NT>(a, b, L, Ns, batch, stride, tw, twh); break;
       default: stockham_pass<T, 7, INV, NT>(a, b, L, Ns, batch, stride, tw, twh); break;
     }
-    __syncthreads();
+    lds_barrier();
     cpx<T>* tmp = a;
     a = b;
     b = tmp;

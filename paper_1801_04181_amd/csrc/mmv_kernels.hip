@@ -58,7 +58,7 @@ __device__ __forceinline__ void row_fwd_body(int row0, int nb, int rstride, cons
     const int i0 = 2 * n, i1 = 2 * n + 1;
     a[t] = mk<T>(i0 < nin ? s[i0] : T(0), i1 < nin ? s[i1] : T(0));
   }
-  __syncthreads();
+  lds_barrier();
   cpx<T>* Z = fft_lds<T, false, FWD_THREADS>(a, b, P, nb, N2x, stw);
   const int K1 = N2x + 1;
   const float ink = 1.0f / (float)K1;
@@ -159,18 +159,16 @@ __device__ __forceinline__ void col_body(int blk, const cpx<T>* __restrict__ spe
     const int y = t - ch * Ly;
     return (y < ny) ? spec1[((size_t)ch * Kx + kx) * ny + y] : mk<T>(0, 0);
   });
-  __syncthreads();
-  const int twh = (Ly & 1) ? 0 : Lh;
-  cpx<T>* X = fft_lds<T, false, COL_THREADS>(A, B, P, nin_ch, Ly, stw, twh);
-  cpx<T>* W = (X == A) ? B : A;
+  lds_barrier();
   // one thread per (output, |ky|): the kernel value at |ky| (the stored half)
   // serves both ky and Ly - ky.  The kernel values of PF pairs per thread
-  // are loaded before any is used, so their latencies overlap.
+  // are loaded together; the first PF are issued before the forward
+  // transforms, so their latency overlaps them.
   const int npair = no * Kyh;
   const float invK = 1.0f / (float)Kyh;
   constexpr int PF = 4;
-  for (int t0 = 0; t0 < npair; t0 += PF * COL_THREADS) {
-    T kv[PF][3];
+  T kv[PF][3];
+  auto load_kv = [&](int t0) {
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       const int t = t0 + u * COL_THREADS + (int)threadIdx.x;
@@ -182,6 +180,14 @@ __device__ __forceinline__ void col_body(int blk, const cpx<T>* __restrict__ spe
         kv[u][b] = ko < 0 ? T(0) : kern[ko + kyr];
       }
     }
+  };
+  load_kv(0);
+  const int twh = (Ly & 1) ? 0 : Lh;
+  cpx<T>* X = fft_lds<T, false, COL_THREADS>(A, B, P, nin_ch, Ly, stw, twh);
+  cpx<T>* W = (X == A) ? B : A;
+#pragma unroll 1
+  for (int t0 = 0; t0 < npair; t0 += PF * COL_THREADS) {
+    if (t0 > 0) load_kv(t0);
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       const int t = t0 + u * COL_THREADS + (int)threadIdx.x;
@@ -217,7 +223,7 @@ __device__ __forceinline__ void col_body(int blk, const cpx<T>* __restrict__ spe
       if (two) W[o * Ly + ky2] = a2;
     }
   }
-  __syncthreads();
+  lds_barrier();
   cpx<T>* Y = fft_lds<T, true, COL_THREADS>(W, X, P, no, Ly, stw, twh);
   for (int o = 0; o < no; ++o) {
     const OutCh& oc = tab.ch[o0 + o];
@@ -240,13 +246,13 @@ __device__ __forceinline__ void tick_body(const TickArgs& a, int stage, double d
   for (int t = threadIdx.x; t < a.ntask; t += TICK_THREADS) v += a.partial[(size_t)t * 3];
   v = wave_sum(v);
   if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = v;
-  __syncthreads();
+  lds_barrier();
   if (threadIdx.x == 0) {
     double F = 0.0;
     for (int w = 0; w < (TICK_THREADS + 63) >> 6; ++w) F += s_red[w];
     rigid_stage(a.rigid, a.drive, stage, a.force_scale * F, dt, a.dx, a.travel);
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 template <typename T>
@@ -329,9 +335,52 @@ __device__ __forceinline__ cpx<T>* c2r_rows(const cpx<T>* __restrict__ base, con
     const cpx<T>* X = base + rowo[b];
     return c2r_twist(X[k], X[N2x - k], stp[k]);
   });
-  __syncthreads();
+  lds_barrier();
   return fft_lds<T, true, NT>(fa, fb, P, nb, N2x, stw);
 }
+
+// Inputs of the first batch of inverse row transforms, held in registers:
+// issued early in the row kernel's set-up, they stay in flight across the
+// LDS-only barriers and are folded into the half-length input by finish()
+// once the twiddles are in LDS.  A thread holds CP elements; finish() loads
+// and folds any further ones itself.
+template <typename T, int NT, int CP>
+struct C2rInputs {
+  cpx<T> xk[CP], xm[CP];
+  __device__ __forceinline__ void issue(const cpx<T>* __restrict__ base, const long long* rowo, int tot, int N2x) {
+    const float inv = 1.0f / (float)N2x;
+#pragma unroll
+    for (int u = 0; u < CP; ++u) {
+      const int t = (int)threadIdx.x + u * NT;
+      if (t < tot) {
+        const int b = fdiv(t, inv);
+        const int k = t - b * N2x;
+        const cpx<T>* X = base + rowo[b];
+        xk[u] = X[k];
+        xm[u] = X[N2x - k];
+      }
+    }
+  }
+  __device__ __forceinline__ void finish(const cpx<T>* __restrict__ base, const long long* rowo, int tot, int N2x,
+                                         cpx<T>* fa, const cpx<T>* stp) {
+    const float inv = 1.0f / (float)N2x;
+#pragma unroll
+    for (int u = 0; u < CP; ++u) {
+      const int t = (int)threadIdx.x + u * NT;
+      if (t < tot) {
+        const int k = t - fdiv(t, inv) * N2x;
+        fa[t] = c2r_twist(xk[u], xm[u], stp[k]);
+      }
+    }
+#pragma unroll 1
+    for (int t = (int)threadIdx.x + CP * NT; t < tot; t += NT) {
+      const int b = fdiv(t, inv);
+      const int k = t - b * N2x;
+      const cpx<T>* X = base + rowo[b];
+      fa[t] = c2r_twist(X[k], X[N2x - k], stp[k]);
+    }
+  }
+};
 
 // Spline value at window coordinate u = k0 + frac: sum_q g_q ext(k0 + q).
 template <typename T, int K>
@@ -539,10 +588,16 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   // only after every block of the launch has read it)
   const double xs = rigid->xs;
   const int s_int = rigid->s_int;
-  // twiddles: stw (N2x) and stp (N2x + 1) are contiguous
-  stage_copy<4, NT>(stw, 2 * N2x + 1, [&](int t) { return t < N2x ? tw[t] : twp[t - N2x]; });
-#pragma unroll 1
-  for (int t = threadIdx.x; t < 3 * nx; t += NT) H[t] = T(0);
+  // twiddles (stw: N2x, stp: N2x + 1, contiguous): loads issued before the
+  // row table is built, stored after it
+  constexpr int TWR = 2;
+  const int ntw = 2 * N2x + 1;
+  cpx<T> tv[TWR];
+#pragma unroll
+  for (int u = 0; u < TWR; ++u) {
+    const int t = (int)threadIdx.x + u * NT;
+    if (t < ntw) tv[u] = t < N2x ? tw[t] : twp[t - N2x];
+  }
   if (closed) {
 #pragma unroll 1
     for (int i = threadIdx.x; i < n_tot; i += NT) {
@@ -617,6 +672,23 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     }
     s_nrow = n;
   }
+#pragma unroll
+  for (int u = 0; u < TWR; ++u) {
+    const int t = (int)threadIdx.x + u * NT;
+    if (t < ntw) stw[t] = tv[u];
+  }
+#pragma unroll 1
+  for (int t = (int)threadIdx.x + TWR * NT; t < ntw; t += NT) stw[t] = t < N2x ? tw[t] : twp[t - N2x];
+  lds_barrier();  // row table, twiddles
+  const int nrow = s_nrow;
+  // the first batch's transform inputs: issued now, consumed after the
+  // spline weights
+  constexpr int CP = (sizeof(T) == 4 && 4096 / NT > 4) ? 4096 / NT : 4;
+  C2rInputs<T, NT, CP> in0;
+  const int tot0 = min(nbr, nrow) * N2x;
+  in0.issue(spec2, rowo, tot0, N2x);
+#pragma unroll 1
+  for (int t = threadIdx.x; t < 3 * nx; t += NT) H[t] = T(0);
 
   double xp = xs / p.dx - (double)s_int;
   const bool xp_bad = !(xp >= -1.0 && xp < 2.0);
@@ -647,7 +719,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
       }
       wterm[u] = v;
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll 1
     for (int tq = threadIdx.x; tq < 2 * NQ; tq += NT) {
       double g = 0.0;
@@ -655,14 +727,16 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
       (tq < NQ ? gs : gb)[tq % NQ] = (T)g;
     }
   }
-  __syncthreads();
-  const int nrow = s_nrow;
+  in0.finish(spec2, rowo, tot0, N2x, fa, stp);
+  lds_barrier();
   const int W0c = (film == 1) ? s_int - h : -s_int - h;  // cross window start
   const int W0f = s_int - h;                              // force windows (base field)
 
   for (int b0 = 0; b0 < nrow; b0 += nbr) {
     const int bn = min(nbr, nrow - b0);
-    cpx<T>* Z = c2r_rows<T, NT>(spec2, rowo + b0, bn, fa, fb, N2x, p.px, stw, stp);
+    // the first batch's half-length inputs were formed during the set-up
+    cpx<T>* Z = b0 == 0 ? fft_lds<T, true, NT>(fa, fb, p.px, bn, N2x, stw)
+                        : c2r_rows<T, NT>(spec2, rowo + b0, bn, fa, fb, N2x, p.px, stw, stp);
     const T* xr = reinterpret_cast<const T*>(Z);
     // self rows -> H, spline rows -> windows with mirror extension
     const float invMW = 1.0f / (float)MW;
@@ -691,7 +765,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
         ext[(size_t)r * MWS + k] = row[X];
       }
     }
-    __syncthreads();
+    lds_barrier();
     const int NP = nx + 6;  // outputs i = -3 .. nx+2
     const int NB2 = (NP + 1) >> 1;
     const float invNB = 1.0f / (float)NB2;
@@ -734,7 +808,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
 
   if (need_cross && p.pot) {
@@ -775,7 +849,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
           }
         }
     }
-    __syncthreads();
+    lds_barrier();
   }
 
   // --- per cell: local terms, LLG stage, force partials
@@ -787,7 +861,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
       const int c = t / nx, i = t - c * nx;
       H[t] += sc * (T)p.hsur[(size_t)c * plane + (size_t)y * nx + i];
     }
-    __syncthreads();
+    lds_barrier();
   }
   double fpart[3] = {0.0, 0.0, 0.0};
   const T* ms = mst + (size_t)film * 3 * plane;
@@ -908,7 +982,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   }
   if (fuse) {
     // forward real transform of the three rows (as the x pass computes it)
-    __syncthreads();
+    lds_barrier();
     const cpx<T>* Z = fft_lds<T, false, NT>(fa, fb, p.px, 3, N2x, stw);
     cpx<T>* dst = reinterpret_cast<cpx<T>*>(p.spec1_out);
     const int K1 = N2x + 1;
@@ -968,7 +1042,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     const double v = wave_sum(fpart[a]);
     if (lane == 0) red[wv * 3 + a] = v;
   }
-  __syncthreads();
+  lds_barrier();
   if (p.mode == MODE_EVAL) return;
   if (p.mode == MODE_STAGE && p.defer_tick) {
     // partials only; the slider update runs after this launch
