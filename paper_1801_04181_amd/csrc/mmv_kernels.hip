@@ -382,21 +382,20 @@ struct C2rInputs {
   }
 };
 
-// Spline value at window coordinate u = k0 + frac: sum_q g_q ext(k0 + q).
-template <typename T, int K>
-__device__ __forceinline__ T fir_eval(const T* ext, const T* g, int k0, int E) {
-  const T* p = ext + E + k0 - K - 1;
-  T acc = 0;
-#pragma unroll
-  for (int q = 0; q < 2 * K + 4; ++q) acc += g[q] * p[q];
-  return acc;
-}
+// Two consecutive spline values at window coordinates k0 + frac and
+// k0 + 1 + frac: o_j = sum_q g_q ext(k0 + j - K - 1 + q), q = 0 .. 2K+3, summed
+// in q order, from one register window (neighbouring lanes read windows two
+// samples apart, which keeps the LDS reads free of bank conflicts).  The window is
+// read in pairs from the even-aligned sample at or below its start (PAR =
+// parity of the start) and the weights in 16-byte vectors: g must be 16-byte
+// aligned and the window row even-aligned, with one readable sample past
+// the 2K+5 the taps use.
+template <typename T> struct alignas(2 * sizeof(T)) Pair { T x, y; };
 
-// Two consecutive spline values k0, k0+1 from one register window (same tap
-// order per output as fir_eval; neighbouring lanes read windows two samples
-// apart, which keeps the LDS reads free of bank conflicts).
+// Scalar-read form of the same sums (float64: its 2K+5-sample window already
+// fills half the register file).
 template <typename T, int K>
-__device__ __forceinline__ void fir_eval2(const T* ext, const T* g, int k0, int E, T& o0, T& o1) {
+__device__ __forceinline__ void fir_eval2s(const T* ext, const T* g, int k0, int E, T& o0, T& o1) {
   constexpr int NQ = 2 * K + 4;
   const T* p = ext + E + k0 - K - 1;
   T w[NQ + 1];
@@ -408,6 +407,41 @@ __device__ __forceinline__ void fir_eval2(const T* ext, const T* g, int k0, int 
     const T gq = g[q];
     a0 += gq * w[q];
     a1 += gq * w[q + 1];
+  }
+  o0 = a0;
+  o1 = a1;
+}
+
+template <typename T, int K, int PAR>
+__device__ __forceinline__ void fir_eval2(const T* ext, const T* g, int k0, int E, T& o0, T& o1) {
+  constexpr int NQ = 2 * K + 4;
+  constexpr int NW = NQ + 2;  // samples read: taps of both outputs plus the parity shift
+  constexpr int GV = 16 / sizeof(T);
+  static_assert(NQ % GV == 0 && NW % 2 == 0, "vector widths");
+  const Pair<T>* p = reinterpret_cast<const Pair<T>*>(ext + E + k0 - K - 1 - PAR);
+  T w[NW];
+#pragma unroll
+  for (int j = 0; j < NW / 2; ++j) {
+    const Pair<T> v = p[j];
+    w[2 * j] = v.x;
+    w[2 * j + 1] = v.y;
+  }
+  T a0 = 0, a1 = 0;
+#pragma unroll
+  for (int q0 = 0; q0 < NQ; q0 += GV) {
+    T gv[GV];
+    if constexpr (GV == 4) {
+      const float4 v = *reinterpret_cast<const float4*>(g + q0);
+      gv[0] = v.x; gv[1] = v.y; gv[2] = v.z; gv[3] = v.w;
+    } else {
+      const Pair<T> v = *reinterpret_cast<const Pair<T>*>(g + q0);
+      gv[0] = v.x; gv[1] = v.y;
+    }
+#pragma unroll
+    for (int u = 0; u < GV; ++u) {
+      a0 += gv[u] * w[q0 + u + PAR];
+      a1 += gv[u] * w[q0 + u + 1 + PAR];
+    }
   }
   o0 = a0;
   o1 = a1;
@@ -490,14 +524,15 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nx = p.nx, ny = p.ny, N2x = p.N2x, M = p.M, Lx = 2 * N2x, nbr = p.nbr;
   const int MW = M + 2 * E;
-  const int MWS = MW + 4;  // row stride of the windows (slack for the paired FIR outputs)
+  const int MWS = (MW + 5) & ~1;  // even row stride of the windows, >= MW + 4 (slack for the paired FIR reads)
   const int nfc = p.full_force ? 3 : 1;
   cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* stp = stw + N2x;
   cpx<T>* fa = stp + N2x + 1;
   cpx<T>* fb = fa + (size_t)nbr * N2x;
   T* ext = reinterpret_cast<T*>(fb + (size_t)nbr * N2x);  // [nbr][MW]
-  T* gs = ext + (size_t)nbr * MWS;  // weights, slider samples base field
+  // weights, slider samples base field (16-byte aligned for vector reads)
+  T* gs = reinterpret_cast<T*>(smem_raw + ((static_cast<size_t>(reinterpret_cast<unsigned char*>(ext + (size_t)nbr * MWS) - smem_raw) + 15) & ~size_t(15)));
   T* gb = gs + NQ;                 // weights, base samples slider field
   T* H = gb + NQ;                  // [3][nx] demag accumulation
   T* gc = H + 3 * nx;              // [3][nx+2] slider cross field at i = -1..nx
@@ -779,10 +814,19 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
       // the base film samples the slider's field (and potential) at -x_p
       const bool base = film == 0 && (kind < RK_FP || (kind >= RK_PHI && kind < RK_XB));
       T v[2];
-      if (base)
-        fir_eval2<T, K>(e, gb, i0 + h + ifb, E, v[0], v[1]);
-      else
-        fir_eval2<T, K>(e, gs, i0 + h + ifs, E, v[0], v[1]);
+      if constexpr (sizeof(T) == 8) {
+        if (base)
+          fir_eval2s<T, K>(e, gb, i0 + h + ifb, E, v[0], v[1]);
+        else
+          fir_eval2s<T, K>(e, gs, i0 + h + ifs, E, v[0], v[1]);
+      } else {
+        const int k0 = i0 + h + (base ? ifb : ifs);
+        const T* g = base ? gb : gs;
+        if ((k0 + E - K - 1) & 1)
+          fir_eval2<T, K, 1>(e, g, k0, E, v[0], v[1]);
+        else
+          fir_eval2<T, K, 0>(e, g, k0, E, v[0], v[1]);
+      }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const int i = i0 + j;
@@ -1244,8 +1288,8 @@ size_t row_lds_bytes(const RowParams& p) {
   const int nfc = p.full_force ? 3 : 1;
   size_t b = sizeof(cpx<T>) * (size_t)(2 * p.N2x + 1 + 2 * (size_t)p.nbr * p.N2x);
   const int nslot = p.pot ? (p.full_force ? 19 : 9) : 0;
-  b += sizeof(T) * ((size_t)p.nbr * (p.M + 2 * E + 4) + 2 * NQ + 3 * p.nx + 3 * (p.nx + 2) + 2 * nfc * p.nx +
-                    (size_t)nslot * (p.nx + 6) + 2 * (size_t)p.nx + 2);
+  b += sizeof(T) * ((size_t)p.nbr * ((p.M + 2 * E + 5) & ~1) + 2 * NQ + 3 * p.nx + 3 * (p.nx + 2) + 2 * nfc * p.nx +
+                    (size_t)nslot * (p.nx + 6) + 2 * (size_t)p.nx + 2) + 16;  // + alignment of the weights
   b = (b + 15) & ~size_t(15);
   b += sizeof(double) * (96 + 8 * NQ) + 16;  // wave partials of the force reduction, spline-weight terms
   return b;
