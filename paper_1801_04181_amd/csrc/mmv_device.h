@@ -360,11 +360,6 @@ __device__ __forceinline__ cpx<T>* fft_ct_from(cpx<T>* a, cpx<T>* b, int batch, 
   }
 }
 
-// Lengths with compiled plans (film x and y transforms of the workloads).
-__host__ __device__ constexpr bool has_cplan(int L) {
-  return L == 270 || L == 525 || L == 135 || L == 140 || L == 72;
-}
-
 // Batched in-LDS FFT of `batch` transforms of length P.L, transform t at
 // a + t*stride.  Ping-pongs between a and b; returns the buffer holding the
 // result.  Unnormalised.  Must be entered by the whole block after the data
@@ -393,8 +388,9 @@ __device__ __forceinline__ cpx<T>* fft_lds_generic(cpx<T>* a, cpx<T>* b, const F
   return a;
 }
 
-// Dispatch: compiled plan for contiguous transforms of a known length, else
-// the generic runtime-plan passes; NT = the launch's block size.
+// Dispatch: compiled plans for contiguous transforms of the workloads'
+// lengths (270, 525, 135, 140, 72 points), else the generic runtime-plan
+// passes; NT = the launch's block size.
 template <typename T, bool INV, int NT>
 __device__ __forceinline__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, const FftPlan& P, int batch, int stride,
                            const cpx<T>* __restrict__ tw, int twh = 0) {
