@@ -178,6 +178,15 @@ int batch_instance(mmv_batch_handle b, int i, mmv_handle* out);
 int batch_step(mmv_batch_handle b, double dt, int nsteps);
 /* Chosen y-pass grouping of instance i (diagnostics).                   */
 int batch_tuning(mmv_batch_handle b, int i, int* col_groups);
+/* Tuning cache for MMV_BATCH_AUTOTUNE (process-wide; NULL or "" = none).
+ * A text file, one line per tuned mesh size: a key naming the device (arch,
+ * CU count), the precision, the batch's size mix and the size, a tab, and
+ * the chosen y-pass grouping.  init_batch reads it, times only the sizes not
+ * in it and rewrites the file (temporary file + rename) with the new
+ * results; malformed lines are ignored, a failed write is reported on
+ * stderr and does not fail init_batch.  The path is copied.  MMV_EINVAL
+ * for a path of 4096 bytes or more.                                      */
+int set_tune_cache(const char* path);
 int destroy_batch(mmv_batch_handle b);
 
 /* Release every device buffer of the handle.  NULL is accepted.         */

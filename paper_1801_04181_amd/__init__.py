@@ -13,7 +13,7 @@ __all__ = ["MMVError", "lib_path", "load", "MeshDesc", "DriveDesc", "init_mesh",
            "set_m", "get_m", "set_offset", "set_drive", "eval_heff", "llg_step",
            "stray_force", "get_state", "get_fft_lengths", "destroy_mesh",
            "profile_begin", "profile_end", "profile_repeat", "init_batch", "batch_instance", "batch_step",
-           "batch_tuning", "destroy_batch", "Batch", "SurDesc", "sur_create", "sur_param_count",
+           "batch_tuning", "set_tune_cache", "destroy_batch", "Batch", "SurDesc", "sur_create", "sur_param_count",
            "sur_param_offsets", "sur_set_params", "sur_get_params", "sur_forward", "sur_gradient",
            "sur_train_step", "sur_gemm_bf16", "sur_destroy", "sur_attach", "sur_status", "Surrogate",
            "last_error", "Mesh", "TERM", "EXPORTS"]
@@ -28,7 +28,7 @@ ERRORS = {-1: "MMV_EINVAL", -2: "MMV_ENOMEM", -3: "MMV_EHIP", -4: "MMV_ERANGE",
 EXPORTS = ("init_mesh", "set_m", "get_m", "set_offset", "set_drive", "eval_heff",
            "llg_step", "stray_force", "get_state", "profile_begin", "profile_end",
            "get_fft_lengths", "profile_repeat", "init_batch", "batch_instance", "batch_step", "batch_tuning",
-           "destroy_batch", "destroy_mesh", "sur_create", "sur_param_count", "sur_param_offsets",
+           "set_tune_cache", "destroy_batch", "destroy_mesh", "sur_create", "sur_param_count", "sur_param_offsets",
            "sur_set_params", "sur_get_params", "sur_forward", "sur_gradient", "sur_train_step",
            "sur_gemm_bf16", "sur_destroy", "sur_attach", "sur_status", "mmv_last_error")
 BATCH_AUTOTUNE, BATCH_GRAPH = 1, 2
@@ -96,6 +96,7 @@ def load():
         lib.batch_instance.argtypes = [vp, i, ctypes.POINTER(vp)]
         lib.batch_step.argtypes = [vp, d, i]
         lib.batch_tuning.argtypes = [vp, i, ctypes.POINTER(i)]
+        lib.set_tune_cache.argtypes = [ctypes.c_char_p]
         lib.destroy_batch.argtypes = [vp]
         lib.profile_end.argtypes = [vp, pd, ctypes.POINTER(ctypes.c_long)]
         lib.profile_repeat.argtypes = [vp, i, i, pd]
@@ -262,6 +263,11 @@ def batch_tuning(b, i):
     g = ctypes.c_int()
     _check(load().batch_tuning(b, int(i), ctypes.byref(g)))
     return g.value
+
+
+def set_tune_cache(path):
+    """Tuning cache file for MMV_BATCH_AUTOTUNE (None or "" = none)."""
+    _check(load().set_tune_cache(None if not path else os.fsencode(path)))
 
 
 def destroy_batch(b):

@@ -5,9 +5,11 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <unistd.h>
 #include <string>
 #include <vector>
 #include <algorithm>
+#include <map>
 #include "mmv.h"
 #include "mmv_internal.h"
 #include "mmv_kernels.h"
@@ -1106,8 +1108,69 @@ int batch_step_typed(mmv_batch* b, double dt, int nsteps) {
   return batch_launch_steps<T>(b, b->st, dt, nsteps - done);
 }
 
+// Tuning cache on disk (process-wide path; empty = none).  One line per
+// tuned mesh size: "<key>\t<groups>", the key naming the device (arch, CU
+// count), the precision, the batch's size mix (FNV-1a over the instances'
+// (Kx, Ly) in order) and the size.  Unreadable or malformed lines are
+// ignored; the file is rewritten whole (temporary file + rename).
+std::string g_tune_cache;
+
+std::map<std::string, int> tune_cache_read(const std::string& path) {
+  std::map<std::string, int> m;
+  FILE* f = fopen(path.c_str(), "r");
+  if (!f) return m;
+  char line[512];
+  while (fgets(line, sizeof line, f)) {
+    char* tab = strchr(line, '\t');
+    if (!tab) continue;
+    *tab = 0;
+    char* end = nullptr;
+    const long g = strtol(tab + 1, &end, 10);
+    if (end == tab + 1 || g < 1 || g > 8) continue;
+    m[line] = (int)g;
+  }
+  fclose(f);
+  return m;
+}
+
+bool tune_cache_write(const std::string& path, const std::map<std::string, int>& m) {
+  const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  bool ok = true;
+  for (const auto& kv : m) ok = ok && fprintf(f, "%s\t%d\n", kv.first.c_str(), kv.second) > 0;
+  ok = (fclose(f) == 0) && ok;
+  if (ok) ok = rename(tmp.c_str(), path.c_str()) == 0;
+  if (!ok) remove(tmp.c_str());
+  return ok;
+}
+
+std::string tune_key(const mmv_batch* b, const std::pair<int, int>& sz) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  memset(&prop, 0, sizeof prop);
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return std::string();
+  unsigned long long hsh = 1469598103934665603ull;
+  auto mix = [&](unsigned v) {
+    for (int k = 0; k < 4; ++k) {
+      hsh ^= (v >> (8 * k)) & 0xffu;
+      hsh *= 1099511628211ull;
+    }
+  };
+  for (const mmv_mesh* h : b->inst) {
+    mix((unsigned)h->Kx);
+    mix((unsigned)h->Ly);
+  }
+  char buf[320];
+  snprintf(buf, sizeof buf, "%s cu%d f%d n%d mix%016llx Kx%d Ly%d", prop.gcnArchName, prop.multiProcessorCount,
+           b->esz * 8, (int)b->inst.size(), hsh, sz.first, sz.second);
+  return std::string(buf);
+}
+
 // Autotuner: per mesh size, time the batched y pass for each grouping of
-// that size's instances (others fixed) and keep the fastest.
+// that size's instances (others fixed) and keep the fastest.  With a tuning
+// cache, sizes tuned before for the same device, precision and size mix take
+// the stored grouping without timing; new results are added to the file.
 template <typename T>
 int batch_autotune(mmv_batch* b) {
   std::vector<std::pair<int, int>> sizes;
@@ -1115,11 +1178,22 @@ int batch_autotune(mmv_batch* b) {
     std::pair<int, int> k(h->Kx, h->Ly);
     if (std::find(sizes.begin(), sizes.end(), k) == sizes.end()) sizes.push_back(k);
   }
+  const bool use_cache = !g_tune_cache.empty();
+  std::map<std::string, int> cache;
+  if (use_cache) cache = tune_cache_read(g_tune_cache);
+  bool added = false;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   const int n = (int)b->inst.size();
   for (auto& sz : sizes) {
+    const std::string key = use_cache ? tune_key(b, sz) : std::string();
+    auto hit = key.empty() ? cache.end() : cache.find(key);
+    if (hit != cache.end()) {
+      for (mmv_mesh* h : b->inst)
+        if (h->Kx == sz.first && h->Ly == sz.second) h->ngroup = hit->second;
+      continue;
+    }
     int best = b->inst[0]->ngroup;
     float best_ms = 1e30f;
     for (int g : {1, 2, 3, 4}) {
@@ -1141,9 +1215,15 @@ int batch_autotune(mmv_batch* b) {
     }
     for (mmv_mesh* h : b->inst)
       if (h->Kx == sz.first && h->Ly == sz.second) h->ngroup = best;
+    if (!key.empty()) {
+      cache[key] = best;
+      added = true;
+    }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
+  if (added && !tune_cache_write(g_tune_cache, cache))
+    fprintf(stderr, "mmv: could not write the tuning cache %s\n", g_tune_cache.c_str());
   return batch_build<T>(b);
 }
 
@@ -1405,6 +1485,12 @@ int batch_step(mmv_batch_handle b, double dt, int nsteps) {
   if (!(dt > 0) || !isfinite(dt)) return fail(MMV_EINVAL, "dt must be finite and > 0");
   if (nsteps < 0) return fail(MMV_EINVAL, "nsteps must be >= 0");
   return b->esz == 8 ? batch_step_typed<double>(b, dt, nsteps) : batch_step_typed<float>(b, dt, nsteps);
+}
+
+int set_tune_cache(const char* path) {
+  if (path && strlen(path) >= 4096) return fail(MMV_EINVAL, "tuning cache path too long");
+  g_tune_cache = path ? path : "";
+  return MMV_OK;
 }
 
 int batch_tuning(mmv_batch_handle b, int i, int* col_groups) {

@@ -63,6 +63,17 @@ def test_null_handle_and_pointers():
     assert lib.stray_force(None, F) == -1
 
 
+def test_tune_cache_path_checks():
+    """The tuning-cache path is validated and copied; clearing it is always
+    accepted (no GPU call is made)."""
+    with pytest.raises(mmv.MMVError) as e:
+        mmv.set_tune_cache("x" * 5000)
+    assert e.value.code == -1 and "too long" in str(e.value)
+    mmv.set_tune_cache("/tmp/some_cache_file")
+    mmv.set_tune_cache("")
+    mmv.set_tune_cache(None)
+
+
 def test_potential_mode_needs_two_films():
     d = get_config("tiny_potential")["desc"].replace(n_films=1)
     with pytest.raises(mmv.MMVError) as e:

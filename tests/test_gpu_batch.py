@@ -107,3 +107,43 @@ def test_autotune_choice_is_valid_and_harmless():
             assert np.array_equal(state(mmv, T.h[i], p["desc"])[0][f], state(mmv, U.h[i], p["desc"])[0][f])
     T.close()
     U.close()
+
+
+def test_tuning_cache_is_written_and_read_back(tmp_path):
+    """The first autotuned batch writes one line per mesh size; a second batch
+    of the same mix takes the stored groupings without timing (an edited
+    entry is honoured and left in place)."""
+    import paper_1801_04181_amd as mmv
+    pairs = small_pairs(8, 2)
+    ms = [initial_state(p) for p in pairs]
+    descs = [p["desc"] for p in pairs]
+    drives = [p["drive"] for p in pairs]
+    path = tmp_path / "tune.txt"
+    sizes = {(d.nx, d.ny) for d in descs}
+    try:
+        mmv.set_tune_cache(str(path))
+        T = mmv.Batch(descs, drives, ms, flags=mmv.BATCH_AUTOTUNE)
+        groups = [T.tuning(i) for i in range(len(pairs))]
+        T.close()
+        lines = path.read_text().splitlines()
+        print("cache", lines, flush=True)
+        assert len(lines) == len(sizes)
+        stored = {}
+        for ln in lines:
+            key, g = ln.split("\t")
+            assert "gfx" in key and " f32 " in key
+            stored[key] = int(g)
+        assert set(stored.values()) <= set(groups)
+        # edit every entry to another valid grouping
+        edited = {k: (3 if g != 3 else 1) for k, g in stored.items()}
+        path.write_text("".join(f"{k}\t{g}\n" for k, g in edited.items()) + "malformed line\n")
+        U = mmv.Batch(descs, drives, ms, flags=mmv.BATCH_AUTOTUNE)
+        regroup = [U.tuning(i) for i in range(len(pairs))]
+        U.close()
+        for i, g in enumerate(groups):
+            assert regroup[i] == (3 if g != 3 else 1), (i, g, regroup[i])
+        # nothing was re-timed, so the file keeps the edited entries
+        kept = dict(ln.split("\t") for ln in path.read_text().splitlines() if "\t" in ln)
+        assert {k: int(v) for k, v in kept.items()} == edited
+    finally:
+        mmv.set_tune_cache(None)
