@@ -98,7 +98,12 @@ typedef struct {
  * spectra on the GPU in float64 (Sec. III.A: the tensor is computed once,
  * Fourier transformed and kept on the GPU).  hip_stream is a hipStream_t
  * (NULL = default stream).  Magnetisation starts at +z, slider at x = 0,
- * drive frozen, t = 0.  On success *out receives the handle.           */
+ * drive frozen, t = 0.  On success *out receives the handle.
+ * Size limits of the film path (a film row and a spectrum column each
+ * live in one CU's 160 KB of LDS): with the default halo and travel, nx up
+ * to 1736 (float32) / 849 (float64) and ny up to 809 / 404; beyond them,
+ * or for a kernel-spectrum table of 2^31 elements or more, MMV_EINVAL
+ * before any device call.                                                */
 int init_mesh(const mmv_mesh_desc* d, void* hip_stream, mmv_handle* out);
 
 /* Copy a film's magnetisation from / to a caller device buffer

@@ -400,21 +400,47 @@ int build_kernels(mmv_mesh* h) {
   return MMV_OK;
 }
 
+// Size limits set by the LDS of the row and y-pass kernels and by the 32-bit
+// kernel-spectrum index, from the descriptor and the channel tables alone
+// (checked before any device call).
+template <typename T>
+int check_sizes(const mmv_mesh* h) {
+  const size_t lds_limit = 160 * 1024;
+  RowParams probe{};
+  probe.nx = h->nx;
+  probe.N2x = h->N2x;
+  probe.M = h->M;
+  probe.nbr = 1;
+  probe.full_force = 1;
+  probe.pot = h->d.cross_mode == 1;
+  if (row_lds_bytes<T>(probe) > lds_limit) return fail(MMV_EINVAL, "nx too large for the row kernel's LDS");
+  if (sizeof(T) * 2 * (4 * (size_t)h->N2x + 1) > lds_limit) return fail(MMV_EINVAL, "nx too large");
+  if ((long long)h->nkc * h->Kx * h->Kyh >= (1LL << 31)) return fail(MMV_EINVAL, "kernel spectra too large");
+  const int nin = 3 * h->nfilm;
+  const int nmax = h->tab_force.n > h->tab_hot.n ? h->tab_force.n : h->tab_hot.n;
+  for (int g = 1; g <= 8; ++g) {
+    const int per = (nmax + g - 1) / g;
+    if (col_lds_bytes<T>(h->Ly, nin > per ? nin : per) <= lds_limit) return MMV_OK;
+  }
+  return fail(MMV_EINVAL, "ny too large for the y pass");
+}
+
 template <typename T>
 int init_typed(mmv_mesh* h) {
   const mmv_mesh_desc& d = h->d;
   h->esz = sizeof(T);
   const size_t ncell = (size_t)h->nfilm * h->nx * h->ny;
   int rc;
+  long long n_hot = 0, n_force = 0;
+  assign_channels(h);
+  build_tables(h, false, h->tab_hot, h->rp_hot, n_hot);
+  build_tables(h, true, h->tab_force, h->rp_force, n_force);
+  if ((rc = check_sizes<T>(h))) return rc;
   if ((rc = dalloc(h, &h->m0, 3 * ncell * sizeof(T)))) return rc;
   if ((rc = dalloc(h, &h->mb[0], 3 * ncell * sizeof(T)))) return rc;
   if ((rc = dalloc(h, &h->mb[1], 3 * ncell * sizeof(T)))) return rc;
   if ((rc = dalloc(h, &h->acc, 3 * ncell * sizeof(T)))) return rc;
   if ((rc = dalloc(h, &h->spec1, 2 * sizeof(T) * 3 * (size_t)h->nfilm * h->ny * h->Kx))) return rc;
-  long long n_hot = 0, n_force = 0;
-  assign_channels(h);
-  build_tables(h, false, h->tab_hot, h->rp_hot, n_hot);
-  build_tables(h, true, h->tab_force, h->rp_force, n_force);
   const long long n2 = n_hot > n_force ? n_hot : n_force;
   if ((rc = dalloc(h, &h->spec2, 2 * sizeof(T) * (size_t)n2))) return rc;
   if ((rc = upload_tw(h, &h->twx, h->N2x, h->N2x, sizeof(T) == 8))) return rc;

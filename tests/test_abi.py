@@ -74,6 +74,20 @@ def test_tune_cache_path_checks():
     mmv.set_tune_cache(None)
 
 
+@pytest.mark.parametrize("kw,msg", [(dict(nx=1800, ny=16), "row kernel's LDS"),
+                                    (dict(nx=900, ny=16, precision=64), "row kernel's LDS"),
+                                    (dict(nx=64, ny=820), "y pass"),
+                                    (dict(nx=64, ny=410, precision=64), "y pass")])
+def test_size_limits_are_checked_before_any_device_call(kw, msg):
+    """Meshes past the LDS limits of the film kernels are refused with
+    MMV_EINVAL from the host checks (no GPU here: a device call would have
+    returned MMV_EHIP)."""
+    d = get_config("stickslip")["desc"].replace(**kw)
+    with pytest.raises(mmv.MMVError) as e:
+        mmv.init_mesh(mmv.to_desc(d))
+    assert e.value.code == -1 and msg in str(e.value)
+
+
 def test_potential_mode_needs_two_films():
     d = get_config("tiny_potential")["desc"].replace(n_films=1)
     with pytest.raises(mmv.MMVError) as e:
