@@ -143,6 +143,39 @@ def batched_vs_plain(steps_batch=200, steps_plain=50):
             "ms_per_step_batched": t_batch / steps_batch * 1e3, "autotuned_groups": groups}
 
 
+def cube_report(steps=40, warmup=4):
+    """Step time of the 64^3 conducting cube (the single-magnet 3-D path),
+    float32 and float64, with the eddy term (sigma = 1e7 S/m, once per step:
+    dB/dt, the E_sol convolution, 40 red-black SOR sweeps, J x S) and without
+    it (sigma = 0): HIP events around `steps` RK4 steps on the mesh's stream."""
+    import torch
+    import paper_1801_04181_amd as mmv
+    from workloads import get_config, initial_state
+
+    cfg = get_config("cube_eddy")
+    m = initial_state(cfg)
+    cells = cfg["desc"].nx * cfg["desc"].ny * cfg["desc"].nz
+    out = {"workload": "64^3 cube, 2 nm cells, RK4 dt 5e-14 s, Zeeman + exchange + demag (+ eddy)",
+           "cells": cells, "steps": steps}
+    for prec in (32, 64):
+        for eddy in (True, False):
+            d = cfg["desc"].replace(precision=prec, sigma=cfg["desc"].sigma if eddy else 0.0)
+            mesh = mmv.Mesh(d, cfg["drive"], m)
+            mesh.step(cfg["dt"], warmup)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(mesh.stream)
+            mesh.step(cfg["dt"], steps)
+            e1.record(mesh.stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            mesh.close()
+            out[f"fp{prec}_{'eddy' if eddy else 'no_eddy'}"] = {
+                "ms_per_step": ms, "cell_updates_per_s": cells / (ms * 1e-3)}
+    return out
+
+
 def precision_report(steps_cube=6, steps_film=50):
     """Per-term error of the float32 and float64 GPU paths against the float64
     oracle: the 64^3 conducting cube (eddy currents on) and the stick-slip films.
@@ -298,13 +331,16 @@ def main():
     ap.add_argument("--config", default="stickslip")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--report", choices=["precision", "surrogate"], default=None)
+    ap.add_argument("--report", choices=["precision", "surrogate", "cube"], default=None)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy 256 MiB device to device 3 times (counter calibration)")
     args = ap.parse_args()
     if args.report == "precision":
         print(json.dumps({"precision_report": precision_report()}), flush=True)
+        return
+    if args.report == "cube":
+        print(json.dumps({"cube_report": cube_report()}), flush=True)
         return
     if args.report == "surrogate":
         print(json.dumps({"surrogate_report": surrogate_report(args.train_steps)}), flush=True)
