@@ -1310,7 +1310,8 @@ int init_mesh(const mmv_mesh_desc* d, void* hip_stream, mmv_handle* out) {
       delete h;
       return fail(MMV_EINVAL, "FFT length has too many factors");
     }
-    if (sizeof(double) * 2 * (4 * (size_t)h->N2x + 1) > 160 * 1024 || h->Ly > 4096 || h->Lz > 2048) {
+    if (sizeof(double) * 2 * (4 * (size_t)h->N2x + 1) > 160 * 1024 || h->Ly > 4096 || h->Lz > 2048 ||
+        (long long)d->nx * d->ny * d->nz >= (1LL << 31)) {
       delete h;
       return fail(MMV_EINVAL, "mesh too large for the three-dimensional path");
     }

@@ -176,15 +176,24 @@ struct CubeParams {
   double pref_ex, pref_an, u[3], hext[3], gam, alpha, dt;
 };
 
+// (i, j, k) of cell id on an nx x ny x nz grid of fewer than 2^31 cells
+// (checked at set-up), in 32-bit arithmetic.
+__device__ __forceinline__ void cell_ijk(size_t id, int nx, int ny, int& i, int& j, int& k) {
+  const unsigned u = (unsigned)id, unx = (unsigned)nx, uny = (unsigned)ny;
+  const unsigned q = u / unx;
+  i = (int)(u - q * unx);
+  k = (int)(q / uny);
+  j = (int)(q - (unsigned)k * uny);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_stage3(CubeParams p, const T* __restrict__ ms, const T* m0, T* mnext, T* __restrict__ acc,
              const T* __restrict__ hd, const T* __restrict__ he, T* __restrict__ hout, int* __restrict__ flags) {
   const size_t N = (size_t)p.nx * p.ny * p.nz;
   for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < N; id += (size_t)gridDim.x * blockDim.x) {
-  const int i = id % p.nx;
-  const int j = (id / p.nx) % p.ny;
-  const int k = id / ((size_t)p.nx * p.ny);
+  int i, j, k;
+  cell_ijk(id, p.nx, p.ny, i, j, k);
   const T mx = ms[id], my = ms[N + id], mz = ms[2 * N + id];
   T hx = 0, hy = 0, hz = 0;
   if (p.term_mask & 8) {
@@ -292,7 +301,8 @@ __global__ void __launch_bounds__(256)
   double acc = 0.0;
   for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < N; id += (size_t)gridDim.x * blockDim.x) {
     double v = 0.0;
-    const int i = id % nx, j = (id / nx) % ny, k = id / ((size_t)nx * ny);
+    int i, j, k;
+    cell_ijk(id, nx, ny, i, j, k);
     const double ex = es[id], ey = es[N + id], ez = es[2 * N + id];
     if (i == nx - 1) v -= ex / dx;
     if (i == 0) v += ex / dx;
@@ -350,25 +360,32 @@ __global__ void k_shift(size_t N, T* __restrict__ x, const double* __restrict__ 
 
 // One colour of a red-black SOR sweep (colour = (i + j + k) mod 2).
 template <typename T>
-__global__ void k_sor(int nx, int ny, int nz, double dx, double dy, double dz, T* __restrict__ phi,
-                      const T* __restrict__ r, double omega, int colour) {
-  const size_t N = (size_t)nx * ny * nz;
+__global__ void __launch_bounds__(256)
+    k_sor(int nx, int ny, int nz, double dx, double dy, double dz, T* __restrict__ phi,
+          const T* __restrict__ r, double omega, int colour) {
+  // thread (x, y) owns the x-th cell of this colour in row (j = y, k):
+  // i = 2 x + ((colour + j + k) & 1), no index division (the launch covers
+  // every cell with one pass of the strided loops)
+  const int k = blockIdx.z;
+  const int nxh = (nx + 1) / 2;
   const T wx = T(1.0 / (dx * dx)), wy = T(1.0 / (dy * dy)), wz = T(1.0 / (dz * dz));
   const size_t sy = nx, sz = (size_t)nx * ny;
-  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < N; id += (size_t)gridDim.x * blockDim.x) {
-  const int i = id % nx, j = (id / nx) % ny, k = id / ((size_t)nx * ny);
-  if (((i + j + k) & 1) != colour) continue;
-  T s = 0, w = 0;
-  if (i > 0) { s += phi[id - 1] * wx; w += wx; }
-  if (i < nx - 1) { s += phi[id + 1] * wx; w += wx; }
-  if (j > 0) { s += phi[id - sy] * wy; w += wy; }
-  if (j < ny - 1) { s += phi[id + sy] * wy; w += wy; }
-  if (k > 0) { s += phi[id - sz] * wz; w += wz; }
-  if (k < nz - 1) { s += phi[id + sz] * wz; w += wz; }
-  if (w == T(0)) continue;
-  const T upd = (s - r[id]) / w;
-  phi[id] = (T(1) - (T)omega) * phi[id] + (T)omega * upd;
-  }
+  for (int j = blockIdx.y * blockDim.y + threadIdx.y; j < ny; j += gridDim.y * blockDim.y)
+    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < nxh; x += gridDim.x * blockDim.x) {
+      const int i = 2 * x + ((colour + j + k) & 1);
+      if (i >= nx) continue;
+      const size_t id = (size_t)k * sz + (size_t)j * sy + i;
+      T s = 0, w = 0;
+      if (i > 0) { s += phi[id - 1] * wx; w += wx; }
+      if (i < nx - 1) { s += phi[id + 1] * wx; w += wx; }
+      if (j > 0) { s += phi[id - sy] * wy; w += wy; }
+      if (j < ny - 1) { s += phi[id + sy] * wy; w += wy; }
+      if (k > 0) { s += phi[id - sz] * wz; w += wz; }
+      if (k < nz - 1) { s += phi[id + sz] * wz; w += wz; }
+      if (w == T(0)) continue;
+      const T upd = (s - r[id]) / w;
+      phi[id] = (T(1) - (T)omega) * phi[id] + (T)omega * upd;
+    }
 }
 
 // J = sigma (E_sol + E_irrot), E_irrot,a = -(g+ + g-)/2, surface faces take E_sol,a.
@@ -377,7 +394,8 @@ __global__ void k_current(int nx, int ny, int nz, double dx, double dy, double d
                           const T* __restrict__ es, T* __restrict__ J, double sigma) {
   const size_t N = (size_t)nx * ny * nz;
   for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < N; id += (size_t)gridDim.x * blockDim.x) {
-  const int i = id % nx, j = (id / nx) % ny, k = id / ((size_t)nx * ny);
+  int i, j, k;
+  cell_ijk(id, nx, ny, i, j, k);
   const int idx[3] = {i, j, k};
   const int n[3] = {nx, ny, nz};
   const size_t st[3] = {1, (size_t)nx, (size_t)nx * ny};
@@ -538,10 +556,12 @@ template <typename T>
 hipError_t launch_sor(const CubeLaunch& c, T* phi, const T* r, double omega, int sweeps, double* part, double* mean,
                       hipStream_t st) {
   const size_t N = (size_t)c.nx * c.ny * c.nz;
+  // one thread per cell of the swept colour: rows of (nx + 1) / 2, 32 x 8
+  // threads per block, one z layer per grid slice
+  const dim3 blk(32, 8), grid((unsigned)(((c.nx + 1) / 2 + 31) / 32), (unsigned)((c.ny + 7) / 8), (unsigned)c.nz);
   for (int s = 0; s < sweeps; ++s)
     for (int col = 0; col < 2; ++col)
-      hipLaunchKernelGGL(k_sor<T>, grid1(N), dim3(256), 0, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz, phi, r, omega,
-                         col);
+      hipLaunchKernelGGL(k_sor<T>, grid, blk, 0, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz, phi, r, omega, col);
   const int nb = (int)((N + 255) / 256);
   hipLaunchKernelGGL(k_sum_part<T>, dim3(nb), dim3(256), 0, st, N, (const T*)phi, part);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, nb, (const double*)part, mean, 1.0 / (double)N);
