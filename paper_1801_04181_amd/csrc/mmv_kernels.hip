@@ -382,51 +382,24 @@ struct C2rInputs {
   }
 };
 
-// Two consecutive spline values at window coordinates k0 + frac and
-// k0 + 1 + frac: o_j = sum_q g_q ext(k0 + j - K - 1 + q), q = 0 .. 2K+3, summed
-// in q order, from one register window (neighbouring lanes read windows two
-// samples apart, which keeps the LDS reads free of bank conflicts).  The window is
-// read in pairs from the even-aligned sample at or below its start (PAR =
-// parity of the start) and the weights in 16-byte vectors: g must be 16-byte
-// aligned and the window row even-aligned, with one readable sample past
-// the 2K+5 the taps use.
 template <typename T> struct alignas(2 * sizeof(T)) Pair { T x, y; };
 
-// Scalar-read form of the same sums (float64: its 2K+5-sample window already
-// fills half the register file).
-template <typename T, int K>
-__device__ __forceinline__ void fir_eval2s(const T* ext, const T* g, int k0, int E, T& o0, T& o1) {
+// NO consecutive spline values at window coordinates k0 + j + frac,
+// j = 0 .. NO-1: o_j = sum_q g_q ext(k0 + j - K - 1 + q), q = 0 .. 2K+3,
+// summed in q order, from one register window read one sample at a time
+// (neighbouring lanes NO samples apart: conflict-free LDS reads for odd NO).
+// g (16-byte aligned) is read in 16-byte vectors.
+template <typename T, int K, int NO>
+__device__ __forceinline__ void fir_evaln(const T* ext, const T* g, int k0, int E, T* o) {
   constexpr int NQ = 2 * K + 4;
-  const T* p = ext + E + k0 - K - 1;
-  T w[NQ + 1];
-#pragma unroll
-  for (int q = 0; q < NQ + 1; ++q) w[q] = p[q];
-  T a0 = 0, a1 = 0;
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const T gq = g[q];
-    a0 += gq * w[q];
-    a1 += gq * w[q + 1];
-  }
-  o0 = a0;
-  o1 = a1;
-}
-
-template <typename T, int K, int PAR>
-__device__ __forceinline__ void fir_eval2(const T* ext, const T* g, int k0, int E, T& o0, T& o1) {
-  constexpr int NQ = 2 * K + 4;
-  constexpr int NW = NQ + 2;  // samples read: taps of both outputs plus the parity shift
   constexpr int GV = 16 / sizeof(T);
-  static_assert(NQ % GV == 0 && NW % 2 == 0, "vector widths");
-  const Pair<T>* p = reinterpret_cast<const Pair<T>*>(ext + E + k0 - K - 1 - PAR);
-  T w[NW];
+  const T* p = ext + E + k0 - K - 1;
+  T w[NQ + NO - 1];
 #pragma unroll
-  for (int j = 0; j < NW / 2; ++j) {
-    const Pair<T> v = p[j];
-    w[2 * j] = v.x;
-    w[2 * j + 1] = v.y;
-  }
-  T a0 = 0, a1 = 0;
+  for (int q = 0; q < NQ + NO - 1; ++q) w[q] = p[q];
+  T a[NO];
+#pragma unroll
+  for (int j = 0; j < NO; ++j) a[j] = 0;
 #pragma unroll
   for (int q0 = 0; q0 < NQ; q0 += GV) {
     T gv[GV];
@@ -438,13 +411,12 @@ __device__ __forceinline__ void fir_eval2(const T* ext, const T* g, int k0, int 
       gv[0] = v.x; gv[1] = v.y;
     }
 #pragma unroll
-    for (int u = 0; u < GV; ++u) {
-      a0 += gv[u] * w[q0 + u + PAR];
-      a1 += gv[u] * w[q0 + u + 1 + PAR];
-    }
+    for (int u = 0; u < GV; ++u)
+#pragma unroll
+      for (int j = 0; j < NO; ++j) a[j] += gv[u] * w[q0 + u + j];
   }
-  o0 = a0;
-  o1 = a1;
+#pragma unroll
+  for (int j = 0; j < NO; ++j) o[j] = a[j];
 }
 
 __device__ void rigid_stage(RigidState* R, const DriveP& d, int stage, double F, double h,
@@ -524,7 +496,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nx = p.nx, ny = p.ny, N2x = p.N2x, M = p.M, Lx = 2 * N2x, nbr = p.nbr;
   const int MW = M + 2 * E;
-  const int MWS = (MW + 5) & ~1;  // even row stride of the windows, >= MW + 4 (slack for the paired FIR reads)
+  const int MWS = (MW + 5) & ~1;  // row stride of the windows, >= MW + 4 (slack for the FIR reads past a row)
   const int nfc = p.full_force ? 3 : 1;
   cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* stp = stw + N2x;
@@ -801,54 +773,74 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
       }
     }
     lds_barrier();
-    const int NP = nx + 6;  // outputs i = -3 .. nx+2
-    const int NB2 = (NP + 1) >> 1;
-    const float invNB = 1.0f / (float)NB2;
+    const int NP = nx + 6;  // potential outputs i = -3 .. nx+2
+    // spline outputs: NO consecutive i per thread, over the spline rows of
+    // the batch only, each row over the outputs its kind needs (potential
+    // -3..nx+2, the slider's cross field -1..nx, otherwise 0..nx-1), so a
+    // float32 task fits one pass of the block
+    constexpr int NO = sizeof(T) == 4 ? 3 : 2;
+    auto out_range = [&](int kind, int& lo, int& cnt) {
+      lo = 0;
+      cnt = nx;
+      if (kind < RK_CROSS) {
+        cnt = 0;
+      } else if (kind >= RK_PHI && kind < RK_XB) {
+        lo = -3;
+        cnt = NP;
+      } else if (kind < RK_FP && film == 1) {
+        lo = -1;
+        cnt = nx + 2;
+      }
+    };
+    int nitem = 0;
+    for (int r = 0; r < bn; ++r) {
+      int lo, cnt;
+      out_range(rowkind[b0 + r], lo, cnt);
+      nitem += (cnt + NO - 1) / NO;
+    }
 #pragma unroll 1
-    for (int t = threadIdx.x; t < bn * NB2; t += NT) {
-      const int r = fdiv(t, invNB);
-      const int i0 = (t - r * NB2) * 2 - 3;
+    for (int t = threadIdx.x; t < nitem; t += NT) {
+      int r = 0, first = 0, lo = 0, cnt = 0;
+      for (;; ++r) {
+        out_range(rowkind[b0 + r], lo, cnt);
+        const int ng = (cnt + NO - 1) / NO;
+        if (t < first + ng) break;
+        first += ng;
+      }
       const int kind = rowkind[b0 + r];
-      if (kind < RK_CROSS) continue;
+      const int i0 = lo + NO * (t - first);
       const T* e = ext + (size_t)r * MWS;
       // the base film samples the slider's field (and potential) at -x_p
       const bool base = film == 0 && (kind < RK_FP || (kind >= RK_PHI && kind < RK_XB));
-      T v[2];
-      if constexpr (sizeof(T) == 8) {
+      T v[NO];
+      if constexpr (sizeof(T) == 8) {  // float64: two call sites keep its wide window in registers
         if (base)
-          fir_eval2s<T, K>(e, gb, i0 + h + ifb, E, v[0], v[1]);
+          fir_evaln<T, K, NO>(e, gb, i0 + h + ifb, E, v);
         else
-          fir_eval2s<T, K>(e, gs, i0 + h + ifs, E, v[0], v[1]);
+          fir_evaln<T, K, NO>(e, gs, i0 + h + ifs, E, v);
       } else {
-        const int k0 = i0 + h + (base ? ifb : ifs);
-        const T* g = base ? gb : gs;
-        if ((k0 + E - K - 1) & 1)
-          fir_eval2<T, K, 1>(e, g, k0, E, v[0], v[1]);
-        else
-          fir_eval2<T, K, 0>(e, g, k0, E, v[0], v[1]);
+        fir_evaln<T, K, NO>(e, base ? gb : gs, i0 + h + (base ? ifb : ifs), E, v);
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < NO; ++j) {
         const int i = i0 + j;
-        if (i > nx + 2) continue;
+        if (i >= lo + cnt) break;
         if (kind >= RK_XB) {
-          if (i >= 0 && i < nx) gxb[(kind - RK_XB) * nx + i] = v[j];
+          gxb[(kind - RK_XB) * nx + i] = v[j];
         } else if (kind >= RK_PHI) {
           phit[(size_t)(kind - RK_PHI) * NP + i + 3] = v[j];
         } else if (kind < RK_FP) {
-          if (i < -1 || i > nx) continue;
           const int c = kind - RK_CROSS;
           if (film == 1) {
             gc[c * (nx + 2) + i + 1] = v[j];
             if (cell_row && i >= 0 && i < nx && (p.term_mask & 16)) H[c * nx + i] += v[j];
-          } else if (i >= 0 && i < nx) {
+          } else {
             H[c * nx + i] += v[j];
           }
-        } else if (i >= 0 && i < nx) {
-          if (kind < RK_FM)
-            gp[(kind - RK_FP) * nx + i] = v[j];
-          else
-            gm[(kind - RK_FM) * nx + i] = v[j];
+        } else if (kind < RK_FM) {
+          gp[(kind - RK_FP) * nx + i] = v[j];
+        } else {
+          gm[(kind - RK_FM) * nx + i] = v[j];
         }
       }
     }
