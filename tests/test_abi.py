@@ -7,6 +7,8 @@ import pytest
 import paper_1801_04181_amd as mmv
 from workloads import Desc, get_config
 
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
 HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "mmv.h")
 
 
@@ -61,6 +63,29 @@ def test_null_handle_and_pointers():
     assert lib.init_mesh(None, None, None) == -1
     F = (ctypes.c_double * 3)()
     assert lib.stray_force(None, F) == -1
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built library every call raises (no CPU fallback): run in
+    a fresh interpreter so the loaded library of this process is untouched."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_1801_04181_amd as mmv\n"
+        "mmv.lib_path = %r\n"
+        "from workloads import get_config\n"
+        "for f in (lambda: mmv.load(), lambda: mmv.init_mesh(mmv.to_desc(get_config('tiny')['desc']))):\n"
+        "    try:\n"
+        "        f()\n"
+        "    except ImportError as e:\n"
+        "        assert 'no fallback' in str(e), e\n"
+        "    else:\n"
+        "        raise SystemExit('call succeeded without the library')\n"
+        "print('ok')\n"
+    ) % (ROOT, str(tmp_path / "absent" / "libmmv.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.strip() == "ok", r.stdout + r.stderr
 
 
 def test_tune_cache_path_checks():
