@@ -400,12 +400,13 @@ int build_kernels(mmv_mesh* h) {
   return MMV_OK;
 }
 
-// Size limits set by the LDS of the row and y-pass kernels and by the 32-bit
+// Size limits set by the LDS of the row and y-pass kernels (the CU's 160 KB
+// less what the kernels declare statically) and by the 32-bit
 // kernel-spectrum index, from the descriptor and the channel tables alone
 // (checked before any device call).
 template <typename T>
 int check_sizes(const mmv_mesh* h) {
-  const size_t lds_limit = 160 * 1024;
+  const size_t lds_limit = LDS_PER_CU - ROW_STATIC_LDS;
   RowParams probe{};
   probe.nx = h->nx;
   probe.N2x = h->N2x;
@@ -414,13 +415,13 @@ int check_sizes(const mmv_mesh* h) {
   probe.full_force = 1;
   probe.pot = h->d.cross_mode == 1;
   if (row_lds_bytes<T>(probe) > lds_limit) return fail(MMV_EINVAL, "nx too large for the row kernel's LDS");
-  if (sizeof(T) * 2 * (4 * (size_t)h->N2x + 1) > lds_limit) return fail(MMV_EINVAL, "nx too large");
+  if (sizeof(T) * 2 * (4 * (size_t)h->N2x + 1) > LDS_PER_CU) return fail(MMV_EINVAL, "nx too large");
   if ((long long)h->nkc * h->Kx * h->Kyh >= (1LL << 31)) return fail(MMV_EINVAL, "kernel spectra too large");
   const int nin = 3 * h->nfilm;
   const int nmax = h->tab_force.n > h->tab_hot.n ? h->tab_force.n : h->tab_hot.n;
   for (int g = 1; g <= 8; ++g) {
     const int per = (nmax + g - 1) / g;
-    if (col_lds_bytes<T>(h->Ly, nin > per ? nin : per) <= lds_limit) return MMV_OK;
+    if (col_lds_bytes<T>(h->Ly, nin > per ? nin : per) <= LDS_PER_CU - COL_STATIC_LDS) return MMV_OK;
   }
   return fail(MMV_EINVAL, "ny too large for the y pass");
 }
@@ -437,6 +438,8 @@ int init_typed(mmv_mesh* h) {
   build_tables(h, true, h->tab_force, h->rp_force, n_force);
   if ((rc = check_sizes<T>(h))) return rc;
   if ((rc = dalloc(h, &h->m0, 3 * ncell * sizeof(T)))) return rc;
+  if (!static_lds_within_reserve<T>())
+    return fail(MMV_EHIP, "the film kernels' static LDS exceeds the reserve the size limits assume");
   if ((rc = dalloc(h, &h->mb[0], 3 * ncell * sizeof(T)))) return rc;
   if ((rc = dalloc(h, &h->mb[1], 3 * ncell * sizeof(T)))) return rc;
   if ((rc = dalloc(h, &h->acc, 3 * ncell * sizeof(T)))) return rc;
@@ -485,8 +488,9 @@ int init_typed(mmv_mesh* h) {
     rp->force_scale = MU0 * d.Ms * d.dx * d.dy * d.dz;
     rp->px = h->px;
   }
-  // LDS limits
-  const size_t lds_limit = 160 * 1024;
+  // LDS limits (the CU's 160 KB less the kernels' static LDS)
+  const size_t lds_limit = LDS_PER_CU - ROW_STATIC_LDS;
+  const size_t col_limit = LDS_PER_CU - COL_STATIC_LDS;
   // inverse row transforms per batch of the row kernel: as many as fit
   int nbr = 0;
   for (int b : {9, 8, 6, 4, 3, 2, 1}) {
@@ -502,7 +506,7 @@ int init_typed(mmv_mesh* h) {
   if (!nbr) return fail(MMV_EINVAL, "nx too large for the row kernel's LDS");
   h->rp_hot.nbr = h->rp_force.nbr = nbr;
   h->fuse_fwd = nbr >= 3;
-  if (sizeof(T) * 2 * (4 * (size_t)h->N2x + 1) > lds_limit) return fail(MMV_EINVAL, "nx too large");
+  if (sizeof(T) * 2 * (4 * (size_t)h->N2x + 1) > LDS_PER_CU) return fail(MMV_EINVAL, "nx too large");
   // output groups per column of the y pass.  Each group recomputes the
   // column's forward transforms (an L2 hit); more groups give shorter blocks,
   // and the launch should fit in one round of resident blocks.  Estimated
@@ -519,7 +523,7 @@ int init_typed(mmv_mesh* h) {
   for (int g = 1; g <= 4; ++g) {
     // LDS of the stage launches (the force table only has to fit)
     const int pf = (nmax + g - 1) / g;
-    if (col_lds_bytes<T>(h->Ly, nin > pf ? nin : pf) > lds_limit) continue;
+    if (col_lds_bytes<T>(h->Ly, nin > pf ? nin : pf) > col_limit) continue;
     const int pg = (h->tab_hot.n + g - 1) / g;
     const size_t lds = col_lds_bytes<T>(h->Ly, nin > pg ? nin : pg);
     const int occ = col_blocks_per_cu<T>(lds);
@@ -541,7 +545,7 @@ int init_typed(mmv_mesh* h) {
     if (v >= 1 && v <= 8) h->ngroup = v;
   }
   const int per = (nmax + h->ngroup - 1) / h->ngroup;
-  if (col_lds_bytes<T>(h->Ly, nin > per ? nin : per) > lds_limit)
+  if (col_lds_bytes<T>(h->Ly, nin > per ? nin : per) > col_limit)
     return fail(MMV_EINVAL, "ny too large for the y pass");
   return MMV_OK;
 }

@@ -79,4 +79,14 @@ size_t col_lds_bytes(int Ly, int nbuf);
 template <typename T>
 int col_blocks_per_cu(size_t lds);
 
+// LDS of one CU, and the parts of it reserved for what the row and y-pass
+// kernels declare statically (row and output tables, reduction slots): a
+// launch's dynamic LDS must fit in the rest.
+constexpr size_t LDS_PER_CU = 160 * 1024;
+constexpr size_t ROW_STATIC_LDS = 512;
+constexpr size_t COL_STATIC_LDS = 640;
+// true if the compiled row and y-pass kernels stay within those reserves
+template <typename T>
+bool static_lds_within_reserve();
+
 }  // namespace mmv

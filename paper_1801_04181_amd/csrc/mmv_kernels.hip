@@ -1245,6 +1245,18 @@ int col_blocks_per_cu(size_t lds) {
 }
 
 template <typename T>
+bool static_lds_within_reserve() {
+  hipFuncAttributes a{};
+  for (const void* k : {(const void*)k_row_stage<T>, (const void*)k_row_stage_batch<T>}) {
+    if (hipFuncGetAttributes(&a, k) != hipSuccess || a.sharedSizeBytes > ROW_STATIC_LDS) return false;
+  }
+  for (const void* k : {(const void*)k_col<T>, (const void*)k_col_batch<T>}) {
+    if (hipFuncGetAttributes(&a, k) != hipSuccess || a.sharedSizeBytes > COL_STATIC_LDS) return false;
+  }
+  return true;
+}
+
+template <typename T>
 hipError_t launch_col(const void* spec1, void* spec2, const T* kern, int Kx, int Ly, int Kyh, int ny,
                       int nin_ch, int ngroup, const FftPlan& P, const void* twy, const OutTable& tab,
                       hipStream_t st, const TickArgs* tick, int tick_stage, double tick_dt) {
@@ -1365,7 +1377,8 @@ hipError_t launch_colpack(const void* spec, T* out, int Kx, int Ly, int Kyh, con
                                         hipStream_t);                                                          \
   template size_t row_lds_bytes<T>(const RowParams&);                                                           \
   template size_t col_lds_bytes<T>(int, int);                                                                    \
-  template int col_blocks_per_cu<T>(size_t);                                                                     \
+  template int col_blocks_per_cu<T>(size_t);\
+  template bool static_lds_within_reserve<T>();                                                                     \
   template hipError_t prepare_batch_kernels<T>(size_t, size_t, size_t);                                         \
   template hipError_t launch_row_fwd_batch<T>(const RowFwdDesc*, const int*, int, int, size_t, hipStream_t);      \
   template hipError_t launch_col_batch<T>(const ColDesc*, const int*, int, int, size_t, hipStream_t, int, double);             \

@@ -101,6 +101,16 @@ def test_gap_zero_and_single_film(prec):
     check_fields(d1, Drive(), m[:1])
 
 
+@pytest.mark.parametrize("prec,nx,ny", [(32, 1728, 8), (64, 844, 8), (32, 16, 809), (64, 16, 404)])
+def test_largest_meshes(prec, nx, ny):
+    """The largest two-film meshes init_mesh accepts with the default halo
+    and travel (a film row, or a spectrum column, in one CU's LDS): every
+    term and the force against the oracle."""
+    d = get_config("stickslip")["desc"].replace(nx=nx, ny=ny, precision=prec)
+    m = [domain_state((1, ny, nx), 11), domain_state((1, ny, nx), 12)]
+    check_fields(d, Drive(), m, x_cells=1.7)
+
+
 def run_steps(desc, drive, m, dt, n):
     mmv = _mmv()
     import torch
@@ -139,6 +149,20 @@ def test_spring_fp32_steps():
 
 
 # ---------------------------------------------------------------- scalar potential mode
+def test_largest_mesh_spring_steps():
+    """Three RK4 steps with the spring drive on the widest float32 mesh."""
+    from workloads import slider_mass_damping
+    nx, ny = 1728, 8
+    d = get_config("stickslip")["desc"].replace(nx=nx, ny=ny, precision=32)
+    mass, gv = slider_mass_damping(nx, ny, 1e-3)
+    drv = Drive(mode=2, v_d=5.0, k=1e-3, mass=mass, gamma_v=gv, x0=0.6 * d.dx)
+    m = [domain_state((1, ny, nx), 13), domain_state((1, ny, nx), 14)]
+    dm, st, s = run_steps(d, drv, m, 1e-13, 3)
+    print("largest mesh 3 steps max|dm|", dm, "x gpu", st["x"], "oracle", s.x, flush=True)
+    assert dm < 1e-4
+    assert abs(st["x"] - s.x) < 1e-4 * d.dx
+
+
 def test_tiny_potential_fp64_fields():
     cfg = get_config("tiny_potential")
     check_fields(cfg["desc"], cfg["drive"], initial_state(cfg), x_cells=0.37)
