@@ -101,7 +101,8 @@ typedef struct {
  * drive frozen, t = 0.  On success *out receives the handle.
  * Size limits of the film path (a film row and a spectrum column each
  * live in one CU's 160 KB of LDS): with the default halo and travel, nx up
- * to 1728 (float32) / 844 (float64) and ny up to 809 / 404; beyond them,
+ * to 1728 (float32) / 844 (float64) and ny up to 809 / 404 (potential mode,
+ * gap 3: nx 944 / 459, ny 781 / 402); beyond them,
  * or for a kernel-spectrum table of 2^31 elements or more, MMV_EINVAL
  * before any device call.                                                */
 int init_mesh(const mmv_mesh_desc* d, void* hip_stream, mmv_handle* out);

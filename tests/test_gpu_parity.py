@@ -149,6 +149,15 @@ def test_spring_fp32_steps():
 
 
 # ---------------------------------------------------------------- scalar potential mode
+@pytest.mark.parametrize("prec,nx,ny", [(32, 944, 16), (64, 459, 16), (32, 32, 781), (64, 32, 402)])
+def test_largest_potential_meshes(prec, nx, ny):
+    """The largest meshes init_mesh accepts in the scalar-potential mode
+    (gap 3, halo 4; more rows per task than the direct mode)."""
+    d = get_config("tiny_potential")["desc"].replace(nx=nx, ny=ny, precision=prec)
+    m = [domain_state((1, ny, nx), 11), domain_state((1, ny, nx), 12)]
+    check_fields(d, Drive(), m, x_cells=0.0)
+
+
 def test_largest_mesh_spring_steps():
     """Three RK4 steps with the spring drive on the widest float32 mesh."""
     from workloads import slider_mass_damping
