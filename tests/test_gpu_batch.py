@@ -147,3 +147,43 @@ def test_tuning_cache_is_written_and_read_back(tmp_path):
         assert {k: int(v) for k, v in kept.items()} == edited
     finally:
         mmv.set_tune_cache(None)
+
+
+def test_batch_with_a_largest_instance_equals_single_instances():
+    """A batch mixing the widest float32 mesh init_mesh accepts with small
+    ones: every instance's magnetisation bitwise equal to the same instance
+    stepped alone.  The slider state agrees to float64 rounding: the batch
+    row kernel runs 512 threads and the single-mesh one 1024, so on rows
+    wider than 512 cells each thread sums a different set of cells into
+    its float64 force partial."""
+    import torch
+    import paper_1801_04181_amd as mmv
+    from workloads import slider_mass_damping
+    from workloads.configs import DRIVE_SPRING
+    from workloads import Drive
+    base = batch_pairs(2)
+    descs, drives, ms = [], [], []
+    for nx, ny in [(1728, 8), (64, 64), (96, 24)]:
+        d = base[0]["desc"].replace(nx=nx, ny=ny)
+        mass, gv = slider_mass_damping(nx, ny, 1e-3)
+        descs.append(d)
+        drives.append(Drive(mode=DRIVE_SPRING, v_d=3.0, k=1e-3, mass=mass, gamma_v=gv))
+        ms.append([np.asarray(x) for x in initial_state(dict(base[0], desc=d))])
+    print("batch with the widest instance", [(d.nx, d.ny) for d in descs], flush=True)
+    B = mmv.Batch(descs, drives, ms)
+    B.step(1e-13, 4)
+    torch.cuda.synchronize()
+    for i, d in enumerate(descs):
+        single = mmv.Mesh(d, drives[i], ms[i])
+        single.step(1e-13, 4)
+        mb, sb = state(mmv, B.h[i], d)
+        m1, s1 = state(mmv, single.h, d)
+        for f in range(2):
+            assert np.array_equal(mb[f], m1[f]), (i, f)
+        assert sb["step"] == s1["step"] and sb["t"] == s1["t"]
+        for k in ("x", "v"):
+            assert abs(sb[k] - s1[k]) <= 1e-12 * max(abs(s1[k]), 1e-30), (i, k, sb[k], s1[k])
+        if d.nx <= 512:
+            assert sb == s1, i
+        single.close()
+    B.close()

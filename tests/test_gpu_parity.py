@@ -54,7 +54,7 @@ def test_tiny_fp64_fields():
     check_fields(cfg["desc"], cfg["drive"], initial_state(cfg), x_cells=0.37)
 
 
-@pytest.mark.parametrize("x_cells", [0.37, 3.6, -2.25])
+@pytest.mark.parametrize("x_cells", [0.37, 3.6, -2.25, 4.0, -4.0])
 def test_stickslip_fp32_fields_full_size(x_cells):
     cfg = get_config("stickslip")
     check_fields(cfg["desc"], cfg["drive"], initial_state(cfg), x_cells=x_cells)
@@ -109,6 +109,17 @@ def test_largest_meshes(prec, nx, ny):
     d = get_config("stickslip")["desc"].replace(nx=nx, ny=ny, precision=prec)
     m = [domain_state((1, ny, nx), 11), domain_state((1, ny, nx), 12)]
     check_fields(d, Drive(), m, x_cells=1.7)
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+@pytest.mark.parametrize("halo", [2, 64])
+def test_halo_extremes(prec, halo):
+    """The smallest and largest spline halo the descriptor accepts."""
+    d = Desc(n_films=2, nx=40, ny=12, nz=1, dx=2e-9, dy=2e-9, dz=2e-9, gap_cells=1, max_travel_cells=3,
+             halo=halo, Ms=1.1e6, Aex=1.5e-11, alpha=0.1, Ku=8e5, precision=prec)
+    m = [domain_state((1, 12, 40), 21), domain_state((1, 12, 40), 22)]
+    check_fields(d, Drive(), m, x_cells=2.6)
+    check_fields(d, Drive(), m, x_cells=-3.0)
 
 
 def run_steps(desc, drive, m, dt, n):
