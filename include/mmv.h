@@ -104,7 +104,10 @@ typedef struct {
  * to 1728 (float32) / 844 (float64) and ny up to 809 / 404 (potential mode,
  * gap 3: nx 944 / 459, ny 781 / 402); beyond them,
  * or for a kernel-spectrum table of 2^31 elements or more, MMV_EINVAL
- * before any device call.                                                */
+ * before any device call.  The three-dimensional path (one film, nz > 1)
+ * holds one x row, y column or z column of a transform pass per
+ * block in LDS: nx up to 2520, ny up to 1701 and nz up to 1458 (float32) /
+ * 729 (float64), and fewer than 2^31 cells; beyond them, MMV_EINVAL.   */
 int init_mesh(const mmv_mesh_desc* d, void* hip_stream, mmv_handle* out);
 
 /* Copy a film's magnetisation from / to a caller device buffer

@@ -1314,8 +1314,14 @@ int init_mesh(const mmv_mesh_desc* d, void* hip_stream, mmv_handle* out) {
       delete h;
       return fail(MMV_EINVAL, "FFT length has too many factors");
     }
-    if (sizeof(double) * 2 * (4 * (size_t)h->N2x + 1) > 160 * 1024 || h->Ly > 4096 || h->Lz > 2048 ||
-        (long long)d->nx * d->ny * d->nz >= (1LL << 31)) {
+    // LDS of one block of each 3-D pass at its smallest batch (one row or
+    // column): x transforms (4 N2x + 1), y and z transforms (3 L) in float64
+    // for the kernel build and in the mesh precision, the z pass with the
+    // kernel product (7 Lz) in the mesh precision
+    const size_t es = d->precision == 64 ? 16 : 8, lim = 160 * 1024;
+    const bool lds_ok = 16 * (4 * (size_t)h->N2x + 1) <= lim && 16 * 3 * (size_t)h->Ly <= lim &&
+                        16 * 3 * (size_t)h->Lz <= lim && es * 7 * (size_t)h->Lz <= lim;
+    if (!lds_ok || (long long)d->nx * d->ny * d->nz >= (1LL << 31)) {
       delete h;
       return fail(MMV_EINVAL, "mesh too large for the three-dimensional path");
     }

@@ -474,6 +474,13 @@ hipError_t launch_fft_axis(const void* in, void* out, int nplanes, int ncols, in
     if (CB < 1) CB = 1;
   }
   const size_t lds = sizeof(cpx<T>) * ((size_t)P.L + 2 * (size_t)CB * P.L);
+  if (lds > 65536) {  // one column per block past 64 KB (the set-up bounds L so that it fits)
+    hipError_t e = inv ? hipFuncSetAttribute((const void*)k_fft_axis<T, true>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)
+                       : hipFuncSetAttribute((const void*)k_fft_axis<T, false>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   dim3 grid((ncols + CB - 1) / CB, nplanes);
   if (inv)
     hipLaunchKernelGGL((k_fft_axis<T, true>), grid, dim3(CUBE_THREADS), lds, st, (const cpx<T>*)in, (cpx<T>*)out, ncols, CB,
@@ -487,6 +494,9 @@ hipError_t launch_fft_axis(const void* in, void* out, int nplanes, int ncols, in
 template <typename T>
 hipError_t launch_zmul(void* buf, const T* kern, int Kx, int Ly, int nz, int CB, int mode, double sgn,
                        const FftPlan& P, const void* twz, hipStream_t st) {
+  // columns per block: at most CB, as many as the CU's LDS holds (at least
+  // one fits: the set-up bounds Lz)
+  while (CB > 1 && sizeof(cpx<T>) * ((size_t)P.L + 6 * (size_t)CB * P.L) > 160 * 1024) --CB;
   const size_t lds = sizeof(cpx<T>) * ((size_t)P.L + 6 * (size_t)CB * P.L);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_zmul<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -502,6 +512,10 @@ template <typename T>
 hipError_t launch_row_inv(const void* spec, T* out, int nrows, int nx, int N2x, int Kx, const FftPlan& P,
                           const void* tw, const void* twp, hipStream_t st) {
   const size_t lds = sizeof(cpx<T>) * (4 * (size_t)N2x + 1);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_row_inv<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(k_row_inv<T>, dim3(nrows), dim3(CUBE_THREADS), lds, st, (const cpx<T>*)spec, out, nx, N2x, Kx, P,
                      (const cpx<T>*)tw, (const cpx<T>*)twp);
   return hipGetLastError();

@@ -113,6 +113,16 @@ def test_size_limits_are_checked_before_any_device_call(kw, msg):
     assert e.value.code == -1 and msg in str(e.value)
 
 
+@pytest.mark.parametrize("prec,shape", [(32, (2600, 4, 4)), (32, (4, 1800, 4)), (32, (4, 4, 1500)),
+                                        (64, (4, 4, 760))])
+def test_cube_size_limits_are_checked_before_any_device_call(prec, shape):
+    nx, ny, nz = shape
+    d = get_config("cube_eddy")["desc"].replace(nx=nx, ny=ny, nz=nz, precision=prec)
+    with pytest.raises(mmv.MMVError) as e:
+        mmv.init_mesh(mmv.to_desc(d))
+    assert e.value.code == -1 and "three-dimensional" in str(e.value)
+
+
 def test_potential_mode_needs_two_films():
     d = get_config("tiny_potential")["desc"].replace(n_films=1)
     with pytest.raises(mmv.MMVError) as e:

@@ -68,3 +68,15 @@ def test_cube_full_size_fp32():
     d = get_config("cube_eddy")["desc"].replace(sor_sweeps=10)
     out = run(d, 3)
     assert out["m"] < 1e-6
+
+
+@pytest.mark.parametrize("prec,shape", [(32, (2520, 4, 4)), (64, (2520, 4, 4)), (32, (4, 1701, 4)),
+                                        (64, (4, 1701, 4)), (32, (4, 4, 1458)), (64, (4, 4, 729))])
+def test_cube_largest_extents(prec, shape):
+    """Thin cubes at the largest extent init_mesh accepts along each axis
+    (one row or column of each 3-D pass per block in the CU's LDS), eddy
+    currents on: field terms and two steps against the oracle."""
+    nx, ny, nz = shape
+    d = get_config("cube_eddy")["desc"].replace(nx=nx, ny=ny, nz=nz, precision=prec, sor_sweeps=9)
+    out = run(d, 2)
+    assert out["m"] < (1e-6 if prec == 32 else 1e-12)
