@@ -675,17 +675,21 @@ int init_cube(mmv_mesh* h) {
 
 // Demagnetising-type convolution of a three-channel cell field:
 // x transform, y transform, z pencils with the kernel, inverse y, inverse x.
+// The x transforms take about 1024 points (at most 16 rows) per block.
+static int cube_rows_per_block(int N2x) { return std::max(1, std::min(16, 1024 / N2x)); }
+
 template <typename T>
 int conv3(mmv_mesh* h, const void* src, void* dst, const T* kern, int mode, double sgn) {
   const int nrow = 3 * h->nz * h->ny;
-  HIPCHK(launch_row_fwd<T>((const T*)src, h->spec1, nrow, h->nx, h->N2x, h->Kx, h->px, h->twx, h->twp, h->st));
+  const int R = cube_rows_per_block(h->N2x);
+  HIPCHK(launch_row_fwd<T>((const T*)src, h->spec1, nrow, h->nx, h->N2x, h->Kx, h->px, h->twx, h->twp, h->st, -R));
   HIPCHK(launch_fft_axis<T>(h->spec1, h->specB, 3 * h->nz, h->Kx, 0, h->ny, (long long)h->ny * h->Kx, h->Ly,
                             (long long)h->Ly * h->Kx, h->py, h->twy, false, h->st));
-  const int CBz = sizeof(T) == 4 ? 8 : 4;
+  const int CBz = 4;  // pencils per block of the z pass
   HIPCHK(launch_zmul<T>(h->specB, kern, h->Kx, h->Ly, h->nz, CBz, mode, sgn, h->pz, h->twz, h->st));
   HIPCHK(launch_fft_axis<T>(h->specB, h->spec1, 3 * h->nz, h->Kx, 0, h->Ly, (long long)h->Ly * h->Kx, h->ny,
                             (long long)h->ny * h->Kx, h->py, h->twy, true, h->st));
-  HIPCHK(launch_row_inv<T>(h->spec1, (T*)dst, nrow, h->nx, h->N2x, h->Kx, h->px, h->twx, h->twp, h->st));
+  HIPCHK(launch_row_inv<T>(h->spec1, (T*)dst, nrow, R, h->nx, h->N2x, h->Kx, h->px, h->twx, h->twp, h->st));
   return MMV_OK;
 }
 

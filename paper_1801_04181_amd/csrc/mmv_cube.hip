@@ -67,24 +67,26 @@ template <typename T>
 __global__ void __launch_bounds__(CUBE_THREADS)
     k_zmul(cpx<T>* __restrict__ buf, const T* __restrict__ kern, int Kx, int Ly, int nz, int CB, int mode,
            T sgn, FftPlan P, const cpx<T>* __restrict__ twz) {
+  // block b: the CB pencils q = ky * Kx + kx from b * CB (fewer in the last
+  // block); pencil q of plane z sits at z * Ly * Kx + q
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int Lz = P.L;
   const int Kyh = Ly / 2 + 1, Kzh = Lz / 2 + 1;
   cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* A = stw + Lz;
   cpx<T>* B = A + (size_t)3 * CB * Lz;
-  const int kx0 = blockIdx.x * CB;
-  if (kx0 >= Kx) return;
-  const int nc = min(CB, Kx - kx0);
-  const int ky = blockIdx.y;
-  const long long cs = (long long)nz * Ly * Kx;  // channel stride
+  const int ncol = Ly * Kx;
+  const int q0 = blockIdx.x * CB;
+  if (q0 >= ncol) return;
+  const int nc = min(CB, ncol - q0);
+  const long long zs = ncol, cs = (long long)nz * ncol;  // plane and channel strides
   for (int t = threadIdx.x; t < Lz; t += CUBE_THREADS) stw[t] = twz[t];
   const float inc = 1.0f / (float)nc;
   for (int t = threadIdx.x; t < 3 * nz * nc; t += CUBE_THREADS) {
     const int cz = fdiv(t, inc);  // c * nz + z
     const int cc = t - cz * nc;
     const int c = cz / nz, z = cz - c * nz;
-    A[(c * nc + cc) * Lz + z] = buf[c * cs + ((long long)z * Ly + ky) * Kx + kx0 + cc];
+    A[(c * nc + cc) * Lz + z] = buf[c * cs + z * zs + q0 + cc];
   }
   for (int t = threadIdx.x; t < 3 * nc * (Lz - nz); t += CUBE_THREADS) {
     const int b = t / (Lz - nz), z = nz + t - b * (Lz - nz);
@@ -92,13 +94,14 @@ __global__ void __launch_bounds__(CUBE_THREADS)
   }
   lds_barrier();
   cpx<T>* X = fft_lds<T, false, CUBE_THREADS>(A, B, P, 3 * nc, Lz, stw);
-  const bool yup = ky >= Kyh;
-  const int kyr = yup ? Ly - ky : ky;
   for (int t = threadIdx.x; t < nc * Lz; t += CUBE_THREADS) {
     const int cc = t / Lz, kz = t - cc * Lz;
+    const int ky = (q0 + cc) / Kx, kx = q0 + cc - ky * Kx;
+    const bool yup = ky >= Kyh;
+    const int kyr = yup ? Ly - ky : ky;
     const bool zup = kz >= Kzh;
     const int kzr = zup ? Lz - kz : kz;
-    const size_t kb = (((size_t)(kx0 + cc) * Kyh + kyr) * Kzh + kzr);
+    const size_t kb = (((size_t)kx * Kyh + kyr) * Kzh + kzr);
     const size_t ks = (size_t)Kx * Kyh * Kzh;
     cpx<T> v0 = X[(0 * nc + cc) * Lz + kz], v1 = X[(1 * nc + cc) * Lz + kz], v2 = X[(2 * nc + cc) * Lz + kz];
     cpx<T> o0, o1, o2;
@@ -134,36 +137,48 @@ __global__ void __launch_bounds__(CUBE_THREADS)
     const int cz = fdiv(t, inc);
     const int cc = t - cz * nc;
     const int c = cz / nz, z = cz - c * nz;
-    buf[c * cs + ((long long)z * Ly + ky) * Kx + kx0 + cc] = Y[(c * nc + cc) * Lz + z];
+    buf[c * cs + z * zs + q0 + cc] = Y[(c * nc + cc) * Lz + z];
   }
 }
 
 // ------------------------------------------------------------ inverse x transform
+// Block b turns the R consecutive spectrum rows from b * R (fewer in the
+// last block) into cell values.
 template <typename T>
 __global__ void __launch_bounds__(CUBE_THREADS)
-    k_row_inv(const cpx<T>* __restrict__ spec, T* __restrict__ out, int nx, int N2x, int Kx, FftPlan P,
-              const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp) {
+    k_row_inv(const cpx<T>* __restrict__ spec, T* __restrict__ out, int nrows, int R, int nx, int N2x, int Kx,
+              FftPlan P, const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* stp = stw + N2x;
   cpx<T>* a = stp + N2x + 1;
-  cpx<T>* b = a + N2x;
-  const size_t row = blockIdx.x;
+  cpx<T>* b = a + (size_t)R * N2x;
+  const int row0 = (int)blockIdx.x * R;
+  if (row0 >= nrows) return;
+  const int nb = min(R, nrows - row0);
   for (int t = threadIdx.x; t < N2x; t += CUBE_THREADS) stw[t] = tw[t];
   for (int t = threadIdx.x; t <= N2x; t += CUBE_THREADS) stp[t] = twp[t];
-  const cpx<T>* X = spec + row * Kx;
   lds_barrier();
-  for (int k = threadIdx.x; k < N2x; k += CUBE_THREADS) {
+  const float ink = 1.0f / (float)N2x;
+  for (int t = threadIdx.x; t < nb * N2x; t += CUBE_THREADS) {
+    const int r = fdiv(t, ink);
+    const int k = t - r * N2x;
+    const cpx<T>* X = spec + (size_t)(row0 + r) * Kx;
     cpx<T> xk = X[k];
     cpx<T> xm = X[N2x - k];
     xm.y = -xm.y;
     cpx<T> s = xk + xm;
     cpx<T> d = cmulc(xk - xm, stp[k]);
-    a[k] = mk<T>(s.x - d.y, s.y + d.x);
+    a[t] = mk<T>(s.x - d.y, s.y + d.x);
   }
   lds_barrier();
-  const T* xr = reinterpret_cast<const T*>(fft_lds<T, true, CUBE_THREADS>(a, b, P, 1, N2x, stw));
-  for (int i = threadIdx.x; i < nx; i += CUBE_THREADS) out[row * nx + i] = xr[i];
+  const T* xr = reinterpret_cast<const T*>(fft_lds<T, true, CUBE_THREADS>(a, b, P, nb, N2x, stw));
+  const float inx = 1.0f / (float)nx;
+  for (int t = threadIdx.x; t < nb * nx; t += CUBE_THREADS) {
+    const int r = fdiv(t, inx);
+    const int i = t - r * nx;
+    out[(size_t)(row0 + r) * nx + i] = xr[(size_t)r * 2 * N2x + i];
+  }
 }
 
 // ------------------------------------------------------------ cell kernels
@@ -472,6 +487,8 @@ hipError_t launch_fft_axis(const void* in, void* out, int nplanes, int ncols, in
     CB = (int)((65536 / sizeof(cpx<T>) - P.L) / (2 * (size_t)P.L));
     if (CB > 16) CB = 16;
     if (CB < 1) CB = 1;
+    const int nblk = (ncols + CB - 1) / CB;  // spread the columns evenly over the blocks
+    CB = (ncols + nblk - 1) / nblk;
   }
   const size_t lds = sizeof(cpx<T>) * ((size_t)P.L + 2 * (size_t)CB * P.L);
   if (lds > 65536) {  // one column per block past 64 KB (the set-up bounds L so that it fits)
@@ -502,22 +519,22 @@ hipError_t launch_zmul(void* buf, const T* kern, int Kx, int Ly, int nz, int CB,
     hipError_t e = hipFuncSetAttribute((const void*)k_zmul<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  dim3 grid((Kx + CB - 1) / CB, Ly);
+  dim3 grid((Ly * Kx + CB - 1) / CB);
   hipLaunchKernelGGL(k_zmul<T>, grid, dim3(CUBE_THREADS), lds, st, (cpx<T>*)buf, kern, Kx, Ly, nz, CB, mode, (T)sgn, P,
                      (const cpx<T>*)twz);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_row_inv(const void* spec, T* out, int nrows, int nx, int N2x, int Kx, const FftPlan& P,
+hipError_t launch_row_inv(const void* spec, T* out, int nrows, int R, int nx, int N2x, int Kx, const FftPlan& P,
                           const void* tw, const void* twp, hipStream_t st) {
-  const size_t lds = sizeof(cpx<T>) * (4 * (size_t)N2x + 1);
+  const size_t lds = sizeof(cpx<T>) * (2 * (size_t)N2x + 1 + 2 * (size_t)R * N2x);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_row_inv<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_row_inv<T>, dim3(nrows), dim3(CUBE_THREADS), lds, st, (const cpx<T>*)spec, out, nx, N2x, Kx, P,
-                     (const cpx<T>*)tw, (const cpx<T>*)twp);
+  hipLaunchKernelGGL(k_row_inv<T>, dim3((nrows + R - 1) / R), dim3(CUBE_THREADS), lds, st, (const cpx<T>*)spec, out,
+                     nrows, R, nx, N2x, Kx, P, (const cpx<T>*)tw, (const cpx<T>*)twp);
   return hipGetLastError();
 }
 
@@ -615,7 +632,7 @@ hipError_t launch_pack3(const void* spec, T* out, int Kx, int Ly, int Lz, int im
                                          const FftPlan&, const void*, bool, hipStream_t);                         \
   template hipError_t launch_zmul<T>(void*, const T*, int, int, int, int, int, double, const FftPlan&,           \
                                      const void*, hipStream_t);                                                   \
-  template hipError_t launch_row_inv<T>(const void*, T*, int, int, int, int, const FftPlan&, const void*,        \
+  template hipError_t launch_row_inv<T>(const void*, T*, int, int, int, int, int, const FftPlan&, const void*,        \
                                         const void*, hipStream_t);                                                \
   template hipError_t launch_stage3<T>(const CubeLaunch&, int, int, int, double, const T*, const T*, T*, T*,    \
                                        const T*, const T*, T*, int*, hipStream_t);                                \

@@ -54,7 +54,7 @@ template <typename T>
 hipError_t launch_zmul(void* buf, const T* kern, int Kx, int Ly, int nz, int CB, int mode, double sgn,
                        const FftPlan& P, const void* twz, hipStream_t st);
 template <typename T>
-hipError_t launch_row_inv(const void* spec, T* out, int nrows, int nx, int N2x, int Kx, const FftPlan& P,
+hipError_t launch_row_inv(const void* spec, T* out, int nrows, int R, int nx, int N2x, int Kx, const FftPlan& P,
                           const void* tw, const void* twp, hipStream_t st);
 template <typename T>
 hipError_t launch_stage3(const CubeLaunch& c, int mode, int stage, int mask, double dt, const T* ms, const T* m0,

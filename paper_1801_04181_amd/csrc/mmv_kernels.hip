@@ -77,8 +77,9 @@ __device__ __forceinline__ void row_fwd_body(int row0, int nb, int rstride, cons
   }
 }
 
-// Block b transforms rows b of a (rows / 3) x 3 arrangement when `three`
-// (the x, y, z components of one film row, ny rows apart), else row b.
+// ny3 > 0: block b transforms the x, y, z components of one film row (ny3
+// rows apart); ny3 < 0: block b transforms the -ny3 consecutive rows from
+// b * -ny3 (fewer in the last block); ny3 == 0: block b transforms row b.
 template <typename T>
 __global__ void __launch_bounds__(FWD_THREADS)
     k_row_fwd(const T* __restrict__ src, cpx<T>* __restrict__ dst, int nrows, int nin, int N2x,
@@ -89,6 +90,10 @@ __global__ void __launch_bounds__(FWD_THREADS)
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int f = b / ny3, y = b - f * ny3;
     row_fwd_body<T>(f * 3 * ny3 + y, 3, ny3, src, dst, nin, N2x, Kx, P, tw, twp, ny3);
+  } else if (ny3 < 0) {
+    const int row0 = (int)blockIdx.x * -ny3;
+    if (row0 >= nrows) return;
+    row_fwd_body<T>(row0, min(-ny3, nrows - row0), 1, src, dst, nin, N2x, Kx, P, tw, twp);
   } else {
     if ((int)blockIdx.x >= nrows) return;
     row_fwd_body<T>(blockIdx.x, 1, 0, src, dst, nin, N2x, Kx, P, tw, twp);
@@ -1208,13 +1213,13 @@ __global__ void __launch_bounds__(COLPACK_THREADS)
 template <typename T>
 hipError_t launch_row_fwd(const T* src, void* dst, int nrows, int nin, int N2x, int Kx, const FftPlan& P,
                           const void* tw, const void* twp, hipStream_t st, int ny3) {
-  const int nb = ny3 > 0 ? 3 : 1;
+  const int nb = ny3 > 0 ? 3 : ny3 < 0 ? -ny3 : 1;
   const size_t lds = sizeof(cpx<T>) * (2 * (size_t)N2x + 1 + 2 * (size_t)nb * N2x);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_row_fwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  const int nblk = ny3 > 0 ? nrows / 3 : nrows;
+  const int nblk = ny3 > 0 ? nrows / 3 : ny3 < 0 ? (nrows - ny3 - 1) / -ny3 : nrows;
   hipLaunchKernelGGL(k_row_fwd<T>, dim3(nblk), dim3(FWD_THREADS), lds, st, src, (cpx<T>*)dst, nrows, nin, N2x, Kx,
                      P, (const cpx<T>*)tw, (const cpx<T>*)twp, ny3);
   return hipGetLastError();
