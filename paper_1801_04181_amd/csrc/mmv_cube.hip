@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(CUBE_THREADS)
     A[c * L + r] = r < n_in ? src[(size_t)r * ncols + c] : mk<T>(0, 0);
   }
   lds_barrier();
-  const cpx<T>* R = fft_lds<T, INV, CUBE_THREADS>(A, B, P, nc, L, stw);
+  const cpx<T>* R = fft_lds_pow2<T, INV, CUBE_THREADS>(A, B, P, nc, L, stw);
   for (int t = threadIdx.x; t < nc * n_out; t += CUBE_THREADS) {
     const int r = fdiv(t, inc);
     const int c = t - r * nc;
@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(CUBE_THREADS)
     A[b * Lz + z] = mk<T>(0, 0);
   }
   lds_barrier();
-  cpx<T>* X = fft_lds<T, false, CUBE_THREADS>(A, B, P, 3 * nc, Lz, stw);
+  cpx<T>* X = fft_lds_pow2<T, false, CUBE_THREADS>(A, B, P, 3 * nc, Lz, stw);
   for (int t = threadIdx.x; t < nc * Lz; t += CUBE_THREADS) {
     const int cc = t / Lz, kz = t - cc * Lz;
     const int ky = (q0 + cc) / Kx, kx = q0 + cc - ky * Kx;
@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(CUBE_THREADS)
     X[(2 * nc + cc) * Lz + kz] = o2;
   }
   lds_barrier();
-  cpx<T>* Y = fft_lds<T, true, CUBE_THREADS>(X, (X == A) ? B : A, P, 3 * nc, Lz, stw);
+  cpx<T>* Y = fft_lds_pow2<T, true, CUBE_THREADS>(X, (X == A) ? B : A, P, 3 * nc, Lz, stw);
   for (int t = threadIdx.x; t < 3 * nz * nc; t += CUBE_THREADS) {
     const int cz = fdiv(t, inc);
     const int cc = t - cz * nc;
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(CUBE_THREADS)
     a[t] = mk<T>(s.x - d.y, s.y + d.x);
   }
   lds_barrier();
-  const T* xr = reinterpret_cast<const T*>(fft_lds<T, true, CUBE_THREADS>(a, b, P, nb, N2x, stw));
+  const T* xr = reinterpret_cast<const T*>(fft_lds_pow2<T, true, CUBE_THREADS>(a, b, P, nb, N2x, stw));
   const float inx = 1.0f / (float)nx;
   for (int t = threadIdx.x; t < nb * nx; t += CUBE_THREADS) {
     const int r = fdiv(t, inx);

@@ -142,6 +142,27 @@ __device__ __forceinline__ void dft(cpx<T>* v) {
     v[2] = t0 - t2;
     v[1] = t1 + t3;
     v[3] = t1 - t3;
+  } else if constexpr (R == 8) {
+    // two length-4 DFTs of the even and odd samples, odd half twiddled by
+    // w^k = exp(-+2 pi i k / 8), combined as X[k], X[k + 4] = e_k +- w^k o_k
+    cpx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cpx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    dft<T, 4, INV>(e);
+    dft<T, 4, INV>(o);
+    const T h = T(0.70710678118654752440);
+    const cpx<T> o1 = INV ? mk((o[1].x - o[1].y) * h, (o[1].x + o[1].y) * h)
+                          : mk((o[1].x + o[1].y) * h, (o[1].y - o[1].x) * h);
+    const cpx<T> o2 = INV ? mk(-o[2].y, o[2].x) : mk(o[2].y, -o[2].x);
+    const cpx<T> o3 = INV ? mk((-o[3].x - o[3].y) * h, (o[3].x - o[3].y) * h)
+                          : mk((o[3].y - o[3].x) * h, (-o[3].x - o[3].y) * h);
+    v[0] = e[0] + o[0];
+    v[4] = e[0] - o[0];
+    v[1] = e[1] + o1;
+    v[5] = e[1] - o1;
+    v[2] = e[2] + o2;
+    v[6] = e[2] - o2;
+    v[3] = e[3] + o3;
+    v[7] = e[3] - o3;
   } else if constexpr (R == 6) {
     // prime-factor 2 x 3 (no twiddles): inputs n = (3 n1 + 2 n2) mod 6,
     // outputs k = (3 k1 + 4 k2) mod 6
@@ -278,7 +299,8 @@ __device__ __forceinline__ void stockham_pass(const cpx<T>* __restrict__ a, cpx<
 // For the lengths the workloads use, the radix plan, butterfly counts, thread
 // mapping and LDS strides are compile-time constants: index arithmetic folds,
 // LDS accesses take immediate offsets.  Radices: 7, 5, then 3s paired into 9,
-// then 4s, and a remaining 2 paired with a 3 into 6.
+// then 4s, and a remaining 2 paired with a 3 into 6; a power of two takes
+// 8s, then a 4 or a 2.
 struct CPlan {
   int np;
   int r[12];
@@ -291,6 +313,11 @@ constexpr CPlan make_cplan(int L) {
   while (n % 5 == 0) { p.r[p.np++] = 5; n /= 5; }
   while (n % 3 == 0) { ++n3; n /= 3; }
   while (n % 2 == 0) { ++n2; n /= 2; }
+  if (n == 1 && p.np == 0 && n3 == 0) {  // power of two
+    while (n2 >= 3) { p.r[p.np++] = 8; n2 -= 3; }
+    if (n2 > 0) p.r[p.np++] = n2 == 2 ? 4 : 2;
+    return p;
+  }
   if (n2 % 2 == 1 && n3 > 0) { p.r[p.np++] = 6; --n3; --n2; }
   while (n3 >= 2) { p.r[p.np++] = 9; n3 -= 2; }
   if (n3 == 1) p.r[p.np++] = 3;
@@ -414,6 +441,21 @@ __device__ __forceinline__ cpx<T>* fft_lds(cpx<T>* a, cpx<T>* b, const FftPlan& 
     }
   }
   return fft_lds_generic<T, INV, NT>(a, b, P, batch, stride, tw, twh);
+}
+
+// Dispatch of the three-dimensional path: compiled plans for contiguous
+// transforms of 64 and 128 points, else as fft_lds.
+template <typename T, bool INV, int NT>
+__device__ __forceinline__ cpx<T>* fft_lds_pow2(cpx<T>* a, cpx<T>* b, const FftPlan& P, int batch, int stride,
+                                                const cpx<T>* __restrict__ tw) {
+  if (stride == P.L) {
+    switch (P.L) {
+      case 64: return fft_ct_from<T, 64, NT, INV, false, 0, 1>(a, b, batch, tw);
+      case 128: return fft_ct_from<T, 128, NT, INV, false, 0, 1>(a, b, batch, tw);
+      default: break;
+    }
+  }
+  return fft_lds<T, INV, NT>(a, b, P, batch, stride, tw);
 }
 
 }  // namespace mmv

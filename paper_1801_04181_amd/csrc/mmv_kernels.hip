@@ -38,7 +38,8 @@ static_assert(TICK_THREADS == COL_THREADS, "the y pass runs the tick with its ow
 // rows apart (the three components of one film row, or one row).  Output
 // layout: tny == 0, row-major [row][Kx]; tny > 0 (film spectra), column-major
 // [row / tny][Kx][row % tny], so the y pass reads each column contiguously.
-template <typename T>
+// POW2: compiled transforms for 64 and 128 points (the 3-D path's rows).
+template <typename T, bool POW2 = false>
 __device__ __forceinline__ void row_fwd_body(int row0, int nb, int rstride, const T* __restrict__ src,
                                              cpx<T>* __restrict__ dst, int nin, int N2x, int Kx, const FftPlan& P,
                                              const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ twp,
@@ -59,7 +60,8 @@ __device__ __forceinline__ void row_fwd_body(int row0, int nb, int rstride, cons
     a[t] = mk<T>(i0 < nin ? s[i0] : T(0), i1 < nin ? s[i1] : T(0));
   }
   lds_barrier();
-  cpx<T>* Z = fft_lds<T, false, FWD_THREADS>(a, b, P, nb, N2x, stw);
+  cpx<T>* Z = POW2 ? fft_lds_pow2<T, false, FWD_THREADS>(a, b, P, nb, N2x, stw)
+                   : fft_lds<T, false, FWD_THREADS>(a, b, P, nb, N2x, stw);
   const int K1 = N2x + 1;
   const float ink = 1.0f / (float)K1;
   for (int t = threadIdx.x; t < nb * K1; t += FWD_THREADS) {
@@ -93,7 +95,7 @@ __global__ void __launch_bounds__(FWD_THREADS)
   } else if (ny3 < 0) {
     const int row0 = (int)blockIdx.x * -ny3;
     if (row0 >= nrows) return;
-    row_fwd_body<T>(row0, min(-ny3, nrows - row0), 1, src, dst, nin, N2x, Kx, P, tw, twp);
+    row_fwd_body<T, true>(row0, min(-ny3, nrows - row0), 1, src, dst, nin, N2x, Kx, P, tw, twp);
   } else {
     if ((int)blockIdx.x >= nrows) return;
     row_fwd_body<T>(blockIdx.x, 1, 0, src, dst, nin, N2x, Kx, P, tw, twp);
