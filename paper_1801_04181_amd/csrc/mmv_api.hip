@@ -119,7 +119,8 @@ struct mmv_mesh {
   void* twz = nullptr;
   void* specB = nullptr;
   void* kern_s = nullptr;  // potential kernel S (eddy currents)
-  void *hd = nullptr, *he = nullptr, *bprev = nullptr, *bdot = nullptr, *es = nullptr, *phi = nullptr, *rr = nullptr;
+  void *hd = nullptr, *he = nullptr, *bprev = nullptr, *bdot = nullptr, *es = nullptr, *phi = nullptr, *phi2 = nullptr,
+       *rr = nullptr;
   double* red = nullptr;   // reduction partials + mean
   CubeLaunch cl{};
   bool eddy_first = true;
@@ -634,6 +635,7 @@ int init_cube(mmv_mesh* h) {
     for (void** b : e3)
       if ((rc = dalloc(h, b, 3 * N * sizeof(T)))) return rc;
     if ((rc = dalloc(h, &h->phi, N * sizeof(T)))) return rc;
+    if ((rc = dalloc(h, &h->phi2, N * sizeof(T)))) return rc;
     if ((rc = dalloc(h, &h->rr, N * sizeof(T)))) return rc;
     HIPCHK(hipMemsetAsync(h->phi, 0, N * sizeof(T), h->st));
   }
@@ -705,7 +707,7 @@ int eddy_update(mmv_mesh* h, double dt) {
   int rc = conv3<T>(h, h->bdot, h->es, (const T*)h->kern_s, 1, +1.0);
   if (rc) return rc;
   HIPCHK(launch_sor_rhs<T>(h->cl, (const T*)h->es, (T*)h->rr, h->red, mean, h->st));
-  HIPCHK(launch_sor<T>(h->cl, (T*)h->phi, (const T*)h->rr, h->sor_omega, h->sor_sweeps, h->red, mean, h->st));
+  HIPCHK(launch_sor<T>(h->cl, (T*)h->phi, (T*)h->phi2, (const T*)h->rr, h->sor_omega, h->sor_sweeps, h->red, mean, h->st));
   HIPCHK(launch_current<T>(h->cl, (const T*)h->phi, (const T*)h->es, (T*)h->bdot, h->d.sigma, h->st));
   (void)part;
   return conv3<T>(h, h->bdot, h->he, (const T*)h->kern_s, 1, -1.0);

@@ -10,7 +10,7 @@
 //                Biot-Savart field of J), inverse z transform.
 //   k_row_inv    inverse real x transform of each row into cell values.
 //   k_stage3     local terms, LLG (Eq. 1) and the RK4 stage on each cell.
-//   k_bdot, k_sor_rhs, k_sor, k_current, k_sum_*, k_shift
+//   k_bdot, k_sor_rhs, k_sor_tile, k_current, k_sum_*, k_shift
 //                B and dB/dt, the finite-volume Neumann problem for the
 //                electric potential and its red-black SOR sweeps, J.
 #include <hip/hip_runtime.h>
@@ -367,40 +367,134 @@ __global__ void __launch_bounds__(256) k_sum_final(int n, const double* __restri
   if (threadIdx.x == 0) *mean = red[0] * inv_count;
 }
 
+// dst = src - mean (src may be dst)
 template <typename T>
-__global__ void k_shift(size_t N, T* __restrict__ x, const double* __restrict__ mean) {
+__global__ void k_shift(size_t N, const T* src, T* dst, const double* __restrict__ mean) {
   for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < N; id += (size_t)gridDim.x * blockDim.x)
-    x[id] = (T)((double)x[id] - *mean);
+    dst[id] = (T)((double)src[id] - *mean);
 }
 
-// One colour of a red-black SOR sweep (colour = (i + j + k) mod 2).
-template <typename T>
-__global__ void __launch_bounds__(256)
-    k_sor(int nx, int ny, int nz, double dx, double dy, double dz, T* __restrict__ phi,
-          const T* __restrict__ r, double omega, int colour) {
-  // thread (x, y) owns the x-th cell of this colour in row (j = y, k):
-  // i = 2 x + ((colour + j + k) & 1), no index division (the launch covers
-  // every cell with one pass of the strided loops)
-  const int k = blockIdx.z;
-  const int nxh = (nx + 1) / 2;
-  const T wx = T(1.0 / (dx * dx)), wy = T(1.0 / (dy * dy)), wz = T(1.0 / (dz * dz));
+// Red-black SOR sweeps (colour = (i + j + k) mod 2, red = 0 first) on 3-D
+// tiles.  A cell's update is
+//   phi <- (1 - omega) phi + omega (sum_nb w_nb phi_nb - r) / sum_nb w_nb
+// over its face neighbours inside the mesh (w = 1/d^2 of the axis; a mesh
+// face contributes nothing, the Neumann condition being in r); all cells of
+// one colour update from the other colour's values, so the order within a
+// half-sweep does not matter.
+constexpr int SOR_THREADS = 256;
+constexpr int SOR_T = 8;                    // tile edge
+constexpr int SOR_S = 2;                    // sweeps per launch at most
+constexpr int SOR_H = 2 * SOR_S;            // halo
+constexpr int SOR_D = SOR_T + 2 * SOR_H;    // loaded box edge
+
+// One half-sweep of `colour` over the centred E^3 region of the LDS box
+// (E even).  Every neighbour of the region lies in the box.  A thread
+// computes all of its new values before storing any: the half-sweep reads
+// only the other colour and each updated cell's own old value.
+template <typename T, int E>
+__device__ __forceinline__ void sor_half(T* sp, const T* sr, int colour, int ox, int oy, int oz, int nx, int ny,
+                                         int nz, T wx, T wy, T wz, T om) {
+  constexpr int D = SOR_D, D2 = D * D, O = (SOR_D - E) / 2, EH = E / 2;
+  constexpr int NC = E * E * E / 2, NU = (NC + SOR_THREADS - 1) / SOR_THREADS;
+  static_assert(E % 2 == 0 && O >= 1, "the region and its neighbours lie in the box");
+  T val[NU];
+  int cell[NU];
+#pragma unroll
+  for (int u = 0; u < NU; ++u) {
+    const int t = (int)threadIdx.x + u * SOR_THREADS;
+    const int row = t / EH, xh = t - row * EH;
+    const int lj = O + row % E, lk = O + row / E;
+    const int j = oy + lj, k = oz + lk;
+    const int li = O + 2 * xh + ((colour - ox - O - j - k) & 1);
+    const int i = ox + li;
+    const bool upd = t < NC && i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
+    const bool x0 = i > 0, x1 = i < nx - 1, y0 = j > 0, y1 = j < ny - 1, z0 = k > 0, z1 = k < nz - 1;
+    const int c = upd ? lk * D2 + lj * D + li : D2 + D + 1;  // an in-box cell for the lanes past the region
+    const T px0 = sp[c - 1], px1 = sp[c + 1], py0 = sp[c - D], py1 = sp[c + D], pz0 = sp[c - D2],
+            pz1 = sp[c + D2], pc = sp[c], rc = sr[c];
+    // absent neighbours enter with weight 0 (s + 0 * 0 and w + 0 are exact)
+    T s = 0, w = 0;
+    s = fma(x0 ? px0 : T(0), x0 ? wx : T(0), s);
+    w += x0 ? wx : T(0);
+    s = fma(x1 ? px1 : T(0), x1 ? wx : T(0), s);
+    w += x1 ? wx : T(0);
+    s = fma(y0 ? py0 : T(0), y0 ? wy : T(0), s);
+    w += y0 ? wy : T(0);
+    s = fma(y1 ? py1 : T(0), y1 ? wy : T(0), s);
+    w += y1 ? wy : T(0);
+    s = fma(z0 ? pz0 : T(0), z0 ? wz : T(0), s);
+    w += z0 ? wz : T(0);
+    s = fma(z1 ? pz1 : T(0), z1 ? wz : T(0), s);
+    w += z1 ? wz : T(0);
+    const bool ok = upd && w != T(0);
+    val[u] = (T(1) - om) * pc + om * ((s - rc) / (ok ? w : T(1)));
+    cell[u] = ok ? c : -1;
+  }
+#pragma unroll
+  for (int u = 0; u < NU; ++u)
+    if (cell[u] >= 0) sp[cell[u]] = val[u];
+  lds_barrier();
+}
+
+// Half-sweeps HS .. 2 NSW - 1 of a launch: half-sweep h updates the region
+// of edge SOR_T + 2 (2 NSW - 1 - h), the cells the tile still depends on,
+// which reads the region of half-sweep h - 1 (the whole box for h = 0).
+template <typename T, int NSW, int HS>
+__device__ __forceinline__ void sor_halves(T* sp, const T* sr, int ox, int oy, int oz, int nx, int ny, int nz, T wx,
+                                           T wy, T wz, T om) {
+  if constexpr (HS < 2 * NSW) {
+    sor_half<T, SOR_T + 2 * (2 * NSW - 1 - HS)>(sp, sr, HS & 1, ox, oy, oz, nx, ny, nz, wx, wy, wz, om);
+    sor_halves<T, NSW, HS + 1>(sp, sr, ox, oy, oz, nx, ny, nz, wx, wy, wz, om);
+  }
+}
+
+// NSW <= SOR_S sweeps in one launch.  Block (bx, by, bz) loads the box of
+// the 8^3 tile of cells from (8 bx, 8 by, 8 bz) with a halo of 2 SOR_S
+// cells (the parts inside the mesh) from pin into LDS, runs the 2 NSW
+// half-sweeps there and writes the tile's cells (those inside the mesh) to
+// pout, as global half-sweeps would leave them.
+template <typename T, int NSW>
+__global__ void __launch_bounds__(SOR_THREADS)
+    k_sor_tile(int nx, int ny, int nz, double dx, double dy, double dz, const T* __restrict__ pin,
+               T* __restrict__ pout, const T* __restrict__ r, double omega) {
+  static_assert(NSW >= 1 && NSW <= SOR_S, "the halo covers the half-sweeps");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int D = SOR_D, D2 = D * D, D3 = D * D * D;
+  T* sp = reinterpret_cast<T*>(smem_raw);
+  T* sr = sp + D3;
+  const int ox = (int)blockIdx.x * SOR_T - SOR_H, oy = (int)blockIdx.y * SOR_T - SOR_H,
+            oz = (int)blockIdx.z * SOR_T - SOR_H;
   const size_t sy = nx, sz = (size_t)nx * ny;
-  for (int j = blockIdx.y * blockDim.y + threadIdx.y; j < ny; j += gridDim.y * blockDim.y)
-    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < nxh; x += gridDim.x * blockDim.x) {
-      const int i = 2 * x + ((colour + j + k) & 1);
-      if (i >= nx) continue;
+  // all of a thread's loads in flight before the first LDS store
+  constexpr int NL = D3 / SOR_THREADS;
+  static_assert(NL * SOR_THREADS == D3, "the box is a whole number of block passes");
+  T vp[NL], vr[NL];
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int t = (int)threadIdx.x + u * SOR_THREADS;
+    const int li = t % D, lj = (t / D) % D, lk = t / D2;
+    const int i = ox + li, j = oy + lj, k = oz + lk;
+    vp[u] = vr[u] = T(0);
+    if (i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz) {
       const size_t id = (size_t)k * sz + (size_t)j * sy + i;
-      T s = 0, w = 0;
-      if (i > 0) { s += phi[id - 1] * wx; w += wx; }
-      if (i < nx - 1) { s += phi[id + 1] * wx; w += wx; }
-      if (j > 0) { s += phi[id - sy] * wy; w += wy; }
-      if (j < ny - 1) { s += phi[id + sy] * wy; w += wy; }
-      if (k > 0) { s += phi[id - sz] * wz; w += wz; }
-      if (k < nz - 1) { s += phi[id + sz] * wz; w += wz; }
-      if (w == T(0)) continue;
-      const T upd = (s - r[id]) / w;
-      phi[id] = (T(1) - (T)omega) * phi[id] + (T)omega * upd;
+      vp[u] = pin[id];
+      vr[u] = r[id];
     }
+  }
+#pragma unroll
+  for (int u = 0; u < NL; ++u) {
+    const int t = (int)threadIdx.x + u * SOR_THREADS;
+    sp[t] = vp[u];
+    sr[t] = vr[u];
+  }
+  lds_barrier();
+  const T wx = T(1.0 / (dx * dx)), wy = T(1.0 / (dy * dy)), wz = T(1.0 / (dz * dz));
+  sor_halves<T, NSW, 0>(sp, sr, ox, oy, oz, nx, ny, nz, wx, wy, wz, (T)omega);
+  for (int t = threadIdx.x; t < SOR_T * SOR_T * SOR_T; t += SOR_THREADS) {
+    const int li = SOR_H + t % SOR_T, lj = SOR_H + (t / SOR_T) % SOR_T, lk = SOR_H + t / (SOR_T * SOR_T);
+    const int i = ox + li, j = oy + lj, k = oz + lk;
+    if (i < nx && j < ny && k < nz) pout[(size_t)k * sz + (size_t)j * sy + i] = sp[lk * D2 + lj * D + li];
+  }
 }
 
 // J = sigma (E_sol + E_irrot), E_irrot,a = -(g+ + g-)/2, surface faces take E_sol,a.
@@ -579,24 +673,35 @@ hipError_t launch_sor_rhs(const CubeLaunch& c, const T* es, T* r, double* part, 
   const int nb = (int)((N + 255) / 256);
   hipLaunchKernelGGL(k_sor_rhs<T>, dim3(nb), dim3(256), 0, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz, es, r, part);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, nb, (const double*)part, mean, 1.0 / (double)N);
-  hipLaunchKernelGGL(k_shift<T>, grid1(N), dim3(256), 0, st, N, r, (const double*)mean);
+  hipLaunchKernelGGL(k_shift<T>, grid1(N), dim3(256), 0, st, N, (const T*)r, r, (const double*)mean);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_sor(const CubeLaunch& c, T* phi, const T* r, double omega, int sweeps, double* part, double* mean,
-                      hipStream_t st) {
+hipError_t launch_sor(const CubeLaunch& c, T* phi, T* phi2, const T* r, double omega, int sweeps, double* part,
+                      double* mean, hipStream_t st) {
   const size_t N = (size_t)c.nx * c.ny * c.nz;
-  // one thread per cell of the swept colour: rows of (nx + 1) / 2, 32 x 8
-  // threads per block, one z layer per grid slice
-  const dim3 blk(32, 8), grid((unsigned)(((c.nx + 1) / 2 + 31) / 32), (unsigned)((c.ny + 7) / 8), (unsigned)c.nz);
-  for (int s = 0; s < sweeps; ++s)
-    for (int col = 0; col < 2; ++col)
-      hipLaunchKernelGGL(k_sor<T>, grid, blk, 0, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz, phi, r, omega, col);
+  // SOR_S sweeps per launch on tiles, alternating between phi and phi2
+  const dim3 grid((unsigned)((c.nx + SOR_T - 1) / SOR_T), (unsigned)((c.ny + SOR_T - 1) / SOR_T),
+                  (unsigned)((c.nz + SOR_T - 1) / SOR_T));
+  const size_t lds = 2 * sizeof(T) * SOR_D * SOR_D * SOR_D;
+  T* cur = phi;
+  T* nxt = phi2;
+  for (int s = 0; s < sweeps; s += SOR_S) {
+    if (sweeps - s >= 2)
+      hipLaunchKernelGGL((k_sor_tile<T, 2>), grid, dim3(SOR_THREADS), lds, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz,
+                         (const T*)cur, nxt, r, omega);
+    else
+      hipLaunchKernelGGL((k_sor_tile<T, 1>), grid, dim3(SOR_THREADS), lds, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz,
+                         (const T*)cur, nxt, r, omega);
+    T* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
   const int nb = (int)((N + 255) / 256);
-  hipLaunchKernelGGL(k_sum_part<T>, dim3(nb), dim3(256), 0, st, N, (const T*)phi, part);
+  hipLaunchKernelGGL(k_sum_part<T>, dim3(nb), dim3(256), 0, st, N, (const T*)cur, part);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, nb, (const double*)part, mean, 1.0 / (double)N);
-  hipLaunchKernelGGL(k_shift<T>, grid1(N), dim3(256), 0, st, N, phi, (const double*)mean);
+  hipLaunchKernelGGL(k_shift<T>, grid1(N), dim3(256), 0, st, N, (const T*)cur, phi, (const double*)mean);
   return hipGetLastError();
 }
 
@@ -639,7 +744,8 @@ hipError_t launch_pack3(const void* spec, T* out, int Kx, int Ly, int Lz, int im
   template hipError_t launch_eddy_bdot<T>(size_t, const T*, const T*, T*, T*, double, double, const double*,     \
                                           double, int, hipStream_t);                                              \
   template hipError_t launch_sor_rhs<T>(const CubeLaunch&, const T*, T*, double*, double*, hipStream_t);         \
-  template hipError_t launch_sor<T>(const CubeLaunch&, T*, const T*, double, int, double*, double*, hipStream_t); \
+  template hipError_t launch_sor<T>(const CubeLaunch&, T*, T*, const T*, double, int, double*, double*,          \
+                                     hipStream_t);                                                             \
   template hipError_t launch_current<T>(const CubeLaunch&, const T*, const T*, T*, double, hipStream_t);         \
   template hipError_t launch_pack3<T>(const void*, T*, int, int, int, int, hipStream_t);
 

@@ -65,7 +65,7 @@ hipError_t launch_eddy_bdot(size_t N, const T* m, const T* hd, T* bprev, T* bdot
 template <typename T>
 hipError_t launch_sor_rhs(const CubeLaunch& c, const T* es, T* r, double* part, double* mean, hipStream_t st);
 template <typename T>
-hipError_t launch_sor(const CubeLaunch& c, T* phi, const T* r, double omega, int sweeps, double* part, double* mean,
+hipError_t launch_sor(const CubeLaunch& c, T* phi, T* phi2, const T* r, double omega, int sweeps, double* part, double* mean,
                       hipStream_t st);
 template <typename T>
 hipError_t launch_current(const CubeLaunch& c, const T* phi, const T* es, T* J, double sigma, hipStream_t st);
