@@ -35,10 +35,13 @@ __global__ void __launch_bounds__(CUBE_THREADS)
   cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* A = stw + L;
   cpx<T>* B = A + (size_t)CB * L;
-  const int c0 = blockIdx.x * CB;
+  // the column groups of one plane share cache lines: keep them on one XCD
+  const int lb = xcd_remap(blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y);
+  const int by = lb / gridDim.x;
+  const int c0 = (lb - by * gridDim.x) * CB;
   if (c0 >= ncols) return;
   const int nc = min(CB, ncols - c0);
-  const long long p = blockIdx.y;
+  const long long p = by;
   const cpx<T>* src = in + p * in_ps + c0;
   cpx<T>* dst = out + p * out_ps + c0;
   for (int t = threadIdx.x; t < L; t += CUBE_THREADS) stw[t] = tw[t];
@@ -76,7 +79,8 @@ __global__ void __launch_bounds__(CUBE_THREADS)
   cpx<T>* A = stw + Lz;
   cpx<T>* B = A + (size_t)3 * CB * Lz;
   const int ncol = Ly * Kx;
-  const int q0 = blockIdx.x * CB;
+  // neighbouring pencil groups share cache lines: keep them on one XCD
+  const int q0 = xcd_remap(blockIdx.x, gridDim.x) * CB;
   if (q0 >= ncol) return;
   const int nc = min(CB, ncol - q0);
   const long long zs = ncol, cs = (long long)nz * ncol;  // plane and channel strides
