@@ -452,7 +452,7 @@ __device__ __forceinline__ void sor_halves(T* sp, const T* sr, int ox, int oy, i
   }
 }
 
-// NSW <= SOR_S sweeps in one launch.  Block (bx, by, bz) loads the box of
+// NSW <= SOR_S sweeps in one launch.  Tile (bx, by, bz) loads the box of
 // the 8^3 tile of cells from (8 bx, 8 by, 8 bz) with a halo of 2 SOR_S
 // cells (the parts inside the mesh) from pin into LDS, runs the 2 NSW
 // half-sweeps there and writes the tile's cells (those inside the mesh) to
@@ -466,8 +466,12 @@ __global__ void __launch_bounds__(SOR_THREADS)
   constexpr int D = SOR_D, D2 = D * D, D3 = D * D * D;
   T* sp = reinterpret_cast<T*>(smem_raw);
   T* sr = sp + D3;
-  const int ox = (int)blockIdx.x * SOR_T - SOR_H, oy = (int)blockIdx.y * SOR_T - SOR_H,
-            oz = (int)blockIdx.z * SOR_T - SOR_H;
+  // neighbouring tiles share halo cells: consecutive tiles (x fastest, then
+  // y, z) go to one XCD
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int lb = xcd_remap((blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x, gx * gy * gridDim.z);
+  const int bz = lb / (gx * gy), byx = lb - bz * gx * gy, by = byx / gx, bx = byx - by * gx;
+  const int ox = bx * SOR_T - SOR_H, oy = by * SOR_T - SOR_H, oz = bz * SOR_T - SOR_H;
   const size_t sy = nx, sz = (size_t)nx * ny;
   // all of a thread's loads in flight before the first LDS store
   constexpr int NL = D3 / SOR_THREADS;
