@@ -55,6 +55,16 @@ def test_cube_small_with_eddy(prec):
     assert out["m"] < (1e-6 if prec == 32 else 1e-12)
 
 
+@pytest.mark.parametrize("prec,sweeps", [(32, 5), (64, 5), (64, 4)])
+def test_cube_eddy_tiles_with_interior_halos(prec, sweeps):
+    """A mesh of 5 x 3 x 3 SOR tiles (8^3 cells, ragged at the far faces)
+    whose inner tiles have halo faces inside the mesh, with an odd sweep
+    count (one launch of a single sweep) and an even one."""
+    d = get_config("cube_eddy")["desc"].replace(nx=37, ny=21, nz=19, precision=prec, sor_sweeps=sweeps)
+    out = run(d, 3)
+    assert out["m"] < (1e-6 if prec == 32 else 1e-12)
+
+
 @pytest.mark.parametrize("prec", [32, 64])
 def test_cube_without_eddy_ragged(prec):
     d = get_config("cube_eddy")["desc"].replace(nx=7, ny=13, nz=5, sigma=0.0, precision=prec, Ku=4e5,
