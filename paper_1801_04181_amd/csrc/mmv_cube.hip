@@ -46,11 +46,16 @@ __global__ void __launch_bounds__(CUBE_THREADS)
   cpx<T>* dst = out + p * out_ps + c0;
   for (int t = threadIdx.x; t < L; t += CUBE_THREADS) stw[t] = tw[t];
   const float inc = 1.0f / (float)nc;
-  for (int t = threadIdx.x; t < nc * L; t += CUBE_THREADS) {
-    const int r = fdiv(t, inc);
-    const int c = t - r * nc;
-    A[c * L + r] = r < n_in ? src[(size_t)r * ncols + c] : mk<T>(0, 0);
-  }
+  stage_move<4, CUBE_THREADS>(
+      nc * L,
+      [&](int t) {
+        const int r = fdiv(t, inc);
+        return r < n_in ? src[(size_t)r * ncols + (t - r * nc)] : mk<T>(0, 0);
+      },
+      [&](int t, cpx<T> v) {
+        const int r = fdiv(t, inc);
+        A[(t - r * nc) * L + r] = v;
+      });
   lds_barrier();
   const cpx<T>* R = fft_lds_pow2<T, INV, CUBE_THREADS>(A, B, P, nc, L, stw);
   for (int t = threadIdx.x; t < nc * n_out; t += CUBE_THREADS) {
@@ -86,12 +91,18 @@ __global__ void __launch_bounds__(CUBE_THREADS)
   const long long zs = ncol, cs = (long long)nz * ncol;  // plane and channel strides
   for (int t = threadIdx.x; t < Lz; t += CUBE_THREADS) stw[t] = twz[t];
   const float inc = 1.0f / (float)nc;
-  for (int t = threadIdx.x; t < 3 * nz * nc; t += CUBE_THREADS) {
-    const int cz = fdiv(t, inc);  // c * nz + z
-    const int cc = t - cz * nc;
-    const int c = cz / nz, z = cz - c * nz;
-    A[(c * nc + cc) * Lz + z] = buf[c * cs + z * zs + q0 + cc];
-  }
+  stage_move<4, CUBE_THREADS>(
+      3 * nz * nc,
+      [&](int t) {
+        const int cz = fdiv(t, inc);  // c * nz + z
+        const int c = cz / nz, z = cz - c * nz;
+        return buf[c * cs + z * zs + q0 + (t - cz * nc)];
+      },
+      [&](int t, cpx<T> v) {
+        const int cz = fdiv(t, inc);
+        const int c = cz / nz, z = cz - c * nz;
+        A[(c * nc + t - cz * nc) * Lz + z] = v;
+      });
   for (int t = threadIdx.x; t < 3 * nc * (Lz - nz); t += CUBE_THREADS) {
     const int b = t / (Lz - nz), z = nz + t - b * (Lz - nz);
     A[b * Lz + z] = mk<T>(0, 0);
@@ -164,7 +175,7 @@ __global__ void __launch_bounds__(CUBE_THREADS)
   for (int t = threadIdx.x; t <= N2x; t += CUBE_THREADS) stp[t] = twp[t];
   lds_barrier();
   const float ink = 1.0f / (float)N2x;
-  for (int t = threadIdx.x; t < nb * N2x; t += CUBE_THREADS) {
+  stage_copy<4, CUBE_THREADS>(a, nb * N2x, [&](int t) {
     const int r = fdiv(t, ink);
     const int k = t - r * N2x;
     const cpx<T>* X = spec + (size_t)(row0 + r) * Kx;
@@ -173,8 +184,8 @@ __global__ void __launch_bounds__(CUBE_THREADS)
     xm.y = -xm.y;
     cpx<T> s = xk + xm;
     cpx<T> d = cmulc(xk - xm, stp[k]);
-    a[t] = mk<T>(s.x - d.y, s.y + d.x);
-  }
+    return mk<T>(s.x - d.y, s.y + d.x);
+  });
   lds_barrier();
   const T* xr = reinterpret_cast<const T*>(fft_lds_pow2<T, true, CUBE_THREADS>(a, b, P, nb, N2x, stw));
   const float inx = 1.0f / (float)nx;

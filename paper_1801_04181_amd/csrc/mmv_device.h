@@ -212,6 +212,26 @@ __device__ __forceinline__ void stage_copy(V* dst, int n, F load) {
   }
 }
 
+// As stage_copy, for a destination that is not dst[t]: store(t, load(t)).
+template <int U, int NT, typename F, typename S>
+__device__ __forceinline__ void stage_move(int n, F load, S store) {
+  using V = decltype(load(0));
+#pragma unroll 1
+  for (int t0 = threadIdx.x; t0 < n; t0 += U * NT) {
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * NT;
+      if (t < n) v[u] = load(t);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * NT;
+      if (t < n) store(t, v[u]);
+    }
+  }
+}
+
 // Block barrier for data exchanged through LDS only.  It waits for this
 // wave's LDS operations but not for its global loads: on this architecture
 // the workgroup fence of __syncthreads() waits for every outstanding

@@ -52,13 +52,13 @@ __device__ __forceinline__ void row_fwd_body(int row0, int nb, int rstride, cons
   for (int t = threadIdx.x; t < N2x; t += FWD_THREADS) stw[t] = tw[t];
   for (int t = threadIdx.x; t <= N2x; t += FWD_THREADS) stp[t] = twp[t];
   const float inv = 1.0f / (float)N2x;
-  for (int t = threadIdx.x; t < nb * N2x; t += FWD_THREADS) {
+  stage_copy<4, FWD_THREADS>(a, nb * N2x, [&](int t) {
     const int r = fdiv(t, inv);
     const int n = t - r * N2x;
     const T* s = src + (size_t)(row0 + r * rstride) * nin;
     const int i0 = 2 * n, i1 = 2 * n + 1;
-    a[t] = mk<T>(i0 < nin ? s[i0] : T(0), i1 < nin ? s[i1] : T(0));
-  }
+    return mk<T>(i0 < nin ? s[i0] : T(0), i1 < nin ? s[i1] : T(0));
+  });
   lds_barrier();
   cpx<T>* Z = POW2 ? fft_lds_pow2<T, false, FWD_THREADS>(a, b, P, nb, N2x, stw)
                    : fft_lds<T, false, FWD_THREADS>(a, b, P, nb, N2x, stw);
