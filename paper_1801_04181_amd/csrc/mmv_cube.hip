@@ -71,7 +71,11 @@ __global__ void __launch_bounds__(CUBE_THREADS)
 // imaginary); the other half follows from the parity in y and z.
 // mode 0: out_a = sum_b N_ab v_b (six components xx yy zz xy xz yz)
 // mode 1: out = sgn * S x v (components Sx Sy Sz)
-template <typename T>
+// IP: Lz of 64 or 128 points, transformed in place (one LDS buffer, at most
+// ZMUL_IP_CB pencils per block); else ping-pong buffers.
+constexpr int ZMUL_IP_CB = 5;
+
+template <typename T, bool IP>
 __global__ void __launch_bounds__(CUBE_THREADS)
     k_zmul(cpx<T>* __restrict__ buf, const T* __restrict__ kern, int Kx, int Ly, int nz, int CB, int mode,
            T sgn, FftPlan P, const cpx<T>* __restrict__ twz) {
@@ -82,7 +86,7 @@ __global__ void __launch_bounds__(CUBE_THREADS)
   const int Kyh = Ly / 2 + 1, Kzh = Lz / 2 + 1;
   cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* A = stw + Lz;
-  cpx<T>* B = A + (size_t)3 * CB * Lz;
+  cpx<T>* B = IP ? A : A + (size_t)3 * CB * Lz;
   const int ncol = Ly * Kx;
   // neighbouring pencil groups share cache lines: keep them on one XCD
   const int q0 = xcd_remap(blockIdx.x, gridDim.x) * CB;
@@ -108,7 +112,15 @@ __global__ void __launch_bounds__(CUBE_THREADS)
     A[b * Lz + z] = mk<T>(0, 0);
   }
   lds_barrier();
-  cpx<T>* X = fft_lds_pow2<T, false, CUBE_THREADS>(A, B, P, 3 * nc, Lz, stw);
+  cpx<T>* X = A;
+  if constexpr (IP) {
+    if (Lz == 128)
+      fft_inplace<T, 128, CUBE_THREADS, false, 3 * ZMUL_IP_CB>(A, 3 * nc, stw);
+    else
+      fft_inplace<T, 64, CUBE_THREADS, false, 3 * ZMUL_IP_CB>(A, 3 * nc, stw);
+  } else {
+    X = fft_lds_pow2<T, false, CUBE_THREADS>(A, B, P, 3 * nc, Lz, stw);
+  }
   for (int t = threadIdx.x; t < nc * Lz; t += CUBE_THREADS) {
     const int cc = t / Lz, kz = t - cc * Lz;
     const int ky = (q0 + cc) / Kx, kx = q0 + cc - ky * Kx;
@@ -147,7 +159,15 @@ __global__ void __launch_bounds__(CUBE_THREADS)
     X[(2 * nc + cc) * Lz + kz] = o2;
   }
   lds_barrier();
-  cpx<T>* Y = fft_lds_pow2<T, true, CUBE_THREADS>(X, (X == A) ? B : A, P, 3 * nc, Lz, stw);
+  cpx<T>* Y = X;
+  if constexpr (IP) {
+    if (Lz == 128)
+      fft_inplace<T, 128, CUBE_THREADS, true, 3 * ZMUL_IP_CB>(X, 3 * nc, stw);
+    else
+      fft_inplace<T, 64, CUBE_THREADS, true, 3 * ZMUL_IP_CB>(X, 3 * nc, stw);
+  } else {
+    Y = fft_lds_pow2<T, true, CUBE_THREADS>(X, (X == A) ? B : A, P, 3 * nc, Lz, stw);
+  }
   for (int t = threadIdx.x; t < 3 * nz * nc; t += CUBE_THREADS) {
     const int cz = fdiv(t, inc);
     const int cc = t - cz * nc;
@@ -624,17 +644,27 @@ hipError_t launch_fft_axis(const void* in, void* out, int nplanes, int ncols, in
 template <typename T>
 hipError_t launch_zmul(void* buf, const T* kern, int Kx, int Ly, int nz, int CB, int mode, double sgn,
                        const FftPlan& P, const void* twz, hipStream_t st) {
-  // columns per block: at most CB, as many as the CU's LDS holds (at least
-  // one fits: the set-up bounds Lz)
-  while (CB > 1 && sizeof(cpx<T>) * ((size_t)P.L + 6 * (size_t)CB * P.L) > 160 * 1024) --CB;
-  const size_t lds = sizeof(cpx<T>) * ((size_t)P.L + 6 * (size_t)CB * P.L);
+  // 64 or 128 points: in place, ZMUL_IP_CB pencils per block in float32 and
+  // 3 in float64 (one LDS buffer).  Else ping-pong buffers with at most CB
+  // pencils, as many as the CU's LDS holds (at least one fits: the set-up
+  // bounds Lz).
+  const bool ip = P.L == 64 || P.L == 128;
+  if (ip) CB = sizeof(T) == 4 ? ZMUL_IP_CB : 3;
+  const int nbuf = ip ? 3 : 6;
+  while (CB > 1 && sizeof(cpx<T>) * ((size_t)P.L + nbuf * (size_t)CB * P.L) > 160 * 1024) --CB;
+  const size_t lds = sizeof(cpx<T>) * ((size_t)P.L + nbuf * (size_t)CB * P.L);
+  const void* fn = ip ? (const void*)k_zmul<T, true> : (const void*)k_zmul<T, false>;
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_zmul<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   dim3 grid((Ly * Kx + CB - 1) / CB);
-  hipLaunchKernelGGL(k_zmul<T>, grid, dim3(CUBE_THREADS), lds, st, (cpx<T>*)buf, kern, Kx, Ly, nz, CB, mode, (T)sgn, P,
-                     (const cpx<T>*)twz);
+  if (ip)
+    hipLaunchKernelGGL((k_zmul<T, true>), grid, dim3(CUBE_THREADS), lds, st, (cpx<T>*)buf, kern, Kx, Ly, nz, CB, mode,
+                       (T)sgn, P, (const cpx<T>*)twz);
+  else
+    hipLaunchKernelGGL((k_zmul<T, false>), grid, dim3(CUBE_THREADS), lds, st, (cpx<T>*)buf, kern, Kx, Ly, nz, CB,
+                       mode, (T)sgn, P, (const cpx<T>*)twz);
   return hipGetLastError();
 }
 

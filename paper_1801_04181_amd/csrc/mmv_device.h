@@ -407,6 +407,58 @@ __device__ __forceinline__ cpx<T>* fft_ct_from(cpx<T>* a, cpx<T>* b, int batch, 
   }
 }
 
+// In-place batched FFT of `batch` <= MAXBATCH contiguous transforms of
+// length L in LDS (the compiled plan's Stockham passes).  Each pass reads all
+// inputs of the thread's butterflies into registers, waits for the block,
+// and writes the outputs over the inputs: half the LDS of the ping-pong form
+// for two barriers per pass.  Unnormalised; entered by the whole block after
+// an lds_barrier(), ends with one.
+template <typename T, int L, int NT, bool INV, int MAXBATCH, int P = 0, int Ns = 1>
+__device__ __forceinline__ void fft_inplace(cpx<T>* a, int batch, const cpx<T>* __restrict__ tw) {
+  constexpr CPlan pl = make_cplan(L);
+  if constexpr (P < pl.np) {
+    constexpr int R = pl.r[P];
+    constexpr int nb = L / R;
+    constexpr int tws = L / (Ns * R);
+    constexpr int MB = (MAXBATCH * nb + NT - 1) / NT;  // butterflies per thread at most
+    const int total = batch * nb;
+    cpx<T> v[MB][R];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+      const int w = local_tid() + m * NT;
+      if (w < total) {
+        const int t = w / nb, j = w - t * nb;
+        const int k = j % Ns;
+        const cpx<T>* s = a + t * L + j;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[m][r] = s[r * nb];
+        if constexpr (Ns > 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            const cpx<T> wv = tw[r * k * tws];
+            v[m][r] = INV ? cmulc(v[m][r], wv) : cmul(v[m][r], wv);
+          }
+        }
+        dft<T, R, INV>(v[m]);
+      }
+    }
+    lds_barrier();
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+      const int w = local_tid() + m * NT;
+      if (w < total) {
+        const int t = w / nb, j = w - t * nb;
+        const int q = j / Ns, k = j - q * Ns;
+        cpx<T>* d = a + t * L + q * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) d[r * Ns] = v[m][r];
+      }
+    }
+    lds_barrier();
+    fft_inplace<T, L, NT, INV, MAXBATCH, P + 1, Ns * R>(a, batch, tw);
+  }
+}
+
 // Batched in-LDS FFT of `batch` transforms of length P.L, transform t at
 // a + t*stride.  Ping-pongs between a and b; returns the buffer holding the
 // result.  Unnormalised.  Must be entered by the whole block after the data
