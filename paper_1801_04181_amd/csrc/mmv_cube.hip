@@ -79,8 +79,9 @@ template <typename T, bool IP>
 __global__ void __launch_bounds__(CUBE_THREADS)
     k_zmul(cpx<T>* __restrict__ buf, const T* __restrict__ kern, int Kx, int Ly, int nz, int CB, int mode,
            T sgn, FftPlan P, const cpx<T>* __restrict__ twz) {
-  // block b: the CB pencils q = ky * Kx + kx from b * CB (fewer in the last
-  // block); pencil q of plane z sits at z * Ly * Kx + q
+  // logical block b (XCD-remapped): the CB pencils q = ky * Kx + kx from
+  // b * CB (fewer in the last block); pencil q of plane z sits at
+  // z * Ly * Kx + q
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int Lz = P.L;
   const int Kyh = Ly / 2 + 1, Kzh = Lz / 2 + 1;
