@@ -727,10 +727,9 @@ int step_cube(mmv_mesh* h, double dt, int nsteps) {
       if (s == 0 && h->d.sigma > 0 && (rc = eddy_update<T>(h, dt))) return rc;
       PROF(3);
       HIPCHK(launch_stage3<T>(h->cl, MODE_STAGE, s, MMV_TERM_ALL, dt, in, m0, out, (T*)h->acc, (const T*)h->hd,
-                              (const T*)h->he, nullptr, &h->rigid->flags, h->st));
+                              (const T*)h->he, nullptr, &h->rigid->flags, s == 3 ? h->rigid : nullptr, h->st));
       PROF(3);
     }
-    HIPCHK(launch_rigid_tick(h->rigid, dt, h->st));
   }
   return MMV_OK;
 }
@@ -742,7 +741,8 @@ int eval_cube(mmv_mesh* h, int mask, void* hout) {
     if (rc) return rc;
   }
   HIPCHK(launch_stage3<T>(h->cl, MODE_EVAL, 0, mask & (1 | 2 | 4 | 8 | 32), 0.0, (const T*)h->m0, (const T*)h->m0,
-                          nullptr, nullptr, (const T*)h->hd, (const T*)h->he, (T*)hout, &h->rigid->flags, h->st));
+                          nullptr, nullptr, (const T*)h->hd, (const T*)h->he, (T*)hout, &h->rigid->flags, nullptr,
+                          h->st));
   return MMV_OK;
 }
 

@@ -240,8 +240,15 @@ __device__ __forceinline__ void cell_ijk(size_t id, int nx, int ny, int& i, int&
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_stage3(CubeParams p, const T* __restrict__ ms, const T* m0, T* mnext, T* __restrict__ acc,
-             const T* __restrict__ hd, const T* __restrict__ he, T* __restrict__ hout, int* __restrict__ flags) {
+             const T* __restrict__ hd, const T* __restrict__ he, T* __restrict__ hout, int* __restrict__ flags,
+             RigidState* tick) {
   const size_t N = (size_t)p.nx * p.ny * p.nz;
+  // the step's clock (time, step count) advances with its last stage
+  if (tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
+    tick->t0 = tick->t0 + p.dt;
+    tick->ts = tick->t0;
+    tick->step += 1;
+  }
   for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < N; id += (size_t)gridDim.x * blockDim.x) {
   int i, j, k;
   cell_ijk(id, p.nx, p.ny, i, j, k);
@@ -559,14 +566,6 @@ __global__ void k_current(int nx, int ny, int nz, double dx, double dy, double d
 }
 
 // Time and step count of a mesh without a moving magnet.
-__global__ void k_rigid_tick(RigidState* R, double dt) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    R->t0 = R->t0 + dt;
-    R->ts = R->t0;
-    R->step += 1;
-  }
-}
-
 // ------------------------------------------------------------ kernel construction (float64)
 __global__ void k_kernel_real3(double* __restrict__ out, int Lx, int Ly, int Lz, int kind, int comp, double dx,
                                double dy, double dz, double rc, double scale) {
@@ -684,7 +683,8 @@ hipError_t launch_row_inv(const void* spec, T* out, int nrows, int R, int nx, in
 
 template <typename T>
 hipError_t launch_stage3(const CubeLaunch& c, int mode, int stage, int mask, double dt, const T* ms, const T* m0,
-                         T* mnext, T* acc, const T* hd, const T* he, T* hout, int* flags, hipStream_t st) {
+                         T* mnext, T* acc, const T* hd, const T* he, T* hout, int* flags, RigidState* tick,
+                         hipStream_t st) {
   CubeParams p;
   p.nx = c.nx;
   p.ny = c.ny;
@@ -705,7 +705,7 @@ hipError_t launch_stage3(const CubeLaunch& c, int mode, int stage, int mask, dou
   p.alpha = c.alpha;
   p.dt = dt;
   const size_t N = (size_t)c.nx * c.ny * c.nz;
-  hipLaunchKernelGGL(k_stage3<T>, grid1(N), dim3(256), 0, st, p, ms, m0, mnext, acc, hd, he, hout, flags);
+  hipLaunchKernelGGL(k_stage3<T>, grid1(N), dim3(256), 0, st, p, ms, m0, mnext, acc, hd, he, hout, flags, tick);
   return hipGetLastError();
 }
 
@@ -763,10 +763,6 @@ hipError_t launch_current(const CubeLaunch& c, const T* phi, const T* es, T* J, 
   return hipGetLastError();
 }
 
-hipError_t launch_rigid_tick(RigidState* r, double dt, hipStream_t st) {
-  hipLaunchKernelGGL(k_rigid_tick, dim3(1), dim3(64), 0, st, r, dt);
-  return hipGetLastError();
-}
 
 hipError_t launch_kernel_real3(double* out, int Lx, int Ly, int Lz, int kind, int comp, double dx, double dy,
                                double dz, double rc, double scale, hipStream_t st) {
@@ -790,7 +786,7 @@ hipError_t launch_pack3(const void* spec, T* out, int Kx, int Ly, int Lz, int im
   template hipError_t launch_row_inv<T>(const void*, T*, int, int, int, int, int, const FftPlan&, const void*,        \
                                         const void*, hipStream_t);                                                \
   template hipError_t launch_stage3<T>(const CubeLaunch&, int, int, int, double, const T*, const T*, T*, T*,    \
-                                       const T*, const T*, T*, int*, hipStream_t);                                \
+                                       const T*, const T*, T*, int*, RigidState*, hipStream_t);                   \
   template hipError_t launch_eddy_bdot<T>(size_t, const T*, const T*, T*, T*, double, double, const double*,     \
                                           double, int, hipStream_t);                                              \
   template hipError_t launch_sor_rhs<T>(const CubeLaunch&, const T*, T*, double*, double*, hipStream_t);         \

@@ -58,7 +58,8 @@ hipError_t launch_row_inv(const void* spec, T* out, int nrows, int R, int nx, in
                           const void* tw, const void* twp, hipStream_t st);
 template <typename T>
 hipError_t launch_stage3(const CubeLaunch& c, int mode, int stage, int mask, double dt, const T* ms, const T* m0,
-                         T* mnext, T* acc, const T* hd, const T* he, T* hout, int* flags, hipStream_t st);
+                         T* mnext, T* acc, const T* hd, const T* he, T* hout, int* flags, RigidState* tick,
+                         hipStream_t st);
 template <typename T>
 hipError_t launch_eddy_bdot(size_t N, const T* m, const T* hd, T* bprev, T* bdot, double mu0, double Ms,
                             const double* hext, double idt, int first, hipStream_t st);
@@ -69,7 +70,6 @@ hipError_t launch_sor(const CubeLaunch& c, T* phi, T* phi2, const T* r, double o
                       hipStream_t st);
 template <typename T>
 hipError_t launch_current(const CubeLaunch& c, const T* phi, const T* es, T* J, double sigma, hipStream_t st);
-hipError_t launch_rigid_tick(RigidState* r, double dt, hipStream_t st);
 hipError_t launch_kernel_real3(double* out, int Lx, int Ly, int Lz, int kind, int comp, double dx, double dy,
                                double dz, double rc, double scale, hipStream_t st);
 template <typename T>
