@@ -66,6 +66,15 @@ def test_cube_eddy_tiles_with_interior_halos(prec, sweeps):
 
 
 @pytest.mark.parametrize("prec", [32, 64])
+def test_cube_z64_in_place(prec):
+    """nz = 32: 64-point z pencils (the in-place z pass) and 64-point x rows
+    (nx = 32), eddy currents on."""
+    d = get_config("cube_eddy")["desc"].replace(nx=32, ny=9, nz=32, precision=prec, sor_sweeps=7)
+    out = run(d, 3)
+    assert out["m"] < (1e-6 if prec == 32 else 1e-12)
+
+
+@pytest.mark.parametrize("prec", [32, 64])
 def test_cube_without_eddy_ragged(prec):
     d = get_config("cube_eddy")["desc"].replace(nx=7, ny=13, nz=5, sigma=0.0, precision=prec, Ku=4e5,
                                               u=(0.2, 0.3, 0.9))
