@@ -26,8 +26,10 @@ Per time step, from the magnetisation at the start of the step:
 
 Pins (tests/test_oracle_eddy.py): the window sums equal brute-force sums;
 Faraday's law for a divergence-free dB/dt; the converged SOR equals a direct
-sparse solve of the same system; the discrete surface flux J . n vanishes;
-Lenz's law (the eddy field opposes a growing uniform dB/dt).
+sparse solve of the same system; a uniform E_sol is screened completely
+(phi = E0 . r, so J = 0 in every cell and no current leaves the surface;
+a flipped surface sign fails it); Lenz's law (the eddy field opposes a
+growing uniform dB/dt).
 """
 import numpy as np
 from .constants import MU0

@@ -7,7 +7,7 @@ Landau-Lifshitz form
 
 The sign of the precession term is taken so that damping lowers the
 energy: with it, dE/dt = -P_diss of Eq. (4) (pinned in
-tests/test_oracle_llg.py together with the macrospin closed form
+tests/test_oracle_dynamics.py together with the macrospin closed form
 tan(theta/2) = tan(theta0/2) exp(-alpha gamma H t / (1+alpha^2)),
 phi = phi0 + gamma H t / (1+alpha^2)).
 """

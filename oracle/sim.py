@@ -31,11 +31,14 @@ v_s); every stage evaluates H_eff at its own (m, x_s, t); m is
 renormalised after the step.  Drives: frozen, constant velocity, or
 m x'' = k (v_d t + x_a0 - x) - gamma_v m x' + F_x.
 
-Parity: direct-mode fields and force are pinned through their parts
-(convolution, spline, Newell, S) and by F_x = 0 for mirror-symmetric
-states, F_x ~ -dE_cross/dx_s and base/slider reaction; energy decay pins
-the integrator.  Potential-mode fields are pinned against the direct field
-(far-field agreement) and curl-free construction.
+Parity: at integer offsets the cross fields of both films and the force
+of Eq. 3 equal brute-force sums over physical cell centres, in direct mode
+(tensor) and potential mode (four-point differences of the brute-force
+potential), which pins the window layers, rows, offset signs and the
+stencil (tests/test_oracle_cross.py, with planted slips rejected); the
+spline's sub-cell sampling is pinned by its own tests; F_x = 0 for
+mirror-symmetric states, F_x ~ -dE_cross/dx_s and base/slider reaction;
+energy decay pins the integrator.
 """
 import math
 import numpy as np

@@ -130,3 +130,31 @@ def test_update_history_and_units():
     assert np.abs(s.eddy.H_eddy).max() == 0.0
     s.step(1e-14)
     assert np.abs(s.eddy.H_eddy).max() > 0.0
+
+
+def _uniform_field_current(d, shape, E0, rhs=eddy.neumann_rhs):
+    Esol = np.zeros((3,) + shape)
+    for a in range(3):
+        Esol[a] = E0[a]
+    r = rhs(d, Esol)
+    phi = eddy.sor(d, np.zeros(shape), r, 3000, eddy.default_omega(d))
+    return d.sigma * (Esol + eddy.irrotational(d, phi, Esol)), d.sigma * np.linalg.norm(E0)
+
+
+def test_uniform_field_is_screened_no_current_leaves():
+    # A uniform solenoidal field inside an insulated conductor is cancelled
+    # by the surface charge: phi = E0 . r solves Laplace's equation with
+    # d phi / dn = E0 . n on every face, so E_irrot = -E0 and J = 0 in every
+    # cell, in particular no current crosses the surface (Eq. 12).
+    shape = (5, 6, 7)
+    d = cube(shape[::-1], d=2e-9)
+    J, scale = _uniform_field_current(d, shape, np.array([3.0, -2.0, 1.5]))
+    assert np.abs(J).max() < 1e-9 * scale
+
+
+def test_uniform_field_pin_rejects_flipped_surface_sign():
+    shape = (5, 6, 7)
+    d = cube(shape[::-1], d=2e-9)
+    J, scale = _uniform_field_current(d, shape, np.array([3.0, -2.0, 1.5]),
+                                      rhs=lambda dd, E: -eddy.neumann_rhs(dd, E))
+    assert np.abs(J).max() > 0.5 * scale
