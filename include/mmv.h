@@ -22,8 +22,9 @@
  *     [3][nz][ny][nx] (component, z, y, x; x fastest) of the mesh's
  *     precision: float for precision 32, double for precision 64.
  *   - Work is enqueued on the stream given to init_mesh and is
- *     asynchronous, except stray_force and get_state, which synchronise
- *     that stream.  A handle is not thread-safe.
+ *     asynchronous, except stray_force, get_state, set_offset and
+ *     set_drive, which synchronise that stream.  A handle is not
+ *     thread-safe.
  *   - Units are SI, except offsets given in cells where stated.
  */
 #ifndef MMV_H
@@ -73,7 +74,9 @@ typedef struct {
   double Hext[3];       /* uniform applied field [A/m]                        */
   double sigma;         /* conductivity [S/m]; 0 = no eddy currents           */
   int precision;        /* 32 or 64                                           */
-  int cross_mode;       /* 0: direct field spline; 1: scalar potential        */
+  int cross_mode;       /* 0: direct field spline; 1: scalar potential (needs
+                           gap_cells >= 3: Sec. IV.D asks for films more than
+                           two cells apart; MMV_EINVAL otherwise)              */
   int halo;             /* spline window extension along x in cells (>= 2)    */
   double rc_cells;      /* Newell / point-dipole switch radius in cells (> 0) */
   int sor_sweeps;       /* eddy SOR sweeps per step (0: library default)      */
@@ -117,11 +120,14 @@ int get_m(mmv_handle h, int film, void* m_dev);
 
 /* Place the slider at x_s = x_cells * dx (Fig. 3: x_s = (s_int + x_p) dx
  * with s_int = floor(x_cells)).  MMV_ERANGE if |s_int| exceeds
- * max_travel_cells.  Enqueued on the stream.                            */
+ * max_travel_cells.  Reads the device-side slider state back and writes it
+ * again: synchronises the stream.                                       */
 int set_offset(mmv_handle h, double x_cells);
 
 /* Set the drive and the slider's position and velocity (x0, v0; for the
- * velocity drive v0 is replaced by v_d).                                */
+ * velocity drive v0 is replaced by v_d).  Synchronises the stream (as
+ * set_offset).  On a batch instance the batch's launch descriptors are
+ * rebuilt before its next batch_step.                                   */
 int set_drive(mmv_handle h, const mmv_drive* drv);
 
 /* Effective field of one film at the current state: the sum of the terms

@@ -119,7 +119,7 @@ struct mmv_mesh {
   void* twz = nullptr;
   void* specB = nullptr;
   void* kern_s = nullptr;  // potential kernel S (eddy currents)
-  void *hd = nullptr, *he = nullptr, *bprev = nullptr, *bdot = nullptr, *es = nullptr, *phi = nullptr, *phi2 = nullptr,
+  void *hd = nullptr, *he = nullptr, *dmstep = nullptr, *bdot = nullptr, *es = nullptr, *phi = nullptr, *phi2 = nullptr,
        *rr = nullptr;
   double* red = nullptr;   // reduction partials + mean
   CubeLaunch cl{};
@@ -183,6 +183,12 @@ int validate(const mmv_mesh_desc* d) {
   if (d->precision != 32 && d->precision != 64) return fail(MMV_EINVAL, "precision must be 32 or 64");
   if (d->cross_mode != 0 && d->cross_mode != 1) return fail(MMV_EINVAL, "cross_mode must be 0 or 1");
   if (d->cross_mode == 1 && d->n_films != 2) return fail(MMV_EINVAL, "cross_mode 1 needs two films");
+  // the four-point difference of the potential and the force stencil around
+  // it reach two cells towards the other film: the films must be more than
+  // two cells apart (Sec. IV.D)
+  if (d->cross_mode == 1 && d->gap_cells < 3)
+    return fail(MMV_EINVAL, "cross_mode 1 (scalar potential) needs gap_cells >= 3: its four-point difference "
+                            "would reach into the other film");
   if (!isfinite(d->sigma) || d->sigma < 0) return fail(MMV_EINVAL, "sigma must be finite and >= 0");
   if (d->sigma != 0.0 && !(d->n_films == 1 && d->nz > 1 && d->ny > 1 && d->nx > 1))
     return fail(MMV_EINVAL,
@@ -631,7 +637,7 @@ int init_cube(mmv_mesh* h) {
   if ((rc = dalloc(h, &h->spec1, 2 * sizeof(T) * 3 * (size_t)h->nz * h->ny * h->Kx))) return rc;
   if ((rc = dalloc(h, &h->specB, 2 * sizeof(T) * 3 * (size_t)h->nz * h->Ly * h->Kx))) return rc;
   if (d.sigma > 0) {
-    void** e3[] = {&h->bprev, &h->bdot, &h->es};
+    void** e3[] = {&h->dmstep, &h->bdot, &h->es};
     for (void** b : e3)
       if ((rc = dalloc(h, b, 3 * N * sizeof(T)))) return rc;
     if ((rc = dalloc(h, &h->phi, N * sizeof(T)))) return rc;
@@ -701,10 +707,14 @@ int eddy_update(mmv_mesh* h, double dt) {
   const size_t N = (size_t)h->nx * h->ny * h->nz;
   const double* part = h->red;
   double* mean = h->red + (N / 256 + 2);
-  HIPCHK(launch_eddy_bdot<T>(N, (const T*)h->m0, (const T*)h->hd, (T*)h->bprev, (T*)h->bdot, MU0, h->d.Ms,
-                             h->d.Hext, 1.0 / dt, h->eddy_first ? 1 : 0, h->st));
+  // dmstep holds the last step's change of m (written by its last stage):
+  // dB/dt = mu0 (H_d(dm) + Ms dm) / dt
+  int rc;
+  if (!h->eddy_first && (rc = conv3<T>(h, h->dmstep, h->bdot, (const T*)h->kern, 0, 1.0))) return rc;
+  HIPCHK(launch_eddy_bdot<T>(N, (const T*)h->dmstep, (const T*)h->bdot, (T*)h->bdot, MU0, h->d.Ms, 1.0 / dt,
+                             h->eddy_first ? 1 : 0, h->st));
   h->eddy_first = false;
-  int rc = conv3<T>(h, h->bdot, h->es, (const T*)h->kern_s, 1, +1.0);
+  rc = conv3<T>(h, h->bdot, h->es, (const T*)h->kern_s, 1, +1.0);
   if (rc) return rc;
   HIPCHK(launch_sor_rhs<T>(h->cl, (const T*)h->es, (T*)h->rr, h->red, mean, h->st));
   HIPCHK(launch_sor<T>(h->cl, (T*)h->phi, (T*)h->phi2, (const T*)h->rr, h->sor_omega, h->sor_sweeps, h->red, mean, h->st));
@@ -727,7 +737,8 @@ int step_cube(mmv_mesh* h, double dt, int nsteps) {
       if (s == 0 && h->d.sigma > 0 && (rc = eddy_update<T>(h, dt))) return rc;
       PROF(3);
       HIPCHK(launch_stage3<T>(h->cl, MODE_STAGE, s, MMV_TERM_ALL, dt, in, m0, out, (T*)h->acc, (const T*)h->hd,
-                              (const T*)h->he, nullptr, &h->rigid->flags, s == 3 ? h->rigid : nullptr, h->st));
+                              (const T*)h->he, nullptr, &h->rigid->flags, s == 3 ? h->rigid : nullptr,
+                              (s == 3 && h->d.sigma > 0) ? (T*)h->dmstep : nullptr, h->st));
       PROF(3);
     }
   }
@@ -742,7 +753,7 @@ int eval_cube(mmv_mesh* h, int mask, void* hout) {
   }
   HIPCHK(launch_stage3<T>(h->cl, MODE_EVAL, 0, mask & (1 | 2 | 4 | 8 | 32), 0.0, (const T*)h->m0, (const T*)h->m0,
                           nullptr, nullptr, (const T*)h->hd, (const T*)h->he, (T*)hout, &h->rigid->flags, nullptr,
-                          h->st));
+                          nullptr, h->st));
   return MMV_OK;
 }
 
@@ -948,7 +959,7 @@ struct mmv_batch {
   int *s_fwd = nullptr, *s_col = nullptr, *s_stage = nullptr;
   int nblk_fwd = 0, nblk_col = 0, nblk_stage = 0;
   size_t lds_fwd = 0, lds_col = 0, lds_stage = 0;
-  std::vector<int> drive_sig;  // drive modes the stage descriptors were built for
+  std::vector<DriveP> drive_sig;  // drives the stage and tick descriptors were built for
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   double g_dt = 0.0;
@@ -986,12 +997,12 @@ int batch_build(mmv_batch* b) {
   std::vector<ColDesc> col(n);
   std::vector<int> sf(n + 1, 0), sc(n + 1, 0), ss(n + 1, 0);
   b->lds_fwd = b->lds_col = b->lds_stage = 0;
-  b->drive_sig.assign(n, 0);
+  b->drive_sig.assign(n, DriveP{});
   b->fuse = true;
   for (int i = 0; i < n; ++i) b->fuse = b->fuse && b->inst[i]->fuse_fwd;
   for (int i = 0; i < n; ++i) {
     mmv_mesh* h = b->inst[i];
-    b->drive_sig[i] = h->drive.mode;
+    b->drive_sig[i] = h->drive;
     T* m0 = (T*)h->m0;
     T* b1 = (T*)h->mb[0];
     T* b2 = (T*)h->mb[1];
@@ -1107,10 +1118,17 @@ int batch_launch_steps(mmv_batch* b, hipStream_t st, double dt, int nsteps) {
 
 constexpr int GRAPH_STEPS = 8;
 
+bool same_drive(const DriveP& a, const DriveP& c) {
+  return a.mode == c.mode && a.v_d == c.v_d && a.k == c.k && a.mass == c.mass && a.gamma_v == c.gamma_v &&
+         a.xa0 == c.xa0;
+}
+
 template <typename T>
 int batch_step_typed(mmv_batch* b, double dt, int nsteps) {
+  // the descriptors carry each instance's drive by value: any change made by
+  // set_drive since they were built rebuilds them (and drops the graph)
   for (size_t i = 0; i < b->inst.size(); ++i)
-    if (b->inst[i]->drive.mode != b->drive_sig[i]) {
+    if (!same_drive(b->inst[i]->drive, b->drive_sig[i])) {
       int rc = batch_build<T>(b);
       if (rc) return rc;
       break;

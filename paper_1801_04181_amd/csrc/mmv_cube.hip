@@ -241,7 +241,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
     k_stage3(CubeParams p, const T* __restrict__ ms, const T* m0, T* mnext, T* __restrict__ acc,
              const T* __restrict__ hd, const T* __restrict__ he, T* __restrict__ hout, int* __restrict__ flags,
-             RigidState* tick) {
+             RigidState* tick, T* __restrict__ dmstep) {
   const size_t N = (size_t)p.nx * p.ny * p.nz;
   // the step's clock (time, step count) advances with its last stage
   if (tick != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -322,29 +322,39 @@ __global__ void __launch_bounds__(256)
     mnext[2 * N + id] = oz + c * kz;
   } else {
     const T c = h / T(6);
-    const T nx_ = ox + c * (acc[id] + kx), ny_ = oy + c * (acc[N + id] + ky), nz_ = oz + c * (acc[2 * N + id] + kz);
+    const T ix = c * (acc[id] + kx), iy = c * (acc[N + id] + ky), iz = c * (acc[2 * N + id] + kz);
+    const T nx_ = ox + ix, ny_ = oy + iy, nz_ = oz + iz;
     const T nrm = sqrt(nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
     if (!(nrm > T(0)) || !isfinite(nrm)) atomicOr(flags, (int)FLAG_NUMERIC);
     mnext[id] = nx_ / nrm;
     mnext[N + id] = ny_ / nrm;
     mnext[2 * N + id] = nz_ / nrm;
+    if (dmstep != nullptr) {
+      // the step's change of m, normalise(m + inc) - m for a unit m, formed
+      // from the increment (no difference of two rounded states):
+      // q = |m + inc|^2 - 1 = 2 m.inc + |inc|^2, 1/|m + inc| - 1 = -q / (s (1 + s))
+      const T q = T(2) * (ox * ix + oy * iy + oz * iz) + (ix * ix + iy * iy + iz * iz);
+      const T sn = sqrt(T(1) + q);
+      const T rm1 = -q / (sn * (T(1) + sn));
+      const T r = T(1) + rm1;
+      dmstep[id] = ix * r + ox * rm1;
+      dmstep[N + id] = iy * r + oy * rm1;
+      dmstep[2 * N + id] = iz * r + oz * rm1;
+    }
   }
   }
 }
 
-// B = mu0 (H_d + H_ext + Ms m); dB/dt = (B - B_prev) / dt (zero on the first
-// update); B_prev = B.
+// dB/dt over the last step.  B = mu0 (H_d + H_ext + Ms m) with H_d linear in
+// m and H_ext constant, so B_n - B_{n-1} = mu0 (H_d(dm) + Ms dm) for the
+// step's change dm: bdot = mu0 (hdm + Ms dm) / dt (zero on the first update).
+// bdot may alias hdm.
 template <typename T>
-__global__ void k_bdot(size_t N, const T* __restrict__ m, const T* __restrict__ hd, T* __restrict__ bprev,
-                       T* __restrict__ bdot, double mu0, double Ms, double h0, double h1, double h2, double idt,
-                       int first) {
-  const double he[3] = {h0, h1, h2};
+__global__ void k_bdot(size_t N, const T* dm, const T* hdm, T* bdot, double mu0, double Ms, double idt, int first) {
   for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < N; id += (size_t)gridDim.x * blockDim.x)
     for (int a = 0; a < 3; ++a) {
       const size_t q = a * N + id;
-      const T B = (T)(mu0 * ((double)hd[q] + he[a] + Ms * (double)m[q]));
-      bdot[q] = first ? T(0) : (B - bprev[q]) * (T)idt;
-      bprev[q] = B;
+      bdot[q] = first ? T(0) : (T)(mu0 * ((double)hdm[q] + Ms * (double)dm[q]) * idt);
     }
 }
 
@@ -684,7 +694,7 @@ hipError_t launch_row_inv(const void* spec, T* out, int nrows, int R, int nx, in
 template <typename T>
 hipError_t launch_stage3(const CubeLaunch& c, int mode, int stage, int mask, double dt, const T* ms, const T* m0,
                          T* mnext, T* acc, const T* hd, const T* he, T* hout, int* flags, RigidState* tick,
-                         hipStream_t st) {
+                         T* dmstep, hipStream_t st) {
   CubeParams p;
   p.nx = c.nx;
   p.ny = c.ny;
@@ -705,15 +715,15 @@ hipError_t launch_stage3(const CubeLaunch& c, int mode, int stage, int mask, dou
   p.alpha = c.alpha;
   p.dt = dt;
   const size_t N = (size_t)c.nx * c.ny * c.nz;
-  hipLaunchKernelGGL(k_stage3<T>, grid1(N), dim3(256), 0, st, p, ms, m0, mnext, acc, hd, he, hout, flags, tick);
+  hipLaunchKernelGGL(k_stage3<T>, grid1(N), dim3(256), 0, st, p, ms, m0, mnext, acc, hd, he, hout, flags, tick,
+                     dmstep);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_eddy_bdot(size_t N, const T* m, const T* hd, T* bprev, T* bdot, double mu0, double Ms,
-                            const double* hext, double idt, int first, hipStream_t st) {
-  hipLaunchKernelGGL(k_bdot<T>, grid1(N), dim3(256), 0, st, N, m, hd, bprev, bdot, mu0, Ms, hext[0], hext[1],
-                     hext[2], idt, first);
+hipError_t launch_eddy_bdot(size_t N, const T* dm, const T* hdm, T* bdot, double mu0, double Ms, double idt,
+                            int first, hipStream_t st) {
+  hipLaunchKernelGGL(k_bdot<T>, grid1(N), dim3(256), 0, st, N, dm, hdm, bdot, mu0, Ms, idt, first);
   return hipGetLastError();
 }
 
@@ -786,9 +796,9 @@ hipError_t launch_pack3(const void* spec, T* out, int Kx, int Ly, int Lz, int im
   template hipError_t launch_row_inv<T>(const void*, T*, int, int, int, int, int, const FftPlan&, const void*,        \
                                         const void*, hipStream_t);                                                \
   template hipError_t launch_stage3<T>(const CubeLaunch&, int, int, int, double, const T*, const T*, T*, T*,    \
-                                       const T*, const T*, T*, int*, RigidState*, hipStream_t);                   \
-  template hipError_t launch_eddy_bdot<T>(size_t, const T*, const T*, T*, T*, double, double, const double*,     \
-                                          double, int, hipStream_t);                                              \
+                                       const T*, const T*, T*, int*, RigidState*, T*, hipStream_t);               \
+  template hipError_t launch_eddy_bdot<T>(size_t, const T*, const T*, T*, double, double, double, int,           \
+                                          hipStream_t);                                                           \
   template hipError_t launch_sor_rhs<T>(const CubeLaunch&, const T*, T*, double*, double*, hipStream_t);         \
   template hipError_t launch_sor<T>(const CubeLaunch&, T*, T*, const T*, double, int, double*, double*,          \
                                      hipStream_t);                                                             \

@@ -59,10 +59,10 @@ hipError_t launch_row_inv(const void* spec, T* out, int nrows, int R, int nx, in
 template <typename T>
 hipError_t launch_stage3(const CubeLaunch& c, int mode, int stage, int mask, double dt, const T* ms, const T* m0,
                          T* mnext, T* acc, const T* hd, const T* he, T* hout, int* flags, RigidState* tick,
-                         hipStream_t st);
+                         T* dmstep, hipStream_t st);
 template <typename T>
-hipError_t launch_eddy_bdot(size_t N, const T* m, const T* hd, T* bprev, T* bdot, double mu0, double Ms,
-                            const double* hext, double idt, int first, hipStream_t st);
+hipError_t launch_eddy_bdot(size_t N, const T* dm, const T* hdm, T* bdot, double mu0, double Ms, double idt,
+                            int first, hipStream_t st);
 template <typename T>
 hipError_t launch_sor_rhs(const CubeLaunch& c, const T* es, T* r, double* part, double* mean, hipStream_t st);
 template <typename T>

@@ -55,6 +55,17 @@ def test_init_rejects_bad_descriptors(field, value, msg):
     assert msg in str(e.value)
 
 
+@pytest.mark.parametrize("gap", [0, 1, 2])
+def test_potential_mode_refused_closer_than_three_cells(gap):
+    # Sec. IV.D: the films must be more than two cells apart for the
+    # potential's four-point difference (and the force stencil around it)
+    d = get_config("tiny_potential")["desc"].replace(gap_cells=gap)
+    with pytest.raises(mmv.MMVError) as e:
+        mmv.init_mesh(d)
+    assert e.value.code == -1
+    assert "gap_cells >= 3" in str(e.value)
+
+
 def test_null_handle_and_pointers():
     lib = mmv.load()
     assert lib.destroy_mesh(None) == 0

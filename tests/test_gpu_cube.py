@@ -7,12 +7,12 @@ from gpu_common import TERMS, rel
 
 pytestmark = pytest.mark.gpu
 
-# float32: the eddy field is driven by dB/dt = (B_n - B_{n-1})/dt, a difference
-# of ~1e-4 of |B| per step, so the float32 state rounding (~6e-8 per step)
-# gives ~1e-3 per cell and ~1e-4 after the Biot-Savart average (Sec. IV.D of
-# the paper notes that weak eddy fields are lost to floating-point precision).
+# The eddy field is driven by dB/dt over the last step, a change of ~1e-4 of
+# |B|.  The float32 path forms it from the step's own increment of m
+# (mu0 (H_d(dm) + Ms dm) / dt, H_d linear), not as the difference of two
+# rounded states, so it meets the same bar as the other terms.
 TOL_TERM = {32: 1e-5, 64: 1e-10}
-TOL_EDDY = {32: 1e-3, 64: 1e-10}
+TOL_EDDY = {32: 1e-5, 64: 1e-10}
 
 
 def run(desc, nsteps, dt=5e-14, check_initial=True):
@@ -83,9 +83,10 @@ def test_cube_without_eddy_ragged(prec):
 
 
 def test_cube_full_size_fp32():
-    """The 64^3 conducting cube at its real size: every field term and 3 steps."""
-    d = get_config("cube_eddy")["desc"].replace(sor_sweeps=10)
-    out = run(d, 3)
+    """The 64^3 conducting cube at its real size with the library's default
+    40 SOR sweeps per step: every field term, 4 steps, the eddy field."""
+    d = get_config("cube_eddy")["desc"].replace(sor_sweeps=0)
+    out = run(d, 4)
     assert out["m"] < 1e-6
 
 
