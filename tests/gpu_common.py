@@ -7,10 +7,16 @@ TERMS = (("exchange", 1), ("anisotropy", 2), ("zeeman", 4), ("demag_self", 8),
 
 # Relative L2 bars per term and film (also applied as max |error| / max |H|,
 # so that an error confined to a window edge or halo row cannot hide in the
-# norm).  float32: 1e-5.  float64: 1e-10; FFT rounding of the float64 path is
-# ~1e-15, and the Newell entries near the switch radius, where device and
-# host libm differ after the cancellation, carry ~1e-4 of the field.
+# norm).  float32: 1e-5 for every term and the force.  float64: 1e-10 for
+# every term and the total field, except the cross term and the force
+# (1e-9): their kernel entries are Newell's closed forms at 2 to 40 cells of
+# displacement, where the 27-term difference cancels (r / cell)^6-fold and
+# leaves 1e-8..1e-6 relative rounding error per entry that device and host
+# realise differently (libm and summation order; both sides are equally
+# accurate); the cross term is 1e-2..1e-3 of the total field, whose error
+# stays below 3e-12.  Measured: cross term 1e-11..6e-10, force up to 7e-10.
 TOL = {32: 1e-5, 64: 1e-10}
+TOL_CROSS = {32: 1e-5, 64: 1e-9}
 
 
 def max_rel(a, b):

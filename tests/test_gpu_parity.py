@@ -5,7 +5,7 @@ import pytest
 
 from workloads import Desc, Drive, get_config, initial_state
 from workloads.states import random_unit, domain_state
-from gpu_common import TERMS, TOL, rel, max_rel, oracle_system
+from gpu_common import TERMS, TOL, TOL_CROSS, rel, max_rel, oracle_system
 
 pytestmark = pytest.mark.gpu
 
@@ -17,6 +17,7 @@ def _mmv():
 
 def check_fields(desc, drive, m, x_cells=None, tol=None):
     mmv = _mmv()
+    tol_cross = tol or TOL_CROSS[desc.precision]
     tol = tol or TOL[desc.precision]
     print(f"fields: n_films={desc.n_films} {desc.nx}x{desc.ny} p{desc.precision} x={x_cells}", flush=True)
     mesh = mmv.Mesh(desc, drive, m)
@@ -32,23 +33,19 @@ def check_fields(desc, drive, m, x_cells=None, tol=None):
             if not np.any(ref):
                 assert np.abs(got).max() == 0.0, (f, name)
                 continue
-            e = rel(got, ref)
-            em = max_rel(got, ref)
-            worst[(f, name)] = e
-            worst[(f, name, "max")] = em
-            assert e <= tol, (f, name, e)
-            assert em <= tol, (f, name, "max", em)
+            worst[(f, name)] = rel(got, ref)
+            worst[(f, name, "max")] = max_rel(got, ref)
         tot = sum(terms[f][k] for k, _ in TERMS)
-        e = rel(mesh.eval_heff(f, 63).cpu().numpy(), tot)
-        worst[(f, "total")] = e
-        assert e <= tol, (f, "total", e)
-    print("  worst rel err", max(worst.values()), flush=True)
+        worst[(f, "total")] = rel(mesh.eval_heff(f, 63).cpu().numpy(), tot)
     if desc.n_films == 2:
         Fg = np.array(mesh.force())
-        eF = np.linalg.norm(Fg - F) / np.linalg.norm(F)
-        print(f"  force gpu {Fg} oracle {F} rel {eF:.2e}", flush=True)
-        assert eF <= tol
+        worst["force"] = np.linalg.norm(Fg - F) / np.linalg.norm(F)
+        print(f"  force gpu {Fg} oracle {F}", flush=True)
     mesh.close()
+    print("  errors", {k: f"{v:.2e}" for k, v in worst.items()}, flush=True)
+    for k, e in worst.items():
+        cross = k == "force" or "demag_cross" in k
+        assert e <= (tol_cross if cross else tol), (k, e)
     return worst
 
 
