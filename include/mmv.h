@@ -149,6 +149,22 @@ int llg_step(mmv_handle h, double dt, int nsteps);
  * Synchronises the stream.  MMV_ESTATE for a single-film mesh.          */
 int stray_force(mmv_handle h, double F_out[3]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the force
+ * of stray_force with no allocation and no synchronisation.  Same kernels
+ * and fixed summation order as stray_force; the three float64 components
+ * [N] are written to the caller's device buffer F_dev (3 doubles),
+ * asynchronously on the handle's stream.  The float64 partial sums of the
+ * row blocks and the arrival counter live in a static device array of
+ * 64 KiB per GPU, held until the process ends (the counter is cleared by a
+ * fill kernel at each call): the ny + 2 force rows need 24 bytes each, at
+ * most 65280 bytes (ny <= 2718, which covers every two-film mesh init_mesh
+ * accepts), MMV_EINVAL otherwise.  All calls on one GPU share that array:
+ * calls that overlap on one GPU (other streams, handles or threads) race
+ * and must be ordered by the caller.  Pending MMV_ERANGE / MMV_ENUMERIC
+ * flags are left for get_state.  MMV_ESTATE for a single-film mesh.     */
+int stray_force_noalloc(mmv_handle h, double* F_dev);
+
 /* Time [s], slider position [m] and velocity [m/s] and step count.
  * Synchronises the stream; reports a pending MMV_ERANGE / MMV_ENUMERIC. */
 int get_state(mmv_handle h, double* t, double* x_s, double* v_s, long* step);

@@ -11,7 +11,7 @@ import os
 
 __all__ = ["MMVError", "lib_path", "load", "MeshDesc", "DriveDesc", "init_mesh",
            "set_m", "get_m", "set_offset", "set_drive", "eval_heff", "llg_step",
-           "stray_force", "get_state", "get_fft_lengths", "destroy_mesh",
+           "stray_force", "stray_force_noalloc", "get_state", "get_fft_lengths", "destroy_mesh",
            "profile_begin", "profile_end", "profile_repeat", "init_batch", "batch_instance", "batch_step",
            "batch_tuning", "set_tune_cache", "destroy_batch", "Batch", "SurDesc", "sur_create", "sur_param_count",
            "sur_param_offsets", "sur_set_params", "sur_get_params", "sur_forward", "sur_gradient",
@@ -26,7 +26,7 @@ TERM = dict(exchange=1, anisotropy=2, zeeman=4, demag_self=8, demag_cross=16,
 ERRORS = {-1: "MMV_EINVAL", -2: "MMV_ENOMEM", -3: "MMV_EHIP", -4: "MMV_ERANGE",
           -5: "MMV_ENUMERIC", -6: "MMV_ESTATE"}
 EXPORTS = ("init_mesh", "set_m", "get_m", "set_offset", "set_drive", "eval_heff",
-           "llg_step", "stray_force", "get_state", "profile_begin", "profile_end",
+           "llg_step", "stray_force", "stray_force_noalloc", "get_state", "profile_begin", "profile_end",
            "get_fft_lengths", "profile_repeat", "init_batch", "batch_instance", "batch_step", "batch_tuning",
            "set_tune_cache", "destroy_batch", "destroy_mesh", "sur_create", "sur_param_count", "sur_param_offsets",
            "sur_set_params", "sur_get_params", "sur_forward", "sur_gradient", "sur_train_step",
@@ -88,6 +88,7 @@ def load():
         lib.eval_heff.argtypes = [vp, i, i, vp]
         lib.llg_step.argtypes = [vp, d, i]
         lib.stray_force.argtypes = [vp, pd]
+        lib.stray_force_noalloc.argtypes = [vp, vp]
         lib.get_state.argtypes = [vp, pd, pd, pd, ctypes.POINTER(ctypes.c_long)]
         lib.get_fft_lengths.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
         lib.destroy_mesh.argtypes = [vp]
@@ -201,6 +202,13 @@ def stray_force(h):
     F = (ctypes.c_double * 3)()
     _check(load().stray_force(h, F))
     return [F[0], F[1], F[2]]
+
+
+def stray_force_noalloc(h, F_dev):
+    """Force [N] into the float64 device tensor F_dev (3 elements), no
+    allocation, no synchronisation."""
+    _check(load().stray_force_noalloc(h, _ptr(F_dev)))
+    return F_dev
 
 
 def get_state(h):

@@ -10,6 +10,7 @@
 #include <vector>
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include "mmv.h"
 #include "mmv_internal.h"
 #include "mmv_kernels.h"
@@ -903,8 +904,12 @@ int eval_typed(mmv_mesh* h, int film, int mask, void* hout) {
   return MMV_OK;
 }
 
+// Eq. 3 force at the current state: the force rows' field pass, then one
+// row-kernel launch whose blocks write float64 partials [ny + 2][3] and whose
+// last block (arrival counter) sums them in a fixed order into fout (NULL:
+// the slider state's F).
 template <typename T>
-int force_typed(mmv_mesh* h) {
+int force_typed(mmv_mesh* h, double* partial, unsigned* counter, double* fout) {
   int rc = run_fields<T>(h, h->m0, h->tab_force);
   if (rc) return rc;
   RowParams rp = h->rp_force;
@@ -914,8 +919,9 @@ int force_typed(mmv_mesh* h) {
   rp.full_force = 1;
   rp.ntask = h->ny + 2;
   rp.drive = h->drive;
+  rp.fout = fout;
   HIPCHK(launch_row_stage<T>(rp, h->spec2, (const T*)h->m0, (const T*)h->m0, nullptr, nullptr, nullptr, h->twx,
-                             h->twp, h->rigid, h->partial, h->counter, h->st));
+                             h->twp, h->rigid, partial, counter, h->st));
   return MMV_OK;
 }
 
@@ -939,6 +945,46 @@ int report_flags(mmv_mesh* h, RigidState& r) {
   if (rc) return rc;
   if (f & FLAG_NUMERIC) return fail(MMV_ENUMERIC, "non-finite magnetisation or slider state");
   return fail(MMV_ERANGE, "slider left the window the FFT lengths were sized for (max_travel_cells)");
+}
+
+// Static scratch of stray_force_noalloc (the entry point for callers that
+// cannot allocate): the float64 force partials of the row blocks followed by
+// the launch's arrival counter.  One copy per device, held until the process
+// ends; its device address is resolved once per device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = 64 * 1024;
+constexpr size_t NOALLOC_COUNTER_BYTES = 256;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+__global__ void k_fill_u32(unsigned* p, int n, unsigned v) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+size_t noalloc_partial_bytes(int ntask) { return ((size_t)ntask * 3 * sizeof(double) + 255) & ~size_t(255); }
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch_ptr;
+
+// Device address of this device's scratch (host code must not use the
+// array's name: on the host it only stands in for the symbol).
+int noalloc_scratch(unsigned char** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(MMV_EHIP, "hipGetSymbolAddress returned NULL for the static scratch");
+    it = g_scratch_ptr.emplace(dev, static_cast<unsigned char*>(p)).first;
+  }
+  *out = it->second;
+  return MMV_OK;
 }
 
 }  // namespace
@@ -1389,6 +1435,10 @@ int init_mesh(const mmv_mesh_desc* d, void* hip_stream, mmv_handle* out) {
     return fail(MMV_EINVAL, "FFT length has too many factors");
   }
   rc = d->precision == 64 ? init_typed<double>(h) : init_typed<float>(h);
+  // two films: resolve this device's static scratch of stray_force_noalloc
+  // now, so that its calls (possibly under graph capture) only look it up
+  unsigned char* scratch_dev = nullptr;
+  if (!rc && d->n_films == 2) rc = noalloc_scratch(&scratch_dev);
   if (rc) {
     free_all(h);
     delete h;
@@ -1709,12 +1759,32 @@ int stray_force(mmv_handle h, double F_out[3]) {
   if (rc) return rc;
   if (!F_out) return fail(MMV_EINVAL, "F_out is NULL");
   if (h->nfilm != 2) return fail(MMV_ESTATE, "stray_force needs two films");
-  rc = h->esz == 8 ? force_typed<double>(h) : force_typed<float>(h);
+  rc = h->esz == 8 ? force_typed<double>(h, h->partial, h->counter, nullptr)
+                    : force_typed<float>(h, h->partial, h->counter, nullptr);
   if (rc) return rc;
   RigidState r;
   if ((rc = read_rigid(h, r))) return rc;
   for (int a = 0; a < 3; ++a) F_out[a] = r.F[a];
   return report_flags(h, r);
+}
+
+int stray_force_noalloc(mmv_handle h, double* F_dev) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!F_dev) return fail(MMV_EINVAL, "F_dev is NULL");
+  if (h->nfilm != 2) return fail(MMV_ESTATE, "stray_force_noalloc needs two films");
+  const size_t part_bytes = noalloc_partial_bytes(h->ny + 2);
+  if (part_bytes + NOALLOC_COUNTER_BYTES > NOALLOC_SCRATCH_BYTES)
+    return fail(MMV_EINVAL, "stray_force_noalloc: ny + 2 force rows need " + std::to_string(part_bytes) +
+                                " bytes of partials, more than the static scratch of " +
+                                std::to_string(NOALLOC_SCRATCH_BYTES - NOALLOC_COUNTER_BYTES) + " bytes");
+  unsigned char* base = nullptr;
+  if ((rc = noalloc_scratch(&base))) return rc;
+  double* partial = reinterpret_cast<double*>(base);
+  unsigned* counter = reinterpret_cast<unsigned*>(base + part_bytes);
+  // the arrival counter must start at zero (a fill kernel, not a memset node)
+  HIPCHK(launch_fill_u32(counter, (int)(NOALLOC_COUNTER_BYTES / sizeof(unsigned)), 0u, h->st));
+  return h->esz == 8 ? force_typed<double>(h, partial, counter, F_dev) : force_typed<float>(h, partial, counter, F_dev);
 }
 
 int get_state(mmv_handle h, double* t, double* x_s, double* v_s, long* step) {

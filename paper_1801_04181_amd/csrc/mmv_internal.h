@@ -116,6 +116,8 @@ struct RowParams {
   // components of its new magnetisation row into this spectrum array (the
   // x-pass input of the next stage), [film][comp][y][Kx]
   void* spec1_out;
+  // MODE_FORCE: when set, the force [N] goes here instead of rigid->F
+  double* fout;
 };
 
 // Per-instance descriptors of the batched launches (device memory).

@@ -1130,7 +1130,8 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     }
     const double F0 = p.force_scale * tot[0];
     if (p.mode == MODE_FORCE) {
-      for (int a = 0; a < 3; ++a) rigid->F[a] = p.force_scale * tot[a];
+      double* Fo = p.fout != nullptr ? p.fout : rigid->F;
+      for (int a = 0; a < 3; ++a) Fo[a] = p.force_scale * tot[a];
     } else {
       rigid_stage(rigid, p.drive, stage, F0, dt, p.dx, p.travel);
     }
