@@ -514,6 +514,9 @@ int init_typed(mmv_mesh* h) {
   if (!nbr) return fail(MMV_EINVAL, "nx too large for the row kernel's LDS");
   h->rp_hot.nbr = h->rp_force.nbr = nbr;
   h->fuse_fwd = nbr >= 3;
+  // compiled lengths: the row transforms run in place (the batched kernel
+  // does the same, so batch and single-mesh launches compute alike)
+  h->rp_hot.inplace = h->rp_force.inplace = row_inplace_length(h->N2x) ? 1 : 0;
   if (sizeof(T) * 2 * (4 * (size_t)h->N2x + 1) > LDS_PER_CU) return fail(MMV_EINVAL, "nx too large");
   // output groups per column of the y pass.  Each group recomputes the
   // column's forward transforms (an L2 hit); more groups give shorter blocks,
@@ -991,6 +994,14 @@ int noalloc_scratch(unsigned char** out) {
 
 
 // ---------------------------------------------------------------- batches
+// One launch of a batched pass over a class of instances: their descriptors
+// at [off, off + n) of the pass's array, block starts at soff.
+struct BatchLaunch {
+  int off = 0, n = 0, soff = 0, nblk = 0;
+  size_t lds = 0;
+  bool inplace = false;
+};
+
 struct mmv_batch {
   std::vector<mmv_mesh*> inst;
   hipStream_t st = nullptr;
@@ -998,13 +1009,18 @@ struct mmv_batch {
   int esz = 4;
   int flags = 0;
   std::vector<void*> allocs;
+  // Descriptor arrays (device), instances ordered by launch class, and the
+  // classes' block-start tables (class c's table at its soff, n + 1 entries).
   RowFwdDesc* d_fwd[4] = {};
   ColDesc* d_col = nullptr;
+  ColDesc* d_col_all = nullptr;  // every instance in batch order (closing slider tick)
   RowStageDesc* d_stage[4] = {};
   bool fuse = false;  // every instance x-transforms its new rows in the row kernel
   int *s_fwd = nullptr, *s_col = nullptr, *s_stage = nullptr;
-  int nblk_fwd = 0, nblk_col = 0, nblk_stage = 0;
-  size_t lds_fwd = 0, lds_col = 0, lds_stage = 0;
+  // one launch per class of instances with the same launch shape (dynamic
+  // LDS, transform variant): small meshes are not held to the LDS of the
+  // largest, so more of their blocks share a CU
+  std::vector<BatchLaunch> l_fwd, l_col, l_stage;
   std::vector<DriveP> drive_sig;  // drives the stage and tick descriptors were built for
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -1034,25 +1050,65 @@ RowParams stage_params(mmv_mesh* h, bool fuse) {
   return rp;
 }
 
-// (Re)build the per-instance descriptors and block tables.
+// Rows per transform batch of the batched row kernel for one instance:
+// a direct-mode stage task needs at most 8 inverse transforms (7 except the
+// slider's first and last rows).  Pick the batch size that lets the most
+// blocks share a CU's LDS, then the largest at that occupancy (at least 3:
+// the fused forward transform of the new row's three components).
+template <typename T>
+int batch_rows_per_transform(const RowParams& rp, size_t limit) {
+  if (rp.pot) return rp.nbr;
+  int best = 0, best_occ = 0;
+  for (int nb = std::min(rp.nbr, 8); nb >= 3; --nb) {
+    RowParams q = rp;
+    q.nbr = nb;
+    const size_t lds = row_lds_bytes<T>(q) + ROW_STATIC_LDS;
+    if (lds > limit) continue;
+    const int occ = std::min(4, (int)((160 * 1024) / (((lds + 511) / 512) * 512)));
+    if (occ > best_occ) {
+      best_occ = occ;
+      best = nb;
+    }
+  }
+  return best ? best : rp.nbr;
+}
+
+// Group instance indices by key (stable), one class per distinct key.
+template <typename K>
+std::vector<std::vector<int>> group_by(const std::vector<K>& key) {
+  std::vector<int> idx(key.size());
+  for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return key[a] < key[c]; });
+  std::vector<std::vector<int>> out;
+  for (size_t k = 0; k < idx.size(); ++k) {
+    if (k == 0 || key[idx[k]] != key[idx[k - 1]]) out.emplace_back();
+    out.back().push_back(idx[k]);
+  }
+  return out;
+}
+
+// (Re)build the per-instance descriptors, launch classes and block tables.
 template <typename T>
 int batch_build(mmv_batch* b) {
   const int n = (int)b->inst.size();
-  std::vector<RowFwdDesc> fwd[4];
-  std::vector<RowStageDesc> stg[4];
-  std::vector<ColDesc> col(n);
-  std::vector<int> sf(n + 1, 0), sc(n + 1, 0), ss(n + 1, 0);
-  b->lds_fwd = b->lds_col = b->lds_stage = 0;
+  std::vector<RowFwdDesc> fwd_i[4], fwd[4];
+  std::vector<RowStageDesc> stg_i[4], stg[4];
+  std::vector<ColDesc> col_i(n), col;
+  std::vector<int> sf, sc, ss;
+  std::vector<size_t> k_fwd(n), k_col(n);
+  std::vector<std::pair<size_t, int>> k_stage(n);
   b->drive_sig.assign(n, DriveP{});
   b->fuse = true;
   for (int i = 0; i < n; ++i) b->fuse = b->fuse && b->inst[i]->fuse_fwd;
+  const size_t lds_limit = LDS_PER_CU - ROW_STATIC_LDS;
   for (int i = 0; i < n; ++i) {
     mmv_mesh* h = b->inst[i];
     b->drive_sig[i] = h->drive;
     T* m0 = (T*)h->m0;
     T* b1 = (T*)h->mb[0];
     T* b2 = (T*)h->mb[1];
-    const RowParams rp = stage_params(h, b->fuse);
+    RowParams rp = stage_params(h, b->fuse);
+    rp.nbr = batch_rows_per_transform<T>(rp, lds_limit);
     for (int s = 0; s < 4; ++s) {
       T* in = s == 0 ? m0 : (s == 1 ? b1 : (s == 2 ? b2 : b1));
       T* out = s == 0 ? b1 : (s == 1 ? b2 : (s == 2 ? b1 : m0));
@@ -1066,7 +1122,7 @@ int batch_build(mmv_batch* b) {
       f.P = h->px;
       f.tw = h->twx;
       f.twp = h->twp;
-      fwd[s].push_back(f);
+      fwd_i[s].push_back(f);
       RowStageDesc r{};
       r.p = rp;
       r.spec2 = h->spec2;
@@ -1079,9 +1135,9 @@ int batch_build(mmv_batch* b) {
       r.rigid = h->rigid;
       r.partial = h->partial;
       r.counter = h->counter;
-      stg[s].push_back(r);
+      stg_i[s].push_back(r);
     }
-    ColDesc& c = col[i];
+    ColDesc& c = col_i[i];
     c.spec1 = h->spec1;
     c.spec2 = h->spec2;
     c.kern = h->kern;
@@ -1097,16 +1153,49 @@ int batch_build(mmv_batch* b) {
     c.twy = h->twy;
     c.tab = h->tab_hot;
     c.tick = tick_args(h, rp.ntask);
-    sf[i + 1] = sf[i] + h->nfilm * h->ny;
-    sc[i + 1] = sc[i] + h->Kx * h->ngroup;
-    ss[i + 1] = ss[i] + rp.ntask;
-    b->lds_fwd = std::max(b->lds_fwd, row_fwd_lds_bytes(h->N2x, sizeof(T)));
-    b->lds_col = std::max(b->lds_col, col_lds_bytes<T>(h->Ly, c.nbuf));
-    b->lds_stage = std::max(b->lds_stage, row_lds_bytes<T>(rp));
+    k_fwd[i] = row_fwd_lds_bytes(h->N2x, sizeof(T));
+    k_col[i] = col_lds_bytes<T>(h->Ly, c.nbuf);
+    k_stage[i] = std::make_pair(row_lds_bytes<T>(rp), rp.inplace);
   }
-  b->nblk_fwd = sf[n];
-  b->nblk_col = sc[n];
-  b->nblk_stage = ss[n];
+  // launch classes: descriptors in class order, one block-start table each
+  auto make = [&](const std::vector<std::vector<int>>& groups, std::vector<BatchLaunch>& L, std::vector<int>& st,
+                  auto blocks, auto lds_of, auto fill) {
+    L.clear();
+    st.clear();
+    int off = 0;
+    for (const auto& g : groups) {
+      BatchLaunch c;
+      c.off = off;
+      c.n = (int)g.size();
+      c.soff = (int)st.size();
+      int acc = 0;
+      for (int i : g) {
+        st.push_back(acc);
+        acc += blocks(i);
+        c.lds = std::max(c.lds, lds_of(i));
+        fill(i);
+      }
+      st.push_back(acc);
+      c.nblk = acc;
+      c.inplace = k_stage[g[0]].second != 0;
+      off += c.n;
+      L.push_back(c);
+    }
+  };
+  for (int s = 0; s < 4; ++s) {
+    fwd[s].clear();
+    stg[s].clear();
+  }
+  make(group_by(k_fwd), b->l_fwd, sf, [&](int i) { return b->inst[i]->nfilm * b->inst[i]->ny; },
+       [&](int i) { return k_fwd[i]; }, [&](int i) {
+         for (int s = 0; s < 4; ++s) fwd[s].push_back(fwd_i[s][i]);
+       });
+  make(group_by(k_col), b->l_col, sc, [&](int i) { return b->inst[i]->Kx * b->inst[i]->ngroup; },
+       [&](int i) { return k_col[i]; }, [&](int i) { col.push_back(col_i[i]); });
+  make(group_by(k_stage), b->l_stage, ss, [&](int i) { return stg_i[0][i].p.ntask; },
+       [&](int i) { return k_stage[i].first; }, [&](int i) {
+         for (int s = 0; s < 4; ++s) stg[s].push_back(stg_i[s][i]);
+       });
   int rc;
   if (!b->d_col) {
     for (int s = 0; s < 4; ++s) {
@@ -1114,26 +1203,46 @@ int batch_build(mmv_batch* b) {
       if ((rc = balloc(b, (void**)&b->d_stage[s], sizeof(RowStageDesc) * n))) return rc;
     }
     if ((rc = balloc(b, (void**)&b->d_col, sizeof(ColDesc) * n))) return rc;
-    if ((rc = balloc(b, (void**)&b->s_fwd, sizeof(int) * (n + 1)))) return rc;
-    if ((rc = balloc(b, (void**)&b->s_col, sizeof(int) * (n + 1)))) return rc;
-    if ((rc = balloc(b, (void**)&b->s_stage, sizeof(int) * (n + 1)))) return rc;
+    if ((rc = balloc(b, (void**)&b->d_col_all, sizeof(ColDesc) * n))) return rc;
+    // at most one class per instance: n + 1 + (classes - 1) <= 2 n entries
+    if ((rc = balloc(b, (void**)&b->s_fwd, sizeof(int) * 2 * (n + 1)))) return rc;
+    if ((rc = balloc(b, (void**)&b->s_col, sizeof(int) * 2 * (n + 1)))) return rc;
+    if ((rc = balloc(b, (void**)&b->s_stage, sizeof(int) * 2 * (n + 1)))) return rc;
   }
   for (int s = 0; s < 4; ++s) {
     HIPCHK(hipMemcpyAsync(b->d_fwd[s], fwd[s].data(), sizeof(RowFwdDesc) * n, hipMemcpyHostToDevice, b->st));
     HIPCHK(hipMemcpyAsync(b->d_stage[s], stg[s].data(), sizeof(RowStageDesc) * n, hipMemcpyHostToDevice, b->st));
   }
   HIPCHK(hipMemcpyAsync(b->d_col, col.data(), sizeof(ColDesc) * n, hipMemcpyHostToDevice, b->st));
-  HIPCHK(hipMemcpyAsync(b->s_fwd, sf.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, b->st));
-  HIPCHK(hipMemcpyAsync(b->s_col, sc.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, b->st));
-  HIPCHK(hipMemcpyAsync(b->s_stage, ss.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, b->st));
-  HIPCHK(prepare_batch_kernels<T>(b->lds_fwd, b->lds_col, b->lds_stage));
+  HIPCHK(hipMemcpyAsync(b->d_col_all, col_i.data(), sizeof(ColDesc) * n, hipMemcpyHostToDevice, b->st));
+  HIPCHK(hipMemcpyAsync(b->s_fwd, sf.data(), sizeof(int) * sf.size(), hipMemcpyHostToDevice, b->st));
+  HIPCHK(hipMemcpyAsync(b->s_col, sc.data(), sizeof(int) * sc.size(), hipMemcpyHostToDevice, b->st));
+  HIPCHK(hipMemcpyAsync(b->s_stage, ss.data(), sizeof(int) * ss.size(), hipMemcpyHostToDevice, b->st));
+  size_t mf = 0, mc = 0, ms = 0;
+  for (auto& c : b->l_fwd) mf = std::max(mf, c.lds);
+  for (auto& c : b->l_col) mc = std::max(mc, c.lds);
+  for (auto& c : b->l_stage) ms = std::max(ms, c.lds);
+  HIPCHK(prepare_batch_kernels<T>(mf, mc, ms));
   HIPCHK(hipStreamSynchronize(b->st));
+  if (getenv("MMV_VERBOSE"))
+    for (auto& c : b->l_stage)
+      fprintf(stderr, "mmv: batch row class: %d instances, %d blocks, LDS %zu, in place %d\n", c.n, c.nblk, c.lds,
+              (int)c.inplace);
   if (b->exec) {
     hipGraphExecDestroy(b->exec);
     hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
   }
+  return MMV_OK;
+}
+
+// The y pass of every class (its block 0 per instance applies the pending
+// slider stage when tick_stage >= 0).
+template <typename T>
+int batch_col_launches(mmv_batch* b, hipStream_t st, int tick_stage, double dt) {
+  for (const BatchLaunch& c : b->l_col)
+    HIPCHK(launch_col_batch<T>(b->d_col + c.off, b->s_col + c.soff, c.n, c.nblk, c.lds, st, tick_stage, dt));
   return MMV_OK;
 }
 
@@ -1147,18 +1256,22 @@ int batch_launch_steps(mmv_batch* b, hipStream_t st, double dt, int nsteps) {
       mmv_mesh* h = h0;
       if (!b->fuse || (k == 0 && s == 0)) {
         PROF(1);
-        HIPCHK(launch_row_fwd_batch<T>(b->d_fwd[s], b->s_fwd, n, b->nblk_fwd, b->lds_fwd, st));
+        for (const BatchLaunch& c : b->l_fwd)
+          HIPCHK(launch_row_fwd_batch<T>(b->d_fwd[s] + c.off, b->s_fwd + c.soff, c.n, c.nblk, c.lds, st));
         PROF(1);
       }
       PROF(2);
-      HIPCHK(launch_col_batch<T>(b->d_col, b->s_col, n, b->nblk_col, b->lds_col, st, pending, dt));
+      int rc = batch_col_launches<T>(b, st, pending, dt);
+      if (rc) return rc;
       PROF(2);
       PROF(3);
-      HIPCHK(launch_row_stage_batch<T>(b->d_stage[s], b->s_stage, n, b->nblk_stage, b->lds_stage, s, dt, st));
+      for (const BatchLaunch& c : b->l_stage)
+        HIPCHK(launch_row_stage_batch<T>(b->d_stage[s] + c.off, b->s_stage + c.soff, c.n, c.nblk, c.lds, s, dt,
+                                         c.inplace, st));
       PROF(3);
       pending = s;
     }
-  if (pending >= 0) HIPCHK(launch_tick_batch(b->d_col, n, pending, dt, st));
+  if (pending >= 0) HIPCHK(launch_tick_batch(b->d_col_all, n, pending, dt, st));
   return MMV_OK;
 }
 
@@ -1301,9 +1414,10 @@ int batch_autotune(mmv_batch* b) {
         if (h->Kx == sz.first && h->Ly == sz.second) h->ngroup = g;
       int rc = batch_build<T>(b);
       if (rc) return rc;
-      HIPCHK(launch_col_batch<T>(b->d_col, b->s_col, n, b->nblk_col, b->lds_col, b->st));
+      if ((rc = batch_col_launches<T>(b, b->st, -1, 0.0))) return rc;
       HIPCHK(hipEventRecord(e0, b->st));
-      for (int r = 0; r < 5; ++r) HIPCHK(launch_col_batch<T>(b->d_col, b->s_col, n, b->nblk_col, b->lds_col, b->st));
+      for (int r = 0; r < 5; ++r)
+        if ((rc = batch_col_launches<T>(b, b->st, -1, 0.0))) return rc;
       HIPCHK(hipEventRecord(e1, b->st));
       HIPCHK(hipEventSynchronize(e1));
       float ms = 0;

@@ -118,6 +118,8 @@ struct RowParams {
   void* spec1_out;
   // MODE_FORCE: when set, the force [N] goes here instead of rigid->F
   double* fout;
+  // the row transforms run in place (compiled lengths only): sizes the LDS
+  int inplace;
 };
 
 // Per-instance descriptors of the batched launches (device memory).

@@ -36,7 +36,9 @@ hipError_t launch_col_batch(const ColDesc* d, const int* start, int n, int nblk,
                             int tick_stage = -1, double tick_dt = 0.0);
 template <typename T>
 hipError_t launch_row_stage_batch(const RowStageDesc* d, const int* start, int n, int nblk, size_t lds, int stage,
-                                  double dt, hipStream_t st);
+                                  double dt, bool inplace, hipStream_t st);
+// The row kernel can transform rows of this length in place.
+bool row_inplace_length(int L);
 size_t row_fwd_lds_bytes(int N2x, int esz);
 template <typename T>
 hipError_t prepare_batch_kernels(size_t lds_fwd, size_t lds_col, size_t lds_stage);

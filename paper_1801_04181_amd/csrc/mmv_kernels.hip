@@ -33,6 +33,38 @@ constexpr int TICK_THREADS = 256;     // slider tick
 constexpr int COLPACK_THREADS = 256;  // kernel-spectrum packing
 static_assert(TICK_THREADS == COL_THREADS, "the y pass runs the tick with its own block");
 
+// Rows per batch of the row kernel's transforms, at most.
+constexpr int MAX_NBR = 9;
+
+// Lengths with a compiled plan that the row kernel can transform in place
+// (half the LDS of the ping-pong form).
+__host__ __device__ constexpr bool inplace_length(int L) { return L == 525 || L == 270 || L == 140 || L == 72; }
+
+// In-place batched transform of `batch` <= MAX_NBR contiguous rows of
+// length P.L (one of inplace_length); returns a.
+template <typename T, bool INV, int NT>
+__device__ __forceinline__ cpx<T>* fft_rows_inplace(cpx<T>* a, const FftPlan& P, int batch,
+                                                   const cpx<T>* __restrict__ tw) {
+  switch (P.L) {
+    case 525: fft_inplace<T, 525, NT, INV, MAX_NBR>(a, batch, tw); break;
+    case 270: fft_inplace<T, 270, NT, INV, MAX_NBR>(a, batch, tw); break;
+    case 140: fft_inplace<T, 140, NT, INV, MAX_NBR>(a, batch, tw); break;
+    case 72: fft_inplace<T, 72, NT, INV, MAX_NBR>(a, batch, tw); break;
+    default: break;  // the host only selects the in-place kernel for these lengths
+  }
+  return a;
+}
+
+// The row kernel's transforms: in place (INPL) or ping-pong between a and b.
+template <typename T, bool INV, int NT, bool INPL>
+__device__ __forceinline__ cpx<T>* row_fft(cpx<T>* a, cpx<T>* b, const FftPlan& P, int batch,
+                                           const cpx<T>* __restrict__ tw) {
+  if constexpr (INPL)
+    return fft_rows_inplace<T, INV, NT>(a, P, batch, tw);
+  else
+    return fft_lds<T, INV, NT>(a, b, P, batch, P.L, tw);
+}
+
 // ------------------------------------------------------------ x transform
 // Rows handled by one block of the x pass: `nb` rows at `row0`, `rstride`
 // rows apart (the three components of one film row, or one row).  Output
@@ -60,8 +92,11 @@ __device__ __forceinline__ void row_fwd_body(int row0, int nb, int rstride, cons
     return mk<T>(i0 < nin ? s[i0] : T(0), i1 < nin ? s[i1] : T(0));
   });
   lds_barrier();
+  // the film lengths run in place, as in the row kernel's fused forward
+  // transform, so both produce the same spectra
   cpx<T>* Z = POW2 ? fft_lds_pow2<T, false, FWD_THREADS>(a, b, P, nb, N2x, stw)
-                   : fft_lds<T, false, FWD_THREADS>(a, b, P, nb, N2x, stw);
+              : (inplace_length(P.L) && nb <= MAX_NBR) ? fft_rows_inplace<T, false, FWD_THREADS>(a, P, nb, stw)
+                                                       : fft_lds<T, false, FWD_THREADS>(a, b, P, nb, N2x, stw);
   const int K1 = N2x + 1;
   const float ink = 1.0f / (float)K1;
   for (int t = threadIdx.x; t < nb * K1; t += FWD_THREADS) {
@@ -330,7 +365,7 @@ __device__ __forceinline__ cpx<T> c2r_twist(cpx<T> xk, cpx<T> xm, cpx<T> w) {
 // Inverse real transform of nb rows (Hermitian halves X[0..N2x] at base + rowo[b])
 // into LDS; result buffer viewed as T* holds x[0..Lx) of each row at stride
 // 2*N2x reals.
-template <typename T, int NT>
+template <typename T, int NT, bool INPL = false>
 __device__ __forceinline__ cpx<T>* c2r_rows(const cpx<T>* __restrict__ base, const long long* rowo, int nb, cpx<T>* fa, cpx<T>* fb,
                             int N2x,
                             const FftPlan& P, const cpx<T>* stw, const cpx<T>* stp) {
@@ -343,7 +378,7 @@ __device__ __forceinline__ cpx<T>* c2r_rows(const cpx<T>* __restrict__ base, con
     return c2r_twist(X[k], X[N2x - k], stp[k]);
   });
   lds_barrier();
-  return fft_lds<T, true, NT>(fa, fb, P, nb, N2x, stw);
+  return row_fft<T, true, NT, INPL>(fa, fb, P, nb, stw);
 }
 
 // Inputs of the first batch of inverse row transforms, held in registers:
@@ -490,7 +525,7 @@ constexpr int MAX_ROWS = 24;
 // rows 0 and ny-1, one more inverse transform each, so that a stage
 // launches exactly nfilm * ny blocks.  All inverse row transforms of a task run as one batch (or
 // batches of p.nbr rows); every spline window is filtered in parallel.
-template <typename T, int NT>
+template <typename T, int NT, bool INPL = false>
 __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, double dt, int task, int ntask,
                                                const cpx<T>* __restrict__ spec2, const T* __restrict__ mst,
                                                const T* m0, T* mnext, T* __restrict__ acc, T* __restrict__ hout,
@@ -508,7 +543,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* stp = stw + N2x;
   cpx<T>* fa = stp + N2x + 1;
-  cpx<T>* fb = fa + (size_t)nbr * N2x;
+  cpx<T>* fb = INPL ? fa : fa + (size_t)nbr * N2x;  // ping-pong partner (none in place)
   T* ext = reinterpret_cast<T*>(fb + (size_t)nbr * N2x);  // [nbr][MW]
   // weights, slider samples base field (16-byte aligned for vector reads)
   T* gs = reinterpret_cast<T*>(smem_raw + ((static_cast<size_t>(reinterpret_cast<unsigned char*>(ext + (size_t)nbr * MWS) - smem_raw) + 15) & ~size_t(15)));
@@ -749,8 +784,8 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   for (int b0 = 0; b0 < nrow; b0 += nbr) {
     const int bn = min(nbr, nrow - b0);
     // the first batch's half-length inputs were formed during the set-up
-    cpx<T>* Z = b0 == 0 ? fft_lds<T, true, NT>(fa, fb, p.px, bn, N2x, stw)
-                        : c2r_rows<T, NT>(spec2, rowo + b0, bn, fa, fb, N2x, p.px, stw, stp);
+    cpx<T>* Z = b0 == 0 ? row_fft<T, true, NT, INPL>(fa, fb, p.px, bn, stw)
+                        : c2r_rows<T, NT, INPL>(spec2, rowo + b0, bn, fa, fb, N2x, p.px, stw, stp);
     const T* xr = reinterpret_cast<const T*>(Z);
     // self rows -> H, spline rows -> windows with mirror extension
     const float invMW = 1.0f / (float)MW;
@@ -1026,7 +1061,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   if (fuse) {
     // forward real transform of the three rows (as the x pass computes it)
     lds_barrier();
-    const cpx<T>* Z = fft_lds<T, false, NT>(fa, fb, p.px, 3, N2x, stw);
+    const cpx<T>* Z = row_fft<T, false, NT, INPL>(fa, fb, p.px, 3, stw);
     cpx<T>* dst = reinterpret_cast<cpx<T>*>(p.spec1_out);
     const int K1 = N2x + 1;
 #pragma unroll 1
@@ -1140,7 +1175,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   }
 }
 
-template <typename T>
+template <typename T, bool INPL>
 __global__ void __launch_bounds__((RowThreads<T, false>::n))
     k_row_stage(RowParams p, const cpx<T>* __restrict__ spec2, const T* __restrict__ mst, const T* m0, T* mnext,
                 T* __restrict__ acc, T* __restrict__ hout, const cpx<T>* __restrict__ tw,
@@ -1148,17 +1183,18 @@ __global__ void __launch_bounds__((RowThreads<T, false>::n))
                 unsigned int* __restrict__ counter) {
   // XCD-contiguous tasks: the column-major spectrum writes of neighbouring
   // rows meet in one L2
-  row_stage_body<T, RowThreads<T, false>::n>(p, p.stage, p.dt, xcd_remap(blockIdx.x, gridDim.x), gridDim.x, spec2, mst, m0, mnext, acc, hout, tw, twp, rigid,
-                    partial, counter);
+  row_stage_body<T, RowThreads<T, false>::n, INPL>(p, p.stage, p.dt, xcd_remap(blockIdx.x, gridDim.x), gridDim.x,
+                                                    spec2, mst, m0, mnext, acc, hout, tw, twp, rigid, partial,
+                                                    counter);
 }
 
-template <typename T>
+template <typename T, bool INPL>
 __global__ void __launch_bounds__((RowThreads<T, true>::n)) k_row_stage_batch(const RowStageDesc* __restrict__ d,
                                                          const int* __restrict__ start, int n, int stage, double dt) {
   const int bl = xcd_remap(blockIdx.x, gridDim.x);
   const int i = find_instance(start, n, bl);
   const RowStageDesc& q = d[i];
-  row_stage_body<T, RowThreads<T, true>::n>(q.p, stage, dt, bl - start[i], start[i + 1] - start[i], (const cpx<T>*)q.spec2,
+  row_stage_body<T, RowThreads<T, true>::n, INPL>(q.p, stage, dt, bl - start[i], start[i + 1] - start[i], (const cpx<T>*)q.spec2,
                     (const T*)q.mst, (const T*)q.m0, (T*)q.mnext, (T*)q.acc, nullptr, (const cpx<T>*)q.tw,
                     (const cpx<T>*)q.twp, q.rigid, q.partial, q.counter);
 }
@@ -1255,7 +1291,9 @@ int col_blocks_per_cu(size_t lds) {
 template <typename T>
 bool static_lds_within_reserve() {
   hipFuncAttributes a{};
-  for (const void* k : {(const void*)k_row_stage<T>, (const void*)k_row_stage_batch<T>}) {
+  for (const void* k : {(const void*)k_row_stage<T, false>, (const void*)k_row_stage<T, true>,
+                        (const void*)k_row_stage_batch<T, false>,
+                        (const void*)k_row_stage_batch<T, true>}) {
     if (hipFuncGetAttributes(&a, k) != hipSuccess || a.sharedSizeBytes > ROW_STATIC_LDS) return false;
   }
   for (const void* k : {(const void*)k_col<T>, (const void*)k_col_batch<T>}) {
@@ -1298,7 +1336,7 @@ template <typename T>
 size_t row_lds_bytes(const RowParams& p) {
   const int K = FirHalf<T>::K, NQ = 2 * K + 4, E = K + 4;
   const int nfc = p.full_force ? 3 : 1;
-  size_t b = sizeof(cpx<T>) * (size_t)(2 * p.N2x + 1 + 2 * (size_t)p.nbr * p.N2x);
+  size_t b = sizeof(cpx<T>) * (size_t)(2 * p.N2x + 1 + (p.inplace ? 1 : 2) * (size_t)p.nbr * p.N2x);
   const int nslot = p.pot ? (p.full_force ? 19 : 9) : 0;
   b += sizeof(T) * ((size_t)p.nbr * ((p.M + 2 * E + 5) & ~1) + 2 * NQ + 3 * p.nx + 3 * (p.nx + 2) + 2 * nfc * p.nx +
                     (size_t)nslot * (p.nx + 6) + 2 * (size_t)p.nx + 2) + 16;  // + alignment of the weights
@@ -1312,12 +1350,19 @@ hipError_t launch_row_stage(const RowParams& p, const void* spec2, const T* mst,
                             T* hout, const void* tw, const void* twp, RigidState* rigid, double* partial,
                             unsigned* counter, hipStream_t st) {
   const size_t lds = row_lds_bytes<T>(p);
+  const void* kf = p.inplace ? (const void*)k_row_stage<T, true> : (const void*)k_row_stage<T, false>;
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_row_stage<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_row_stage<T>, dim3(p.ntask), dim3(RowThreads<T, false>::n), lds, st, p, (const cpx<T>*)spec2, mst, m0,
-                     mnext, acc, hout, (const cpx<T>*)tw, (const cpx<T>*)twp, rigid, partial, counter);
+  if (p.inplace)
+    hipLaunchKernelGGL((k_row_stage<T, true>), dim3(p.ntask), dim3(RowThreads<T, false>::n), lds, st, p,
+                       (const cpx<T>*)spec2, mst, m0, mnext, acc, hout, (const cpx<T>*)tw, (const cpx<T>*)twp, rigid,
+                       partial, counter);
+  else
+    hipLaunchKernelGGL((k_row_stage<T, false>), dim3(p.ntask), dim3(RowThreads<T, false>::n), lds, st, p,
+                       (const cpx<T>*)spec2, mst, m0, mnext, acc, hout, (const cpx<T>*)tw, (const cpx<T>*)twp, rigid,
+                       partial, counter);
   return hipGetLastError();
 }
 
@@ -1336,8 +1381,13 @@ hipError_t launch_col_batch(const ColDesc* d, const int* start, int n, int nblk,
 
 template <typename T>
 hipError_t launch_row_stage_batch(const RowStageDesc* d, const int* start, int n, int nblk, size_t lds, int stage,
-                                  double dt, hipStream_t st) {
-  hipLaunchKernelGGL(k_row_stage_batch<T>, dim3(nblk), dim3(RowThreads<T, true>::n), lds, st, d, start, n, stage, dt);
+                                  double dt, bool inplace, hipStream_t st) {
+  if (inplace)
+    hipLaunchKernelGGL((k_row_stage_batch<T, true>), dim3(nblk), dim3(RowThreads<T, true>::n), lds, st, d, start, n,
+                       stage, dt);
+  else
+    hipLaunchKernelGGL((k_row_stage_batch<T, false>), dim3(nblk), dim3(RowThreads<T, true>::n), lds, st, d, start, n,
+                       stage, dt);
   return hipGetLastError();
 }
 
@@ -1349,11 +1399,13 @@ hipError_t prepare_batch_kernels(size_t lds_fwd, size_t lds_col, size_t lds_stag
     e = hipFuncSetAttribute((const void*)k_row_fwd_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_fwd);
   if (e == hipSuccess && lds_col > 65536)
     e = hipFuncSetAttribute((const void*)k_col_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_col);
-  if (e == hipSuccess && lds_stage > 65536)
-    e = hipFuncSetAttribute((const void*)k_row_stage_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds_stage);
+  for (const void* k : {(const void*)k_row_stage_batch<T, false>, (const void*)k_row_stage_batch<T, true>})
+    if (e == hipSuccess && lds_stage > 65536)
+      e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_stage);
   return e;
 }
+
+bool row_inplace_length(int L) { return inplace_length(L); }
 
 size_t row_fwd_lds_bytes(int N2x, int esz) { return (size_t)2 * esz * (8 * (size_t)N2x + 1); }
 
@@ -1391,7 +1443,7 @@ hipError_t launch_colpack(const void* spec, T* out, int Kx, int Ly, int Kyh, con
   template hipError_t launch_row_fwd_batch<T>(const RowFwdDesc*, const int*, int, int, size_t, hipStream_t);      \
   template hipError_t launch_col_batch<T>(const ColDesc*, const int*, int, int, size_t, hipStream_t, int, double);             \
   template hipError_t launch_row_stage_batch<T>(const RowStageDesc*, const int*, int, int, size_t, int, double,   \
-                                                hipStream_t);
+                                                bool, hipStream_t);
 
 MMV_INST(float)
 MMV_INST(double)
