@@ -19,6 +19,8 @@ framework") step by step:
   sim.py               two-film system: cross fields, force Eq. (3),
                        RK4 with the slider equation of motion Eq. (15),
                        diagnostics incl. P_diss Eq. (4)
+  dormand_prince.py    adaptive Dormand-Prince RK5(4) of the same system
+                       (the paper's RK45 solver, Sec. III)
   fno.py               learned stray-field operator (Fourier neural
                        operator standing in for the cross term), float64
                        torch with autograd gradients
@@ -27,7 +29,7 @@ Parity status of each function is stated in its docstring; functions with
 no independent pin say "parity unpinned".
 """
 from .constants import MU0, GAMMA_E, GAMMA0
-from . import newell, potential_kernel, convolution, spline, fields, llg, sim, fno
+from . import newell, potential_kernel, convolution, spline, fields, llg, sim, fno, dormand_prince
 
 __all__ = ["MU0", "GAMMA_E", "GAMMA0", "newell", "potential_kernel",
-           "convolution", "spline", "fields", "llg", "sim", "fno"]
+           "convolution", "spline", "fields", "llg", "sim", "fno", "dormand_prince"]
