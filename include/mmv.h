@@ -144,6 +144,28 @@ int eval_heff(mmv_handle h, int film, int term_mask, void* h_dev);
  * the next get_state / stray_force.                                      */
 int llg_step(mmv_handle h, double dt, int nsteps);
 
+/* Adaptive Dormand-Prince RK5(4) run from the current state to t_end [s]
+ * (the paper's RK45 solver with the slider's equation of motion, Sec. III).
+ * Every attempt evaluates seven stages, each the full field at its own
+ * magnetisation, offset and time; it advances with the fifth-order state
+ * and estimates the error from the embedded fourth-order one.  Error ratio:
+ * the largest of max over cells |e_m|, |e_x| / dx and |e_v| h / dx, over
+ * tol; accepted when <= 1 (then m is renormalised and s_int re-seated).
+ * Next step h * min(5, max(0.2, 0.9 ratio^(-1/5))) (at most h after a
+ * rejection), clipped so the run ends exactly at t_end (reached when
+ * t_end - t <= 1e-9 t_end).  The step control runs on the device; the host
+ * checks the run's end every 8 attempts (synchronising the stream) and
+ * stops at t_end or after max_attempts attempts (the state then lies
+ * before t_end: get_state tells).  *h_io: initial step in, next proposed
+ * step out; *accepted / *rejected (may be NULL): attempts of this call.
+ * Film meshes only (MMV_ESTATE for the three-dimensional path, batch
+ * instances and meshes with a learned operator attached); MMV_EINVAL for
+ * t_end not after the current time, tol or *h_io not finite and > 0.
+ * Reports pending MMV_ERANGE / MMV_ENUMERIC (a non-finite error stops the
+ * run with MMV_ENUMERIC).                                                */
+int llg_run_dp(mmv_handle h, double t_end, double tol, double* h_io, int max_attempts, long* accepted,
+               long* rejected);
+
 /* Force of Eq. (3) exerted by the base on the slider [N] at the current
  * state, all three components, accumulated in float64 in a fixed order.
  * Synchronises the stream.  MMV_ESTATE for a single-film mesh.          */

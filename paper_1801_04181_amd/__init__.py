@@ -10,7 +10,7 @@ import ctypes
 import os
 
 __all__ = ["MMVError", "lib_path", "load", "MeshDesc", "DriveDesc", "init_mesh",
-           "set_m", "get_m", "set_offset", "set_drive", "eval_heff", "llg_step",
+           "set_m", "get_m", "set_offset", "set_drive", "eval_heff", "llg_step", "llg_run_dp",
            "stray_force", "stray_force_noalloc", "get_state", "get_fft_lengths", "destroy_mesh",
            "profile_begin", "profile_end", "profile_repeat", "init_batch", "batch_instance", "batch_step",
            "batch_tuning", "set_tune_cache", "destroy_batch", "Batch", "SurDesc", "sur_create", "sur_param_count",
@@ -26,7 +26,7 @@ TERM = dict(exchange=1, anisotropy=2, zeeman=4, demag_self=8, demag_cross=16,
 ERRORS = {-1: "MMV_EINVAL", -2: "MMV_ENOMEM", -3: "MMV_EHIP", -4: "MMV_ERANGE",
           -5: "MMV_ENUMERIC", -6: "MMV_ESTATE"}
 EXPORTS = ("init_mesh", "set_m", "get_m", "set_offset", "set_drive", "eval_heff",
-           "llg_step", "stray_force", "stray_force_noalloc", "get_state", "profile_begin", "profile_end",
+           "llg_step", "llg_run_dp", "stray_force", "stray_force_noalloc", "get_state", "profile_begin", "profile_end",
            "get_fft_lengths", "profile_repeat", "init_batch", "batch_instance", "batch_step", "batch_tuning",
            "set_tune_cache", "destroy_batch", "destroy_mesh", "sur_create", "sur_param_count", "sur_param_offsets",
            "sur_set_params", "sur_get_params", "sur_forward", "sur_gradient", "sur_train_step",
@@ -87,6 +87,7 @@ def load():
         lib.set_drive.argtypes = [vp, ctypes.POINTER(DriveDesc)]
         lib.eval_heff.argtypes = [vp, i, i, vp]
         lib.llg_step.argtypes = [vp, d, i]
+        lib.llg_run_dp.argtypes = [vp, d, d, pd, i, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]
         lib.stray_force.argtypes = [vp, pd]
         lib.stray_force_noalloc.argtypes = [vp, vp]
         lib.get_state.argtypes = [vp, pd, pd, pd, ctypes.POINTER(ctypes.c_long)]
@@ -196,6 +197,16 @@ def eval_heff(h, film, term_mask, out):
 
 def llg_step(h, dt, nsteps=1):
     _check(load().llg_step(h, float(dt), int(nsteps)))
+
+
+def llg_run_dp(h, t_end, tol, h0, max_attempts=100000):
+    """Adaptive Dormand-Prince run to t_end; returns accepted and rejected
+    attempts and the next proposed step."""
+    hh = ctypes.c_double(float(h0))
+    acc, rej = ctypes.c_long(), ctypes.c_long()
+    _check(load().llg_run_dp(h, float(t_end), float(tol), ctypes.byref(hh), int(max_attempts), ctypes.byref(acc),
+                             ctypes.byref(rej)))
+    return dict(accepted=acc.value, rejected=rej.value, h=hh.value)
 
 
 def stray_force(h):
@@ -366,6 +377,9 @@ class Mesh:
 
     def step(self, dt, n=1):
         llg_step(self.h, dt, n)
+
+    def run_dp(self, t_end, tol, h0, max_attempts=100000):
+        return llg_run_dp(self.h, t_end, tol, h0, max_attempts)
 
     def force(self):
         return stray_force(self.h)

@@ -136,6 +136,10 @@ struct mmv_mesh {
   long sur_judged = 0, sur_steps = 0;
   float* sur_in = nullptr;
   float* sur_exact = nullptr;
+  // adaptive Dormand-Prince run (allocated at its first use)
+  void* kdp = nullptr;         // stage derivatives [7][film][3][y][x]
+  double* errpart = nullptr;   // per row block largest error
+  DpCtrl* dpc = nullptr;       // step control
   OutTable tab_sur{};
   int sor_sweeps = 40;
   double sor_omega = 1.0;
@@ -925,6 +929,55 @@ int force_typed(mmv_mesh* h, double* partial, unsigned* counter, double* fout) {
   rp.fout = fout;
   HIPCHK(launch_row_stage<T>(rp, h->spec2, (const T*)h->m0, (const T*)h->m0, nullptr, nullptr, nullptr, h->twx,
                              h->twp, h->rigid, partial, counter, h->st));
+  return MMV_OK;
+}
+
+// Attempts of the adaptive Dormand-Prince run (Sec. III): per attempt the x
+// pass of m, seven stages (y pass with the previous stage's slider update,
+// row kernel writing the stage derivative and the next stage's state), the
+// step control and the commit of an accepted state.  Every launch reads the
+// step size from the device; after t_end they return at once.
+template <typename T>
+int dp_attempts(mmv_mesh* h, int n) {
+  RowParams rp = h->rp_hot;
+  rp.mode = MODE_STAGE;
+  rp.term_mask = MMV_TERM_ALL;
+  rp.drive = h->drive;
+  rp.with_force = (h->nfilm == 2 && h->drive.mode == MMV_DRIVE_SPRING) ? 1 : 0;
+  rp.full_force = 0;
+  rp.ntask = h->nfilm * h->ny + ((rp.with_force && rp.pot) ? 2 : 0);
+  rp.defer_tick = 1;
+  rp.hsur = nullptr;
+  rp.scheme = 1;
+  rp.kdp = h->kdp;
+  rp.errpart = h->errpart;
+  rp.ctrl = h->dpc;
+  TickArgs ta = tick_args(h, rp.ntask);
+  ta.scheme = 1;
+  ta.ctrl = h->dpc;
+  T* m0 = (T*)h->m0;
+  T* b1 = (T*)h->mb[0];
+  T* b2 = (T*)h->mb[1];
+  const size_t plane = (size_t)h->ny * h->nx;
+  for (int a = 0; a < n; ++a) {
+    int pending = -1;
+    for (int i = 0; i < 7; ++i) {
+      T* in = i == 0 ? m0 : ((i & 1) ? b1 : b2);
+      T* out = (i & 1) ? b2 : b1;
+      if (i == 0 || !h->fuse_fwd)
+        HIPCHK(launch_row_fwd<T>(in, h->spec1, 3 * h->nfilm * h->ny, h->nx, h->N2x, h->Kx, h->px, h->twx, h->twp,
+                                 h->st, h->ny));
+      HIPCHK(launch_col<T>(h->spec1, h->spec2, (const T*)h->kern, h->Kx, h->Ly, h->Kyh, h->ny, 3 * h->nfilm,
+                           h->ngroup, h->py, h->twy, h->tab_hot, h->st, &ta, pending, 0.0));
+      rp.stage = i;
+      rp.spec1_out = (i < 6 && h->fuse_fwd) ? h->spec1 : nullptr;
+      HIPCHK(launch_row_stage<T>(rp, h->spec2, in, m0, out, (T*)h->acc, nullptr, h->twx, h->twp, h->rigid,
+                                 h->partial, h->counter, h->st));
+      pending = i;
+    }
+    HIPCHK(launch_dp_control(ta, h->dpc, h->errpart, rp.ntask, h->st));
+    HIPCHK(launch_dp_commit<T>(b2, m0, h->nfilm, plane, h->dpc, &h->rigid->flags, h->st));
+  }
   return MMV_OK;
 }
 
@@ -1899,6 +1952,54 @@ int stray_force_noalloc(mmv_handle h, double* F_dev) {
   // the arrival counter must start at zero (a fill kernel, not a memset node)
   HIPCHK(launch_fill_u32(counter, (int)(NOALLOC_COUNTER_BYTES / sizeof(unsigned)), 0u, h->st));
   return h->esz == 8 ? force_typed<double>(h, partial, counter, F_dev) : force_typed<float>(h, partial, counter, F_dev);
+}
+
+int llg_run_dp(mmv_handle h, double t_end, double tol, double* h_io, int max_attempts, long* accepted,
+               long* rejected) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (h->cube) return fail(MMV_ESTATE, "llg_run_dp runs on the film path (nz == 1)");
+  if (h->in_batch) return fail(MMV_ESTATE, "llg_run_dp does not run on batch instances");
+  if (h->sur) return fail(MMV_ESTATE, "llg_run_dp does not run with a learned operator attached");
+  if (!h_io) return fail(MMV_EINVAL, "h_io is NULL");
+  if (!(*h_io > 0) || !isfinite(*h_io)) return fail(MMV_EINVAL, "the initial step must be finite and > 0");
+  if (!(tol > 0) || !isfinite(tol)) return fail(MMV_EINVAL, "tol must be finite and > 0");
+  if (!isfinite(t_end)) return fail(MMV_EINVAL, "t_end must be finite");
+  if (max_attempts < 1) return fail(MMV_EINVAL, "max_attempts must be >= 1");
+  RigidState r;
+  if ((rc = read_rigid(h, r))) return rc;
+  if (!(t_end > r.t0)) return fail(MMV_EINVAL, "t_end must lie after the current time");
+  const size_t plane = (size_t)h->ny * h->nx;
+  if (!h->kdp && (rc = dalloc(h, &h->kdp, (size_t)7 * h->nfilm * 3 * plane * h->esz))) return rc;
+  if (!h->errpart && (rc = dalloc(h, (void**)&h->errpart, sizeof(double) * (size_t)(h->nfilm * h->ny + 2))))
+    return rc;
+  if (!h->dpc && (rc = dalloc(h, (void**)&h->dpc, sizeof(DpCtrl)))) return rc;
+  DpCtrl c{};
+  c.h = std::min(*h_io, t_end - r.t0);
+  c.t_end = t_end;
+  c.tol = tol;
+  r.xs = r.x0;
+  r.vs = r.v0;
+  r.ts = r.t0;
+  HIPCHK(hipMemcpyAsync(h->dpc, &c, sizeof(c), hipMemcpyHostToDevice, h->st));
+  if ((rc = write_rigid(h, r))) return rc;
+  // attempts in chunks between host checks of the run's end
+  constexpr int CHUNK = 8;
+  int done_attempts = 0;
+  while (done_attempts < max_attempts) {
+    const int n = std::min(CHUNK, max_attempts - done_attempts);
+    rc = h->esz == 8 ? dp_attempts<double>(h, n) : dp_attempts<float>(h, n);
+    if (rc) return rc;
+    done_attempts += n;
+    HIPCHK(hipMemcpyAsync(&c, h->dpc, sizeof(c), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    if (c.done) break;
+  }
+  *h_io = c.h;
+  if (accepted) *accepted = (long)c.accepted;
+  if (rejected) *rejected = (long)c.rejected;
+  if ((rc = read_rigid(h, r))) return rc;
+  return report_flags(h, r);
 }
 
 int get_state(mmv_handle h, double* t, double* x_s, double* v_s, long* step) {

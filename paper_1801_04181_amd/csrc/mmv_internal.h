@@ -49,6 +49,20 @@ struct RigidState {
   long long step;
   int s_int;          // floor(x / dx), fixed within a step
   int flags;          // FLAG_* (sticky until read by the host)
+  double kx[7], kv[7];  // Dormand-Prince stage derivatives of x and v
+};
+
+// Step control of the adaptive Dormand-Prince run, in device memory: every
+// launch of an attempt reads the step size from here, the control kernel at
+// the attempt's end decides and writes the next one.
+struct DpCtrl {
+  double h;         // step size of the current attempt [s]
+  double t_end;     // end of the run [s]
+  double tol;       // error tolerance
+  double err;       // error ratio of the last attempt
+  long long accepted, rejected;
+  int accept;       // the last attempt was accepted (read by the commit kernel)
+  int done;         // t_end reached: the field and row launches return at once
 };
 
 enum { FLAG_RANGE = 1, FLAG_NUMERIC = 2 };
@@ -70,6 +84,8 @@ struct TickArgs {
   DriveP drive;
   double force_scale, dx;
   int ntask, travel;
+  int scheme;             // 0: classic RK4 stages; 1: Dormand-Prince stages
+  const DpCtrl* ctrl;     // Dormand-Prince: step size and run state
 };
 
 // Parameters of the fused row kernel (inverse row transform, spline,
@@ -120,6 +136,14 @@ struct RowParams {
   double* fout;
   // the row transforms run in place (compiled lengths only): sizes the LDS
   int inplace;
+  // MODE_STAGE scheme: 0 classic RK4 (acc, mnext); 1 Dormand-Prince stage
+  // `stage` (0..6): writes its derivative to kdp[stage] ([7][film][3][y][x]),
+  // the next stage's state to mnext (stages 0..5) or, at stage 6, the
+  // block's largest |error| of m to errpart[task]; step size from ctrl
+  int scheme;
+  void* kdp;
+  double* errpart;
+  const DpCtrl* ctrl;
 };
 
 // Per-instance descriptors of the batched launches (device memory).

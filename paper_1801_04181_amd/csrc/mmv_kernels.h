@@ -37,6 +37,12 @@ hipError_t launch_col_batch(const ColDesc* d, const int* start, int n, int nblk,
 template <typename T>
 hipError_t launch_row_stage_batch(const RowStageDesc* d, const int* start, int n, int nblk, size_t lds, int stage,
                                   double dt, bool inplace, hipStream_t st);
+// Adaptive Dormand-Prince run: end of an attempt (slider's last stage, error,
+// decision, next step) and the commit of an accepted state.
+hipError_t launch_dp_control(const TickArgs& tick, DpCtrl* ctrl, const double* errpart, int ntask, hipStream_t st);
+template <typename T>
+hipError_t launch_dp_commit(const T* y5, T* m, int nfilm, size_t plane, const DpCtrl* ctrl, int* flags,
+                            hipStream_t st);
 // The row kernel can transform rows of this length in place.
 bool row_inplace_length(int L);
 size_t row_fwd_lds_bytes(int N2x, int esz);

@@ -19,6 +19,7 @@
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <algorithm>
 #include "mmv_device.h"
 #include "mmv_kernels.h"
 #include "mmv_kernel_fn.h"
@@ -279,6 +280,92 @@ __device__ __forceinline__ void col_body(int blk, const cpx<T>* __restrict__ spe
 
 __device__ void rigid_stage(RigidState* R, const DriveP& d, int stage, double F, double h, double dxc, int travel);
 
+// ------------------------------------------------------------ Dormand-Prince pair
+// Nodes, stage coefficients (row i, j < i), fifth-order weights (the last
+// row) and embedded fourth-order weights of the Dormand-Prince RK5(4) pair
+// (Dormand & Prince, J. Comput. Appl. Math. 6, 19, 1980).
+__device__ __forceinline__ double dp_c(int i) {
+  switch (i) {
+    case 1: return 1.0 / 5.0;
+    case 2: return 3.0 / 10.0;
+    case 3: return 4.0 / 5.0;
+    case 4: return 8.0 / 9.0;
+    case 5: case 6: return 1.0;
+    default: return 0.0;
+  }
+}
+
+__device__ __forceinline__ double dp_a(int i, int j) {
+  switch (i * 8 + j) {
+    case 8 + 0: return 1.0 / 5.0;
+    case 16 + 0: return 3.0 / 40.0;
+    case 16 + 1: return 9.0 / 40.0;
+    case 24 + 0: return 44.0 / 45.0;
+    case 24 + 1: return -56.0 / 15.0;
+    case 24 + 2: return 32.0 / 9.0;
+    case 32 + 0: return 19372.0 / 6561.0;
+    case 32 + 1: return -25360.0 / 2187.0;
+    case 32 + 2: return 64448.0 / 6561.0;
+    case 32 + 3: return -212.0 / 729.0;
+    case 40 + 0: return 9017.0 / 3168.0;
+    case 40 + 1: return -355.0 / 33.0;
+    case 40 + 2: return 46732.0 / 5247.0;
+    case 40 + 3: return 49.0 / 176.0;
+    case 40 + 4: return -5103.0 / 18656.0;
+    case 48 + 0: return 35.0 / 384.0;
+    case 48 + 2: return 500.0 / 1113.0;
+    case 48 + 3: return 125.0 / 192.0;
+    case 48 + 4: return -2187.0 / 6784.0;
+    case 48 + 5: return 11.0 / 84.0;
+    default: return 0.0;
+  }
+}
+
+// Error weights: fifth-order minus embedded fourth-order weights.
+__device__ __forceinline__ double dp_e(int j) {
+  const double b5 = j < 6 ? dp_a(6, j) : 0.0;
+  double b4 = 0.0;
+  switch (j) {
+    case 0: b4 = 5179.0 / 57600.0; break;
+    case 2: b4 = 7571.0 / 16695.0; break;
+    case 3: b4 = 393.0 / 640.0; break;
+    case 4: b4 = -92097.0 / 339200.0; break;
+    case 5: b4 = 187.0 / 2100.0; break;
+    case 6: b4 = 1.0 / 40.0; break;
+    default: break;
+  }
+  return b5 - b4;
+}
+
+// The slider's Dormand-Prince stage: its derivative at the stage state
+// (Eq. 15) is kept, and the next stage's state x_n + h sum_j a_(i+1)j k_j
+// (stages 0..5) formed.  At stage 6 the state stays (it is the fifth-order
+// solution); the step control decides.
+__device__ void rigid_stage_dp(RigidState* R, const DriveP& d, int stage, double F, double h) {
+  const double x = R->xs, v = R->vs, t = R->ts;
+  double dxdt = 0.0, dvdt = 0.0;
+  if (d.mode == 1) {
+    dxdt = d.v_d;
+  } else if (d.mode == 2) {
+    dxdt = v;
+    dvdt = (d.k * (d.v_d * t + d.xa0 - x) - d.gamma_v * d.mass * v + F) / d.mass;
+  }
+  R->F[0] = F;
+  R->kx[stage] = dxdt;
+  R->kv[stage] = dvdt;
+  if (stage < 6) {
+    double sx = 0.0, sv = 0.0;
+    for (int j = 0; j <= stage; ++j) {
+      const double a = dp_a(stage + 1, j);
+      sx += a * R->kx[j];
+      sv += a * R->kv[j];
+    }
+    R->xs = R->x0 + h * sx;
+    R->vs = R->v0 + h * sv;
+    R->ts = R->t0 + dp_c(stage + 1) * h;
+  }
+}
+
 // Slider stage update from a finished row launch's force partials, by one
 // whole block: fixed-order float64 sum (strided per thread, then per wave,
 // then over the waves), then Eq. 15's RK4 stage.
@@ -292,7 +379,10 @@ __device__ __forceinline__ void tick_body(const TickArgs& a, int stage, double d
   if (threadIdx.x == 0) {
     double F = 0.0;
     for (int w = 0; w < (TICK_THREADS + 63) >> 6; ++w) F += s_red[w];
-    rigid_stage(a.rigid, a.drive, stage, a.force_scale * F, dt, a.dx, a.travel);
+    if (a.scheme == 1)
+      rigid_stage_dp(a.rigid, a.drive, stage, a.force_scale * F, a.ctrl->h);
+    else
+      rigid_stage(a.rigid, a.drive, stage, a.force_scale * F, dt, a.dx, a.travel);
   }
   lds_barrier();
 }
@@ -302,6 +392,7 @@ __global__ void __launch_bounds__(COL_THREADS)
     k_col(const cpx<T>* __restrict__ spec1, cpx<T>* __restrict__ spec2, const T* __restrict__ kern,
           int Kx, int Ly, int Kyh, int ny, int nin_ch, int ngroup, int nbuf, FftPlan P,
           const cpx<T>* __restrict__ twy, OutTable tab, TickArgs tick, int tick_stage, double tick_dt) {
+  if (tick.ctrl != nullptr && tick.ctrl->done) return;  // adaptive run finished
   if (tick_stage >= 0 && blockIdx.x == 0) tick_body(tick, tick_stage, tick_dt);
   col_body<T>(xcd_remap(blockIdx.x, gridDim.x), spec1, spec2, kern, Kx, Ly, Kyh, ny, nin_ch, ngroup, nbuf, P, twy,
               tab);
@@ -311,6 +402,103 @@ __global__ void __launch_bounds__(TICK_THREADS) k_tick(TickArgs tick, int stage,
 
 __global__ void __launch_bounds__(TICK_THREADS) k_tick_batch(const ColDesc* __restrict__ d, int stage, double dt) {
   tick_body(d[blockIdx.x].tick, stage, dt);
+}
+
+// End of a Dormand-Prince attempt (one block): the slider's last stage from
+// the last row launch's force partials, the error ratio over the cells'
+// block maxima and the slider's position and velocity errors, the decision
+// and the next step size.  An accepted step takes the fifth-order state,
+// advances t and re-seats s_int; the commit kernel then renormalises m.
+constexpr double DP_END_REL = 1e-9;  // t_end reached when t_end - t <= DP_END_REL * t_end
+
+__global__ void __launch_bounds__(TICK_THREADS)
+    k_dp_control(TickArgs a, DpCtrl* ctrl, const double* __restrict__ errpart, int ntask) {
+  __shared__ double s_max[16];
+  if (ctrl->done) {
+    if (threadIdx.x == 0) ctrl->accept = 0;
+    return;
+  }
+  tick_body(a, 6, 0.0);
+  double m = 0.0;
+  for (int t = threadIdx.x; t < ntask; t += TICK_THREADS) m = (errpart[t] > m || errpart[t] != errpart[t]) ? errpart[t] : m;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double q = __shfl_down(m, o, 64);
+    m = (q > m || q != q) ? q : m;
+  }
+  if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = m;
+  lds_barrier();
+  if (threadIdx.x != 0) return;
+  for (int w = 1; w < TICK_THREADS / 64; ++w) m = (s_max[w] > m || s_max[w] != s_max[w]) ? s_max[w] : m;
+  m = (s_max[0] > m || s_max[0] != s_max[0]) ? s_max[0] : m;
+  RigidState* R = a.rigid;
+  const double h = ctrl->h;
+  double ex = 0.0, ev = 0.0;
+  for (int j = 0; j < 7; ++j) {
+    ex += dp_e(j) * R->kx[j];
+    ev += dp_e(j) * R->kv[j];
+  }
+  ex *= h;
+  ev *= h;
+  const double err = fmax(m, fmax(fabs(ex) / a.dx, fabs(ev) * h / a.dx));
+  const double ratio = (m != m) ? m : err / ctrl->tol;
+  const bool ok = ratio <= 1.0;
+  double fac = ratio == 0.0 ? 5.0 : fmin(5.0, fmax(0.2, 0.9 * pow(ratio, -0.2)));
+  if (!ok) fac = fmin(fac, 1.0);
+  double hn = h * fac;
+  if (ok) {
+    R->x0 = R->xs;
+    R->v0 = R->vs;
+    R->t0 = R->t0 + h;
+    R->step += 1;
+    ctrl->accepted += 1;
+    if (isfinite(R->x0)) {
+      const double sc = floor(R->x0 / a.dx);
+      if (fabs(sc) > (double)a.travel)
+        R->flags |= FLAG_RANGE;
+      else
+        R->s_int = (int)sc;
+    } else {
+      R->flags |= FLAG_NUMERIC;
+    }
+    if (ctrl->t_end - R->t0 <= DP_END_REL * ctrl->t_end) {
+      R->t0 = ctrl->t_end;
+      ctrl->done = 1;
+    }
+  } else {
+    ctrl->rejected += 1;
+  }
+  R->xs = R->x0;
+  R->vs = R->v0;
+  R->ts = R->t0;
+  if (!ctrl->done) hn = fmin(hn, ctrl->t_end - R->t0);
+  if (!isfinite(ratio) || !(hn > 0.0)) {
+    // non-finite error or no step left: stop the run
+    R->flags |= FLAG_NUMERIC;
+    ctrl->done = 1;
+  }
+  ctrl->err = ratio;
+  ctrl->accept = ok ? 1 : 0;
+  ctrl->h = hn;
+}
+
+// Accepted attempt: m = the fifth-order state renormalised (y5 and m are
+// [film][3][plane]).
+template <typename T>
+__global__ void k_dp_commit(const T* __restrict__ y5, T* __restrict__ m, int nfilm, size_t plane,
+                            const DpCtrl* __restrict__ ctrl, int* __restrict__ flags) {
+  if (!ctrl->accept) return;
+  const size_t n = (size_t)nfilm * plane;
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x) {
+    const size_t f = q / plane, i = q - f * plane;
+    const size_t o = f * 3 * plane + i;
+    const T x = y5[o], y = y5[o + plane], z = y5[o + 2 * plane];
+    const T nrm = sqrt(x * x + y * y + z * z);
+    if (!(nrm > T(0)) || !isfinite(nrm)) atomicOr(flags, (int)FLAG_NUMERIC);
+    m[o] = x / nrm;
+    m[o + plane] = y / nrm;
+    m[o + 2 * plane] = z / nrm;
+  }
 }
 
 template <typename T>
@@ -635,6 +823,8 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
 
   // slider offset of this stage (issued first; the slider state is written
   // only after every block of the launch has read it)
+  if (p.scheme == 1 && p.ctrl->done) return;  // adaptive run finished
+  if (p.scheme == 1) dt = p.ctrl->h;
   const double xs = rigid->xs;
   const int s_int = rigid->s_int;
   // twiddles (stw: N2x, stp: N2x + 1, contiguous): loads issued before the
@@ -949,6 +1139,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   const T gam = (T)p.gam, alp = (T)p.alpha;
   const T hdt = (T)dt;
   bool bad = false;
+  double errmax = 0.0;  // Dormand-Prince last stage: largest |error| of m
   // fused x transform of the new row: real rows packed in fa (Lx reals each)
   const bool fuse = p.spec1_out != nullptr && p.mode == MODE_STAGE && cell_row;
   T* fr = reinterpret_cast<T*>(fa);
@@ -1013,7 +1204,54 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
       const T kx = -gam * (cx + alp * dx_), ky = -gam * (cy + alp * dy_), kz = -gam * (cz + alp * dz_);
       const size_t fo = (size_t)film * 3 * plane + id;
       const T ox = m0[fo], oy = m0[fo + plane], oz = m0[fo + 2 * plane];
-      if (stage == 0) {
+      if (p.scheme == 1) {
+        // Dormand-Prince stage: keep k_stage; form the next stage's state
+        // m_n + h sum_j a_(stage+1)j k_j (j ascending), or at the last stage
+        // the error h sum_j e_j k_j
+        T* K = reinterpret_cast<T*>(p.kdp);
+        const size_t kst = (size_t)p.nfilm * 3 * plane;
+        K[stage * kst + fo] = kx;
+        K[stage * kst + fo + plane] = ky;
+        K[stage * kst + fo + 2 * plane] = kz;
+        if (stage < 6) {
+          T sx = 0, sy = 0, sz = 0;
+          for (int j = 0; j < stage; ++j) {
+            const T a = (T)dp_a(stage + 1, j);
+            if (a == T(0)) continue;
+            sx += a * K[j * kst + fo];
+            sy += a * K[j * kst + fo + plane];
+            sz += a * K[j * kst + fo + 2 * plane];
+          }
+          const T a = (T)dp_a(stage + 1, stage);
+          sx += a * kx;
+          sy += a * ky;
+          sz += a * kz;
+          const T nx_ = ox + hdt * sx, ny_ = oy + hdt * sy, nz_ = oz + hdt * sz;
+          mnext[fo] = nx_;
+          mnext[fo + plane] = ny_;
+          mnext[fo + 2 * plane] = nz_;
+          if (fuse) {
+            fr[i] = nx_;
+            fr[Lx + i] = ny_;
+            fr[2 * Lx + i] = nz_;
+          }
+        } else {
+          T ex = 0, ey = 0, ez = 0;
+          for (int j = 0; j < 6; ++j) {
+            const T e = (T)dp_e(j);
+            if (e == T(0)) continue;
+            ex += e * K[j * kst + fo];
+            ey += e * K[j * kst + fo + plane];
+            ez += e * K[j * kst + fo + 2 * plane];
+          }
+          const T e6 = (T)dp_e(6);
+          ex = hdt * (ex + e6 * kx);
+          ey = hdt * (ey + e6 * ky);
+          ez = hdt * (ez + e6 * kz);
+          const double en = sqrt((double)ex * ex + (double)ey * ey + (double)ez * ez);
+          errmax = (en > errmax || en != en) ? en : errmax;
+        }
+      } else if (stage == 0) {
         acc[fo] = kx;
         acc[fo + plane] = ky;
         acc[fo + 2 * plane] = kz;
@@ -1122,6 +1360,22 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   }
   lds_barrier();
   if (p.mode == MODE_EVAL) return;
+  if (p.mode == MODE_STAGE && p.scheme == 1 && stage == 6) {
+    // the block's largest error (a maximum: independent of order)
+    double e = errmax;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double q = __shfl_down(e, o, 64);
+      e = (q > e || q != q) ? q : e;
+    }
+    if (lane == 0) red[48 + wv] = e;
+    lds_barrier();
+    if (threadIdx.x == 0) {
+      double m = 0.0;
+      for (int w = 0; w < nw; ++w) m = (red[48 + w] > m || red[48 + w] != red[48 + w]) ? red[48 + w] : m;
+      p.errpart[task] = m;
+    }
+  }
   if (p.mode == MODE_STAGE && p.defer_tick) {
     // partials only; the slider update runs after this launch
     if (threadIdx.x == 0) {
@@ -1327,6 +1581,20 @@ hipError_t launch_tick(const TickArgs& tick, int stage, double dt, hipStream_t s
   return hipGetLastError();
 }
 
+hipError_t launch_dp_control(const TickArgs& tick, DpCtrl* ctrl, const double* errpart, int ntask, hipStream_t st) {
+  hipLaunchKernelGGL(k_dp_control, dim3(1), dim3(TICK_THREADS), 0, st, tick, ctrl, errpart, ntask);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dp_commit(const T* y5, T* m, int nfilm, size_t plane, const DpCtrl* ctrl, int* flags,
+                            hipStream_t st) {
+  const size_t n = (size_t)nfilm * plane;
+  const int nb = (int)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_dp_commit<T>, dim3(nb), dim3(256), 0, st, y5, m, nfilm, plane, ctrl, flags);
+  return hipGetLastError();
+}
+
 hipError_t launch_tick_batch(const ColDesc* d, int n, int stage, double dt, hipStream_t st) {
   hipLaunchKernelGGL(k_tick_batch, dim3(n), dim3(TICK_THREADS), 0, st, d, stage, dt);
   return hipGetLastError();
@@ -1443,7 +1711,8 @@ hipError_t launch_colpack(const void* spec, T* out, int Kx, int Ly, int Kyh, con
   template hipError_t launch_row_fwd_batch<T>(const RowFwdDesc*, const int*, int, int, size_t, hipStream_t);      \
   template hipError_t launch_col_batch<T>(const ColDesc*, const int*, int, int, size_t, hipStream_t, int, double);             \
   template hipError_t launch_row_stage_batch<T>(const RowStageDesc*, const int*, int, int, size_t, int, double,   \
-                                                bool, hipStream_t);
+                                                bool, hipStream_t);                                             \
+  template hipError_t launch_dp_commit<T>(const T*, T*, int, size_t, const DpCtrl*, int*, hipStream_t);
 
 MMV_INST(float)
 MMV_INST(double)
