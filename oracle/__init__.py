@@ -21,6 +21,8 @@ framework") step by step:
                        diagnostics incl. P_diss Eq. (4)
   dormand_prince.py    adaptive Dormand-Prince RK5(4) of the same system
                        (the paper's RK45 solver, Sec. III)
+  periodic.py          periodic in-plane boundaries: image-summed kernels,
+                       periodic windows (halo copies), periodic exchange
   fno.py               learned stray-field operator (Fourier neural
                        operator standing in for the cross term), float64
                        torch with autograd gradients
@@ -29,7 +31,8 @@ Parity status of each function is stated in its docstring; functions with
 no independent pin say "parity unpinned".
 """
 from .constants import MU0, GAMMA_E, GAMMA0
-from . import newell, potential_kernel, convolution, spline, fields, llg, sim, fno, dormand_prince
+from . import newell, potential_kernel, convolution, spline, fields, llg, sim, fno, dormand_prince, periodic
 
 __all__ = ["MU0", "GAMMA_E", "GAMMA0", "newell", "potential_kernel",
-           "convolution", "spline", "fields", "llg", "sim", "fno", "dormand_prince"]
+           "convolution", "spline", "fields", "llg", "sim", "fno", "dormand_prince",
+           "periodic"]

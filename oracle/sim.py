@@ -90,6 +90,10 @@ class System:
 
     def self_op(self):
         d = self.desc
+        if d.pbc:
+            from .periodic import BoxWindow
+            assert d.nz == 1, "periodic boundaries: films one cell thick"
+            return self._op(("self",), lambda: BoxWindow(d, (0, d.nx, 0, d.ny, 0, 1)))
         return self._op(("self",), lambda: demag_window(
             d, (0, d.nx, 0, d.ny, 0, d.nz)))
 
@@ -109,6 +113,12 @@ class System:
     def cross_op(self, direction, s_int):
         d = self.desc
         box = self.cross_box(direction, s_int)
+        if d.pbc:
+            # periodic films: the window is the periodic field, its halo the
+            # copy from the other side (direct mode only)
+            from .periodic import BoxWindow
+            assert d.cross_mode == 0, "periodic boundaries: direct mode only"
+            return self._op(("cross", direction, s_int, 0), lambda: BoxWindow(d, box))
         maker = (lambda: demag_window(d, box)) if d.cross_mode == 0 else (
             lambda: potential_window(d, box))
         return self._op(("cross", direction, s_int, d.cross_mode), maker)
@@ -197,8 +207,13 @@ class System:
         op = self.self_op()
         out = []
         for m in m_list:
+            if d.pbc:
+                from .periodic import exchange_periodic
+                ex = exchange_periodic(d, m)
+            else:
+                ex = _fields.exchange(d, m)
             out.append({
-                "exchange": _fields.exchange(d, m),
+                "exchange": ex,
                 "anisotropy": _fields.anisotropy(d, m),
                 "zeeman": _fields.zeeman(d, m),
                 "demag_self": op(m),
