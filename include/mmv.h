@@ -82,6 +82,18 @@ typedef struct {
   int sor_sweeps;       /* eddy SOR sweeps per step (0: library default)      */
   double sor_omega;     /* eddy SOR factor (0: 2/(1+sin(pi/n_max)))           */
   int fft_lx, fft_ly, fft_lz; /* FFT lengths; 0 = smallest admissible       */
+  int pbc;              /* periodic in-plane axes (Sec. III.A end, Sec. IV.B):
+                           bit 0 = x, bit 1 = y; 0 = open.  Film meshes
+                           (nz == 1) in the direct mode without eddy
+                           currents.  Along a periodic axis the transform
+                           length is the period (nx even and {2,3,5,7}-smooth,
+                           ny {2,3,5,7}-smooth), the kernel of a displacement
+                           is summed over its minimum image and pbc_images
+                           repetitions of the period on each side, the
+                           spline window's halo is the copy from the other
+                           side, exchange wraps, and along x the slider may
+                           travel without bound (max_travel_cells unused)  */
+  int pbc_images;       /* repetitions summed on each side (0..1024)          */
 } mmv_mesh_desc;
 
 typedef struct {

@@ -51,7 +51,8 @@ class MeshDesc(ctypes.Structure):
                 ("cross_mode", ctypes.c_int), ("halo", ctypes.c_int),
                 ("rc_cells", ctypes.c_double), ("sor_sweeps", ctypes.c_int),
                 ("sor_omega", ctypes.c_double), ("fft_lx", ctypes.c_int),
-                ("fft_ly", ctypes.c_int), ("fft_lz", ctypes.c_int)]
+                ("fft_ly", ctypes.c_int), ("fft_lz", ctypes.c_int),
+                ("pbc", ctypes.c_int), ("pbc_images", ctypes.c_int)]
 
 
 class DriveDesc(ctypes.Structure):
@@ -151,7 +152,7 @@ def to_desc(desc):
         if name in ("u", "Hext"):
             arr = (ctypes.c_double * 3)(*[float(v) for v in getattr(desc, name)])
             setattr(c, name, arr)
-        elif name in ("fft_lx", "fft_ly", "fft_lz"):
+        elif name in ("fft_lx", "fft_ly", "fft_lz", "pbc", "pbc_images"):
             setattr(c, name, int(getattr(desc, name, 0)))
         else:
             setattr(c, name, getattr(desc, name))

@@ -206,6 +206,18 @@ int validate(const mmv_mesh_desc* d) {
   if (d->n_films == 2 && (d->halo < 2 || d->halo > 64)) return fail(MMV_EINVAL, "halo must be in [2, 64]");
   if (!pos(d->rc_cells)) return fail(MMV_EINVAL, "rc_cells must be finite and > 0");
   if (d->fft_lx < 0 || d->fft_ly < 0 || d->fft_lz < 0) return fail(MMV_EINVAL, "FFT lengths must be >= 0");
+  if (d->pbc < 0 || d->pbc > 3) return fail(MMV_EINVAL, "pbc must be 0..3 (bit 0 = x, bit 1 = y)");
+  if (d->pbc_images < 0 || d->pbc_images > 1024) return fail(MMV_EINVAL, "pbc_images must be in [0, 1024]");
+  if (d->pbc) {
+    if (d->nz != 1) return fail(MMV_EINVAL, "pbc: periodic boundaries need films one cell thick (nz == 1)");
+    if (d->cross_mode != 0) return fail(MMV_EINVAL, "pbc: periodic boundaries run in the direct mode (cross_mode 0)");
+    if ((d->pbc & 1) && (d->nx % 2 || !smooth2357(d->nx)))
+      return fail(MMV_EINVAL, "pbc: a periodic x needs nx even and {2,3,5,7}-smooth (the transform length)");
+    if ((d->pbc & 2) && !smooth2357(d->ny))
+      return fail(MMV_EINVAL, "pbc: a periodic y needs ny {2,3,5,7}-smooth (the transform length)");
+    if (((d->pbc & 1) && d->fft_lx && d->fft_lx != d->nx) || ((d->pbc & 2) && d->fft_ly && d->fft_ly != d->ny))
+      return fail(MMV_EINVAL, "pbc: the transform length of a periodic axis is its period (fft_lx/fft_ly 0 or n)");
+  }
   return MMV_OK;
 }
 
@@ -395,7 +407,7 @@ int build_kernels(mmv_mesh* h) {
   hipError_t err = hipSuccess;
   for (const Job& j : jobs) {
     err = launch_kernel_real((double*)tmp, h->Lx, h->Ly, j.kind, j.comp, j.dzc, d.dx, d.dy, d.dz, d.rc_cells,
-                             j.kind == 0 ? -scale : scale, h->st);
+                             j.kind == 0 ? -scale : scale, d.pbc, d.pbc_images, h->st);
     if (err != hipSuccess) break;
     err = launch_row_fwd<double>((const double*)tmp, tspec, h->Ly, h->Lx, h->N2x, h->Kx, h->px, twxd, twpd, h->st);
     if (err != hipSuccess) break;
@@ -484,7 +496,9 @@ int init_typed(mmv_mesh* h) {
     rp->Kx = h->Kx;
     rp->halo = d.halo;
     rp->M = h->M;
-    rp->travel = d.max_travel_cells;
+    // a periodic x lets the slider travel without bound
+    rp->travel = (d.pbc & 1) ? (1 << 30) : d.max_travel_cells;
+    rp->pbc = d.pbc;
     rp->dx = d.dx;
     rp->dy = d.dy;
     rp->dz = d.dz;
@@ -1497,7 +1511,8 @@ int batch_autotune(mmv_batch* b) {
 bool same_kernel(const mmv_mesh_desc& a, const mmv_mesh_desc& c) {
   return a.nx == c.nx && a.ny == c.ny && a.dx == c.dx && a.dy == c.dy && a.dz == c.dz && a.gap_cells == c.gap_cells &&
          a.Ms == c.Ms && a.rc_cells == c.rc_cells && a.cross_mode == c.cross_mode && a.halo == c.halo &&
-         a.max_travel_cells == c.max_travel_cells && a.fft_lx == c.fft_lx && a.fft_ly == c.fft_ly;
+         a.max_travel_cells == c.max_travel_cells && a.fft_lx == c.fft_lx && a.fft_ly == c.fft_ly &&
+         a.pbc == c.pbc && a.pbc_images == c.pbc_images;
 }
 
 void batch_free(mmv_batch* b) {
@@ -1573,8 +1588,11 @@ int init_mesh(const mmv_mesh_desc* d, void* hip_stream, mmv_handle* out) {
   }
   const int hx = d->n_films == 2 ? d->halo : 0;
   const int T = d->n_films == 2 ? d->max_travel_cells : 0;
-  const int lx_min = d->n_films == 2 ? 2 * (d->nx + hx + T) : 2 * d->nx;
-  const int ly_min = d->n_films == 2 ? 2 * (d->ny + (d->cross_mode == 1 ? 3 : 1)) : 2 * d->ny;
+  int lx_min = d->n_films == 2 ? 2 * (d->nx + hx + T) : 2 * d->nx;
+  int ly_min = d->n_films == 2 ? 2 * (d->ny + (d->cross_mode == 1 ? 3 : 1)) : 2 * d->ny;
+  // a periodic axis is transformed over one period
+  if (d->pbc & 1) lx_min = d->nx;
+  if (d->pbc & 2) ly_min = d->ny;
   if (d->fft_lx) {
     if (d->fft_lx < lx_min || d->fft_lx % 2 || !smooth2357(d->fft_lx)) {
       delete h;
@@ -1582,7 +1600,7 @@ int init_mesh(const mmv_mesh_desc* d, void* hip_stream, mmv_handle* out) {
     }
     h->Lx = d->fft_lx;
   } else {
-    h->Lx = next_smooth(lx_min, true);
+    h->Lx = (d->pbc & 1) ? d->nx : next_smooth(lx_min, true);
   }
   if (d->fft_ly) {
     if (d->fft_ly < ly_min || !smooth2357(d->fft_ly)) {
@@ -1591,7 +1609,7 @@ int init_mesh(const mmv_mesh_desc* d, void* hip_stream, mmv_handle* out) {
     }
     h->Ly = d->fft_ly;
   } else {
-    h->Ly = next_smooth(ly_min, false);
+    h->Ly = (d->pbc & 2) ? d->ny : next_smooth(ly_min, false);
   }
   h->N2x = h->Lx / 2;
   h->Kx = h->N2x + 1;
@@ -1823,7 +1841,7 @@ int set_offset(mmv_handle h, double x_cells) {
   if (h->nfilm != 2) return fail(MMV_ESTATE, "set_offset needs two films");
   if (!isfinite(x_cells)) return fail(MMV_EINVAL, "offset must be finite");
   const double s = floor(x_cells);
-  if (fabs(s) > h->d.max_travel_cells)
+  if (fabs(s) > h->rp_hot.travel)
     return fail(MMV_ERANGE, "offset outside the window sized by max_travel_cells");
   RigidState r;
   if ((rc = read_rigid(h, r))) return rc;
@@ -1844,7 +1862,7 @@ int set_drive(mmv_handle h, const mmv_drive* drv) {
       !isfinite(drv->x0) || !isfinite(drv->v0))
     return fail(MMV_EINVAL, "drive parameters must be finite");
   const double s = floor(drv->x0 / h->d.dx);
-  if (fabs(s) > h->d.max_travel_cells) return fail(MMV_ERANGE, "x0 outside the window sized by max_travel_cells");
+  if (fabs(s) > h->rp_hot.travel) return fail(MMV_ERANGE, "x0 outside the window sized by max_travel_cells");
   RigidState r;
   if ((rc = read_rigid(h, r))) return rc;
   r.x0 = r.xs = drv->x0;

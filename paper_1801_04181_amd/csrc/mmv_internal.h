@@ -144,6 +144,9 @@ struct RowParams {
   void* kdp;
   double* errpart;
   const DpCtrl* ctrl;
+  // periodic in-plane axes (bit 0 = x, 1 = y): exchange wraps, and along y
+  // the force's rows -1 and ny are the rows ny-1 and 0
+  int pbc;
 };
 
 // Per-instance descriptors of the batched launches (device memory).

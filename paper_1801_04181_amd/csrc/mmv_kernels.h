@@ -21,7 +21,7 @@ hipError_t launch_row_stage(const RowParams& p, const void* spec2, const T* mst,
                             T* hout, const void* tw, const void* twp, RigidState* rigid, double* partial,
                             unsigned* counter, hipStream_t st);
 hipError_t launch_kernel_real(double* out, int Lx, int Ly, int kind, int comp, double dzc, double dx, double dy,
-                              double dz, double rc, double scale, hipStream_t st);
+                              double dz, double rc, double scale, int pbc, int images, hipStream_t st);
 template <typename T>
 hipError_t launch_colpack(const void* spec, T* out, int Kx, int Ly, int Kyh, const FftPlan& P, const void* twy,
                           int imag, hipStream_t st);

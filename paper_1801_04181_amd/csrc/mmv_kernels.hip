@@ -771,13 +771,16 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   }
   const bool cell_row = (y >= 0 && y < ny);
   const bool two = (p.nfilm == 2);
-  const bool need_force =
-      two && film == 1 && ((p.mode == MODE_STAGE && p.with_force) || p.mode == MODE_FORCE);
+  // periodic y: the rows -1 and ny are rows of the film, summed by parts
+  // with wrapped neighbours; the tasks outside the film add nothing
+  const bool pbc_y = (p.pbc & 2) != 0, pbc_x = (p.pbc & 1) != 0;
+  const bool need_force = two && film == 1 && (cell_row || !pbc_y) &&
+                          ((p.mode == MODE_STAGE && p.with_force) || p.mode == MODE_FORCE);
   const bool ext_cross = two && film == 0 && p.hsur != nullptr;
   const bool need_cross = two && !ext_cross && ((p.term_mask & 16) || need_force);
   // boundary force rows carried by this task (direct mode, stage launches)
-  const bool xb_lo = p.mode == MODE_STAGE && need_force && !p.pot && y == 0;
-  const bool xb_hi = p.mode == MODE_STAGE && need_force && !p.pot && y == ny - 1;
+  const bool xb_lo = p.mode == MODE_STAGE && need_force && !p.pot && !pbc_y && y == 0;
+  const bool xb_hi = p.mode == MODE_STAGE && need_force && !p.pot && !pbc_y && y == ny - 1;
   // direct-mode stage launches: the force's z_s - 1 layer row of slider row y
   // is transformed and filtered by the base-film task of row y, which adds
   // that part of the z term (seven rows per task on both films)
@@ -1157,26 +1160,28 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
       T hx = H[i], hy = H[nx + i], hz = H[2 * nx + i];
       if (p.term_mask & 1) {
         T ex = 0, ey = 0, ez = 0;
-        if (i > 0) {
-          ex += (ms[id - 1] - mx) * idx2;
-          ey += (ms[plane + id - 1] - my) * idx2;
-          ez += (ms[2 * plane + id - 1] - mz) * idx2;
-        }
-        if (i < nx - 1) {
-          ex += (ms[id + 1] - mx) * idx2;
-          ey += (ms[plane + id + 1] - my) * idx2;
-          ez += (ms[2 * plane + id + 1] - mz) * idx2;
-        }
-        if (y > 0) {
-          ex += (ms[id - nx] - mx) * idy2;
-          ey += (ms[plane + id - nx] - my) * idy2;
-          ez += (ms[2 * plane + id - nx] - mz) * idy2;
-        }
-        if (y < ny - 1) {
-          ex += (ms[id + nx] - mx) * idy2;
-          ey += (ms[plane + id + nx] - my) * idy2;
-          ez += (ms[2 * plane + id + nx] - mz) * idy2;
-        }
+        // neighbours (free boundaries, or wrapped along a periodic axis)
+        auto nb = [&](size_t q, T w) {
+          ex += (ms[q] - mx) * w;
+          ey += (ms[plane + q] - my) * w;
+          ez += (ms[2 * plane + q] - mz) * w;
+        };
+        if (i > 0)
+          nb(id - 1, idx2);
+        else if (pbc_x && nx > 1)
+          nb(id + nx - 1, idx2);
+        if (i < nx - 1)
+          nb(id + 1, idx2);
+        else if (pbc_x && nx > 1)
+          nb(id + 1 - nx, idx2);
+        if (y > 0)
+          nb(id - nx, idy2);
+        else if (pbc_y && ny > 1)
+          nb(id + plane - nx, idy2);
+        if (y < ny - 1)
+          nb(id + nx, idy2);
+        else if (pbc_y && ny > 1)
+          nb(id + nx - plane, idy2);
         hx += pex * ex;
         hy += pex * ey;
         hz += pex * ez;
@@ -1319,10 +1324,12 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     // Eq. (3), component a: sum_i m_x d_x G_a + m_y d_y G_a + m_z d_z G_a,
     // the y term summed by parts over rows -1..ny.
     const double i2dx = 1.0 / (2.0 * p.dx), i2dy = 1.0 / (2.0 * p.dy), i2dz = 1.0 / (2.0 * p.dz);
+    // neighbouring rows of m_y (wrapped along a periodic y: no boundary rows)
+    const int yl = pbc_y ? (y - 1 + ny) % ny : y - 1, yh = pbc_y ? (y + 1) % ny : y + 1;
 #pragma unroll 1
     for (int i = threadIdx.x; i < nx; i += NT) {
-      const double myl = (y - 1 >= 0 && y - 1 < ny) ? (double)ms[plane + (size_t)(y - 1) * nx + i] : 0.0;
-      const double myh = (y + 1 >= 0 && y + 1 < ny) ? (double)ms[plane + (size_t)(y + 1) * nx + i] : 0.0;
+      const double myl = (yl >= 0 && yl < ny) ? (double)ms[plane + (size_t)yl * nx + i] : 0.0;
+      const double myh = (yh >= 0 && yh < ny) ? (double)ms[plane + (size_t)yh * nx + i] : 0.0;
       double mx = 0, mz = 0;
       if (cell_row) {
         mx = ms[(size_t)y * nx + i];
@@ -1458,8 +1465,11 @@ __global__ void __launch_bounds__((RowThreads<T, true>::n)) k_row_stage_batch(co
 // displacement index r maps to r (r <= L/2) or r - L; odd components are
 // zeroed on the Nyquist index of an even length so that every spectrum is
 // purely real or imaginary.
+// Periodic axes (pbc bit 0 = x, 1 = y; the transform length is then the
+// period): the displacement on the cyclic grid is its minimum image, and the
+// kernel is summed over `images` repetitions of the period on each side.
 __global__ void k_kernel_real(double* __restrict__ out, int Lx, int Ly, int kind, int comp, double dzc,
-                              double dx, double dy, double dz, double rc, double scale) {
+                              double dx, double dy, double dz, double rc, double scale, int pbc, int images) {
   const int ry = blockIdx.y;
   if (ry >= Ly) return;
   for (int rx = blockIdx.x * blockDim.x + threadIdx.x; rx < Lx; rx += gridDim.x * blockDim.x) {
@@ -1471,7 +1481,11 @@ __global__ void k_kernel_real(double* __restrict__ out, int Lx, int Ly, int kind
     const int px[6] = {0, 0, 0, 1, 1, 0}, py[6] = {0, 0, 0, 1, 0, 1};
     oddx = px[comp];
     oddy = py[comp];
-    v = tensor_comp(comp, ix * dx, iy * dy, dzc * dz, dx, dy, dz, rc);
+    const int qx = (pbc & 1) ? images : 0, qy = (pbc & 2) ? images : 0;
+    v = 0.0;
+    for (int a = -qx; a <= qx; ++a)
+      for (int b = -qy; b <= qy; ++b)
+        v += tensor_comp(comp, (ix + a * Lx) * dx, (iy + b * Ly) * dy, dzc * dz, dx, dy, dz, rc);
   } else {
     oddx = (comp == 0);
     oddy = (comp == 1);
@@ -1678,9 +1692,10 @@ bool row_inplace_length(int L) { return inplace_length(L); }
 size_t row_fwd_lds_bytes(int N2x, int esz) { return (size_t)2 * esz * (8 * (size_t)N2x + 1); }
 
 hipError_t launch_kernel_real(double* out, int Lx, int Ly, int kind, int comp, double dzc, double dx, double dy,
-                              double dz, double rc, double scale, hipStream_t st) {
+                              double dz, double rc, double scale, int pbc, int images, hipStream_t st) {
   dim3 grid((Lx + 127) / 128, Ly);
-  hipLaunchKernelGGL(k_kernel_real, grid, dim3(128), 0, st, out, Lx, Ly, kind, comp, dzc, dx, dy, dz, rc, scale);
+  hipLaunchKernelGGL(k_kernel_real, grid, dim3(128), 0, st, out, Lx, Ly, kind, comp, dzc, dx, dy, dz, rc, scale,
+                     pbc, images);
   return hipGetLastError();
 }
 

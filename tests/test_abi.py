@@ -33,7 +33,7 @@ def test_library_exports_every_header_symbol():
 
 def test_struct_layout_matches_header():
     # offsets the C compiler assigns (x86-64 SysV): checked against ctypes
-    assert ctypes.sizeof(mmv.MeshDesc) == 192
+    assert ctypes.sizeof(mmv.MeshDesc) == 200
     assert ctypes.sizeof(mmv.DriveDesc) == 64
     assert ctypes.sizeof(mmv.SurDesc) == 64
 
@@ -53,6 +53,29 @@ def test_init_rejects_bad_descriptors(field, value, msg):
         mmv.init_mesh(c)
     assert e.value.code == -1
     assert msg in str(e.value)
+
+
+@pytest.mark.parametrize("change,msg", [
+    (dict(pbc=4), "pbc must be"), (dict(pbc=1, pbc_images=-1), "pbc_images"),
+    (dict(pbc=1, pbc_images=1025), "pbc_images"), (dict(pbc=1, nx=31), "nx even"),
+    (dict(pbc=2, ny=11), "ny {2,3,5,7}"), (dict(pbc=1, fft_lx=72), "period"),
+    (dict(pbc=1, gap_cells=3, cross_mode=1), "direct mode"),
+])
+def test_periodic_descriptor_validation(change, msg):
+    c = mmv.to_desc(get_config("tiny")["desc"])
+    for k, v in change.items():
+        setattr(c, k, v)
+    with pytest.raises(mmv.MMVError) as e:
+        mmv.init_mesh(c)
+    assert e.value.code == -1
+    assert msg in str(e.value)
+
+
+def test_periodic_needs_films():
+    d = get_config("cube_eddy")["desc"].replace(nx=8, ny=8, nz=8, pbc=1)
+    with pytest.raises(mmv.MMVError) as e:
+        mmv.init_mesh(d)
+    assert "one cell thick" in str(e.value)
 
 
 @pytest.mark.parametrize("gap", [0, 1, 2])
