@@ -337,6 +337,20 @@ int sur_attach(mmv_handle h, mmv_sur_handle s, int judge_every, double tol);
  * fallen back to the exact path, and how many judges ran.               */
 int sur_status(mmv_handle h, double* last_rel_err, int* fallback, long* judged);
 
+/* The operator inside batch_step for every instance of a batch (the
+ * surrogate + batched form): at every RK stage one batched inference over
+ * all instances (each instance's stage slider magnetisation and offset)
+ * replaces film 0's cross field, as sur_attach does for one mesh.  Every
+ * judge_every steps, before the step, the exact cross fields of all
+ * instances are computed and compared with the network's (relative L2 over
+ * the whole batch); above tol the whole batch falls back to the exact path
+ * until attached again.  Needs precision 32, cross_mode 0, every instance
+ * on the operator's grid (H = ny, W = nx) and at most max_batch instances.
+ * With the operator the batch's steps are launched without graph replay.
+ * s = NULL detaches.  Each judge blocks the host until its error is known. */
+int batch_sur_attach(mmv_batch_handle b, mmv_sur_handle s, int judge_every, double tol);
+int batch_sur_status(mmv_batch_handle b, double* last_rel_err, int* fallback, long* judged);
+
 /* Thread-local message for the most recent failing call ("" if none).   */
 const char* mmv_last_error(void);
 

@@ -13,7 +13,7 @@ __all__ = ["MMVError", "lib_path", "load", "MeshDesc", "DriveDesc", "init_mesh",
            "set_m", "get_m", "set_offset", "set_drive", "eval_heff", "llg_step", "llg_run_dp",
            "stray_force", "stray_force_noalloc", "get_state", "get_fft_lengths", "destroy_mesh",
            "profile_begin", "profile_end", "profile_repeat", "init_batch", "batch_instance", "batch_step",
-           "batch_tuning", "set_tune_cache", "destroy_batch", "Batch", "SurDesc", "sur_create", "sur_param_count",
+           "batch_tuning", "set_tune_cache", "destroy_batch", "Batch", "batch_sur_attach", "batch_sur_status", "SurDesc", "sur_create", "sur_param_count",
            "sur_param_offsets", "sur_set_params", "sur_get_params", "sur_forward", "sur_gradient",
            "sur_train_step", "sur_gemm_bf16", "sur_destroy", "sur_attach", "sur_status", "Surrogate",
            "last_error", "Mesh", "TERM", "EXPORTS"]
@@ -30,7 +30,8 @@ EXPORTS = ("init_mesh", "set_m", "get_m", "set_offset", "set_drive", "eval_heff"
            "get_fft_lengths", "profile_repeat", "init_batch", "batch_instance", "batch_step", "batch_tuning",
            "set_tune_cache", "destroy_batch", "destroy_mesh", "sur_create", "sur_param_count", "sur_param_offsets",
            "sur_set_params", "sur_get_params", "sur_forward", "sur_gradient", "sur_train_step",
-           "sur_gemm_bf16", "sur_destroy", "sur_attach", "sur_status", "mmv_last_error")
+           "sur_gemm_bf16", "sur_destroy", "sur_attach", "sur_status", "batch_sur_attach", "batch_sur_status",
+           "mmv_last_error")
 BATCH_AUTOTUNE, BATCH_GRAPH = 1, 2
 
 
@@ -116,6 +117,8 @@ def load():
         lib.sur_destroy.argtypes = [vp]
         lib.sur_attach.argtypes = [vp, vp, i, d]
         lib.sur_status.argtypes = [vp, pd, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_long)]
+        lib.batch_sur_attach.argtypes = [vp, vp, i, d]
+        lib.batch_sur_status.argtypes = [vp, pd, ctypes.POINTER(i), ctypes.POINTER(ctypes.c_long)]
         lib.mmv_last_error.restype = ctypes.c_char_p
         for name in EXPORTS[:-1]:
             getattr(lib, name).restype = ctypes.c_int
@@ -466,6 +469,16 @@ def sur_attach(h, s, judge_every=10, tol=1e-3):
 def sur_status(h):
     e, f, n = ctypes.c_double(), ctypes.c_int(), ctypes.c_long()
     _check(load().sur_status(h, ctypes.byref(e), ctypes.byref(f), ctypes.byref(n)))
+    return e.value, bool(f.value), n.value
+
+
+def batch_sur_attach(b, s, judge_every=10, tol=1e-3):
+    _check(load().batch_sur_attach(b, s, judge_every, tol))
+
+
+def batch_sur_status(b):
+    e, f, n = ctypes.c_double(), ctypes.c_int(), ctypes.c_long()
+    _check(load().batch_sur_status(b, ctypes.byref(e), ctypes.byref(f), ctypes.byref(n)))
     return e.value, bool(f.value), n.value
 
 

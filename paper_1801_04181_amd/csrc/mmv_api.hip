@@ -1088,6 +1088,15 @@ struct mmv_batch {
   // LDS, transform variant): small meshes are not held to the LDS of the
   // largest, so more of their blocks share a CU
   std::vector<BatchLaunch> l_fwd, l_col, l_stage;
+  // learned operator for every instance's film-0 cross field (not owned):
+  // one batched inference per RK stage over all instances
+  mmv_sur* sur = nullptr;
+  int sur_every = 10, sur_fallback = 0;
+  double sur_tol = 1e-3, sur_err = -1.0;
+  long sur_judged = 0, sur_steps = 0;
+  float* sur_in = nullptr;     // [n][4][ny][nx]
+  float* sur_exact = nullptr;  // [n][3][ny][nx]
+  bool built_sur = false;      // the descriptors read the operator's output
   std::vector<DriveP> drive_sig;  // drives the stage and tick descriptors were built for
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
@@ -1164,6 +1173,9 @@ int batch_build(mmv_batch* b) {
   std::vector<int> sf, sc, ss;
   std::vector<size_t> k_fwd(n), k_col(n);
   std::vector<std::pair<size_t, int>> k_stage(n);
+  const bool use_sur = b->sur != nullptr && !b->sur_fallback;
+  const float* sur_out = use_sur ? sur_output(b->sur) : nullptr;
+  b->built_sur = use_sur;
   b->drive_sig.assign(n, DriveP{});
   b->fuse = true;
   for (int i = 0; i < n; ++i) b->fuse = b->fuse && b->inst[i]->fuse_fwd;
@@ -1176,6 +1188,11 @@ int batch_build(mmv_batch* b) {
     T* b2 = (T*)h->mb[1];
     RowParams rp = stage_params(h, b->fuse);
     rp.nbr = batch_rows_per_transform<T>(rp, lds_limit);
+    if (use_sur) {
+      // film 0's cross field from the operator's output of this instance
+      rp.hsur = sur_out + (size_t)i * 3 * h->ny * h->nx;
+      rp.sur_scale = h->d.Ms;
+    }
     for (int s = 0; s < 4; ++s) {
       T* in = s == 0 ? m0 : (s == 1 ? b1 : (s == 2 ? b2 : b1));
       T* out = s == 0 ? b1 : (s == 1 ? b2 : (s == 2 ? b1 : m0));
@@ -1214,11 +1231,11 @@ int batch_build(mmv_batch* b) {
     c.ny = h->ny;
     c.nin_ch = 3 * h->nfilm;
     c.ngroup = h->ngroup;
-    const int per = (h->tab_hot.n + h->ngroup - 1) / h->ngroup;
+    const int per = ((use_sur ? h->tab_sur.n : h->tab_hot.n) + h->ngroup - 1) / h->ngroup;
     c.nbuf = c.nin_ch > per ? c.nin_ch : per;
     c.P = h->py;
     c.twy = h->twy;
-    c.tab = h->tab_hot;
+    c.tab = use_sur ? h->tab_sur : h->tab_hot;
     c.tick = tick_args(h, rp.ntask);
     k_fwd[i] = row_fwd_lds_bytes(h->N2x, sizeof(T));
     k_col[i] = col_lds_bytes<T>(h->Ly, c.nbuf);
@@ -1314,6 +1331,87 @@ int batch_col_launches(mmv_batch* b, hipStream_t st, int tick_stage, double dt) 
 }
 
 template <typename T>
+int eval_typed(mmv_mesh* h, int film, int mask, void* hout);
+
+// Inputs of the batched operator: each instance's slider magnetisation of
+// the stage and its offset x_s / dx.
+template <typename T>
+int batch_sur_inputs(mmv_batch* b, int stage, hipStream_t st) {
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    mmv_mesh* h = b->inst[i];
+    const T* in = stage == 0 ? (const T*)h->m0 : (stage == 2 ? (const T*)h->mb[1] : (const T*)h->mb[0]);
+    const size_t plane = (size_t)h->ny * h->nx;
+    HIPCHK(launch_sur_input((const float*)in + 3 * plane, h->rigid, 1.0 / h->d.dx, h->ny, h->nx,
+                            b->sur_in + i * 4 * plane, st));
+  }
+  return MMV_OK;
+}
+
+// Error judge of the batched operator at the step-start state: the exact
+// cross field of every instance against the network's, relative L2 over the
+// whole batch; above tol every instance falls back to the exact path.
+template <typename T>
+int batch_sur_judge(mmv_batch* b, hipStream_t st) {
+  const int n = (int)b->inst.size();
+  const size_t plane = (size_t)b->inst[0]->ny * b->inst[0]->nx;
+  for (int i = 0; i < n; ++i) {
+    int rc = eval_typed<T>(b->inst[i], 0, MMV_TERM_DEMAG_CROSS, b->sur_exact + (size_t)i * 3 * plane);
+    if (rc) return rc;
+  }
+  int rc = batch_sur_inputs<T>(b, 0, st);
+  if (rc) return rc;
+  const float* pred = nullptr;
+  if ((rc = sur_infer(b->sur, b->sur_in, n, st, &pred))) return rc;
+  double e = 0.0;
+  if ((rc = sur_rel_err(b->sur, pred, b->sur_exact, (long long)n * 3 * plane, b->inst[0]->d.Ms, st, &e)))
+    return rc;
+  b->sur_err = e;
+  b->sur_judged += 1;
+  if (!(e <= b->sur_tol)) b->sur_fallback = 1;
+  return MMV_OK;
+}
+
+// Steps with the operator: before each stage the pending slider stage is
+// applied (the network reads the stage offset), the operator runs once over
+// all instances, then the y pass without film 0's cross channels and the
+// row kernel reading the operator's output.
+template <typename T>
+int batch_sur_steps(mmv_batch* b, hipStream_t st, double dt, int nsteps, int* done) {
+  const int n = (int)b->inst.size();
+  int pending = -1;
+  *done = 0;
+  for (int k = 0; k < nsteps; ++k) {
+    if (b->sur_steps % b->sur_every == 0) {
+      if (pending >= 0) HIPCHK(launch_tick_batch(b->d_col_all, n, pending, dt, st));
+      pending = -1;
+      int rc = batch_sur_judge<T>(b, st);
+      if (rc) return rc;
+      if (b->sur_fallback) break;
+    }
+    for (int s = 0; s < 4; ++s) {
+      if (pending >= 0) HIPCHK(launch_tick_batch(b->d_col_all, n, pending, dt, st));
+      pending = -1;
+      int rc = batch_sur_inputs<T>(b, s, st);
+      if (rc) return rc;
+      const float* pred = nullptr;
+      if ((rc = sur_infer(b->sur, b->sur_in, n, st, &pred))) return rc;
+      if (!b->fuse || (k == 0 && s == 0))
+        for (const BatchLaunch& c : b->l_fwd)
+          HIPCHK(launch_row_fwd_batch<T>(b->d_fwd[s] + c.off, b->s_fwd + c.soff, c.n, c.nblk, c.lds, st));
+      if ((rc = batch_col_launches<T>(b, st, -1, dt))) return rc;
+      for (const BatchLaunch& c : b->l_stage)
+        HIPCHK(launch_row_stage_batch<T>(b->d_stage[s] + c.off, b->s_stage + c.soff, c.n, c.nblk, c.lds, s, dt,
+                                         c.inplace, st));
+      pending = s;
+    }
+    b->sur_steps += 1;
+    *done += 1;
+  }
+  if (pending >= 0) HIPCHK(launch_tick_batch(b->d_col_all, n, pending, dt, st));
+  return MMV_OK;
+}
+
+template <typename T>
 int batch_launch_steps(mmv_batch* b, hipStream_t st, double dt, int nsteps) {
   const int n = (int)b->inst.size();
   mmv_mesh* h0 = b->inst[0];  // timing events of the first instance's profile slot
@@ -1353,12 +1451,22 @@ template <typename T>
 int batch_step_typed(mmv_batch* b, double dt, int nsteps) {
   // the descriptors carry each instance's drive by value: any change made by
   // set_drive since they were built rebuilds them (and drops the graph)
+  bool rebuild = b->built_sur != (b->sur != nullptr && !b->sur_fallback);
   for (size_t i = 0; i < b->inst.size(); ++i)
-    if (!same_drive(b->inst[i]->drive, b->drive_sig[i])) {
-      int rc = batch_build<T>(b);
-      if (rc) return rc;
-      break;
-    }
+    if (!same_drive(b->inst[i]->drive, b->drive_sig[i])) rebuild = true;
+  if (rebuild) {
+    int rc = batch_build<T>(b);
+    if (rc) return rc;
+  }
+  if (b->sur && !b->sur_fallback) {
+    int done = 0;
+    int rc = batch_sur_steps<T>(b, b->st, dt, nsteps, &done);
+    if (rc) return rc;
+    if (done == nsteps) return MMV_OK;
+    // the judge sent the batch back to the exact path
+    if ((rc = batch_build<T>(b))) return rc;
+    return batch_launch_steps<T>(b, b->st, dt, nsteps - done);
+  }
   const bool graph = (b->flags & MMV_BATCH_GRAPH) && b->inst[0]->prof_kernel == 0;
   if (!graph) return batch_launch_steps<T>(b, b->st, dt, nsteps);
   int done = 0;
@@ -1793,6 +1901,53 @@ int batch_tuning(mmv_batch_handle b, int i, int* col_groups) {
   if (!b || !col_groups) return fail(MMV_EINVAL, "NULL argument");
   if (i < 0 || i >= (int)b->inst.size()) return fail(MMV_EINVAL, "instance out of range");
   *col_groups = b->inst[i]->ngroup;
+  return MMV_OK;
+}
+
+int batch_sur_attach(mmv_batch_handle b, mmv_sur_handle s, int judge_every, double tol) {
+  if (!b) return fail(MMV_EINVAL, "batch is NULL");
+  if (!s) {
+    b->sur = nullptr;
+    return MMV_OK;
+  }
+  if (b->esz != 4) return fail(MMV_ESTATE, "the learned operator runs with precision 32");
+  if (judge_every < 1) return fail(MMV_EINVAL, "judge_every must be >= 1");
+  if (!(tol > 0) || !isfinite(tol)) return fail(MMV_EINVAL, "tol must be finite and > 0");
+  int H = 0, W = 0, Bmax = 0;
+  sur_shape(s, &H, &W);
+  sur_max_batch(s, &Bmax);
+  const int n = (int)b->inst.size();
+  if (n > Bmax) return fail(MMV_EINVAL, "the operator's max_batch is smaller than the batch");
+  for (mmv_mesh* h : b->inst) {
+    if (h->d.cross_mode != 0) return fail(MMV_ESTATE, "the learned operator replaces the direct cross term");
+    if (H != h->ny || W != h->nx) return fail(MMV_EINVAL, "every instance must have the operator's grid");
+    const OutTable& t = h->tab_hot;
+    if (t.n < 3 || t.ch[t.n - 3].off != h->rp_hot.off_cross[0][0])
+      return fail(MMV_ESTATE, "unexpected channel table");
+  }
+  const size_t plane = (size_t)H * W;
+  int rc;
+  if (!b->sur_in && (rc = balloc(b, (void**)&b->sur_in, sizeof(float) * 4 * plane * (size_t)n))) return rc;
+  if (!b->sur_exact && (rc = balloc(b, (void**)&b->sur_exact, sizeof(float) * 3 * plane * (size_t)n))) return rc;
+  for (mmv_mesh* h : b->inst) {
+    h->tab_sur = h->tab_hot;
+    h->tab_sur.n = h->tab_hot.n - 3;
+  }
+  b->sur = s;
+  b->sur_every = judge_every;
+  b->sur_tol = tol;
+  b->sur_fallback = 0;
+  b->sur_err = -1.0;
+  b->sur_judged = 0;
+  b->sur_steps = 0;
+  return MMV_OK;
+}
+
+int batch_sur_status(mmv_batch_handle b, double* last_rel_err, int* fallback, long* judged) {
+  if (!b) return fail(MMV_EINVAL, "batch is NULL");
+  if (last_rel_err) *last_rel_err = b->sur_err;
+  if (fallback) *fallback = b->sur_fallback;
+  if (judged) *judged = b->sur_judged;
   return MMV_OK;
 }
 

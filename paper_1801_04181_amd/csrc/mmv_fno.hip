@@ -315,6 +315,10 @@ void sur_shape(const mmv_sur* s, int* H, int* W) {
   *W = s->W;
 }
 
+void sur_max_batch(const mmv_sur* s, int* Bmax) { *Bmax = s->Bmax; }
+
+const float* sur_output(const mmv_sur* s) { return s->pred; }
+
 hipError_t launch_sur_input(const float* m_slider, const RigidState* rigid, double inv_dx, int ny, int nx, float* a,
                             hipStream_t st) {
   const long long plane = (long long)ny * nx;

@@ -193,6 +193,9 @@ int report_error(int code, const std::string& msg);
 // handle's own output buffer [B][3][H][W] (valid until its next call).
 int sur_infer(mmv_sur* s, const float* a, int B, hipStream_t st, const float** out);
 void sur_shape(const mmv_sur* s, int* H, int* W);
+void sur_max_batch(const mmv_sur* s, int* Bmax);
+// the operator's output buffer [max_batch][3][H][W] (written by sur_infer)
+const float* sur_output(const mmv_sur* s);
 // a[4][ny][nx] = (m_x, m_y, m_z of the slider, x_s / dx of the current stage)
 hipError_t launch_sur_input(const float* m_slider, const RigidState* rigid, double inv_dx, int ny, int nx, float* a,
                             hipStream_t st);
