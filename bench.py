@@ -28,8 +28,9 @@ METRIC = "cell-updates/s per LLG step; surrogate+batched vs plain at ≤1e-3 H e
 # device copy of known size, keyed by kernel and by the hash of the kernel
 # sources they were taken on: a changed kernel reports null.
 TRAFFIC = {
-    "col": {"source": "8fc95c702d51", "bytes": 16078500},
-    "row_stage": {"source": "8fc95c702d51", "bytes": 19553008},
+    "col": {"source": "132dc540717e", "bytes": 16161985},
+    "row_stage": {"source": "132dc540717e", "bytes": 19413481},
+    "batch_step": {"source": "132dc540717e", "bytes": 3059939938},
 }
 KERNEL_SOURCES = ("paper_1801_04181_amd/csrc/mmv_kernels.hip", "paper_1801_04181_amd/csrc/mmv_device.h",
                   "paper_1801_04181_amd/csrc/mmv_internal.h")
@@ -103,7 +104,102 @@ def cpu_baseline(cfg, m, budget_s=12.0):
                       f"NumPy/SciPy oracle, 1 thread, {dt:.1f} s"}
 
 
-def batched_vs_plain(steps_batch=200, steps_plain=50):
+def host_info():
+    """Cores this process may run on and the CPU model (the baseline's host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return n, model
+
+
+class scipy_fft_backend:
+    """Within the block, numpy's FFT calls (the oracle's) run on scipy.fft
+    with `workers` threads; the oracle's code itself is unchanged."""
+    NAMES = ("fft2", "ifft2", "rfftn", "irfftn", "fftn", "ifftn", "rfft", "irfft", "fft", "ifft")
+
+    def __init__(self, workers):
+        self.workers = workers
+
+    def __enter__(self):
+        import numpy as np
+        import scipy.fft as sf
+        self.saved = {k: getattr(np.fft, k) for k in self.NAMES}
+        for k in self.NAMES:
+            fn = getattr(sf, k)
+            setattr(np.fft, k, (lambda f: lambda *a, **kw: f(*a, workers=self.workers, **kw))(fn))
+        return self
+
+    def __exit__(self, *exc):
+        import numpy as np
+        for k, f in self.saved.items():
+            setattr(np.fft, k, f)
+
+
+def cpu_baseline_variants():
+    """The float64 oracle on the other workloads and with a multi-threaded FFT
+    backend (bounded samples; throughput per step is constant)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle.sim import System
+    from workloads import get_config, initial_state
+    from workloads.configs import batch_pairs
+    ncore, model = host_info()
+    out = {"host_cores": ncore, "cpu_model": model, "runs": []}
+
+    def timed(name, systems, steps, dt, workers):
+        cells = sum(sy.desc.cells for sy in systems)
+        ctx = scipy_fft_backend(workers) if workers > 1 else None
+        with threadpool_limits(limits=workers):
+            if ctx:
+                ctx.__enter__()
+            try:
+                for sy in systems:
+                    sy.field_terms()            # kernel windows built outside the clock
+                t0 = time.perf_counter()
+                for sy in systems:
+                    sy.run(dt, steps)
+                el = time.perf_counter() - t0
+            finally:
+                if ctx:
+                    ctx.__exit__(None, None, None)
+        out["runs"].append({"workload": name, "value": cells * steps / el, "unit": "cell-updates/s",
+                            "cores": workers, "fft": "scipy.fft workers=%d" % workers if workers > 1
+                            else "numpy.fft (1 thread)", "steps": steps, "seconds": el})
+
+    cfg = get_config("stickslip")
+    timed("stickslip 2x512x128 f64 oracle", [System(cfg["desc"], cfg["drive"], initial_state(cfg))], 8,
+          cfg["dt"], ncore)
+    cfg = get_config("tiny")
+    timed("tiny 2x32x32 (100 steps)", [System(cfg["desc"], cfg["drive"], initial_state(cfg))], 100, cfg["dt"], 1)
+    cfg = get_config("cube_eddy")
+    timed("cube 64^3 with eddy currents", [System(cfg["desc"], cfg["drive"], initial_state(cfg))], 2, cfg["dt"], 1)
+    pairs = batch_pairs(64)[:8]          # one pair of each size class
+    timed("batch: 8 of the 64 uneven pairs (one per size class)",
+          [System(p["desc"], p["drive"], initial_state(p)) for p in pairs], 1, pairs[0]["dt"], 1)
+    return out
+
+
+def batch_step_bytes(descs, lxly):
+    """Algorithmic bytes of one batched RK4 step (four stages of the y pass
+    and the row kernel per instance; the x pass runs inside the row kernel)."""
+    tot = 0.0
+    for d, (lx, ly) in zip(descs, lxly):
+        per, _ = kernel_bytes(d, lx, ly)
+        tot += 4 * (per["col"] + per["row_stage"])
+    return tot
+
+
+def batched_vs_plain(steps_batch=200, steps_plain=50, graph=True):
     """64 uneven pairs: per-instance launches vs one batched, graph-replayed launch per pass."""
     import torch
     import paper_1801_04181_amd as mmv
@@ -116,6 +212,7 @@ def batched_vs_plain(steps_batch=200, steps_plain=50):
     dt = pairs[0]["dt"]
     cells = sum(d.cells for d in descs)
     meshes = [mmv.Mesh(d, drv, m) for d, drv, m in zip(descs, drives, ms)]
+    lxly = [me.fft_lengths()[:2] for me in meshes]
     for me in meshes:
         me.step(dt, 2)
     torch.cuda.synchronize()
@@ -126,7 +223,7 @@ def batched_vs_plain(steps_batch=200, steps_plain=50):
     t_plain = time.perf_counter() - t0
     for me in meshes:
         me.close()
-    B = mmv.Batch(descs, drives, ms, flags=mmv.BATCH_AUTOTUNE | mmv.BATCH_GRAPH)
+    B = mmv.Batch(descs, drives, ms, flags=mmv.BATCH_AUTOTUNE | (mmv.BATCH_GRAPH if graph else 0))
     B.step(dt, 16)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -137,10 +234,77 @@ def batched_vs_plain(steps_batch=200, steps_plain=50):
     B.close()
     plain = cells * steps_plain / t_plain
     batched = cells * steps_batch / t_batch
+    step_bytes = batch_step_bytes(descs, lxly)
+    step_s = t_batch / steps_batch
+    achieved = step_bytes / step_s / 1e9
     return {"workload": "64 uneven pairs nx {64,128,256,512} x ny {64,128}, 2 nm, f32, spring drives",
             "cells": cells, "plain_cell_updates_per_s": plain,
             "batched_cell_updates_per_s": batched, "speedup": batched / plain,
-            "ms_per_step_batched": t_batch / steps_batch * 1e3, "autotuned_groups": groups}
+            "ms_per_step_batched": step_s * 1e3, "autotuned_groups": groups,
+            "roofline": {"bound": "hbm", "scope": "whole batched step (every launch of the 4 stages)",
+                         "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": achieved / PEAK_HBM_GBS, "bytes_per_step": step_bytes,
+                         "traffic": traffic_of("batch_step"),
+                         "timing": "host clock around graph-replayed steps, stream synchronised"}}
+
+
+def surrogate_batched(n=16, steps=20):
+    """The metric's comparison on the learned-operator workload (2 x 256 x
+    256 films): n instances stepped with the width-32 operator replacing film
+    0's cross field (one batched inference per RK stage), against the same
+    instances exact-batched and stepped one by one.  The operator here is
+    untrained (seeded initial weights): its speed does not depend on the
+    weights, and its judged error is reported as measured."""
+    import torch
+    import paper_1801_04181_amd as mmv
+    from workloads import get_config, initial_state
+    from workloads.fno_inputs import init_params
+    cfg = get_config("learned")
+    d, drv, dt = cfg["desc"], cfg["drive"], cfg["dt"]
+    m = initial_state(cfg)
+    C, Mx, My, L = 32, 16, 32, 4
+    cells = d.cells * n
+    sur = mmv.Surrogate(d.ny, d.nx, C, Mx, My, L, max_batch=n)
+    sur.set_params(torch.from_numpy(init_params(C, Mx, My, L, seed=2)).float())
+    B = mmv.Batch([d] * n, [drv] * n, [m] * n)
+    mmv.batch_sur_attach(B.b, sur.h, 10, 1e30)      # judge every 10 steps, never falls back
+    B.step(dt, 4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.step(dt, steps)
+    torch.cuda.synchronize()
+    t_sur = time.perf_counter() - t0
+    err, fell, judged = mmv.batch_sur_status(B.b)
+    B.close()
+    E = mmv.Batch([d] * n, [drv] * n, [m] * n, flags=mmv.BATCH_GRAPH)
+    E.step(dt, 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E.step(dt, 2 * steps)
+    torch.cuda.synchronize()
+    t_exact = (time.perf_counter() - t0) / 2
+    E.close()
+    meshes = [mmv.Mesh(d, drv, m) for _ in range(n)]
+    for me in meshes:
+        me.step(dt, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for me in meshes:
+        me.step(dt, steps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    for me in meshes:
+        me.close()
+    sur.close()
+    return {"workload": f"{n} x (2 films 256x256), f32, spring drive; operator width {C}, "
+                        f"{Mx}x{My} modes, {L} layers, BF16 matrix cores (untrained weights)",
+            "instances": n, "cells": cells,
+            "surrogate_batched_cell_updates_per_s": cells * steps / t_sur,
+            "exact_batched_cell_updates_per_s": cells * steps / t_exact,
+            "plain_cell_updates_per_s": cells * steps / t_plain,
+            "surrogate_batched_vs_plain": t_plain / t_sur,
+            "judged_rel_err": err, "judges": judged,
+            "meets_1e-3": bool(err <= 1e-3)}
 
 
 def cube_report(steps=40, warmup=4):
@@ -331,7 +495,9 @@ def main():
     ap.add_argument("--config", default="stickslip")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--report", choices=["precision", "surrogate", "cube"], default=None)
+    ap.add_argument("--no-graph", action="store_true", help="--report batch: eager launches (counter runs)")
+    ap.add_argument("--report", choices=["precision", "surrogate", "cube", "batch", "surrogate-batched"],
+                    default=None)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy 256 MiB device to device 3 times (counter calibration)")
@@ -341,6 +507,15 @@ def main():
         return
     if args.report == "cube":
         print(json.dumps({"cube_report": cube_report()}), flush=True)
+        return
+    if args.report == "batch":
+        print(json.dumps({"batched": batched_vs_plain(steps_batch=args.steps, steps_plain=2,
+                                                      graph=not args.no_graph)}), flush=True)
+        if args.calib_copy:
+            calib_copy()
+        return
+    if args.report == "surrogate-batched":
+        print(json.dumps({"surrogate_batched": surrogate_batched()}), flush=True)
         return
     if args.report == "surrogate":
         print(json.dumps({"surrogate_report": surrogate_report(args.train_steps)}), flush=True)
@@ -418,16 +593,24 @@ def main():
     }
     if not args.no_batch:
         out["batched"] = batched_vs_plain()
+        out["surrogate_batched"] = surrogate_batched()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, m)
+        out["cpu_baseline_variants"] = cpu_baseline_variants()
     print(json.dumps(out), flush=True)
     if args.calib_copy:
-        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print("calib copy: 268435456 bytes read and written per launch", file=sys.stderr, flush=True)
+        calib_copy()
+
+
+def calib_copy():
+    """Three device copies of 256 MiB: the counters' scale for known bytes."""
+    import torch
+    a = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("calib copy: 268435456 bytes read and written per launch", file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":
