@@ -23,6 +23,7 @@ framework") step by step:
                        (the paper's RK45 solver, Sec. III)
   periodic.py          periodic in-plane boundaries: image-summed kernels,
                        periodic windows (halo copies), periodic exchange
+  divcurl.py           divergence / curl of the interpolated field, Eq. (13)
   fno.py               learned stray-field operator (Fourier neural
                        operator standing in for the cross term), float64
                        torch with autograd gradients
@@ -31,8 +32,8 @@ Parity status of each function is stated in its docstring; functions with
 no independent pin say "parity unpinned".
 """
 from .constants import MU0, GAMMA_E, GAMMA0
-from . import newell, potential_kernel, convolution, spline, fields, llg, sim, fno, dormand_prince, periodic
+from . import newell, potential_kernel, convolution, spline, fields, llg, sim, fno, dormand_prince, periodic, divcurl
 
 __all__ = ["MU0", "GAMMA_E", "GAMMA0", "newell", "potential_kernel",
            "convolution", "spline", "fields", "llg", "sim", "fno", "dormand_prince",
-           "periodic"]
+           "periodic", "divcurl"]

@@ -46,7 +46,7 @@ from .constants import MU0, GAMMA0
 from . import fields as _fields
 from .llg import llg_rhs
 from .convolution import demag_window, potential_window
-from .spline import prefilter, interp_1d
+from .spline import prefilter, interp_1d, linear_1d
 
 FROZEN, VELOCITY, SPRING = 0, 1, 2
 TERMS = ("exchange", "anisotropy", "zeeman", "demag_self", "demag_cross",
@@ -102,7 +102,7 @@ class System:
         d = self.desc
         h, zs = d.halo, d.z_s
         nwx = d.nx + 2 * h
-        if d.cross_mode == 0:
+        if d.cross_mode in (0, 2):
             if direction == "b2s":
                 return (s_int - h, nwx, -1, d.ny + 2, zs - 1, 3)
             return (-s_int - h, nwx, 0, d.ny, -zs, 1)
@@ -119,7 +119,7 @@ class System:
             from .periodic import BoxWindow
             assert d.cross_mode == 0, "periodic boundaries: direct mode only"
             return self._op(("cross", direction, s_int, 0), lambda: BoxWindow(d, box))
-        maker = (lambda: demag_window(d, box)) if d.cross_mode == 0 else (
+        maker = (lambda: demag_window(d, box)) if d.cross_mode in (0, 2) else (
             lambda: potential_window(d, box))
         return self._op(("cross", direction, s_int, d.cross_mode), maker)
 
@@ -139,23 +139,23 @@ class System:
         V = d.dx * d.dy * d.dz
         ny = d.ny
         F = np.zeros(3)
-        if d.cross_mode == 0:
-            G = self.cross_op("b2s", s_int)(m_b)          # (3, 3, ny+2, M)
-            c = prefilter(G, axis=-1)
-            Hs = interp_1d(c[:, 1, 1:ny + 1], u_s)         # (3, ny, nx)
+        if d.cross_mode in (0, 2):
+            # cubic B-spline (mode 0) or linear interpolation (mode 2) of the
+            # window data along the motion axis
+            pre = prefilter if d.cross_mode == 0 else (lambda G, axis: G)
+            samp = interp_1d if d.cross_mode == 0 else linear_1d
+            st = self.base_field_stencil(m_b, x, s_int)
+            Hs = st["c"]
             if want_force:
                 ms = m_s[:, 0]
-                dHdx = (interp_1d(c[:, 1, 1:ny + 1], u_s + 1)
-                        - interp_1d(c[:, 1, 1:ny + 1], u_s - 1)) / (2 * d.dx)
-                dHdy = (interp_1d(c[:, 1, 2:ny + 2], u_s)
-                        - interp_1d(c[:, 1, 0:ny], u_s)) / (2 * d.dy)
-                dHdz = (interp_1d(c[:, 2, 1:ny + 1], u_s)
-                        - interp_1d(c[:, 0, 1:ny + 1], u_s)) / (2 * d.dz)
+                dHdx = (st["xp"] - st["xm"]) / (2 * d.dx)
+                dHdy = (st["yp"] - st["ym"]) / (2 * d.dy)
+                dHdz = (st["zp"] - st["zm"]) / (2 * d.dz)
                 F = MU0 * d.Ms * V * (ms[0][None] * dHdx + ms[1][None] * dHdy
                                       + ms[2][None] * dHdz).sum(axis=(1, 2))
             Gb = self.cross_op("s2b", s_int)(m_s)         # (3, 1, ny, M)
-            cb = prefilter(Gb, axis=-1)
-            Hb = interp_1d(cb[:, 0], u_b)
+            cb = pre(Gb, axis=-1)
+            Hb = samp(cb[:, 0], u_b)
             return Hb[:, None], Hs[:, None], F
         # scalar-potential mode
         phi = self.cross_op("b2s", s_int)(m_b)[0]          # (7, ny+6, M)
@@ -196,6 +196,42 @@ class System:
                   d.dz)
         Hb = np.array([hx, hy, hz])
         return Hb[:, None], Hs[:, None], F
+
+    def base_field_stencil(self, m_b, x, s_int):
+        """The base film's field sampled on the slider's shifted lattice:
+        at the slider cells ("c") and at their six neighbour points
+        (x+-1: "xp"/"xm", y+-1: "yp"/"ym", layers z_s+-1: "zp"/"zm"), each
+        (3, ny, nx) [A/m].  The points of Eq. 3's differences and of Eq. 13's
+        divergence and curl."""
+        d = self.desc
+        h, ny = d.halo, d.ny
+        xp = x / d.dx - s_int
+        u_s = np.arange(d.nx, dtype=np.float64) + h + xp
+        if d.cross_mode in (0, 2):
+            pre = prefilter if d.cross_mode == 0 else (lambda G, axis: G)
+            samp = interp_1d if d.cross_mode == 0 else linear_1d
+            c = pre(self.cross_op("b2s", s_int)(m_b), axis=-1)   # (3, 3, ny+2, M)
+            return {"c": samp(c[:, 1, 1:ny + 1], u_s),
+                    "xp": samp(c[:, 1, 1:ny + 1], u_s + 1), "xm": samp(c[:, 1, 1:ny + 1], u_s - 1),
+                    "yp": samp(c[:, 1, 2:ny + 2], u_s), "ym": samp(c[:, 1, 0:ny], u_s),
+                    "zp": samp(c[:, 2, 1:ny + 1], u_s), "zm": samp(c[:, 0, 1:ny + 1], u_s)}
+        cphi = prefilter(self.cross_op("b2s", s_int)(m_b)[0], axis=-1)
+
+        def ptil(layer, r0, u):
+            return interp_1d(cphi[layer, r0:r0 + ny], u)
+
+        def Htil(layer, r0, u):
+            hx = -_d4(ptil(layer, r0, u - 2), ptil(layer, r0, u - 1),
+                      ptil(layer, r0, u + 1), ptil(layer, r0, u + 2), d.dx)
+            hy = -_d4(ptil(layer, r0 - 2, u), ptil(layer, r0 - 1, u),
+                      ptil(layer, r0 + 1, u), ptil(layer, r0 + 2, u), d.dy)
+            hz = -_d4(ptil(layer - 2, r0, u), ptil(layer - 1, r0, u),
+                      ptil(layer + 1, r0, u), ptil(layer + 2, r0, u), d.dz)
+            return np.array([hx, hy, hz])
+
+        return {"c": Htil(3, 3, u_s), "xp": Htil(3, 3, u_s + 1), "xm": Htil(3, 3, u_s - 1),
+                "yp": Htil(3, 4, u_s), "ym": Htil(3, 2, u_s),
+                "zp": Htil(4, 3, u_s), "zm": Htil(2, 3, u_s)}
 
     # ------------------------------------------------------------- fields
     def field_terms(self, m_list=None, x=None, s_int=None, want_force=True):

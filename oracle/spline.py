@@ -108,3 +108,16 @@ def interp_3d(c, u, v, w):
 
 def prefilter_3d(f):
     return prefilter(prefilter(prefilter(f, axis=2), axis=1), axis=0)
+
+
+def linear_1d(f, u, axis=-1):
+    """Linear interpolation of the samples f (no prefilter) at positions u:
+    (1 - t) f[k] + t f[k + 1], k = floor(u), t = u - k, mirror indices
+    (the comparison interpolant of Sec. IV.A)."""
+    f = np.moveaxis(np.asarray(f, dtype=np.float64), axis, -1)
+    M = f.shape[-1]
+    u = np.asarray(u, dtype=np.float64)
+    k0 = np.floor(u).astype(np.int64)
+    t = u - k0
+    out = f[..., reflect(k0, M)] * (1.0 - t) + f[..., reflect(k0 + 1, M)] * t
+    return np.moveaxis(out, -1, axis) if u.ndim == 1 else out

@@ -41,7 +41,7 @@ class Desc:
     Hext: tuple = (0.0, 0.0, 0.0)
     sigma: float = 0.0        # conductivity [S/m]; 0 disables eddy currents
     precision: int = 32       # 32 or 64
-    cross_mode: int = 0       # 0 direct field spline, 1 scalar potential
+    cross_mode: int = 0       # 0 direct field spline, 1 scalar potential, 2 direct field, linear interpolation
     halo: int = 4             # spline window extension along the motion axis
     rc_cells: float = 30.0    # Newell / point-dipole switch radius [cells]
     sor_sweeps: int = 0       # fixed red-black SOR sweeps per step (0: library default)
