@@ -76,7 +76,9 @@ typedef struct {
   int precision;        /* 32 or 64                                           */
   int cross_mode;       /* 0: direct field spline; 1: scalar potential (needs
                            gap_cells >= 3: Sec. IV.D asks for films more than
-                           two cells apart; MMV_EINVAL otherwise)              */
+                           two cells apart; MMV_EINVAL otherwise); 2: direct
+                           field, linear interpolation of the field vectors
+                           (the comparison interpolant of Sec. IV.A)         */
   int halo;             /* spline window extension along x in cells (>= 2)    */
   double rc_cells;      /* Newell / point-dipole switch radius in cells (> 0) */
   int sor_sweeps;       /* eddy SOR sweeps per step (0: library default)      */
@@ -182,6 +184,16 @@ int llg_run_dp(mmv_handle h, double t_end, double tol, double* h_io, int max_att
  * state, all three components, accumulated in float64 in a fixed order.
  * Synchronises the stream.  MMV_ESTATE for a single-film mesh.          */
 int stray_force(mmv_handle h, double F_out[3]);
+
+/* Divergence and curl of the base film's stray field as the slider samples
+ * it at the current offset (Sec. IV.A, Eq. 13): per slider cell the
+ * two-point central differences of the interpolated field at the six
+ * neighbour points of the shifted lattice (the points of Eq. 3), and
+ * D = mean over the nx*ny slider cells of |div H|, C = mean of |curl H|
+ * [A/m^2], summed in float64 in a fixed order.  Works for every cross_mode
+ * (0 spline, 1 scalar potential, 2 linear interpolation).  Synchronises
+ * the stream.  MMV_ESTATE for a single-film mesh.                       */
+int div_curl(mmv_handle h, double* D, double* C);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the force

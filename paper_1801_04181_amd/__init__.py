@@ -11,7 +11,7 @@ import os
 
 __all__ = ["MMVError", "lib_path", "load", "MeshDesc", "DriveDesc", "init_mesh",
            "set_m", "get_m", "set_offset", "set_drive", "eval_heff", "llg_step", "llg_run_dp",
-           "stray_force", "stray_force_noalloc", "get_state", "get_fft_lengths", "destroy_mesh",
+           "stray_force", "stray_force_noalloc", "div_curl", "get_state", "get_fft_lengths", "destroy_mesh",
            "profile_begin", "profile_end", "profile_repeat", "init_batch", "batch_instance", "batch_step",
            "batch_tuning", "set_tune_cache", "destroy_batch", "Batch", "batch_sur_attach", "batch_sur_status", "SurDesc", "sur_create", "sur_param_count",
            "sur_param_offsets", "sur_set_params", "sur_get_params", "sur_forward", "sur_gradient",
@@ -26,7 +26,7 @@ TERM = dict(exchange=1, anisotropy=2, zeeman=4, demag_self=8, demag_cross=16,
 ERRORS = {-1: "MMV_EINVAL", -2: "MMV_ENOMEM", -3: "MMV_EHIP", -4: "MMV_ERANGE",
           -5: "MMV_ENUMERIC", -6: "MMV_ESTATE"}
 EXPORTS = ("init_mesh", "set_m", "get_m", "set_offset", "set_drive", "eval_heff",
-           "llg_step", "llg_run_dp", "stray_force", "stray_force_noalloc", "get_state", "profile_begin", "profile_end",
+           "llg_step", "llg_run_dp", "stray_force", "stray_force_noalloc", "div_curl", "get_state", "profile_begin", "profile_end",
            "get_fft_lengths", "profile_repeat", "init_batch", "batch_instance", "batch_step", "batch_tuning",
            "set_tune_cache", "destroy_batch", "destroy_mesh", "sur_create", "sur_param_count", "sur_param_offsets",
            "sur_set_params", "sur_get_params", "sur_forward", "sur_gradient", "sur_train_step",
@@ -92,6 +92,7 @@ def load():
         lib.llg_run_dp.argtypes = [vp, d, d, pd, i, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]
         lib.stray_force.argtypes = [vp, pd]
         lib.stray_force_noalloc.argtypes = [vp, vp]
+        lib.div_curl.argtypes = [vp, pd, pd]
         lib.get_state.argtypes = [vp, pd, pd, pd, ctypes.POINTER(ctypes.c_long)]
         lib.get_fft_lengths.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
         lib.destroy_mesh.argtypes = [vp]
@@ -224,6 +225,13 @@ def stray_force_noalloc(h, F_dev):
     allocation, no synchronisation."""
     _check(load().stray_force_noalloc(h, _ptr(F_dev)))
     return F_dev
+
+
+def div_curl(h):
+    """(D, C) of Eq. 13 for the base film's field in the slider [A/m^2]."""
+    D, C = ctypes.c_double(), ctypes.c_double()
+    _check(load().div_curl(h, ctypes.byref(D), ctypes.byref(C)))
+    return D.value, C.value
 
 
 def get_state(h):

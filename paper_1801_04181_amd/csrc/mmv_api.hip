@@ -140,6 +140,9 @@ struct mmv_mesh {
   void* kdp = nullptr;         // stage derivatives [7][film][3][y][x]
   double* errpart = nullptr;   // per row block largest error
   DpCtrl* dpc = nullptr;       // step control
+  // divergence / curl of the interpolated field (allocated at first use)
+  void* divfield = nullptr;    // base field on the slider's stencil points
+  double* divpart = nullptr;   // per row: sum |div|, sum |curl|
   OutTable tab_sur{};
   int sor_sweeps = 40;
   double sor_omega = 1.0;
@@ -186,8 +189,8 @@ int validate(const mmv_mesh_desc* d) {
   for (int i = 0; i < 3; ++i)
     if (!isfinite(d->u[i]) || !isfinite(d->Hext[i])) return fail(MMV_EINVAL, "u and Hext must be finite");
   if (d->precision != 32 && d->precision != 64) return fail(MMV_EINVAL, "precision must be 32 or 64");
-  if (d->cross_mode != 0 && d->cross_mode != 1) return fail(MMV_EINVAL, "cross_mode must be 0 or 1");
-  if (d->cross_mode == 1 && d->n_films != 2) return fail(MMV_EINVAL, "cross_mode 1 needs two films");
+  if (d->cross_mode < 0 || d->cross_mode > 2) return fail(MMV_EINVAL, "cross_mode must be 0, 1 or 2");
+  if (d->cross_mode != 0 && d->n_films != 2) return fail(MMV_EINVAL, "cross_mode 1 and 2 need two films");
   // the four-point difference of the potential and the force stencil around
   // it reach two cells towards the other film: the films must be more than
   // two cells apart (Sec. IV.D)
@@ -277,7 +280,7 @@ void assign_channels(mmv_mesh* h) {
   for (int c = 0; c < 6; ++c) h->cross.kc[c] = h->fp.kc[c] = h->fm.kc[c] = -1;
   for (int d = 0; d < 7; ++d)
     for (int c = 0; c < 3; ++c) h->pot_kc[d][c] = -1;
-  if (h->nfilm == 2 && h->d.cross_mode == 0) {
+  if (h->nfilm == 2 && h->d.cross_mode != 1) {
     for (int c = 0; c < 6; ++c) h->cross.kc[c] = n++;
     for (int c = 0; c < 6; ++c) h->fp.kc[c] = n++;
     for (int c = 0; c < 6; ++c) h->fm.kc[c] = n++;
@@ -512,6 +515,7 @@ int init_typed(mmv_mesh* h) {
     rp->gam = GAMMA0 / (1.0 + d.alpha * d.alpha);
     rp->alpha = d.alpha;
     rp->force_scale = MU0 * d.Ms * d.dx * d.dy * d.dz;
+    rp->interp = d.cross_mode == 2 ? 1 : 0;
     rp->px = h->px;
   }
   // LDS limits (the CU's 160 KB less the kernels' static LDS)
@@ -992,6 +996,41 @@ int dp_attempts(mmv_mesh* h, int n) {
     HIPCHK(launch_dp_control(ta, h->dpc, h->errpart, rp.ntask, h->st));
     HIPCHK(launch_dp_commit<T>(b2, m0, h->nfilm, plane, h->dpc, &h->rigid->flags, h->st));
   }
+  return MMV_OK;
+}
+
+// Eq. 13 at the current state: the force pass writes the base field on the
+// slider's stencil points, then per row the sums of |div| and |curl|.
+template <typename T>
+int div_curl_typed(mmv_mesh* h, double* D, double* C) {
+  const size_t gsz = (size_t)3 * (h->ny + 2) * (h->nx + 2) + (size_t)6 * h->ny * h->nx;
+  int rc;
+  if (!h->divfield && (rc = dalloc(h, &h->divfield, sizeof(T) * gsz))) return rc;
+  if (!h->divpart && (rc = dalloc(h, (void**)&h->divpart, sizeof(double) * 2 * (size_t)h->ny))) return rc;
+  if ((rc = run_fields<T>(h, h->m0, h->tab_force))) return rc;
+  RowParams rp = h->rp_force;
+  rp.mode = MODE_FORCE;
+  rp.term_mask = 0;
+  rp.with_force = 1;
+  rp.full_force = 1;
+  rp.ntask = h->ny + 2;
+  rp.drive = h->drive;
+  rp.fieldout = h->divfield;
+  HIPCHK(launch_row_stage<T>(rp, h->spec2, (const T*)h->m0, (const T*)h->m0, nullptr, nullptr, nullptr, h->twx,
+                             h->twp, h->rigid, h->partial, h->counter, h->st));
+  HIPCHK(launch_div_curl<T>((const T*)h->divfield, h->nx, h->ny, h->d.dx, h->d.dy, h->d.dz, (h->d.pbc & 2) ? 1 : 0,
+                            h->divpart, h->st));
+  std::vector<double> part(2 * (size_t)h->ny);
+  HIPCHK(hipMemcpyAsync(part.data(), h->divpart, sizeof(double) * part.size(), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  double sd = 0.0, sc = 0.0;
+  for (int y = 0; y < h->ny; ++y) {
+    sd += part[2 * y];
+    sc += part[2 * y + 1];
+  }
+  const double n = (double)h->nx * h->ny;
+  *D = sd / n;
+  *C = sc / n;
   return MMV_OK;
 }
 
@@ -2173,6 +2212,14 @@ int llg_run_dp(mmv_handle h, double t_end, double tol, double* h_io, int max_att
   if (rejected) *rejected = (long)c.rejected;
   if ((rc = read_rigid(h, r))) return rc;
   return report_flags(h, r);
+}
+
+int div_curl(mmv_handle h, double* D, double* C) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!D || !C) return fail(MMV_EINVAL, "D and C must not be NULL");
+  if (h->cube || h->nfilm != 2) return fail(MMV_ESTATE, "div_curl needs two films");
+  return h->esz == 8 ? div_curl_typed<double>(h, D, C) : div_curl_typed<float>(h, D, C);
 }
 
 int get_state(mmv_handle h, double* t, double* x_s, double* v_s, long* step) {

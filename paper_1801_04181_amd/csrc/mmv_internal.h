@@ -147,6 +147,15 @@ struct RowParams {
   // periodic in-plane axes (bit 0 = x, 1 = y): exchange wraps, and along y
   // the force's rows -1 and ny are the rows ny-1 and 0
   int pbc;
+  // sampling of the other film's field along x: 0 prefiltered cubic
+  // B-spline, 1 linear interpolation of the field vectors (a comparison
+  // mode, Sec. IV.A)
+  int interp;
+  // MODE_FORCE: when set, the base field on the slider's stencil points is
+  // also written here: layer z_s at rows -1..ny, i = -1..nx
+  // [3][ny+2][nx+2], then layers z_s+1 and z_s-1 on the cells [3][ny][nx]
+  // each (mesh precision)
+  void* fieldout;
 };
 
 // Per-instance descriptors of the batched launches (device memory).

@@ -43,6 +43,11 @@ hipError_t launch_dp_control(const TickArgs& tick, DpCtrl* ctrl, const double* e
 template <typename T>
 hipError_t launch_dp_commit(const T* y5, T* m, int nfilm, size_t plane, const DpCtrl* ctrl, int* flags,
                             hipStream_t st);
+// Eq. 13: per slider row, sums of |div H| and |curl H| of the base field on
+// the stencil points written by the force pass.
+template <typename T>
+hipError_t launch_div_curl(const T* G, int nx, int ny, double dx, double dy, double dz, int pbc_y, double* part,
+                           hipStream_t st);
 // The row kernel can transform rows of this length in place.
 bool row_inplace_length(int L);
 size_t row_fwd_lds_bytes(int N2x, int esz);

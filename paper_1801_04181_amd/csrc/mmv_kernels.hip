@@ -482,6 +482,48 @@ __global__ void __launch_bounds__(TICK_THREADS)
   ctrl->h = hn;
 }
 
+// Eq. 13: per slider row y, the sums over its cells of |div H| and |curl H|
+// with two-point central differences of the base field on the stencil
+// points written by the force pass (layout of RowParams::fieldout); rows
+// wrap along a periodic y.  One block per row; fixed-order float64 sums.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_div_curl(const T* __restrict__ G, int nx, int ny, double dx, double dy, double dz, int pbc_y,
+               double* __restrict__ part) {
+  __shared__ double s_red[2][4];
+  const int y = blockIdx.x;
+  const size_t gcs = (size_t)(ny + 2) * (nx + 2), cs = (size_t)ny * nx;
+  const int yl = pbc_y ? (y - 1 + ny) % ny : y - 1, yh = pbc_y ? (y + 1) % ny : y + 1;
+  auto c = [&](int a, int row, int i) -> double { return (double)G[a * gcs + (size_t)(row + 1) * (nx + 2) + i + 1]; };
+  auto zp = [&](int a, int i) -> double { return (double)G[3 * gcs + a * cs + (size_t)y * nx + i]; };
+  auto zm = [&](int a, int i) -> double { return (double)G[3 * gcs + 3 * cs + a * cs + (size_t)y * nx + i]; };
+  const double i2x = 1.0 / (2.0 * dx), i2y = 1.0 / (2.0 * dy), i2z = 1.0 / (2.0 * dz);
+  double sd = 0.0, sc = 0.0;
+  for (int i = threadIdx.x; i < nx; i += 256) {
+    double dH[3][3];  // dH[a][b] = d_b H_a
+    for (int a = 0; a < 3; ++a) {
+      dH[a][0] = (c(a, y, i + 1) - c(a, y, i - 1)) * i2x;
+      dH[a][1] = (c(a, yh, i) - c(a, yl, i)) * i2y;
+      dH[a][2] = (zp(a, i) - zm(a, i)) * i2z;
+    }
+    const double div = dH[0][0] + dH[1][1] + dH[2][2];
+    const double cx = dH[2][1] - dH[1][2], cy = dH[0][2] - dH[2][0], cz = dH[1][0] - dH[0][1];
+    sd += fabs(div);
+    sc += sqrt(cx * cx + cy * cy + cz * cz);
+  }
+  sd = wave_sum(sd);
+  sc = wave_sum(sc);
+  if ((threadIdx.x & 63) == 0) {
+    s_red[0][threadIdx.x >> 6] = sd;
+    s_red[1][threadIdx.x >> 6] = sc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * y] = s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3];
+    part[2 * y + 1] = s_red[1][0] + s_red[1][1] + s_red[1][2] + s_red[1][3];
+  }
+}
+
 // Accepted attempt: m = the fifth-order state renormalised (y5 and m are
 // [film][3][plane]).
 template <typename T>
@@ -966,6 +1008,12 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     for (int tq = threadIdx.x; tq < 2 * NQ; tq += NT) {
       double g = 0.0;
       for (int t = 0; t < 4; ++t) g += wterm[tq * 4 + t];
+      if (p.interp == 1) {
+        // linear interpolation: taps at offsets 0 and 1 of the window
+        const int q = tq % NQ;
+        const double fr = tq < NQ ? frs : frb;
+        g = q == K + 1 ? 1.0 - fr : (q == K + 2 ? fr : 0.0);
+      }
       (tq < NQ ? gs : gb)[tq % NQ] = (T)g;
     }
   }
@@ -1123,6 +1171,25 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     lds_barrier();
   }
 
+  if (p.mode == MODE_FORCE && p.fieldout != nullptr && need_force) {
+    // the base field on the slider's stencil points, for Eq. 13's
+    // divergence and curl (gc holds i = -1..nx of this row; gp, gm the
+    // layers z_s +- 1 on the cells)
+    T* G = reinterpret_cast<T*>(p.fieldout);
+    const size_t gcs = (size_t)(ny + 2) * (nx + 2), cs = (size_t)ny * nx;
+#pragma unroll 1
+    for (int t = threadIdx.x; t < 3 * (nx + 2); t += NT) {
+      const int a = t / (nx + 2), i = t - a * (nx + 2);
+      G[a * gcs + (size_t)(y + 1) * (nx + 2) + i] = gc[a * (nx + 2) + i];
+    }
+    if (cell_row)
+#pragma unroll 1
+      for (int t = threadIdx.x; t < 3 * nx; t += NT) {
+        const int a = t / nx, i = t - a * nx;
+        G[3 * gcs + a * cs + (size_t)y * nx + i] = gp[a * nx + i];
+        G[3 * gcs + 3 * cs + a * cs + (size_t)y * nx + i] = gm[a * nx + i];
+      }
+  }
   // --- per cell: local terms, LLG stage, force partials
   const size_t plane = (size_t)ny * nx;
   if (ext_cross && cell_row && (p.term_mask & 16)) {
@@ -1595,6 +1662,13 @@ hipError_t launch_tick(const TickArgs& tick, int stage, double dt, hipStream_t s
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_div_curl(const T* G, int nx, int ny, double dx, double dy, double dz, int pbc_y, double* part,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_div_curl<T>, dim3(ny), dim3(256), 0, st, G, nx, ny, dx, dy, dz, pbc_y, part);
+  return hipGetLastError();
+}
+
 hipError_t launch_dp_control(const TickArgs& tick, DpCtrl* ctrl, const double* errpart, int ntask, hipStream_t st) {
   hipLaunchKernelGGL(k_dp_control, dim3(1), dim3(TICK_THREADS), 0, st, tick, ctrl, errpart, ntask);
   return hipGetLastError();
@@ -1727,7 +1801,8 @@ hipError_t launch_colpack(const void* spec, T* out, int Kx, int Ly, int Kyh, con
   template hipError_t launch_col_batch<T>(const ColDesc*, const int*, int, int, size_t, hipStream_t, int, double);             \
   template hipError_t launch_row_stage_batch<T>(const RowStageDesc*, const int*, int, int, size_t, int, double,   \
                                                 bool, hipStream_t);                                             \
-  template hipError_t launch_dp_commit<T>(const T*, T*, int, size_t, const DpCtrl*, int*, hipStream_t);
+  template hipError_t launch_dp_commit<T>(const T*, T*, int, size_t, const DpCtrl*, int*, hipStream_t);         \
+  template hipError_t launch_div_curl<T>(const T*, int, int, double, double, double, int, double*, hipStream_t);
 
 MMV_INST(float)
 MMV_INST(double)
