@@ -231,6 +231,9 @@ def batched_vs_plain(steps_batch=200, steps_plain=50, graph=True):
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     groups = sorted(set(B.tuning(i) for i in range(len(descs))))
+    row_threads = {}
+    for i, d in enumerate(descs):
+        row_threads[str(d.nx)] = B.tuning(i, row_threads=True)[1]
     B.close()
     plain = cells * steps_plain / t_plain
     batched = cells * steps_batch / t_batch
@@ -241,6 +244,7 @@ def batched_vs_plain(steps_batch=200, steps_plain=50, graph=True):
             "cells": cells, "plain_cell_updates_per_s": plain,
             "batched_cell_updates_per_s": batched, "speedup": batched / plain,
             "ms_per_step_batched": step_s * 1e3, "autotuned_groups": groups,
+            "autotuned_row_threads_by_nx": row_threads,
             "roofline": {"bound": "hbm", "scope": "whole batched step (every launch of the 4 stages)",
                          "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": achieved / PEAK_HBM_GBS, "bytes_per_step": step_bytes,
@@ -487,6 +491,60 @@ def surrogate_report(train_steps=3000, B=8, steps=200, log=None):
     }
 
 
+def divcurl_study(nx=256, ny=64, gaps=(3, 5), npts=21, seed=13):
+    """Eq. 13 on the GPU: D(x) and C(x) of the base film's field sampled in the
+    slider, relative to the stationary (lattice) position, while the slider
+    moves one cell (4 nm) over a frozen random base (Sec. IV.A), for the
+    spline of the direct field, the scalar potential and linear
+    interpolation; float64 curves, the float32 maxima beside them, and the
+    time of one div_curl call (HIP events)."""
+    import numpy as np
+    import torch
+    import paper_1801_04181_amd as mmv
+    from workloads import Desc, Drive
+    from workloads.states import random_unit
+
+    rng = np.random.default_rng(seed)
+    m = [random_unit((1, ny, nx), rng), random_unit((1, ny, nx), rng)]
+    xs = [i / (npts - 1) for i in range(npts)]
+    out = {"workload": f"2 films {nx}x{ny}x1, 4 nm cells, random frozen base and slider (seed {seed}), "
+                       f"slider moved 0..1 cell in {npts - 1} steps",
+           "x_cells": xs, "runs": []}
+    for gap in gaps:
+        for mode, name in ((0, "spline"), (1, "potential"), (2, "linear")):
+            run = {"gap_cells": gap, "interpolant": name}
+            for prec in (64, 32):
+                d = Desc(n_films=2, nx=nx, ny=ny, nz=1, dx=4e-9, dy=4e-9, dz=4e-9, gap_cells=gap,
+                         max_travel_cells=2, Ms=8e5, Aex=1.3e-11, alpha=0.5, cross_mode=mode, precision=prec)
+                mesh = mmv.Mesh(d, Drive(), m)
+                rD, rC = [], []
+                D0 = C0 = None
+                for x in xs:
+                    mesh.set_offset(x)
+                    D, C = mmv.div_curl(mesh.h)
+                    if D0 is None:
+                        D0, C0 = D, C
+                    rD.append((D - D0) / D0)
+                    rC.append((C - C0) / C0)
+                if prec == 64:
+                    run.update(D0=D0, C0=C0, rel_D=rD, rel_C=rC)
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(mesh.stream)
+                    for _ in range(5):
+                        mmv.div_curl(mesh.h)
+                    e1.record(mesh.stream)
+                    torch.cuda.synchronize()
+                    run["ms_per_call_f64"] = e0.elapsed_time(e1) / 5
+                run[f"max_abs_rel_D_f{prec}"] = max(abs(v) for v in rD)
+                run[f"max_abs_rel_C_f{prec}"] = max(abs(v) for v in rC)
+                mesh.close()
+            print(f"divcurl gap {gap} {name}: max |dD/D| {run['max_abs_rel_D_f64']:.3e} "
+                  f"max |dC/C| {run['max_abs_rel_C_f64']:.3e}", file=sys.stderr, flush=True)
+            out["runs"].append(run)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -496,7 +554,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="--report batch: eager launches (counter runs)")
-    ap.add_argument("--report", choices=["precision", "surrogate", "cube", "batch", "surrogate-batched"],
+    ap.add_argument("--report", choices=["precision", "surrogate", "cube", "batch", "surrogate-batched", "divcurl"],
                     default=None)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--calib-copy", action="store_true",
@@ -513,6 +571,9 @@ def main():
                                                       graph=not args.no_graph)}), flush=True)
         if args.calib_copy:
             calib_copy()
+        return
+    if args.report == "divcurl":
+        print(json.dumps({"divcurl_study": divcurl_study()}), flush=True)
         return
     if args.report == "surrogate-batched":
         print(json.dumps({"surrogate_batched": surrogate_batched()}), flush=True)

@@ -253,12 +253,16 @@ int init_batch(const mmv_mesh_desc* descs, int n, void* hip_stream, int flags, m
 int batch_instance(mmv_batch_handle b, int i, mmv_handle* out);
 /* Advance every instance nsteps RK4 steps of size dt (llg_step semantics). */
 int batch_step(mmv_batch_handle b, double dt, int nsteps);
-/* Chosen y-pass grouping of instance i (diagnostics).                   */
-int batch_tuning(mmv_batch_handle b, int i, int* col_groups);
+/* Chosen launch shape of instance i (diagnostics): the y-pass grouping
+ * and, if row_threads is not NULL, the row kernel's threads per block (128,
+ * 256 or 512).  MMV_EINVAL for a NULL batch or col_groups or i out of
+ * range.                                                                  */
+int batch_tuning(mmv_batch_handle b, int i, int* col_groups, int* row_threads);
 /* Tuning cache for MMV_BATCH_AUTOTUNE (process-wide; NULL or "" = none).
  * A text file, one line per tuned mesh size: a key naming the device (arch,
  * CU count), the precision, the batch's size mix and the size, a tab, and
- * the chosen y-pass grouping.  init_batch reads it, times only the sizes not
+ * the chosen y-pass grouping; and one line per tuned row length (key ending
+ * in " row") with the row kernel's threads per block / 64.  init_batch reads it, times only the sizes not
  * in it and rewrites the file (temporary file + rename) with the new
  * results; malformed lines are ignored, a failed write is reported on
  * stderr and does not fail init_batch.  The path is copied.  MMV_EINVAL

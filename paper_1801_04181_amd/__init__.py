@@ -100,7 +100,7 @@ def load():
         lib.init_batch.argtypes = [ctypes.POINTER(MeshDesc), i, vp, i, ctypes.POINTER(vp)]
         lib.batch_instance.argtypes = [vp, i, ctypes.POINTER(vp)]
         lib.batch_step.argtypes = [vp, d, i]
-        lib.batch_tuning.argtypes = [vp, i, ctypes.POINTER(i)]
+        lib.batch_tuning.argtypes = [vp, i, ctypes.POINTER(i), ctypes.POINTER(i)]
         lib.set_tune_cache.argtypes = [ctypes.c_char_p]
         lib.destroy_batch.argtypes = [vp]
         lib.profile_end.argtypes = [vp, pd, ctypes.POINTER(ctypes.c_long)]
@@ -290,10 +290,13 @@ def batch_step(b, dt, nsteps=1):
     _check(load().batch_step(b, float(dt), int(nsteps)))
 
 
-def batch_tuning(b, i):
+def batch_tuning(b, i, row_threads=False):
+    """y-pass grouping of instance i, or (grouping, row kernel threads per
+    block) with row_threads=True."""
     g = ctypes.c_int()
-    _check(load().batch_tuning(b, int(i), ctypes.byref(g)))
-    return g.value
+    r = ctypes.c_int()
+    _check(load().batch_tuning(b, int(i), ctypes.byref(g), ctypes.byref(r)))
+    return (g.value, r.value) if row_threads else g.value
 
 
 def set_tune_cache(path):
@@ -338,8 +341,8 @@ class Batch:
     def state(self, i):
         return get_state(self.h[i])
 
-    def tuning(self, i):
-        return batch_tuning(self.b, i)
+    def tuning(self, i, row_threads=False):
+        return batch_tuning(self.b, i, row_threads)
 
     def close(self):
         if self.b is not None:

@@ -10,6 +10,7 @@
 #include <vector>
 #include <algorithm>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include "mmv.h"
 #include "mmv_internal.h"
@@ -93,6 +94,7 @@ struct mmv_mesh {
   int esz = 4;  // bytes per real
   int nfilm = 2, nx = 0, ny = 0;
   int Lx = 0, Ly = 0, N2x = 0, Kx = 0, Kyh = 0, ngroup = 1, M = 0;
+  int row_nt = 0;  // batched row kernel's block size (0: by row length)
   FftPlan px{}, py{};
   void* m0 = nullptr;
   void* mb[2] = {nullptr, nullptr};
@@ -1106,6 +1108,7 @@ struct BatchLaunch {
   int off = 0, n = 0, soff = 0, nblk = 0;
   size_t lds = 0;
   bool inplace = false;
+  int nt = 0;  // row kernel: threads per block
 };
 
 struct mmv_batch {
@@ -1127,6 +1130,7 @@ struct mmv_batch {
   // LDS, transform variant): small meshes are not held to the LDS of the
   // largest, so more of their blocks share a CU
   std::vector<BatchLaunch> l_fwd, l_col, l_stage;
+  std::vector<int> stage_inst;  // instance of each row-stage descriptor (class order)
   // learned operator for every instance's film-0 cross field (not owned):
   // one batched inference per RK stage over all instances
   mmv_sur* sur = nullptr;
@@ -1165,13 +1169,25 @@ RowParams stage_params(mmv_mesh* h, bool fuse) {
   return rp;
 }
 
+// Threads per block of the batched row kernel for one instance: the tuned
+// value if it is valid, else the smallest of 128, 256, 512 that is at least
+// nx (one cell per thread in the force sums, as in the single-mesh kernel).
+template <typename T>
+int batch_row_threads(const mmv_mesh* h, const RowParams& rp) {
+  if (h->row_nt >= h->nx && row_batch_threads_ok<T>(h->row_nt, rp.inplace != 0)) return h->row_nt;
+  for (int nt : {128, 256})
+    if (nt >= h->nx && row_batch_threads_ok<T>(nt, rp.inplace != 0)) return nt;
+  return 512;
+}
+
 // Rows per transform batch of the batched row kernel for one instance:
 // a direct-mode stage task needs at most 8 inverse transforms (7 except the
 // slider's first and last rows).  Pick the batch size that lets the most
-// blocks share a CU's LDS, then the largest at that occupancy (at least 3:
-// the fused forward transform of the new row's three components).
+// blocks share a CU (LDS, and 2048 threads per CU), then the largest at that
+// occupancy (at least 3: the fused forward transform of the new row's three
+// components).
 template <typename T>
-int batch_rows_per_transform(const RowParams& rp, size_t limit) {
+int batch_rows_per_transform(const RowParams& rp, size_t limit, int nt) {
   if (rp.pot) return rp.nbr;
   int best = 0, best_occ = 0;
   for (int nb = std::min(rp.nbr, 8); nb >= 3; --nb) {
@@ -1179,7 +1195,7 @@ int batch_rows_per_transform(const RowParams& rp, size_t limit) {
     q.nbr = nb;
     const size_t lds = row_lds_bytes<T>(q) + ROW_STATIC_LDS;
     if (lds > limit) continue;
-    const int occ = std::min(4, (int)((160 * 1024) / (((lds + 511) / 512) * 512)));
+    const int occ = std::min(2048 / nt, (int)((160 * 1024) / (((lds + 511) / 512) * 512)));
     if (occ > best_occ) {
       best_occ = occ;
       best = nb;
@@ -1211,7 +1227,7 @@ int batch_build(mmv_batch* b) {
   std::vector<ColDesc> col_i(n), col;
   std::vector<int> sf, sc, ss;
   std::vector<size_t> k_fwd(n), k_col(n);
-  std::vector<std::pair<size_t, int>> k_stage(n);
+  std::vector<std::tuple<size_t, int, int>> k_stage(n);
   const bool use_sur = b->sur != nullptr && !b->sur_fallback;
   const float* sur_out = use_sur ? sur_output(b->sur) : nullptr;
   b->built_sur = use_sur;
@@ -1226,7 +1242,8 @@ int batch_build(mmv_batch* b) {
     T* b1 = (T*)h->mb[0];
     T* b2 = (T*)h->mb[1];
     RowParams rp = stage_params(h, b->fuse);
-    rp.nbr = batch_rows_per_transform<T>(rp, lds_limit);
+    const int nt = batch_row_threads<T>(h, rp);
+    rp.nbr = batch_rows_per_transform<T>(rp, lds_limit, nt);
     if (use_sur) {
       // film 0's cross field from the operator's output of this instance
       rp.hsur = sur_out + (size_t)i * 3 * h->ny * h->nx;
@@ -1278,7 +1295,7 @@ int batch_build(mmv_batch* b) {
     c.tick = tick_args(h, rp.ntask);
     k_fwd[i] = row_fwd_lds_bytes(h->N2x, sizeof(T));
     k_col[i] = col_lds_bytes<T>(h->Ly, c.nbuf);
-    k_stage[i] = std::make_pair(row_lds_bytes<T>(rp), rp.inplace);
+    k_stage[i] = std::make_tuple(row_lds_bytes<T>(rp), rp.inplace, nt);
   }
   // launch classes: descriptors in class order, one block-start table each
   auto make = [&](const std::vector<std::vector<int>>& groups, std::vector<BatchLaunch>& L, std::vector<int>& st,
@@ -1300,7 +1317,8 @@ int batch_build(mmv_batch* b) {
       }
       st.push_back(acc);
       c.nblk = acc;
-      c.inplace = k_stage[g[0]].second != 0;
+      c.inplace = std::get<1>(k_stage[g[0]]) != 0;
+      c.nt = std::get<2>(k_stage[g[0]]);
       off += c.n;
       L.push_back(c);
     }
@@ -1315,9 +1333,11 @@ int batch_build(mmv_batch* b) {
        });
   make(group_by(k_col), b->l_col, sc, [&](int i) { return b->inst[i]->Kx * b->inst[i]->ngroup; },
        [&](int i) { return k_col[i]; }, [&](int i) { col.push_back(col_i[i]); });
+  b->stage_inst.clear();
   make(group_by(k_stage), b->l_stage, ss, [&](int i) { return stg_i[0][i].p.ntask; },
-       [&](int i) { return k_stage[i].first; }, [&](int i) {
+       [&](int i) { return std::get<0>(k_stage[i]); }, [&](int i) {
          for (int s = 0; s < 4; ++s) stg[s].push_back(stg_i[s][i]);
+         b->stage_inst.push_back(i);
        });
   int rc;
   if (!b->d_col) {
@@ -1349,8 +1369,8 @@ int batch_build(mmv_batch* b) {
   HIPCHK(hipStreamSynchronize(b->st));
   if (getenv("MMV_VERBOSE"))
     for (auto& c : b->l_stage)
-      fprintf(stderr, "mmv: batch row class: %d instances, %d blocks, LDS %zu, in place %d\n", c.n, c.nblk, c.lds,
-              (int)c.inplace);
+      fprintf(stderr, "mmv: batch row class: %d instances, %d blocks of %d threads, LDS %zu, in place %d\n", c.n,
+              c.nblk, c.nt, c.lds, (int)c.inplace);
   if (b->exec) {
     hipGraphExecDestroy(b->exec);
     hipGraphDestroy(b->graph);
@@ -1440,7 +1460,7 @@ int batch_sur_steps(mmv_batch* b, hipStream_t st, double dt, int nsteps, int* do
       if ((rc = batch_col_launches<T>(b, st, -1, dt))) return rc;
       for (const BatchLaunch& c : b->l_stage)
         HIPCHK(launch_row_stage_batch<T>(b->d_stage[s] + c.off, b->s_stage + c.soff, c.n, c.nblk, c.lds, s, dt,
-                                         c.inplace, st));
+                                         c.inplace, c.nt, st));
       pending = s;
     }
     b->sur_steps += 1;
@@ -1471,7 +1491,7 @@ int batch_launch_steps(mmv_batch* b, hipStream_t st, double dt, int nsteps) {
       PROF(3);
       for (const BatchLaunch& c : b->l_stage)
         HIPCHK(launch_row_stage_batch<T>(b->d_stage[s] + c.off, b->s_stage + c.soff, c.n, c.nblk, c.lds, s, dt,
-                                         c.inplace, st));
+                                         c.inplace, c.nt, st));
       PROF(3);
       pending = s;
     }
@@ -1645,6 +1665,62 @@ int batch_autotune(mmv_batch* b) {
       if (h->Kx == sz.first && h->Ly == sz.second) h->ngroup = best;
     if (!key.empty()) {
       cache[key] = best;
+      added = true;
+    }
+  }
+  // Row kernel: per row length, the block size (128, 256 or 512 threads, at
+  // least the widest nx of that length), timed over the stage-0 row launches
+  // of the whole batch (they write only stage buffers, the accumulator and
+  // the next x pass's spectra, all rewritten by the next step).  Cached as
+  // threads / 64.
+  std::vector<int> lens;
+  for (mmv_mesh* h : b->inst)
+    if (std::find(lens.begin(), lens.end(), h->N2x) == lens.end()) lens.push_back(h->N2x);
+  for (int len : lens) {
+    int nxmax = 0;
+    for (mmv_mesh* h : b->inst)
+      if (h->N2x == len) nxmax = std::max(nxmax, h->nx);
+    std::vector<int> cand;
+    for (int nt : {128, 256, 512})
+      if (nt >= nxmax && row_batch_threads_ok<T>(nt, row_inplace_length(len))) cand.push_back(nt);
+    if (cand.size() < 2) continue;
+    const std::string key = use_cache ? tune_key(b, std::make_pair(len, 0)) + " row" : std::string();
+    auto hit = key.empty() ? cache.end() : cache.find(key);
+    if (hit != cache.end()) {
+      for (mmv_mesh* h : b->inst)
+        if (h->N2x == len) h->row_nt = 64 * hit->second;
+      continue;
+    }
+    int best = cand.back();
+    float best_ms = 1e30f;
+    for (int nt : cand) {
+      for (mmv_mesh* h : b->inst)
+        if (h->N2x == len) h->row_nt = nt;
+      int rc = batch_build<T>(b);
+      if (rc) return rc;
+      auto launches = [&]() -> int {
+        for (const BatchLaunch& c : b->l_stage)
+          HIPCHK(launch_row_stage_batch<T>(b->d_stage[0] + c.off, b->s_stage + c.soff, c.n, c.nblk, c.lds, 0, 0.0,
+                                           c.inplace, c.nt, b->st));
+        return MMV_OK;
+      };
+      if ((rc = launches())) return rc;
+      HIPCHK(hipEventRecord(e0, b->st));
+      for (int r = 0; r < 5; ++r)
+        if ((rc = launches())) return rc;
+      HIPCHK(hipEventRecord(e1, b->st));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = nt;
+      }
+    }
+    for (mmv_mesh* h : b->inst)
+      if (h->N2x == len) h->row_nt = best;
+    if (!key.empty()) {
+      cache[key] = best / 64;
       added = true;
     }
   }
@@ -1936,10 +2012,17 @@ int set_tune_cache(const char* path) {
   return MMV_OK;
 }
 
-int batch_tuning(mmv_batch_handle b, int i, int* col_groups) {
+int batch_tuning(mmv_batch_handle b, int i, int* col_groups, int* row_threads) {
   if (!b || !col_groups) return fail(MMV_EINVAL, "NULL argument");
   if (i < 0 || i >= (int)b->inst.size()) return fail(MMV_EINVAL, "instance out of range");
   *col_groups = b->inst[i]->ngroup;
+  if (row_threads) {
+    int nt = 0;
+    for (const BatchLaunch& c : b->l_stage)
+      for (int k = c.off; k < c.off + c.n; ++k)
+        if (b->stage_inst[k] == i) nt = c.nt;
+    *row_threads = nt;
+  }
   return MMV_OK;
 }
 

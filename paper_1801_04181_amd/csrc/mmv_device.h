@@ -252,6 +252,18 @@ __device__ __forceinline__ int local_tid() {
   return t;
 }
 
+// A pointer read from memory (a batch descriptor, a parameter struct in
+// device memory) is a generic pointer to the compiler, and its loads and
+// stores become flat instructions (both wait counters, full 64-bit
+// addresses).  Every such pointer here addresses device global memory; the
+// round trip through the global address space lets the compiler emit global
+// instructions instead.
+template <typename P>
+__device__ __forceinline__ P* gptr(P* p) {
+  typedef __attribute__((address_space(1))) P GP;
+  return (P*)(GP*)(unsigned long long)p;
+}
+
 // Sum over the 64 lanes of a wave; the total is returned in lane 0.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -36,7 +36,11 @@ hipError_t launch_col_batch(const ColDesc* d, const int* start, int n, int nblk,
                             int tick_stage = -1, double tick_dt = 0.0);
 template <typename T>
 hipError_t launch_row_stage_batch(const RowStageDesc* d, const int* start, int n, int nblk, size_t lds, int stage,
-                                  double dt, bool inplace, hipStream_t st);
+                                  double dt, bool inplace, int nt, hipStream_t st);
+// Whether the batched row kernel exists with nt threads per block (512; 128
+// and 256 for float32 in-place row lengths).
+template <typename T>
+bool row_batch_threads_ok(int nt, bool inplace);
 // Adaptive Dormand-Prince run: end of an attempt (slider's last stage, error,
 // decision, next step) and the commit of an accepted state.
 hipError_t launch_dp_control(const TickArgs& tick, DpCtrl* ctrl, const double* errpart, int ntask, hipStream_t st);

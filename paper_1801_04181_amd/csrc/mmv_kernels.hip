@@ -156,8 +156,8 @@ __global__ void __launch_bounds__(FWD_THREADS) k_row_fwd_batch(const RowFwdDesc*
   const RowFwdDesc& q = d[i];
   const int b = bl - start[i];
   const int f = b / q.ny, y = b - f * q.ny;
-  row_fwd_body<T>(f * 3 * q.ny + y, 3, q.ny, (const T*)q.src, (cpx<T>*)q.dst, q.nin, q.N2x, q.Kx, q.P,
-                  (const cpx<T>*)q.tw, (const cpx<T>*)q.twp, q.ny);
+  row_fwd_body<T>(f * 3 * q.ny + y, 3, q.ny, gptr((const T*)q.src), gptr((cpx<T>*)q.dst), q.nin, q.N2x, q.Kx, q.P,
+                  gptr((const cpx<T>*)q.tw), gptr((const cpx<T>*)q.twp), q.ny);
 }
 
 // ------------------------------------------------------------ y pass
@@ -550,8 +550,8 @@ __global__ void __launch_bounds__(COL_THREADS) k_col_batch(const ColDesc* __rest
   const int i = find_instance(start, n, b);
   const ColDesc& q = d[i];
   if (tick_stage >= 0 && b == start[i]) tick_body(q.tick, tick_stage, tick_dt);
-  col_body<T>(b - start[i], (const cpx<T>*)q.spec1, (cpx<T>*)q.spec2, (const T*)q.kern, q.Kx, q.Ly, q.Kyh, q.ny,
-              q.nin_ch, q.ngroup, q.nbuf, q.P, (const cpx<T>*)q.twy, q.tab);
+  col_body<T>(b - start[i], gptr((const cpx<T>*)q.spec1), gptr((cpx<T>*)q.spec2), gptr((const T*)q.kern), q.Kx,
+              q.Ly, q.Kyh, q.ny, q.nin_ch, q.ngroup, q.nbuf, q.P, gptr((const cpx<T>*)q.twy), q.tab);
 }
 
 // ------------------------------------------------------------ row kernel
@@ -819,6 +819,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   const bool need_force = two && film == 1 && (cell_row || !pbc_y) &&
                           ((p.mode == MODE_STAGE && p.with_force) || p.mode == MODE_FORCE);
   const bool ext_cross = two && film == 0 && p.hsur != nullptr;
+  const float* __restrict__ hsur = gptr(p.hsur);
   const bool need_cross = two && !ext_cross && ((p.term_mask & 16) || need_force);
   // boundary force rows carried by this task (direct mode, stage launches)
   const bool xb_lo = p.mode == MODE_STAGE && need_force && !p.pot && !pbc_y && y == 0;
@@ -868,8 +869,9 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
 
   // slider offset of this stage (issued first; the slider state is written
   // only after every block of the launch has read it)
-  if (p.scheme == 1 && p.ctrl->done) return;  // adaptive run finished
-  if (p.scheme == 1) dt = p.ctrl->h;
+  const DpCtrl* ctrl = gptr(p.ctrl);
+  if (p.scheme == 1 && ctrl->done) return;  // adaptive run finished
+  if (p.scheme == 1) dt = ctrl->h;
   const double xs = rigid->xs;
   const int s_int = rigid->s_int;
   // twiddles (stw: N2x, stp: N2x + 1, contiguous): loads issued before the
@@ -967,7 +969,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
   const int nrow = s_nrow;
   // the first batch's transform inputs: issued now, consumed after the
   // spline weights
-  constexpr int CP = (sizeof(T) == 4 && 4096 / NT > 4) ? 4096 / NT : 4;
+  constexpr int CP = (sizeof(T) == 4 && 4096 / NT > 4) ? (4096 / NT > 8 ? 8 : 4096 / NT) : 4;
   C2rInputs<T, NT, CP> in0;
   const int tot0 = min(nbr, nrow) * N2x;
   in0.issue(spec2, rowo, tot0, N2x);
@@ -1175,7 +1177,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     // the base field on the slider's stencil points, for Eq. 13's
     // divergence and curl (gc holds i = -1..nx of this row; gp, gm the
     // layers z_s +- 1 on the cells)
-    T* G = reinterpret_cast<T*>(p.fieldout);
+    T* G = gptr(reinterpret_cast<T*>(p.fieldout));
     const size_t gcs = (size_t)(ny + 2) * (nx + 2), cs = (size_t)ny * nx;
 #pragma unroll 1
     for (int t = threadIdx.x; t < 3 * (nx + 2); t += NT) {
@@ -1197,7 +1199,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
 #pragma unroll 1
     for (int t = threadIdx.x; t < 3 * nx; t += NT) {
       const int c = t / nx, i = t - c * nx;
-      H[t] += sc * (T)p.hsur[(size_t)c * plane + (size_t)y * nx + i];
+      H[t] += sc * (T)hsur[(size_t)c * plane + (size_t)y * nx + i];
     }
     lds_barrier();
   }
@@ -1280,7 +1282,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
         // Dormand-Prince stage: keep k_stage; form the next stage's state
         // m_n + h sum_j a_(stage+1)j k_j (j ascending), or at the last stage
         // the error h sum_j e_j k_j
-        T* K = reinterpret_cast<T*>(p.kdp);
+        T* K = gptr(reinterpret_cast<T*>(p.kdp));
         const size_t kst = (size_t)p.nfilm * 3 * plane;
         K[stage * kst + fo] = kx;
         K[stage * kst + fo + plane] = ky;
@@ -1372,7 +1374,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     // forward real transform of the three rows (as the x pass computes it)
     lds_barrier();
     const cpx<T>* Z = row_fft<T, false, NT, INPL>(fa, fb, p.px, 3, stw);
-    cpx<T>* dst = reinterpret_cast<cpx<T>*>(p.spec1_out);
+    cpx<T>* dst = gptr(reinterpret_cast<cpx<T>*>(p.spec1_out));
     const int K1 = N2x + 1;
 #pragma unroll 1
     for (int t = threadIdx.x; t < 3 * K1; t += NT) {
@@ -1447,7 +1449,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     if (threadIdx.x == 0) {
       double m = 0.0;
       for (int w = 0; w < nw; ++w) m = (red[48 + w] > m || red[48 + w] != red[48 + w]) ? red[48 + w] : m;
-      p.errpart[task] = m;
+      gptr(p.errpart)[task] = m;
     }
   }
   if (p.mode == MODE_STAGE && p.defer_tick) {
@@ -1493,7 +1495,7 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     }
     const double F0 = p.force_scale * tot[0];
     if (p.mode == MODE_FORCE) {
-      double* Fo = p.fout != nullptr ? p.fout : rigid->F;
+      double* Fo = p.fout != nullptr ? gptr(p.fout) : rigid->F;
       for (int a = 0; a < 3; ++a) Fo[a] = p.force_scale * tot[a];
     } else {
       rigid_stage(rigid, p.drive, stage, F0, dt, p.dx, p.travel);
@@ -1516,15 +1518,20 @@ __global__ void __launch_bounds__((RowThreads<T, false>::n))
                                                     counter);
 }
 
-template <typename T, bool INPL>
-__global__ void __launch_bounds__((RowThreads<T, true>::n)) k_row_stage_batch(const RowStageDesc* __restrict__ d,
-                                                         const int* __restrict__ start, int n, int stage, double dt) {
+// NT: 512, or 128 / 256 for the float32 in-place classes of short rows
+// (more blocks per CU; the batch picks it per row length, never below nx, so
+// every thread sums at most one cell of the force and the sums equal those
+// of the single-mesh kernel bit for bit).
+template <typename T, bool INPL, int NT>
+__global__ void __launch_bounds__(NT) k_row_stage_batch(const RowStageDesc* __restrict__ d,
+                                                        const int* __restrict__ start, int n, int stage, double dt) {
   const int bl = xcd_remap(blockIdx.x, gridDim.x);
   const int i = find_instance(start, n, bl);
   const RowStageDesc& q = d[i];
-  row_stage_body<T, RowThreads<T, true>::n, INPL>(q.p, stage, dt, bl - start[i], start[i + 1] - start[i], (const cpx<T>*)q.spec2,
-                    (const T*)q.mst, (const T*)q.m0, (T*)q.mnext, (T*)q.acc, nullptr, (const cpx<T>*)q.tw,
-                    (const cpx<T>*)q.twp, q.rigid, q.partial, q.counter);
+  row_stage_body<T, NT, INPL>(q.p, stage, dt, bl - start[i], start[i + 1] - start[i], gptr((const cpx<T>*)q.spec2),
+                              gptr((const T*)q.mst), gptr((const T*)q.m0), gptr((T*)q.mnext), gptr((T*)q.acc),
+                              nullptr, gptr((const cpx<T>*)q.tw), gptr((const cpx<T>*)q.twp), gptr(q.rigid),
+                              gptr(q.partial), gptr(q.counter));
 }
 
 // ------------------------------------------------------------ kernel init (float64)
@@ -1626,9 +1633,10 @@ int col_blocks_per_cu(size_t lds) {
 template <typename T>
 bool static_lds_within_reserve() {
   hipFuncAttributes a{};
+  constexpr int NB = RowThreads<T, true>::n;
   for (const void* k : {(const void*)k_row_stage<T, false>, (const void*)k_row_stage<T, true>,
-                        (const void*)k_row_stage_batch<T, false>,
-                        (const void*)k_row_stage_batch<T, true>}) {
+                        (const void*)k_row_stage_batch<T, false, NB>, (const void*)k_row_stage_batch<T, true, NB>,
+                        (const void*)k_row_stage_batch<T, true, 128>, (const void*)k_row_stage_batch<T, true, 256>}) {
     if (hipFuncGetAttributes(&a, k) != hipSuccess || a.sharedSizeBytes > ROW_STATIC_LDS) return false;
   }
   for (const void* k : {(const void*)k_col<T>, (const void*)k_col_batch<T>}) {
@@ -1737,14 +1745,31 @@ hipError_t launch_col_batch(const ColDesc* d, const int* start, int n, int nblk,
 
 template <typename T>
 hipError_t launch_row_stage_batch(const RowStageDesc* d, const int* start, int n, int nblk, size_t lds, int stage,
-                                  double dt, bool inplace, hipStream_t st) {
-  if (inplace)
-    hipLaunchKernelGGL((k_row_stage_batch<T, true>), dim3(nblk), dim3(RowThreads<T, true>::n), lds, st, d, start, n,
-                       stage, dt);
-  else
-    hipLaunchKernelGGL((k_row_stage_batch<T, false>), dim3(nblk), dim3(RowThreads<T, true>::n), lds, st, d, start, n,
-                       stage, dt);
+                                  double dt, bool inplace, int nt, hipStream_t st) {
+  constexpr int NB = RowThreads<T, true>::n;
+  if (!inplace) {
+    hipLaunchKernelGGL((k_row_stage_batch<T, false, NB>), dim3(nblk), dim3(NB), lds, st, d, start, n, stage, dt);
+    return hipGetLastError();
+  }
+  if constexpr (sizeof(T) == 4) {
+    if (nt == 128) {
+      hipLaunchKernelGGL((k_row_stage_batch<T, true, 128>), dim3(nblk), dim3(128), lds, st, d, start, n, stage, dt);
+      return hipGetLastError();
+    }
+    if (nt == 256) {
+      hipLaunchKernelGGL((k_row_stage_batch<T, true, 256>), dim3(nblk), dim3(256), lds, st, d, start, n, stage, dt);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_row_stage_batch<T, true, NB>), dim3(nblk), dim3(NB), lds, st, d, start, n, stage, dt);
   return hipGetLastError();
+}
+
+template <typename T>
+bool row_batch_threads_ok(int nt, bool inplace) {
+  constexpr int NB = RowThreads<T, true>::n;
+  if (nt == NB) return true;
+  return sizeof(T) == 4 && inplace && (nt == 128 || nt == 256);
 }
 
 // Dynamic-LDS limits of the batched kernels, set outside any graph capture.
@@ -1755,7 +1780,9 @@ hipError_t prepare_batch_kernels(size_t lds_fwd, size_t lds_col, size_t lds_stag
     e = hipFuncSetAttribute((const void*)k_row_fwd_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_fwd);
   if (e == hipSuccess && lds_col > 65536)
     e = hipFuncSetAttribute((const void*)k_col_batch<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_col);
-  for (const void* k : {(const void*)k_row_stage_batch<T, false>, (const void*)k_row_stage_batch<T, true>})
+  constexpr int NB = RowThreads<T, true>::n;
+  for (const void* k : {(const void*)k_row_stage_batch<T, false, NB>, (const void*)k_row_stage_batch<T, true, NB>,
+                        (const void*)k_row_stage_batch<T, true, 128>, (const void*)k_row_stage_batch<T, true, 256>})
     if (e == hipSuccess && lds_stage > 65536)
       e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_stage);
   return e;
@@ -1800,7 +1827,8 @@ hipError_t launch_colpack(const void* spec, T* out, int Kx, int Ly, int Kyh, con
   template hipError_t launch_row_fwd_batch<T>(const RowFwdDesc*, const int*, int, int, size_t, hipStream_t);      \
   template hipError_t launch_col_batch<T>(const ColDesc*, const int*, int, int, size_t, hipStream_t, int, double);             \
   template hipError_t launch_row_stage_batch<T>(const RowStageDesc*, const int*, int, int, size_t, int, double,   \
-                                                bool, hipStream_t);                                             \
+                                                bool, int, hipStream_t);                                        \
+  template bool row_batch_threads_ok<T>(int, bool);                                                             \
   template hipError_t launch_dp_commit<T>(const T*, T*, int, size_t, const DpCtrl*, int*, hipStream_t);         \
   template hipError_t launch_div_curl<T>(const T*, int, int, double, double, double, int, double*, hipStream_t);
 

@@ -97,8 +97,11 @@ def test_autotune_choice_is_valid_and_harmless():
     T = mmv.Batch(descs, drives, ms, flags=mmv.BATCH_AUTOTUNE)
     U = mmv.Batch(descs, drives, ms)
     groups = [T.tuning(i) for i in range(len(pairs))]
-    print("autotuned groups", groups, flush=True)
+    rows = [T.tuning(i, row_threads=True)[1] for i in range(len(pairs))]
+    print("autotuned groups", groups, "row threads", rows, flush=True)
     assert all(1 <= g <= 4 for g in groups)
+    for nt, d in zip(rows, descs):
+        assert nt in (128, 256, 512) and nt >= min(d.nx, 512), (nt, d.nx)
     T.step(1e-13, 5)
     U.step(1e-13, 5)
     torch.cuda.synchronize()
@@ -127,15 +130,19 @@ def test_tuning_cache_is_written_and_read_back(tmp_path):
         T.close()
         lines = path.read_text().splitlines()
         print("cache", lines, flush=True)
-        assert len(lines) == len(sizes)
-        stored = {}
+        stored, row_lines = {}, {}
         for ln in lines:
             key, g = ln.split("\t")
             assert "gfx" in key and " f32 " in key
-            stored[key] = int(g)
+            (row_lines if key.endswith(" row") else stored)[key] = int(g)
+        assert len(stored) == len(sizes)
         assert set(stored.values()) <= set(groups)
-        # edit every entry to another valid grouping
+        # row lengths with more than one block size to choose from: 72 and
+        # 140 points (nx 64 and 128; 128, 256 or 512 threads), 270 (nx 256)
+        assert len(row_lines) == 3 and set(row_lines.values()) <= {2, 4, 8}
+        # edit every grouping to another valid one; keep the row entries
         edited = {k: (3 if g != 3 else 1) for k, g in stored.items()}
+        edited.update(row_lines)
         path.write_text("".join(f"{k}\t{g}\n" for k, g in edited.items()) + "malformed line\n")
         U = mmv.Batch(descs, drives, ms, flags=mmv.BATCH_AUTOTUNE)
         regroup = [U.tuning(i) for i in range(len(pairs))]
