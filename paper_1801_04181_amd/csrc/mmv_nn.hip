@@ -23,39 +23,104 @@ __device__ __forceinline__ short to_bf16(float f) {
   return (short)(u >> 16);
 }
 
-// One 64-lane wave computes a 32 x 32 tile; a block of four waves a 64 x 64
-// tile.  Lane l feeds A(i, k) with i = l % 32, k = k0 + 4 (l / 32) + v and
-// B(k, j) with j = l % 32; accumulator register r holds
+// Block of four 64-lane waves, WM x WN waves of 32 x 32 output tiles each
+// (64 x 64, or 128 x 32 / 32 x 128 for a narrow N / M).  K advances in
+// chunks of KC: the block loads the A and B pieces of a chunk with every
+// element's load in flight at once, along whichever index is contiguous in
+// memory (coalesced for row- and column-major views alike), rounds them to
+// bfloat16 into LDS, and while the matrix cores consume the chunk from LDS
+// the next chunk's loads are already issued.  Each wave's accumulation runs
+// through the same 8-wide k steps in the same order as a single-wave loop.
+// MFMA operands: lane l feeds A(i, k) with i = l % 32, k = k0 + 4 (l / 32) + v
+// and B(k, j) with j = l % 32; accumulator register r holds
 // C(8 (r / 4) + 4 (l / 32) + r % 4, l % 32).
-__global__ void __launch_bounds__(256)
-    k_gemm_bf16(GemmArgs g) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+constexpr int GEMM_KC = 32;
+constexpr int GEMM_PAD = 4;  // bf16 elements of padding per LDS row
+
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <int WM, int WN>
+__global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
+  constexpr int TM = 32 * WM, TN = 32 * WN, KC = GEMM_KC, RS = KC + GEMM_PAD;
+  constexpr int NA = TM * KC / 256, NB = TN * KC / 256;  // elements per thread and chunk
+  __shared__ __align__(16) short sA[TM * RS];
+  __shared__ __align__(16) short sB[TN * RS];
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wave = t >> 6;
   const int nsplit = g.kchunk > 0 ? (g.K + g.kchunk - 1) / g.kchunk : 1;
   const long long b = blockIdx.z / nsplit;
   const int split = blockIdx.z - (int)b * nsplit;
   const int kbeg = g.kchunk > 0 ? split * g.kchunk : 0;
   const int kend = g.kchunk > 0 ? min(g.K, kbeg + g.kchunk) : g.K;
-  const int m0 = blockIdx.y * 64 + (wave >> 1) * 32;
-  const int n0 = blockIdx.x * 64 + (wave & 1) * 32;
+  const int bm0 = blockIdx.y * TM, bn0 = blockIdx.x * TN;
   const float* A = g.A + b * g.sa;
   const float* B = g.B + b * g.sb;
   float* C = g.C + b * g.sc + split * g.ps;
-  const int li = lane & 31, lk = (lane >> 5) * 4;
-  const int mi = m0 + li, nj = n0 + li;
-  f32x16 acc;
-  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  for (int k0 = kbeg; k0 < kend; k0 += 8) {
-    bf16x4 av, bv;
-    for (int v = 0; v < 4; ++v) {
-      const int k = k0 + lk + v;
-      const float a = (mi < g.M && k < kend) ? A[(long long)mi * g.am + (long long)k * g.ak] : 0.0f;
-      const float bb = (nj < g.N && k < kend) ? B[(long long)k * g.bk + (long long)nj * g.bn] : 0.0f;
-      av[v] = to_bf16(a);
-      bv[v] = to_bf16(bb);
+  // element e of a chunk -> (row, k): k fastest where it is contiguous
+  const bool a_kfast = g.ak == 1, b_kfast = g.bn != 1;
+  float ra[NA], rb[NB];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = t + 256 * u;
+      const int m = a_kfast ? e / KC : e % TM, k = a_kfast ? e % KC : e / TM;
+      const int gm = bm0 + m, gk = k0 + k;
+      ra[u] = (gm < g.M && gk < kend) ? A[(long long)gm * g.am + (long long)gk * g.ak] : 0.0f;
     }
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = t + 256 * u;
+      const int n = b_kfast ? e / KC : e % TN, k = b_kfast ? e % KC : e / TN;
+      const int gn = bn0 + n, gk = k0 + k;
+      rb[u] = (gn < g.N && gk < kend) ? B[(long long)gk * g.bk + (long long)gn * g.bn] : 0.0f;
+    }
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = t + 256 * u;
+      const int m = a_kfast ? e / KC : e % TM, k = a_kfast ? e % KC : e / TM;
+      sA[m * RS + k] = to_bf16(ra[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = t + 256 * u;
+      const int n = b_kfast ? e / KC : e % TN, k = b_kfast ? e % KC : e / TN;
+      sB[n * RS + k] = to_bf16(rb[u]);
+    }
+  };
+  const int wm = wave / WN, wn = wave % WN;
+  const int li = lane & 31, lk = (lane >> 5) * 4;
+  const short* pa = sA + (wm * 32 + li) * RS + lk;
+  const short* pb = sB + (wn * 32 + li) * RS + lk;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  if (kbeg < kend) load(kbeg);
+#pragma unroll 1
+  for (int k0 = kbeg; k0 < kend; k0 += KC) {
+    store();
+    lds_sync();
+    if (k0 + KC < kend) load(k0 + KC);
+    // k steps past kend hold zeros in both operands
+    const int nk = min(KC, ((kend - k0) + 7) & ~7);
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 8) {
+      if (kk < nk) {
+        const bf16x4 av = *reinterpret_cast<const bf16x4*>(pa + kk);
+        const bf16x4 bv = *reinterpret_cast<const bf16x4*>(pb + kk);
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+      }
+    }
+    lds_sync();
   }
+  const int m0 = bm0 + wm * 32, n0 = bn0 + wn * 32;
+#pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = m0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
     const int j = n0 + (lane & 31);
@@ -66,11 +131,96 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// Small products (M, N <= 32; the batched transforms over the kept modes):
+// one 32 x 32 output tile per block, K in chunks of 128 whose loads are all in
+// flight at once, and the four waves taking interleaved 8-wide k steps of a
+// chunk (wave w: steps w, w + 4, ...); their partial tiles are summed in
+// wave order at the end.
+__global__ void __launch_bounds__(256) k_gemm_bf16_small(GemmArgs g) {
+  constexpr int KC = 128, RS = KC + GEMM_PAD, NE = 32 * KC / 256;
+  __shared__ __align__(16) short sA[32 * RS];
+  __shared__ __align__(16) short sB[32 * RS];
+  __shared__ float red[3][16][64];
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wave = t >> 6;
+  const int nsplit = g.kchunk > 0 ? (g.K + g.kchunk - 1) / g.kchunk : 1;
+  const long long b = blockIdx.z / nsplit;
+  const int split = blockIdx.z - (int)b * nsplit;
+  const int kbeg = g.kchunk > 0 ? split * g.kchunk : 0;
+  const int kend = g.kchunk > 0 ? min(g.K, kbeg + g.kchunk) : g.K;
+  const float* A = g.A + b * g.sa;
+  const float* B = g.B + b * g.sb;
+  float* C = g.C + b * g.sc + split * g.ps;
+  const bool a_kfast = g.ak == 1, b_kfast = g.bn != 1;
+  const int li = lane & 31, lk = (lane >> 5) * 4;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll 1
+  for (int k0 = kbeg; k0 < kend; k0 += KC) {
+    float ra[NE], rb[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = t + 256 * u;
+      const int m = a_kfast ? e / KC : e % 32, k = a_kfast ? e % KC : e / 32;
+      ra[u] = (m < g.M && k0 + k < kend) ? A[(long long)m * g.am + (long long)(k0 + k) * g.ak] : 0.0f;
+      const int n = b_kfast ? e / KC : e % 32, kb = b_kfast ? e % KC : e / 32;
+      rb[u] = (n < g.N && k0 + kb < kend) ? B[(long long)(k0 + kb) * g.bk + (long long)n * g.bn] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = t + 256 * u;
+      const int m = a_kfast ? e / KC : e % 32, k = a_kfast ? e % KC : e / 32;
+      sA[m * RS + k] = to_bf16(ra[u]);
+      const int n = b_kfast ? e / KC : e % 32, kb = b_kfast ? e % KC : e / 32;
+      sB[n * RS + kb] = to_bf16(rb[u]);
+    }
+    lds_sync();
+    const int nk = min(KC, ((kend - k0) + 7) & ~7);
+#pragma unroll
+    for (int kk = 8 * wave; kk < KC; kk += 32) {
+      if (kk < nk) {
+        const bf16x4 av = *reinterpret_cast<const bf16x4*>(sA + li * RS + lk + kk);
+        const bf16x4 bv = *reinterpret_cast<const bf16x4*>(sB + li * RS + lk + kk);
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+      }
+    }
+    lds_sync();
+  }
+  if (wave > 0)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) red[wave - 1][r][lane] = acc[r];
+  lds_sync();
+  if (wave == 0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float v = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
+      const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      const int j = lane & 31;
+      if (i < g.M && j < g.N) {
+        float* c = C + (long long)i * g.cm + (long long)j * g.cn;
+        *c = g.alpha * v + (g.beta != 0.0f ? g.beta * *c : 0.0f);
+      }
+    }
+  }
+}
+
 hipError_t launch_gemm(const GemmArgs& g, int batch, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0 || batch <= 0) return hipSuccess;
   const int nsplit = g.kchunk > 0 ? (g.K + g.kchunk - 1) / g.kchunk : 1;
-  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, batch * nsplit);
-  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, g);
+  if (g.M <= 32 && g.N <= 32 && g.K > 32) {
+    hipLaunchKernelGGL(k_gemm_bf16_small, dim3(1, 1, batch * nsplit), dim3(256), 0, st, g);
+  } else if (g.N <= 32) {
+    dim3 grid((g.N + 31) / 32, (g.M + 127) / 128, batch * nsplit);
+    hipLaunchKernelGGL((k_gemm_bf16<4, 1>), grid, dim3(256), 0, st, g);
+  } else if (g.M <= 32) {
+    dim3 grid((g.N + 127) / 128, (g.M + 31) / 32, batch * nsplit);
+    hipLaunchKernelGGL((k_gemm_bf16<1, 4>), grid, dim3(256), 0, st, g);
+  } else {
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, batch * nsplit);
+    hipLaunchKernelGGL((k_gemm_bf16<2, 2>), grid, dim3(256), 0, st, g);
+  }
   return hipGetLastError();
 }
 

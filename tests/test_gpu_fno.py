@@ -36,6 +36,10 @@ def rel(a, b):
     (70, 100, 45, False, False, False),    # ragged in every dimension
     (70, 100, 45, True, True, False),      # transposed operands
     (33, 65, 129, False, True, True),      # transposed output
+    (200, 17, 300, False, True, False),    # narrow N: 128 x 32 block tiles
+    (20, 150, 70, True, False, True),      # narrow M: 32 x 128 block tiles
+    (32, 16, 256, True, False, False),     # small product, k steps split over the waves
+    (20, 30, 300, False, True, True),      # small, ragged, three k chunks
     (1, 1, 1, False, False, False)])
 def test_gemm_matches_float64_of_rounded_operands(M, N, K, ta, tb, tc):
     import paper_1801_04181_amd as mmv
