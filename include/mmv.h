@@ -144,6 +144,24 @@ int set_offset(mmv_handle h, double x_cells);
  * rebuilt before its next batch_step.                                   */
 int set_drive(mmv_handle h, const mmv_drive* drv);
 
+/* Non-uniform applied field (Sec. II.A), added to the Zeeman term (with the
+ * uniform Hext of the descriptor).  The field does not move with either
+ * film; it is given on the fixed lattice.
+ *   film 0: field[3][ny][nx] (SoA, mesh precision) on the base film's cells.
+ *   film 1: field[3][ny][nx + 2 W], W = max_travel_cells + halo, on the
+ *           slider's layer.  Column c is lattice x index c - W; with
+ *           periodic x (pbc bit 0) it is [3][ny][nx], the period.
+ * The slider's cells take the field at their moved positions, interpolated
+ * along x like the cross field: same window and mirror ends, the cubic
+ * B-spline (cross_mode 0, 1) or linear interpolation (cross_mode 2).  The
+ * force of Eq. 3 does not include this field.
+ * The array (host or device memory) is copied, stream-ordered, on the mesh's
+ * stream into a buffer the library owns; NULL removes the field.
+ * MMV_EINVAL if film is out of range; MMV_ESTATE on the single-magnet 3-D
+ * path.  On a batch instance, the batch's descriptors are rebuilt before
+ * its next batch_step.                                                  */
+int set_hext_field(mmv_handle h, int film, const void* field);
+
 /* Effective field of one film at the current state: the sum of the terms
  * in term_mask (MMV_TERM_*), in A/m, written to h_dev (SoA, mesh
  * precision).  The cross term is the other film's stray field sampled at

@@ -24,6 +24,8 @@ framework") step by step:
   periodic.py          periodic in-plane boundaries: image-summed kernels,
                        periodic windows (halo copies), periodic exchange
   divcurl.py           divergence / curl of the interpolated field, Eq. (13)
+  applied.py           non-uniform applied field sampled in the moving
+                       magnet (Sec. II.A)
   fno.py               learned stray-field operator (Fourier neural
                        operator standing in for the cross term), float64
                        torch with autograd gradients
@@ -33,7 +35,8 @@ no independent pin say "parity unpinned".
 """
 from .constants import MU0, GAMMA_E, GAMMA0
 from . import newell, potential_kernel, convolution, spline, fields, llg, sim, fno, dormand_prince, periodic, divcurl
+from . import applied
 
 __all__ = ["MU0", "GAMMA_E", "GAMMA0", "newell", "potential_kernel",
            "convolution", "spline", "fields", "llg", "sim", "fno", "dormand_prince",
-           "periodic", "divcurl"]
+           "periodic", "divcurl", "applied"]

@@ -78,6 +78,9 @@ class System:
         # optional replacement of the base film's cross field: a callable
         # (m_slider, x_s) -> H [A/m] (used to compose with the learned operator)
         self.base_cross = None
+        # non-uniform applied field (oracle/applied.py): film 0 on its cells,
+        # the slider's layer on the frame lattice; None = uniform Hext only
+        self.hext_fields = [None, None]
         if desc.sigma > 0:
             from .eddy import EddyState
             self.eddy = EddyState(desc)
@@ -256,6 +259,11 @@ class System:
                 "demag_cross": np.zeros_like(m),
                 "eddy": np.zeros_like(m),
             })
+        if self.hext_fields[0] is not None:
+            out[0]["zeeman"] = out[0]["zeeman"] + np.asarray(self.hext_fields[0], dtype=np.float64)[:, None]
+        if d.n_films == 2 and self.hext_fields[1] is not None:
+            from .applied import slider_samples
+            out[1]["zeeman"] = out[1]["zeeman"] + slider_samples(d, self.hext_fields[1], x, s_int)[:, None]
         F = np.zeros(3)
         if d.n_films == 2:
             Hb, Hs, F = self.cross_fields(m_list[0], m_list[1], x, s_int,

@@ -10,7 +10,7 @@ import ctypes
 import os
 
 __all__ = ["MMVError", "lib_path", "load", "MeshDesc", "DriveDesc", "init_mesh",
-           "set_m", "get_m", "set_offset", "set_drive", "eval_heff", "llg_step", "llg_run_dp",
+           "set_m", "get_m", "set_offset", "set_drive", "set_hext_field", "eval_heff", "llg_step", "llg_run_dp",
            "stray_force", "stray_force_noalloc", "div_curl", "get_state", "get_fft_lengths", "destroy_mesh",
            "profile_begin", "profile_end", "profile_repeat", "init_batch", "batch_instance", "batch_step",
            "batch_tuning", "set_tune_cache", "destroy_batch", "Batch", "batch_sur_attach", "batch_sur_status", "SurDesc", "sur_create", "sur_param_count",
@@ -25,7 +25,7 @@ TERM = dict(exchange=1, anisotropy=2, zeeman=4, demag_self=8, demag_cross=16,
             eddy=32, all=63)
 ERRORS = {-1: "MMV_EINVAL", -2: "MMV_ENOMEM", -3: "MMV_EHIP", -4: "MMV_ERANGE",
           -5: "MMV_ENUMERIC", -6: "MMV_ESTATE"}
-EXPORTS = ("init_mesh", "set_m", "get_m", "set_offset", "set_drive", "eval_heff",
+EXPORTS = ("init_mesh", "set_m", "get_m", "set_offset", "set_drive", "set_hext_field", "eval_heff",
            "llg_step", "llg_run_dp", "stray_force", "stray_force_noalloc", "div_curl", "get_state", "profile_begin", "profile_end",
            "get_fft_lengths", "profile_repeat", "init_batch", "batch_instance", "batch_step", "batch_tuning",
            "set_tune_cache", "destroy_batch", "destroy_mesh", "sur_create", "sur_param_count", "sur_param_offsets",
@@ -88,6 +88,7 @@ def load():
         lib.set_offset.argtypes = [vp, d]
         lib.set_drive.argtypes = [vp, ctypes.POINTER(DriveDesc)]
         lib.eval_heff.argtypes = [vp, i, i, vp]
+        lib.set_hext_field.argtypes = [vp, i, vp]
         lib.llg_step.argtypes = [vp, d, i]
         lib.llg_run_dp.argtypes = [vp, d, d, pd, i, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]
         lib.stray_force.argtypes = [vp, pd]
@@ -193,6 +194,13 @@ def set_offset(h, x_cells):
 def set_drive(h, drv):
     cd = drv if isinstance(drv, DriveDesc) else to_drive(drv)
     _check(load().set_drive(h, ctypes.byref(cd)))
+
+
+def set_hext_field(h, film, field):
+    """Non-uniform applied field of one film (a tensor in the mesh precision,
+    [3][ny][nx] for film 0, [3][ny][nx + 2 (max_travel_cells + halo)] for the
+    slider's layer, [3][ny][nx] with periodic x), or None to remove it."""
+    _check(load().set_hext_field(h, int(film), None if field is None else _ptr(field)))
 
 
 def eval_heff(h, film, term_mask, out):
@@ -384,6 +392,14 @@ class Mesh:
         out = self.torch.empty(self.shape, dtype=self.dtype, device=self.device)
         get_m(self.h, film, out)
         return out
+
+    def set_hext_field(self, film, field):
+        if field is None:
+            set_hext_field(self.h, film, None)
+            return
+        t = self.torch.as_tensor(field, dtype=self.dtype).to(self.device).contiguous()
+        set_hext_field(self.h, film, t)
+        self.stream.synchronize()
 
     def eval_heff(self, film, mask=63):
         out = self.torch.empty(self.shape, dtype=self.dtype, device=self.device)

@@ -95,6 +95,8 @@ struct mmv_mesh {
   int nfilm = 2, nx = 0, ny = 0;
   int Lx = 0, Ly = 0, N2x = 0, Kx = 0, Kyh = 0, ngroup = 1, M = 0;
   int row_nt = 0;  // batched row kernel's block size (0: by row length)
+  void* hext_buf[2] = {nullptr, nullptr};  // non-uniform applied field per film (owned)
+  long hext_gen = 0;                       // bumped by every set_hext_field
   FftPlan px{}, py{};
   void* m0 = nullptr;
   void* mb[2] = {nullptr, nullptr};
@@ -1141,6 +1143,7 @@ struct mmv_batch {
   float* sur_exact = nullptr;  // [n][3][ny][nx]
   bool built_sur = false;      // the descriptors read the operator's output
   std::vector<DriveP> drive_sig;  // drives the stage and tick descriptors were built for
+  std::vector<long> hext_sig;     // applied-field generations they were built for
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   double g_dt = 0.0;
@@ -1232,12 +1235,14 @@ int batch_build(mmv_batch* b) {
   const float* sur_out = use_sur ? sur_output(b->sur) : nullptr;
   b->built_sur = use_sur;
   b->drive_sig.assign(n, DriveP{});
+  b->hext_sig.assign(n, 0);
   b->fuse = true;
   for (int i = 0; i < n; ++i) b->fuse = b->fuse && b->inst[i]->fuse_fwd;
   const size_t lds_limit = LDS_PER_CU - ROW_STATIC_LDS;
   for (int i = 0; i < n; ++i) {
     mmv_mesh* h = b->inst[i];
     b->drive_sig[i] = h->drive;
+    b->hext_sig[i] = h->hext_gen;
     T* m0 = (T*)h->m0;
     T* b1 = (T*)h->mb[0];
     T* b2 = (T*)h->mb[1];
@@ -1512,7 +1517,7 @@ int batch_step_typed(mmv_batch* b, double dt, int nsteps) {
   // set_drive since they were built rebuilds them (and drops the graph)
   bool rebuild = b->built_sur != (b->sur != nullptr && !b->sur_fallback);
   for (size_t i = 0; i < b->inst.size(); ++i)
-    if (!same_drive(b->inst[i]->drive, b->drive_sig[i])) rebuild = true;
+    if (!same_drive(b->inst[i]->drive, b->drive_sig[i]) || b->inst[i]->hext_gen != b->hext_sig[i]) rebuild = true;
   if (rebuild) {
     int rc = batch_build<T>(b);
     if (rc) return rc;
@@ -2152,6 +2157,33 @@ int set_drive(mmv_handle h, const mmv_drive* drv) {
   h->drive.gamma_v = drv->gamma_v;
   h->drive.xa0 = drv->x_anchor0;
   return write_rigid(h, r);
+}
+
+int set_hext_field(mmv_handle h, int film, const void* field) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (h->cube) return fail(MMV_ESTATE, "the applied-field array belongs to the film path");
+  if (film < 0 || film >= h->nfilm) return fail(MMV_EINVAL, "film out of range");
+  const bool px = (h->d.pbc & 1) != 0;
+  const int w = (film == 0 || px) ? h->nx : h->nx + 2 * (h->rp_hot.travel + h->d.halo);
+  const size_t bytes = (size_t)3 * h->ny * w * h->esz;
+  void* buf = nullptr;
+  if (field) {
+    if (!h->hext_buf[film] && (rc = dalloc(h, &h->hext_buf[film], bytes))) return rc;
+    HIPCHK(hipMemcpyAsync(h->hext_buf[film], field, bytes, hipMemcpyDefault, h->st));
+    buf = h->hext_buf[film];
+  }
+  for (RowParams* rp : {&h->rp_hot, &h->rp_force}) {
+    if (film == 0) {
+      rp->hext_b = buf;
+    } else {
+      rp->hext_s = buf;
+      rp->hext_w = w;
+      rp->hext_off = px ? 0 : h->rp_hot.travel + h->d.halo;
+    }
+  }
+  h->hext_gen += 1;
+  return MMV_OK;
 }
 
 int eval_heff(mmv_handle h, int film, int term_mask, void* h_dev) {

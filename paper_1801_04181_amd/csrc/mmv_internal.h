@@ -156,6 +156,13 @@ struct RowParams {
   // [3][ny+2][nx+2], then layers z_s+1 and z_s-1 on the cells [3][ny][nx]
   // each (mesh precision)
   void* fieldout;
+  // non-uniform applied field (mesh precision), added to the Zeeman term:
+  // film 0 [3][ny][nx] on its cells; the slider's layer [3][ny][hext_w] on
+  // the frame lattice, column c at lattice x c - hext_off (periodic x: the
+  // period, indices modulo nx).  Null: the uniform hext only.
+  const void* hext_b;
+  const void* hext_s;
+  int hext_w, hext_off;
 };
 
 // Per-instance descriptors of the batched launches (device memory).

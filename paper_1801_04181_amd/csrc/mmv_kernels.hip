@@ -1132,6 +1132,56 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
     lds_barrier();
   }
 
+  // non-uniform applied field (Sec. II.A): the base film's cells take the
+  // frame values; the slider's cells the samples of the frame field at their
+  // moved positions, interpolated along x like its cross field (same window,
+  // mirror ends and weights)
+  if (cell_row && (p.term_mask & 4)) {
+    if (film == 0 && p.hext_b != nullptr) {
+      const T* src = gptr(reinterpret_cast<const T*>(p.hext_b)) + (size_t)y * nx;
+#pragma unroll 1
+      for (int t = threadIdx.x; t < 3 * nx; t += NT) {
+        const int c = t / nx, i = t - c * nx;
+        H[t] += src[(size_t)c * ny * nx + i];
+      }
+      lds_barrier();
+    } else if (film == 1 && p.hext_s != nullptr) {
+      constexpr int NOH = sizeof(T) == 4 ? 3 : 2;
+      const T* src = gptr(reinterpret_cast<const T*>(p.hext_s)) + (size_t)y * p.hext_w;
+      const size_t cs = (size_t)ny * p.hext_w;
+      const float invMW = 1.0f / (float)MW;
+      const int nch = (nx + NOH - 1) / NOH;
+      for (int c0 = 0; c0 < 3; c0 += nbr) {
+        const int nc = min(nbr, 3 - c0);
+#pragma unroll 1
+        for (int t = threadIdx.x; t < nc * MW; t += NT) {
+          const int r = fdiv(t, invMW), k = t - r * MW;
+          int w = k - E;
+          if (w < 0 || w >= M) w = reflect_idx(w, M);
+          int X = W0f + w;
+          if (pbc_x) {
+            X %= nx;
+            if (X < 0) X += nx;
+          } else {
+            X += p.hext_off;
+          }
+          ext[(size_t)r * MWS + k] = src[(size_t)(c0 + r) * cs + X];
+        }
+        lds_barrier();
+#pragma unroll 1
+        for (int t = threadIdx.x; t < nc * nch; t += NT) {
+          const int r = t / nch, i0 = NOH * (t - r * nch);
+          T v[NOH];
+          fir_evaln<T, K, NOH>(ext + (size_t)r * MWS, gs, i0 + h + ifs, E, v);
+#pragma unroll
+          for (int j = 0; j < NOH; ++j)
+            if (i0 + j < nx) H[(c0 + r) * nx + i0 + j] += v[j];
+        }
+        lds_barrier();
+      }
+    }
+  }
+
   if (need_cross && p.pot) {
     // H = -grad phi with the four-point central difference on the shifted
     // lattice (far field from the scalar potential, Sec. III.A)
