@@ -162,6 +162,31 @@ int set_drive(mmv_handle h, const mmv_drive* drv);
  * its next batch_step.                                                  */
 int set_hext_field(mmv_handle h, int film, const void* field);
 
+/* Tricubic B-spline of a scalar field on a 3-D lattice (Sec. III.A's
+ * spline, here along all three axes; the 4 x 4 x 4 nearest-neighbour
+ * evaluation of Sec. IV.D), for interpolation at arbitrary displacements.
+ * field, coef, work: device [nz][ny][nx] arrays of the precision (32 or
+ * 64).  The lattice point (i, j, k) sits at (x, y, z) = (i, j, k) in cells.
+ *
+ * spline3_prefilter: coef = the coefficients whose spline passes through
+ * field.  Prefilter along x, then y, then z: the exact inverse of the
+ * B-spline's sampling filter with whole-sample mirror ends, truncated below
+ * the precision's rounding.  work is scratch.  The three arrays must not
+ * overlap.
+ *
+ * spline3_gather: out[p] = sum over the 4 x 4 x 4 nearest coefficients of
+ * beta3(x - i) beta3(y - j) beta3(z - k) c[k][j][i], for points[p] =
+ * (x, y, z), [npts][3], device, in the precision.  Points outside the box
+ * use the mirror extension.
+ *
+ * Both are asynchronous on hip_stream.  MMV_EINVAL for a bad precision, a
+ * size < 1 or of 2^31 elements or more, NULL buffers, npts < 0, or
+ * overlapping prefilter buffers.                                         */
+int spline3_prefilter(int precision, const void* field, void* coef, void* work, int nx, int ny, int nz,
+                      void* hip_stream);
+int spline3_gather(int precision, const void* coef, int nx, int ny, int nz, const void* points, int npts, void* out,
+                   void* hip_stream);
+
 /* Effective field of one film at the current state: the sum of the terms
  * in term_mask (MMV_TERM_*), in A/m, written to h_dev (SoA, mesh
  * precision).  The cross term is the other film's stray field sampled at

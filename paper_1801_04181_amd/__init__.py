@@ -11,6 +11,7 @@ import os
 
 __all__ = ["MMVError", "lib_path", "load", "MeshDesc", "DriveDesc", "init_mesh",
            "set_m", "get_m", "set_offset", "set_drive", "set_hext_field", "eval_heff", "llg_step", "llg_run_dp",
+           "spline3_prefilter", "spline3_gather",
            "stray_force", "stray_force_noalloc", "div_curl", "get_state", "get_fft_lengths", "destroy_mesh",
            "profile_begin", "profile_end", "profile_repeat", "init_batch", "batch_instance", "batch_step",
            "batch_tuning", "set_tune_cache", "destroy_batch", "Batch", "batch_sur_attach", "batch_sur_status", "SurDesc", "sur_create", "sur_param_count",
@@ -26,6 +27,7 @@ TERM = dict(exchange=1, anisotropy=2, zeeman=4, demag_self=8, demag_cross=16,
 ERRORS = {-1: "MMV_EINVAL", -2: "MMV_ENOMEM", -3: "MMV_EHIP", -4: "MMV_ERANGE",
           -5: "MMV_ENUMERIC", -6: "MMV_ESTATE"}
 EXPORTS = ("init_mesh", "set_m", "get_m", "set_offset", "set_drive", "set_hext_field", "eval_heff",
+           "spline3_prefilter", "spline3_gather",
            "llg_step", "llg_run_dp", "stray_force", "stray_force_noalloc", "div_curl", "get_state", "profile_begin", "profile_end",
            "get_fft_lengths", "profile_repeat", "init_batch", "batch_instance", "batch_step", "batch_tuning",
            "set_tune_cache", "destroy_batch", "destroy_mesh", "sur_create", "sur_param_count", "sur_param_offsets",
@@ -89,6 +91,8 @@ def load():
         lib.set_drive.argtypes = [vp, ctypes.POINTER(DriveDesc)]
         lib.eval_heff.argtypes = [vp, i, i, vp]
         lib.set_hext_field.argtypes = [vp, i, vp]
+        lib.spline3_prefilter.argtypes = [i, vp, vp, vp, i, i, i, vp]
+        lib.spline3_gather.argtypes = [i, vp, i, i, i, vp, i, vp, vp]
         lib.llg_step.argtypes = [vp, d, i]
         lib.llg_run_dp.argtypes = [vp, d, d, pd, i, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]
         lib.stray_force.argtypes = [vp, pd]
@@ -201,6 +205,32 @@ def set_hext_field(h, film, field):
     [3][ny][nx] for film 0, [3][ny][nx + 2 (max_travel_cells + halo)] for the
     slider's layer, [3][ny][nx] with periodic x), or None to remove it."""
     _check(load().set_hext_field(h, int(film), None if field is None else _ptr(field)))
+
+
+def _prec(t):
+    import torch
+    if t.dtype == torch.float64:
+        return 64
+    if t.dtype == torch.float32:
+        return 32
+    raise TypeError("float32 or float64 tensors")
+
+
+def spline3_prefilter(field, coef, work, stream=None):
+    """coef <- spline coefficients of field ([nz][ny][nx] tensors of one
+    precision on the device); work is scratch."""
+    nz, ny, nx = field.shape
+    _check(load().spline3_prefilter(_prec(field), _ptr(field), _ptr(coef), _ptr(work), nx, ny, nz,
+                                    _stream(stream)))
+    return coef
+
+
+def spline3_gather(coef, points, out, stream=None):
+    """out[p] = tricubic spline of coef at points[p] = (x, y, z) in cells."""
+    nz, ny, nx = coef.shape
+    _check(load().spline3_gather(_prec(coef), _ptr(coef), nx, ny, nz, _ptr(points), int(points.shape[0]),
+                                 _ptr(out), _stream(stream)))
+    return out
 
 
 def eval_heff(h, film, term_mask, out):

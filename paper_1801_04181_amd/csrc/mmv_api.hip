@@ -2159,6 +2159,46 @@ int set_drive(mmv_handle h, const mmv_drive* drv) {
   return write_rigid(h, r);
 }
 
+int spline3_prefilter(int precision, const void* field, void* coef, void* work, int nx, int ny, int nz,
+                      void* hip_stream) {
+  g_err.clear();
+  if (precision != 32 && precision != 64) return fail(MMV_EINVAL, "precision must be 32 or 64");
+  if (!field || !coef || !work) return fail(MMV_EINVAL, "NULL buffer");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(MMV_EINVAL, "nx, ny, nz must be >= 1");
+  if ((long long)nx * ny * nz >= (1LL << 31)) return fail(MMV_EINVAL, "field too large");
+  const size_t bytes = (size_t)nx * ny * nz * (precision / 8);
+  auto overlap = [&](const void* a, const void* b) {
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + bytes && y < x + bytes;
+  };
+  if (overlap(field, coef) || overlap(field, work) || overlap(coef, work))
+    return fail(MMV_EINVAL, "field, coef and work must not overlap");
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (precision == 64)
+    HIPCHK(launch_spline3_prefilter<double>((const double*)field, (double*)coef, (double*)work, nx, ny, nz, st));
+  else
+    HIPCHK(launch_spline3_prefilter<float>((const float*)field, (float*)coef, (float*)work, nx, ny, nz, st));
+  return MMV_OK;
+}
+
+int spline3_gather(int precision, const void* coef, int nx, int ny, int nz, const void* points, int npts, void* out,
+                   void* hip_stream) {
+  g_err.clear();
+  if (precision != 32 && precision != 64) return fail(MMV_EINVAL, "precision must be 32 or 64");
+  if (nx < 1 || ny < 1 || nz < 1) return fail(MMV_EINVAL, "nx, ny, nz must be >= 1");
+  if ((long long)nx * ny * nz >= (1LL << 31)) return fail(MMV_EINVAL, "field too large");
+  if (npts < 0) return fail(MMV_EINVAL, "npts must be >= 0");
+  if (npts > 0 && (!coef || !points || !out)) return fail(MMV_EINVAL, "NULL buffer");
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (precision == 64)
+    HIPCHK(launch_spline3_gather<double>((const double*)coef, nx, ny, nz, (const double*)points, npts, (double*)out,
+                                         st));
+  else
+    HIPCHK(launch_spline3_gather<float>((const float*)coef, nx, ny, nz, (const float*)points, npts, (float*)out, st));
+  return MMV_OK;
+}
+
 int set_hext_field(mmv_handle h, int film, const void* field) {
   int rc = check_handle(h);
   if (rc) return rc;

@@ -106,4 +106,13 @@ constexpr size_t COL_STATIC_LDS = 640;
 template <typename T>
 bool static_lds_within_reserve();
 
+// Tricubic B-spline of a [nz][ny][nx] field: prefilter along x, y, z
+// (field -> coef, using work; the three must not overlap) and the 64-tap
+// gather at npts points [npts][3] (x, y, z in cells).
+template <typename T>
+hipError_t launch_spline3_prefilter(const T* field, T* coef, T* work, int nx, int ny, int nz, hipStream_t st);
+template <typename T>
+hipError_t launch_spline3_gather(const T* coef, int nx, int ny, int nz, const T* pts, int npts, T* out,
+                                 hipStream_t st);
+
 }  // namespace mmv

@@ -183,3 +183,31 @@ def test_surrogate_rejects_bad_shapes(kw, msg):
     with pytest.raises(mmv.MMVError) as e:
         mmv.sur_create(**args)
     assert e.value.code == -1 and msg in str(e.value)
+
+
+@pytest.mark.parametrize("args,msg", [
+    ((16, 1, 1, 1, 1, 1, 1, 1), "precision"),
+    ((32, 0, 8, 16, 0, 4, 4, 0), "NULL"),
+    ((32, 8, 16, 24, 0, 4, 4, 0), "nx, ny, nz"),
+    ((64, 8, 16, 24, 2048, 2048, 1024, 0), "too large"),
+    ((32, 8, 8, 24, 2, 2, 2, 0), "overlap"),
+])
+def test_spline3_prefilter_argument_checks(args, msg):
+    """Rejected before any device call (the pointers are never touched)."""
+    lib = mmv.load()
+    prec, f, c, w, nx, ny, nz, st = args
+    vp = ctypes.c_void_p
+    rc = lib.spline3_prefilter(prec, vp(f) if f else None, vp(c) if c else None, vp(w) if w else None,
+                               nx, ny, nz, None)
+    assert rc == -1
+    assert msg in mmv.last_error()
+
+
+def test_spline3_gather_argument_checks():
+    lib = mmv.load()
+    assert lib.spline3_gather(8, None, 2, 2, 2, None, 1, None, None) == -1
+    assert lib.spline3_gather(32, None, 2, 0, 2, None, 1, None, None) == -1
+    assert lib.spline3_gather(32, None, 2, 2, 2, None, -1, None, None) == -1
+    assert lib.spline3_gather(32, None, 2, 2, 2, None, 3, None, None) == -1
+    assert "NULL" in mmv.last_error()
+    assert lib.spline3_gather(32, None, 2, 2, 2, None, 0, None, None) == 0   # empty: nothing launched
