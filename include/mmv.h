@@ -162,6 +162,15 @@ int set_drive(mmv_handle h, const mmv_drive* drv);
  * its next batch_step.                                                  */
 int set_hext_field(mmv_handle h, int film, const void* field);
 
+/* Residual of the last eddy-current solve (Eq. 12, Sec. III.B): the
+ * relative L2 norm ||L phi - r|| / ||r|| of the finite-volume Neumann
+ * problem after the step's SOR sweeps (L: sum over interior faces of
+ * (phi_j - phi_i) / d^2; r: the surface flux of E_sol, zero mean).  The
+ * sweeps per step are fixed (sor_sweeps), so this is the check of how far
+ * they left the potential from the solution.  Synchronises the stream.
+ * MMV_ESTATE if the mesh has no eddy currents or no step has run yet.    */
+int eddy_residual(mmv_handle h, double* rel);
+
 /* Tricubic B-spline of a scalar field on a 3-D lattice (Sec. III.A's
  * spline, here along all three axes; the 4 x 4 x 4 nearest-neighbour
  * evaluation of Sec. IV.D), for interpolation at arbitrary displacements.

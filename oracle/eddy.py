@@ -124,6 +124,16 @@ def sor(desc, phi, r, sweeps, omega):
     return phi - phi.mean()
 
 
+def residual(desc, phi, r):
+    """Relative L2 residual ||L phi - r|| / ||r|| of the Neumann problem
+    (L = laplacian above), the measure of how far the fixed sweeps left phi
+    from the solution."""
+    res = laplacian(desc, phi) - r
+    nr = float(np.sqrt((r * r).sum()))
+    nres = float(np.sqrt((res * res).sum()))
+    return nres / nr if nr > 0 else nres
+
+
 def irrotational(desc, phi, Esol):
     """E_irrot = -(g+ + g-)/2 per axis; a surface face gradient is E_sol,a."""
     E = np.zeros_like(Esol)
@@ -152,6 +162,7 @@ class EddyState:
         self.H_eddy = np.zeros(shape)
         self.B_prev = None
         self.phi = np.zeros(shape[1:])
+        self.r = np.zeros(shape[1:])
         self.E_sol = np.zeros(shape)
         self.J = np.zeros(shape)
         self._esol = None
@@ -179,6 +190,7 @@ class EddyState:
         esol_op, heddy_op = self.ops()
         self.E_sol = esol_op(dB)
         r = neumann_rhs(d, self.E_sol)
+        self.r = r
         self.phi = sor(d, self.phi, r, default_sweeps(d), default_omega(d))
         self.J = d.sigma * (self.E_sol + irrotational(d, self.phi, self.E_sol))
         self.H_eddy = heddy_op(self.J)

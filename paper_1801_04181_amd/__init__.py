@@ -11,7 +11,7 @@ import os
 
 __all__ = ["MMVError", "lib_path", "load", "MeshDesc", "DriveDesc", "init_mesh",
            "set_m", "get_m", "set_offset", "set_drive", "set_hext_field", "eval_heff", "llg_step", "llg_run_dp",
-           "spline3_prefilter", "spline3_gather",
+           "spline3_prefilter", "spline3_gather", "eddy_residual",
            "stray_force", "stray_force_noalloc", "div_curl", "get_state", "get_fft_lengths", "destroy_mesh",
            "profile_begin", "profile_end", "profile_repeat", "init_batch", "batch_instance", "batch_step",
            "batch_tuning", "set_tune_cache", "destroy_batch", "Batch", "batch_sur_attach", "batch_sur_status", "SurDesc", "sur_create", "sur_param_count",
@@ -27,7 +27,7 @@ TERM = dict(exchange=1, anisotropy=2, zeeman=4, demag_self=8, demag_cross=16,
 ERRORS = {-1: "MMV_EINVAL", -2: "MMV_ENOMEM", -3: "MMV_EHIP", -4: "MMV_ERANGE",
           -5: "MMV_ENUMERIC", -6: "MMV_ESTATE"}
 EXPORTS = ("init_mesh", "set_m", "get_m", "set_offset", "set_drive", "set_hext_field", "eval_heff",
-           "spline3_prefilter", "spline3_gather",
+           "spline3_prefilter", "spline3_gather", "eddy_residual",
            "llg_step", "llg_run_dp", "stray_force", "stray_force_noalloc", "div_curl", "get_state", "profile_begin", "profile_end",
            "get_fft_lengths", "profile_repeat", "init_batch", "batch_instance", "batch_step", "batch_tuning",
            "set_tune_cache", "destroy_batch", "destroy_mesh", "sur_create", "sur_param_count", "sur_param_offsets",
@@ -92,6 +92,7 @@ def load():
         lib.eval_heff.argtypes = [vp, i, i, vp]
         lib.set_hext_field.argtypes = [vp, i, vp]
         lib.spline3_prefilter.argtypes = [i, vp, vp, vp, i, i, i, vp]
+        lib.eddy_residual.argtypes = [vp, pd]
         lib.spline3_gather.argtypes = [i, vp, i, i, i, vp, i, vp, vp]
         lib.llg_step.argtypes = [vp, d, i]
         lib.llg_run_dp.argtypes = [vp, d, d, pd, i, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_long)]
@@ -205,6 +206,13 @@ def set_hext_field(h, film, field):
     [3][ny][nx] for film 0, [3][ny][nx + 2 (max_travel_cells + halo)] for the
     slider's layer, [3][ny][nx] with periodic x), or None to remove it."""
     _check(load().set_hext_field(h, int(film), None if field is None else _ptr(field)))
+
+
+def eddy_residual(h):
+    """Relative L2 residual of the last eddy-current solve (Eq. 12)."""
+    r = ctypes.c_double()
+    _check(load().eddy_residual(h, ctypes.byref(r)))
+    return r.value
 
 
 def _prec(t):

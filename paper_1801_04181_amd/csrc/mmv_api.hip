@@ -2159,6 +2159,32 @@ int set_drive(mmv_handle h, const mmv_drive* drv) {
   return write_rigid(h, r);
 }
 
+int eddy_residual(mmv_handle h, double* rel) {
+  int rc = check_handle(h);
+  if (rc) return rc;
+  if (!rel) return fail(MMV_EINVAL, "rel is NULL");
+  if (!h->cube || !(h->d.sigma > 0)) return fail(MMV_ESTATE, "no eddy-current solve on this mesh");
+  if (h->eddy_first) return fail(MMV_ESTATE, "no step has run the eddy solve yet");
+  const size_t N = (size_t)h->nx * h->ny * h->nz;
+  // the partials reuse the eddy update's reduction buffer (N/256 + 2 doubles
+  // before the mean), free between steps
+  const int nblk = (int)std::max<size_t>(1, std::min<size_t>(512, (N / 256 + 2) / 2));
+  if (h->esz == 8)
+    HIPCHK(launch_sor_residual<double>(h->cl, (const double*)h->phi, (const double*)h->rr, h->red, nblk, h->st));
+  else
+    HIPCHK(launch_sor_residual<float>(h->cl, (const float*)h->phi, (const float*)h->rr, h->red, nblk, h->st));
+  std::vector<double> part(2 * (size_t)nblk);
+  HIPCHK(hipMemcpyAsync(part.data(), h->red, sizeof(double) * part.size(), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  double a = 0.0, b = 0.0;
+  for (int k = 0; k < nblk; ++k) {
+    a += part[2 * (size_t)k];
+    b += part[2 * (size_t)k + 1];
+  }
+  *rel = b > 0 ? sqrt(a / b) : sqrt(a);
+  return MMV_OK;
+}
+
 int spline3_prefilter(int precision, const void* field, void* coef, void* work, int nx, int ny, int nz,
                       void* hip_stream) {
   g_err.clear();

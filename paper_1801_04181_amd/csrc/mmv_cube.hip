@@ -427,6 +427,48 @@ __global__ void k_shift(size_t N, const T* src, T* dst, const double* __restrict
     dst[id] = (T)((double)src[id] - *mean);
 }
 
+// Residual of the Neumann problem after the sweeps: per cell
+// res_i = sum over interior faces (phi_j - phi_i) / d^2 - r_i; each block
+// writes its float64 sums of res^2 and r^2 (part[2 b], part[2 b + 1]).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_sor_residual(int nx, int ny, int nz, double dx, double dy, double dz, const T* __restrict__ phi,
+                   const T* __restrict__ r, double* __restrict__ part) {
+  __shared__ double red[2][256];
+  const size_t N = (size_t)nx * ny * nz;
+  const double wx = 1.0 / (dx * dx), wy = 1.0 / (dy * dy), wz = 1.0 / (dz * dz);
+  double a = 0.0, b = 0.0;
+  for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < N; id += (size_t)gridDim.x * blockDim.x) {
+    int i, j, k;
+    cell_ijk(id, nx, ny, i, j, k);
+    const double p = phi[id];
+    double s = 0.0;
+    if (i > 0) s += wx * ((double)phi[id - 1] - p);
+    if (i < nx - 1) s += wx * ((double)phi[id + 1] - p);
+    if (j > 0) s += wy * ((double)phi[id - nx] - p);
+    if (j < ny - 1) s += wy * ((double)phi[id + nx] - p);
+    if (k > 0) s += wz * ((double)phi[id - (size_t)nx * ny] - p);
+    if (k < nz - 1) s += wz * ((double)phi[id + (size_t)nx * ny] - p);
+    const double res = s - (double)r[id];
+    a += res * res;
+    b += (double)r[id] * (double)r[id];
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + h];
+      red[1][threadIdx.x] += red[1][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = red[0][0];
+    part[2 * blockIdx.x + 1] = red[1][0];
+  }
+}
+
 // Red-black SOR sweeps (colour = (i + j + k) mod 2, red = 0 first) on 3-D
 // tiles.  A cell's update is
 //   phi <- (1 - omega) phi + omega (sum_nb w_nb phi_nb - r) / sum_nb w_nb
@@ -738,6 +780,14 @@ hipError_t launch_sor_rhs(const CubeLaunch& c, const T* es, T* r, double* part, 
 }
 
 template <typename T>
+hipError_t launch_sor_residual(const CubeLaunch& c, const T* phi, const T* r, double* part, int nblk,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_sor_residual<T>, dim3(nblk), dim3(256), 0, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz, phi, r,
+                     part);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_sor(const CubeLaunch& c, T* phi, T* phi2, const T* r, double omega, int sweeps, double* part,
                       double* mean, hipStream_t st) {
   const size_t N = (size_t)c.nx * c.ny * c.nz;
@@ -803,6 +853,7 @@ hipError_t launch_pack3(const void* spec, T* out, int Kx, int Ly, int Lz, int im
   template hipError_t launch_sor<T>(const CubeLaunch&, T*, T*, const T*, double, int, double*, double*,          \
                                      hipStream_t);                                                             \
   template hipError_t launch_current<T>(const CubeLaunch&, const T*, const T*, T*, double, hipStream_t);         \
+  template hipError_t launch_sor_residual<T>(const CubeLaunch&, const T*, const T*, double*, int, hipStream_t);  \
   template hipError_t launch_pack3<T>(const void*, T*, int, int, int, int, hipStream_t);
 
 MMV_CUBE_INST(float)

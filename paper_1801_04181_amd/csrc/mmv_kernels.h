@@ -82,6 +82,9 @@ hipError_t launch_eddy_bdot(size_t N, const T* dm, const T* hdm, T* bdot, double
                             int first, hipStream_t st);
 template <typename T>
 hipError_t launch_sor_rhs(const CubeLaunch& c, const T* es, T* r, double* part, double* mean, hipStream_t st);
+// float64 partial sums (res^2, r^2) of the Neumann residual, nblk blocks
+template <typename T>
+hipError_t launch_sor_residual(const CubeLaunch& c, const T* phi, const T* r, double* part, int nblk, hipStream_t st);
 template <typename T>
 hipError_t launch_sor(const CubeLaunch& c, T* phi, T* phi2, const T* r, double omega, int sweeps, double* part, double* mean,
                       hipStream_t st);

@@ -100,3 +100,48 @@ def test_cube_largest_extents(prec, shape):
     d = get_config("cube_eddy")["desc"].replace(nx=nx, ny=ny, nz=nz, precision=prec, sor_sweeps=9)
     out = run(d, 2)
     assert out["m"] < (1e-6 if prec == 32 else 1e-12)
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_eddy_residual_matches_the_oracle_and_falls_with_sweeps(prec):
+    """eddy_residual: ||L phi - r|| / ||r|| after the step's sweeps, against
+    the oracle's residual of its own potential after the same steps
+    (float64: the potentials agree to ~1e-10, so the residuals to 1e-6 of
+    themselves; float32: to 1e-2), and smaller with more sweeps."""
+    import torch
+    import paper_1801_04181_amd as mmv
+    from oracle.sim import System
+    from oracle import eddy
+    base = get_config("cube_eddy")["desc"].replace(nx=12, ny=10, nz=9, precision=prec)
+    m = [cube_state((9, 10, 12), 33)]
+    res = {}
+    for sweeps in (2, 40, 400):
+        d = base.replace(sor_sweeps=sweeps)
+        mesh = mmv.Mesh(d, Drive(), m)
+        if sweeps == 40:
+            with pytest.raises(mmv.MMVError) as e:
+                mmv.eddy_residual(mesh.h)              # no solve yet
+            assert e.value.code == -6
+        mesh.step(5e-14, 3)
+        torch.cuda.synchronize()
+        res[sweeps] = mmv.eddy_residual(mesh.h)
+        mesh.close()
+        if sweeps == 40:
+            s = System(d, Drive(), m)
+            s.run(5e-14, 3)
+            ro = eddy.residual(d, s.eddy.phi, s.eddy.r)
+            print(f"  fp{prec} sweeps 40: residual {res[40]:.6e} (oracle {ro:.6e})", flush=True)
+            assert abs(res[40] - ro) <= (1e-6 if prec == 64 else 1e-2) * ro + (1e-12 if prec == 64 else 1e-5)
+    print(f"  fp{prec} residuals by sweeps: {res}", flush=True)
+    assert res[2] > res[40] > res[400]
+
+
+def test_eddy_residual_needs_an_eddy_mesh():
+    import paper_1801_04181_amd as mmv
+    cfg = get_config("tiny")
+    from workloads import initial_state
+    mesh = mmv.Mesh(cfg["desc"], cfg["drive"], initial_state(cfg))
+    with pytest.raises(mmv.MMVError) as e:
+        mmv.eddy_residual(mesh.h)
+    assert e.value.code == -6
+    mesh.close()
