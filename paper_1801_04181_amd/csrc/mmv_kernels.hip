@@ -1146,11 +1146,9 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
       }
       lds_barrier();
     } else if (film == 1 && p.hext_s != nullptr) {
-      constexpr int NOH = sizeof(T) == 4 ? 3 : 2;
       const T* src = gptr(reinterpret_cast<const T*>(p.hext_s)) + (size_t)y * p.hext_w;
       const size_t cs = (size_t)ny * p.hext_w;
       const float invMW = 1.0f / (float)MW;
-      const int nch = (nx + NOH - 1) / NOH;
       for (int c0 = 0; c0 < 3; c0 += nbr) {
         const int nc = min(nbr, 3 - c0);
 #pragma unroll 1
@@ -1168,14 +1166,16 @@ __device__ __forceinline__ void row_stage_body(const RowParams& p, int stage, do
           ext[(size_t)r * MWS + k] = src[(size_t)(c0 + r) * cs + X];
         }
         lds_barrier();
+        // one output per thread, taps streamed from LDS (an optional term:
+        // kept off the register window of the spline rows' FIR)
 #pragma unroll 1
-        for (int t = threadIdx.x; t < nc * nch; t += NT) {
-          const int r = t / nch, i0 = NOH * (t - r * nch);
-          T v[NOH];
-          fir_evaln<T, K, NOH>(ext + (size_t)r * MWS, gs, i0 + h + ifs, E, v);
-#pragma unroll
-          for (int j = 0; j < NOH; ++j)
-            if (i0 + j < nx) H[(c0 + r) * nx + i0 + j] += v[j];
+        for (int t = threadIdx.x; t < nc * nx; t += NT) {
+          const int r = t / nx, i = t - r * nx;
+          const T* e = ext + (size_t)r * MWS + E + i + h + ifs - K - 1;
+          T a = T(0);
+#pragma unroll 4
+          for (int q = 0; q < NQ; ++q) a += gs[q] * e[q];
+          H[(c0 + r) * nx + i] += a;
         }
         lds_barrier();
       }
