@@ -344,72 +344,6 @@ def cube_report(steps=40, warmup=4):
     return out
 
 
-def precision_report(steps_cube=6, steps_film=50):
-    """Per-term error of the float32 and float64 GPU paths against the float64
-    oracle: the 64^3 conducting cube (eddy currents on) and the stick-slip films.
-    float64 is kept on the GPU for the tensor/S construction and for the
-    slider's position, velocity and force accumulation in both precisions."""
-    import numpy as np
-    import torch
-    import paper_1801_04181_amd as mmv
-    from workloads import get_config, initial_state
-    from oracle.sim import System
-
-    def rel(a, b):
-        nb = np.linalg.norm(b)
-        return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
-
-    names = (("exchange", 1), ("anisotropy", 2), ("zeeman", 4), ("demag_self", 8),
-             ("demag_cross", 16), ("eddy", 32))
-    out = {}
-    cfg = get_config("cube_eddy")
-    m = initial_state(cfg)
-    ref = System(cfg["desc"], cfg["drive"], m)
-    ref.run(cfg["dt"], 2)                     # two steps: dB/dt and the eddy field exist
-    terms2, _ = ref.field_terms()
-    m2 = [x.copy() for x in ref.m]
-    ref.run(cfg["dt"], steps_cube - 2)
-    for prec in (32, 64):
-        d = cfg["desc"].replace(precision=prec)
-        mesh = mmv.Mesh(d, cfg["drive"], m)
-        mesh.step(cfg["dt"], 2)
-        torch.cuda.synchronize()
-        r = {"m_after_2": float(np.abs(mesh.get_m(0).cpu().numpy() - m2[0]).max())}
-        for name, bit in names:
-            if name == "demag_cross" or not np.any(terms2[0][name]):
-                continue
-            # field terms of the GPU state after 2 steps vs the oracle's
-            r[name] = rel(mesh.eval_heff(0, bit).cpu().numpy(), terms2[0][name])
-        r["total"] = rel(mesh.eval_heff(0, 63).cpu().numpy(), System.total(terms2[0]))
-        mesh.step(cfg["dt"], steps_cube - 2)
-        torch.cuda.synchronize()
-        r[f"m_after_{steps_cube}"] = float(np.abs(mesh.get_m(0).cpu().numpy() - ref.m[0]).max())
-        mesh.close()
-        out[f"cube_eddy_fp{prec}"] = r
-    cfg = get_config("stickslip")
-    m = initial_state(cfg)
-    ref = System(cfg["desc"], cfg["drive"], m)
-    terms, F = ref.field_terms()
-    mesh = mmv.Mesh(cfg["desc"], cfg["drive"], m)
-    r = {}
-    for f in range(2):
-        for name, bit in names[:5]:
-            if np.any(terms[f][name]):
-                r[f"film{f}_{name}"] = rel(mesh.eval_heff(f, bit).cpu().numpy(), terms[f][name])
-    Fg = np.array(mesh.force())
-    r["force"] = float(np.linalg.norm(Fg - F) / np.linalg.norm(F))
-    mesh.step(cfg["dt"], steps_film)
-    torch.cuda.synchronize()
-    ref.run(cfg["dt"], steps_film)
-    r[f"m_after_{steps_film}"] = max(float(np.abs(mesh.get_m(f).cpu().numpy() - ref.m[f]).max())
-                                     for f in range(2))
-    st = mesh.state()
-    r[f"x_after_{steps_film}_cells"] = abs(st["x"] - ref.x) / cfg["desc"].dx
-    mesh.close()
-    out["stickslip_fp32"] = r
-    return out
-
-
 def surrogate_report(train_steps=3000, B=8, steps=200, log=None):
     """Learned stray-field operator on the 2 x 256 x 256 films: train on fresh
     exact pairs, held-out error, then LLG steps with the operator attached
@@ -554,15 +488,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="--report batch: eager launches (counter runs)")
-    ap.add_argument("--report", choices=["precision", "surrogate", "cube", "batch", "surrogate-batched", "divcurl"],
+    ap.add_argument("--report", choices=["surrogate", "cube", "batch", "surrogate-batched", "divcurl"],
                     default=None)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the run, copy 256 MiB device to device 3 times (counter calibration)")
     args = ap.parse_args()
-    if args.report == "precision":
-        print(json.dumps({"precision_report": precision_report()}), flush=True)
-        return
     if args.report == "cube":
         print(json.dumps({"cube_report": cube_report()}), flush=True)
         return
