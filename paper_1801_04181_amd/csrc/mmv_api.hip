@@ -1148,6 +1148,14 @@ struct mmv_batch {
   hipGraph_t graph = nullptr;
   double g_dt = 0.0;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // the launch classes of one pass touch disjoint instances: they run on
+  // side streams forked from the launching stream and joined back into it
+  // (in a captured graph, parallel branches), so that one class's blocks
+  // fill the CUs another class's tail leaves idle
+  static constexpr int NSIDE = 3;
+  hipStream_t side[NSIDE] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[NSIDE] = {};
 };
 
 namespace {
@@ -1385,13 +1393,45 @@ int batch_build(mmv_batch* b) {
   return MMV_OK;
 }
 
+// Launch every class of a pass, class k on side stream k - 1 (class 0, and
+// classes past the side streams, on st), forked from and joined into st.
+template <typename F>
+int batch_classes(mmv_batch* b, hipStream_t st, const std::vector<BatchLaunch>& L, F launch) {
+  const int n = (int)L.size();
+  if (n <= 1) {
+    for (const BatchLaunch& c : L) HIPCHK(launch(c, st));
+    return MMV_OK;
+  }
+  HIPCHK(hipEventRecord(b->ev_fork, st));
+  const int nside = std::min(n - 1, mmv_batch::NSIDE);
+  for (int k = 0; k < nside; ++k) HIPCHK(hipStreamWaitEvent(b->side[k], b->ev_fork, 0));
+  for (int k = 0; k < n; ++k) {
+    hipStream_t s = (k >= 1 && k <= nside) ? b->side[k - 1] : st;
+    HIPCHK(launch(L[k], s));
+  }
+  for (int k = 0; k < nside; ++k) {
+    HIPCHK(hipEventRecord(b->ev_join[k], b->side[k]));
+    HIPCHK(hipStreamWaitEvent(st, b->ev_join[k], 0));
+  }
+  return MMV_OK;
+}
+
 // The y pass of every class (its block 0 per instance applies the pending
 // slider stage when tick_stage >= 0).
 template <typename T>
 int batch_col_launches(mmv_batch* b, hipStream_t st, int tick_stage, double dt) {
-  for (const BatchLaunch& c : b->l_col)
-    HIPCHK(launch_col_batch<T>(b->d_col + c.off, b->s_col + c.soff, c.n, c.nblk, c.lds, st, tick_stage, dt));
-  return MMV_OK;
+  return batch_classes(b, st, b->l_col, [&](const BatchLaunch& c, hipStream_t s) {
+    return launch_col_batch<T>(b->d_col + c.off, b->s_col + c.soff, c.n, c.nblk, c.lds, s, tick_stage, dt);
+  });
+}
+
+// The row kernel of every class at stage s.
+template <typename T>
+int batch_stage_launches(mmv_batch* b, hipStream_t st, int s, double dt) {
+  return batch_classes(b, st, b->l_stage, [&](const BatchLaunch& c, hipStream_t q) {
+    return launch_row_stage_batch<T>(b->d_stage[s] + c.off, b->s_stage + c.soff, c.n, c.nblk, c.lds, s, dt,
+                                     c.inplace, c.nt, q);
+  });
 }
 
 template <typename T>
@@ -1463,9 +1503,7 @@ int batch_sur_steps(mmv_batch* b, hipStream_t st, double dt, int nsteps, int* do
         for (const BatchLaunch& c : b->l_fwd)
           HIPCHK(launch_row_fwd_batch<T>(b->d_fwd[s] + c.off, b->s_fwd + c.soff, c.n, c.nblk, c.lds, st));
       if ((rc = batch_col_launches<T>(b, st, -1, dt))) return rc;
-      for (const BatchLaunch& c : b->l_stage)
-        HIPCHK(launch_row_stage_batch<T>(b->d_stage[s] + c.off, b->s_stage + c.soff, c.n, c.nblk, c.lds, s, dt,
-                                         c.inplace, c.nt, st));
+      if ((rc = batch_stage_launches<T>(b, st, s, dt))) return rc;
       pending = s;
     }
     b->sur_steps += 1;
@@ -1494,9 +1532,7 @@ int batch_launch_steps(mmv_batch* b, hipStream_t st, double dt, int nsteps) {
       if (rc) return rc;
       PROF(2);
       PROF(3);
-      for (const BatchLaunch& c : b->l_stage)
-        HIPCHK(launch_row_stage_batch<T>(b->d_stage[s] + c.off, b->s_stage + c.soff, c.n, c.nblk, c.lds, s, dt,
-                                         c.inplace, c.nt, st));
+      if ((rc = batch_stage_launches<T>(b, st, s, dt))) return rc;
       PROF(3);
       pending = s;
     }
@@ -1703,12 +1739,7 @@ int batch_autotune(mmv_batch* b) {
         if (h->N2x == len) h->row_nt = nt;
       int rc = batch_build<T>(b);
       if (rc) return rc;
-      auto launches = [&]() -> int {
-        for (const BatchLaunch& c : b->l_stage)
-          HIPCHK(launch_row_stage_batch<T>(b->d_stage[0] + c.off, b->s_stage + c.soff, c.n, c.nblk, c.lds, 0, 0.0,
-                                           c.inplace, c.nt, b->st));
-        return MMV_OK;
-      };
+      auto launches = [&]() -> int { return batch_stage_launches<T>(b, b->st, 0, 0.0); };
       if ((rc = launches())) return rc;
       HIPCHK(hipEventRecord(e0, b->st));
       for (int r = 0; r < 5; ++r)
@@ -1755,6 +1786,11 @@ void batch_free(mmv_batch* b) {
   if (b->gst) hipStreamDestroy(b->gst);
   if (b->ev_in) hipEventDestroy(b->ev_in);
   if (b->ev_out) hipEventDestroy(b->ev_out);
+  if (b->ev_fork) hipEventDestroy(b->ev_fork);
+  for (int k = 0; k < mmv_batch::NSIDE; ++k) {
+    if (b->side[k]) hipStreamDestroy(b->side[k]);
+    if (b->ev_join[k]) hipEventDestroy(b->ev_join[k]);
+  }
   delete b;
 }
 
@@ -1985,8 +2021,13 @@ int init_batch(const mmv_mesh_desc* descs, int n, void* hip_stream, int flags, m
   int rc = hipStreamCreateWithFlags(&b->gst, hipStreamNonBlocking) == hipSuccess ? MMV_OK
                                                                                    : fail(MMV_EHIP, "stream create");
   if (!rc && (hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
-              hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess))
+              hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess))
     rc = fail(MMV_EHIP, "event create");
+  for (int k = 0; !rc && k < mmv_batch::NSIDE; ++k)
+    if (hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming) != hipSuccess)
+      rc = fail(MMV_EHIP, "side stream create");
   if (!rc) rc = b->esz == 8 ? batch_build<double>(b) : batch_build<float>(b);
   if (!rc && (flags & MMV_BATCH_AUTOTUNE)) rc = b->esz == 8 ? batch_autotune<double>(b) : batch_autotune<float>(b);
   if (rc) {
@@ -2082,6 +2123,8 @@ int destroy_batch(mmv_batch_handle b) {
   if (!b) return MMV_OK;
   hipStreamSynchronize(b->st);
   if (b->gst) hipStreamSynchronize(b->gst);
+  for (hipStream_t q : b->side)
+    if (q) hipStreamSynchronize(q);
   batch_free(b);
   return MMV_OK;
 }
