@@ -128,6 +128,23 @@ def cube_long():
         done = s
         print(f"cube long: step {s}: fp32 {out['fp32'][-1]['max_dm_sampled']:.3e} "
               f"fp64 {out['fp64'][-1]['max_dm_sampled']:.3e}", file=sys.stderr, flush=True)
+    # per-term float32 rounding on the state 2000 steps in: the float32
+    # kernels evaluated on the float64 run's state against the float64
+    # kernels on it (instantaneous terms); the eddy field, which carries the
+    # step history, float32 run against float64 run
+    def rel(a, b):
+        nb = np.linalg.norm(b)
+        return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+    m64 = meshes[64].get_m(0).cpu().numpy()
+    probe = mmv.Mesh(cfg["desc"].replace(precision=32, sigma=0.0), cfg["drive"], [m64])
+    terms = {}
+    for name, bit in (("exchange", 1), ("zeeman", 4), ("demag_self", 8)):
+        terms[name] = rel(probe.eval_heff(0, bit).cpu().numpy().astype(np.float64),
+                          meshes[64].eval_heff(0, bit).cpu().numpy())
+    terms["eddy_fp32_run_vs_fp64_run"] = rel(meshes[32].eval_heff(0, 32).cpu().numpy().astype(np.float64),
+                                             meshes[64].eval_heff(0, 32).cpu().numpy())
+    probe.close()
+    out["terms_at_2000"] = terms
     for mesh in meshes.values():
         mesh.close()
     return out
