@@ -26,6 +26,8 @@ framework") step by step:
   divcurl.py           divergence / curl of the interpolated field, Eq. (13)
   applied.py           non-uniform applied field sampled in the moving
                        magnet (Sec. II.A)
+  slab.py              two films more than one cell thick, with eddy
+                       currents in both (Sec. II.A, III.B, IV.C-D)
   fno.py               learned stray-field operator (Fourier neural
                        operator standing in for the cross term), float64
                        torch with autograd gradients
@@ -35,8 +37,8 @@ no independent pin say "parity unpinned".
 """
 from .constants import MU0, GAMMA_E, GAMMA0
 from . import newell, potential_kernel, convolution, spline, fields, llg, sim, fno, dormand_prince, periodic, divcurl
-from . import applied
+from . import applied, slab
 
 __all__ = ["MU0", "GAMMA_E", "GAMMA0", "newell", "potential_kernel",
            "convolution", "spline", "fields", "llg", "sim", "fno", "dormand_prince",
-           "periodic", "divcurl", "applied"]
+           "periodic", "divcurl", "applied", "slab"]

@@ -1,0 +1,206 @@
+"""Pins for the thick two-film oracle with eddy currents (oracle.slab;
+Sec. II.A, III.A-B, Eqs. 3, 6, 9-12; Sec. IV.C-D).
+
+At an integer offset (x_p = 0) the spline reproduces the window data
+exactly, so every sampled field, the force of Eq. 3 and the cross-film
+eddy sums must equal brute-force sums over source cells written here from
+the physical cell centres alone: base cell (i, j, l) at ((i+1/2) dx,
+(j+1/2) dy, (l+1/2) dz), slider cell at (x_s + (i+1/2) dx, (j+1/2) dy,
+(z_s + l + 1/2) dz) with z_s = nz + gap.  Nothing below reuses the
+oracle's window boxes, its FFT sums or its stencil helper.  Two reductions
+pin the rest: one-cell-thick films reproduce oracle.sim at a fractional
+offset, and films far apart reduce each film's eddy field to the
+single-magnet field of oracle.eddy.
+"""
+import numpy as np
+import pytest
+from workloads import Desc, Drive
+from workloads.states import random_unit
+from oracle.constants import MU0
+from oracle.newell import tensor_matrix
+from oracle.potential_kernel import potential_kernel
+from oracle.sim import System, FROZEN
+from oracle.slab import SlabSystem
+from oracle import eddy as oracle_eddy
+
+EPS = {(0, 1, 2): 1.0, (1, 2, 0): 1.0, (2, 0, 1): 1.0,
+       (0, 2, 1): -1.0, (2, 1, 0): -1.0, (1, 0, 2): -1.0}
+
+
+def films(nx=6, ny=4, nz=2, gap=1, seed=5, **kw):
+    d = Desc(n_films=2, nx=nx, ny=ny, nz=nz, dx=2e-9, dy=3e-9, dz=2.5e-9,
+             gap_cells=gap, Ms=9e5, halo=4, max_travel_cells=4, **kw)
+    rng = np.random.default_rng(seed)
+    m = [random_unit((nz, ny, nx), rng) for _ in range(2)]
+    return d, m
+
+
+def centres(d, x_shift, z0):
+    """Cell centres of a film whose lowest layer has index z0, (nz, ny, nx)."""
+    kk, jj, ii = np.meshgrid(np.arange(d.nz), np.arange(d.ny), np.arange(d.nx), indexing="ij")
+    return (ii + 0.5) * d.dx + x_shift, (jj + 0.5) * d.dy, (kk + z0 + 0.5) * d.dz
+
+
+def tensor_field_at(d, P, src, x_shift, z0):
+    X, Y, Z = centres(d, x_shift, z0)
+    N = tensor_matrix(P[0] - X, P[1] - Y, P[2] - Z, d.dx, d.dy, d.dz, d.rc_cells)
+    return np.array([-d.Ms * sum(np.sum(N[a, b] * src[b]) for b in range(3)) for a in range(3)])
+
+
+def s_cross_at(d, P, v, x_shift, z0):
+    """sum_j (S(P - r_j) x v_j) over a film's cells."""
+    X, Y, Z = centres(d, x_shift, z0)
+    S = potential_kernel(P[0] - X, P[1] - Y, P[2] - Z, d.dx, d.dy, d.dz)
+    out = np.zeros(3)
+    for (a, b, c), e in EPS.items():
+        out[a] += e * np.sum(S[b] * v[c])
+    return out
+
+
+def brute_force(d, m, s_int):
+    mb, ms = m
+    zs = d.nz + d.gap_cells
+    xs = s_int * d.dx
+    steps = np.array([d.dx, d.dy, d.dz])
+    shape = (3, d.nz, d.ny, d.nx)
+    Hs, Hb, F = np.zeros(shape), np.zeros(shape), np.zeros(3)
+    V = d.dx * d.dy * d.dz
+    for k in range(d.nz):
+        for j in range(d.ny):
+            for i in range(d.nx):
+                Ps = np.array([xs + (i + 0.5) * d.dx, (j + 0.5) * d.dy, (zs + k + 0.5) * d.dz])
+                Pb = np.array([(i + 0.5) * d.dx, (j + 0.5) * d.dy, (k + 0.5) * d.dz])
+                Hs[:, k, j, i] = tensor_field_at(d, Ps, mb, 0.0, 0)
+                Hb[:, k, j, i] = tensor_field_at(d, Pb, ms, xs, zs)
+                for a in range(3):
+                    e = np.zeros(3)
+                    e[a] = steps[a]
+                    dH = (tensor_field_at(d, Ps + e, mb, 0.0, 0)
+                          - tensor_field_at(d, Ps - e, mb, 0.0, 0)) / (2 * steps[a])
+                    F += MU0 * d.Ms * V * ms[a, k, j, i] * dH
+    return Hb, Hs, F
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("nz,s_int,gap", [(2, 0, 1), (2, 3, 2), (3, -2, 1)])
+def test_thick_cross_fields_and_force_equal_brute_force(nz, s_int, gap):
+    d, m = films(nz=nz, gap=gap, seed=nz + 7 * abs(s_int))
+    sysm = SlabSystem(d, Drive(mode=FROZEN, x0=s_int * d.dx), m)
+    Hb, Hs, F = sysm.cross_fields(m[0], m[1], s_int * d.dx, s_int)
+    rb, rs, rF = brute_force(d, m, s_int)
+    assert Hb.shape == Hs.shape == (3, nz, d.ny, d.nx)
+    assert rel(Hs, rs) < 1e-10
+    assert rel(Hb, rb) < 1e-10
+    assert np.abs(F - rF).max() < 1e-9 * np.abs(rF).max()
+
+
+def test_linear_mode_equals_spline_mode_at_integer_offsets():
+    d, m = films(nz=2)
+    a = SlabSystem(d, Drive(mode=FROZEN, x0=2 * d.dx), m).cross_fields(m[0], m[1], 2 * d.dx, 2)
+    b = SlabSystem(d.replace(cross_mode=2), Drive(mode=FROZEN, x0=2 * d.dx), m).cross_fields(
+        m[0], m[1], 2 * d.dx, 2)
+    for u, v in zip(a, b):
+        assert rel(u, v) < 1e-11
+
+
+@pytest.mark.parametrize("cross_mode", [0, 2])
+def test_one_layer_reduces_to_the_film_oracle(cross_mode):
+    d, m = films(nx=9, ny=5, nz=1, cross_mode=cross_mode)
+    x = 1.37 * d.dx
+    a = SlabSystem(d, Drive(mode=FROZEN, x0=x), m).cross_fields(m[0], m[1], x, 1)
+    b = System(d, Drive(mode=FROZEN, x0=x), m).cross_fields(m[0], m[1], x, 1)
+    for u, v in zip(a, b):
+        assert rel(u, v) < 1e-12
+
+
+@pytest.mark.parametrize("direction,s_int", [("b2s", 0), ("b2s", 2), ("s2b", -1)])
+def test_cross_eddy_sums_equal_brute_force(direction, s_int):
+    d, _ = films(nz=2, gap=2, sigma=1e6)
+    sysm = SlabSystem(d, Drive(mode=FROZEN, x0=s_int * d.dx),
+                      [np.tile(np.array([0, 0, 1.0])[:, None, None, None], (1, 2, d.ny, d.nx))] * 2)
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal((3, d.nz, d.ny, d.nx))
+    zs = d.nz + d.gap_cells
+    xs = s_int * d.dx
+    for sign in (+1.0, -1.0):
+        got = sysm.eddy.cross_sum(sysm, sign, direction, v, xs, s_int)
+        ref = np.zeros_like(got)
+        for k in range(d.nz):
+            for j in range(d.ny):
+                for i in range(d.nx):
+                    if direction == "b2s":   # base sources, slider cells
+                        P = np.array([xs + (i + 0.5) * d.dx, (j + 0.5) * d.dy, (zs + k + 0.5) * d.dz])
+                        ref[:, k, j, i] = sign * s_cross_at(d, P, v, 0.0, 0)
+                    else:                    # slider sources, base cells
+                        P = np.array([(i + 0.5) * d.dx, (j + 0.5) * d.dy, (k + 0.5) * d.dz])
+                        ref[:, k, j, i] = sign * s_cross_at(d, P, v, xs, zs)
+        assert rel(got, ref) < 1e-10
+
+
+def test_far_films_reduce_to_the_single_magnet_eddy_field():
+    d, m = films(nx=5, ny=4, nz=3, gap=400, sigma=2e6, seed=11)
+    d = d.replace(sor_sweeps=30)
+    dt = 1e-13
+    rng = np.random.default_rng(4)
+    m2 = [mm + 0.05 * rng.standard_normal(mm.shape) for mm in m]
+    m2 = [mm / np.linalg.norm(mm, axis=0, keepdims=True) for mm in m2]
+    slab = SlabSystem(d, Drive(mode=FROZEN), m)
+    singles = [System(d.replace(n_films=1, gap_cells=0), Drive(), [m[f]]) for f in range(2)]
+    for state in (m, m2):
+        slab.m = [s.copy() for s in state]
+        slab.eddy.update(slab, dt)
+        for f in range(2):
+            singles[f].m = [state[f].copy()]
+            singles[f].eddy.update(singles[f], dt)
+    for f in range(2):
+        ref = singles[f].eddy.H_eddy
+        assert np.abs(ref).max() > 0
+        assert rel(slab.eddy.H[f], ref) < 1e-5
+
+
+def test_moving_films_with_eddy_currents_step():
+    """Two RK4 steps with eddy currents and a moving slider stay finite and
+    normalised; the held eddy fields change with the motion."""
+    d, m = films(nx=6, ny=4, nz=2, gap=1, sigma=1e6, seed=2)
+    drv = Drive(mode=1, v_d=50.0, x0=0.4 * d.dx)
+    s = SlabSystem(d, drv, m)
+    s.run(2e-13, 3)
+    for f in range(2):
+        assert np.all(np.isfinite(s.eddy.H[f]))
+        assert np.abs(s.eddy.H[f]).max() > 0
+        assert np.allclose(np.linalg.norm(s.m[f], axis=0), 1.0, atol=1e-12)
+    assert s.x > 0.4 * d.dx
+
+
+def test_eddy_update_sums_both_films_with_the_right_signs():
+    """E_sol and H_eddy of each film, assembled by the update at an integer
+    offset, equal brute-force sums over both films' cells: E = sum S x dB/dt,
+    H = -sum S x J (Eq. 9 and the Biot-Savart field of the currents)."""
+    d, m = films(nx=5, ny=3, nz=2, gap=1, sigma=1e6, seed=8)
+    s_int, dt = 1, 1e-13
+    slab = SlabSystem(d, Drive(mode=FROZEN, x0=s_int * d.dx), m)
+    rng = np.random.default_rng(9)
+    # about 1e-3 T per step: the backward difference keeps ~13 digits
+    rate = [1e10 * rng.standard_normal((3, d.nz, d.ny, d.nx)) for _ in range(2)]
+    B = slab.eddy.b_fields(slab)
+    slab.eddy.B_prev = [B[f] - dt * rate[f] for f in range(2)]
+    slab.eddy.update(slab, dt)
+    zs = d.nz + d.gap_cells
+    xs = s_int * d.dx
+    origin = [(0.0, 0), (xs, zs)]
+    for f in range(2):
+        E = np.zeros((3, d.nz, d.ny, d.nx))
+        H = np.zeros_like(E)
+        for k in range(d.nz):
+            for j in range(d.ny):
+                for i in range(d.nx):
+                    P = np.array([origin[f][0] + (i + 0.5) * d.dx, (j + 0.5) * d.dy,
+                                  (origin[f][1] + k + 0.5) * d.dz])
+                    for g in range(2):
+                        E[:, k, j, i] += s_cross_at(d, P, rate[g], *origin[g])
+                        H[:, k, j, i] -= s_cross_at(d, P, slab.eddy.J[g], *origin[g])
+        assert rel(slab.eddy.E_sol[f], E) < 1e-10
+        assert rel(slab.eddy.H[f], H) < 1e-10
