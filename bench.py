@@ -344,6 +344,55 @@ def cube_report(steps=40, warmup=4):
     return out
 
 
+def eddy_films_report(steps=20, warmup=2, cpu=True):
+    """Step time of two conducting CoCrPt films, 2 x 128 x 128 x 5 cells of
+    4 nm (the eddy-current friction workload), float32 and float64, with
+    eddy currents in both films (sigma = 1e6 S/m: dB/dt, the E_sol sums with
+    the other film's interpolated part, 40 red-black SOR sweeps per film,
+    J x S) and without (sigma = 0): HIP events around `steps` RK4 steps on
+    the mesh's stream.  The oracle (float64 CPU) times one step."""
+    import torch
+    import paper_1801_04181_amd as mmv
+    from workloads import get_config, initial_state
+
+    cfg = get_config("eddy_films")
+    d0, drv, dt = cfg["desc"], cfg["drive"], cfg["dt"]
+    m = initial_state(cfg)
+    cells = d0.n_films * d0.nx * d0.ny * d0.nz
+    out = {"workload": "2 films 128x128x5 cells of 4 nm, 5 cells apart, CoCrPt, sigma 1e6 S/m, "
+                       "spring drive 2 m/s, RK4 dt 1e-13 s",
+           "cells": cells, "steps": steps}
+    for prec in (32, 64):
+        for eddy in (True, False):
+            d = d0.replace(precision=prec, sigma=d0.sigma if eddy else 0.0)
+            mesh = mmv.Mesh(d, drv, m)
+            mesh.step(dt, warmup)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(mesh.stream)
+            mesh.step(dt, steps)
+            e1.record(mesh.stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            out[f"fp{prec}_{'eddy' if eddy else 'no_eddy'}"] = {
+                "ms_per_step": ms, "cell_updates_per_s": cells / (ms * 1e-3), "fft": list(mesh.fft_lengths()[:2])}
+            mesh.close()
+    if cpu:
+        from threadpoolctl import threadpool_limits
+        from oracle.slab import SlabSystem
+        with threadpool_limits(limits=1):
+            s = SlabSystem(d0.replace(precision=64), drv, m)
+            s.step(dt)              # kernel windows and the first eddy update outside the clock
+            t0 = time.perf_counter()
+            s.step(dt)
+            sec = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": cells / sec, "unit": "cell-updates/s", "kind": "oracle", "cores": 1,
+                               "sample": f"1 RK4 step with eddy currents of the same workload, float64 "
+                                         f"NumPy/SciPy oracle, 1 thread, {sec:.1f} s"}
+    return out
+
+
 def surrogate_report(train_steps=3000, B=8, steps=200, log=None):
     """Learned stray-field operator on the 2 x 256 x 256 films: train on fresh
     exact pairs, held-out error, then LLG steps with the operator attached
@@ -488,7 +537,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="--report batch: eager launches (counter runs)")
-    ap.add_argument("--report", choices=["surrogate", "cube", "batch", "surrogate-batched", "divcurl"],
+    ap.add_argument("--report", choices=["surrogate", "cube", "batch", "surrogate-batched", "divcurl",
+                                         "eddy-films"],
                     default=None)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--calib-copy", action="store_true",
@@ -496,6 +546,10 @@ def main():
     args = ap.parse_args()
     if args.report == "cube":
         print(json.dumps({"cube_report": cube_report()}), flush=True)
+        return
+    if args.report == "eddy-films":
+        print(json.dumps({"eddy_films_report": eddy_films_report(steps=args.steps if args.steps < 2000 else 20,
+                                                                 cpu=not args.no_cpu)}), flush=True)
         return
     if args.report == "batch":
         print(json.dumps({"batched": batched_vs_plain(steps_batch=args.steps, steps_plain=2,

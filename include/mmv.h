@@ -62,7 +62,8 @@ typedef struct mmv_mesh* mmv_handle;
 
 typedef struct {
   int n_films;          /* 1: one magnet; 2: base (film 0) + slider (film 1) */
-  int nx, ny, nz;       /* cells per film; two films need nz == 1            */
+  int nx, ny, nz;       /* cells per film (two films of nz > 1: the thick-film
+                           path below)                                       */
   double dx, dy, dz;    /* cell edges [m]                                     */
   int gap_cells;        /* empty layers between the films (>= 0)              */
   int max_travel_cells; /* |floor(x_s/dx)| allowed; sizes the FFT window      */
@@ -72,7 +73,10 @@ typedef struct {
   double Ku;            /* first-order uniaxial anisotropy [J/m^3]            */
   double u[3];          /* anisotropy axis (normalised by the library)        */
   double Hext[3];       /* uniform applied field [A/m]                        */
-  double sigma;         /* conductivity [S/m]; 0 = no eddy currents           */
+  double sigma;         /* conductivity [S/m]; 0 = no eddy currents.  Eddy
+                           currents need magnets more than one cell thick in
+                           every direction (Sec. IV.D): one magnet with
+                           nz > 1, or two films with nz > 1               */
   int precision;        /* 32 or 64                                           */
   int cross_mode;       /* 0: direct field spline; 1: scalar potential (needs
                            gap_cells >= 3: Sec. IV.D asks for films more than
@@ -124,7 +128,28 @@ typedef struct {
  * before any device call.  The three-dimensional path (one film, nz > 1)
  * holds one x row, y column or z column of a transform pass per
  * block in LDS: nx up to 2520, ny up to 1701 and nz up to 1458 (float32) /
- * 729 (float64), and fewer than 2^31 cells; beyond them, MMV_EINVAL.   */
+ * 729 (float64), and fewer than 2^31 cells; beyond them, MMV_EINVAL.
+ *
+ * Two films more than one cell thick (n_films 2, nz > 1; Sec. II.A end,
+ * III.B, IV.C-D): the thick-film path.  Direct cross modes only (cross_mode
+ * 0 or 2; 1 is MMV_EINVAL), open in-plane boundaries (pbc 0).  Each field
+ * is a sum over the source film's layers of in-plane convolutions with the
+ * kernel of each layer offset (FFT lengths as for one-layer films, fft_lz
+ * unused): the films' own fields, the base's field on the slider's window
+ * (layers z_s - 1 .. z_s + nz, rows -1..ny: Eq. 3's stencil) and the
+ * slider's field on the base's window, sampled along x as in the film
+ * path.  The force of Eq. 3 sums every slider layer.  With sigma > 0, eddy
+ * currents run in both films, once per step from the state at its start
+ * (held through the RK stages): B = mu0 (H_d + H_ext + Ms m) per film with
+ * H_d its own plus the other film's sampled field, dB/dt its backward
+ * difference over the last step (formed in float64 from the fields of the
+ * mesh precision; zero on the first step after set_m), E_sol = sum over
+ * both films of S x dB/dt (the other film's part on its window, sampled),
+ * one Neumann problem per film (SOR as for one magnet), J = sigma (E_sol +
+ * E_irrot) and H_eddy = -sum over both films of S x J the same way.
+ * Uniform H_ext only (set_hext_field: MMV_ESTATE).  Limits: the sampling
+ * rows (6 (nx + 2 halo) reals) and a transform row or column in LDS, and
+ * fewer than 2^31 elements in the product spectra.                      */
 int init_mesh(const mmv_mesh_desc* d, void* hip_stream, mmv_handle* out);
 
 /* Copy a film's magnetisation from / to a caller device buffer
@@ -158,7 +183,7 @@ int set_drive(mmv_handle h, const mmv_drive* drv);
  * The array (host or device memory) is copied, stream-ordered, on the mesh's
  * stream into a buffer the library owns; NULL removes the field.
  * MMV_EINVAL if film is out of range; MMV_ESTATE on the single-magnet 3-D
- * path.  On a batch instance, the batch's descriptors are rebuilt before
+ * path and on two films thicker than one cell.  On a batch instance, the batch's descriptors are rebuilt before
  * its next batch_step.                                                  */
 int set_hext_field(mmv_handle h, int film, const void* field);
 
@@ -167,7 +192,9 @@ int set_hext_field(mmv_handle h, int film, const void* field);
  * problem after the step's SOR sweeps (L: sum over interior faces of
  * (phi_j - phi_i) / d^2; r: the surface flux of E_sol, zero mean).  The
  * sweeps per step are fixed (sor_sweeps), so this is the check of how far
- * they left the potential from the solution.  Synchronises the stream.
+ * they left the potential from the solution; two thick films: both
+ * problems pooled, sqrt(sum_f ||L phi_f - r_f||^2 / sum_f ||r_f||^2).
+ * Synchronises the stream.
  * MMV_ESTATE if the mesh has no eddy currents or no step has run yet.    */
 int eddy_residual(mmv_handle h, double* rel);
 
@@ -224,8 +251,8 @@ int llg_step(mmv_handle h, double dt, int nsteps);
  * stops at t_end or after max_attempts attempts (the state then lies
  * before t_end: get_state tells).  *h_io: initial step in, next proposed
  * step out; *accepted / *rejected (may be NULL): attempts of this call.
- * Film meshes only (MMV_ESTATE for the three-dimensional path, batch
- * instances and meshes with a learned operator attached); MMV_EINVAL for
+ * Film meshes only (MMV_ESTATE for the three-dimensional path, films
+ * thicker than one cell, batch instances and meshes with a learned operator attached); MMV_EINVAL for
  * t_end not after the current time, tol or *h_io not finite and > 0.
  * Reports pending MMV_ERANGE / MMV_ENUMERIC (a non-finite error stops the
  * run with MMV_ENUMERIC).                                                */
@@ -244,7 +271,8 @@ int stray_force(mmv_handle h, double F_out[3]);
  * D = mean over the nx*ny slider cells of |div H|, C = mean of |curl H|
  * [A/m^2], summed in float64 in a fixed order.  Works for every cross_mode
  * (0 spline, 1 scalar potential, 2 linear interpolation).  Synchronises
- * the stream.  MMV_ESTATE for a single-film mesh.                       */
+ * the stream.  MMV_ESTATE for a single-film mesh and for films thicker
+ * than one cell.                                                         */
 int div_curl(mmv_handle h, double* D, double* C);
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -260,7 +288,8 @@ int div_curl(mmv_handle h, double* D, double* C);
  * accepts), MMV_EINVAL otherwise.  All calls on one GPU share that array:
  * calls that overlap on one GPU (other streams, handles or threads) race
  * and must be ordered by the caller.  Pending MMV_ERANGE / MMV_ENUMERIC
- * flags are left for get_state.  MMV_ESTATE for a single-film mesh.     */
+ * flags are left for get_state.  MMV_ESTATE for a single-film mesh and
+ * for films thicker than one cell.                                      */
 int stray_force_noalloc(mmv_handle h, double* F_dev);
 
 /* Time [s], slider position [m] and velocity [m/s] and step count.
@@ -280,7 +309,8 @@ int profile_end(mmv_handle h, double* total_ms, long* launches);
  * stream, and return the mean time per launch (blocks).  The launches
  * overwrite the stage buffers, spectra and force partials: the mesh state is
  * undefined afterwards (set m, offset and drive again before stepping).
- * Two-film meshes that are not part of a batch (MMV_ESTATE otherwise).   */
+ * Two-film meshes of one-cell-thick films that are not part of a batch
+ * (MMV_ESTATE otherwise).                                                */
 int profile_repeat(mmv_handle h, int kernel, int reps, double* avg_ms);
 
 /* Chosen FFT lengths (diagnostics). */

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmmv.so")
-SOURCES = ["mmv_api.hip", "mmv_kernels.hip", "mmv_cube.hip", "mmv_nn.hip", "mmv_fno.hip", "mmv_spline3d.hip"]
+SOURCES = ["mmv_api.hip", "mmv_kernels.hip", "mmv_cube.hip", "mmv_nn.hip", "mmv_fno.hip", "mmv_spline3d.hip", "mmv_slab.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

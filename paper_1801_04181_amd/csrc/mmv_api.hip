@@ -15,6 +15,7 @@
 #include "mmv.h"
 #include "mmv_internal.h"
 #include "mmv_kernels.h"
+#include "mmv_slab.h"
 
 using namespace mmv;
 
@@ -150,6 +151,20 @@ struct mmv_mesh {
   OutTable tab_sur{};
   int sor_sweeps = 40;
   double sor_omega = 1.0;
+  // two films more than one cell thick (uses m0, mb, acc, hd, he, spec1,
+  // kern_s and the eddy buffers above for both films)
+  bool slab = false;
+  int sD = 0;                  // kernel spectra for layer offsets -sD..sD
+  void* kern_t = nullptr;      // tensor spectra [6][2 sD + 1][Ly][Kx]
+  void* specM = nullptr;       // source spectra [2][3][nz][Ly][Kx]
+  void* specP = nullptr;       // product spectra of the target windows
+  void* specI = nullptr;       // after the inverse y transforms
+  void* win_s2b = nullptr;     // slider field on the base's window [3][nz][ny][M]
+  void* win_b2s = nullptr;     // base field on the slider's window [3][nz+2][ny+2][M]
+  void* win_e = nullptr;       // eddy sums on both windows [2][3][nz][ny][M]
+  void* stencil = nullptr;     // base field at the slider's stencil points [3][nz+2][ny+2][nx+2]
+  double* Bprev = nullptr;     // B at the last eddy update [2][3][nz][ny][nx]
+  SlabMulTable tab_t{}, tab_e{};
   // launch timing (diagnostics)
   int prof_kernel = 0;
   size_t prof_used = 0;
@@ -182,8 +197,8 @@ int validate(const mmv_mesh_desc* d) {
   if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(MMV_EINVAL, "nx, ny, nz must be >= 1");
   if (d->nx > 8192 || d->ny > 8192) return fail(MMV_EINVAL, "nx, ny must be <= 8192");
   if (d->nz > 8192) return fail(MMV_EINVAL, "nz must be <= 8192");
-  if (d->nz != 1 && d->n_films != 1)
-    return fail(MMV_EINVAL, "two films must be one cell thick (nz == 1); nz > 1 is the single-magnet path");
+  if (d->nz != 1 && d->n_films == 2 && d->cross_mode == 1)
+    return fail(MMV_EINVAL, "films more than one cell thick run in the direct modes (cross_mode 0 or 2)");
   auto pos = [](double v) { return isfinite(v) && v > 0; };
   if (!pos(d->dx) || !pos(d->dy) || !pos(d->dz)) return fail(MMV_EINVAL, "cell edges must be finite and > 0");
   if (!pos(d->Ms)) return fail(MMV_EINVAL, "Ms must be finite and > 0");
@@ -202,9 +217,9 @@ int validate(const mmv_mesh_desc* d) {
     return fail(MMV_EINVAL, "cross_mode 1 (scalar potential) needs gap_cells >= 3: its four-point difference "
                             "would reach into the other film");
   if (!isfinite(d->sigma) || d->sigma < 0) return fail(MMV_EINVAL, "sigma must be finite and >= 0");
-  if (d->sigma != 0.0 && !(d->n_films == 1 && d->nz > 1 && d->ny > 1 && d->nx > 1))
+  if (d->sigma != 0.0 && !(d->nz > 1 && d->ny > 1 && d->nx > 1))
     return fail(MMV_EINVAL,
-                "eddy currents need a single magnet more than one cell thick in every direction (sigma must be 0)");
+                "eddy currents need magnets more than one cell thick in every direction (sigma must be 0)");
   if (d->sor_sweeps < 0 || d->sor_sweeps > 100000) return fail(MMV_EINVAL, "sor_sweeps must be in [0, 100000]");
   if (!isfinite(d->sor_omega) || d->sor_omega < 0 || d->sor_omega >= 2) return fail(MMV_EINVAL, "sor_omega must be in [0, 2)");
   if (d->gap_cells < 0) return fail(MMV_EINVAL, "gap_cells must be >= 0");
@@ -784,6 +799,317 @@ int eval_cube(mmv_mesh* h, int mask, void* hout) {
   HIPCHK(launch_stage3<T>(h->cl, MODE_EVAL, 0, mask & (1 | 2 | 4 | 8 | 32), 0.0, (const T*)h->m0, (const T*)h->m0,
                           nullptr, nullptr, (const T*)h->hd, (const T*)h->he, (T*)hout, &h->rigid->flags, nullptr,
                           nullptr, h->st));
+  return MMV_OK;
+}
+
+// ---------------------------------------------------------------- two thick films
+// Films of nz > 1 layers in relative motion (Sec. II.A, III.A-B, IV.C-D).
+// Each field is a layer-coupled in-plane convolution (mmv_slab.hip): the
+// films' own fields, the base's field on the slider's window (layers z_s - 1
+// .. z_s + nz, rows -1..ny: the force stencil) and the slider's field on the
+// base's window, then the spline (or linear) sampling along x.
+constexpr int SLAB_KIND_TENSOR = 0, SLAB_KIND_S = 1;
+
+int slab_rows_per_block(int N2x) { return std::max(1, std::min(16, 1024 / N2x)); }
+
+template <typename T>
+int build_kernels_slab(mmv_mesh* h) {
+  const mmv_mesh_desc& d = h->d;
+  const int ndz = 2 * h->sD + 1;
+  const size_t plane = (size_t)h->Ly * h->Kx;
+  int rc = dalloc(h, &h->kern_t, sizeof(T) * 6 * ndz * plane);
+  if (rc) return rc;
+  if (d.sigma > 0 && (rc = dalloc(h, &h->kern_s, sizeof(T) * 3 * ndz * plane))) return rc;
+  mmv_mesh tmp_owner;
+  void *grid = nullptr, *s1 = nullptr, *s2 = nullptr, *twxd = nullptr, *twpd = nullptr, *twyd = nullptr;
+  rc = dalloc(&tmp_owner, &grid, sizeof(double) * (size_t)h->Lx * h->Ly);
+  if (!rc) rc = dalloc(&tmp_owner, &s1, 2 * sizeof(double) * plane);
+  if (!rc) rc = dalloc(&tmp_owner, &s2, 2 * sizeof(double) * plane);
+  if (!rc) rc = upload_tw(&tmp_owner, &twxd, h->N2x, h->N2x, true);
+  if (!rc) rc = upload_tw(&tmp_owner, &twpd, h->Lx, h->N2x + 1, true);
+  if (!rc) rc = upload_tw(&tmp_owner, &twyd, h->Ly, h->Ly, true);
+  if (rc) {
+    free_all(&tmp_owner);
+    return rc;
+  }
+  const double inv = 1.0 / ((double)h->Lx * h->Ly);
+  // stored part of each spectrum: tensor xz, yz and S x, y are imaginary
+  const int imag_t[6] = {0, 0, 0, 0, 1, 1}, imag_s[3] = {1, 1, 0};
+  hipError_t err = hipSuccess;
+  for (int kind = 0; kind < (d.sigma > 0 ? 2 : 1) && err == hipSuccess; ++kind) {
+    const int ncomp = kind == SLAB_KIND_TENSOR ? 6 : 3;
+    for (int comp = 0; comp < ncomp && err == hipSuccess; ++comp) {
+      for (int dz = -h->sD; dz <= h->sD && err == hipSuccess; ++dz) {
+        // tensor spectra carry -Ms (Eq. 6); S spectra enter the eddy sums bare
+        const double sc = kind == SLAB_KIND_TENSOR ? -d.Ms * inv : inv;
+        err = launch_kernel_real((double*)grid, h->Lx, h->Ly, kind, comp, (double)dz, d.dx, d.dy, d.dz, d.rc_cells,
+                                 sc, 0, 0, h->st);
+        if (err == hipSuccess)
+          err = launch_row_fwd<double>((const double*)grid, s1, h->Ly, h->Lx, h->N2x, h->Kx, h->px, twxd, twpd, h->st);
+        if (err == hipSuccess)
+          err = launch_fft_axis<double>(s1, s2, 1, h->Kx, 0, h->Ly, 0, h->Ly, 0, h->py, twyd, false, h->st);
+        T* dst = (T*)(kind == SLAB_KIND_TENSOR ? h->kern_t : h->kern_s) + ((size_t)comp * ndz + dz + h->sD) * plane;
+        if (err == hipSuccess)
+          err = launch_slab_pack<T>(s2, dst, (int)plane, kind == SLAB_KIND_TENSOR ? imag_t[comp] : imag_s[comp], h->st);
+      }
+    }
+  }
+  if (err == hipSuccess) err = hipStreamSynchronize(h->st);
+  free_all(&tmp_owner);
+  if (err != hipSuccess) return fail(MMV_EHIP, std::string("kernel construction: ") + hipGetErrorString(err));
+  return MMV_OK;
+}
+
+template <typename T>
+int init_slab(mmv_mesh* h) {
+  const mmv_mesh_desc& d = h->d;
+  h->esz = sizeof(T);
+  const int nz = h->nz, ny = h->ny, nx = h->nx, M = h->M;
+  const size_t ncell = (size_t)nx * ny * nz, F = 3 * ncell;
+  const size_t plane = (size_t)h->Ly * h->Kx, cs = 2 * sizeof(T);
+  const int zs = nz + d.gap_cells, hl = d.halo;
+  h->sD = zs + nz;
+  int rc;
+  void** bufs[] = {&h->m0, &h->mb[0], &h->mb[1], &h->acc, &h->hd, &h->he};
+  for (void** b : bufs)
+    if ((rc = dalloc(h, b, 2 * F * sizeof(T)))) return rc;
+  const bool eddy = d.sigma > 0;
+  const size_t chP = std::max<size_t>(9 * (size_t)nz + 3 * (size_t)(nz + 2), eddy ? 12 * (size_t)nz : 0);
+  const size_t rowsI = std::max<size_t>(9 * (size_t)nz * ny + 3 * (size_t)(nz + 2) * (ny + 2),
+                                        eddy ? 12 * (size_t)nz * ny : 0);
+  if ((rc = dalloc(h, &h->spec1, cs * 2 * 3 * nz * (size_t)ny * h->Kx))) return rc;
+  if ((rc = dalloc(h, &h->specM, cs * 2 * 3 * nz * plane))) return rc;
+  if ((rc = dalloc(h, &h->specP, cs * chP * plane))) return rc;
+  if ((rc = dalloc(h, &h->specI, cs * rowsI * h->Kx))) return rc;
+  if ((rc = dalloc(h, &h->win_s2b, sizeof(T) * 3 * (size_t)nz * ny * M))) return rc;
+  if ((rc = dalloc(h, &h->win_b2s, sizeof(T) * 3 * (size_t)(nz + 2) * (ny + 2) * M))) return rc;
+  if ((rc = dalloc(h, &h->stencil, sizeof(T) * 3 * (size_t)(nz + 2) * (ny + 2) * (nx + 2)))) return rc;
+  if ((rc = dalloc(h, (void**)&h->partial, sizeof(double) * 3 * (size_t)slab_force_blocks((int)ncell)))) return rc;
+  if (eddy) {
+    void** e2[] = {&h->bdot, &h->es};
+    for (void** b : e2)
+      if ((rc = dalloc(h, b, 2 * F * sizeof(T)))) return rc;
+    void** e1[] = {&h->phi, &h->phi2, &h->rr};
+    for (void** b : e1)
+      if ((rc = dalloc(h, b, 2 * ncell * sizeof(T)))) return rc;
+    if ((rc = dalloc(h, (void**)&h->Bprev, 2 * F * sizeof(double)))) return rc;
+    if ((rc = dalloc(h, &h->win_e, sizeof(T) * 2 * 3 * (size_t)nz * ny * M))) return rc;
+    if ((rc = dalloc(h, (void**)&h->red, sizeof(double) * (ncell / 256 + 4)))) return rc;
+    HIPCHK(hipMemsetAsync(h->phi, 0, 2 * ncell * sizeof(T), h->st));
+  }
+  HIPCHK(hipMemsetAsync(h->he, 0, 2 * F * sizeof(T), h->st));
+  if ((rc = upload_tw(h, &h->twx, h->N2x, h->N2x, sizeof(T) == 8))) return rc;
+  if ((rc = upload_tw(h, &h->twp, h->Lx, h->N2x + 1, sizeof(T) == 8))) return rc;
+  if ((rc = upload_tw(h, &h->twy, h->Ly, h->Ly, sizeof(T) == 8))) return rc;
+  if ((rc = dalloc(h, (void**)&h->rigid, sizeof(RigidState)))) return rc;
+  RigidState r{};
+  HIPCHK(hipMemcpyAsync(h->rigid, &r, sizeof(r), hipMemcpyHostToDevice, h->st));
+  std::vector<T> mz(2 * F, T(0));
+  for (int f = 0; f < 2; ++f)
+    for (size_t i = 0; i < ncell; ++i) mz[f * F + 2 * ncell + i] = T(1);
+  HIPCHK(hipMemcpyAsync(h->m0, mz.data(), mz.size() * sizeof(T), hipMemcpyHostToDevice, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  if ((rc = build_kernels_slab<T>(h))) return rc;
+  // target windows of the two products (mmv_slab.h): the films' own fields,
+  // the slider's field on the base (x0 = -s_int - h), the base's field on
+  // the slider (x0 = s_int - h; with rows -1..ny and layers z_s-1..z_s+nz
+  // for the tensor product); every group [3][ntz][Ly][Kx]
+  const long long P = (long long)plane;
+  h->tab_t.n = 4;
+  h->tab_t.g[0] = SlabGroup{0, 0, nz, 0, 0, 0, 0};
+  h->tab_t.g[1] = SlabGroup{1, 0, nz, 0, 0, 0, 3LL * nz * P};
+  h->tab_t.g[2] = SlabGroup{1, -zs, nz, -1, -hl, 0, 6LL * nz * P};
+  h->tab_t.g[3] = SlabGroup{0, zs - 1, nz + 2, 1, -hl, -1, 9LL * nz * P};
+  h->tab_e.n = 4;
+  h->tab_e.g[0] = SlabGroup{0, 0, nz, 0, 0, 0, 0};
+  h->tab_e.g[1] = SlabGroup{1, 0, nz, 0, 0, 0, 3LL * nz * P};
+  h->tab_e.g[2] = SlabGroup{1, -zs, nz, -1, -hl, 0, 6LL * nz * P};
+  h->tab_e.g[3] = SlabGroup{0, zs, nz, 1, -hl, 0, 9LL * nz * P};
+  CubeLaunch& c = h->cl;
+  c.nx = nx;
+  c.ny = ny;
+  c.nz = nz;
+  c.dx = d.dx;
+  c.dy = d.dy;
+  c.dz = d.dz;
+  c.pref_ex = 2.0 * d.Aex / (MU0 * d.Ms);
+  c.pref_an = 2.0 * d.Ku / (MU0 * d.Ms);
+  const double un = sqrt(d.u[0] * d.u[0] + d.u[1] * d.u[1] + d.u[2] * d.u[2]);
+  for (int i = 0; i < 3; ++i) {
+    c.u[i] = un > 0 ? d.u[i] / un : 0.0;
+    c.hext[i] = d.Hext[i];
+  }
+  c.gam = GAMMA0 / (1.0 + d.alpha * d.alpha);
+  c.alpha = d.alpha;
+  h->sor_sweeps = d.sor_sweeps > 0 ? d.sor_sweeps : 40;
+  const int nmax = std::max(nx, std::max(ny, nz));
+  h->sor_omega = d.sor_omega > 0 ? d.sor_omega : 2.0 / (1.0 + sin(M_PI / nmax));
+  h->rp_hot.travel = h->rp_force.travel = d.max_travel_cells;
+  h->rp_hot.halo = h->rp_force.halo = hl;
+  return MMV_OK;
+}
+
+// Fields of both films at the state m ([2][3][nz][ny][nx]) and the current
+// slider stage: hd = the films' own fields (self) plus the other film's
+// sampled field (cross); the force partials of Eq. 3 (always).
+template <typename T>
+int slab_fields(mmv_mesh* h, const T* m, bool self_on, bool cross_on) {
+  const int nz = h->nz, ny = h->ny, nx = h->nx, Kx = h->Kx, M = h->M;
+  const size_t F = 3 * (size_t)nx * ny * nz;
+  const size_t P = (size_t)h->Ly * Kx;
+  const int R = slab_rows_per_block(h->N2x);
+  const double idx = 1.0 / h->d.dx;
+  const int interp = h->d.cross_mode == 2 ? 1 : 0;
+  HIPCHK(launch_row_fwd<T>(m, h->spec1, 6 * nz * ny, nx, h->N2x, Kx, h->px, h->twx, h->twp, h->st, -R));
+  HIPCHK(launch_fft_axis<T>(h->spec1, h->specM, 6 * nz, Kx, 0, ny, (long long)ny * Kx, h->Ly, (long long)P, h->py,
+                            h->twy, false, h->st));
+  HIPCHK(launch_slab_mul<T>(h->specM, h->specP, (const T*)h->kern_t, h->tab_t, nz, h->sD, h->Lx, h->Ly, Kx, 0, 1.0,
+                            h->rigid, h->st));
+  char* pI = (char*)h->specI;
+  const size_t cs = 2 * sizeof(T);
+  HIPCHK(launch_fft_axis<T>(h->specP, pI, 9 * nz, Kx, 0, h->Ly, (long long)P, ny, (long long)ny * Kx, h->py, h->twy,
+                            true, h->st));
+  HIPCHK(launch_fft_axis<T>((char*)h->specP + cs * 9 * nz * P, pI + cs * 9 * (size_t)nz * ny * Kx, 3 * (nz + 2), Kx, 0,
+                            h->Ly, (long long)P, ny + 2, (long long)(ny + 2) * Kx, h->py, h->twy, true, h->st));
+  HIPCHK(launch_row_inv<T>(pI, (T*)h->hd, 6 * nz * ny, R, nx, h->N2x, Kx, h->px, h->twx, h->twp, h->st));
+  HIPCHK(launch_row_inv<T>(pI + cs * 6 * (size_t)nz * ny * Kx, (T*)h->win_s2b, 3 * nz * ny, R, M, h->N2x, Kx, h->px,
+                           h->twx, h->twp, h->st));
+  HIPCHK(launch_row_inv<T>(pI + cs * 9 * (size_t)nz * ny * Kx, (T*)h->win_b2s, 3 * (nz + 2) * (ny + 2), R, M, h->N2x,
+                           Kx, h->px, h->twx, h->twp, h->st));
+  if (!self_on) HIPCHK(hipMemsetAsync(h->hd, 0, 2 * F * sizeof(T), h->st));
+  if (cross_on)
+    HIPCHK(launch_slab_sample<T>((const T*)h->win_s2b, nz * ny, M, h->d.halo, (T*)h->hd, 0, nx, -1, 1, interp, idx,
+                                 h->rigid, h->st));
+  HIPCHK(launch_slab_sample<T>((const T*)h->win_b2s, (nz + 2) * (ny + 2), M, h->d.halo, (T*)h->stencil, -1, nx + 2, 1,
+                               0, interp, idx, h->rigid, h->st));
+  HIPCHK(launch_slab_force<T>((const T*)h->stencil, m + F, (T*)h->hd + F, nx, ny, nz, cross_on ? 1 : 0, h->d.dx,
+                              h->d.dy, h->d.dz, h->partial, h->st));
+  return MMV_OK;
+}
+
+// sgn * sum over both films of S x src (own film: lattice sum; other film:
+// sampled window), src and dst [2][3][nz][ny][nx]
+template <typename T>
+int slab_s_sum(mmv_mesh* h, const T* src, T* dst, double sgn) {
+  const int nz = h->nz, ny = h->ny, nx = h->nx, Kx = h->Kx, M = h->M;
+  const size_t F = 3 * (size_t)nx * ny * nz;
+  const size_t P = (size_t)h->Ly * Kx;
+  const int R = slab_rows_per_block(h->N2x);
+  const size_t cs = 2 * sizeof(T);
+  const int interp = h->d.cross_mode == 2 ? 1 : 0;
+  char* pI = (char*)h->specI;
+  HIPCHK(launch_row_fwd<T>(src, h->spec1, 6 * nz * ny, nx, h->N2x, Kx, h->px, h->twx, h->twp, h->st, -R));
+  HIPCHK(launch_fft_axis<T>(h->spec1, h->specM, 6 * nz, Kx, 0, ny, (long long)ny * Kx, h->Ly, (long long)P, h->py,
+                            h->twy, false, h->st));
+  HIPCHK(launch_slab_mul<T>(h->specM, h->specP, (const T*)h->kern_s, h->tab_e, nz, h->sD, h->Lx, h->Ly, Kx, 1, sgn,
+                            h->rigid, h->st));
+  HIPCHK(launch_fft_axis<T>(h->specP, pI, 12 * nz, Kx, 0, h->Ly, (long long)P, ny, (long long)ny * Kx, h->py, h->twy,
+                            true, h->st));
+  HIPCHK(launch_row_inv<T>(pI, dst, 6 * nz * ny, R, nx, h->N2x, Kx, h->px, h->twx, h->twp, h->st));
+  HIPCHK(launch_row_inv<T>(pI + cs * 6 * (size_t)nz * ny * Kx, (T*)h->win_e, 6 * nz * ny, R, M, h->N2x, Kx, h->px,
+                           h->twx, h->twp, h->st));
+  const size_t wsz = 3 * (size_t)nz * ny * M;
+  HIPCHK(launch_slab_sample<T>((const T*)h->win_e, nz * ny, M, h->d.halo, dst, 0, nx, -1, 1, interp, 1.0 / h->d.dx,
+                               h->rigid, h->st));
+  HIPCHK(launch_slab_sample<T>((const T*)h->win_e + wsz, nz * ny, M, h->d.halo, dst + F, 0, nx, 1, 1, interp,
+                               1.0 / h->d.dx, h->rigid, h->st));
+  return MMV_OK;
+}
+
+// Eddy-current update at the start of a step, from the fields hd of its
+// first stage (held through the step's stages).
+template <typename T>
+int slab_eddy(mmv_mesh* h, const T* m, double dt) {
+  const size_t ncell = (size_t)h->nx * h->ny * h->nz, F = 3 * ncell;
+  double* mean = h->red + (ncell / 256 + 2);
+  HIPCHK(launch_slab_bdot<T>((int)(2 * F), (int)ncell, (const T*)h->hd, m, h->d.Hext, MU0, h->d.Ms, 1.0 / dt,
+                             h->eddy_first ? 1 : 0, h->Bprev, (T*)h->bdot, h->st));
+  h->eddy_first = false;
+  int rc = slab_s_sum<T>(h, (const T*)h->bdot, (T*)h->es, +1.0);
+  if (rc) return rc;
+  for (int f = 0; f < 2; ++f) {
+    T* es = (T*)h->es + f * F;
+    T* rr = (T*)h->rr + f * ncell;
+    T* phi = (T*)h->phi + f * ncell;
+    T* phi2 = (T*)h->phi2 + f * ncell;
+    HIPCHK(launch_sor_rhs<T>(h->cl, es, rr, h->red, mean, h->st));
+    HIPCHK(launch_sor<T>(h->cl, phi, phi2, rr, h->sor_omega, h->sor_sweeps, h->red, mean, h->st));
+    HIPCHK(launch_current<T>(h->cl, phi, es, (T*)h->bdot + f * F, h->d.sigma, h->st));
+  }
+  return slab_s_sum<T>(h, (const T*)h->bdot, (T*)h->he, -1.0);
+}
+
+TickArgs slab_tick(mmv_mesh* h) {
+  TickArgs a{};
+  a.partial = h->partial;
+  a.rigid = h->rigid;
+  a.drive = h->drive;
+  a.force_scale = MU0 * h->d.Ms * h->d.dx * h->d.dy * h->d.dz;
+  a.dx = h->d.dx;
+  a.ntask = slab_force_blocks(h->nx * h->ny * h->nz);
+  a.travel = h->d.max_travel_cells;
+  a.scheme = 0;
+  a.ctrl = nullptr;
+  return a;
+}
+
+template <typename T>
+int step_slab(mmv_mesh* h, double dt, int nsteps) {
+  T* m0 = (T*)h->m0;
+  T* b1 = (T*)h->mb[0];
+  T* b2 = (T*)h->mb[1];
+  const size_t F = 3 * (size_t)h->nx * h->ny * h->nz;
+  const TickArgs tick = slab_tick(h);
+  for (int n = 0; n < nsteps; ++n) {
+    for (int s = 0; s < 4; ++s) {
+      T* in = s == 0 ? m0 : (s == 1 ? b1 : (s == 2 ? b2 : b1));
+      T* out = s == 0 ? b1 : (s == 1 ? b2 : (s == 2 ? b1 : m0));
+      int rc = slab_fields<T>(h, in, true, true);
+      if (rc) return rc;
+      if (s == 0 && h->d.sigma > 0 && (rc = slab_eddy<T>(h, m0, dt))) return rc;
+      // the slider's stage from this stage's force (after every sampling of
+      // the stage has read its position)
+      HIPCHK(launch_tick(tick, s, dt, h->st));
+      for (int f = 0; f < 2; ++f)
+        HIPCHK(launch_stage3<T>(h->cl, MODE_STAGE, s, MMV_TERM_ALL, dt, in + f * F, m0 + f * F, out + f * F,
+                                (T*)h->acc + f * F, (const T*)h->hd + f * F, (const T*)h->he + f * F, nullptr,
+                                &h->rigid->flags, nullptr, nullptr, h->st));
+    }
+  }
+  return MMV_OK;
+}
+
+template <typename T>
+int eval_slab(mmv_mesh* h, int film, int mask, void* hout) {
+  const size_t F = 3 * (size_t)h->nx * h->ny * h->nz;
+  const bool dem = (mask & (MMV_TERM_DEMAG_SELF | MMV_TERM_DEMAG_CROSS)) != 0;
+  if (dem) {
+    int rc = slab_fields<T>(h, (const T*)h->m0, (mask & MMV_TERM_DEMAG_SELF) != 0, (mask & MMV_TERM_DEMAG_CROSS) != 0);
+    if (rc) return rc;
+  }
+  const int m3 = (mask & (MMV_TERM_EXCHANGE | MMV_TERM_ANISOTROPY | MMV_TERM_ZEEMAN | MMV_TERM_EDDY)) |
+                 (dem ? MMV_TERM_DEMAG_SELF : 0);
+  const T* m0 = (const T*)h->m0 + film * F;
+  HIPCHK(launch_stage3<T>(h->cl, MODE_EVAL, 0, m3, 0.0, m0, m0, nullptr, nullptr, (const T*)h->hd + film * F,
+                          (const T*)h->he + film * F, (T*)hout, &h->rigid->flags, nullptr, nullptr, h->st));
+  return MMV_OK;
+}
+
+// Eq. 3's force at the current state [N] (blocks on the stream).
+template <typename T>
+int force_slab(mmv_mesh* h, double F_out[3]) {
+  int rc = slab_fields<T>(h, (const T*)h->m0, true, true);
+  if (rc) return rc;
+  const int nb = slab_force_blocks(h->nx * h->ny * h->nz);
+  std::vector<double> part(3 * (size_t)nb);
+  HIPCHK(hipMemcpyAsync(part.data(), h->partial, sizeof(double) * part.size(), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  const double sc = MU0 * h->d.Ms * h->d.dx * h->d.dy * h->d.dz;
+  for (int a = 0; a < 3; ++a) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[3 * (size_t)b + a];
+    F_out[a] = sc * s;
+  }
   return MMV_OK;
 }
 
@@ -1850,6 +2176,46 @@ int init_mesh(const mmv_mesh_desc* d, void* hip_stream, mmv_handle* out) {
     *out = h;
     return MMV_OK;
   }
+  if (d->n_films == 2 && d->nz > 1) {
+    // two thick films: in-plane transforms sized as for one-layer films
+    h->slab = true;
+    h->nz = d->nz;
+    const int lx_min = 2 * (d->nx + d->halo + d->max_travel_cells), ly_min = 2 * (d->ny + 1);
+    h->Lx = d->fft_lx ? d->fft_lx : next_smooth(lx_min, true);
+    h->Ly = d->fft_ly ? d->fft_ly : next_smooth(ly_min, false);
+    if (h->Lx < lx_min || h->Lx % 2 || !smooth2357(h->Lx) || h->Ly < ly_min || !smooth2357(h->Ly)) {
+      delete h;
+      return fail(MMV_EINVAL, "fft_lx must be even, {2,3,5,7}-smooth and >= " + std::to_string(lx_min) +
+                                  "; fft_ly {2,3,5,7}-smooth and >= " + std::to_string(ly_min));
+    }
+    h->N2x = h->Lx / 2;
+    h->Kx = h->N2x + 1;
+    h->Kyh = h->Ly / 2 + 1;
+    h->M = d->nx + 2 * d->halo;
+    // LDS of the transforms (one row or column, float64 at set-up), the
+    // sampling rows, and 32-bit indexing of every array
+    const size_t es = d->precision == 64 ? 8 : 4, lim = 160 * 1024;
+    const bool lds_ok = 16 * (4 * (size_t)h->N2x + 1) <= lim && 16 * 3 * (size_t)h->Ly <= lim &&
+                        slab_sample_lds(h->M, (int)es) + 1024 <= lim;
+    const long long chans = 9LL * d->nz + 3LL * (d->nz + 2) + 12LL * d->nz;
+    if (!lds_ok || chans * h->Ly * h->Kx >= (1LL << 31) || 2LL * 3 * d->nx * d->ny * d->nz >= (1LL << 31) ||
+        2LL * (2 * d->nz + d->gap_cells) + 1 > 4096) {
+      delete h;
+      return fail(MMV_EINVAL, "films too large for the thick-film path");
+    }
+    if (!make_plan(h->N2x, h->px) || !make_plan(h->Ly, h->py)) {
+      delete h;
+      return fail(MMV_EINVAL, "FFT length has too many factors");
+    }
+    rc = d->precision == 64 ? init_slab<double>(h) : init_slab<float>(h);
+    if (rc) {
+      free_all(h);
+      delete h;
+      return rc;
+    }
+    *out = h;
+    return MMV_OK;
+  }
   const int hx = d->n_films == 2 ? d->halo : 0;
   const int T = d->n_films == 2 ? d->max_travel_cells : 0;
   int lx_min = d->n_films == 2 ? 2 * (d->nx + hx + T) : 2 * d->nx;
@@ -1978,7 +2344,8 @@ int profile_repeat(mmv_handle h, int kernel, int reps, double* avg_ms) {
   if (rc) return rc;
   if (kernel < 1 || kernel > 3) return fail(MMV_EINVAL, "kernel must be 1, 2 or 3");
   if (reps < 1 || reps > 100000) return fail(MMV_EINVAL, "reps must be in [1, 100000]");
-  if (h->cube || h->nfilm != 2 || h->in_batch) return fail(MMV_ESTATE, "profile_repeat needs a two-film mesh");
+  if (h->cube || h->slab || h->nfilm != 2 || h->in_batch)
+    return fail(MMV_ESTATE, "profile_repeat needs a two-film mesh of one-cell-thick films");
   return h->esz == 8 ? repeat_typed<double>(h, kernel, reps, avg_ms) : repeat_typed<float>(h, kernel, reps, avg_ms);
 }
 
@@ -2206,23 +2573,29 @@ int eddy_residual(mmv_handle h, double* rel) {
   int rc = check_handle(h);
   if (rc) return rc;
   if (!rel) return fail(MMV_EINVAL, "rel is NULL");
-  if (!h->cube || !(h->d.sigma > 0)) return fail(MMV_ESTATE, "no eddy-current solve on this mesh");
+  if (!(h->cube || h->slab) || !(h->d.sigma > 0)) return fail(MMV_ESTATE, "no eddy-current solve on this mesh");
   if (h->eddy_first) return fail(MMV_ESTATE, "no step has run the eddy solve yet");
   const size_t N = (size_t)h->nx * h->ny * h->nz;
   // the partials reuse the eddy update's reduction buffer (N/256 + 2 doubles
-  // before the mean), free between steps
+  // before the mean), free between steps; two thick films: both problems
+  // summed, ||L phi - r|| and ||r|| over the two films together
   const int nblk = (int)std::max<size_t>(1, std::min<size_t>(512, (N / 256 + 2) / 2));
-  if (h->esz == 8)
-    HIPCHK(launch_sor_residual<double>(h->cl, (const double*)h->phi, (const double*)h->rr, h->red, nblk, h->st));
-  else
-    HIPCHK(launch_sor_residual<float>(h->cl, (const float*)h->phi, (const float*)h->rr, h->red, nblk, h->st));
-  std::vector<double> part(2 * (size_t)nblk);
-  HIPCHK(hipMemcpyAsync(part.data(), h->red, sizeof(double) * part.size(), hipMemcpyDeviceToHost, h->st));
-  HIPCHK(hipStreamSynchronize(h->st));
   double a = 0.0, b = 0.0;
-  for (int k = 0; k < nblk; ++k) {
-    a += part[2 * (size_t)k];
-    b += part[2 * (size_t)k + 1];
+  for (int f = 0; f < (h->slab ? 2 : 1); ++f) {
+    const size_t off = (size_t)f * N * h->esz;
+    if (h->esz == 8)
+      HIPCHK(launch_sor_residual<double>(h->cl, (const double*)((char*)h->phi + off),
+                                         (const double*)((char*)h->rr + off), h->red, nblk, h->st));
+    else
+      HIPCHK(launch_sor_residual<float>(h->cl, (const float*)((char*)h->phi + off), (const float*)((char*)h->rr + off),
+                                        h->red, nblk, h->st));
+    std::vector<double> part(2 * (size_t)nblk);
+    HIPCHK(hipMemcpyAsync(part.data(), h->red, sizeof(double) * part.size(), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    for (int k = 0; k < nblk; ++k) {
+      a += part[2 * (size_t)k];
+      b += part[2 * (size_t)k + 1];
+    }
   }
   *rel = b > 0 ? sqrt(a / b) : sqrt(a);
   return MMV_OK;
@@ -2271,7 +2644,7 @@ int spline3_gather(int precision, const void* coef, int nx, int ny, int nz, cons
 int set_hext_field(mmv_handle h, int film, const void* field) {
   int rc = check_handle(h);
   if (rc) return rc;
-  if (h->cube) return fail(MMV_ESTATE, "the applied-field array belongs to the film path");
+  if (h->cube || h->slab) return fail(MMV_ESTATE, "the applied-field array belongs to the one-cell-thick film path");
   if (film < 0 || film >= h->nfilm) return fail(MMV_EINVAL, "film out of range");
   const bool px = (h->d.pbc & 1) != 0;
   const int w = (film == 0 || px) ? h->nx : h->nx + 2 * (h->rp_hot.travel + h->d.halo);
@@ -2302,6 +2675,8 @@ int eval_heff(mmv_handle h, int film, int term_mask, void* h_dev) {
   if (!h_dev) return fail(MMV_EINVAL, "h_dev is NULL");
   if (term_mask & ~MMV_TERM_ALL) return fail(MMV_EINVAL, "unknown term bits");
   if (h->cube) return h->esz == 8 ? eval_cube<double>(h, term_mask, h_dev) : eval_cube<float>(h, term_mask, h_dev);
+  if (h->slab)
+    return h->esz == 8 ? eval_slab<double>(h, film, term_mask, h_dev) : eval_slab<float>(h, film, term_mask, h_dev);
   return h->esz == 8 ? eval_typed<double>(h, film, term_mask, h_dev) : eval_typed<float>(h, film, term_mask, h_dev);
 }
 
@@ -2311,6 +2686,7 @@ int llg_step(mmv_handle h, double dt, int nsteps) {
   if (!(dt > 0) || !isfinite(dt)) return fail(MMV_EINVAL, "dt must be finite and > 0");
   if (nsteps < 0) return fail(MMV_EINVAL, "nsteps must be >= 0");
   if (h->cube) return h->esz == 8 ? step_cube<double>(h, dt, nsteps) : step_cube<float>(h, dt, nsteps);
+  if (h->slab) return h->esz == 8 ? step_slab<double>(h, dt, nsteps) : step_slab<float>(h, dt, nsteps);
   return h->esz == 8 ? step_typed<double>(h, dt, nsteps) : step_typed<float>(h, dt, nsteps);
 }
 
@@ -2362,6 +2738,13 @@ int stray_force(mmv_handle h, double F_out[3]) {
   if (rc) return rc;
   if (!F_out) return fail(MMV_EINVAL, "F_out is NULL");
   if (h->nfilm != 2) return fail(MMV_ESTATE, "stray_force needs two films");
+  if (h->slab) {
+    rc = h->esz == 8 ? force_slab<double>(h, F_out) : force_slab<float>(h, F_out);
+    if (rc) return rc;
+    RigidState r;
+    if ((rc = read_rigid(h, r))) return rc;
+    return report_flags(h, r);
+  }
   rc = h->esz == 8 ? force_typed<double>(h, h->partial, h->counter, nullptr)
                     : force_typed<float>(h, h->partial, h->counter, nullptr);
   if (rc) return rc;
@@ -2375,7 +2758,7 @@ int stray_force_noalloc(mmv_handle h, double* F_dev) {
   int rc = check_handle(h);
   if (rc) return rc;
   if (!F_dev) return fail(MMV_EINVAL, "F_dev is NULL");
-  if (h->nfilm != 2) return fail(MMV_ESTATE, "stray_force_noalloc needs two films");
+  if (h->nfilm != 2 || h->slab) return fail(MMV_ESTATE, "stray_force_noalloc needs two one-cell-thick films");
   const size_t part_bytes = noalloc_partial_bytes(h->ny + 2);
   if (part_bytes + NOALLOC_COUNTER_BYTES > NOALLOC_SCRATCH_BYTES)
     return fail(MMV_EINVAL, "stray_force_noalloc: ny + 2 force rows need " + std::to_string(part_bytes) +
@@ -2394,7 +2777,7 @@ int llg_run_dp(mmv_handle h, double t_end, double tol, double* h_io, int max_att
                long* rejected) {
   int rc = check_handle(h);
   if (rc) return rc;
-  if (h->cube) return fail(MMV_ESTATE, "llg_run_dp runs on the film path (nz == 1)");
+  if (h->cube || h->slab) return fail(MMV_ESTATE, "llg_run_dp runs on the film path (nz == 1)");
   if (h->in_batch) return fail(MMV_ESTATE, "llg_run_dp does not run on batch instances");
   if (h->sur) return fail(MMV_ESTATE, "llg_run_dp does not run with a learned operator attached");
   if (!h_io) return fail(MMV_EINVAL, "h_io is NULL");
@@ -2442,7 +2825,7 @@ int div_curl(mmv_handle h, double* D, double* C) {
   int rc = check_handle(h);
   if (rc) return rc;
   if (!D || !C) return fail(MMV_EINVAL, "D and C must not be NULL");
-  if (h->cube || h->nfilm != 2) return fail(MMV_ESTATE, "div_curl needs two films");
+  if (h->cube || h->slab || h->nfilm != 2) return fail(MMV_ESTATE, "div_curl needs two one-cell-thick films");
   return h->esz == 8 ? div_curl_typed<double>(h, D, C) : div_curl_typed<float>(h, D, C);
 }
 

@@ -1,0 +1,301 @@
+// HIP kernels of the thick two-film path: films nx x ny x nz cells (nz > 1)
+// in relative motion along x, with eddy currents in both (Sec. II.A end,
+// Sec. III.A-B, Eqs. 3, 6, 9-12; Sec. IV.C-D).
+//
+// Every field of one film on another film's cells (or its own) is a sum over
+// the source film's layers of in-plane convolutions: the m (or dB/dt, or J)
+// of each source layer is transformed along x and y once, and each target
+// layer t takes sum_l K(t - l) * mhat_l with the kernel of the layer offset
+// t - l (2-D spectra of the tensor N of Eq. 6, or of the potential kernel S of
+// Eq. 8 for the eddy sums).  A target window that starts at lattice point
+// (x0, y0) is shifted to the origin by the phase exp(2 pi i (kx x0 / Lx +
+// ky y0 / Ly)) in the product, so the inverse transforms write it from index
+// 0; x0 follows the slider's seat s_int, read from device memory.
+//
+//   k_slab_pack    one real part (or imaginary part) of a float64 kernel
+//                  spectrum, in the mesh precision
+//   k_slab_mul     the layer-coupled product of the source spectra with the
+//                  kernel spectra, per target window (tensor or S x v)
+//   k_slab_sample  one window row: cubic B-spline coefficients (mirror
+//                  boundaries, a truncated symmetric filter) and samples at
+//                  the other film's shifted cells, or linear interpolation
+//   k_slab_force   the base field on the slider's cells and Eq. 3's force
+//                  partials from the sampled stencil points
+//   k_slab_bdot    B = mu0 (H_d + H_ext + Ms m) per cell and its backward
+//                  difference over the step
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include "mmv_device.h"
+#include "mmv_slab.h"
+
+namespace mmv {
+
+constexpr int SLAB_THREADS = 256;
+
+template <typename T>
+__global__ void __launch_bounds__(SLAB_THREADS)
+    k_slab_pack(const cpx<double>* __restrict__ spec, T* __restrict__ out, int n, int imag) {
+  const int i = (int)(blockIdx.x * SLAB_THREADS + threadIdx.x);
+  if (i < n) out[i] = (T)(imag ? spec[i].y : spec[i].x);
+}
+
+// Kernel spectra: kern[(comp * ndz + dz + D) * Ly * Kx + ky * Kx + kx], one
+// real number per point: tensor components xx yy zz xy (real spectra) and
+// xz yz (imaginary, value = i * stored); S components x, y (imaginary) and z
+// (real).  Grid: (points / SLAB_THREADS, groups).
+template <typename T>
+__global__ void __launch_bounds__(SLAB_THREADS)
+    k_slab_mul(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, const T* __restrict__ kern, SlabMulTable tab,
+               int nz, int D, int Lx, int Ly, int Kx, int mode, T sgn, const RigidState* __restrict__ rigid) {
+  const int plane = Ly * Kx;
+  const int q = (int)(blockIdx.x * SLAB_THREADS + threadIdx.x);
+  if (q >= plane) return;
+  const SlabGroup G = tab.g[blockIdx.y];
+  const int ky = q / Kx, kx = q - ky * Kx;
+  const int x0 = G.xs * rigid->s_int + G.xoff;
+  long long px = ((long long)kx * x0) % Lx;
+  if (px < 0) px += Lx;
+  long long py = ((long long)ky * G.yoff) % Ly;
+  if (py < 0) py += Ly;
+  const double frac = (double)px / (double)Lx + (double)py / (double)Ly;
+  T ps, pc;
+  if constexpr (sizeof(T) == 8)
+    sincospi(2.0 * frac, &ps, &pc);
+  else
+    sincospif((float)(2.0 * frac), &ps, &pc);
+  const size_t ks = (size_t)plane * (2 * D + 1);  // stride of one component
+  const cpx<T>* src = in + (size_t)G.src * 3 * nz * plane + q;
+  cpx<T>* dst = out + G.out + q;
+  for (int k = 0; k < G.ntz; ++k) {
+    const int t = G.tz0 + k;
+    cpx<T> o0 = mk<T>(0, 0), o1 = mk<T>(0, 0), o2 = mk<T>(0, 0);
+    for (int l = 0; l < nz; ++l) {
+      const T* K = kern + (size_t)(t - l + D) * plane + q;
+      const cpx<T> v0 = src[(size_t)(0 * nz + l) * plane];
+      const cpx<T> v1 = src[(size_t)(1 * nz + l) * plane];
+      const cpx<T> v2 = src[(size_t)(2 * nz + l) * plane];
+      if (mode == 0) {
+        const T nxx = K[0], nyy = K[ks], nzz = K[2 * ks], nxy = K[3 * ks], ixz = K[4 * ks], iyz = K[5 * ks];
+        // i * a for a complex v: (-v.y, v.x)
+        o0 = o0 + scale(v0, nxx) + scale(v1, nxy) + mk<T>(-ixz * v2.y, ixz * v2.x);
+        o1 = o1 + scale(v0, nxy) + scale(v1, nyy) + mk<T>(-iyz * v2.y, iyz * v2.x);
+        o2 = o2 + mk<T>(-(ixz * v0.y + iyz * v1.y), ixz * v0.x + iyz * v1.x) + scale(v2, nzz);
+      } else {
+        // S = (i sx, i sy, sz): (S x v) = (i sy v2 - sz v1, sz v0 - i sx v2, i (sx v1 - sy v0))
+        const T sx = K[0], sy = K[ks], sz = K[2 * ks];
+        o0 = o0 + mk<T>(-sy * v2.y, sy * v2.x) - scale(v1, sz);
+        o1 = o1 + scale(v0, sz) - mk<T>(-sx * v2.y, sx * v2.x);
+        const cpx<T> d = scale(v1, sx) - scale(v0, sy);
+        o2 = o2 + mk<T>(-d.y, d.x);
+      }
+    }
+    const cpx<T> ph = mk<T>(pc * sgn, ps * sgn);
+    dst[(size_t)(0 * G.ntz + k) * plane] = cmul(o0, ph);
+    dst[(size_t)(1 * G.ntz + k) * plane] = cmul(o1, ph);
+    dst[(size_t)(2 * G.ntz + k) * plane] = cmul(o2, ph);
+  }
+}
+
+// Whole-sample mirror index of k into [0, M) (M >= 2).
+__device__ __forceinline__ int slab_reflect(int k, int M) {
+  const int P = 2 * M - 2;
+  k %= P;
+  if (k < 0) k += P;
+  return k > M - 1 ? P - k : k;
+}
+
+// Window rows win[3][nrow][M] -> out[3][nrow][nw] at u = i + h + sgn * x_p,
+// i = i0 .. i0 + nw - 1, x_p = x_s / dx - s_int of the current stage.
+// interp 0: cubic B-spline; its coefficients solve the mirror-bounded
+// system (c_{k-1} + 4 c_k + c_{k+1}) / 6 = f_k, i.e. the symmetric filter
+// sqrt(3) z^|j| (z = sqrt(3) - 2) on the mirror-periodic extension of the
+// row, truncated at |j| <= KF where |z|^KF is below the precision.
+// interp 1: linear interpolation of the samples.  One block per row.
+template <typename T>
+__global__ void __launch_bounds__(SLAB_THREADS)
+    k_slab_sample(const T* __restrict__ win, int nrow, int M, int h, T* __restrict__ out, int i0, int nw, int sgn,
+                  int add, int interp, double inv_dx, const RigidState* __restrict__ rigid) {
+  constexpr int KF = sizeof(T) == 8 ? 30 : 16;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* f = reinterpret_cast<T*>(smem_raw);  // [3][M]
+  T* c = f + 3 * M;                        // [3][M]
+  __shared__ T w[KF + 1];
+  const int r = blockIdx.x;
+  if (r >= nrow) return;
+  if (threadIdx.x <= KF) w[threadIdx.x] = (T)(1.7320508075688772935 * pow(1.7320508075688772935 - 2.0, (double)threadIdx.x));
+  for (int t = threadIdx.x; t < 3 * M; t += SLAB_THREADS) {
+    const int a = t / M, k = t - a * M;
+    f[t] = win[((size_t)a * nrow + r) * M + k];
+  }
+  __syncthreads();
+  const T* src = f;
+  if (interp == 0) {
+    for (int t = threadIdx.x; t < 3 * M; t += SLAB_THREADS) {
+      const int a = t / M, k = t - a * M;
+      const T* fa = f + a * M;
+      T s = w[0] * fa[k];
+      for (int j = 1; j <= KF; ++j) s += w[j] * (fa[slab_reflect(k + j, M)] + fa[slab_reflect(k - j, M)]);
+      c[t] = s;
+    }
+    __syncthreads();
+    src = c;
+  }
+  const double xp = sgn * (rigid->xs * inv_dx - (double)rigid->s_int);
+  const double fl = floor(xp);
+  const int k0 = (int)fl + h;
+  const T tt = (T)(xp - fl);
+  T wb[4];
+  if (interp == 0) {
+    const T u = T(1) - tt;
+    wb[0] = u * u * u / T(6);
+    wb[1] = T(2) / T(3) - tt * tt + T(0.5) * tt * tt * tt;
+    wb[2] = T(2) / T(3) - u * u + T(0.5) * u * u * u;
+    wb[3] = tt * tt * tt / T(6);
+  } else {
+    wb[0] = T(0);
+    wb[1] = T(1) - tt;
+    wb[2] = tt;
+    wb[3] = T(0);
+  }
+  for (int t = threadIdx.x; t < 3 * nw; t += SLAB_THREADS) {
+    const int a = t / nw, o = t - a * nw;
+    const int k = k0 + i0 + o;
+    const T* sa = src + a * M;
+    const T v = wb[0] * sa[slab_reflect(k - 1, M)] + wb[1] * sa[slab_reflect(k, M)] +
+                wb[2] * sa[slab_reflect(k + 1, M)] + wb[3] * sa[slab_reflect(k + 2, M)];
+    T* d = out + ((size_t)a * nrow + r) * nw + o;
+    *d = add ? *d + v : v;
+  }
+}
+
+// Stencil G[3][nz+2][ny+2][nx+2]: the base field at window layer t (slider
+// layer t - 1), row y (lattice row y - 1), point i (slider column i - 1).
+// Per slider cell: the centre value is added to hd (when add), and the force
+// density (m . grad) H with two-point central differences is summed in
+// float64; block b writes its sums to part[3 b .. 3 b + 2].
+template <typename T>
+__global__ void __launch_bounds__(SLAB_THREADS)
+    k_slab_force(const T* __restrict__ G, const T* __restrict__ m, T* __restrict__ hd, int nx, int ny, int nz, int add,
+                 double i2dx, double i2dy, double i2dz, double* __restrict__ part) {
+  __shared__ double red[3][SLAB_THREADS / 64];
+  const int N = nx * ny * nz;
+  const int id = (int)(blockIdx.x * SLAB_THREADS + threadIdx.x);
+  double F0 = 0.0, F1 = 0.0, F2 = 0.0;
+  if (id < N) {
+    const int i = id % nx, j = (id / nx) % ny, l = id / (nx * ny);
+    const int W = nx + 2, Hh = ny + 2, Zl = nz + 2;
+    auto at = [&](int a, int t, int y, int x) { return G[(((size_t)a * Zl + t) * Hh + y) * W + x]; };
+    const double mx = m[id], my = m[N + id], mz = m[2 * N + id];
+    double Fa[3];
+    for (int a = 0; a < 3; ++a) {
+      const T cv = at(a, l + 1, j + 1, i + 1);
+      if (add) hd[(size_t)a * N + id] += cv;
+      const double gx = ((double)at(a, l + 1, j + 1, i + 2) - (double)at(a, l + 1, j + 1, i)) * i2dx;
+      const double gy = ((double)at(a, l + 1, j + 2, i + 1) - (double)at(a, l + 1, j, i + 1)) * i2dy;
+      const double gz = ((double)at(a, l + 2, j + 1, i + 1) - (double)at(a, l, j + 1, i + 1)) * i2dz;
+      Fa[a] = mx * gx + my * gy + mz * gz;
+    }
+    F0 = Fa[0];
+    F1 = Fa[1];
+    F2 = Fa[2];
+  }
+  F0 = wave_sum(F0);
+  F1 = wave_sum(F1);
+  F2 = wave_sum(F2);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[0][wv] = F0;
+    red[1][wv] = F1;
+    red[2][wv] = F2;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double s = 0.0;
+    for (int k = 0; k < SLAB_THREADS / 64; ++k) s += red[threadIdx.x][k];
+    part[3 * (size_t)blockIdx.x + threadIdx.x] = s;
+  }
+}
+
+// Per element id of [film][3][ncell]: B = mu0 (hd + hext_c + Ms m) in
+// float64, bdot = (B - Bprev) / dt (zero on the first update), Bprev = B.
+template <typename T>
+__global__ void __launch_bounds__(SLAB_THREADS)
+    k_slab_bdot(int n, int ncell, const T* __restrict__ hd, const T* __restrict__ m, double hx, double hy, double hz,
+                double mu0, double Ms, double idt, int first, double* __restrict__ Bprev, T* __restrict__ bdot) {
+  const int id = (int)(blockIdx.x * SLAB_THREADS + threadIdx.x);
+  if (id >= n) return;
+  const int c = (id / ncell) % 3;
+  const double he = c == 0 ? hx : (c == 1 ? hy : hz);
+  const double B = mu0 * ((double)hd[id] + he + Ms * (double)m[id]);
+  bdot[id] = first ? T(0) : (T)((B - Bprev[id]) * idt);
+  Bprev[id] = B;
+}
+
+// ------------------------------------------------------------ launchers
+template <typename T>
+hipError_t launch_slab_pack(const void* spec, T* out, int n, int imag, hipStream_t st) {
+  hipLaunchKernelGGL(k_slab_pack<T>, dim3((n + SLAB_THREADS - 1) / SLAB_THREADS), dim3(SLAB_THREADS), 0, st,
+                     (const cpx<double>*)spec, out, n, imag);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_slab_mul(const void* in, void* out, const T* kern, const SlabMulTable& tab, int nz, int D, int Lx,
+                           int Ly, int Kx, int mode, double sgn, const RigidState* rigid, hipStream_t st) {
+  const int plane = Ly * Kx;
+  dim3 grid((plane + SLAB_THREADS - 1) / SLAB_THREADS, tab.n);
+  hipLaunchKernelGGL(k_slab_mul<T>, grid, dim3(SLAB_THREADS), 0, st, (const cpx<T>*)in, (cpx<T>*)out, kern, tab, nz,
+                     D, Lx, Ly, Kx, mode, (T)sgn, rigid);
+  return hipGetLastError();
+}
+
+size_t slab_sample_lds(int M, int esz) { return (size_t)6 * M * esz; }
+
+template <typename T>
+hipError_t launch_slab_sample(const T* win, int nrow, int M, int h, T* out, int i0, int nw, int sgn, int add,
+                              int interp, double inv_dx, const RigidState* rigid, hipStream_t st) {
+  const size_t lds = slab_sample_lds(M, sizeof(T));
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_slab_sample<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_slab_sample<T>, dim3(nrow), dim3(SLAB_THREADS), lds, st, win, nrow, M, h, out, i0, nw, sgn,
+                     add, interp, inv_dx, rigid);
+  return hipGetLastError();
+}
+
+int slab_force_blocks(int ncell) { return (ncell + SLAB_THREADS - 1) / SLAB_THREADS; }
+
+template <typename T>
+hipError_t launch_slab_force(const T* G, const T* m, T* hd, int nx, int ny, int nz, int add, double dx, double dy,
+                             double dz, double* part, hipStream_t st) {
+  const int nb = slab_force_blocks(nx * ny * nz);
+  hipLaunchKernelGGL(k_slab_force<T>, dim3(nb), dim3(SLAB_THREADS), 0, st, G, m, hd, nx, ny, nz, add,
+                     0.5 / dx, 0.5 / dy, 0.5 / dz, part);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_slab_bdot(int n, int ncell, const T* hd, const T* m, const double hext[3], double mu0, double Ms,
+                            double idt, int first, double* Bprev, T* bdot, hipStream_t st) {
+  hipLaunchKernelGGL(k_slab_bdot<T>, dim3((n + SLAB_THREADS - 1) / SLAB_THREADS), dim3(SLAB_THREADS), 0, st, n,
+                     ncell, hd, m, hext[0], hext[1], hext[2], mu0, Ms, idt, first, Bprev, bdot);
+  return hipGetLastError();
+}
+
+#define MMV_SLAB_INST(T)                                                                                        \
+  template hipError_t launch_slab_pack<T>(const void*, T*, int, int, hipStream_t);                              \
+  template hipError_t launch_slab_mul<T>(const void*, void*, const T*, const SlabMulTable&, int, int, int, int,  \
+                                         int, int, double, const RigidState*, hipStream_t);                    \
+  template hipError_t launch_slab_sample<T>(const T*, int, int, int, T*, int, int, int, int, int, double,      \
+                                            const RigidState*, hipStream_t);                                    \
+  template hipError_t launch_slab_force<T>(const T*, const T*, T*, int, int, int, int, double, double, double,   \
+                                           double*, hipStream_t);                                               \
+  template hipError_t launch_slab_bdot<T>(int, int, const T*, const T*, const double*, double, double, double,  \
+                                          int, double*, T*, hipStream_t);
+
+MMV_SLAB_INST(float)
+MMV_SLAB_INST(double)
+
+}  // namespace mmv

@@ -41,7 +41,7 @@ def test_struct_layout_matches_header():
 @pytest.mark.parametrize("field,value,msg", [
     ("n_films", 3, "n_films"), ("nx", 0, "nx"), ("dx", 0.0, "cell edges"),
     ("dz", float("nan"), "cell edges"), ("Ms", -1.0, "Ms"), ("precision", 16, "precision"),
-    ("halo", 1, "halo"), ("gap_cells", -1, "gap_cells"), ("nz", 2, "one cell thick"),
+    ("halo", 1, "halo"), ("gap_cells", -1, "gap_cells"),
     ("sigma", 1e6, "eddy"), ("rc_cells", 0.0, "rc_cells"), ("max_travel_cells", -1, "max_travel"),
     ("fft_lx", 71, "fft_lx"), ("fft_ly", 11, "fft_ly"),
 ])
@@ -155,6 +155,17 @@ def test_cube_size_limits_are_checked_before_any_device_call(prec, shape):
     with pytest.raises(mmv.MMVError) as e:
         mmv.init_mesh(mmv.to_desc(d))
     assert e.value.code == -1 and "three-dimensional" in str(e.value)
+
+
+def test_thick_films_run_in_the_direct_modes():
+    d = get_config("tiny_potential")["desc"].replace(nz=2)
+    with pytest.raises(mmv.MMVError) as e:
+        mmv.init_mesh(mmv.to_desc(d))
+    assert e.value.code == -1 and "direct modes" in str(e.value)
+    d = get_config("tiny")["desc"].replace(nz=2, pbc=1)
+    with pytest.raises(mmv.MMVError) as e:
+        mmv.init_mesh(mmv.to_desc(d))
+    assert "one cell thick" in str(e.value)
 
 
 def test_potential_mode_needs_two_films():

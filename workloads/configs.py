@@ -79,12 +79,28 @@ def _cfg_learned():
                 state="domains")
 
 
+def _cfg_eddy_films():
+    """Two CoCrPt films 512 nm x 512 nm x 20 nm in 4 nm cells, 20 nm apart,
+    conductivity 1e6 S/m, stripes ~80 nm wide, spring drive at 2 m/s with
+    k = 0.005 N/m (the paper's eddy-current friction test, Sec. IV.C, on the
+    material and drive of Sec. IV.B); open in-plane boundaries."""
+    d = Desc(n_films=2, nx=128, ny=128, nz=5, dx=4e-9, dy=4e-9, dz=4e-9,
+             gap_cells=5, max_travel_cells=8, Ms=3.5e5, Aex=5e-12,
+             alpha=0.05, Ku=1.225e5, u=(0.0, 0.0, 1.0), sigma=1e6,
+             precision=32)
+    mass, gv = slider_mass_damping(128, 128, 0.005)
+    drv = Drive(mode=DRIVE_SPRING, v_d=2.0, k=0.005, mass=mass, gamma_v=gv)
+    return dict(desc=d, drive=drv, dt=1e-13, steps=1000, seed=(7, 8),
+                state="stripes")
+
+
 CONFIGS = {
     "tiny": _cfg_tiny,                                     # 2x 32x32x1, FP64
     "tiny_potential": lambda: _cfg_tiny(gap=3, cross_mode=1),
     "stickslip": _cfg_stickslip,                           # 2x 512x128x1, FP32
     "cube_eddy": _cfg_cube,                                # 64^3 + eddy
     "learned": _cfg_learned,                               # 2x 256x256x1
+    "eddy_films": _cfg_eddy_films,                         # 2x 128x128x5 + eddy
 }
 
 

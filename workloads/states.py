@@ -34,6 +34,25 @@ def domain_state(shape, seed, sigma_cells=8.0, tilt=0.1):
     return m
 
 
+def stripe_state(shape, seed, width_cells=20, tilt=0.1):
+    """Perpendicular stripe domains along y, alternating +z / -z every
+    width_cells columns (the same in every layer), the stripe pattern shifted
+    by a seeded offset, each cell tilted by tilt*|N(0,1)| rad towards a
+    uniformly random azimuth."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    off = int(rng.integers(0, 2 * width_cells))
+    sgn1 = np.where(((np.arange(nx) + off) // width_cells) % 2 == 0, 1.0, -1.0)
+    sgn = np.broadcast_to(sgn1[None, None, :], shape)
+    theta = tilt * np.abs(rng.standard_normal(shape))
+    phi = rng.uniform(0.0, 2.0 * np.pi, size=shape)
+    m = np.empty((3,) + tuple(shape))
+    m[0] = np.sin(theta) * np.cos(phi)
+    m[1] = np.sin(theta) * np.sin(phi)
+    m[2] = sgn * np.cos(theta)
+    return m
+
+
 def cube_state(shape, seed, tilt_deg=1.0, noise=0.01):
     """+z tilted by tilt_deg towards (1,1,0)/sqrt2, plus small seeded noise."""
     rng = np.random.default_rng(seed)
@@ -57,4 +76,7 @@ def initial_state(cfg):
         return [domain_state(shape, seeds[f]) for f in range(d.n_films)]
     if kind == "cube":
         return [cube_state(shape, cfg["seed"])]
+    if kind == "stripes":
+        seeds = cfg["seed"]
+        return [stripe_state(shape, seeds[f]) for f in range(d.n_films)]
     raise ValueError(kind)
