@@ -762,7 +762,8 @@ int eddy_update(mmv_mesh* h, double dt) {
   rc = conv3<T>(h, h->bdot, h->es, (const T*)h->kern_s, 1, +1.0);
   if (rc) return rc;
   HIPCHK(launch_sor_rhs<T>(h->cl, (const T*)h->es, (T*)h->rr, h->red, mean, h->st));
-  HIPCHK(launch_sor<T>(h->cl, (T*)h->phi, (T*)h->phi2, (const T*)h->rr, h->sor_omega, h->sor_sweeps, h->red, mean, h->st));
+  HIPCHK(launch_sor<T>(h->cl, 1, (T*)h->phi, (T*)h->phi2, (const T*)h->rr, h->sor_omega, h->sor_sweeps, h->red, mean,
+                       h->st));
   HIPCHK(launch_current<T>(h->cl, (const T*)h->phi, (const T*)h->es, (T*)h->bdot, h->d.sigma, h->st));
   (void)part;
   return conv3<T>(h, h->bdot, h->he, (const T*)h->kern_s, 1, -1.0);
@@ -1027,15 +1028,14 @@ int slab_eddy(mmv_mesh* h, const T* m, double dt) {
   h->eddy_first = false;
   int rc = slab_s_sum<T>(h, (const T*)h->bdot, (T*)h->es, +1.0);
   if (rc) return rc;
-  for (int f = 0; f < 2; ++f) {
-    T* es = (T*)h->es + f * F;
-    T* rr = (T*)h->rr + f * ncell;
-    T* phi = (T*)h->phi + f * ncell;
-    T* phi2 = (T*)h->phi2 + f * ncell;
-    HIPCHK(launch_sor_rhs<T>(h->cl, es, rr, h->red, mean, h->st));
-    HIPCHK(launch_sor<T>(h->cl, phi, phi2, rr, h->sor_omega, h->sor_sweeps, h->red, mean, h->st));
-    HIPCHK(launch_current<T>(h->cl, phi, es, (T*)h->bdot + f * F, h->d.sigma, h->st));
-  }
+  for (int f = 0; f < 2; ++f)
+    HIPCHK(launch_sor_rhs<T>(h->cl, (T*)h->es + f * F, (T*)h->rr + f * ncell, h->red, mean, h->st));
+  // the two films' Neumann problems in the same sweep launches
+  HIPCHK(launch_sor<T>(h->cl, 2, (T*)h->phi, (T*)h->phi2, (const T*)h->rr, h->sor_omega, h->sor_sweeps, h->red, mean,
+                       h->st));
+  for (int f = 0; f < 2; ++f)
+    HIPCHK(launch_current<T>(h->cl, (T*)h->phi + f * ncell, (T*)h->es + f * F, (T*)h->bdot + f * F, h->d.sigma,
+                             h->st));
   return slab_s_sum<T>(h, (const T*)h->bdot, (T*)h->he, -1.0);
 }
 

@@ -547,11 +547,13 @@ __device__ __forceinline__ void sor_halves(T* sp, const T* sr, int ox, int oy, i
 // the 8^3 tile of cells from (8 bx, 8 by, 8 bz) with a halo of 2 SOR_S
 // cells (the parts inside the mesh) from pin into LDS, runs the 2 NSW
 // half-sweeps there and writes the tile's cells (those inside the mesh) to
-// pout, as global half-sweeps would leave them.
+// pout, as global half-sweeps would leave them.  Several independent meshes
+// of the same size (consecutive, bstride cells apart) share a launch: grid z
+// runs over tz tiles of each mesh in turn.
 template <typename T, int NSW>
 __global__ void __launch_bounds__(SOR_THREADS)
     k_sor_tile(int nx, int ny, int nz, double dx, double dy, double dz, const T* __restrict__ pin,
-               T* __restrict__ pout, const T* __restrict__ r, double omega) {
+               T* __restrict__ pout, const T* __restrict__ r, double omega, int tz, size_t bstride) {
   static_assert(NSW >= 1 && NSW <= SOR_S, "the halo covers the half-sweeps");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int D = SOR_D, D2 = D * D, D3 = D * D * D;
@@ -561,7 +563,11 @@ __global__ void __launch_bounds__(SOR_THREADS)
   // y, z) go to one XCD
   const int gx = gridDim.x, gy = gridDim.y;
   const int lb = xcd_remap((blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x, gx * gy * gridDim.z);
-  const int bz = lb / (gx * gy), byx = lb - bz * gx * gy, by = byx / gx, bx = byx - by * gx;
+  const int bzb = lb / (gx * gy), byx = lb - bzb * gx * gy, by = byx / gx, bx = byx - by * gx;
+  const int box = bzb / tz, bz = bzb - box * tz;
+  pin += box * bstride;
+  pout += box * bstride;
+  r += box * bstride;
   const int ox = bx * SOR_T - SOR_H, oy = by * SOR_T - SOR_H, oz = bz * SOR_T - SOR_H;
   const size_t sy = nx, sz = (size_t)nx * ny;
   // all of a thread's loads in flight before the first LDS store
@@ -788,30 +794,37 @@ hipError_t launch_sor_residual(const CubeLaunch& c, const T* phi, const T* r, do
 }
 
 template <typename T>
-hipError_t launch_sor(const CubeLaunch& c, T* phi, T* phi2, const T* r, double omega, int sweeps, double* part,
-                      double* mean, hipStream_t st) {
+hipError_t launch_sor(const CubeLaunch& c, int nbox, T* phi, T* phi2, const T* r, double omega, int sweeps,
+                      double* part, double* mean, hipStream_t st) {
   const size_t N = (size_t)c.nx * c.ny * c.nz;
-  // SOR_S sweeps per launch on tiles, alternating between phi and phi2
+  // SOR_S sweeps per launch on tiles, alternating between phi and phi2; the
+  // nbox meshes (N cells apart) in one launch
+  const int tz = (c.nz + SOR_T - 1) / SOR_T;
   const dim3 grid((unsigned)((c.nx + SOR_T - 1) / SOR_T), (unsigned)((c.ny + SOR_T - 1) / SOR_T),
-                  (unsigned)((c.nz + SOR_T - 1) / SOR_T));
+                  (unsigned)(tz * nbox));
   const size_t lds = 2 * sizeof(T) * SOR_D * SOR_D * SOR_D;
   T* cur = phi;
   T* nxt = phi2;
   for (int s = 0; s < sweeps; s += SOR_S) {
     if (sweeps - s >= 2)
       hipLaunchKernelGGL((k_sor_tile<T, 2>), grid, dim3(SOR_THREADS), lds, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz,
-                         (const T*)cur, nxt, r, omega);
+                         (const T*)cur, nxt, r, omega, tz, N);
     else
       hipLaunchKernelGGL((k_sor_tile<T, 1>), grid, dim3(SOR_THREADS), lds, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz,
-                         (const T*)cur, nxt, r, omega);
+                         (const T*)cur, nxt, r, omega, tz, N);
     T* tmp = cur;
     cur = nxt;
     nxt = tmp;
   }
+  // each mesh's potential to zero mean (the reduction buffers serve the
+  // meshes in turn, in stream order)
   const int nb = (int)((N + 255) / 256);
-  hipLaunchKernelGGL(k_sum_part<T>, dim3(nb), dim3(256), 0, st, N, (const T*)cur, part);
-  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, nb, (const double*)part, mean, 1.0 / (double)N);
-  hipLaunchKernelGGL(k_shift<T>, grid1(N), dim3(256), 0, st, N, (const T*)cur, phi, (const double*)mean);
+  for (int b = 0; b < nbox; ++b) {
+    hipLaunchKernelGGL(k_sum_part<T>, dim3(nb), dim3(256), 0, st, N, (const T*)cur + b * N, part);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, nb, (const double*)part, mean, 1.0 / (double)N);
+    hipLaunchKernelGGL(k_shift<T>, grid1(N), dim3(256), 0, st, N, (const T*)cur + b * N, phi + b * N,
+                       (const double*)mean);
+  }
   return hipGetLastError();
 }
 
@@ -850,7 +863,7 @@ hipError_t launch_pack3(const void* spec, T* out, int Kx, int Ly, int Lz, int im
   template hipError_t launch_eddy_bdot<T>(size_t, const T*, const T*, T*, double, double, double, int,           \
                                           hipStream_t);                                                           \
   template hipError_t launch_sor_rhs<T>(const CubeLaunch&, const T*, T*, double*, double*, hipStream_t);         \
-  template hipError_t launch_sor<T>(const CubeLaunch&, T*, T*, const T*, double, int, double*, double*,          \
+  template hipError_t launch_sor<T>(const CubeLaunch&, int, T*, T*, const T*, double, int, double*, double*,     \
                                      hipStream_t);                                                             \
   template hipError_t launch_current<T>(const CubeLaunch&, const T*, const T*, T*, double, hipStream_t);         \
   template hipError_t launch_sor_residual<T>(const CubeLaunch&, const T*, const T*, double*, int, hipStream_t);  \

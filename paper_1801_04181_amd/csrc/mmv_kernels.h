@@ -86,8 +86,8 @@ hipError_t launch_sor_rhs(const CubeLaunch& c, const T* es, T* r, double* part, 
 template <typename T>
 hipError_t launch_sor_residual(const CubeLaunch& c, const T* phi, const T* r, double* part, int nblk, hipStream_t st);
 template <typename T>
-hipError_t launch_sor(const CubeLaunch& c, T* phi, T* phi2, const T* r, double omega, int sweeps, double* part, double* mean,
-                      hipStream_t st);
+hipError_t launch_sor(const CubeLaunch& c, int nbox, T* phi, T* phi2, const T* r, double omega, int sweeps,
+                      double* part, double* mean, hipStream_t st);
 template <typename T>
 hipError_t launch_current(const CubeLaunch& c, const T* phi, const T* es, T* J, double sigma, hipStream_t st);
 hipError_t launch_kernel_real3(double* out, int Lx, int Ly, int Lz, int kind, int comp, double dx, double dy,

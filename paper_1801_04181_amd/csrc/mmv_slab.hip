@@ -39,10 +39,102 @@ __global__ void __launch_bounds__(SLAB_THREADS)
   if (i < n) out[i] = (T)(imag ? spec[i].y : spec[i].x);
 }
 
+// exp(2 pi i (kx x0 / Lx + ky y0 / Ly)) with the integer products reduced
+// first (an exact argument for any offset), times sgn.
+template <typename T>
+__device__ __forceinline__ cpx<T> slab_phase(int kx, int ky, int x0, int y0, int Lx, int Ly, T sgn) {
+  long long px = ((long long)kx * x0) % Lx;
+  if (px < 0) px += Lx;
+  long long py = ((long long)ky * y0) % Ly;
+  if (py < 0) py += Ly;
+  const double frac = (double)px / (double)Lx + (double)py / (double)Ly;
+  T ps, pc;
+  if constexpr (sizeof(T) == 8)
+    sincospi(2.0 * frac, &ps, &pc);
+  else
+    sincospif((float)(2.0 * frac), &ps, &pc);
+  return mk<T>(pc * sgn, ps * sgn);
+}
+
+// out += K v for one layer pair: the six tensor components (xz, yz
+// imaginary) in mode 0, S x v (S = (i sx, i sy, sz)) in mode 1.
+template <typename T>
+__device__ __forceinline__ void slab_mac(int mode, const T* kv, const cpx<T>& v0, const cpx<T>& v1, const cpx<T>& v2,
+                                         cpx<T>& o0, cpx<T>& o1, cpx<T>& o2) {
+  if (mode == 0) {
+    const T nxx = kv[0], nyy = kv[1], nzz = kv[2], nxy = kv[3], ixz = kv[4], iyz = kv[5];
+    // i * a for a complex v: (-v.y, v.x)
+    o0 = o0 + scale(v0, nxx) + scale(v1, nxy) + mk<T>(-ixz * v2.y, ixz * v2.x);
+    o1 = o1 + scale(v0, nxy) + scale(v1, nyy) + mk<T>(-iyz * v2.y, iyz * v2.x);
+    o2 = o2 + mk<T>(-(ixz * v0.y + iyz * v1.y), ixz * v0.x + iyz * v1.x) + scale(v2, nzz);
+  } else {
+    // (S x v) = (i sy v2 - sz v1, sz v0 - i sx v2, i (sx v1 - sy v0))
+    const T sx = kv[0], sy = kv[1], sz = kv[2];
+    o0 = o0 + mk<T>(-sy * v2.y, sy * v2.x) - scale(v1, sz);
+    o1 = o1 + scale(v0, sz) - mk<T>(-sx * v2.y, sx * v2.x);
+    const cpx<T> d = scale(v1, sx) - scale(v0, sy);
+    o2 = o2 + mk<T>(-d.y, d.x);
+  }
+}
+
+// The product for a compile-time layer count NZ: one thread per spectral
+// point and target window holds the NZ source layers and the (at most
+// NZ + 2) target layers in registers and reads each layer offset's kernel
+// once (offsets tz0 - NZ + 1 .. tz0 + ntz - 1).  Grid: (points / SLAB_THREADS,
+// groups).
+template <typename T, int NZ>
+__global__ void __launch_bounds__(SLAB_THREADS)
+    k_slab_mul_nz(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, const T* __restrict__ kern,
+                  SlabMulTable tab, int D, int Lx, int Ly, int Kx, int mode, T sgn,
+                  const RigidState* __restrict__ rigid) {
+  constexpr int NT = NZ + 2;
+  const int plane = Ly * Kx;
+  const int q = (int)(blockIdx.x * SLAB_THREADS + threadIdx.x);
+  if (q >= plane) return;
+  const SlabGroup G = tab.g[blockIdx.y];
+  const int ky = q / Kx, kx = q - ky * Kx;
+  const size_t ks = (size_t)plane * (2 * D + 1);  // stride of one component
+  const cpx<T>* src = in + (size_t)G.src * 3 * NZ * plane + q;
+  cpx<T> v[3][NZ];
+#pragma unroll
+  for (int l = 0; l < NZ; ++l)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[a][l] = src[(size_t)(a * NZ + l) * plane];
+  cpx<T> o[3][NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o[a][k] = mk<T>(0, 0);
+  const int ncomp = mode == 0 ? 6 : 3;
+  // e = k - l + NZ - 1 runs over the layer offsets dz = tz0 - NZ + 1 + e
+#pragma unroll
+  for (int e = 0; e < NT + NZ - 1; ++e) {
+    if (e < G.ntz + NZ - 1) {
+      const T* K = kern + (size_t)(G.tz0 - NZ + 1 + e + D) * plane + q;
+      T kv[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) kv[c] = c < ncomp ? K[c * ks] : T(0);
+#pragma unroll
+      for (int l = 0; l < NZ; ++l) {
+        const int k = e - (NZ - 1) + l;
+        if (k >= 0 && k < NT && k < G.ntz) slab_mac<T>(mode, kv, v[0][l], v[1][l], v[2][l], o[0][k], o[1][k], o[2][k]);
+      }
+    }
+  }
+  const cpx<T> ph = slab_phase<T>(kx, ky, G.xs * rigid->s_int + G.xoff, G.yoff, Lx, Ly, sgn);
+  cpx<T>* dst = out + G.out + q;
+#pragma unroll
+  for (int k = 0; k < NT; ++k)
+    if (k < G.ntz)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) dst[(size_t)(a * G.ntz + k) * plane] = cmul(o[a][k], ph);
+}
+
 // Kernel spectra: kern[(comp * ndz + dz + D) * Ly * Kx + ky * Kx + kx], one
 // real number per point: tensor components xx yy zz xy (real spectra) and
 // xz yz (imaginary, value = i * stored); S components x, y (imaginary) and z
-// (real).  Grid: (points / SLAB_THREADS, groups).
+// (real).  Grid: (points / SLAB_THREADS, groups, target layers): one
+// thread per spectral point and target layer.
 template <typename T>
 __global__ void __launch_bounds__(SLAB_THREADS)
     k_slab_mul(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, const T* __restrict__ kern, SlabMulTable tab,
@@ -51,45 +143,24 @@ __global__ void __launch_bounds__(SLAB_THREADS)
   const int q = (int)(blockIdx.x * SLAB_THREADS + threadIdx.x);
   if (q >= plane) return;
   const SlabGroup G = tab.g[blockIdx.y];
+  const int k = blockIdx.z;
+  if (k >= G.ntz) return;
   const int ky = q / Kx, kx = q - ky * Kx;
-  const int x0 = G.xs * rigid->s_int + G.xoff;
-  long long px = ((long long)kx * x0) % Lx;
-  if (px < 0) px += Lx;
-  long long py = ((long long)ky * G.yoff) % Ly;
-  if (py < 0) py += Ly;
-  const double frac = (double)px / (double)Lx + (double)py / (double)Ly;
-  T ps, pc;
-  if constexpr (sizeof(T) == 8)
-    sincospi(2.0 * frac, &ps, &pc);
-  else
-    sincospif((float)(2.0 * frac), &ps, &pc);
   const size_t ks = (size_t)plane * (2 * D + 1);  // stride of one component
   const cpx<T>* src = in + (size_t)G.src * 3 * nz * plane + q;
   cpx<T>* dst = out + G.out + q;
-  for (int k = 0; k < G.ntz; ++k) {
+  {
     const int t = G.tz0 + k;
     cpx<T> o0 = mk<T>(0, 0), o1 = mk<T>(0, 0), o2 = mk<T>(0, 0);
+    const int ncomp = mode == 0 ? 6 : 3;
     for (int l = 0; l < nz; ++l) {
       const T* K = kern + (size_t)(t - l + D) * plane + q;
-      const cpx<T> v0 = src[(size_t)(0 * nz + l) * plane];
-      const cpx<T> v1 = src[(size_t)(1 * nz + l) * plane];
-      const cpx<T> v2 = src[(size_t)(2 * nz + l) * plane];
-      if (mode == 0) {
-        const T nxx = K[0], nyy = K[ks], nzz = K[2 * ks], nxy = K[3 * ks], ixz = K[4 * ks], iyz = K[5 * ks];
-        // i * a for a complex v: (-v.y, v.x)
-        o0 = o0 + scale(v0, nxx) + scale(v1, nxy) + mk<T>(-ixz * v2.y, ixz * v2.x);
-        o1 = o1 + scale(v0, nxy) + scale(v1, nyy) + mk<T>(-iyz * v2.y, iyz * v2.x);
-        o2 = o2 + mk<T>(-(ixz * v0.y + iyz * v1.y), ixz * v0.x + iyz * v1.x) + scale(v2, nzz);
-      } else {
-        // S = (i sx, i sy, sz): (S x v) = (i sy v2 - sz v1, sz v0 - i sx v2, i (sx v1 - sy v0))
-        const T sx = K[0], sy = K[ks], sz = K[2 * ks];
-        o0 = o0 + mk<T>(-sy * v2.y, sy * v2.x) - scale(v1, sz);
-        o1 = o1 + scale(v0, sz) - mk<T>(-sx * v2.y, sx * v2.x);
-        const cpx<T> d = scale(v1, sx) - scale(v0, sy);
-        o2 = o2 + mk<T>(-d.y, d.x);
-      }
+      T kv[6];
+      for (int c = 0; c < 6; ++c) kv[c] = c < ncomp ? K[c * ks] : T(0);
+      slab_mac<T>(mode, kv, src[(size_t)(0 * nz + l) * plane], src[(size_t)(1 * nz + l) * plane],
+                  src[(size_t)(2 * nz + l) * plane], o0, o1, o2);
     }
-    const cpx<T> ph = mk<T>(pc * sgn, ps * sgn);
+    const cpx<T> ph = slab_phase<T>(kx, ky, G.xs * rigid->s_int + G.xoff, G.yoff, Lx, Ly, sgn);
     dst[(size_t)(0 * G.ntz + k) * plane] = cmul(o0, ph);
     dst[(size_t)(1 * G.ntz + k) * plane] = cmul(o1, ph);
     dst[(size_t)(2 * G.ntz + k) * plane] = cmul(o2, ph);
@@ -98,6 +169,7 @@ __global__ void __launch_bounds__(SLAB_THREADS)
 
 // Whole-sample mirror index of k into [0, M) (M >= 2).
 __device__ __forceinline__ int slab_reflect(int k, int M) {
+  if (k >= 0 && k < M) return k;
   const int P = 2 * M - 2;
   k %= P;
   if (k < 0) k += P;
@@ -110,35 +182,43 @@ __device__ __forceinline__ int slab_reflect(int k, int M) {
 // system (c_{k-1} + 4 c_k + c_{k+1}) / 6 = f_k, i.e. the symmetric filter
 // sqrt(3) z^|j| (z = sqrt(3) - 2) on the mirror-periodic extension of the
 // row, truncated at |j| <= KF where |z|^KF is below the precision.
-// interp 1: linear interpolation of the samples.  One block per row.
+// interp 1: linear interpolation of the samples.  One block per row; the
+// row is staged in LDS with its mirror images KF samples past each end, so
+// the filter taps index it directly.
+constexpr int SLAB_KF_MAX = 30;
 template <typename T>
 __global__ void __launch_bounds__(SLAB_THREADS)
     k_slab_sample(const T* __restrict__ win, int nrow, int M, int h, T* __restrict__ out, int i0, int nw, int sgn,
                   int add, int interp, double inv_dx, const RigidState* __restrict__ rigid) {
   constexpr int KF = sizeof(T) == 8 ? 30 : 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* f = reinterpret_cast<T*>(smem_raw);  // [3][M]
-  T* c = f + 3 * M;                        // [3][M]
+  static_assert(KF <= SLAB_KF_MAX, "LDS sized for SLAB_KF_MAX");
+  const int ME = M + 2 * KF;
+  T* fe = reinterpret_cast<T*>(smem_raw);  // [3][M + 2 KF]: f_{k - KF}, mirror-extended
+  T* c = fe + 3 * ME;                       // [3][M]
   __shared__ T w[KF + 1];
   const int r = blockIdx.x;
   if (r >= nrow) return;
   if (threadIdx.x <= KF) w[threadIdx.x] = (T)(1.7320508075688772935 * pow(1.7320508075688772935 - 2.0, (double)threadIdx.x));
-  for (int t = threadIdx.x; t < 3 * M; t += SLAB_THREADS) {
-    const int a = t / M, k = t - a * M;
-    f[t] = win[((size_t)a * nrow + r) * M + k];
+  for (int t = threadIdx.x; t < 3 * ME; t += SLAB_THREADS) {
+    const int a = t / ME, k = t - a * ME - KF;
+    fe[t] = win[((size_t)a * nrow + r) * M + slab_reflect(k, M)];
   }
   __syncthreads();
-  const T* src = f;
+  const T* src = fe + KF;
+  int stride = ME;
   if (interp == 0) {
     for (int t = threadIdx.x; t < 3 * M; t += SLAB_THREADS) {
       const int a = t / M, k = t - a * M;
-      const T* fa = f + a * M;
-      T s = w[0] * fa[k];
-      for (int j = 1; j <= KF; ++j) s += w[j] * (fa[slab_reflect(k + j, M)] + fa[slab_reflect(k - j, M)]);
+      const T* fa = fe + a * ME + KF + k;
+      T s = w[0] * fa[0];
+#pragma unroll
+      for (int j = 1; j <= KF; ++j) s += w[j] * (fa[j] + fa[-j]);
       c[t] = s;
     }
     __syncthreads();
     src = c;
+    stride = M;
   }
   const double xp = sgn * (rigid->xs * inv_dx - (double)rigid->s_int);
   const double fl = floor(xp);
@@ -160,7 +240,7 @@ __global__ void __launch_bounds__(SLAB_THREADS)
   for (int t = threadIdx.x; t < 3 * nw; t += SLAB_THREADS) {
     const int a = t / nw, o = t - a * nw;
     const int k = k0 + i0 + o;
-    const T* sa = src + a * M;
+    const T* sa = src + a * stride;
     const T v = wb[0] * sa[slab_reflect(k - 1, M)] + wb[1] * sa[slab_reflect(k, M)] +
                 wb[2] * sa[slab_reflect(k + 1, M)] + wb[3] * sa[slab_reflect(k + 2, M)];
     T* d = out + ((size_t)a * nrow + r) * nw + o;
@@ -243,13 +323,35 @@ template <typename T>
 hipError_t launch_slab_mul(const void* in, void* out, const T* kern, const SlabMulTable& tab, int nz, int D, int Lx,
                            int Ly, int Kx, int mode, double sgn, const RigidState* rigid, hipStream_t st) {
   const int plane = Ly * Kx;
-  dim3 grid((plane + SLAB_THREADS - 1) / SLAB_THREADS, tab.n);
+  int ntz = 1;
+  for (int g = 0; g < tab.n; ++g) {
+    ntz = tab.g[g].ntz > ntz ? tab.g[g].ntz : ntz;
+    if (tab.g[g].ntz > nz + 2) return hipErrorInvalidValue;  // the register form holds nz + 2 target layers
+  }
+  const dim3 grid2((plane + SLAB_THREADS - 1) / SLAB_THREADS, tab.n);
+#define MMV_SLAB_MUL_NZ(N)                                                                                      \
+  case N:                                                                                                       \
+    hipLaunchKernelGGL((k_slab_mul_nz<T, N>), grid2, dim3(SLAB_THREADS), 0, st, (const cpx<T>*)in, (cpx<T>*)out, \
+                       kern, tab, D, Lx, Ly, Kx, mode, (T)sgn, rigid);                                          \
+    return hipGetLastError();
+  switch (nz) {
+    MMV_SLAB_MUL_NZ(2)
+    MMV_SLAB_MUL_NZ(3)
+    MMV_SLAB_MUL_NZ(4)
+    MMV_SLAB_MUL_NZ(5)
+    MMV_SLAB_MUL_NZ(6)
+    MMV_SLAB_MUL_NZ(7)
+    MMV_SLAB_MUL_NZ(8)
+    default: break;
+  }
+#undef MMV_SLAB_MUL_NZ
+  dim3 grid((plane + SLAB_THREADS - 1) / SLAB_THREADS, tab.n, ntz);
   hipLaunchKernelGGL(k_slab_mul<T>, grid, dim3(SLAB_THREADS), 0, st, (const cpx<T>*)in, (cpx<T>*)out, kern, tab, nz,
                      D, Lx, Ly, Kx, mode, (T)sgn, rigid);
   return hipGetLastError();
 }
 
-size_t slab_sample_lds(int M, int esz) { return (size_t)6 * M * esz; }
+size_t slab_sample_lds(int M, int esz) { return ((size_t)6 * M + 6 * SLAB_KF_MAX) * esz; }
 
 template <typename T>
 hipError_t launch_slab_sample(const T* win, int nrow, int M, int h, T* out, int i0, int nw, int sgn, int add,

@@ -3,12 +3,15 @@ currents in both; Sec. II.A, III.A-B, Eqs. 3, 6, 9-12; Sec. IV.C-D) against
 the float64 oracle (oracle.slab).
 
 Bars: the field terms and the force take the film path's bars (gpu_common:
-float32 1e-5, float64 1e-10, cross term and force 1e-9 in float64).  The
-eddy field is driven by dB/dt, the backward difference of B over one step,
-a change of about 1e-4 of |B| per step here: float32 rounding of the fields
-B is formed from (1e-7 of |B|) becomes ~1e-3 of dB/dt, so the float32 eddy
-bar is 1e-2 (relative L2, per film); float64 keeps 1e-8 (1e-16 / 1e-4 times
-the SOR and transform rounding, with margin).
+float32 1e-5, float64 1e-10, cross term and force 1e-9 in float64; measured
+1e-7 to 4e-7 and 3e-12 to 3.5e-10).  The eddy field is driven by dB/dt,
+the backward difference of B over one step, formed in float64 from the
+fields of the mesh precision.  In the stepping test below (stripe walls six
+cells apart, alpha 0.05, a slider at 1500 m/s) B changes by about 1e-2 of
+|B| per step, so the float32 rounding of the fields (1e-7 of |B|) leaves
+~1e-5 on dB/dt: bar 1e-4 (measured 7.5e-6); float64 1e-10 (measured
+1.6e-12).  Slower dynamics shrink dB/dt and raise the float32 error in
+proportion (the loss of weak eddy fields to precision, Sec. IV.D).
 """
 import math
 import numpy as np
@@ -20,7 +23,7 @@ from gpu_common import TERMS, TOL, TOL_CROSS, rel, max_rel
 
 pytestmark = pytest.mark.gpu
 
-TOL_EDDY = {32: 1e-2, 64: 1e-8}
+TOL_EDDY = {32: 1e-4, 64: 1e-10}
 TOL_M = {32: 2e-6, 64: 1e-12}
 
 
@@ -123,7 +126,7 @@ def test_thick_films_step_with_eddy_currents_and_a_spring(prec):
     num = sum((residual(d, s.eddy.phi[f], s.eddy.r[f]) * rn[f]) ** 2 for f in range(2))
     ref_res = math.sqrt(num / sum(r * r for r in rn))
     out["residual"] = (got, ref_res)
-    assert abs(got - ref_res) <= (0.05 if prec == 32 else 1e-6) * ref_res, out
+    assert abs(got - ref_res) <= (1e-3 if prec == 32 else 1e-9) * ref_res, out
     mesh.close()
     print("  ", out, flush=True)
 
