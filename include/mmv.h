@@ -147,7 +147,7 @@ typedef struct {
  * both films of S x dB/dt (the other film's part on its window, sampled),
  * one Neumann problem per film (SOR as for one magnet), J = sigma (E_sol +
  * E_irrot) and H_eddy = -sum over both films of S x J the same way.
- * Uniform H_ext only (set_hext_field: MMV_ESTATE).  Limits: the sampling
+ * A non-uniform H_ext per layer with set_hext_field.  Limits: the sampling
  * rows (6 (nx + 2 halo) reals) and a transform row or column in LDS, and
  * fewer than 2^31 elements in the product spectra.                      */
 int init_mesh(const mmv_mesh_desc* d, void* hip_stream, mmv_handle* out);
@@ -176,6 +176,9 @@ int set_drive(mmv_handle h, const mmv_drive* drv);
  *   film 1: field[3][ny][nx + 2 W], W = max_travel_cells + halo, on the
  *           slider's layer.  Column c is lattice x index c - W; with
  *           periodic x (pbc bit 0) it is [3][ny][nx], the period.
+ * Films thicker than one cell take one such plane per layer:
+ * [3][nz][ny][nx] for film 0 and [3][nz][ny][nx + 2 W] for the slider's
+ * layers; the field also enters B of the eddy-current update.
  * The slider's cells take the field at their moved positions, interpolated
  * along x like the cross field: same window and mirror ends, the cubic
  * B-spline (cross_mode 0, 1) or linear interpolation (cross_mode 2).  The
@@ -183,7 +186,7 @@ int set_drive(mmv_handle h, const mmv_drive* drv);
  * The array (host or device memory) is copied, stream-ordered, on the mesh's
  * stream into a buffer the library owns; NULL removes the field.
  * MMV_EINVAL if film is out of range; MMV_ESTATE on the single-magnet 3-D
- * path and on two films thicker than one cell.  On a batch instance, the batch's descriptors are rebuilt before
+ * path.  On a batch instance, the batch's descriptors are rebuilt before
  * its next batch_step.                                                  */
 int set_hext_field(mmv_handle h, int film, const void* field);
 

@@ -41,6 +41,12 @@ Eddy currents in both films (readings, listed in the design notes):
   held through its RK stages (as in oracle.eddy); Eq. 3's force is the
   base's stray field only.
 
+Non-uniform applied field (Sec. II.A; the reading of oracle.applied, layer
+by layer): film 0 takes its values on its cells, (3, nz, ny, nx); the
+slider's layers take the frame field (3, nz, ny, nx + 2 (max_travel_cells +
+halo)) sampled at their moved cells with the cross field's interpolant.  It
+enters the Zeeman term, and so B of the eddy update; not the force.
+
 Pins (tests/test_oracle_slab.py): at integer offsets the thick-film cross
 fields, the force and the cross eddy sums equal brute-force sums over
 physical cell centres; nz = 1 reproduces oracle.sim's fields at a
@@ -54,6 +60,7 @@ from .convolution import displacement_grid, WindowSum
 from .potential_kernel import potential_kernel
 from .spline import prefilter, interp_1d, linear_1d
 from .sim import System
+from .applied import slider_width
 from . import eddy as _eddy
 
 
@@ -79,6 +86,8 @@ class SlabSystem(System):
         super().__init__(desc.replace(sigma=0.0), drive, m_init)
         self.desc = desc
         self.eddy = FilmEddy(desc) if desc.sigma > 0 else None
+        # non-uniform applied field of each film (module docstring); None = none
+        self.hext_thick = [None, None]
 
     # ------------------------------------------------------------ windows
     def cross_box(self, direction, s_int):
@@ -132,8 +141,24 @@ class SlabSystem(System):
         Hb = samp(Gb, self.positions(x, s_int, "s2b"))
         return Hb, st["c"], F
 
+    def slider_hext(self, x, s_int):
+        """The slider's non-uniform applied field at its cells, (3, nz, ny, nx)."""
+        d = self.desc
+        hs = np.asarray(self.hext_thick[1], dtype=np.float64)
+        assert hs.shape == (3, d.nz, d.ny, slider_width(d)), hs.shape
+        cols = s_int - d.halo + np.arange(d.nx + 2 * d.halo) + d.max_travel_cells + d.halo
+        assert cols.min() >= 0 and cols.max() < hs.shape[-1], "slider beyond the applied field's columns"
+        pre, samp = self.interpolant()
+        return samp(pre(hs[..., cols]), self.positions(x, s_int, "b2s"))
+
     def field_terms(self, m_list=None, x=None, s_int=None, want_force=True):
         out, F = super().field_terms(m_list, x, s_int, want_force)
+        x = self.x if x is None else x
+        s_int = self.s_int if s_int is None else s_int
+        if self.hext_thick[0] is not None:
+            out[0]["zeeman"] = out[0]["zeeman"] + np.asarray(self.hext_thick[0], dtype=np.float64)
+        if self.hext_thick[1] is not None:
+            out[1]["zeeman"] = out[1]["zeeman"] + self.slider_hext(x, s_int)
         if self.eddy is not None:
             for f in range(2):
                 out[f]["eddy"] = self.eddy.H[f].copy()

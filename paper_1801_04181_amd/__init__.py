@@ -204,7 +204,8 @@ def set_drive(h, drv):
 def set_hext_field(h, film, field):
     """Non-uniform applied field of one film (a tensor in the mesh precision,
     [3][ny][nx] for film 0, [3][ny][nx + 2 (max_travel_cells + halo)] for the
-    slider's layer, [3][ny][nx] with periodic x), or None to remove it."""
+    slider's layer, [3][ny][nx] with periodic x; films thicker than one cell
+    one such plane per layer, [3][nz][ny][...]), or None to remove it."""
     _check(load().set_hext_field(h, int(film), None if field is None else _ptr(field)))
 
 
@@ -435,7 +436,12 @@ class Mesh:
         if field is None:
             set_hext_field(self.h, film, None)
             return
+        d = self.desc
+        w = d.nx if (film == 0 or getattr(d, "pbc", 0) & 1) else d.nx + 2 * (d.max_travel_cells + d.halo)
+        want = (3, d.ny, w) if d.nz == 1 else (3, d.nz, d.ny, w)
         t = self.torch.as_tensor(field, dtype=self.dtype).to(self.device).contiguous()
+        if tuple(t.shape) != want:
+            raise ValueError(f"applied field of film {film}: shape {tuple(t.shape)}, expected {want}")
         set_hext_field(self.h, film, t)
         self.stream.synchronize()
 

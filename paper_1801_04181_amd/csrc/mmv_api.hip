@@ -164,6 +164,7 @@ struct mmv_mesh {
   void* win_e = nullptr;       // eddy sums on both windows [2][3][nz][ny][M]
   void* stencil = nullptr;     // base field at the slider's stencil points [3][nz+2][ny+2][nx+2]
   double* Bprev = nullptr;     // B at the last eddy update [2][3][nz][ny][nx]
+  const void* slab_hext[2] = {nullptr, nullptr};  // applied field in use (hext_buf or NULL)
   SlabMulTable tab_t{}, tab_e{};
   // launch timing (diagnostics)
   int prof_kernel = 0;
@@ -952,9 +953,11 @@ int init_slab(mmv_mesh* h) {
 
 // Fields of both films at the state m ([2][3][nz][ny][nx]) and the current
 // slider stage: hd = the films' own fields (self) plus the other film's
-// sampled field (cross); the force partials of Eq. 3 (always).
+// sampled field (cross) plus the non-uniform applied field (zee: film 0's
+// values, the slider's samples of the frame field); the force partials of
+// Eq. 3 (always, from the stray field alone).
 template <typename T>
-int slab_fields(mmv_mesh* h, const T* m, bool self_on, bool cross_on) {
+int slab_fields(mmv_mesh* h, const T* m, bool self_on, bool cross_on, bool zee_on) {
   const int nz = h->nz, ny = h->ny, nx = h->nx, Kx = h->Kx, M = h->M;
   const size_t F = 3 * (size_t)nx * ny * nz;
   const size_t P = (size_t)h->Ly * Kx;
@@ -979,12 +982,19 @@ int slab_fields(mmv_mesh* h, const T* m, bool self_on, bool cross_on) {
                            Kx, h->px, h->twx, h->twp, h->st));
   if (!self_on) HIPCHK(hipMemsetAsync(h->hd, 0, 2 * F * sizeof(T), h->st));
   if (cross_on)
-    HIPCHK(launch_slab_sample<T>((const T*)h->win_s2b, nz * ny, M, h->d.halo, (T*)h->hd, 0, nx, -1, 1, interp, idx,
-                                 h->rigid, h->st));
-  HIPCHK(launch_slab_sample<T>((const T*)h->win_b2s, (nz + 2) * (ny + 2), M, h->d.halo, (T*)h->stencil, -1, nx + 2, 1,
-                               0, interp, idx, h->rigid, h->st));
+    HIPCHK(launch_slab_sample<T>((const T*)h->win_s2b, nz * ny, M, M, 0, 0, h->d.halo, (T*)h->hd, 0, nx, -1, 1, interp,
+                                 idx, h->rigid, h->st));
+  HIPCHK(launch_slab_sample<T>((const T*)h->win_b2s, (nz + 2) * (ny + 2), M, M, 0, 0, h->d.halo, (T*)h->stencil, -1,
+                               nx + 2, 1, 0, interp, idx, h->rigid, h->st));
   HIPCHK(launch_slab_force<T>((const T*)h->stencil, m + F, (T*)h->hd + F, nx, ny, nz, cross_on ? 1 : 0, h->d.dx,
                               h->d.dy, h->d.dz, h->partial, h->st));
+  if (zee_on && h->slab_hext[0]) HIPCHK(launch_slab_add<T>((int)F, (const T*)h->slab_hext[0], (T*)h->hd, h->st));
+  if (zee_on && h->slab_hext[1]) {
+    // the slider's window of the frame rows starts at column s_int + travel
+    const int W = nx + 2 * (h->d.max_travel_cells + h->d.halo);
+    HIPCHK(launch_slab_sample<T>((const T*)h->slab_hext[1], nz * ny, M, W, 1, h->d.max_travel_cells, h->d.halo,
+                                 (T*)h->hd + F, 0, nx, 1, 1, interp, idx, h->rigid, h->st));
+  }
   return MMV_OK;
 }
 
@@ -1010,9 +1020,9 @@ int slab_s_sum(mmv_mesh* h, const T* src, T* dst, double sgn) {
   HIPCHK(launch_row_inv<T>(pI + cs * 6 * (size_t)nz * ny * Kx, (T*)h->win_e, 6 * nz * ny, R, M, h->N2x, Kx, h->px,
                            h->twx, h->twp, h->st));
   const size_t wsz = 3 * (size_t)nz * ny * M;
-  HIPCHK(launch_slab_sample<T>((const T*)h->win_e, nz * ny, M, h->d.halo, dst, 0, nx, -1, 1, interp, 1.0 / h->d.dx,
-                               h->rigid, h->st));
-  HIPCHK(launch_slab_sample<T>((const T*)h->win_e + wsz, nz * ny, M, h->d.halo, dst + F, 0, nx, 1, 1, interp,
+  HIPCHK(launch_slab_sample<T>((const T*)h->win_e, nz * ny, M, M, 0, 0, h->d.halo, dst, 0, nx, -1, 1, interp,
+                               1.0 / h->d.dx, h->rigid, h->st));
+  HIPCHK(launch_slab_sample<T>((const T*)h->win_e + wsz, nz * ny, M, M, 0, 0, h->d.halo, dst + F, 0, nx, 1, 1, interp,
                                1.0 / h->d.dx, h->rigid, h->st));
   return MMV_OK;
 }
@@ -1064,7 +1074,7 @@ int step_slab(mmv_mesh* h, double dt, int nsteps) {
     for (int s = 0; s < 4; ++s) {
       T* in = s == 0 ? m0 : (s == 1 ? b1 : (s == 2 ? b2 : b1));
       T* out = s == 0 ? b1 : (s == 1 ? b2 : (s == 2 ? b1 : m0));
-      int rc = slab_fields<T>(h, in, true, true);
+      int rc = slab_fields<T>(h, in, true, true, true);
       if (rc) return rc;
       if (s == 0 && h->d.sigma > 0 && (rc = slab_eddy<T>(h, m0, dt))) return rc;
       // the slider's stage from this stage's force (after every sampling of
@@ -1082,9 +1092,11 @@ int step_slab(mmv_mesh* h, double dt, int nsteps) {
 template <typename T>
 int eval_slab(mmv_mesh* h, int film, int mask, void* hout) {
   const size_t F = 3 * (size_t)h->nx * h->ny * h->nz;
-  const bool dem = (mask & (MMV_TERM_DEMAG_SELF | MMV_TERM_DEMAG_CROSS)) != 0;
+  const bool zee = (mask & MMV_TERM_ZEEMAN) && (h->slab_hext[0] || h->slab_hext[1]);
+  const bool dem = (mask & (MMV_TERM_DEMAG_SELF | MMV_TERM_DEMAG_CROSS)) != 0 || zee;
   if (dem) {
-    int rc = slab_fields<T>(h, (const T*)h->m0, (mask & MMV_TERM_DEMAG_SELF) != 0, (mask & MMV_TERM_DEMAG_CROSS) != 0);
+    int rc = slab_fields<T>(h, (const T*)h->m0, (mask & MMV_TERM_DEMAG_SELF) != 0, (mask & MMV_TERM_DEMAG_CROSS) != 0,
+                            zee);
     if (rc) return rc;
   }
   const int m3 = (mask & (MMV_TERM_EXCHANGE | MMV_TERM_ANISOTROPY | MMV_TERM_ZEEMAN | MMV_TERM_EDDY)) |
@@ -1098,7 +1110,7 @@ int eval_slab(mmv_mesh* h, int film, int mask, void* hout) {
 // Eq. 3's force at the current state [N] (blocks on the stream).
 template <typename T>
 int force_slab(mmv_mesh* h, double F_out[3]) {
-  int rc = slab_fields<T>(h, (const T*)h->m0, true, true);
+  int rc = slab_fields<T>(h, (const T*)h->m0, true, true, false);
   if (rc) return rc;
   const int nb = slab_force_blocks(h->nx * h->ny * h->nz);
   std::vector<double> part(3 * (size_t)nb);
@@ -2644,8 +2656,21 @@ int spline3_gather(int precision, const void* coef, int nx, int ny, int nz, cons
 int set_hext_field(mmv_handle h, int film, const void* field) {
   int rc = check_handle(h);
   if (rc) return rc;
-  if (h->cube || h->slab) return fail(MMV_ESTATE, "the applied-field array belongs to the one-cell-thick film path");
+  if (h->cube) return fail(MMV_ESTATE, "the applied-field array belongs to the film paths");
   if (film < 0 || film >= h->nfilm) return fail(MMV_EINVAL, "film out of range");
+  if (h->slab) {
+    // thick films: [3][nz][ny][nx] for film 0, [3][nz][ny][nx + 2 (travel +
+    // halo)] for the slider's layers; read by slab_fields
+    const int w = film == 0 ? h->nx : h->nx + 2 * (h->d.max_travel_cells + h->d.halo);
+    const size_t bytes = (size_t)3 * h->nz * h->ny * w * h->esz;
+    h->slab_hext[film] = nullptr;
+    if (field) {
+      if (!h->hext_buf[film] && (rc = dalloc(h, &h->hext_buf[film], bytes))) return rc;
+      HIPCHK(hipMemcpyAsync(h->hext_buf[film], field, bytes, hipMemcpyDefault, h->st));
+      h->slab_hext[film] = h->hext_buf[film];
+    }
+    return MMV_OK;
+  }
   const bool px = (h->d.pbc & 1) != 0;
   const int w = (film == 0 || px) ? h->nx : h->nx + 2 * (h->rp_hot.travel + h->d.halo);
   const size_t bytes = (size_t)3 * h->ny * w * h->esz;

@@ -31,9 +31,13 @@ template <typename T>
 hipError_t launch_slab_mul(const void* in, void* out, const T* kern, const SlabMulTable& tab, int nz, int D, int Lx,
                            int Ly, int Kx, int mode, double sgn, const RigidState* rigid, hipStream_t st);
 size_t slab_sample_lds(int M, int esz);
+// window rows of length M starting at column cs * s_int + c_off of rows ld
+// apart (ld = M, cs = c_off = 0: rows of their own)
 template <typename T>
-hipError_t launch_slab_sample(const T* win, int nrow, int M, int h, T* out, int i0, int nw, int sgn, int add,
-                              int interp, double inv_dx, const RigidState* rigid, hipStream_t st);
+hipError_t launch_slab_sample(const T* win, int nrow, int M, int ld, int cs, int c_off, int h, T* out, int i0, int nw,
+                              int sgn, int add, int interp, double inv_dx, const RigidState* rigid, hipStream_t st);
+template <typename T>
+hipError_t launch_slab_add(int n, const T* src, T* dst, hipStream_t st);
 int slab_force_blocks(int ncell);
 template <typename T>
 hipError_t launch_slab_force(const T* G, const T* m, T* hd, int nx, int ny, int nz, int add, double dx, double dy,

@@ -176,8 +176,11 @@ __device__ __forceinline__ int slab_reflect(int k, int M) {
   return k > M - 1 ? P - k : k;
 }
 
-// Window rows win[3][nrow][M] -> out[3][nrow][nw] at u = i + h + sgn * x_p,
-// i = i0 .. i0 + nw - 1, x_p = x_s / dx - s_int of the current stage.
+// Window rows -> out[3][nrow][nw] at u = i + h + sgn * x_p, i = i0 .. i0 +
+// nw - 1, x_p = x_s / dx - s_int of the current stage.  Window row r of
+// component a: the M elements from column cs * s_int + c_off of row
+// win[(a * nrow + r) * ld ...] (ld = M, cs = c_off = 0 for a window of its
+// own; a frame row of the applied field otherwise).
 // interp 0: cubic B-spline; its coefficients solve the mirror-bounded
 // system (c_{k-1} + 4 c_k + c_{k+1}) / 6 = f_k, i.e. the symmetric filter
 // sqrt(3) z^|j| (z = sqrt(3) - 2) on the mirror-periodic extension of the
@@ -188,8 +191,8 @@ __device__ __forceinline__ int slab_reflect(int k, int M) {
 constexpr int SLAB_KF_MAX = 30;
 template <typename T>
 __global__ void __launch_bounds__(SLAB_THREADS)
-    k_slab_sample(const T* __restrict__ win, int nrow, int M, int h, T* __restrict__ out, int i0, int nw, int sgn,
-                  int add, int interp, double inv_dx, const RigidState* __restrict__ rigid) {
+    k_slab_sample(const T* __restrict__ win, int nrow, int M, int ld, int cs, int c_off, int h, T* __restrict__ out,
+                  int i0, int nw, int sgn, int add, int interp, double inv_dx, const RigidState* __restrict__ rigid) {
   constexpr int KF = sizeof(T) == 8 ? 30 : 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   static_assert(KF <= SLAB_KF_MAX, "LDS sized for SLAB_KF_MAX");
@@ -200,9 +203,10 @@ __global__ void __launch_bounds__(SLAB_THREADS)
   const int r = blockIdx.x;
   if (r >= nrow) return;
   if (threadIdx.x <= KF) w[threadIdx.x] = (T)(1.7320508075688772935 * pow(1.7320508075688772935 - 2.0, (double)threadIdx.x));
+  const int c0 = cs * rigid->s_int + c_off;
   for (int t = threadIdx.x; t < 3 * ME; t += SLAB_THREADS) {
     const int a = t / ME, k = t - a * ME - KF;
-    fe[t] = win[((size_t)a * nrow + r) * M + slab_reflect(k, M)];
+    fe[t] = win[((size_t)a * nrow + r) * ld + c0 + slab_reflect(k, M)];
   }
   __syncthreads();
   const T* src = fe + KF;
@@ -296,6 +300,13 @@ __global__ void __launch_bounds__(SLAB_THREADS)
   }
 }
 
+// dst[i] += src[i]
+template <typename T>
+__global__ void __launch_bounds__(SLAB_THREADS) k_slab_add(int n, const T* __restrict__ src, T* __restrict__ dst) {
+  const int i = (int)(blockIdx.x * SLAB_THREADS + threadIdx.x);
+  if (i < n) dst[i] += src[i];
+}
+
 // Per element id of [film][3][ncell]: B = mu0 (hd + hext_c + Ms m) in
 // float64, bdot = (B - Bprev) / dt (zero on the first update), Bprev = B.
 template <typename T>
@@ -354,16 +365,23 @@ hipError_t launch_slab_mul(const void* in, void* out, const T* kern, const SlabM
 size_t slab_sample_lds(int M, int esz) { return ((size_t)6 * M + 6 * SLAB_KF_MAX) * esz; }
 
 template <typename T>
-hipError_t launch_slab_sample(const T* win, int nrow, int M, int h, T* out, int i0, int nw, int sgn, int add,
-                              int interp, double inv_dx, const RigidState* rigid, hipStream_t st) {
+hipError_t launch_slab_sample(const T* win, int nrow, int M, int ld, int cs, int c_off, int h, T* out, int i0, int nw,
+                              int sgn, int add, int interp, double inv_dx, const RigidState* rigid, hipStream_t st) {
   const size_t lds = slab_sample_lds(M, sizeof(T));
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_slab_sample<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_slab_sample<T>, dim3(nrow), dim3(SLAB_THREADS), lds, st, win, nrow, M, h, out, i0, nw, sgn,
-                     add, interp, inv_dx, rigid);
+  hipLaunchKernelGGL(k_slab_sample<T>, dim3(nrow), dim3(SLAB_THREADS), lds, st, win, nrow, M, ld, cs, c_off, h, out,
+                     i0, nw, sgn, add, interp, inv_dx, rigid);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_slab_add(int n, const T* src, T* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_slab_add<T>, dim3((n + SLAB_THREADS - 1) / SLAB_THREADS), dim3(SLAB_THREADS), 0, st, n, src,
+                     dst);
   return hipGetLastError();
 }
 
@@ -390,8 +408,9 @@ hipError_t launch_slab_bdot(int n, int ncell, const T* hd, const T* m, const dou
   template hipError_t launch_slab_pack<T>(const void*, T*, int, int, hipStream_t);                              \
   template hipError_t launch_slab_mul<T>(const void*, void*, const T*, const SlabMulTable&, int, int, int, int,  \
                                          int, int, double, const RigidState*, hipStream_t);                    \
-  template hipError_t launch_slab_sample<T>(const T*, int, int, int, T*, int, int, int, int, int, double,      \
-                                            const RigidState*, hipStream_t);                                    \
+  template hipError_t launch_slab_sample<T>(const T*, int, int, int, int, int, int, T*, int, int, int, int, int, \
+                                            double, const RigidState*, hipStream_t);                            \
+  template hipError_t launch_slab_add<T>(int, const T*, T*, hipStream_t);                                       \
   template hipError_t launch_slab_force<T>(const T*, const T*, T*, int, int, int, int, double, double, double,   \
                                            double*, hipStream_t);                                               \
   template hipError_t launch_slab_bdot<T>(int, int, const T*, const T*, const double*, double, double, double,  \

@@ -144,3 +144,50 @@ def test_thick_films_refuse_the_film_path_only_calls():
     with pytest.raises(mmv.MMVError):
         mmv.eddy_residual(mesh.h)
     mesh.close()
+
+
+@pytest.mark.parametrize("prec,cross_mode", [(32, 0), (64, 0), (64, 2)])
+def test_thick_films_non_uniform_applied_field(prec, cross_mode):
+    """A non-uniform applied field per layer (set_hext_field): the Zeeman
+    term of both films at a fractional offset, then RK4 steps with eddy
+    currents (the field enters B) and a moving slider, against the oracle."""
+    import torch
+    from oracle.applied import slider_width
+    d, m = films(15, 9, 3, prec, gap=1, travel=4, sigma=1e6, cross_mode=cross_mode, state="stripes", seed=9,
+                 sor_sweeps=10)
+    rng = np.random.default_rng(21)
+    W = slider_width(d)
+    # smooth in x and y, different per layer: a few low harmonics
+    xs, ys = np.arange(W) / W, np.arange(d.ny) / d.ny
+    hs = np.zeros((3, d.nz, d.ny, W))
+    for a in range(3):
+        for l in range(d.nz):
+            c = rng.standard_normal(4)
+            hs[a, l] = 2e4 * (c[0] + c[1] * np.sin(2 * np.pi * (xs[None, :] + c[2]))
+                              * np.cos(2 * np.pi * (ys[:, None] + c[3])))
+    hb = hs[..., d.max_travel_cells + d.halo:d.max_travel_cells + d.halo + d.nx] * 0.7
+    drv = Drive(mode=1, v_d=900.0, x0=1.41 * d.dx)
+    print(f"slab applied p{prec} mode {cross_mode}", flush=True)
+    mesh, s = pair(d, m, drv)
+    mesh.set_hext_field(0, hb)
+    mesh.set_hext_field(1, hs)
+    s.hext_thick = [hb, hs]
+    terms, _ = s.field_terms()
+    out = {}
+    for f in range(2):
+        got = mesh.eval_heff(f, 4).cpu().numpy()
+        out[f"zeeman{f}"] = max(rel(got, terms[f]["zeeman"]), max_rel(got, terms[f]["zeeman"]))
+        assert out[f"zeeman{f}"] <= TOL[prec], out
+    dt, n = 1e-13, 3
+    mesh.step(dt, n)
+    torch.cuda.synchronize()
+    s.run(dt, n)
+    for f in range(2):
+        out[f"m{f}"] = float(np.abs(mesh.get_m(f).cpu().numpy() - s.m[f]).max())
+        assert out[f"m{f}"] < TOL_M[prec], out
+        out[f"eddy{f}"] = rel(mesh.eval_heff(f, 32).cpu().numpy(), s.eddy.H[f])
+        assert out[f"eddy{f}"] <= TOL_EDDY[prec], out
+    with pytest.raises(ValueError):
+        mesh.set_hext_field(1, hb)
+    mesh.close()
+    print("  ", out, flush=True)

@@ -204,3 +204,25 @@ def test_eddy_update_sums_both_films_with_the_right_signs():
                         H[:, k, j, i] -= s_cross_at(d, P, slab.eddy.J[g], *origin[g])
         assert rel(slab.eddy.E_sol[f], E) < 1e-10
         assert rel(slab.eddy.H[f], H) < 1e-10
+
+
+@pytest.mark.parametrize("cross_mode", [0, 2])
+def test_thick_applied_field_is_the_film_sampling_layer_by_layer(cross_mode):
+    """The slider's applied field in thick films equals oracle.applied's
+    (pinned) sampling of each layer; a uniform field is exact."""
+    from oracle.applied import slider_samples, slider_width
+    d, m = films(nx=9, ny=5, nz=3, cross_mode=cross_mode)
+    rng = np.random.default_rng(12)
+    hs = rng.standard_normal((3, d.nz, d.ny, slider_width(d)))
+    s = SlabSystem(d, Drive(mode=FROZEN), m)
+    s.hext_thick = [None, hs]
+    d1 = d.replace(nz=1)
+    for x_cells in (0.0, 1.37, -2.5, 4.0):
+        s_int = int(np.floor(x_cells))
+        got = s.slider_hext(x_cells * d.dx, s_int)
+        for layer in range(d.nz):
+            ref = slider_samples(d1, hs[:, layer], x_cells * d.dx, s_int)
+            assert np.allclose(got[:, layer], ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+    s.hext_thick = [None, np.broadcast_to(np.array([1.0, -2.0, 3.0])[:, None, None, None], hs.shape)]
+    got = s.slider_hext(1.37 * d.dx, 1)
+    assert np.allclose(got, np.array([1.0, -2.0, 3.0])[:, None, None, None], rtol=0, atol=1e-12)
