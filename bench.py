@@ -314,8 +314,10 @@ def surrogate_batched(n=16, steps=20):
 def cube_report(steps=40, warmup=4):
     """Step time of the 64^3 conducting cube (the single-magnet 3-D path),
     float32 and float64, with the eddy term (sigma = 1e7 S/m, once per step:
-    dB/dt, the E_sol convolution, 40 red-black SOR sweeps, J x S) and without
-    it (sigma = 0): HIP events around `steps` RK4 steps on the mesh's stream."""
+    dB/dt, the E_sol convolution, 40 red-black SOR sweeps, J x S), with it
+    and the exact cosine-basis Neumann solve instead of the sweeps, and
+    without it (sigma = 0): HIP events around `steps` RK4 steps on the mesh's
+    stream."""
     import torch
     import paper_1801_04181_amd as mmv
     from workloads import get_config, initial_state
@@ -326,8 +328,9 @@ def cube_report(steps=40, warmup=4):
     out = {"workload": "64^3 cube, 2 nm cells, RK4 dt 5e-14 s, Zeeman + exchange + demag (+ eddy)",
            "cells": cells, "steps": steps}
     for prec in (32, 64):
-        for eddy in (True, False):
-            d = cfg["desc"].replace(precision=prec, sigma=cfg["desc"].sigma if eddy else 0.0)
+        for eddy in (True, "exact", False):
+            d = cfg["desc"].replace(precision=prec, sigma=cfg["desc"].sigma if eddy else 0.0,
+                                    sor_sweeps=-1 if eddy == "exact" else cfg["desc"].sor_sweeps)
             mesh = mmv.Mesh(d, cfg["drive"], m)
             mesh.step(cfg["dt"], warmup)
             torch.cuda.synchronize()
@@ -339,8 +342,8 @@ def cube_report(steps=40, warmup=4):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps
             mesh.close()
-            out[f"fp{prec}_{'eddy' if eddy else 'no_eddy'}"] = {
-                "ms_per_step": ms, "cell_updates_per_s": cells / (ms * 1e-3)}
+            name = {True: "eddy", "exact": "eddy_exact_solve", False: "no_eddy"}[eddy]
+            out[f"fp{prec}_{name}"] = {"ms_per_step": ms, "cell_updates_per_s": cells / (ms * 1e-3)}
     return out
 
 
@@ -349,8 +352,9 @@ def eddy_films_report(steps=20, warmup=2, cpu=True):
     4 nm (the eddy-current friction workload), float32 and float64, with
     eddy currents in both films (sigma = 1e6 S/m: dB/dt, the E_sol sums with
     the other film's interpolated part, 40 red-black SOR sweeps per film,
-    J x S) and without (sigma = 0): HIP events around `steps` RK4 steps on
-    the mesh's stream.  The oracle (float64 CPU) times one step."""
+    J x S), with the exact cosine-basis Neumann solve instead of the sweeps,
+    and without (sigma = 0): HIP events around `steps` RK4 steps on the
+    mesh's stream.  The oracle (float64 CPU) times one step."""
     import torch
     import paper_1801_04181_amd as mmv
     from workloads import get_config, initial_state
@@ -363,8 +367,9 @@ def eddy_films_report(steps=20, warmup=2, cpu=True):
                        "spring drive 2 m/s, RK4 dt 1e-13 s",
            "cells": cells, "steps": steps}
     for prec in (32, 64):
-        for eddy in (True, False):
-            d = d0.replace(precision=prec, sigma=d0.sigma if eddy else 0.0)
+        for eddy in (True, "exact", False):
+            d = d0.replace(precision=prec, sigma=d0.sigma if eddy else 0.0,
+                           sor_sweeps=-1 if eddy == "exact" else d0.sor_sweeps)
             mesh = mmv.Mesh(d, drv, m)
             mesh.step(dt, warmup)
             torch.cuda.synchronize()
@@ -375,8 +380,9 @@ def eddy_films_report(steps=20, warmup=2, cpu=True):
             e1.record(mesh.stream)
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps
-            out[f"fp{prec}_{'eddy' if eddy else 'no_eddy'}"] = {
-                "ms_per_step": ms, "cell_updates_per_s": cells / (ms * 1e-3), "fft": list(mesh.fft_lengths()[:2])}
+            name = {True: "eddy", "exact": "eddy_exact_solve", False: "no_eddy"}[eddy]
+            out[f"fp{prec}_{name}"] = {"ms_per_step": ms, "cell_updates_per_s": cells / (ms * 1e-3),
+                                       "fft": list(mesh.fft_lengths()[:2])}
             mesh.close()
     if cpu:
         from threadpoolctl import threadpool_limits

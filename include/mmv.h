@@ -85,7 +85,12 @@ typedef struct {
                            (the comparison interpolant of Sec. IV.A)         */
   int halo;             /* spline window extension along x in cells (>= 2)    */
   double rc_cells;      /* Newell / point-dipole switch radius in cells (> 0) */
-  int sor_sweeps;       /* eddy SOR sweeps per step (0: library default)      */
+  int sor_sweeps;       /* eddy SOR sweeps per step (0: library default 40);
+                           -1: the Neumann problem solved exactly in the
+                           cosine basis that diagonalises it (DCT-II along
+                           x, y, z, division by the eigenvalues, inverse;
+                           nx, ny, nz {2,3,5,7}-smooth, MMV_EINVAL
+                           otherwise)                                     */
   double sor_omega;     /* eddy SOR factor (0: 2/(1+sin(pi/n_max)))           */
   int fft_lx, fft_ly, fft_lz; /* FFT lengths; 0 = smallest admissible       */
   int pbc;              /* periodic in-plane axes (Sec. III.A end, Sec. IV.B):

@@ -18,13 +18,20 @@ Per time step, from the magnetisation at the start of the step:
    zero mean (compatibility of the pure Neumann problem) and phi has zero
    mean (gauge).  Solved by red-black successive over-relaxation (colour
    (i + j + k) mod 2, red first), omega = 2 / (1 + sin(pi / n_max)), a fixed
-   number of sweeps per step from the previous step's phi.
+   number of sweeps per step from the previous step's phi.  A negative
+   sweep count asks for the exact solution instead: the finite-volume
+   Neumann Laplacian of a box is diagonal in the cosine basis
+   cos(pi k (i + 1/2) / n) per axis (eigenvalue sum over axes of
+   (2 cos(pi k / n) - 2) / d^2), so phi = DCT-III of (DCT-II of r / lambda)
+   with the k = 0 mode (the gauge) set to zero.
    E_irrot,a(i) = -(g+ + g-) / 2 with g the face gradients, a surface face
    taking E_sol,a(i).
 4. J = sigma (E_sol + E_irrot) and H_eddy(r_i) = sum_j J_j x S(r_i - r_j)
    (Biot-Savart with the same kernel), held through the step's RK stages.
 
 Pins (tests/test_oracle_eddy.py): the window sums equal brute-force sums;
+the exact solve equals a sparse least-squares solve of the independently
+assembled finite-volume system;
 Faraday's law for a divergence-free dB/dt; the converged SOR equals a direct
 sparse solve of the same system; a uniform E_sol is screened completely
 (phi = E0 . r, so J = 0 in every cell and no current leaves the surface;
@@ -52,7 +59,25 @@ def cross_kernels(desc, sign):
 
 
 def default_sweeps(desc):
-    return desc.sor_sweeps if desc.sor_sweeps > 0 else 40
+    """Sweeps per step (0: 40); negative: the exact solve."""
+    return desc.sor_sweeps if desc.sor_sweeps != 0 else 40
+
+
+def neumann_solve(desc, r):
+    """The zero-mean solution of L phi = r (L = laplacian below) for a
+    zero-mean r, by the cosine diagonalisation of L (module docstring)."""
+    from scipy.fft import dctn, idctn
+    nz, ny, nx = r.shape
+    lam = np.zeros(r.shape)
+    for axis, (n, d) in enumerate(((nz, desc.dz), (ny, desc.dy), (nx, desc.dx))):
+        ev = (2.0 * np.cos(np.pi * np.arange(n) / n) - 2.0) / (d * d)
+        sh = [1, 1, 1]
+        sh[axis] = n
+        lam = lam + ev.reshape(sh)
+    c = dctn(r, type=2, norm="ortho")
+    c[0, 0, 0] = 0.0
+    lam[0, 0, 0] = 1.0
+    return idctn(c / lam, type=2, norm="ortho")
 
 
 def default_omega(desc):
@@ -191,6 +216,7 @@ class EddyState:
         self.E_sol = esol_op(dB)
         r = neumann_rhs(d, self.E_sol)
         self.r = r
-        self.phi = sor(d, self.phi, r, default_sweeps(d), default_omega(d))
+        sweeps = default_sweeps(d)
+        self.phi = neumann_solve(d, r) if sweeps < 0 else sor(d, self.phi, r, sweeps, default_omega(d))
         self.J = d.sigma * (self.E_sol + irrotational(d, self.phi, self.E_sol))
         self.H_eddy = heddy_op(self.J)

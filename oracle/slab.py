@@ -237,7 +237,8 @@ class FilmEddy:
         sweeps, omega = _eddy.default_sweeps(d), _eddy.default_omega(d)
         for f in range(2):
             self.r[f] = _eddy.neumann_rhs(d, self.E_sol[f])
-            self.phi[f] = _eddy.sor(d, self.phi[f], self.r[f], sweeps, omega)
+            self.phi[f] = (_eddy.neumann_solve(d, self.r[f]) if sweeps < 0
+                           else _eddy.sor(d, self.phi[f], self.r[f], sweeps, omega))
             self.J[f] = d.sigma * (self.E_sol[f] + _eddy.irrotational(d, self.phi[f], self.E_sol[f]))
         self.H = [hop(self.J[0]) + self.cross_sum(system, -1.0, "s2b", self.J[1], x, s_int),
                   hop(self.J[1]) + self.cross_sum(system, -1.0, "b2s", self.J[0], x, s_int)]

@@ -149,8 +149,10 @@ struct mmv_mesh {
   void* divfield = nullptr;    // base field on the slider's stencil points
   double* divpart = nullptr;   // per row: sum |div|, sum |curl|
   OutTable tab_sur{};
-  int sor_sweeps = 40;
+  int sor_sweeps = 40;         // < 0: the exact Neumann solve
   double sor_omega = 1.0;
+  FftPlan pdct[3]{};           // exact solve: plans and twiddles of lengths nx, ny, nz
+  void* twdct[3] = {nullptr, nullptr, nullptr};
   // two films more than one cell thick (uses m0, mb, acc, hd, he, spec1,
   // kern_s and the eddy buffers above for both films)
   bool slab = false;
@@ -221,7 +223,10 @@ int validate(const mmv_mesh_desc* d) {
   if (d->sigma != 0.0 && !(d->nz > 1 && d->ny > 1 && d->nx > 1))
     return fail(MMV_EINVAL,
                 "eddy currents need magnets more than one cell thick in every direction (sigma must be 0)");
-  if (d->sor_sweeps < 0 || d->sor_sweeps > 100000) return fail(MMV_EINVAL, "sor_sweeps must be in [0, 100000]");
+  if (d->sor_sweeps < -1 || d->sor_sweeps > 100000)
+    return fail(MMV_EINVAL, "sor_sweeps must be -1 (the exact solve) or in [0, 100000]");
+  if (d->sor_sweeps == -1 && d->sigma != 0.0 && !(smooth2357(d->nx) && smooth2357(d->ny) && smooth2357(d->nz)))
+    return fail(MMV_EINVAL, "sor_sweeps -1 (the exact solve) needs nx, ny, nz {2,3,5,7}-smooth");
   if (!isfinite(d->sor_omega) || d->sor_omega < 0 || d->sor_omega >= 2) return fail(MMV_EINVAL, "sor_omega must be in [0, 2)");
   if (d->gap_cells < 0) return fail(MMV_EINVAL, "gap_cells must be >= 0");
   if (d->max_travel_cells < 0 || d->max_travel_cells > 4096)
@@ -621,6 +626,20 @@ int prof_mark(mmv_mesh* h, int kernel) {
     if (rc_) return rc_;             \
   } while (0)
 
+// Plans and twiddles of the exact Neumann solve (eddy currents with
+// sor_sweeps < 0).
+template <typename T>
+int init_dct(mmv_mesh* h) {
+  if (!(h->d.sigma > 0) || h->sor_sweeps >= 0) return MMV_OK;
+  const int n[3] = {h->nx, h->ny, h->nz};
+  for (int a = 0; a < 3; ++a) {
+    if (!make_plan(n[a], h->pdct[a])) return fail(MMV_EINVAL, "exact Neumann solve: an axis length has too many factors");
+    int rc = upload_tw(h, &h->twdct[a], n[a], n[a], sizeof(T) == 8);
+    if (rc) return rc;
+  }
+  return MMV_OK;
+}
+
 // ---------------------------------------------------------------- single magnet, 3-D
 template <typename T>
 int build_kernels_cube(mmv_mesh* h) {
@@ -721,10 +740,10 @@ int init_cube(mmv_mesh* h) {
   }
   c.gam = GAMMA0 / (1.0 + d.alpha * d.alpha);
   c.alpha = d.alpha;
-  h->sor_sweeps = d.sor_sweeps > 0 ? d.sor_sweeps : 40;
+  h->sor_sweeps = d.sor_sweeps != 0 ? d.sor_sweeps : 40;
   const int nmax = std::max(h->nx, std::max(h->ny, h->nz));
   h->sor_omega = d.sor_omega > 0 ? d.sor_omega : 2.0 / (1.0 + sin(M_PI / nmax));
-  return MMV_OK;
+  return init_dct<T>(h);
 }
 
 // Demagnetising-type convolution of a three-channel cell field:
@@ -763,8 +782,11 @@ int eddy_update(mmv_mesh* h, double dt) {
   rc = conv3<T>(h, h->bdot, h->es, (const T*)h->kern_s, 1, +1.0);
   if (rc) return rc;
   HIPCHK(launch_sor_rhs<T>(h->cl, (const T*)h->es, (T*)h->rr, h->red, mean, h->st));
-  HIPCHK(launch_sor<T>(h->cl, 1, (T*)h->phi, (T*)h->phi2, (const T*)h->rr, h->sor_omega, h->sor_sweeps, h->red, mean,
-                       h->st));
+  if (h->sor_sweeps < 0)
+    HIPCHK(launch_neumann_solve<T>(h->cl, 1, (const T*)h->rr, (T*)h->phi, (T*)h->phi2, h->pdct, h->twdct, h->st));
+  else
+    HIPCHK(launch_sor<T>(h->cl, 1, (T*)h->phi, (T*)h->phi2, (const T*)h->rr, h->sor_omega, h->sor_sweeps, h->red,
+                         mean, h->st));
   HIPCHK(launch_current<T>(h->cl, (const T*)h->phi, (const T*)h->es, (T*)h->bdot, h->d.sigma, h->st));
   (void)part;
   return conv3<T>(h, h->bdot, h->he, (const T*)h->kern_s, 1, -1.0);
@@ -943,9 +965,10 @@ int init_slab(mmv_mesh* h) {
   }
   c.gam = GAMMA0 / (1.0 + d.alpha * d.alpha);
   c.alpha = d.alpha;
-  h->sor_sweeps = d.sor_sweeps > 0 ? d.sor_sweeps : 40;
+  h->sor_sweeps = d.sor_sweeps != 0 ? d.sor_sweeps : 40;
   const int nmax = std::max(nx, std::max(ny, nz));
   h->sor_omega = d.sor_omega > 0 ? d.sor_omega : 2.0 / (1.0 + sin(M_PI / nmax));
+  if ((rc = init_dct<T>(h))) return rc;
   h->rp_hot.travel = h->rp_force.travel = d.max_travel_cells;
   h->rp_hot.halo = h->rp_force.halo = hl;
   return MMV_OK;
@@ -1040,9 +1063,12 @@ int slab_eddy(mmv_mesh* h, const T* m, double dt) {
   if (rc) return rc;
   for (int f = 0; f < 2; ++f)
     HIPCHK(launch_sor_rhs<T>(h->cl, (T*)h->es + f * F, (T*)h->rr + f * ncell, h->red, mean, h->st));
-  // the two films' Neumann problems in the same sweep launches
-  HIPCHK(launch_sor<T>(h->cl, 2, (T*)h->phi, (T*)h->phi2, (const T*)h->rr, h->sor_omega, h->sor_sweeps, h->red, mean,
-                       h->st));
+  // the two films' Neumann problems in the same launches
+  if (h->sor_sweeps < 0)
+    HIPCHK(launch_neumann_solve<T>(h->cl, 2, (const T*)h->rr, (T*)h->phi, (T*)h->phi2, h->pdct, h->twdct, h->st));
+  else
+    HIPCHK(launch_sor<T>(h->cl, 2, (T*)h->phi, (T*)h->phi2, (const T*)h->rr, h->sor_omega, h->sor_sweeps, h->red,
+                         mean, h->st));
   for (int f = 0; f < 2; ++f)
     HIPCHK(launch_current<T>(h->cl, (T*)h->phi + f * ncell, (T*)h->es + f * F, (T*)h->bdot + f * F, h->d.sigma,
                              h->st));

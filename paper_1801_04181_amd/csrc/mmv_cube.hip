@@ -602,6 +602,106 @@ __global__ void __launch_bounds__(SOR_THREADS)
   }
 }
 
+// ------------------------------------------------------------ exact Neumann solve
+// The finite-volume Neumann Laplacian of a box is diagonal in the cosine
+// basis cos(pi k (i + 1/2) / n) per axis, eigenvalue sum over axes of
+// (2 cos(pi k / n) - 2) / d^2.  Cosine transforms along one axis of
+// [nbox][nz][ny][nx] arrays take an n-point complex FFT of the reordered
+// line (Makhoul, IEEE Trans. ASSP 28, 27, 1980): the DCT-II
+// C_k = sum_i x_i cos(pi k (2 i + 1) / (2 n)) = Re(exp(-i pi k / (2 n)) V_k)
+// with V = DFT(v), v_p = x_{2p}, v_{n-1-p} = x_{2p+1}; the inverse builds
+// V_k = exp(i pi k / (2 n)) (C_k - i C_{n-k}) (C_n = 0) and v = IDFT(V).
+// Line l of a launch: element i at (l / inner) hs + l % inner + i es.
+// SOLVE (the last forward axis, z): C / lambda(kx, ky, kz), the k = 0 mode
+// (the gauge) set to zero.
+struct DctSolve {
+  int nx, ny;
+  double idx2, idy2, idz2;
+};
+
+template <typename T, bool INV, bool SOLVE>
+__global__ void __launch_bounds__(CUBE_THREADS)
+    k_dct_axis(const T* __restrict__ in, T* __restrict__ out, int nlines, int n, int inner, long long hs,
+               long long es, int CB, FftPlan P, const cpx<T>* __restrict__ tw, DctSolve sv) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* A = stw + n;
+  cpx<T>* B = A + (size_t)CB * n;
+  const int l0 = xcd_remap(blockIdx.x, gridDim.x) * CB;
+  if (l0 >= nlines) return;
+  const int nc = min(CB, nlines - l0);
+  for (int t = threadIdx.x; t < n; t += CUBE_THREADS) stw[t] = tw[t];
+  // element (c, i) of thread slot t: along the line for contiguous lines,
+  // across lines otherwise (coalesced either way)
+  auto slot = [&](int t, int& c, int& i) {
+    if (es == 1) {
+      c = t / n;
+      i = t - c * n;
+    } else {
+      i = t / nc;
+      c = t - i * nc;
+    }
+  };
+  auto addr = [&](int c, int i) {
+    const int l = l0 + c;
+    return (long long)(l / inner) * hs + (l % inner) + (long long)i * es;
+  };
+  if constexpr (!INV) {
+    for (int t = threadIdx.x; t < nc * n; t += CUBE_THREADS) {
+      int c, i;
+      slot(t, c, i);
+      const int p = (i & 1) ? n - 1 - (i >> 1) : (i >> 1);
+      A[c * n + p] = mk<T>(in[addr(c, i)], T(0));
+    }
+  } else {
+    T* Cs = reinterpret_cast<T*>(B);
+    for (int t = threadIdx.x; t < nc * n; t += CUBE_THREADS) {
+      int c, i;
+      slot(t, c, i);
+      Cs[c * n + i] = in[addr(c, i)];
+    }
+    lds_barrier();
+    for (int t = threadIdx.x; t < nc * n; t += CUBE_THREADS) {
+      const int c = t / n, k = t - c * n;
+      const T ck = Cs[c * n + k], cm = k ? Cs[c * n + n - k] : T(0);
+      T sn, cs;
+      if constexpr (sizeof(T) == 8)
+        sincospi((double)k / (2.0 * n), &sn, &cs);
+      else
+        sincospif((float)k / (2.0f * (float)n), &sn, &cs);
+      A[t] = mk<T>(ck * cs + cm * sn, ck * sn - cm * cs);
+    }
+  }
+  lds_barrier();
+  const cpx<T>* R = fft_lds_pow2<T, INV, CUBE_THREADS>(A, B, P, nc, n, stw);
+  for (int t = threadIdx.x; t < nc * n; t += CUBE_THREADS) {
+    int c, i;
+    slot(t, c, i);
+    T v;
+    if constexpr (!INV) {
+      const cpx<T> V = R[c * n + i];
+      T sn, cs;
+      if constexpr (sizeof(T) == 8)
+        sincospi((double)i / (2.0 * n), &sn, &cs);
+      else
+        sincospif((float)i / (2.0f * (float)n), &sn, &cs);
+      v = V.x * cs + V.y * sn;
+      if constexpr (SOLVE) {
+        const int lo = (l0 + c) % inner;
+        const int ky = lo / sv.nx, kx = lo - ky * sv.nx;
+        const double lam = (2.0 * cospi((double)kx / sv.nx) - 2.0) * sv.idx2 +
+                           (2.0 * cospi((double)ky / sv.ny) - 2.0) * sv.idy2 +
+                           (2.0 * cospi((double)i / n) - 2.0) * sv.idz2;
+        v = (kx == 0 && ky == 0 && i == 0) ? T(0) : (T)((double)v / lam);
+      }
+    } else {
+      const int p = (i & 1) ? n - 1 - (i >> 1) : (i >> 1);
+      v = R[c * n + p].x / (T)n;
+    }
+    out[addr(c, i)] = v;
+  }
+}
+
 // J = sigma (E_sol + E_irrot), E_irrot,a = -(g+ + g-)/2, surface faces take E_sol,a.
 template <typename T>
 __global__ void k_current(int nx, int ny, int nz, double dx, double dy, double dz, const T* __restrict__ phi,
@@ -837,6 +937,55 @@ hipError_t launch_current(const CubeLaunch& c, const T* phi, const T* es, T* J, 
 }
 
 
+// Exact solve of the nbox Neumann problems (r -> phi, zero mean), work of
+// the same size: forward x, y, z (with the division), inverse z, y, x.
+template <typename T>
+hipError_t launch_neumann_solve(const CubeLaunch& c, int nbox, const T* r, T* phi, T* work, const FftPlan* P,
+                                const void* const* tw, hipStream_t st) {
+  const int nx = c.nx, ny = c.ny, nz = c.nz;
+  const long long N = (long long)nx * ny * nz;
+  DctSolve sv{nx, ny, 1.0 / (c.dx * c.dx), 1.0 / (c.dy * c.dy), 1.0 / (c.dz * c.dz)};
+  struct Ax {
+    int n, inner;
+    long long hs, es;
+    int nlines;
+  };
+  const Ax ax[3] = {{nx, 1, nx, 1, (int)(nbox * N / nx)},
+                    {ny, nx, (long long)nx * ny, nx, (int)(nbox * N / ny)},
+                    {nz, nx * ny, N, (long long)nx * ny, (int)(nbox * N / nz)}};
+  auto run = [&](int a, bool inv, bool solve, const T* src, T* dst) -> hipError_t {
+    const Ax& x = ax[a];
+    int CB = (int)((65536 / sizeof(cpx<T>) - x.n) / (2 * (size_t)x.n));
+    if (CB > 16) CB = 16;
+    if (CB < 1) CB = 1;
+    const size_t lds = sizeof(cpx<T>) * ((size_t)x.n + 2 * (size_t)CB * x.n);
+    const void* fn = inv ? (const void*)k_dct_axis<T, true, false>
+                         : (solve ? (const void*)k_dct_axis<T, false, true> : (const void*)k_dct_axis<T, false, false>);
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    const dim3 grid((x.nlines + CB - 1) / CB);
+    if (inv)
+      hipLaunchKernelGGL((k_dct_axis<T, true, false>), grid, dim3(CUBE_THREADS), lds, st, src, dst, x.nlines, x.n,
+                         x.inner, x.hs, x.es, CB, P[a], (const cpx<T>*)tw[a], sv);
+    else if (solve)
+      hipLaunchKernelGGL((k_dct_axis<T, false, true>), grid, dim3(CUBE_THREADS), lds, st, src, dst, x.nlines, x.n,
+                         x.inner, x.hs, x.es, CB, P[a], (const cpx<T>*)tw[a], sv);
+    else
+      hipLaunchKernelGGL((k_dct_axis<T, false, false>), grid, dim3(CUBE_THREADS), lds, st, src, dst, x.nlines, x.n,
+                         x.inner, x.hs, x.es, CB, P[a], (const cpx<T>*)tw[a], sv);
+    return hipGetLastError();
+  };
+  hipError_t e = run(0, false, false, r, work);
+  if (e == hipSuccess) e = run(1, false, false, work, phi);
+  if (e == hipSuccess) e = run(2, false, true, phi, work);
+  if (e == hipSuccess) e = run(2, true, false, work, phi);
+  if (e == hipSuccess) e = run(1, true, false, phi, work);
+  if (e == hipSuccess) e = run(0, true, false, work, phi);
+  return e;
+}
+
 hipError_t launch_kernel_real3(double* out, int Lx, int Ly, int Lz, int kind, int comp, double dx, double dy,
                                double dz, double rc, double scale, hipStream_t st) {
   dim3 grid((Lx + 127) / 128, Ly, Lz);
@@ -867,6 +1016,8 @@ hipError_t launch_pack3(const void* spec, T* out, int Kx, int Ly, int Lz, int im
                                      hipStream_t);                                                             \
   template hipError_t launch_current<T>(const CubeLaunch&, const T*, const T*, T*, double, hipStream_t);         \
   template hipError_t launch_sor_residual<T>(const CubeLaunch&, const T*, const T*, double*, int, hipStream_t);  \
+  template hipError_t launch_neumann_solve<T>(const CubeLaunch&, int, const T*, T*, T*, const FftPlan*,          \
+                                              const void* const*, hipStream_t);                                 \
   template hipError_t launch_pack3<T>(const void*, T*, int, int, int, int, hipStream_t);
 
 MMV_CUBE_INST(float)

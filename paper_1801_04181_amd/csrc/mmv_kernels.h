@@ -88,6 +88,12 @@ hipError_t launch_sor_residual(const CubeLaunch& c, const T* phi, const T* r, do
 template <typename T>
 hipError_t launch_sor(const CubeLaunch& c, int nbox, T* phi, T* phi2, const T* r, double omega, int sweeps,
                       double* part, double* mean, hipStream_t st);
+// The nbox Neumann problems solved exactly in the cosine basis (r -> phi,
+// zero mean; work: scratch of the same size); P, tw: FFT plans and twiddle
+// tables of lengths nx, ny, nz ({2,3,5,7}-smooth).
+template <typename T>
+hipError_t launch_neumann_solve(const CubeLaunch& c, int nbox, const T* r, T* phi, T* work, const FftPlan* P,
+                                const void* const* tw, hipStream_t st);
 template <typename T>
 hipError_t launch_current(const CubeLaunch& c, const T* phi, const T* es, T* J, double sigma, hipStream_t st);
 hipError_t launch_kernel_real3(double* out, int Lx, int Ly, int Lz, int kind, int comp, double dx, double dy,

@@ -175,6 +175,17 @@ def test_potential_mode_needs_two_films():
     assert e.value.code == -1 and "two films" in str(e.value)
 
 
+def test_exact_neumann_solve_descriptor():
+    d = get_config("cube_eddy")["desc"]
+    for sweeps in (-2, -100):
+        with pytest.raises(mmv.MMVError) as e:
+            mmv.init_mesh(mmv.to_desc(d.replace(sor_sweeps=sweeps)))
+        assert "sor_sweeps" in str(e.value)
+    with pytest.raises(mmv.MMVError) as e:
+        mmv.init_mesh(mmv.to_desc(d.replace(sor_sweeps=-1, nx=37)))
+    assert "smooth" in str(e.value)
+
+
 def test_eddy_needs_a_thick_single_magnet():
     d = get_config("stickslip")["desc"].replace(sigma=1e6)
     with pytest.raises(mmv.MMVError) as e:

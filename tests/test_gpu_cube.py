@@ -145,3 +145,13 @@ def test_eddy_residual_needs_an_eddy_mesh():
         mmv.eddy_residual(mesh.h)
     assert e.value.code == -6
     mesh.close()
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_cube_eddy_exact_neumann_solve(prec):
+    """sor_sweeps = -1: the Neumann problem solved in the cosine basis on
+    both sides (anisotropic cells): every term incl. eddy, and m."""
+    import paper_1801_04181_amd as mmv
+    d = get_config("cube_eddy")["desc"].replace(nx=12, ny=10, nz=9, dy=2.5e-9, precision=prec, sor_sweeps=-1)
+    out = run(d, 4)
+    assert out["m"] < (1e-6 if prec == 32 else 1e-12)

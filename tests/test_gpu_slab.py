@@ -191,3 +191,30 @@ def test_thick_films_non_uniform_applied_field(prec, cross_mode):
         mesh.set_hext_field(1, hb)
     mesh.close()
     print("  ", out, flush=True)
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_thick_films_exact_neumann_solve(prec):
+    """Eddy currents in both films with the Neumann problems solved exactly
+    (sor_sweeps = -1, both films in the same launches): m and each film's
+    eddy field against the oracle, and a residual at rounding level."""
+    import torch
+    import paper_1801_04181_amd as mmv
+    d, m = films(15, 10, 3, prec, gap=1, travel=4, sigma=1e6, state="stripes", seed=13, sor_sweeps=-1)
+    drv = Drive(mode=1, v_d=1200.0, x0=0.88 * d.dx)
+    print(f"slab exact p{prec}", flush=True)
+    mesh, s = pair(d, m, drv)
+    dt, n = 1e-13, 3
+    mesh.step(dt, n)
+    torch.cuda.synchronize()
+    s.run(dt, n)
+    out = {}
+    for f in range(2):
+        out[f"m{f}"] = float(np.abs(mesh.get_m(f).cpu().numpy() - s.m[f]).max())
+        assert out[f"m{f}"] < TOL_M[prec], out
+        out[f"eddy{f}"] = rel(mesh.eval_heff(f, 32).cpu().numpy(), s.eddy.H[f])
+        assert out[f"eddy{f}"] <= TOL_EDDY[prec], out
+    out["residual"] = mmv.eddy_residual(mesh.h)
+    assert out["residual"] < (1e-4 if prec == 32 else 1e-12), out
+    mesh.close()
+    print("  ", out, flush=True)

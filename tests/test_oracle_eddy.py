@@ -177,3 +177,21 @@ def test_uniform_field_pin_rejects_flipped_surface_sign():
     J, scale = _uniform_field_current(d, shape, np.array([3.0, -2.0, 1.5]),
                                       rhs=lambda dd, E: -eddy.neumann_rhs(dd, E))
     assert np.abs(J).max() > 0.5 * scale
+
+
+@pytest.mark.parametrize("shape", [(5, 6, 8), (2, 7, 3), (1, 4, 9)])
+def test_exact_neumann_solve_equals_the_sparse_solve(shape):
+    """The cosine-basis solve (sor_sweeps < 0) against a least-squares solve
+    of the independently assembled finite-volume system with the zero-mean
+    gauge row; anisotropic cells; one-cell-thin axes included."""
+    d = cube(shape[::-1], d=2e-9).replace(dy=3e-9, dz=1.5e-9, sor_sweeps=-1)
+    rng = np.random.default_rng(sum(shape))
+    r = eddy.neumann_rhs(d, rng.standard_normal((3,) + shape))
+    A = fv_matrix(d, shape)
+    N = r.size
+    Aa = sp.vstack([A, sp.csr_matrix(np.ones((1, N)))])
+    sol = spla.lsqr(Aa, np.concatenate([r.ravel(), [0.0]]), atol=1e-15, btol=1e-15, iter_lim=50000)[0]
+    phi = eddy.neumann_solve(d, r)
+    assert abs(phi.sum()) < 1e-12 * np.abs(phi).sum()
+    assert np.abs(phi.ravel() - sol).max() < 1e-9 * np.abs(sol).max()
+    assert eddy.residual(d, phi, r) < 1e-12
