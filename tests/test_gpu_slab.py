@@ -75,6 +75,18 @@ def test_thick_field_terms_and_force(prec, nz, x_cells, cross_mode):
 
 
 @pytest.mark.parametrize("prec", [32, 64])
+def test_thick_fields_beyond_the_register_product(prec):
+    """nz = 9: more layers than the register-resident product holds, so the
+    generic product kernel (one thread per target layer) runs."""
+    print(f"slab nz=9 p{prec}", flush=True)
+    d, m = films(11, 7, 9, prec, gap=2, seed=19)
+    mesh, s = pair(d, m, Drive(mode=0, x0=-1.23 * d.dx))
+    out = check_terms(mesh, s, prec)
+    mesh.close()
+    print("  ", {k: f"{v:.2e}" for k, v in out.items()}, flush=True)
+
+
+@pytest.mark.parametrize("prec", [32, 64])
 def test_thick_fields_ragged_and_at_the_travel_bound(prec):
     """Odd sizes spanning several transform rows per block and sampling
     blocks, the slider seated at the largest offset the window allows, and
