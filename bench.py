@@ -542,6 +542,7 @@ def main():
     ap.add_argument("--config", default="stickslip")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-eddy", action="store_true", help="skip the conducting cube and thick-film step times")
     ap.add_argument("--no-graph", action="store_true", help="--report batch: eager launches (counter runs)")
     ap.add_argument("--report", choices=["surrogate", "cube", "batch", "surrogate-batched", "divcurl",
                                          "eddy-films"],
@@ -646,6 +647,11 @@ def main():
     if not args.no_batch:
         out["batched"] = batched_vs_plain()
         out["surrogate_batched"] = surrogate_batched()
+    if not args.no_eddy:
+        # the conducting workloads' step times (GPU only; their oracles'
+        # timings are in the reports of their own)
+        out["cube_eddy"] = cube_report()
+        out["eddy_films"] = eddy_films_report(cpu=False)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, m)
         out["cpu_baseline_variants"] = cpu_baseline_variants()
