@@ -230,3 +230,51 @@ def test_thick_films_exact_neumann_solve(prec):
     assert out["residual"] < (1e-4 if prec == 32 else 1e-12), out
     mesh.close()
     print("  ", out, flush=True)
+
+
+def _slab_golden():
+    import importlib.util
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    spec = importlib.util.spec_from_file_location("make_slab_trajectory",
+                                                  os.path.join(here, "golden", "make_slab_trajectory.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod, np.load(os.path.join(here, "golden", "slab_1000.npz"))
+
+
+# 1000 steps with eddy currents in both films and the slider crossing a cell
+# boundary: per-cell max |m_gpu - m_oracle| over both films (the film path's
+# trajectory bars; measured 1.2e-5 / 2.4e-11), the slider's position in
+# cells, the eddy fields at the end (the stepping bar; measured 6.4e-6 /
+# 9.5e-12).
+TOL_M1000 = {32: 1e-4, 64: 1e-8}
+TOL_X1000 = {32: 1e-5, 64: 1e-9}
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_thick_films_1000_steps_against_the_stored_oracle_run(prec):
+    import torch
+    import paper_1801_04181_amd as mmv
+    mod, g = _slab_golden()
+    d, drv, m = mod.case(prec)
+    print(f"slab 1000 steps p{prec}", flush=True)
+    mesh = mmv.Mesh(d, drv, m)
+    done, out = 0, {}
+    for n in (int(k) for k in g["steps"]):
+        mesh.step(mod.DT, n - done)
+        done = n
+        torch.cuda.synchronize()
+        st = mesh.state()
+        assert st["step"] == n
+        dm = max(float(np.abs(mesh.get_m(f).cpu().numpy() - g[f"m{f}_{n}"]).max()) for f in range(2))
+        dx = abs(st["x"] - float(g[f"x_{n}"])) / d.dx
+        out[n] = (dm, dx)
+        assert dm < TOL_M1000[prec], out
+        assert dx < TOL_X1000[prec], out
+    assert float(g["x_1000"]) / d.dx > 1.0 > float(g["x_250"]) / d.dx, "the stored run crosses a cell boundary"
+    for f in range(2):
+        out[f"eddy{f}"] = rel(mesh.eval_heff(f, 32).cpu().numpy(), g[f"eddy{f}"])
+        assert out[f"eddy{f}"] <= TOL_EDDY[prec], out
+    mesh.close()
+    print("  ", out, flush=True)
