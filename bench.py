@@ -399,6 +399,107 @@ def eddy_films_report(steps=20, warmup=2, cpu=True):
     return out
 
 
+def variants_report(steps=400, warmup=40, dp_span_steps=400, dp_tol=1e-5):
+    """The step's variants on the stick-slip films (2 x 512 x 128, float32).
+
+    periodic: in-plane periodic boundaries along x and y (pbc = 3, one image
+      on each side; the transform lengths are the periods, 512 and 128):
+      HIP events around `steps` RK4 steps, and the row kernel's launch time
+      against its algorithmic bytes (as the main line's roofline);
+    adaptive: the Dormand-Prince RK5(4) run (llg_run_dp) over
+      dp_span_steps x 1e-13 s at tol dp_tol from the state after `warmup`
+      RK4 steps: attempts, accepted steps, mean accepted step, wall time
+      (host clock around the call, which checks the run's end every 8
+      attempts), time per attempt (seven stages) and cell-updates per second
+      counted per accepted step."""
+    import torch
+    import paper_1801_04181_amd as mmv
+    from workloads import get_config, initial_state
+
+    cfg = get_config("stickslip")
+    d0, drv, dt = cfg["desc"], cfg["drive"], cfg["dt"]
+    m = initial_state(cfg)
+    out = {"workload": "stickslip: 2 films 512x128x1 cells of 2 nm, float32, spring drive"}
+    d = d0.replace(pbc=3, pbc_images=1)
+    mesh = mmv.Mesh(d, drv, m)
+    mesh.step(dt, warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(mesh.stream)
+    mesh.step(dt, steps)
+    e1.record(mesh.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    lx, ly, _ = mesh.fft_lengths()
+    per_launch, cells = kernel_bytes(d, lx, ly)
+    kern_ms = {k: mmv.profile_repeat(mesh.h, k, 200) for k in ("col", "row_stage")}
+    dom = max(kern_ms, key=kern_ms.get)
+    ach = per_launch[dom] / (kern_ms[dom] * 1e-3) / 1e9
+    out["periodic"] = {"pbc": 3, "pbc_images": 1, "fft": [lx, ly], "ms_per_step": ms,
+                       "cell_updates_per_s": cells / (ms * 1e-3),
+                       "kernel_us": {k: v * 1e3 for k, v in kern_ms.items()},
+                       "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": PEAK_HBM_GBS,
+                                    "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                                    "bytes_per_launch": per_launch[dom]}}
+    mesh.close()
+    mesh = mmv.Mesh(d0, drv, m)
+    mesh.step(dt, warmup)
+    torch.cuda.synchronize()
+    t0s = mesh.state()["t"]
+    t_end = t0s + dp_span_steps * dt
+    w0 = time.perf_counter()
+    r = mesh.run_dp(t_end, dp_tol, dt, max_attempts=20000)
+    wall = time.perf_counter() - w0
+    st = mesh.state()
+    attempts = r["accepted"] + r["rejected"]
+    out["adaptive"] = {"tol": dp_tol, "span_s": t_end - t0s, "reached_s": st["t"] - t0s,
+                       "accepted": r["accepted"], "rejected": r["rejected"],
+                       "mean_step_s": (st["t"] - t0s) / max(r["accepted"], 1), "wall_s": wall,
+                       "ms_per_attempt": wall * 1e3 / max(attempts, 1),
+                       "cell_updates_per_s": cells * r["accepted"] / wall,
+                       "rk4_equivalent_steps_per_s": (st["t"] - t0s) / dt / wall}
+    mesh.close()
+    out["spline3"] = spline3_timing()
+    return out
+
+
+def spline3_timing(n=128, npts=1 << 20, reps=20):
+    """The 64-tap tricubic spline primitives (motion off the x axis) on an
+    n^3 float32 field: the prefilter along x, y, z and the gather at npts
+    seeded random points, HIP events around `reps` calls each.  Algorithmic
+    bytes: the prefilter reads and writes the field once per axis (6 n^3 x 4
+    B); the gather reads each point (12 B) and writes its value (4 B), the
+    coefficients once (n^3 x 4 B)."""
+    import torch
+    import paper_1801_04181_amd as mmv
+    g = torch.Generator(device="cuda:0").manual_seed(5)
+    f = torch.rand((n, n, n), generator=g, device="cuda:0", dtype=torch.float32)
+    coef = torch.empty_like(f)
+    work = torch.empty_like(f)
+    pts = torch.rand((npts, 3), generator=g, device="cuda:0", dtype=torch.float32) * (n - 1)
+    out = torch.empty(npts, device="cuda:0", dtype=torch.float32)
+    st = torch.cuda.current_stream()
+    mmv.spline3_prefilter(f, coef, work, stream=st)
+    mmv.spline3_gather(coef, pts, out, stream=st)
+    res = {"n": n, "points": npts}
+    for name, fn, nbytes in (("prefilter", lambda: mmv.spline3_prefilter(f, coef, work, stream=st), 6 * n ** 3 * 4),
+                             ("gather", lambda: mmv.spline3_gather(coef, pts, out, stream=st),
+                              npts * 16 + n ** 3 * 4)):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        res[name] = {"us_per_call": us, "algorithmic_bytes": nbytes, "achieved_GBs": nbytes / (us * 1e-6) / 1e9,
+                     "frac_of_hbm": nbytes / (us * 1e-6) / 1e9 / PEAK_HBM_GBS}
+    return res
+
+
 def surrogate_report(train_steps=3000, B=8, steps=200, log=None):
     """Learned stray-field operator on the 2 x 256 x 256 films: train on fresh
     exact pairs, held-out error, then LLG steps with the operator attached
@@ -543,9 +644,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-eddy", action="store_true", help="skip the conducting cube and thick-film step times")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the periodic and adaptive variants of the stick-slip step")
     ap.add_argument("--no-graph", action="store_true", help="--report batch: eager launches (counter runs)")
     ap.add_argument("--report", choices=["surrogate", "cube", "batch", "surrogate-batched", "divcurl",
-                                         "eddy-films"],
+                                         "eddy-films", "variants"],
                     default=None)
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--calib-copy", action="store_true",
@@ -553,6 +656,9 @@ def main():
     args = ap.parse_args()
     if args.report == "cube":
         print(json.dumps({"cube_report": cube_report()}), flush=True)
+        return
+    if args.report == "variants":
+        print(json.dumps({"variants": variants_report()}), flush=True)
         return
     if args.report == "eddy-films":
         print(json.dumps({"eddy_films_report": eddy_films_report(steps=args.steps if args.steps < 2000 else 20,
@@ -652,6 +758,8 @@ def main():
         # timings are in the reports of their own)
         out["cube_eddy"] = cube_report()
         out["eddy_films"] = eddy_films_report(cpu=False)
+    if not args.no_variants:
+        out["variants"] = variants_report()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, m)
         out["cpu_baseline_variants"] = cpu_baseline_variants()

@@ -40,11 +40,16 @@ __device__ __forceinline__ T bspline3(T t) {
   return T(0);
 }
 
-// One output coefficient per thread along axis `ax` of a [nz][ny][nx] array.
+// One output coefficient per thread along axis `ax` of a [nz][ny][nx] array:
+// c_i = w_0 f_i + sum_{j=1..K} w_j (f_{i-j} + f_{i+j}), w_j = sqrt(3) z1^j,
+// the block's weights in LDS; mirror indices only near the line's ends.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_spline3_prefilter(const T* __restrict__ in, T* __restrict__ out, int nx, int ny, int nz, int ax) {
   constexpr int K = Spl3Taps<T>::K;
+  __shared__ T w[K + 1];
+  if (threadIdx.x <= K) w[threadIdx.x] = (T)(1.7320508075688772935 * pow(-0.26794919243112270647, (double)threadIdx.x));
+  __syncthreads();
   const long long n = (long long)nx * ny * nz;
   const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= n) return;
@@ -55,15 +60,15 @@ __global__ void __launch_bounds__(256)
   const int i = ax == 0 ? ix : (ax == 1 ? iy : iz);
   const long long stride = ax == 0 ? 1 : (ax == 1 ? nx : (long long)nx * ny);
   const T* line = in + (id - (long long)i * stride);
-  const double z1 = -0.26794919243112270647;  // sqrt(3) - 2
-  // sum over |j| <= K in order j = -K .. K, weights sqrt(3) z1^|j|
-  double zk = 1.0;
-  for (int j = 0; j < K; ++j) zk *= z1;  // z1^K
-  T acc = T(0);
-  for (int j = -K; j <= K; ++j) {
-    const T a = (T)(1.7320508075688772935 * zk);
-    acc += a * line[(long long)mirror(i - j, M) * stride];
-    zk = j < 0 ? zk / z1 : zk * z1;
+  T acc = w[0] * line[(long long)i * stride];
+  if (i >= K && i + K < M) {
+    const T* f = line + (long long)i * stride;
+#pragma unroll
+    for (int j = 1; j <= K; ++j) acc += w[j] * (f[-(long long)j * stride] + f[(long long)j * stride]);
+  } else {
+#pragma unroll 4
+    for (int j = 1; j <= K; ++j)
+      acc += w[j] * (line[(long long)mirror(i - j, M) * stride] + line[(long long)mirror(i + j, M) * stride]);
   }
   out[id] = acc;
 }
