@@ -5,8 +5,9 @@ TEST INFRASTRUCTURE ONLY (part of the float64 oracle).
 
 Geometry.  As in oracle.sim, but each film is nx x ny x nz cells (nz >= 1)
 and the slider's lattice origin sits z_s = nz + gap layers above the base's.
-Open in-plane boundaries; the direct cross modes only (cubic B-spline along
-x, cross_mode 0, or linear interpolation, cross_mode 2).
+Open in-plane boundaries; every cross mode: the direct field with the cubic
+B-spline along x (cross_mode 0) or linear interpolation (2), and the scalar
+potential (1).
 
 Cross fields.  The base's exact lattice field is computed on the slider's
 window of base-lattice points x in [s_int - h, s_int + nx + h), rows
@@ -16,6 +17,13 @@ x = i + s_int + x_p.  The slider's field is computed on the base's window
 (x in [-s_int - h, -s_int + nx + h), rows [0, ny), layers -z_s .. -z_s + nz
 - 1 of the slider's lattice, i.e. the base's layers) and sampled at
 x = i - s_int - x_p.  With nz = 1 these are the windows of oracle.sim.
+
+Scalar-potential mode (Sec. II.A, III.A, Eqs. 7-8).  The base's potential is
+computed on the slider's window with rows [-3, ny + 2] and layers z_s - 3 ..
+z_s + nz + 2, the slider's on the base's window with rows [-2, ny + 1] and
+layers -z_s - 2 .. -z_s + nz + 1; each window row is prefiltered along x and
+sampled at the shifted lattice, and H = -grad phi by the four-point central
+difference along every axis (as oracle.sim, layer by layer).
 
 Force (Eq. 3).  F = mu0 Ms V sum over every slider cell of (m . grad) H
 with two-point central differences of the interpolated base field; the
@@ -80,7 +88,6 @@ class SlabSystem(System):
 
     def __init__(self, desc, drive=None, m_init=None):
         assert desc.n_films == 2, "two films"
-        assert desc.cross_mode in (0, 2), "direct cross modes only"
         assert desc.pbc == 0, "open in-plane boundaries"
         # the base class would set up the single-magnet eddy state
         super().__init__(desc.replace(sigma=0.0), drive, m_init)
@@ -93,14 +100,37 @@ class SlabSystem(System):
     def cross_box(self, direction, s_int):
         d = self.desc
         h, zs, nwx = d.halo, d.z_s, d.nx + 2 * d.halo
+        if d.cross_mode == 1:
+            if direction == "b2s":
+                return (s_int - h, nwx, -3, d.ny + 6, zs - 3, d.nz + 6)
+            return (-s_int - h, nwx, -2, d.ny + 4, -zs - 2, d.nz + 4)
         if direction == "b2s":
             return (s_int - h, nwx, -1, d.ny + 2, zs - 1, d.nz + 2)
         return (-s_int - h, nwx, 0, d.ny, -zs, d.nz)
 
+    @staticmethod
+    def grad4(c, t0, r0, u, n_l, ny, steps):
+        """-grad phi by four-point central differences at window layers t0 ..
+        t0 + n_l - 1, rows r0 .. r0 + ny - 1 and positions u, from the
+        prefiltered potential window c (layers, rows, M): (3, n_l, ny, nx)."""
+        def p(t, r, uu):
+            return np.stack([interp_1d(c[t + k, r:r + ny], uu) for k in range(n_l)])
+
+        def d4(fm2, fm1, fp1, fp2, hh):
+            return (fm2 - 8.0 * fm1 + 8.0 * fp1 - fp2) / (12.0 * hh)
+
+        dx, dy, dz = steps
+        hx = -d4(p(t0, r0, u - 2), p(t0, r0, u - 1), p(t0, r0, u + 1), p(t0, r0, u + 2), dx)
+        hy = -d4(p(t0, r0 - 2, u), p(t0, r0 - 1, u), p(t0, r0 + 1, u), p(t0, r0 + 2, u), dy)
+        hz = -d4(p(t0 - 2, r0, u), p(t0 - 1, r0, u), p(t0 + 1, r0, u), p(t0 + 2, r0, u), dz)
+        return np.array([hx, hy, hz])
+
     def interpolant(self):
-        if self.desc.cross_mode == 0:
-            return (lambda G: prefilter(G, axis=-1)), interp_1d
-        return (lambda G: G), linear_1d
+        """The interpolant of field vectors along x (direct cross field, eddy
+        sums, applied field): linear in cross_mode 2, else the spline."""
+        if self.desc.cross_mode == 2:
+            return (lambda G: G), linear_1d
+        return (lambda G: prefilter(G, axis=-1)), interp_1d
 
     def positions(self, x, s_int, direction):
         """Window coordinates of the target film's cells along x."""
@@ -115,8 +145,17 @@ class SlabSystem(System):
         neighbour points, each (3, nz, ny, nx) [A/m]."""
         d = self.desc
         ny, nz = d.ny, d.nz
-        pre, samp = self.interpolant()
         u = self.positions(x, s_int, "b2s")
+        if d.cross_mode == 1:
+            # potential window: slider layer l at window layer l + 3, row j at j + 3
+            cphi = prefilter(self.cross_op("b2s", s_int)(m_b)[0], axis=-1)
+            st = (d.dx, d.dy, d.dz)
+            g = self.grad4
+            return {"c": g(cphi, 3, 3, u, nz, ny, st),
+                    "xp": g(cphi, 3, 3, u + 1, nz, ny, st), "xm": g(cphi, 3, 3, u - 1, nz, ny, st),
+                    "yp": g(cphi, 3, 4, u, nz, ny, st), "ym": g(cphi, 3, 2, u, nz, ny, st),
+                    "zp": g(cphi, 4, 3, u, nz, ny, st), "zm": g(cphi, 2, 3, u, nz, ny, st)}
+        pre, samp = self.interpolant()
         c = pre(self.cross_op("b2s", s_int)(m_b))     # (3, nz+2, ny+2, M)
         L, R = slice(1, nz + 1), slice(1, ny + 1)
         return {"c": samp(c[:, L, R], u),
@@ -137,6 +176,11 @@ class SlabSystem(System):
             dHdz = (st["zp"] - st["zm"]) / (2 * d.dz)
             F = MU0 * d.Ms * V * (m_s[0][None] * dHdx + m_s[1][None] * dHdy
                                   + m_s[2][None] * dHdz).sum(axis=(1, 2, 3))
+        if d.cross_mode == 1:
+            # base layer k at window layer k + 2, row j at j + 2
+            cb = prefilter(self.cross_op("s2b", s_int)(m_s)[0], axis=-1)
+            Hb = self.grad4(cb, 2, 2, self.positions(x, s_int, "s2b"), d.nz, d.ny, (d.dx, d.dy, d.dz))
+            return Hb, st["c"], F
         Gb = pre(self.cross_op("s2b", s_int)(m_s))     # (3, nz, ny, M)
         Hb = samp(Gb, self.positions(x, s_int, "s2b"))
         return Hb, st["c"], F

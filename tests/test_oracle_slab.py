@@ -240,3 +240,60 @@ def test_thick_films_energy_decays_with_a_frozen_slider():
         s.step(2e-13)
         e.append(s.energies()["total"])
     assert all(b < a for a, b in zip(e, e[1:])), e
+
+
+def potential_at(d, P, src, x_shift, z0):
+    """phi(P) = Ms sum_j S(P - r_j) . m_j over a film's cells."""
+    X, Y, Z = centres(d, x_shift, z0)
+    S = potential_kernel(P[0] - X, P[1] - Y, P[2] - Z, d.dx, d.dy, d.dz)
+    return d.Ms * sum(np.sum(S[b] * src[b]) for b in range(3))
+
+
+def grad4_at(fun, P, steps):
+    H = np.zeros(3)
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = steps[a]
+        H[a] = -(fun(P - 2 * e) - 8 * fun(P - e) + 8 * fun(P + e) - fun(P + 2 * e)) / (12 * steps[a])
+    return H
+
+
+@pytest.mark.parametrize("nz,s_int", [(2, 0), (3, 2)])
+def test_thick_potential_mode_equals_brute_force(nz, s_int):
+    """Scalar-potential mode at integer offsets: the four-point differences of
+    a brute-force potential at the cell centres, and Eq. 3's force from them."""
+    d, m = films(nx=6, ny=5, nz=nz, gap=3, seed=nz + 3 * s_int, cross_mode=1)
+    sysm = SlabSystem(d, Drive(mode=FROZEN, x0=s_int * d.dx), m)
+    Hb, Hs, F = sysm.cross_fields(m[0], m[1], s_int * d.dx, s_int)
+    zs = d.nz + d.gap_cells
+    xs = s_int * d.dx
+    steps = np.array([d.dx, d.dy, d.dz])
+    rb, rs, rF = np.zeros_like(Hb), np.zeros_like(Hs), np.zeros(3)
+    V = d.dx * d.dy * d.dz
+
+    def base_field(P):
+        return grad4_at(lambda Q: potential_at(d, Q, m[0], 0.0, 0), P, steps)
+
+    for k in range(d.nz):
+        for j in range(d.ny):
+            for i in range(d.nx):
+                Ps = np.array([xs + (i + 0.5) * d.dx, (j + 0.5) * d.dy, (zs + k + 0.5) * d.dz])
+                Pb = np.array([(i + 0.5) * d.dx, (j + 0.5) * d.dy, (k + 0.5) * d.dz])
+                rs[:, k, j, i] = base_field(Ps)
+                rb[:, k, j, i] = grad4_at(lambda Q: potential_at(d, Q, m[1], xs, zs), Pb, steps)
+                for a in range(3):
+                    e = np.zeros(3)
+                    e[a] = steps[a]
+                    rF += MU0 * d.Ms * V * m[1][a, k, j, i] * (base_field(Ps + e) - base_field(Ps - e)) / (2 * steps[a])
+    assert rel(Hs, rs) < 1e-9
+    assert rel(Hb, rb) < 1e-9
+    assert np.abs(F - rF).max() < 1e-8 * np.abs(rF).max()
+
+
+def test_thick_potential_mode_one_layer_reduces_to_the_film_oracle():
+    d, m = films(nx=9, ny=5, nz=1, gap=3, cross_mode=1)
+    x = 1.37 * d.dx
+    a = SlabSystem(d, Drive(mode=FROZEN, x0=x), m).cross_fields(m[0], m[1], x, 1)
+    b = System(d, Drive(mode=FROZEN, x0=x), m).cross_fields(m[0], m[1], x, 1)
+    for u, v in zip(a, b):
+        assert rel(u, v) < 1e-12
