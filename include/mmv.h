@@ -136,8 +136,9 @@ typedef struct {
  * 729 (float64), and fewer than 2^31 cells; beyond them, MMV_EINVAL.
  *
  * Two films more than one cell thick (n_films 2, nz > 1; Sec. II.A end,
- * III.B, IV.C-D): the thick-film path.  Direct cross modes only (cross_mode
- * 0 or 2; 1 is MMV_EINVAL), open in-plane boundaries (pbc 0).  Each field
+ * III.B, IV.C-D): the thick-film path.  Every cross mode (the scalar
+ * potential's windows reach three rows and layers past the films, Ly >=
+ * 2 (ny + 3)), open in-plane boundaries (pbc 0).  Each field
  * is a sum over the source film's layers of in-plane convolutions with the
  * kernel of each layer offset (FFT lengths as for one-layer films, fft_lz
  * unused): the films' own fields, the base's field on the slider's window

@@ -168,6 +168,9 @@ struct mmv_mesh {
   double* Bprev = nullptr;     // B at the last eddy update [2][3][nz][ny][nx]
   const void* slab_hext[2] = {nullptr, nullptr};  // applied field in use (hext_buf or NULL)
   SlabMulTable tab_t{}, tab_e{};
+  SlabMulTable tab_p{};        // scalar-potential mode: the two potential windows
+  void *pot_w[2] = {nullptr, nullptr};  // potential windows: slider side [nz+6][ny+6][M], base side [nz+4][ny+4][M]
+  void *pot_s[2] = {nullptr, nullptr};  // their samples [nz+6][ny+6][nx+6], [nz+4][ny+4][nx+4]
   // launch timing (diagnostics)
   int prof_kernel = 0;
   size_t prof_used = 0;
@@ -200,8 +203,6 @@ int validate(const mmv_mesh_desc* d) {
   if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(MMV_EINVAL, "nx, ny, nz must be >= 1");
   if (d->nx > 8192 || d->ny > 8192) return fail(MMV_EINVAL, "nx, ny must be <= 8192");
   if (d->nz > 8192) return fail(MMV_EINVAL, "nz must be <= 8192");
-  if (d->nz != 1 && d->n_films == 2 && d->cross_mode == 1)
-    return fail(MMV_EINVAL, "films more than one cell thick run in the direct modes (cross_mode 0 or 2)");
   auto pos = [](double v) { return isfinite(v) && v > 0; };
   if (!pos(d->dx) || !pos(d->dy) || !pos(d->dz)) return fail(MMV_EINVAL, "cell edges must be finite and > 0");
   if (!pos(d->Ms)) return fail(MMV_EINVAL, "Ms must be finite and > 0");
@@ -843,7 +844,8 @@ int build_kernels_slab(mmv_mesh* h) {
   const size_t plane = (size_t)h->Ly * h->Kx;
   int rc = dalloc(h, &h->kern_t, sizeof(T) * 6 * ndz * plane);
   if (rc) return rc;
-  if (d.sigma > 0 && (rc = dalloc(h, &h->kern_s, sizeof(T) * 3 * ndz * plane))) return rc;
+  const bool need_s = d.sigma > 0 || d.cross_mode == 1;
+  if (need_s && (rc = dalloc(h, &h->kern_s, sizeof(T) * 3 * ndz * plane))) return rc;
   mmv_mesh tmp_owner;
   void *grid = nullptr, *s1 = nullptr, *s2 = nullptr, *twxd = nullptr, *twpd = nullptr, *twyd = nullptr;
   rc = dalloc(&tmp_owner, &grid, sizeof(double) * (size_t)h->Lx * h->Ly);
@@ -860,7 +862,7 @@ int build_kernels_slab(mmv_mesh* h) {
   // stored part of each spectrum: tensor xz, yz and S x, y are imaginary
   const int imag_t[6] = {0, 0, 0, 0, 1, 1}, imag_s[3] = {1, 1, 0};
   hipError_t err = hipSuccess;
-  for (int kind = 0; kind < (d.sigma > 0 ? 2 : 1) && err == hipSuccess; ++kind) {
+  for (int kind = 0; kind < (need_s ? 2 : 1) && err == hipSuccess; ++kind) {
     const int ncomp = kind == SLAB_KIND_TENSOR ? 6 : 3;
     for (int comp = 0; comp < ncomp && err == hipSuccess; ++comp) {
       for (int dz = -h->sD; dz <= h->sD && err == hipSuccess; ++dz) {
@@ -892,15 +894,26 @@ int init_slab(mmv_mesh* h) {
   const size_t ncell = (size_t)nx * ny * nz, F = 3 * ncell;
   const size_t plane = (size_t)h->Ly * h->Kx, cs = 2 * sizeof(T);
   const int zs = nz + d.gap_cells, hl = d.halo;
-  h->sD = zs + nz;
+  const bool pot = d.cross_mode == 1;
+  // layer offsets of the kernel spectra: the windows reach z_s + nz (direct)
+  // or z_s + nz + 2 with the potential's layers below the base reaching -3
+  h->sD = pot ? zs + nz + 3 : zs + nz;
   int rc;
   void** bufs[] = {&h->m0, &h->mb[0], &h->mb[1], &h->acc, &h->hd, &h->he};
   for (void** b : bufs)
     if ((rc = dalloc(h, b, 2 * F * sizeof(T)))) return rc;
   const bool eddy = d.sigma > 0;
-  const size_t chP = std::max<size_t>(9 * (size_t)nz + 3 * (size_t)(nz + 2), eddy ? 12 * (size_t)nz : 0);
-  const size_t rowsI = std::max<size_t>(9 * (size_t)nz * ny + 3 * (size_t)(nz + 2) * (ny + 2),
-                                        eddy ? 12 * (size_t)nz * ny : 0);
+  size_t chP = std::max<size_t>(9 * (size_t)nz + 3 * (size_t)(nz + 2), eddy ? 12 * (size_t)nz : 0);
+  size_t rowsI = std::max<size_t>(9 * (size_t)nz * ny + 3 * (size_t)(nz + 2) * (ny + 2),
+                                  eddy ? 12 * (size_t)nz * ny : 0);
+  if (pot) {
+    chP = std::max<size_t>(chP, 6 * (size_t)nz + (nz + 6) + (nz + 4));
+    rowsI = std::max<size_t>(rowsI, 6 * (size_t)nz * ny + (size_t)(nz + 6) * (ny + 6) + (size_t)(nz + 4) * (ny + 4));
+    if ((rc = dalloc(h, &h->pot_w[0], sizeof(T) * (size_t)(nz + 6) * (ny + 6) * M))) return rc;
+    if ((rc = dalloc(h, &h->pot_w[1], sizeof(T) * (size_t)(nz + 4) * (ny + 4) * M))) return rc;
+    if ((rc = dalloc(h, &h->pot_s[0], sizeof(T) * (size_t)(nz + 6) * (ny + 6) * (nx + 6)))) return rc;
+    if ((rc = dalloc(h, &h->pot_s[1], sizeof(T) * (size_t)(nz + 4) * (ny + 4) * (nx + 4)))) return rc;
+  }
   if ((rc = dalloc(h, &h->spec1, cs * 2 * 3 * nz * (size_t)ny * h->Kx))) return rc;
   if ((rc = dalloc(h, &h->specM, cs * 2 * 3 * nz * plane))) return rc;
   if ((rc = dalloc(h, &h->specP, cs * chP * plane))) return rc;
@@ -939,6 +952,11 @@ int init_slab(mmv_mesh* h) {
   // the slider (x0 = s_int - h; with rows -1..ny and layers z_s-1..z_s+nz
   // for the tensor product); every group [3][ntz][Ly][Kx]
   const long long P = (long long)plane;
+  // potential mode: the films' own fields (the tensor table's first two
+  // groups) and the potentials of the other film on the windows
+  h->tab_p.n = 2;
+  h->tab_p.g[0] = SlabGroup{0, zs - 3, nz + 6, 1, -hl, -3, 6LL * nz * P};
+  h->tab_p.g[1] = SlabGroup{1, -zs - 2, nz + 4, -1, -hl, -2, (6LL * nz + nz + 6) * P};
   h->tab_t.n = 4;
   h->tab_t.g[0] = SlabGroup{0, 0, nz, 0, 0, 0, 0};
   h->tab_t.g[1] = SlabGroup{1, 0, nz, 0, 0, 0, 3LL * nz * P};
@@ -990,10 +1008,48 @@ int slab_fields(mmv_mesh* h, const T* m, bool self_on, bool cross_on, bool zee_o
   HIPCHK(launch_row_fwd<T>(m, h->spec1, 6 * nz * ny, nx, h->N2x, Kx, h->px, h->twx, h->twp, h->st, -R));
   HIPCHK(launch_fft_axis<T>(h->spec1, h->specM, 6 * nz, Kx, 0, ny, (long long)ny * Kx, h->Ly, (long long)P, h->py,
                             h->twy, false, h->st));
-  HIPCHK(launch_slab_mul<T>(h->specM, h->specP, (const T*)h->kern_t, h->tab_t, nz, h->sD, h->Lx, h->Ly, Kx, 0, 1.0,
-                            h->rigid, h->st));
   char* pI = (char*)h->specI;
   const size_t cs = 2 * sizeof(T);
+  if (h->d.cross_mode == 1) {
+    // the films' own fields (tensor groups 0, 1), the other film's potential
+    // on the windows (Eqs. 7-8), sampled along x, four-point differences
+    SlabMulTable own = h->tab_t;
+    own.n = 2;
+    HIPCHK(launch_slab_mul<T>(h->specM, h->specP, (const T*)h->kern_t, own, nz, h->sD, h->Lx, h->Ly, Kx, 0, 1.0,
+                              h->rigid, h->st));
+    HIPCHK(launch_slab_pot<T>(h->specM, h->specP, (const T*)h->kern_s, h->tab_p, nz, h->sD, h->Lx, h->Ly, Kx,
+                              h->d.Ms, h->rigid, h->st));
+    const int L1 = nz + 6, R1 = ny + 6, L2 = nz + 4, R2 = ny + 4;
+    const size_t o1 = 6 * (size_t)nz * ny, o2 = o1 + (size_t)L1 * R1;
+    HIPCHK(launch_fft_axis<T>(h->specP, pI, 6 * nz, Kx, 0, h->Ly, (long long)P, ny, (long long)ny * Kx, h->py, h->twy,
+                              true, h->st));
+    HIPCHK(launch_fft_axis<T>((char*)h->specP + cs * 6 * nz * P, pI + cs * o1 * Kx, L1, Kx, 0, h->Ly, (long long)P, R1,
+                              (long long)R1 * Kx, h->py, h->twy, true, h->st));
+    HIPCHK(launch_fft_axis<T>((char*)h->specP + cs * (6 * nz + L1) * P, pI + cs * o2 * Kx, L2, Kx, 0, h->Ly,
+                              (long long)P, R2, (long long)R2 * Kx, h->py, h->twy, true, h->st));
+    HIPCHK(launch_row_inv<T>(pI, (T*)h->hd, 6 * nz * ny, R, nx, h->N2x, Kx, h->px, h->twx, h->twp, h->st));
+    HIPCHK(launch_row_inv<T>(pI + cs * o1 * Kx, (T*)h->pot_w[0], L1 * R1, R, M, h->N2x, Kx, h->px, h->twx, h->twp,
+                             h->st));
+    HIPCHK(launch_row_inv<T>(pI + cs * o2 * Kx, (T*)h->pot_w[1], L2 * R2, R, M, h->N2x, Kx, h->px, h->twx, h->twp,
+                             h->st));
+    if (!self_on) HIPCHK(hipMemsetAsync(h->hd, 0, 2 * F * sizeof(T), h->st));
+    // slider side: samples at i = -3 .. nx + 2, then H on the force stencil
+    // (stencil point (l', j', i') at window layer l' + 2, row j' + 2, sample i' + 2)
+    HIPCHK(launch_slab_sample<T>((const T*)h->pot_w[0], 1, L1 * R1, M, M, 0, 0, h->d.halo, (T*)h->pot_s[0], -3, nx + 6,
+                                 1, 0, 0, idx, h->rigid, h->st));
+    HIPCHK(launch_slab_potgrad<T>((const T*)h->pot_s[0], R1, nx + 6, 2, nz + 2, ny + 2, nx + 2, (T*)h->stencil, 0,
+                                  h->d.dx, h->d.dy, h->d.dz, h->st));
+    if (cross_on) {
+      // base side: samples at i = -2 .. nx + 1; base cell (k, j, i) at window
+      // layer k + 2, row j + 2, sample i + 2
+      HIPCHK(launch_slab_sample<T>((const T*)h->pot_w[1], 1, L2 * R2, M, M, 0, 0, h->d.halo, (T*)h->pot_s[1], -2,
+                                   nx + 4, -1, 0, 0, idx, h->rigid, h->st));
+      HIPCHK(launch_slab_potgrad<T>((const T*)h->pot_s[1], R2, nx + 4, 2, nz, ny, nx, (T*)h->hd, 1, h->d.dx, h->d.dy,
+                                    h->d.dz, h->st));
+    }
+  } else {
+  HIPCHK(launch_slab_mul<T>(h->specM, h->specP, (const T*)h->kern_t, h->tab_t, nz, h->sD, h->Lx, h->Ly, Kx, 0, 1.0,
+                            h->rigid, h->st));
   HIPCHK(launch_fft_axis<T>(h->specP, pI, 9 * nz, Kx, 0, h->Ly, (long long)P, ny, (long long)ny * Kx, h->py, h->twy,
                             true, h->st));
   HIPCHK(launch_fft_axis<T>((char*)h->specP + cs * 9 * nz * P, pI + cs * 9 * (size_t)nz * ny * Kx, 3 * (nz + 2), Kx, 0,
@@ -1005,17 +1061,18 @@ int slab_fields(mmv_mesh* h, const T* m, bool self_on, bool cross_on, bool zee_o
                            Kx, h->px, h->twx, h->twp, h->st));
   if (!self_on) HIPCHK(hipMemsetAsync(h->hd, 0, 2 * F * sizeof(T), h->st));
   if (cross_on)
-    HIPCHK(launch_slab_sample<T>((const T*)h->win_s2b, nz * ny, M, M, 0, 0, h->d.halo, (T*)h->hd, 0, nx, -1, 1, interp,
+    HIPCHK(launch_slab_sample<T>((const T*)h->win_s2b, 3, nz * ny, M, M, 0, 0, h->d.halo, (T*)h->hd, 0, nx, -1, 1, interp,
                                  idx, h->rigid, h->st));
-  HIPCHK(launch_slab_sample<T>((const T*)h->win_b2s, (nz + 2) * (ny + 2), M, M, 0, 0, h->d.halo, (T*)h->stencil, -1,
+  HIPCHK(launch_slab_sample<T>((const T*)h->win_b2s, 3, (nz + 2) * (ny + 2), M, M, 0, 0, h->d.halo, (T*)h->stencil, -1,
                                nx + 2, 1, 0, interp, idx, h->rigid, h->st));
+  }
   HIPCHK(launch_slab_force<T>((const T*)h->stencil, m + F, (T*)h->hd + F, nx, ny, nz, cross_on ? 1 : 0, h->d.dx,
                               h->d.dy, h->d.dz, h->partial, h->st));
   if (zee_on && h->slab_hext[0]) HIPCHK(launch_slab_add<T>((int)F, (const T*)h->slab_hext[0], (T*)h->hd, h->st));
   if (zee_on && h->slab_hext[1]) {
     // the slider's window of the frame rows starts at column s_int + travel
     const int W = nx + 2 * (h->d.max_travel_cells + h->d.halo);
-    HIPCHK(launch_slab_sample<T>((const T*)h->slab_hext[1], nz * ny, M, W, 1, h->d.max_travel_cells, h->d.halo,
+    HIPCHK(launch_slab_sample<T>((const T*)h->slab_hext[1], 3, nz * ny, M, W, 1, h->d.max_travel_cells, h->d.halo,
                                  (T*)h->hd + F, 0, nx, 1, 1, interp, idx, h->rigid, h->st));
   }
   return MMV_OK;
@@ -1043,9 +1100,9 @@ int slab_s_sum(mmv_mesh* h, const T* src, T* dst, double sgn) {
   HIPCHK(launch_row_inv<T>(pI + cs * 6 * (size_t)nz * ny * Kx, (T*)h->win_e, 6 * nz * ny, R, M, h->N2x, Kx, h->px,
                            h->twx, h->twp, h->st));
   const size_t wsz = 3 * (size_t)nz * ny * M;
-  HIPCHK(launch_slab_sample<T>((const T*)h->win_e, nz * ny, M, M, 0, 0, h->d.halo, dst, 0, nx, -1, 1, interp,
+  HIPCHK(launch_slab_sample<T>((const T*)h->win_e, 3, nz * ny, M, M, 0, 0, h->d.halo, dst, 0, nx, -1, 1, interp,
                                1.0 / h->d.dx, h->rigid, h->st));
-  HIPCHK(launch_slab_sample<T>((const T*)h->win_e + wsz, nz * ny, M, M, 0, 0, h->d.halo, dst + F, 0, nx, 1, 1, interp,
+  HIPCHK(launch_slab_sample<T>((const T*)h->win_e + wsz, 3, nz * ny, M, M, 0, 0, h->d.halo, dst + F, 0, nx, 1, 1, interp,
                                1.0 / h->d.dx, h->rigid, h->st));
   return MMV_OK;
 }
@@ -2218,7 +2275,10 @@ int init_mesh(const mmv_mesh_desc* d, void* hip_stream, mmv_handle* out) {
     // two thick films: in-plane transforms sized as for one-layer films
     h->slab = true;
     h->nz = d->nz;
-    const int lx_min = 2 * (d->nx + d->halo + d->max_travel_cells), ly_min = 2 * (d->ny + 1);
+    // the windows reach one row past the films (direct mode: the force's
+    // rows) or three (the potential's four-point differences and the force)
+    const int lx_min = 2 * (d->nx + d->halo + d->max_travel_cells),
+              ly_min = 2 * (d->ny + (d->cross_mode == 1 ? 3 : 1));
     h->Lx = d->fft_lx ? d->fft_lx : next_smooth(lx_min, true);
     h->Ly = d->fft_ly ? d->fft_ly : next_smooth(ly_min, false);
     if (h->Lx < lx_min || h->Lx % 2 || !smooth2357(h->Lx) || h->Ly < ly_min || !smooth2357(h->Ly)) {

@@ -31,11 +31,22 @@ template <typename T>
 hipError_t launch_slab_mul(const void* in, void* out, const T* kern, const SlabMulTable& tab, int nz, int D, int Lx,
                            int Ly, int Kx, int mode, double sgn, const RigidState* rigid, hipStream_t st);
 size_t slab_sample_lds(int M, int esz);
-// window rows of length M starting at column cs * s_int + c_off of rows ld
-// apart (ld = M, cs = c_off = 0: rows of their own)
+// nch channels of window rows of length M starting at column cs * s_int +
+// c_off of rows ld apart (ld = M, cs = c_off = 0: rows of their own)
 template <typename T>
-hipError_t launch_slab_sample(const T* win, int nrow, int M, int ld, int cs, int c_off, int h, T* out, int i0, int nw,
-                              int sgn, int add, int interp, double inv_dx, const RigidState* rigid, hipStream_t st);
+hipError_t launch_slab_sample(const T* win, int nch, int nrow, int M, int ld, int cs, int c_off, int h, T* out, int i0,
+                              int nw, int sgn, int add, int interp, double inv_dx, const RigidState* rigid,
+                              hipStream_t st);
+// scalar potential sgn * S . v per target layer (one channel), groups as
+// launch_slab_mul
+template <typename T>
+hipError_t launch_slab_pot(const void* in, void* out, const T* kern, const SlabMulTable& tab, int nz, int D, int Lx,
+                           int Ly, int Kx, double sgn, const RigidState* rigid, hipStream_t st);
+// -grad of a sampled potential P[.][py][px] by four-point differences on
+// [3][ol][oy][ox], output (l, j, i) at P[l + o0][j + o0][i + o0]
+template <typename T>
+hipError_t launch_slab_potgrad(const T* P, int py, int px, int o0, int ol, int oy, int ox, T* out, int add, double dx,
+                               double dy, double dz, hipStream_t st);
 template <typename T>
 hipError_t launch_slab_add(int n, const T* src, T* dst, hipStream_t st);
 int slab_force_blocks(int ncell);

@@ -167,6 +167,64 @@ __global__ void __launch_bounds__(SLAB_THREADS)
   }
 }
 
+// Scalar-potential product (Eqs. 7-8): phi_t = sgn * sum_l S(t - l) . mhat_l
+// with S = (i sx, i sy, sz), one channel per target layer; the same groups,
+// phases and kernel layout as k_slab_mul.  Grid: (points / SLAB_THREADS,
+// groups, target layers).
+template <typename T>
+__global__ void __launch_bounds__(SLAB_THREADS)
+    k_slab_pot(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, const T* __restrict__ kern, SlabMulTable tab,
+               int nz, int D, int Lx, int Ly, int Kx, T sgn, const RigidState* __restrict__ rigid) {
+  const int plane = Ly * Kx;
+  const int q = (int)(blockIdx.x * SLAB_THREADS + threadIdx.x);
+  if (q >= plane) return;
+  const SlabGroup G = tab.g[blockIdx.y];
+  const int k = blockIdx.z;
+  if (k >= G.ntz) return;
+  const int ky = q / Kx, kx = q - ky * Kx;
+  const size_t ks = (size_t)plane * (2 * D + 1);
+  const cpx<T>* src = in + (size_t)G.src * 3 * nz * plane + q;
+  const int t = G.tz0 + k;
+  cpx<T> o = mk<T>(0, 0);
+  for (int l = 0; l < nz; ++l) {
+    const T* K = kern + (size_t)(t - l + D) * plane + q;
+    const T sx = K[0], sy = K[ks], sz = K[2 * ks];
+    const cpx<T> v0 = src[(size_t)(0 * nz + l) * plane], v1 = src[(size_t)(1 * nz + l) * plane],
+                 v2 = src[(size_t)(2 * nz + l) * plane];
+    const cpx<T> a = scale(v0, sx) + scale(v1, sy);
+    o = o + mk<T>(-a.y, a.x) + scale(v2, sz);
+  }
+  out[G.out + (size_t)k * plane + q] = cmul(o, slab_phase<T>(kx, ky, G.xs * rigid->s_int + G.xoff, G.yoff, Lx, Ly, sgn));
+}
+
+// H = -grad phi by four-point central differences (Sec. III.A) on an output
+// box [3][ol][oy][ox] from a sampled potential P[pl][py][px]: output point
+// (l, j, i) sits at P[l + o0][j + o0][i + o0] (o0 >= 2).  add: out += H.
+template <typename T>
+__global__ void __launch_bounds__(SLAB_THREADS)
+    k_slab_potgrad(const T* __restrict__ P, int py, int px, int o0, int ol, int oy, int ox, T* __restrict__ out,
+                   int add, T c12x, T c12y, T c12z) {
+  const int n = ol * oy * ox;
+  const int id = (int)(blockIdx.x * SLAB_THREADS + threadIdx.x);
+  if (id >= n) return;
+  const int i = id % ox, j = (id / ox) % oy, l = id / (ox * oy);
+  const size_t sy = px, sz = (size_t)px * py;
+  const T* p = P + (size_t)(l + o0) * sz + (size_t)(j + o0) * sy + (i + o0);
+  auto d4 = [&](size_t s) { return (p[-2 * (long long)s] - T(8) * p[-(long long)s] + T(8) * p[s] - p[2 * s]); };
+  const T hx = -d4(1) * c12x, hy = -d4(sy) * c12y, hz = -d4(sz) * c12z;
+  T* o = out + id;
+  const size_t N = (size_t)n;
+  if (add) {
+    o[0] += hx;
+    o[N] += hy;
+    o[2 * N] += hz;
+  } else {
+    o[0] = hx;
+    o[N] = hy;
+    o[2 * N] = hz;
+  }
+}
+
 // Whole-sample mirror index of k into [0, M) (M >= 2).
 __device__ __forceinline__ int slab_reflect(int k, int M) {
   if (k >= 0 && k < M) return k;
@@ -176,7 +234,7 @@ __device__ __forceinline__ int slab_reflect(int k, int M) {
   return k > M - 1 ? P - k : k;
 }
 
-// Window rows -> out[3][nrow][nw] at u = i + h + sgn * x_p, i = i0 .. i0 +
+// Window rows -> out[nch][nrow][nw] at u = i + h + sgn * x_p, i = i0 .. i0 +
 // nw - 1, x_p = x_s / dx - s_int of the current stage.  Window row r of
 // component a: the M elements from column cs * s_int + c_off of row
 // win[(a * nrow + r) * ld ...] (ld = M, cs = c_off = 0 for a window of its
@@ -191,8 +249,9 @@ __device__ __forceinline__ int slab_reflect(int k, int M) {
 constexpr int SLAB_KF_MAX = 30;
 template <typename T>
 __global__ void __launch_bounds__(SLAB_THREADS)
-    k_slab_sample(const T* __restrict__ win, int nrow, int M, int ld, int cs, int c_off, int h, T* __restrict__ out,
-                  int i0, int nw, int sgn, int add, int interp, double inv_dx, const RigidState* __restrict__ rigid) {
+    k_slab_sample(const T* __restrict__ win, int nch, int nrow, int M, int ld, int cs, int c_off, int h,
+                  T* __restrict__ out, int i0, int nw, int sgn, int add, int interp, double inv_dx,
+                  const RigidState* __restrict__ rigid) {
   constexpr int KF = sizeof(T) == 8 ? 30 : 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   static_assert(KF <= SLAB_KF_MAX, "LDS sized for SLAB_KF_MAX");
@@ -204,7 +263,7 @@ __global__ void __launch_bounds__(SLAB_THREADS)
   if (r >= nrow) return;
   if (threadIdx.x <= KF) w[threadIdx.x] = (T)(1.7320508075688772935 * pow(1.7320508075688772935 - 2.0, (double)threadIdx.x));
   const int c0 = cs * rigid->s_int + c_off;
-  for (int t = threadIdx.x; t < 3 * ME; t += SLAB_THREADS) {
+  for (int t = threadIdx.x; t < nch * ME; t += SLAB_THREADS) {
     const int a = t / ME, k = t - a * ME - KF;
     fe[t] = win[((size_t)a * nrow + r) * ld + c0 + slab_reflect(k, M)];
   }
@@ -212,7 +271,7 @@ __global__ void __launch_bounds__(SLAB_THREADS)
   const T* src = fe + KF;
   int stride = ME;
   if (interp == 0) {
-    for (int t = threadIdx.x; t < 3 * M; t += SLAB_THREADS) {
+    for (int t = threadIdx.x; t < nch * M; t += SLAB_THREADS) {
       const int a = t / M, k = t - a * M;
       const T* fa = fe + a * ME + KF + k;
       T s = w[0] * fa[0];
@@ -241,7 +300,7 @@ __global__ void __launch_bounds__(SLAB_THREADS)
     wb[2] = tt;
     wb[3] = T(0);
   }
-  for (int t = threadIdx.x; t < 3 * nw; t += SLAB_THREADS) {
+  for (int t = threadIdx.x; t < nch * nw; t += SLAB_THREADS) {
     const int a = t / nw, o = t - a * nw;
     const int k = k0 + i0 + o;
     const T* sa = src + a * stride;
@@ -365,16 +424,39 @@ hipError_t launch_slab_mul(const void* in, void* out, const T* kern, const SlabM
 size_t slab_sample_lds(int M, int esz) { return ((size_t)6 * M + 6 * SLAB_KF_MAX) * esz; }
 
 template <typename T>
-hipError_t launch_slab_sample(const T* win, int nrow, int M, int ld, int cs, int c_off, int h, T* out, int i0, int nw,
-                              int sgn, int add, int interp, double inv_dx, const RigidState* rigid, hipStream_t st) {
+hipError_t launch_slab_sample(const T* win, int nch, int nrow, int M, int ld, int cs, int c_off, int h, T* out, int i0,
+                              int nw, int sgn, int add, int interp, double inv_dx, const RigidState* rigid,
+                              hipStream_t st) {
   const size_t lds = slab_sample_lds(M, sizeof(T));
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_slab_sample<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_slab_sample<T>, dim3(nrow), dim3(SLAB_THREADS), lds, st, win, nrow, M, ld, cs, c_off, h, out,
-                     i0, nw, sgn, add, interp, inv_dx, rigid);
+  hipLaunchKernelGGL(k_slab_sample<T>, dim3(nrow), dim3(SLAB_THREADS), lds, st, win, nch, nrow, M, ld, cs, c_off, h,
+                     out, i0, nw, sgn, add, interp, inv_dx, rigid);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_slab_pot(const void* in, void* out, const T* kern, const SlabMulTable& tab, int nz, int D, int Lx,
+                           int Ly, int Kx, double sgn, const RigidState* rigid, hipStream_t st) {
+  const int plane = Ly * Kx;
+  int ntz = 1;
+  for (int g = 0; g < tab.n; ++g) ntz = tab.g[g].ntz > ntz ? tab.g[g].ntz : ntz;
+  dim3 grid((plane + SLAB_THREADS - 1) / SLAB_THREADS, tab.n, ntz);
+  hipLaunchKernelGGL(k_slab_pot<T>, grid, dim3(SLAB_THREADS), 0, st, (const cpx<T>*)in, (cpx<T>*)out, kern, tab, nz, D,
+                     Lx, Ly, Kx, (T)sgn, rigid);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_slab_potgrad(const T* P, int py, int px, int o0, int ol, int oy, int ox, T* out, int add, double dx,
+                               double dy, double dz, hipStream_t st) {
+  const int n = ol * oy * ox;
+  hipLaunchKernelGGL(k_slab_potgrad<T>, dim3((n + SLAB_THREADS - 1) / SLAB_THREADS), dim3(SLAB_THREADS), 0, st, P, py,
+                     px, o0, ol, oy, ox, out, add, (T)(1.0 / (12.0 * dx)), (T)(1.0 / (12.0 * dy)),
+                     (T)(1.0 / (12.0 * dz)));
   return hipGetLastError();
 }
 
@@ -408,8 +490,12 @@ hipError_t launch_slab_bdot(int n, int ncell, const T* hd, const T* m, const dou
   template hipError_t launch_slab_pack<T>(const void*, T*, int, int, hipStream_t);                              \
   template hipError_t launch_slab_mul<T>(const void*, void*, const T*, const SlabMulTable&, int, int, int, int,  \
                                          int, int, double, const RigidState*, hipStream_t);                    \
-  template hipError_t launch_slab_sample<T>(const T*, int, int, int, int, int, int, T*, int, int, int, int, int, \
-                                            double, const RigidState*, hipStream_t);                            \
+  template hipError_t launch_slab_sample<T>(const T*, int, int, int, int, int, int, int, T*, int, int, int, int, \
+                                            int, double, const RigidState*, hipStream_t);                       \
+  template hipError_t launch_slab_pot<T>(const void*, void*, const T*, const SlabMulTable&, int, int, int, int,  \
+                                         int, double, const RigidState*, hipStream_t);                          \
+  template hipError_t launch_slab_potgrad<T>(const T*, int, int, int, int, int, int, T*, int, double, double,    \
+                                             double, hipStream_t);                                              \
   template hipError_t launch_slab_add<T>(int, const T*, T*, hipStream_t);                                       \
   template hipError_t launch_slab_force<T>(const T*, const T*, T*, int, int, int, int, double, double, double,   \
                                            double*, hipStream_t);                                               \

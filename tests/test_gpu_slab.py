@@ -278,3 +278,39 @@ def test_thick_films_1000_steps_against_the_stored_oracle_run(prec):
         assert out[f"eddy{f}"] <= TOL_EDDY[prec], out
     mesh.close()
     print("  ", out, flush=True)
+
+
+@pytest.mark.parametrize("prec,nz,x_cells", [(64, 2, 1.37), (32, 2, 1.37), (64, 3, -2.61), (32, 3, 3.2)])
+def test_thick_potential_mode_terms_and_force(prec, nz, x_cells):
+    """Scalar-potential mode (cross_mode 1, gap 3): the other film's
+    potential on the windows, sampled and differenced (four points per axis);
+    every term of both films and the force against the oracle."""
+    print(f"slab potential p{prec} nz={nz} x={x_cells}", flush=True)
+    d, m = films(19, 13, nz, prec, gap=3, cross_mode=1, seed=nz + 20)
+    mesh, s = pair(d, m, Drive(mode=0, x0=x_cells * d.dx))
+    out = check_terms(mesh, s, prec)
+    mesh.close()
+    print("  ", {k: f"{v:.2e}" for k, v in out.items()}, flush=True)
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_thick_potential_mode_steps_with_eddy_currents(prec):
+    import torch
+    d, m = films(15, 10, 3, prec, gap=3, travel=4, sigma=1e6, cross_mode=1, state="stripes", seed=23,
+                 sor_sweeps=12)
+    drv = Drive(mode=1, v_d=1500.0, x0=0.91 * d.dx)
+    print(f"slab potential steps p{prec}", flush=True)
+    mesh, s = pair(d, m, drv)
+    dt, n = 1e-13, 4
+    mesh.step(dt, n)
+    torch.cuda.synchronize()
+    s.run(dt, n)
+    assert s.s_int == 1, "the slider crosses a cell boundary"
+    out = {}
+    for f in range(2):
+        out[f"m{f}"] = float(np.abs(mesh.get_m(f).cpu().numpy() - s.m[f]).max())
+        assert out[f"m{f}"] < TOL_M[prec], out
+        out[f"eddy{f}"] = rel(mesh.eval_heff(f, 32).cpu().numpy(), s.eddy.H[f])
+        assert out[f"eddy{f}"] <= TOL_EDDY[prec], out
+    mesh.close()
+    print("  ", out, flush=True)
