@@ -157,11 +157,13 @@ def test_cube_size_limits_are_checked_before_any_device_call(prec, shape):
     assert e.value.code == -1 and "three-dimensional" in str(e.value)
 
 
-def test_thick_films_run_in_the_direct_modes():
-    d = get_config("tiny_potential")["desc"].replace(nz=2)
+def test_thick_films_descriptor_rules():
+    """Thick films take the scalar potential only more than two cells apart
+    (as one-layer films) and open in-plane boundaries only."""
+    d = get_config("tiny_potential")["desc"].replace(nz=2, gap_cells=2)
     with pytest.raises(mmv.MMVError) as e:
         mmv.init_mesh(mmv.to_desc(d))
-    assert e.value.code == -1 and "direct modes" in str(e.value)
+    assert e.value.code == -1 and "gap_cells >= 3" in str(e.value)
     d = get_config("tiny")["desc"].replace(nz=2, pbc=1)
     with pytest.raises(mmv.MMVError) as e:
         mmv.init_mesh(mmv.to_desc(d))
