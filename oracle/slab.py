@@ -5,9 +5,12 @@ TEST INFRASTRUCTURE ONLY (part of the float64 oracle).
 
 Geometry.  As in oracle.sim, but each film is nx x ny x nz cells (nz >= 1)
 and the slider's lattice origin sits z_s = nz + gap layers above the base's.
-Open in-plane boundaries; every cross mode: the direct field with the cubic
-B-spline along x (cross_mode 0) or linear interpolation (2), and the scalar
-potential (1).
+Every cross mode: the direct field with the cubic B-spline along x
+(cross_mode 0) or linear interpolation (2), and the scalar potential (1).
+Open in-plane boundaries, or periodic ones (pbc, the direct modes and no
+eddy currents): every layer pair's sum then takes oracle.periodic's image-
+summed kernel, window points outside the period take their image's value,
+and exchange wraps (the paper's friction films, Sec. IV.B).
 
 Cross fields.  The base's exact lattice field is computed on the slider's
 window of base-lattice points x in [s_int - h, s_int + nx + h), rows
@@ -88,7 +91,8 @@ class SlabSystem(System):
 
     def __init__(self, desc, drive=None, m_init=None):
         assert desc.n_films == 2, "two films"
-        assert desc.pbc == 0, "open in-plane boundaries"
+        assert desc.pbc == 0 or (desc.cross_mode != 1 and desc.sigma == 0), \
+            "periodic thick films: direct modes, no eddy currents"
         # the base class would set up the single-magnet eddy state
         super().__init__(desc.replace(sigma=0.0), drive, m_init)
         self.desc = desc
@@ -97,6 +101,19 @@ class SlabSystem(System):
         self.hext_thick = [None, None]
 
     # ------------------------------------------------------------ windows
+    def self_op(self):
+        d = self.desc
+        if d.pbc:
+            return self._op(("self",), lambda: PeriodicLayers(d, (0, d.nx, 0, d.ny, 0, d.nz)))
+        return super().self_op()
+
+    def cross_op(self, direction, s_int):
+        d = self.desc
+        if d.pbc:
+            box = self.cross_box(direction, s_int)
+            return self._op(("cross", direction, s_int, d.cross_mode), lambda: PeriodicLayers(d, box))
+        return super().cross_op(direction, s_int)
+
     def cross_box(self, direction, s_int):
         d = self.desc
         h, zs, nwx = d.halo, d.z_s, d.nx + 2 * d.halo
@@ -190,8 +207,12 @@ class SlabSystem(System):
         d = self.desc
         hs = np.asarray(self.hext_thick[1], dtype=np.float64)
         assert hs.shape == (3, d.nz, d.ny, slider_width(d)), hs.shape
-        cols = s_int - d.halo + np.arange(d.nx + 2 * d.halo) + d.max_travel_cells + d.halo
-        assert cols.min() >= 0 and cols.max() < hs.shape[-1], "slider beyond the applied field's columns"
+        cols = s_int - d.halo + np.arange(d.nx + 2 * d.halo)
+        if d.pbc & 1:
+            cols = np.mod(cols, d.nx)
+        else:
+            cols = cols + d.max_travel_cells + d.halo
+            assert cols.min() >= 0 and cols.max() < hs.shape[-1], "slider beyond the applied field's columns"
         pre, samp = self.interpolant()
         return samp(pre(hs[..., cols]), self.positions(x, s_int, "b2s"))
 
@@ -207,6 +228,27 @@ class SlabSystem(System):
             for f in range(2):
                 out[f]["eddy"] = self.eddy.H[f].copy()
         return out, F
+
+
+class PeriodicLayers:
+    """The stray field of a thick film with periodic in-plane axes on a box
+    of target points (x0, nwx, y0, nwy, z0, nwz): target layer z0 + k takes
+    the sum over source layers l of oracle.periodic.FilmWindow at the layer
+    offset z0 + k - l; output (3, nwz, nwy, nwx) like WindowSum."""
+
+    def __init__(self, desc, box):
+        from .periodic import FilmWindow
+        x0, nwx, y0, nwy, z0, nwz = box
+        self.nwz, self.z0, self.nz = nwz, z0, desc.nz
+        self.win = {dz: FilmWindow(desc, x0, nwx, y0, nwy, dz)
+                    for dz in range(z0 - (desc.nz - 1), z0 + nwz)}
+
+    def __call__(self, m):
+        out = None
+        for k in range(self.nwz):
+            layer = sum(self.win[self.z0 + k - l](m[:, l:l + 1]) for l in range(self.nz))
+            out = layer if out is None else np.concatenate([out, layer], axis=1)
+        return out
 
 
 class FilmEddy:

@@ -297,3 +297,46 @@ def test_thick_potential_mode_one_layer_reduces_to_the_film_oracle():
     b = System(d, Drive(mode=FROZEN, x0=x), m).cross_fields(m[0], m[1], x, 1)
     for u, v in zip(a, b):
         assert rel(u, v) < 1e-12
+
+
+@pytest.mark.parametrize("pbc", [1, 2, 3])
+def test_periodic_thick_films_one_layer_reduces_to_the_film_oracle(pbc):
+    """Periodic thick films with nz = 1 are the pinned periodic film oracle."""
+    d, m = films(nx=8, ny=6, nz=1, gap=1, seed=pbc)
+    d = d.replace(pbc=pbc, pbc_images=2)
+    x = 1.37 * d.dx
+    a = SlabSystem(d, Drive(mode=FROZEN, x0=x), m)
+    b = System(d, Drive(mode=FROZEN, x0=x), m)
+    ta, Fa = a.field_terms()
+    tb, Fb = b.field_terms()
+    for f in range(2):
+        for k in ("exchange", "demag_self", "demag_cross"):
+            assert rel(ta[f][k], tb[f][k]) < 1e-12, (f, k)
+    assert np.abs(Fa - Fb).max() <= 1e-12 * np.abs(Fb).max()
+
+
+def test_periodic_thick_films_physics():
+    """A uniform magnetisation gives the same field in every cell of a layer
+    (translation invariance along both periodic axes); shifting the slider by
+    one period leaves every field and the force unchanged; with many images a
+    uniformly perpendicular periodic film tends to H_z = -Ms in its middle."""
+    d, m = films(nx=8, ny=6, nz=3, gap=1, seed=6)
+    d = d.replace(pbc=3, pbc_images=2, max_travel_cells=16)
+    up = [np.tile(np.array([0.1, -0.2, 0.97])[:, None, None, None], (1, 3, 6, 8))] * 2
+    s = SlabSystem(d, Drive(mode=FROZEN, x0=1.3 * d.dx), up)
+    t, _ = s.field_terms()
+    for f in range(2):
+        for k in ("demag_self", "demag_cross"):
+            h = t[f][k]
+            assert np.abs(h - h[:, :, :1, :1]).max() < 1e-9 * np.abs(h).max(), (f, k)
+    s1 = SlabSystem(d, Drive(mode=FROZEN, x0=1.3 * d.dx), m)
+    s2 = SlabSystem(d, Drive(mode=FROZEN, x0=(1.3 + d.nx) * d.dx), m)
+    t1, F1 = s1.field_terms()
+    t2, F2 = s2.field_terms()
+    for f in range(2):
+        assert rel(t2[f]["demag_cross"], t1[f]["demag_cross"]) < 1e-12
+    assert np.abs(F2 - F1).max() <= 1e-12 * np.abs(F1).max()
+    dz = d.replace(nx=6, ny=6, nz=1, pbc_images=60, dx=2e-9, dy=2e-9, dz=2e-9)
+    zup = [np.tile(np.array([0.0, 0.0, 1.0])[:, None, None, None], (1, 1, 6, 6))] * 2
+    hz = SlabSystem(dz, Drive(mode=FROZEN), zup).field_terms()[0][0]["demag_self"][2]
+    assert abs(hz.mean() / dz.Ms + 1.0) < 0.02
