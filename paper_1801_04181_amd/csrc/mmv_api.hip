@@ -238,7 +238,9 @@ int validate(const mmv_mesh_desc* d) {
   if (d->pbc < 0 || d->pbc > 3) return fail(MMV_EINVAL, "pbc must be 0..3 (bit 0 = x, bit 1 = y)");
   if (d->pbc_images < 0 || d->pbc_images > 1024) return fail(MMV_EINVAL, "pbc_images must be in [0, 1024]");
   if (d->pbc) {
-    if (d->nz != 1) return fail(MMV_EINVAL, "pbc: periodic boundaries need films one cell thick (nz == 1)");
+    if (d->nz != 1 && !(d->n_films == 2 && d->sigma == 0.0))
+      return fail(MMV_EINVAL, "pbc: periodic boundaries need films one cell thick (nz == 1), or two thicker films "
+                              "without eddy currents");
     if (d->cross_mode != 0) return fail(MMV_EINVAL, "pbc: periodic boundaries run in the direct mode (cross_mode 0)");
     if ((d->pbc & 1) && (d->nx % 2 || !smooth2357(d->nx)))
       return fail(MMV_EINVAL, "pbc: a periodic x needs nx even and {2,3,5,7}-smooth (the transform length)");
@@ -869,7 +871,7 @@ int build_kernels_slab(mmv_mesh* h) {
         // tensor spectra carry -Ms (Eq. 6); S spectra enter the eddy sums bare
         const double sc = kind == SLAB_KIND_TENSOR ? -d.Ms * inv : inv;
         err = launch_kernel_real((double*)grid, h->Lx, h->Ly, kind, comp, (double)dz, d.dx, d.dy, d.dz, d.rc_cells,
-                                 sc, 0, 0, h->st);
+                                 sc, d.pbc, d.pbc_images, h->st);
         if (err == hipSuccess)
           err = launch_row_fwd<double>((const double*)grid, s1, h->Ly, h->Lx, h->N2x, h->Kx, h->px, twxd, twpd, h->st);
         if (err == hipSuccess)
@@ -957,11 +959,14 @@ int init_slab(mmv_mesh* h) {
   h->tab_p.n = 2;
   h->tab_p.g[0] = SlabGroup{0, zs - 3, nz + 6, 1, -hl, -3, 6LL * nz * P};
   h->tab_p.g[1] = SlabGroup{1, -zs - 2, nz + 4, -1, -hl, -2, (6LL * nz + nz + 6) * P};
+  // a periodic x keeps the windows' period unshifted (columns from 0; the
+  // sampling reads them modulo nx), a periodic y the rows of the period
+  const bool px = (d.pbc & 1) != 0, py = (d.pbc & 2) != 0;
   h->tab_t.n = 4;
   h->tab_t.g[0] = SlabGroup{0, 0, nz, 0, 0, 0, 0};
   h->tab_t.g[1] = SlabGroup{1, 0, nz, 0, 0, 0, 3LL * nz * P};
-  h->tab_t.g[2] = SlabGroup{1, -zs, nz, -1, -hl, 0, 6LL * nz * P};
-  h->tab_t.g[3] = SlabGroup{0, zs - 1, nz + 2, 1, -hl, -1, 9LL * nz * P};
+  h->tab_t.g[2] = SlabGroup{1, -zs, nz, px ? 0 : -1, px ? 0 : -hl, 0, 6LL * nz * P};
+  h->tab_t.g[3] = SlabGroup{0, zs - 1, nz + 2, px ? 0 : 1, px ? 0 : -hl, py ? 0 : -1, 9LL * nz * P};
   h->tab_e.n = 4;
   h->tab_e.g[0] = SlabGroup{0, 0, nz, 0, 0, 0, 0};
   h->tab_e.g[1] = SlabGroup{1, 0, nz, 0, 0, 0, 3LL * nz * P};
@@ -987,8 +992,10 @@ int init_slab(mmv_mesh* h) {
   const int nmax = std::max(nx, std::max(ny, nz));
   h->sor_omega = d.sor_omega > 0 ? d.sor_omega : 2.0 / (1.0 + sin(M_PI / nmax));
   if ((rc = init_dct<T>(h))) return rc;
-  h->rp_hot.travel = h->rp_force.travel = d.max_travel_cells;
+  // a periodic x lets the slider travel without bound
+  h->rp_hot.travel = h->rp_force.travel = px ? (1 << 30) : d.max_travel_cells;
   h->rp_hot.halo = h->rp_force.halo = hl;
+  c.pbc = d.pbc;
   return MMV_OK;
 }
 
@@ -1035,45 +1042,59 @@ int slab_fields(mmv_mesh* h, const T* m, bool self_on, bool cross_on, bool zee_o
     if (!self_on) HIPCHK(hipMemsetAsync(h->hd, 0, 2 * F * sizeof(T), h->st));
     // slider side: samples at i = -3 .. nx + 2, then H on the force stencil
     // (stencil point (l', j', i') at window layer l' + 2, row j' + 2, sample i' + 2)
-    HIPCHK(launch_slab_sample<T>((const T*)h->pot_w[0], 1, L1 * R1, M, M, 0, 0, h->d.halo, (T*)h->pot_s[0], -3, nx + 6,
-                                 1, 0, 0, idx, h->rigid, h->st));
+    HIPCHK(launch_slab_sample<T>((const T*)h->pot_w[0], slab_rows(1, L1 * R1, M), h->d.halo, (T*)h->pot_s[0], -3,
+                                 nx + 6, 1, 0, 0, idx, h->rigid, h->st));
     HIPCHK(launch_slab_potgrad<T>((const T*)h->pot_s[0], R1, nx + 6, 2, nz + 2, ny + 2, nx + 2, (T*)h->stencil, 0,
                                   h->d.dx, h->d.dy, h->d.dz, h->st));
     if (cross_on) {
       // base side: samples at i = -2 .. nx + 1; base cell (k, j, i) at window
       // layer k + 2, row j + 2, sample i + 2
-      HIPCHK(launch_slab_sample<T>((const T*)h->pot_w[1], 1, L2 * R2, M, M, 0, 0, h->d.halo, (T*)h->pot_s[1], -2,
+      HIPCHK(launch_slab_sample<T>((const T*)h->pot_w[1], slab_rows(1, L2 * R2, M), h->d.halo, (T*)h->pot_s[1], -2,
                                    nx + 4, -1, 0, 0, idx, h->rigid, h->st));
       HIPCHK(launch_slab_potgrad<T>((const T*)h->pot_s[1], R2, nx + 4, 2, nz, ny, nx, (T*)h->hd, 1, h->d.dx, h->d.dy,
                                     h->d.dz, h->st));
     }
   } else {
-  HIPCHK(launch_slab_mul<T>(h->specM, h->specP, (const T*)h->kern_t, h->tab_t, nz, h->sD, h->Lx, h->Ly, Kx, 0, 1.0,
-                            h->rigid, h->st));
-  HIPCHK(launch_fft_axis<T>(h->specP, pI, 9 * nz, Kx, 0, h->Ly, (long long)P, ny, (long long)ny * Kx, h->py, h->twy,
-                            true, h->st));
-  HIPCHK(launch_fft_axis<T>((char*)h->specP + cs * 9 * nz * P, pI + cs * 9 * (size_t)nz * ny * Kx, 3 * (nz + 2), Kx, 0,
-                            h->Ly, (long long)P, ny + 2, (long long)(ny + 2) * Kx, h->py, h->twy, true, h->st));
-  HIPCHK(launch_row_inv<T>(pI, (T*)h->hd, 6 * nz * ny, R, nx, h->N2x, Kx, h->px, h->twx, h->twp, h->st));
-  HIPCHK(launch_row_inv<T>(pI + cs * 6 * (size_t)nz * ny * Kx, (T*)h->win_s2b, 3 * nz * ny, R, M, h->N2x, Kx, h->px,
-                           h->twx, h->twp, h->st));
-  HIPCHK(launch_row_inv<T>(pI + cs * 9 * (size_t)nz * ny * Kx, (T*)h->win_b2s, 3 * (nz + 2) * (ny + 2), R, M, h->N2x,
-                           Kx, h->px, h->twx, h->twp, h->st));
-  if (!self_on) HIPCHK(hipMemsetAsync(h->hd, 0, 2 * F * sizeof(T), h->st));
-  if (cross_on)
-    HIPCHK(launch_slab_sample<T>((const T*)h->win_s2b, 3, nz * ny, M, M, 0, 0, h->d.halo, (T*)h->hd, 0, nx, -1, 1, interp,
-                                 idx, h->rigid, h->st));
-  HIPCHK(launch_slab_sample<T>((const T*)h->win_b2s, 3, (nz + 2) * (ny + 2), M, M, 0, 0, h->d.halo, (T*)h->stencil, -1,
-                               nx + 2, 1, 0, interp, idx, h->rigid, h->st));
+    // window widths and rows: a periodic x keeps the period (the windows'
+    // columns are read modulo nx), a periodic y the ny rows of the period
+    // (the force's rows -1 and ny are rows ny - 1 and 0)
+    const bool px = (h->d.pbc & 1) != 0, py = (h->d.pbc & 2) != 0;
+    const int WC = px ? nx : M, WR = py ? ny : ny + 2;
+    HIPCHK(launch_slab_mul<T>(h->specM, h->specP, (const T*)h->kern_t, h->tab_t, nz, h->sD, h->Lx, h->Ly, Kx, 0, 1.0,
+                              h->rigid, h->st));
+    HIPCHK(launch_fft_axis<T>(h->specP, pI, 9 * nz, Kx, 0, h->Ly, (long long)P, ny, (long long)ny * Kx, h->py, h->twy,
+                              true, h->st));
+    HIPCHK(launch_fft_axis<T>((char*)h->specP + cs * 9 * nz * P, pI + cs * 9 * (size_t)nz * ny * Kx, 3 * (nz + 2), Kx,
+                              0, h->Ly, (long long)P, WR, (long long)WR * Kx, h->py, h->twy, true, h->st));
+    HIPCHK(launch_row_inv<T>(pI, (T*)h->hd, 6 * nz * ny, R, nx, h->N2x, Kx, h->px, h->twx, h->twp, h->st));
+    HIPCHK(launch_row_inv<T>(pI + cs * 6 * (size_t)nz * ny * Kx, (T*)h->win_s2b, 3 * nz * ny, R, WC, h->N2x, Kx,
+                             h->px, h->twx, h->twp, h->st));
+    HIPCHK(launch_row_inv<T>(pI + cs * 9 * (size_t)nz * ny * Kx, (T*)h->win_b2s, 3 * (nz + 2) * WR, R, WC, h->N2x, Kx,
+                             h->px, h->twx, h->twp, h->st));
+    if (!self_on) HIPCHK(hipMemsetAsync(h->hd, 0, 2 * F * sizeof(T), h->st));
+    // base side: lattice columns -s_int - h + k of the slider's field; slider
+    // side: s_int - h + k of the base's (periodic x), rows -1..ny
+    const int hl = h->d.halo;
+    const SlabRows rs{3, nz * ny, nz * ny, nz * ny, nz * ny, 0, M, WC, px ? -1 : 0, px ? -hl : 0, px ? nx : 0};
+    const SlabRows rb{3, (nz + 2) * (ny + 2), (nz + 2) * WR, ny + 2, WR, py ? -1 : 0, M, WC, px ? 1 : 0, px ? -hl : 0,
+                      px ? nx : 0};
+    if (cross_on)
+      HIPCHK(launch_slab_sample<T>((const T*)h->win_s2b, rs, hl, (T*)h->hd, 0, nx, -1, 1, interp, idx, h->rigid, h->st));
+    HIPCHK(launch_slab_sample<T>((const T*)h->win_b2s, rb, hl, (T*)h->stencil, -1, nx + 2, 1, 0, interp, idx, h->rigid,
+                                 h->st));
   }
   HIPCHK(launch_slab_force<T>((const T*)h->stencil, m + F, (T*)h->hd + F, nx, ny, nz, cross_on ? 1 : 0, h->d.dx,
                               h->d.dy, h->d.dz, h->partial, h->st));
   if (zee_on && h->slab_hext[0]) HIPCHK(launch_slab_add<T>((int)F, (const T*)h->slab_hext[0], (T*)h->hd, h->st));
   if (zee_on && h->slab_hext[1]) {
     // the slider's window of the frame rows starts at column s_int + travel
-    const int W = nx + 2 * (h->d.max_travel_cells + h->d.halo);
-    HIPCHK(launch_slab_sample<T>((const T*)h->slab_hext[1], 3, nz * ny, M, W, 1, h->d.max_travel_cells, h->d.halo,
-                                 (T*)h->hd + F, 0, nx, 1, 1, interp, idx, h->rigid, h->st));
+    // (periodic x: the frame is the period, the window from s_int - halo)
+    const bool px = (h->d.pbc & 1) != 0;
+    const int W = px ? nx : nx + 2 * (h->d.max_travel_cells + h->d.halo);
+    const SlabRows rz{3, nz * ny, nz * ny, nz * ny, nz * ny, 0, M, W, 1,
+                      px ? -h->d.halo : h->d.max_travel_cells, px ? nx : 0};
+    HIPCHK(launch_slab_sample<T>((const T*)h->slab_hext[1], rz, h->d.halo, (T*)h->hd + F, 0, nx, 1, 1, interp, idx,
+                                 h->rigid, h->st));
   }
   return MMV_OK;
 }
@@ -1100,10 +1121,10 @@ int slab_s_sum(mmv_mesh* h, const T* src, T* dst, double sgn) {
   HIPCHK(launch_row_inv<T>(pI + cs * 6 * (size_t)nz * ny * Kx, (T*)h->win_e, 6 * nz * ny, R, M, h->N2x, Kx, h->px,
                            h->twx, h->twp, h->st));
   const size_t wsz = 3 * (size_t)nz * ny * M;
-  HIPCHK(launch_slab_sample<T>((const T*)h->win_e, 3, nz * ny, M, M, 0, 0, h->d.halo, dst, 0, nx, -1, 1, interp,
+  HIPCHK(launch_slab_sample<T>((const T*)h->win_e, slab_rows(3, nz * ny, M), h->d.halo, dst, 0, nx, -1, 1, interp,
                                1.0 / h->d.dx, h->rigid, h->st));
-  HIPCHK(launch_slab_sample<T>((const T*)h->win_e + wsz, 3, nz * ny, M, M, 0, 0, h->d.halo, dst + F, 0, nx, 1, 1, interp,
-                               1.0 / h->d.dx, h->rigid, h->st));
+  HIPCHK(launch_slab_sample<T>((const T*)h->win_e + wsz, slab_rows(3, nz * ny, M), h->d.halo, dst + F, 0, nx, 1, 1,
+                               interp, 1.0 / h->d.dx, h->rigid, h->st));
   return MMV_OK;
 }
 
@@ -1140,7 +1161,7 @@ TickArgs slab_tick(mmv_mesh* h) {
   a.force_scale = MU0 * h->d.Ms * h->d.dx * h->d.dy * h->d.dz;
   a.dx = h->d.dx;
   a.ntask = slab_force_blocks(h->nx * h->ny * h->nz);
-  a.travel = h->d.max_travel_cells;
+  a.travel = h->rp_hot.travel;
   a.scheme = 0;
   a.ctrl = nullptr;
   return a;
@@ -2277,10 +2298,11 @@ int init_mesh(const mmv_mesh_desc* d, void* hip_stream, mmv_handle* out) {
     h->nz = d->nz;
     // the windows reach one row past the films (direct mode: the force's
     // rows) or three (the potential's four-point differences and the force)
-    const int lx_min = 2 * (d->nx + d->halo + d->max_travel_cells),
-              ly_min = 2 * (d->ny + (d->cross_mode == 1 ? 3 : 1));
-    h->Lx = d->fft_lx ? d->fft_lx : next_smooth(lx_min, true);
-    h->Ly = d->fft_ly ? d->fft_ly : next_smooth(ly_min, false);
+    // a periodic axis is transformed over its period
+    const int lx_min = (d->pbc & 1) ? d->nx : 2 * (d->nx + d->halo + d->max_travel_cells),
+              ly_min = (d->pbc & 2) ? d->ny : 2 * (d->ny + (d->cross_mode == 1 ? 3 : 1));
+    h->Lx = d->fft_lx ? d->fft_lx : ((d->pbc & 1) ? d->nx : next_smooth(lx_min, true));
+    h->Ly = d->fft_ly ? d->fft_ly : ((d->pbc & 2) ? d->ny : next_smooth(ly_min, false));
     if (h->Lx < lx_min || h->Lx % 2 || !smooth2357(h->Lx) || h->Ly < ly_min || !smooth2357(h->Ly)) {
       delete h;
       return fail(MMV_EINVAL, "fft_lx must be even, {2,3,5,7}-smooth and >= " + std::to_string(lx_min) +
@@ -2747,7 +2769,7 @@ int set_hext_field(mmv_handle h, int film, const void* field) {
   if (h->slab) {
     // thick films: [3][nz][ny][nx] for film 0, [3][nz][ny][nx + 2 (travel +
     // halo)] for the slider's layers; read by slab_fields
-    const int w = film == 0 ? h->nx : h->nx + 2 * (h->d.max_travel_cells + h->d.halo);
+    const int w = (film == 0 || (h->d.pbc & 1)) ? h->nx : h->nx + 2 * (h->d.max_travel_cells + h->d.halo);
     const size_t bytes = (size_t)3 * h->nz * h->ny * w * h->esz;
     h->slab_hext[film] = nullptr;
     if (field) {

@@ -225,6 +225,7 @@ struct CubeParams {
   int term_mask;
   double dx, dy, dz;
   double pref_ex, pref_an, u[3], hext[3], gam, alpha, dt;
+  int pbc;  // periodic x (bit 0) and y (bit 1) neighbours in the exchange
 };
 
 // (i, j, k) of cell id on an nx x ny x nz grid of fewer than 2^31 cells
@@ -273,10 +274,21 @@ __global__ void __launch_bounds__(256)
       ey += (ms[N + nb] - my) * w;
       ez += (ms[2 * N + nb] - mz) * w;
     };
-    if (i > 0) add(id - sx, ix2);
-    if (i < p.nx - 1) add(id + sx, ix2);
-    if (j > 0) add(id - sy, iy2);
-    if (j < p.ny - 1) add(id + sy, iy2);
+    if (p.pbc & 1) {
+      add(id - i + (i == 0 ? p.nx - 1 : i - 1), ix2);
+      add(id - i + (i == p.nx - 1 ? 0 : i + 1), ix2);
+    } else {
+      if (i > 0) add(id - sx, ix2);
+      if (i < p.nx - 1) add(id + sx, ix2);
+    }
+    if (p.pbc & 2) {
+      const size_t row0 = id - (size_t)j * sy;
+      add(row0 + (size_t)(j == 0 ? p.ny - 1 : j - 1) * sy, iy2);
+      add(row0 + (size_t)(j == p.ny - 1 ? 0 : j + 1) * sy, iy2);
+    } else {
+      if (j > 0) add(id - sy, iy2);
+      if (j < p.ny - 1) add(id + sy, iy2);
+    }
     if (k > 0) add(id - sz, iz2);
     if (k < p.nz - 1) add(id + sz, iz2);
     hx += (T)p.pref_ex * ex;
@@ -862,6 +874,7 @@ hipError_t launch_stage3(const CubeLaunch& c, int mode, int stage, int mask, dou
   p.gam = c.gam;
   p.alpha = c.alpha;
   p.dt = dt;
+  p.pbc = c.pbc;
   const size_t N = (size_t)c.nx * c.ny * c.nz;
   hipLaunchKernelGGL(k_stage3<T>, grid1(N), dim3(256), 0, st, p, ms, m0, mnext, acc, hd, he, hout, flags, tick,
                      dmstep);

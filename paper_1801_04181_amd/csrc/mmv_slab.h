@@ -31,12 +31,20 @@ template <typename T>
 hipError_t launch_slab_mul(const void* in, void* out, const T* kern, const SlabMulTable& tab, int nz, int D, int Lx,
                            int Ly, int Kx, int mode, double sgn, const RigidState* rigid, hipStream_t st);
 size_t slab_sample_lds(int M, int esz);
-// nch channels of window rows of length M starting at column cs * s_int +
-// c_off of rows ld apart (ld = M, cs = c_off = 0: rows of their own)
+// The rows of a sampling launch: nch channels of nrow output rows; output
+// row r of a block of orows reads input row (r + roff) mod wrows of the
+// block (nrow_in input rows per channel), whose window is the M elements from
+// column cs * s_int + c_off (rows ld apart), modulo period when period > 0.
+struct SlabRows {
+  int nch, nrow, nrow_in;
+  int orows, wrows, roff;
+  int M, ld, cs, c_off, period;
+};
+// rows of their own (one block, identity row map, no column offset)
+inline SlabRows slab_rows(int nch, int nrow, int M) { return SlabRows{nch, nrow, nrow, nrow, nrow, 0, M, M, 0, 0, 0}; }
 template <typename T>
-hipError_t launch_slab_sample(const T* win, int nch, int nrow, int M, int ld, int cs, int c_off, int h, T* out, int i0,
-                              int nw, int sgn, int add, int interp, double inv_dx, const RigidState* rigid,
-                              hipStream_t st);
+hipError_t launch_slab_sample(const T* win, const SlabRows& R, int h, T* out, int i0, int nw, int sgn, int add,
+                              int interp, double inv_dx, const RigidState* rigid, hipStream_t st);
 // scalar potential sgn * S . v per target layer (one channel), groups as
 // launch_slab_mul
 template <typename T>

@@ -235,10 +235,11 @@ __device__ __forceinline__ int slab_reflect(int k, int M) {
 }
 
 // Window rows -> out[nch][nrow][nw] at u = i + h + sgn * x_p, i = i0 .. i0 +
-// nw - 1, x_p = x_s / dx - s_int of the current stage.  Window row r of
-// component a: the M elements from column cs * s_int + c_off of row
-// win[(a * nrow + r) * ld ...] (ld = M, cs = c_off = 0 for a window of its
-// own; a frame row of the applied field otherwise).
+// nw - 1, x_p = x_s / dx - s_int of the current stage.  Output row r (in
+// blocks of R.orows) reads input row (r + R.roff) mod R.wrows of the same
+// block (R.nrow_in input rows per channel); its window is the M elements
+// from column c0 = R.cs * s_int + R.c_off of that row (ld apart), taken
+// modulo R.period when it is set (a periodic x: the row holds one period).
 // interp 0: cubic B-spline; its coefficients solve the mirror-bounded
 // system (c_{k-1} + 4 c_k + c_{k+1}) / 6 = f_k, i.e. the symmetric filter
 // sqrt(3) z^|j| (z = sqrt(3) - 2) on the mirror-periodic extension of the
@@ -249,12 +250,12 @@ __device__ __forceinline__ int slab_reflect(int k, int M) {
 constexpr int SLAB_KF_MAX = 30;
 template <typename T>
 __global__ void __launch_bounds__(SLAB_THREADS)
-    k_slab_sample(const T* __restrict__ win, int nch, int nrow, int M, int ld, int cs, int c_off, int h,
-                  T* __restrict__ out, int i0, int nw, int sgn, int add, int interp, double inv_dx,
-                  const RigidState* __restrict__ rigid) {
+    k_slab_sample(const T* __restrict__ win, SlabRows R, int h, T* __restrict__ out, int i0, int nw, int sgn, int add,
+                  int interp, double inv_dx, const RigidState* __restrict__ rigid) {
   constexpr int KF = sizeof(T) == 8 ? 30 : 16;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   static_assert(KF <= SLAB_KF_MAX, "LDS sized for SLAB_KF_MAX");
+  const int nch = R.nch, nrow = R.nrow, M = R.M;
   const int ME = M + 2 * KF;
   T* fe = reinterpret_cast<T*>(smem_raw);  // [3][M + 2 KF]: f_{k - KF}, mirror-extended
   T* c = fe + 3 * ME;                       // [3][M]
@@ -262,10 +263,19 @@ __global__ void __launch_bounds__(SLAB_THREADS)
   const int r = blockIdx.x;
   if (r >= nrow) return;
   if (threadIdx.x <= KF) w[threadIdx.x] = (T)(1.7320508075688772935 * pow(1.7320508075688772935 - 2.0, (double)threadIdx.x));
-  const int c0 = cs * rigid->s_int + c_off;
+  const int blk = r / R.orows;
+  int ri = (r - blk * R.orows + R.roff) % R.wrows;
+  if (ri < 0) ri += R.wrows;
+  const int rin = blk * R.wrows + ri;
+  const int c0 = R.cs * rigid->s_int + R.c_off;
   for (int t = threadIdx.x; t < nch * ME; t += SLAB_THREADS) {
     const int a = t / ME, k = t - a * ME - KF;
-    fe[t] = win[((size_t)a * nrow + r) * ld + c0 + slab_reflect(k, M)];
+    int col = c0 + slab_reflect(k, M);
+    if (R.period > 0) {
+      col %= R.period;
+      if (col < 0) col += R.period;
+    }
+    fe[t] = win[((size_t)a * R.nrow_in + rin) * R.ld + col];
   }
   __syncthreads();
   const T* src = fe + KF;
@@ -424,17 +434,16 @@ hipError_t launch_slab_mul(const void* in, void* out, const T* kern, const SlabM
 size_t slab_sample_lds(int M, int esz) { return ((size_t)6 * M + 6 * SLAB_KF_MAX) * esz; }
 
 template <typename T>
-hipError_t launch_slab_sample(const T* win, int nch, int nrow, int M, int ld, int cs, int c_off, int h, T* out, int i0,
-                              int nw, int sgn, int add, int interp, double inv_dx, const RigidState* rigid,
-                              hipStream_t st) {
-  const size_t lds = slab_sample_lds(M, sizeof(T));
+hipError_t launch_slab_sample(const T* win, const SlabRows& R, int h, T* out, int i0, int nw, int sgn, int add,
+                              int interp, double inv_dx, const RigidState* rigid, hipStream_t st) {
+  const size_t lds = slab_sample_lds(R.M, sizeof(T));
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)k_slab_sample<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_slab_sample<T>, dim3(nrow), dim3(SLAB_THREADS), lds, st, win, nch, nrow, M, ld, cs, c_off, h,
-                     out, i0, nw, sgn, add, interp, inv_dx, rigid);
+  hipLaunchKernelGGL(k_slab_sample<T>, dim3(R.nrow), dim3(SLAB_THREADS), lds, st, win, R, h, out, i0, nw, sgn, add,
+                     interp, inv_dx, rigid);
   return hipGetLastError();
 }
 
@@ -490,8 +499,8 @@ hipError_t launch_slab_bdot(int n, int ncell, const T* hd, const T* m, const dou
   template hipError_t launch_slab_pack<T>(const void*, T*, int, int, hipStream_t);                              \
   template hipError_t launch_slab_mul<T>(const void*, void*, const T*, const SlabMulTable&, int, int, int, int,  \
                                          int, int, double, const RigidState*, hipStream_t);                    \
-  template hipError_t launch_slab_sample<T>(const T*, int, int, int, int, int, int, int, T*, int, int, int, int, \
-                                            int, double, const RigidState*, hipStream_t);                       \
+  template hipError_t launch_slab_sample<T>(const T*, const SlabRows&, int, T*, int, int, int, int, int, double, \
+                                            const RigidState*, hipStream_t);                                    \
   template hipError_t launch_slab_pot<T>(const void*, void*, const T*, const SlabMulTable&, int, int, int, int,  \
                                          int, double, const RigidState*, hipStream_t);                          \
   template hipError_t launch_slab_potgrad<T>(const T*, int, int, int, int, int, int, T*, int, double, double,    \

@@ -314,3 +314,49 @@ def test_thick_potential_mode_steps_with_eddy_currents(prec):
         assert out[f"eddy{f}"] <= TOL_EDDY[prec], out
     mesh.close()
     print("  ", out, flush=True)
+
+
+@pytest.mark.parametrize("prec,pbc,x_cells", [(64, 3, 1.37), (32, 3, 1.37), (64, 1, 9.6), (32, 2, -2.4),
+                                              (64, 2, 0.0)])
+def test_periodic_thick_films_terms_and_force(prec, pbc, x_cells):
+    """Periodic in-plane boundaries (one image on each side): the transforms
+    run over the periods, the windows' columns wrap (a slider beyond the
+    period included) and the force's rows -1 and ny are rows ny - 1 and 0."""
+    print(f"slab periodic p{prec} pbc={pbc} x={x_cells}", flush=True)
+    d, m = films(16, 10, 3, prec, gap=1, seed=pbc + 40, pbc=pbc, pbc_images=1)
+    mesh, s = pair(d, m, Drive(mode=0, x0=x_cells * d.dx))
+    out = check_terms(mesh, s, prec)
+    mesh.close()
+    print("  ", {k: f"{v:.2e}" for k, v in out.items()}, flush=True)
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_periodic_thick_films_steps(prec):
+    """RK4 steps of periodic thick films (pbc = 3) with a spring-driven slider
+    crossing a cell boundary and a non-uniform applied field in both."""
+    import torch
+    from workloads.configs import slider_mass_damping
+    d, m = films(16, 10, 3, prec, gap=1, seed=44, state="stripes", pbc=3, pbc_images=1)
+    mass, gv = slider_mass_damping(16, 10, 0.005)
+    drv = Drive(mode=2, v_d=1500.0, k=0.005, mass=mass, gamma_v=gv, x0=0.93 * d.dx, v0=1500.0)
+    rng = np.random.default_rng(45)
+    hb = 1e4 * rng.standard_normal((3, 3, 10, 16))
+    hs = 1e4 * rng.standard_normal((3, 3, 10, 16))
+    print(f"slab periodic steps p{prec}", flush=True)
+    mesh, s = pair(d, m, drv)
+    mesh.set_hext_field(0, hb)
+    mesh.set_hext_field(1, hs)
+    s.hext_thick = [hb, hs]
+    dt, n = 1e-13, 4
+    mesh.step(dt, n)
+    torch.cuda.synchronize()
+    s.run(dt, n)
+    st = mesh.state()
+    assert s.s_int == 1 and math.floor(st["x"] / d.dx) == 1
+    out = {"x": abs(st["x"] - s.x) / d.dx}
+    for f in range(2):
+        out[f"m{f}"] = float(np.abs(mesh.get_m(f).cpu().numpy() - s.m[f]).max())
+        assert out[f"m{f}"] < TOL_M[prec], out
+    assert out["x"] < (1e-6 if prec == 32 else 1e-11), out
+    mesh.close()
+    print("  ", out, flush=True)
