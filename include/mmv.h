@@ -96,8 +96,9 @@ typedef struct {
   int pbc;              /* periodic in-plane axes (Sec. III.A end, Sec. IV.B):
                            bit 0 = x, bit 1 = y; 0 = open.  Film meshes
                            (nz == 1) in the direct mode without eddy
-                           currents.  Along a periodic axis the transform
-                           length is the period (nx even and {2,3,5,7}-smooth,
+                           currents, or two thicker films in the same mode
+                           without eddy currents (sigma 0).  Along a
+                           periodic axis the transform length is the period (nx even and {2,3,5,7}-smooth,
                            ny {2,3,5,7}-smooth), the kernel of a displacement
                            is summed over its minimum image and pbc_images
                            repetitions of the period on each side, the
@@ -138,7 +139,11 @@ typedef struct {
  * Two films more than one cell thick (n_films 2, nz > 1; Sec. II.A end,
  * III.B, IV.C-D): the thick-film path.  Every cross mode (the scalar
  * potential's windows reach three rows and layers past the films, Ly >=
- * 2 (ny + 3)), open in-plane boundaries (pbc 0).  Each field
+ * 2 (ny + 3)).  Periodic in-plane boundaries (pbc) in the direct mode
+ * (cross_mode 0) without eddy currents: the layer kernels summed over the
+ * images, the transform along a periodic axis over the period, windows
+ * unshifted along it (the sampler wraps their columns and rows modulo the
+ * period) and exchange wrapping.  Each field
  * is a sum over the source film's layers of in-plane convolutions with the
  * kernel of each layer offset (FFT lengths as for one-layer films, fft_lz
  * unused): the films' own fields, the base's field on the slider's window
