@@ -26,6 +26,10 @@ Per time step, from the magnetisation at the start of the step:
    with the k = 0 mode (the gauge) set to zero.
    E_irrot,a(i) = -(g+ + g-) / 2 with g the face gradients, a surface face
    taking E_sol,a(i).
+   A conductor periodic along an in-plane axis (pbc, the films of the
+   friction geometry) has no surface across the period: its cells are
+   neighbours through it, the Laplacian and the gradients wrap, and only
+   the faces of the open axes carry E_sol . n.
 4. J = sigma (E_sol + E_irrot) and H_eddy(r_i) = sum_j J_j x S(r_i - r_j)
    (Biot-Savart with the same kernel), held through the step's RK stages.
 
@@ -58,6 +62,13 @@ def cross_kernels(desc, sign):
     return WindowSum(ker, (desc.nz, desc.ny, desc.nx), 3)
 
 
+def periodic_axes(desc):
+    """Array axes (of [nz][ny][nx]) along which the conductor is periodic:
+    x (axis 2) for pbc bit 0, y (axis 1) for bit 1."""
+    pbc = int(getattr(desc, "pbc", 0))
+    return {ax for bit, ax in ((1, 2), (2, 1)) if pbc & bit}
+
+
 def default_sweeps(desc):
     """Sweeps per step (0: 40); negative: the exact solve."""
     return desc.sor_sweeps if desc.sor_sweeps != 0 else 40
@@ -65,19 +76,29 @@ def default_sweeps(desc):
 
 def neumann_solve(desc, r):
     """The zero-mean solution of L phi = r (L = laplacian below) for a
-    zero-mean r, by the cosine diagonalisation of L (module docstring)."""
+    zero-mean r, by the diagonalisation of L (module docstring): the cosine
+    basis along an open axis, the Fourier basis exp(2 pi i k i / n),
+    eigenvalue (2 cos(2 pi k / n) - 2) / d^2, along a periodic one."""
     from scipy.fft import dctn, idctn
+    per = periodic_axes(desc)
+    opn = tuple(a for a in range(3) if a not in per)
     nz, ny, nx = r.shape
     lam = np.zeros(r.shape)
     for axis, (n, d) in enumerate(((nz, desc.dz), (ny, desc.dy), (nx, desc.dx))):
-        ev = (2.0 * np.cos(np.pi * np.arange(n) / n) - 2.0) / (d * d)
+        f = 2.0 if axis in per else 1.0
+        ev = (2.0 * np.cos(f * np.pi * np.arange(n) / n) - 2.0) / (d * d)
         sh = [1, 1, 1]
         sh[axis] = n
         lam = lam + ev.reshape(sh)
-    c = dctn(r, type=2, norm="ortho")
+    c = dctn(r, type=2, norm="ortho", axes=opn) if opn else np.array(r, dtype=np.float64)
+    if per:
+        c = np.fft.fftn(c, axes=tuple(sorted(per)))
     c[0, 0, 0] = 0.0
     lam[0, 0, 0] = 1.0
-    return idctn(c / lam, type=2, norm="ortho")
+    c = c / lam
+    if per:
+        c = np.real(np.fft.ifftn(c, axes=tuple(sorted(per))))
+    return idctn(c, type=2, norm="ortho", axes=opn) if opn else c
 
 
 def default_omega(desc):
@@ -90,7 +111,10 @@ def default_omega(desc):
 def neumann_rhs(desc, Esol):
     """Right-hand side r of sum_interior (phi_j - phi_i)/d^2 = r_i."""
     r = np.zeros(Esol.shape[1:])
+    per = periodic_axes(desc)
     for a, (axis, d) in enumerate(((2, desc.dx), (1, desc.dy), (0, desc.dz))):
+        if axis in per:
+            continue  # no surface across a period
         n = r.shape[axis]
         lo = [slice(None)] * 3
         hi = [slice(None)] * 3
@@ -104,7 +128,11 @@ def neumann_rhs(desc, Esol):
 
 def laplacian(desc, phi):
     out = np.zeros_like(phi)
+    per = periodic_axes(desc)
     for axis, d in ((2, desc.dx), (1, desc.dy), (0, desc.dz)):
+        if axis in per:
+            out += (np.roll(phi, 1, axis=axis) + np.roll(phi, -1, axis=axis) - 2.0 * phi) / (d * d)
+            continue
         n = phi.shape[axis]
         if n < 2:
             continue
@@ -121,11 +149,13 @@ def laplacian(desc, phi):
 def neighbour_weight(desc, shape):
     """sum over interior faces of 1/d^2, per cell."""
     w = np.zeros(shape)
+    per = periodic_axes(desc)
     for axis, d in ((2, desc.dx), (1, desc.dy), (0, desc.dz)):
         n = shape[axis]
         cnt = np.full(n, 2.0)
-        cnt[0] -= 1
-        cnt[-1] -= 1
+        if axis not in per:
+            cnt[0] -= 1
+            cnt[-1] -= 1
         sh = [1, 1, 1]
         sh[axis] = n
         w = w + cnt.reshape(sh) / (d * d)
@@ -135,6 +165,8 @@ def neighbour_weight(desc, shape):
 def sor(desc, phi, r, sweeps, omega):
     """Red-black SOR sweeps (red = (i+j+k) even first), then zero mean."""
     nz, ny, nx = phi.shape
+    for axis in periodic_axes(desc):
+        assert phi.shape[axis] % 2 == 0, "red-black colouring needs even periods"
     k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     colour = (i + j + k) % 2
     W = neighbour_weight(desc, phi.shape)
@@ -162,8 +194,13 @@ def residual(desc, phi, r):
 def irrotational(desc, phi, Esol):
     """E_irrot = -(g+ + g-)/2 per axis; a surface face gradient is E_sol,a."""
     E = np.zeros_like(Esol)
+    per = periodic_axes(desc)
     for a, (axis, d) in enumerate(((2, desc.dx), (1, desc.dy), (0, desc.dz))):
         n = phi.shape[axis]
+        if axis in per:
+            g = (np.roll(phi, -1, axis=axis) - phi) / d   # face i + 1/2, wrapping
+            E[a] = -0.5 * (g + np.roll(g, 1, axis=axis))
+            continue
         gp = np.array(Esol[a], copy=True)
         gm = np.array(Esol[a], copy=True)
         if n >= 2:

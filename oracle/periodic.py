@@ -16,16 +16,23 @@ summed; this module takes (reading in the design notes):
 * the field of a source on target points along a periodic axis is then the
   circular convolution over one period, and target points outside the
   period take the value of their image (the copy of Sec. III.A);
-* along an open axis the zero-padded linear convolution is kept.
+* along an open axis the zero-padded linear convolution is kept;
+* the eddy-current sums (Eq. 9 and the field of the currents) over a
+  periodic film take the same image sum of the scalar-potential kernel S of
+  Eq. 8 (FilmSWindow).
 
 Pins (tests/test_oracle_periodic.py): the FFT route equals a brute-force loop
 over cell pairs and images; a uniform magnetisation gives a field that is the
 same in every cell (translation invariance, exact); a uniform perpendicular
 film periodic in both axes tends to the infinite-film field H_z = -Ms as the
 images grow; shifting the slider by one period leaves its fields unchanged.
+The S x v window equals brute-force loops over cells, components and
+images, and a uniform dB/dt along z in a film periodic in x and y has no
+solenoidal field (tests/test_oracle_periodic_eddy.py).
 """
 import numpy as np
 from .newell import demag_tensor
+from .potential_kernel import potential_kernel
 
 COMPS = ("xx", "yy", "zz", "xy", "xz", "yz")
 _PAIRS = {(0, 0): "xx", (0, 1): "xy", (0, 2): "xz", (1, 0): "xy",
@@ -45,6 +52,20 @@ def periodic_kernel(desc, comp, ix, iy, dz_cells):
     """K_per for one tensor component at integer displacements (ix, iy) in
     cells and layer offset dz_cells (broadcast arrays); axes flagged in
     desc.pbc are periodic with desc.pbc_images images on each side."""
+    return periodic_sum(desc, lambda X, Y, Z: demag_tensor(comp, X, Y, Z, desc.dx, desc.dy, desc.dz,
+                                                           desc.rc_cells), ix, iy, dz_cells)
+
+
+def periodic_s(desc, comp, ix, iy, dz_cells):
+    """The same image sum of the scalar-potential kernel's component comp
+    (0, 1, 2 = S_x, S_y, S_z of Eq. 8), the kernel of the eddy-current sums."""
+    return periodic_sum(desc, lambda X, Y, Z: potential_kernel(X, Y, Z, desc.dx, desc.dy, desc.dz)[comp],
+                        ix, iy, dz_cells)
+
+
+def periodic_sum(desc, kernel, ix, iy, dz_cells):
+    """sum over the images of kernel(X, Y, Z) [displacements in m] at the
+    minimum images of the integer displacements (ix, iy) (module docstring)."""
     P = int(desc.pbc_images)
     px = bool(desc.pbc & 1)
     py = bool(desc.pbc & 2)
@@ -72,7 +93,7 @@ def periodic_kernel(desc, comp, ix, iy, dz_cells):
             Y = (np.asarray(wy)[..., None, None] + qy[None, :] * desc.ny) * desc.dy
             X, Y = np.broadcast_arrays(X, Y)
             Z = np.full(X.shape, dz_cells * desc.dz)
-            acc = demag_tensor(comp, X, Y, Z, desc.dx, desc.dy, desc.dz, desc.rc_cells).sum(axis=(-2, -1))
+            acc = kernel(X, Y, Z).sum(axis=(-2, -1))
             out = out + wgt * acc
     return out
 
@@ -102,10 +123,16 @@ class FilmWindow:
             self.gy = np.arange(y0 - (ny - 1), y0 + nwy)
         IY, IX = np.meshgrid(self.gy, self.gx, indexing="ij")
         self.khat = {}
-        for c in COMPS:
-            k = -desc.Ms * periodic_kernel(desc, c, IX, IY, dz_cells)
+        for (a, b), k in self.kernels(IX, IY, dz_cells).items():
             if np.any(k):
-                self.khat[c] = np.fft.fft2(k)
+                self.khat[(a, b)] = np.fft.fft2(k)
+
+    def kernels(self, IX, IY, dz_cells):
+        """The kernel from source component b to output component a, keyed
+        (a, b), on the displacement grid: -Ms N_ab."""
+        desc = self.desc
+        comp = {c: -desc.Ms * periodic_kernel(desc, c, IX, IY, dz_cells) for c in COMPS}
+        return {(a, b): comp[_PAIRS[(a, b)]] for a in range(3) for b in range(3)}
 
     def __call__(self, m):
         desc = self.desc
@@ -122,14 +149,52 @@ class FilmWindow:
         for a in range(3):
             acc = 0.0
             for b in range(3):
-                c = _PAIRS[(a, b)]
-                if c in self.khat:
-                    acc = acc + self.khat[c] * shat[b]
+                if (a, b) in self.khat:
+                    acc = acc + self.khat[(a, b)] * shat[b]
             if isinstance(acc, float):
                 continue
             full = np.real(np.fft.ifft2(acc))
             out[a, 0] = full[np.ix_(oy, ox)]
         return out
+
+
+# Levi-Civita symbol: (a, b, c) -> eps_abc
+EPS = {(0, 1, 2): 1.0, (1, 2, 0): 1.0, (2, 0, 1): 1.0,
+       (0, 2, 1): -1.0, (2, 1, 0): -1.0, (1, 0, 2): -1.0}
+
+
+class FilmSWindow(FilmWindow):
+    """out_a = sign * sum_j (S_per(p - r_j) x v_j)_a of a one-layer source
+    on the same targets as FilmWindow: the eddy-current sums (Eq. 9 with
+    sign +1 for E_sol = S x dB/dt, and the Biot-Savart field of the
+    currents with sign -1) over a film periodic in plane."""
+
+    def __init__(self, desc, x0, nwx, y0, nwy, dz_cells, sign):
+        self.sign = sign
+        super().__init__(desc, x0, nwx, y0, nwy, dz_cells)
+
+    def kernels(self, IX, IY, dz_cells):
+        S = [periodic_s(self.desc, b, IX, IY, dz_cells) for b in range(3)]
+        ker = {}
+        for (a, b, c), e in EPS.items():
+            ker[(a, c)] = ker.get((a, c), 0.0) + self.sign * e * S[b]
+        return ker
+
+
+def brute_force_s(desc, v, x0, nwx, y0, nwy, dz_cells, sign):
+    """FilmSWindow by loops over target points, source cells and the three
+    components of the cross product, the kernel of each displacement taken
+    from periodic_s."""
+    nx, ny = desc.nx, desc.ny
+    out = np.zeros((3, 1, nwy, nwx))
+    for ty in range(nwy):
+        for tx in range(nwx):
+            for j in range(ny):
+                for i in range(nx):
+                    S = np.array([float(periodic_s(desc, b, x0 + tx - i, y0 + ty - j, dz_cells))
+                                  for b in range(3)])
+                    out[:, 0, ty, tx] += sign * np.cross(S, v[:, 0, j, i])
+    return out
 
 
 def brute_force(desc, m, x0, nwx, y0, nwy, dz_cells):

@@ -7,10 +7,13 @@ Geometry.  As in oracle.sim, but each film is nx x ny x nz cells (nz >= 1)
 and the slider's lattice origin sits z_s = nz + gap layers above the base's.
 Every cross mode: the direct field with the cubic B-spline along x
 (cross_mode 0) or linear interpolation (2), and the scalar potential (1).
-Open in-plane boundaries, or periodic ones (pbc, the direct modes and no
-eddy currents): every layer pair's sum then takes oracle.periodic's image-
-summed kernel, window points outside the period take their image's value,
-and exchange wraps (the paper's friction films, Sec. IV.B).
+Open in-plane boundaries, or periodic ones (pbc, the direct modes): every
+layer pair's sum then takes oracle.periodic's image-summed kernel, window
+points outside the period take their image's value, and exchange wraps
+(the paper's friction films, Sec. IV.B; its eddy-current friction run,
+Sec. IV.C, keeps that geometry).  With eddy currents the eddy sums take the
+image-summed S kernel the same way and each film's Neumann problem is
+periodic along those axes (oracle.eddy).
 
 Cross fields.  The base's exact lattice field is computed on the slider's
 window of base-lattice points x in [s_int - h, s_int + nx + h), rows
@@ -91,8 +94,7 @@ class SlabSystem(System):
 
     def __init__(self, desc, drive=None, m_init=None):
         assert desc.n_films == 2, "two films"
-        assert desc.pbc == 0 or (desc.cross_mode != 1 and desc.sigma == 0), \
-            "periodic thick films: direct modes, no eddy currents"
+        assert desc.pbc == 0 or desc.cross_mode != 1, "periodic thick films: the direct modes"
         # the base class would set up the single-magnet eddy state
         super().__init__(desc.replace(sigma=0.0), drive, m_init)
         self.desc = desc
@@ -234,14 +236,19 @@ class PeriodicLayers:
     """The stray field of a thick film with periodic in-plane axes on a box
     of target points (x0, nwx, y0, nwy, z0, nwz): target layer z0 + k takes
     the sum over source layers l of oracle.periodic.FilmWindow at the layer
-    offset z0 + k - l; output (3, nwz, nwy, nwx) like WindowSum."""
+    offset z0 + k - l; output (3, nwz, nwy, nwx) like WindowSum.  With a
+    sign, the eddy-current sum sign * S x v instead (FilmSWindow)."""
 
-    def __init__(self, desc, box):
-        from .periodic import FilmWindow
+    def __init__(self, desc, box, sign=None):
+        from .periodic import FilmWindow, FilmSWindow
         x0, nwx, y0, nwy, z0, nwz = box
         self.nwz, self.z0, self.nz = nwz, z0, desc.nz
-        self.win = {dz: FilmWindow(desc, x0, nwx, y0, nwy, dz)
-                    for dz in range(z0 - (desc.nz - 1), z0 + nwz)}
+
+        def window(dz):
+            if sign is None:
+                return FilmWindow(desc, x0, nwx, y0, nwy, dz)
+            return FilmSWindow(desc, x0, nwx, y0, nwy, dz, sign)
+        self.win = {dz: window(dz) for dz in range(z0 - (desc.nz - 1), z0 + nwz)}
 
     def __call__(self, m):
         out = None
@@ -275,9 +282,12 @@ class FilmEddy:
         return self.H[0]
 
     def self_ops(self):
+        d = self.desc
+        if self._self is None and d.pbc:
+            box = (0, d.nx, 0, d.ny, 0, d.nz)
+            self._self = (PeriodicLayers(d, box, +1.0), PeriodicLayers(d, box, -1.0))
         if self._self is None:
-            self._self = (_eddy.cross_kernels(self.desc, +1.0),
-                          _eddy.cross_kernels(self.desc, -1.0))
+            self._self = (_eddy.cross_kernels(d, +1.0), _eddy.cross_kernels(d, -1.0))
         return self._self
 
     def cross_box(self, direction, s_int):
@@ -289,6 +299,8 @@ class FilmEddy:
 
     def cross_op(self, sign, direction, s_int):
         key = (sign, direction, s_int)
+        if key not in self._cross and self.desc.pbc:
+            self._cross[key] = PeriodicLayers(self.desc, self.cross_box(direction, s_int), sign)
         if key not in self._cross:
             self._cross[key] = s_cross_window(self.desc, self.cross_box(direction, s_int), sign)
         return self._cross[key]
