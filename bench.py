@@ -28,9 +28,9 @@ METRIC = "cell-updates/s per LLG step; surrogate+batched vs plain at ≤1e-3 H e
 # device copy of known size, keyed by kernel and by the hash of the kernel
 # sources they were taken on: a changed kernel reports null.
 TRAFFIC = {
-    "col": {"source": "716e67d9d903", "bytes": 16144120},
-    "row_stage": {"source": "716e67d9d903", "bytes": 19429031},
-    "batch_step": {"source": "716e67d9d903", "bytes": 3064741616},
+    "col": {"source": "06dd3518653b", "bytes": 16149150},
+    "row_stage": {"source": "06dd3518653b", "bytes": 19418985},
+    "batch_step": {"source": "06dd3518653b", "bytes": 3064962902},
 }
 KERNEL_SOURCES = ("paper_1801_04181_amd/csrc/mmv_kernels.hip", "paper_1801_04181_amd/csrc/mmv_device.h",
                   "paper_1801_04181_amd/csrc/mmv_internal.h")
@@ -342,7 +342,7 @@ def cube_report(steps=40, warmup=4):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps
             mesh.close()
-            name = {True: "eddy", "exact": "eddy_exact_solve", False: "no_eddy"}[eddy]
+            name = {True: "eddy", "exact": "eddy_exact_solve", False: "no_eddy", "periodic": "eddy_periodic"}[eddy]
             out[f"fp{prec}_{name}"] = {"ms_per_step": ms, "cell_updates_per_s": cells / (ms * 1e-3)}
     return out
 
@@ -353,8 +353,10 @@ def eddy_films_report(steps=20, warmup=2, cpu=True):
     eddy currents in both films (sigma = 1e6 S/m: dB/dt, the E_sol sums with
     the other film's interpolated part, 40 red-black SOR sweeps per film,
     J x S), with the exact cosine-basis Neumann solve instead of the sweeps,
-    and without (sigma = 0): HIP events around `steps` RK4 steps on the
-    mesh's stream.  The oracle (float64 CPU) times one step."""
+    without (sigma = 0), and with the sweeps in films periodic in x and y
+    (one image on each side; the transform lengths are the periods, 128):
+    HIP events around `steps` RK4 steps on the mesh's stream.  The oracle
+    (float64 CPU) times one step."""
     import torch
     import paper_1801_04181_amd as mmv
     from workloads import get_config, initial_state
@@ -367,9 +369,11 @@ def eddy_films_report(steps=20, warmup=2, cpu=True):
                        "spring drive 2 m/s, RK4 dt 1e-13 s",
            "cells": cells, "steps": steps}
     for prec in (32, 64):
-        for eddy in (True, "exact", False):
+        for eddy in (True, "exact", False, "periodic"):
             d = d0.replace(precision=prec, sigma=d0.sigma if eddy else 0.0,
                            sor_sweeps=-1 if eddy == "exact" else d0.sor_sweeps)
+            if eddy == "periodic":
+                d = d.replace(pbc=3, pbc_images=1)
             mesh = mmv.Mesh(d, drv, m)
             mesh.step(dt, warmup)
             torch.cuda.synchronize()
@@ -380,7 +384,7 @@ def eddy_films_report(steps=20, warmup=2, cpu=True):
             e1.record(mesh.stream)
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / steps
-            name = {True: "eddy", "exact": "eddy_exact_solve", False: "no_eddy"}[eddy]
+            name = {True: "eddy", "exact": "eddy_exact_solve", False: "no_eddy", "periodic": "eddy_periodic"}[eddy]
             out[f"fp{prec}_{name}"] = {"ms_per_step": ms, "cell_updates_per_s": cells / (ms * 1e-3),
                                        "fft": list(mesh.fft_lengths()[:2])}
             mesh.close()

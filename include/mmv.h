@@ -89,15 +89,16 @@ typedef struct {
                            -1: the Neumann problem solved exactly in the
                            cosine basis that diagonalises it (DCT-II along
                            x, y, z, division by the eigenvalues, inverse;
-                           nx, ny, nz {2,3,5,7}-smooth, MMV_EINVAL
-                           otherwise)                                     */
+                           nx, ny, nz {2,3,5,7}-smooth, open in-plane
+                           boundaries; MMV_EINVAL otherwise)              */
   double sor_omega;     /* eddy SOR factor (0: 2/(1+sin(pi/n_max)))           */
   int fft_lx, fft_ly, fft_lz; /* FFT lengths; 0 = smallest admissible       */
   int pbc;              /* periodic in-plane axes (Sec. III.A end, Sec. IV.B):
                            bit 0 = x, bit 1 = y; 0 = open.  Film meshes
                            (nz == 1) in the direct mode without eddy
                            currents, or two thicker films in the same mode
-                           without eddy currents (sigma 0).  Along a
+                           (with eddy currents: SOR sweeps, sor_sweeps >= 0,
+                           and ny even for a periodic y).  Along a
                            periodic axis the transform length is the period (nx even and {2,3,5,7}-smooth,
                            ny {2,3,5,7}-smooth), the kernel of a displacement
                            is summed over its minimum image and pbc_images
@@ -140,10 +141,12 @@ typedef struct {
  * III.B, IV.C-D): the thick-film path.  Every cross mode (the scalar
  * potential's windows reach three rows and layers past the films, Ly >=
  * 2 (ny + 3)).  Periodic in-plane boundaries (pbc) in the direct mode
- * (cross_mode 0) without eddy currents: the layer kernels summed over the
- * images, the transform along a periodic axis over the period, windows
- * unshifted along it (the sampler wraps their columns and rows modulo the
- * period) and exchange wrapping.  Each field
+ * (cross_mode 0): the layer kernels summed over the images, the transform
+ * along a periodic axis over the period, windows unshifted along it (the
+ * sampler wraps their columns and rows modulo the period) and exchange
+ * wrapping; with eddy currents the S sums take the image-summed kernel and
+ * each film's Neumann problem wraps along the periods (no surface there),
+ * by the SOR sweeps.  Each field
  * is a sum over the source film's layers of in-plane convolutions with the
  * kernel of each layer offset (FFT lengths as for one-layer films, fft_lz
  * unused): the films' own fields, the base's field on the slider's window

@@ -238,9 +238,14 @@ int validate(const mmv_mesh_desc* d) {
   if (d->pbc < 0 || d->pbc > 3) return fail(MMV_EINVAL, "pbc must be 0..3 (bit 0 = x, bit 1 = y)");
   if (d->pbc_images < 0 || d->pbc_images > 1024) return fail(MMV_EINVAL, "pbc_images must be in [0, 1024]");
   if (d->pbc) {
-    if (d->nz != 1 && !(d->n_films == 2 && d->sigma == 0.0))
-      return fail(MMV_EINVAL, "pbc: periodic boundaries need films one cell thick (nz == 1), or two thicker films "
-                              "without eddy currents");
+    if (d->nz != 1 && d->n_films != 2)
+      return fail(MMV_EINVAL, "pbc: periodic boundaries need films one cell thick (nz == 1), or two thicker films");
+    if (d->sigma > 0.0 && (d->pbc & 2) && d->ny % 2)
+      return fail(MMV_EINVAL, "pbc: eddy currents with a periodic y need ny even (red-black colouring over the "
+                              "period)");
+    if (d->sigma > 0.0 && d->sor_sweeps < 0)
+      return fail(MMV_EINVAL, "pbc: eddy currents in periodic films take the SOR sweeps (sor_sweeps >= 0); the exact "
+                              "solve is for open boundaries");
     if (d->cross_mode != 0) return fail(MMV_EINVAL, "pbc: periodic boundaries run in the direct mode (cross_mode 0)");
     if ((d->pbc & 1) && (d->nx % 2 || !smooth2357(d->nx)))
       return fail(MMV_EINVAL, "pbc: a periodic x needs nx even and {2,3,5,7}-smooth (the transform length)");
@@ -970,8 +975,8 @@ int init_slab(mmv_mesh* h) {
   h->tab_e.n = 4;
   h->tab_e.g[0] = SlabGroup{0, 0, nz, 0, 0, 0, 0};
   h->tab_e.g[1] = SlabGroup{1, 0, nz, 0, 0, 0, 3LL * nz * P};
-  h->tab_e.g[2] = SlabGroup{1, -zs, nz, -1, -hl, 0, 6LL * nz * P};
-  h->tab_e.g[3] = SlabGroup{0, zs, nz, 1, -hl, 0, 9LL * nz * P};
+  h->tab_e.g[2] = SlabGroup{1, -zs, nz, px ? 0 : -1, px ? 0 : -hl, 0, 6LL * nz * P};
+  h->tab_e.g[3] = SlabGroup{0, zs, nz, px ? 0 : 1, px ? 0 : -hl, 0, 9LL * nz * P};
   CubeLaunch& c = h->cl;
   c.nx = nx;
   c.ny = ny;
@@ -1118,13 +1123,20 @@ int slab_s_sum(mmv_mesh* h, const T* src, T* dst, double sgn) {
   HIPCHK(launch_fft_axis<T>(h->specP, pI, 12 * nz, Kx, 0, h->Ly, (long long)P, ny, (long long)ny * Kx, h->py, h->twy,
                             true, h->st));
   HIPCHK(launch_row_inv<T>(pI, dst, 6 * nz * ny, R, nx, h->N2x, Kx, h->px, h->twx, h->twp, h->st));
-  HIPCHK(launch_row_inv<T>(pI + cs * 6 * (size_t)nz * ny * Kx, (T*)h->win_e, 6 * nz * ny, R, M, h->N2x, Kx, h->px,
+  // a periodic x keeps the windows' period (columns read modulo nx from
+  // -s_int - h on the base and s_int - h on the slider)
+  const bool px = (h->d.pbc & 1) != 0;
+  const int WC = px ? nx : M, hl = h->d.halo;
+  HIPCHK(launch_row_inv<T>(pI + cs * 6 * (size_t)nz * ny * Kx, (T*)h->win_e, 6 * nz * ny, R, WC, h->N2x, Kx, h->px,
                            h->twx, h->twp, h->st));
-  const size_t wsz = 3 * (size_t)nz * ny * M;
-  HIPCHK(launch_slab_sample<T>((const T*)h->win_e, slab_rows(3, nz * ny, M), h->d.halo, dst, 0, nx, -1, 1, interp,
-                               1.0 / h->d.dx, h->rigid, h->st));
-  HIPCHK(launch_slab_sample<T>((const T*)h->win_e + wsz, slab_rows(3, nz * ny, M), h->d.halo, dst + F, 0, nx, 1, 1,
-                               interp, 1.0 / h->d.dx, h->rigid, h->st));
+  const size_t wsz = 3 * (size_t)nz * ny * WC;
+  const int nr = nz * ny;
+  const SlabRows rs{3, nr, nr, nr, nr, 0, M, WC, px ? -1 : 0, px ? -hl : 0, px ? nx : 0};
+  const SlabRows rb{3, nr, nr, nr, nr, 0, M, WC, px ? 1 : 0, px ? -hl : 0, px ? nx : 0};
+  HIPCHK(launch_slab_sample<T>((const T*)h->win_e, rs, hl, dst, 0, nx, -1, 1, interp, 1.0 / h->d.dx, h->rigid,
+                               h->st));
+  HIPCHK(launch_slab_sample<T>((const T*)h->win_e + wsz, rb, hl, dst + F, 0, nx, 1, 1, interp, 1.0 / h->d.dx,
+                               h->rigid, h->st));
   return MMV_OK;
 }
 

@@ -371,10 +371,11 @@ __global__ void k_bdot(size_t N, const T* dm, const T* hdm, T* bdot, double mu0,
 }
 
 // Right-hand side of sum_interior (phi_j - phi_i)/d^2 = r_i (surface faces
-// carry the normal component of E_sol), plus per-block partial sums.
+// carry the normal component of E_sol; a periodic in-plane axis, pbc bit 0 =
+// x, 1 = y, has no surface), plus per-block partial sums.
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_sor_rhs(int nx, int ny, int nz, double dx, double dy, double dz, const T* __restrict__ es,
+    k_sor_rhs(int nx, int ny, int nz, double dx, double dy, double dz, int pbc, const T* __restrict__ es,
               T* __restrict__ r, double* __restrict__ part) {
   __shared__ double red[256];
   const size_t N = (size_t)nx * ny * nz;
@@ -384,10 +385,14 @@ __global__ void __launch_bounds__(256)
     int i, j, k;
     cell_ijk(id, nx, ny, i, j, k);
     const double ex = es[id], ey = es[N + id], ez = es[2 * N + id];
-    if (i == nx - 1) v -= ex / dx;
-    if (i == 0) v += ex / dx;
-    if (j == ny - 1) v -= ey / dy;
-    if (j == 0) v += ey / dy;
+    if (!(pbc & 1)) {
+      if (i == nx - 1) v -= ex / dx;
+      if (i == 0) v += ex / dx;
+    }
+    if (!(pbc & 2)) {
+      if (j == ny - 1) v -= ey / dy;
+      if (j == 0) v += ey / dy;
+    }
     if (k == nz - 1) v -= ez / dz;
     if (k == 0) v += ez / dz;
     r[id] = (T)v;
@@ -440,11 +445,12 @@ __global__ void k_shift(size_t N, const T* src, T* dst, const double* __restrict
 }
 
 // Residual of the Neumann problem after the sweeps: per cell
-// res_i = sum over interior faces (phi_j - phi_i) / d^2 - r_i; each block
-// writes its float64 sums of res^2 and r^2 (part[2 b], part[2 b + 1]).
+// res_i = sum over interior faces (phi_j - phi_i) / d^2 - r_i (faces through
+// a periodic axis' period included); each block writes its float64 sums of
+// res^2 and r^2 (part[2 b], part[2 b + 1]).
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_sor_residual(int nx, int ny, int nz, double dx, double dy, double dz, const T* __restrict__ phi,
+    k_sor_residual(int nx, int ny, int nz, double dx, double dy, double dz, int pbc, const T* __restrict__ phi,
                    const T* __restrict__ r, double* __restrict__ part) {
   __shared__ double red[2][256];
   const size_t N = (size_t)nx * ny * nz;
@@ -455,10 +461,15 @@ __global__ void __launch_bounds__(256)
     cell_ijk(id, nx, ny, i, j, k);
     const double p = phi[id];
     double s = 0.0;
+    const size_t rx = (size_t)(nx - 1), ry = (size_t)(ny - 1) * nx;  // a period's wrap
     if (i > 0) s += wx * ((double)phi[id - 1] - p);
+    else if (pbc & 1) s += wx * ((double)phi[id + rx] - p);
     if (i < nx - 1) s += wx * ((double)phi[id + 1] - p);
+    else if (pbc & 1) s += wx * ((double)phi[id - rx] - p);
     if (j > 0) s += wy * ((double)phi[id - nx] - p);
+    else if (pbc & 2) s += wy * ((double)phi[id + ry] - p);
     if (j < ny - 1) s += wy * ((double)phi[id + nx] - p);
+    else if (pbc & 2) s += wy * ((double)phi[id - ry] - p);
     if (k > 0) s += wz * ((double)phi[id - (size_t)nx * ny] - p);
     if (k < nz - 1) s += wz * ((double)phi[id + (size_t)nx * ny] - p);
     const double res = s - (double)r[id];
@@ -487,7 +498,8 @@ __global__ void __launch_bounds__(256)
 // over its face neighbours inside the mesh (w = 1/d^2 of the axis; a mesh
 // face contributes nothing, the Neumann condition being in r); all cells of
 // one colour update from the other colour's values, so the order within a
-// half-sweep does not matter.
+// half-sweep does not matter.  Along a periodic in-plane axis (even period)
+// the box holds the wrapped cells, which update like interior ones.
 constexpr int SOR_THREADS = 256;
 constexpr int SOR_T = 8;                    // tile edge
 constexpr int SOR_S = 2;                    // sweeps per launch at most
@@ -500,7 +512,7 @@ constexpr int SOR_D = SOR_T + 2 * SOR_H;    // loaded box edge
 // only the other colour and each updated cell's own old value.
 template <typename T, int E>
 __device__ __forceinline__ void sor_half(T* sp, const T* sr, int colour, int ox, int oy, int oz, int nx, int ny,
-                                         int nz, T wx, T wy, T wz, T om) {
+                                         int nz, int pbc, T wx, T wy, T wz, T om) {
   constexpr int D = SOR_D, D2 = D * D, O = (SOR_D - E) / 2, EH = E / 2;
   constexpr int NC = E * E * E / 2, NU = (NC + SOR_THREADS - 1) / SOR_THREADS;
   static_assert(E % 2 == 0 && O >= 1, "the region and its neighbours lie in the box");
@@ -514,8 +526,10 @@ __device__ __forceinline__ void sor_half(T* sp, const T* sr, int colour, int ox,
     const int j = oy + lj, k = oz + lk;
     const int li = O + 2 * xh + ((colour - ox - O - j - k) & 1);
     const int i = ox + li;
-    const bool upd = t < NC && i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz;
-    const bool x0 = i > 0, x1 = i < nx - 1, y0 = j > 0, y1 = j < ny - 1, z0 = k > 0, z1 = k < nz - 1;
+    const bool px = (pbc & 1) != 0, py = (pbc & 2) != 0;
+    const bool upd = t < NC && (px || (i >= 0 && i < nx)) && (py || (j >= 0 && j < ny)) && k >= 0 && k < nz;
+    const bool x0 = px || i > 0, x1 = px || i < nx - 1, y0 = py || j > 0, y1 = py || j < ny - 1, z0 = k > 0,
+               z1 = k < nz - 1;
     const int c = upd ? lk * D2 + lj * D + li : D2 + D + 1;  // an in-box cell for the lanes past the region
     const T px0 = sp[c - 1], px1 = sp[c + 1], py0 = sp[c - D], py1 = sp[c + D], pz0 = sp[c - D2],
             pz1 = sp[c + D2], pc = sp[c], rc = sr[c];
@@ -547,11 +561,11 @@ __device__ __forceinline__ void sor_half(T* sp, const T* sr, int colour, int ox,
 // of edge SOR_T + 2 (2 NSW - 1 - h), the cells the tile still depends on,
 // which reads the region of half-sweep h - 1 (the whole box for h = 0).
 template <typename T, int NSW, int HS>
-__device__ __forceinline__ void sor_halves(T* sp, const T* sr, int ox, int oy, int oz, int nx, int ny, int nz, T wx,
-                                           T wy, T wz, T om) {
+__device__ __forceinline__ void sor_halves(T* sp, const T* sr, int ox, int oy, int oz, int nx, int ny, int nz, int pbc,
+                                           T wx, T wy, T wz, T om) {
   if constexpr (HS < 2 * NSW) {
-    sor_half<T, SOR_T + 2 * (2 * NSW - 1 - HS)>(sp, sr, HS & 1, ox, oy, oz, nx, ny, nz, wx, wy, wz, om);
-    sor_halves<T, NSW, HS + 1>(sp, sr, ox, oy, oz, nx, ny, nz, wx, wy, wz, om);
+    sor_half<T, SOR_T + 2 * (2 * NSW - 1 - HS)>(sp, sr, HS & 1, ox, oy, oz, nx, ny, nz, pbc, wx, wy, wz, om);
+    sor_halves<T, NSW, HS + 1>(sp, sr, ox, oy, oz, nx, ny, nz, pbc, wx, wy, wz, om);
   }
 }
 
@@ -561,10 +575,11 @@ __device__ __forceinline__ void sor_halves(T* sp, const T* sr, int ox, int oy, i
 // half-sweeps there and writes the tile's cells (those inside the mesh) to
 // pout, as global half-sweeps would leave them.  Several independent meshes
 // of the same size (consecutive, bstride cells apart) share a launch: grid z
-// runs over tz tiles of each mesh in turn.
+// runs over tz tiles of each mesh in turn.  A periodic axis (pbc) loads the
+// box's cells past the mesh from the other side of the period.
 template <typename T, int NSW>
 __global__ void __launch_bounds__(SOR_THREADS)
-    k_sor_tile(int nx, int ny, int nz, double dx, double dy, double dz, const T* __restrict__ pin,
+    k_sor_tile(int nx, int ny, int nz, double dx, double dy, double dz, int pbc, const T* __restrict__ pin,
                T* __restrict__ pout, const T* __restrict__ r, double omega, int tz, size_t bstride) {
   static_assert(NSW >= 1 && NSW <= SOR_S, "the halo covers the half-sweeps");
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -590,7 +605,10 @@ __global__ void __launch_bounds__(SOR_THREADS)
   for (int u = 0; u < NL; ++u) {
     const int t = (int)threadIdx.x + u * SOR_THREADS;
     const int li = t % D, lj = (t / D) % D, lk = t / D2;
-    const int i = ox + li, j = oy + lj, k = oz + lk;
+    int i = ox + li, j = oy + lj;
+    const int k = oz + lk;
+    if (pbc & 1) i = ((i % nx) + nx) % nx;
+    if (pbc & 2) j = ((j % ny) + ny) % ny;
     vp[u] = vr[u] = T(0);
     if (i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz) {
       const size_t id = (size_t)k * sz + (size_t)j * sy + i;
@@ -606,7 +624,7 @@ __global__ void __launch_bounds__(SOR_THREADS)
   }
   lds_barrier();
   const T wx = T(1.0 / (dx * dx)), wy = T(1.0 / (dy * dy)), wz = T(1.0 / (dz * dz));
-  sor_halves<T, NSW, 0>(sp, sr, ox, oy, oz, nx, ny, nz, wx, wy, wz, (T)omega);
+  sor_halves<T, NSW, 0>(sp, sr, ox, oy, oz, nx, ny, nz, pbc, wx, wy, wz, (T)omega);
   for (int t = threadIdx.x; t < SOR_T * SOR_T * SOR_T; t += SOR_THREADS) {
     const int li = SOR_H + t % SOR_T, lj = SOR_H + (t / SOR_T) % SOR_T, lk = SOR_H + t / (SOR_T * SOR_T);
     const int i = ox + li, j = oy + lj, k = oz + lk;
@@ -714,10 +732,12 @@ __global__ void __launch_bounds__(CUBE_THREADS)
   }
 }
 
-// J = sigma (E_sol + E_irrot), E_irrot,a = -(g+ + g-)/2, surface faces take E_sol,a.
+// J = sigma (E_sol + E_irrot), E_irrot,a = -(g+ + g-)/2, surface faces take
+// E_sol,a; along a periodic axis (pbc) the faces through the period are
+// interior ones.
 template <typename T>
-__global__ void k_current(int nx, int ny, int nz, double dx, double dy, double dz, const T* __restrict__ phi,
-                          const T* __restrict__ es, T* __restrict__ J, double sigma) {
+__global__ void k_current(int nx, int ny, int nz, double dx, double dy, double dz, int pbc,
+                          const T* __restrict__ phi, const T* __restrict__ es, T* __restrict__ J, double sigma) {
   const size_t N = (size_t)nx * ny * nz;
   for (size_t id = (size_t)blockIdx.x * blockDim.x + threadIdx.x; id < N; id += (size_t)gridDim.x * blockDim.x) {
   int i, j, k;
@@ -726,10 +746,13 @@ __global__ void k_current(int nx, int ny, int nz, double dx, double dy, double d
   const int n[3] = {nx, ny, nz};
   const size_t st[3] = {1, (size_t)nx, (size_t)nx * ny};
   const double d[3] = {dx, dy, dz};
+  const bool per[3] = {(pbc & 1) != 0, (pbc & 2) != 0, false};
   for (int a = 0; a < 3; ++a) {
     const T e = es[a * N + id];
-    const T gp = idx[a] < n[a] - 1 ? (phi[id + st[a]] - phi[id]) / (T)d[a] : e;
-    const T gm = idx[a] > 0 ? (phi[id] - phi[id - st[a]]) / (T)d[a] : e;
+    const size_t wrap = (size_t)(n[a] - 1) * st[a];
+    const size_t up = idx[a] < n[a] - 1 ? id + st[a] : id - wrap, dn = idx[a] > 0 ? id - st[a] : id + wrap;
+    const T gp = (idx[a] < n[a] - 1 || per[a]) ? (phi[up] - phi[id]) / (T)d[a] : e;
+    const T gm = (idx[a] > 0 || per[a]) ? (phi[id] - phi[dn]) / (T)d[a] : e;
     J[a * N + id] = (T)sigma * (e - T(0.5) * (gp + gm));
   }
   }
@@ -892,7 +915,8 @@ template <typename T>
 hipError_t launch_sor_rhs(const CubeLaunch& c, const T* es, T* r, double* part, double* mean, hipStream_t st) {
   const size_t N = (size_t)c.nx * c.ny * c.nz;
   const int nb = (int)((N + 255) / 256);
-  hipLaunchKernelGGL(k_sor_rhs<T>, dim3(nb), dim3(256), 0, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz, es, r, part);
+  hipLaunchKernelGGL(k_sor_rhs<T>, dim3(nb), dim3(256), 0, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz, c.pbc, es, r,
+                     part);
   hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, st, nb, (const double*)part, mean, 1.0 / (double)N);
   hipLaunchKernelGGL(k_shift<T>, grid1(N), dim3(256), 0, st, N, (const T*)r, r, (const double*)mean);
   return hipGetLastError();
@@ -901,8 +925,8 @@ hipError_t launch_sor_rhs(const CubeLaunch& c, const T* es, T* r, double* part, 
 template <typename T>
 hipError_t launch_sor_residual(const CubeLaunch& c, const T* phi, const T* r, double* part, int nblk,
                                hipStream_t st) {
-  hipLaunchKernelGGL(k_sor_residual<T>, dim3(nblk), dim3(256), 0, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz, phi, r,
-                     part);
+  hipLaunchKernelGGL(k_sor_residual<T>, dim3(nblk), dim3(256), 0, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz, c.pbc,
+                     phi, r, part);
   return hipGetLastError();
 }
 
@@ -921,10 +945,10 @@ hipError_t launch_sor(const CubeLaunch& c, int nbox, T* phi, T* phi2, const T* r
   for (int s = 0; s < sweeps; s += SOR_S) {
     if (sweeps - s >= 2)
       hipLaunchKernelGGL((k_sor_tile<T, 2>), grid, dim3(SOR_THREADS), lds, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz,
-                         (const T*)cur, nxt, r, omega, tz, N);
+                         c.pbc, (const T*)cur, nxt, r, omega, tz, N);
     else
       hipLaunchKernelGGL((k_sor_tile<T, 1>), grid, dim3(SOR_THREADS), lds, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz,
-                         (const T*)cur, nxt, r, omega, tz, N);
+                         c.pbc, (const T*)cur, nxt, r, omega, tz, N);
     T* tmp = cur;
     cur = nxt;
     nxt = tmp;
@@ -944,8 +968,8 @@ hipError_t launch_sor(const CubeLaunch& c, int nbox, T* phi, T* phi2, const T* r
 template <typename T>
 hipError_t launch_current(const CubeLaunch& c, const T* phi, const T* es, T* J, double sigma, hipStream_t st) {
   const size_t N = (size_t)c.nx * c.ny * c.nz;
-  hipLaunchKernelGGL(k_current<T>, grid1(N), dim3(256), 0, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz, phi, es, J,
-                     sigma);
+  hipLaunchKernelGGL(k_current<T>, grid1(N), dim3(256), 0, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz, c.pbc, phi, es,
+                     J, sigma);
   return hipGetLastError();
 }
 

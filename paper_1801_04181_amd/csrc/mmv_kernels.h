@@ -63,7 +63,7 @@ struct CubeLaunch {
   int nx, ny, nz;
   double dx, dy, dz;
   double pref_ex, pref_an, u[3], hext[3], gam, alpha;
-  int pbc;  // periodic in-plane axes of the exchange stencil (bit 0 = x, 1 = y)
+  int pbc;  // periodic in-plane axes (bit 0 = x, 1 = y) of the exchange stencil and the Neumann problem
 };
 template <typename T>
 hipError_t launch_fft_axis(const void* in, void* out, int nplanes, int ncols, int CB, int n_in, long long in_ps,

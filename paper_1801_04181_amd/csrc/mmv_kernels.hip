@@ -1613,7 +1613,10 @@ __global__ void k_kernel_real(double* __restrict__ out, int Lx, int Ly, int kind
   } else {
     oddx = (comp == 0);
     oddy = (comp == 1);
-    v = s_comp(comp, ix * dx, iy * dy, dzc * dz, dx, dy, dz);
+    const int qx = (pbc & 1) ? images : 0, qy = (pbc & 2) ? images : 0;
+    v = 0.0;
+    for (int a = -qx; a <= qx; ++a)
+      for (int b = -qy; b <= qy; ++b) v += s_comp(comp, (ix + a * Lx) * dx, (iy + b * Ly) * dy, dzc * dz, dx, dy, dz);
   }
   if ((Lx % 2 == 0 && rx == Lx / 2 && oddx) || (Ly % 2 == 0 && ry == Ly / 2 && oddy)) v = 0.0;
   out[(size_t)ry * Lx + rx] = scale * v;

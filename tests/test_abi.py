@@ -159,17 +159,19 @@ def test_cube_size_limits_are_checked_before_any_device_call(prec, shape):
 
 def test_thick_films_descriptor_rules():
     """Thick films take the scalar potential only more than two cells apart
-    (as one-layer films), and periodic in-plane boundaries only as two films
-    without eddy currents."""
+    (as one-layer films), periodic in-plane boundaries only as two films, and
+    eddy currents in periodic films with red-black sweeps over even periods."""
     d = get_config("tiny_potential")["desc"].replace(nz=2, gap_cells=2)
     with pytest.raises(mmv.MMVError) as e:
         mmv.init_mesh(mmv.to_desc(d))
     assert e.value.code == -1 and "gap_cells >= 3" in str(e.value)
-    for change in (dict(nz=2, pbc=1, sigma=1e6), dict(nz=2, pbc=1, n_films=1)):
+    for change, msg in ((dict(nz=2, pbc=1, n_films=1), "two thicker films"),
+                        (dict(nz=2, pbc=2, ny=31, sigma=1e6), "ny even"),
+                        (dict(nz=2, pbc=1, sigma=1e6, sor_sweeps=-1), "sor_sweeps >= 0")):
         d = get_config("tiny")["desc"].replace(**change)
         with pytest.raises(mmv.MMVError) as e:
             mmv.init_mesh(mmv.to_desc(d))
-        assert e.value.code == -1 and "without eddy currents" in str(e.value)
+        assert e.value.code == -1 and msg in str(e.value), (change, str(e.value))
 
 
 def test_potential_mode_needs_two_films():

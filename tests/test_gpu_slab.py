@@ -360,3 +360,47 @@ def test_periodic_thick_films_steps(prec):
     assert out["x"] < (1e-6 if prec == 32 else 1e-11), out
     mesh.close()
     print("  ", out, flush=True)
+
+
+@pytest.mark.parametrize("prec,pbc,x_cells", [(64, 3, 0.93), (32, 3, 0.93), (64, 1, 15.93), (32, 1, 15.93),
+                                              (64, 2, 0.93)])
+def test_periodic_thick_films_steps_with_eddy_currents(prec, pbc, x_cells):
+    """RK4 steps of periodic thick films with eddy currents in both (the
+    friction geometry of the eddy-current run): image-summed S sums, the
+    Neumann problems wrapping along the periods, a spring-driven slider
+    crossing a cell boundary (from just below the period into s_int = nx
+    for a periodic x); magnetisation, position, velocity, both films' held
+    eddy fields and the pooled Neumann residual against the oracle."""
+    import torch
+    import paper_1801_04181_amd as mmv
+    from oracle.eddy import residual
+    d, m = films(16, 10, 3, prec, gap=1, seed=50 + pbc, state="stripes", sigma=1e6, sor_sweeps=12, pbc=pbc,
+                 pbc_images=1)
+    mass, gv = slider_mass_damping(16, 10, 0.005)
+    drv = Drive(mode=2, v_d=1500.0, k=0.005, mass=mass, gamma_v=gv, x0=x_cells * d.dx, v0=1500.0)
+    print(f"slab periodic eddy steps p{prec} pbc={pbc} x0={x_cells}", flush=True)
+    mesh, s = pair(d, m, drv)
+    dt, n = 1e-13, 4
+    mesh.step(dt, n)
+    torch.cuda.synchronize()
+    s.run(dt, n)
+    st = mesh.state()
+    assert math.floor(st["x"] / d.dx) == s.s_int == math.floor(x_cells) + 1, "the slider crosses a cell boundary"
+    out = {"x": abs(st["x"] - s.x) / d.dx, "v": abs(st["v"] - s.v) / max(abs(s.v), 1.0)}
+    for f in range(2):
+        out[f"m{f}"] = float(np.abs(mesh.get_m(f).cpu().numpy() - s.m[f]).max())
+        assert out[f"m{f}"] < TOL_M[prec], out
+        ref = s.eddy.H[f]
+        assert np.abs(ref).max() > 0
+        out[f"eddy{f}"] = rel(mesh.eval_heff(f, 32).cpu().numpy(), ref)
+        assert out[f"eddy{f}"] <= TOL_EDDY[prec], out
+    assert out["x"] < (1e-6 if prec == 32 else 1e-11), out
+    assert out["v"] < (1e-5 if prec == 32 else 1e-10), out
+    got = mmv.eddy_residual(mesh.h)
+    rn = [float(np.linalg.norm(s.eddy.r[f])) for f in range(2)]
+    num = sum((residual(d, s.eddy.phi[f], s.eddy.r[f]) * rn[f]) ** 2 for f in range(2))
+    ref_res = math.sqrt(num / sum(r * r for r in rn))
+    out["residual"] = (got, ref_res)
+    assert abs(got - ref_res) <= (1e-3 if prec == 32 else 1e-9) * ref_res, out
+    mesh.close()
+    print("  ", out, flush=True)

@@ -46,7 +46,7 @@ class Desc:
     rc_cells: float = 30.0    # Newell / point-dipole switch radius [cells]
     sor_sweeps: int = 0       # fixed red-black SOR sweeps per step (0: library default)
     sor_omega: float = 0.0    # SOR relaxation factor (0: 2/(1+sin(pi/n_max)))
-    pbc: int = 0              # periodic in-plane axes: bit 0 = x, bit 1 = y (film path)
+    pbc: int = 0              # periodic in-plane axes: bit 0 = x, bit 1 = y (one- and two-layer films)
     pbc_images: int = 0       # periodic images summed on each side per periodic axis
 
     @property
