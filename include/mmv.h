@@ -89,16 +89,17 @@ typedef struct {
                            -1: the Neumann problem solved exactly in the
                            cosine basis that diagonalises it (DCT-II along
                            x, y, z, division by the eigenvalues, inverse;
-                           nx, ny, nz {2,3,5,7}-smooth, open in-plane
-                           boundaries; MMV_EINVAL otherwise)              */
+                           nx, ny, nz {2,3,5,7}-smooth, MMV_EINVAL
+                           otherwise; a periodic axis takes the Hartley
+                           transform, cas(2 pi k i / n), instead)         */
   double sor_omega;     /* eddy SOR factor (0: 2/(1+sin(pi/n_max)))           */
   int fft_lx, fft_ly, fft_lz; /* FFT lengths; 0 = smallest admissible       */
   int pbc;              /* periodic in-plane axes (Sec. III.A end, Sec. IV.B):
                            bit 0 = x, bit 1 = y; 0 = open.  Film meshes
                            (nz == 1) in the direct mode without eddy
                            currents, or two thicker films in the same mode
-                           (with eddy currents: SOR sweeps, sor_sweeps >= 0,
-                           and ny even for a periodic y).  Along a
+                           (with eddy currents: ny even for a periodic
+                           y).  Along a
                            periodic axis the transform length is the period (nx even and {2,3,5,7}-smooth,
                            ny {2,3,5,7}-smooth), the kernel of a displacement
                            is summed over its minimum image and pbc_images
@@ -145,8 +146,8 @@ typedef struct {
  * along a periodic axis over the period, windows unshifted along it (the
  * sampler wraps their columns and rows modulo the period) and exchange
  * wrapping; with eddy currents the S sums take the image-summed kernel and
- * each film's Neumann problem wraps along the periods (no surface there),
- * by the SOR sweeps.  Each field
+ * each film's Neumann problem wraps along the periods (no surface there).
+ * Each field
  * is a sum over the source film's layers of in-plane convolutions with the
  * kernel of each layer offset (FFT lengths as for one-layer films, fft_lz
  * unused): the films' own fields, the base's field on the slider's window

@@ -243,9 +243,6 @@ int validate(const mmv_mesh_desc* d) {
     if (d->sigma > 0.0 && (d->pbc & 2) && d->ny % 2)
       return fail(MMV_EINVAL, "pbc: eddy currents with a periodic y need ny even (red-black colouring over the "
                               "period)");
-    if (d->sigma > 0.0 && d->sor_sweeps < 0)
-      return fail(MMV_EINVAL, "pbc: eddy currents in periodic films take the SOR sweeps (sor_sweeps >= 0); the exact "
-                              "solve is for open boundaries");
     if (d->cross_mode != 0) return fail(MMV_EINVAL, "pbc: periodic boundaries run in the direct mode (cross_mode 0)");
     if ((d->pbc & 1) && (d->nx % 2 || !smooth2357(d->nx)))
       return fail(MMV_EINVAL, "pbc: a periodic x needs nx even and {2,3,5,7}-smooth (the transform length)");

@@ -510,9 +510,9 @@ constexpr int SOR_D = SOR_T + 2 * SOR_H;    // loaded box edge
 // (E even).  Every neighbour of the region lies in the box.  A thread
 // computes all of its new values before storing any: the half-sweep reads
 // only the other colour and each updated cell's own old value.
-template <typename T, int E>
+template <typename T, int E, int PBC>
 __device__ __forceinline__ void sor_half(T* sp, const T* sr, int colour, int ox, int oy, int oz, int nx, int ny,
-                                         int nz, int pbc, T wx, T wy, T wz, T om) {
+                                         int nz, T wx, T wy, T wz, T om) {
   constexpr int D = SOR_D, D2 = D * D, O = (SOR_D - E) / 2, EH = E / 2;
   constexpr int NC = E * E * E / 2, NU = (NC + SOR_THREADS - 1) / SOR_THREADS;
   static_assert(E % 2 == 0 && O >= 1, "the region and its neighbours lie in the box");
@@ -526,7 +526,7 @@ __device__ __forceinline__ void sor_half(T* sp, const T* sr, int colour, int ox,
     const int j = oy + lj, k = oz + lk;
     const int li = O + 2 * xh + ((colour - ox - O - j - k) & 1);
     const int i = ox + li;
-    const bool px = (pbc & 1) != 0, py = (pbc & 2) != 0;
+    constexpr bool px = (PBC & 1) != 0, py = (PBC & 2) != 0;
     const bool upd = t < NC && (px || (i >= 0 && i < nx)) && (py || (j >= 0 && j < ny)) && k >= 0 && k < nz;
     const bool x0 = px || i > 0, x1 = px || i < nx - 1, y0 = py || j > 0, y1 = py || j < ny - 1, z0 = k > 0,
                z1 = k < nz - 1;
@@ -560,12 +560,12 @@ __device__ __forceinline__ void sor_half(T* sp, const T* sr, int colour, int ox,
 // Half-sweeps HS .. 2 NSW - 1 of a launch: half-sweep h updates the region
 // of edge SOR_T + 2 (2 NSW - 1 - h), the cells the tile still depends on,
 // which reads the region of half-sweep h - 1 (the whole box for h = 0).
-template <typename T, int NSW, int HS>
-__device__ __forceinline__ void sor_halves(T* sp, const T* sr, int ox, int oy, int oz, int nx, int ny, int nz, int pbc,
-                                           T wx, T wy, T wz, T om) {
+template <typename T, int NSW, int HS, int PBC>
+__device__ __forceinline__ void sor_halves(T* sp, const T* sr, int ox, int oy, int oz, int nx, int ny, int nz, T wx,
+                                           T wy, T wz, T om) {
   if constexpr (HS < 2 * NSW) {
-    sor_half<T, SOR_T + 2 * (2 * NSW - 1 - HS)>(sp, sr, HS & 1, ox, oy, oz, nx, ny, nz, pbc, wx, wy, wz, om);
-    sor_halves<T, NSW, HS + 1>(sp, sr, ox, oy, oz, nx, ny, nz, pbc, wx, wy, wz, om);
+    sor_half<T, SOR_T + 2 * (2 * NSW - 1 - HS), PBC>(sp, sr, HS & 1, ox, oy, oz, nx, ny, nz, wx, wy, wz, om);
+    sor_halves<T, NSW, HS + 1, PBC>(sp, sr, ox, oy, oz, nx, ny, nz, wx, wy, wz, om);
   }
 }
 
@@ -576,10 +576,12 @@ __device__ __forceinline__ void sor_halves(T* sp, const T* sr, int ox, int oy, i
 // pout, as global half-sweeps would leave them.  Several independent meshes
 // of the same size (consecutive, bstride cells apart) share a launch: grid z
 // runs over tz tiles of each mesh in turn.  A periodic axis (pbc) loads the
-// box's cells past the mesh from the other side of the period.
-template <typename T, int NSW>
+// box's cells past the mesh from the other side of the period (PBC: the
+// periodic axes, bit 0 = x, 1 = y, fixed at compile time so that the open
+// mesh's sweep carries no wrap arithmetic).
+template <typename T, int NSW, int PBC>
 __global__ void __launch_bounds__(SOR_THREADS)
-    k_sor_tile(int nx, int ny, int nz, double dx, double dy, double dz, int pbc, const T* __restrict__ pin,
+    k_sor_tile(int nx, int ny, int nz, double dx, double dy, double dz, const T* __restrict__ pin,
                T* __restrict__ pout, const T* __restrict__ r, double omega, int tz, size_t bstride) {
   static_assert(NSW >= 1 && NSW <= SOR_S, "the halo covers the half-sweeps");
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -607,8 +609,8 @@ __global__ void __launch_bounds__(SOR_THREADS)
     const int li = t % D, lj = (t / D) % D, lk = t / D2;
     int i = ox + li, j = oy + lj;
     const int k = oz + lk;
-    if (pbc & 1) i = ((i % nx) + nx) % nx;
-    if (pbc & 2) j = ((j % ny) + ny) % ny;
+    if constexpr ((PBC & 1) != 0) i = ((i % nx) + nx) % nx;
+    if constexpr ((PBC & 2) != 0) j = ((j % ny) + ny) % ny;
     vp[u] = vr[u] = T(0);
     if (i >= 0 && i < nx && j >= 0 && j < ny && k >= 0 && k < nz) {
       const size_t id = (size_t)k * sz + (size_t)j * sy + i;
@@ -624,7 +626,7 @@ __global__ void __launch_bounds__(SOR_THREADS)
   }
   lds_barrier();
   const T wx = T(1.0 / (dx * dx)), wy = T(1.0 / (dy * dy)), wz = T(1.0 / (dz * dz));
-  sor_halves<T, NSW, 0>(sp, sr, ox, oy, oz, nx, ny, nz, pbc, wx, wy, wz, (T)omega);
+  sor_halves<T, NSW, 0, PBC>(sp, sr, ox, oy, oz, nx, ny, nz, wx, wy, wz, (T)omega);
   for (int t = threadIdx.x; t < SOR_T * SOR_T * SOR_T; t += SOR_THREADS) {
     const int li = SOR_H + t % SOR_T, lj = SOR_H + (t / SOR_T) % SOR_T, lk = SOR_H + t / (SOR_T * SOR_T);
     const int i = ox + li, j = oy + lj, k = oz + lk;
@@ -641,18 +643,25 @@ __global__ void __launch_bounds__(SOR_THREADS)
 // C_k = sum_i x_i cos(pi k (2 i + 1) / (2 n)) = Re(exp(-i pi k / (2 n)) V_k)
 // with V = DFT(v), v_p = x_{2p}, v_{n-1-p} = x_{2p+1}; the inverse builds
 // V_k = exp(i pi k / (2 n)) (C_k - i C_{n-k}) (C_n = 0) and v = IDFT(V).
+// A periodic in-plane axis (pbc) has no faces at its ends: its Laplacian is
+// the symmetric circulant one, diagonal in the Hartley basis
+// cas(2 pi k i / n) = cos + sin with eigenvalue (2 cos(2 pi k / n) - 2) / d^2
+// (cas k and cas n - k span the Fourier pair of one eigenvalue).  The real
+// Hartley transform H_k = Re X_k - Im X_k of X = DFT(x), and x = (Re Y +
+// Im Y) / n of Y = IDFT(H), keep the line real like the cosine one.
 // Line l of a launch: element i at (l / inner) hs + l % inner + i es.
 // SOLVE (the last forward axis, z): C / lambda(kx, ky, kz), the k = 0 mode
 // (the gauge) set to zero.
 struct DctSolve {
   int nx, ny;
   double idx2, idy2, idz2;
+  int pbc;  // periodic x (bit 0) and y (bit 1): Hartley eigenvalues there
 };
 
 template <typename T, bool INV, bool SOLVE>
 __global__ void __launch_bounds__(CUBE_THREADS)
     k_dct_axis(const T* __restrict__ in, T* __restrict__ out, int nlines, int n, int inner, long long hs,
-               long long es, int CB, FftPlan P, const cpx<T>* __restrict__ tw, DctSolve sv) {
+               long long es, int CB, FftPlan P, const cpx<T>* __restrict__ tw, DctSolve sv, int hart) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* stw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* A = stw + n;
@@ -680,8 +689,14 @@ __global__ void __launch_bounds__(CUBE_THREADS)
     for (int t = threadIdx.x; t < nc * n; t += CUBE_THREADS) {
       int c, i;
       slot(t, c, i);
-      const int p = (i & 1) ? n - 1 - (i >> 1) : (i >> 1);
+      const int p = hart ? i : ((i & 1) ? n - 1 - (i >> 1) : (i >> 1));
       A[c * n + p] = mk<T>(in[addr(c, i)], T(0));
+    }
+  } else if (hart) {
+    for (int t = threadIdx.x; t < nc * n; t += CUBE_THREADS) {
+      int c, i;
+      slot(t, c, i);
+      A[c * n + i] = mk<T>(in[addr(c, i)], T(0));
     }
   } else {
     T* Cs = reinterpret_cast<T*>(B);
@@ -710,20 +725,27 @@ __global__ void __launch_bounds__(CUBE_THREADS)
     T v;
     if constexpr (!INV) {
       const cpx<T> V = R[c * n + i];
-      T sn, cs;
-      if constexpr (sizeof(T) == 8)
-        sincospi((double)i / (2.0 * n), &sn, &cs);
-      else
-        sincospif((float)i / (2.0f * (float)n), &sn, &cs);
-      v = V.x * cs + V.y * sn;
+      if (hart) {
+        v = V.x - V.y;
+      } else {
+        T sn, cs;
+        if constexpr (sizeof(T) == 8)
+          sincospi((double)i / (2.0 * n), &sn, &cs);
+        else
+          sincospif((float)i / (2.0f * (float)n), &sn, &cs);
+        v = V.x * cs + V.y * sn;
+      }
       if constexpr (SOLVE) {
         const int lo = (l0 + c) % inner;
         const int ky = lo / sv.nx, kx = lo - ky * sv.nx;
-        const double lam = (2.0 * cospi((double)kx / sv.nx) - 2.0) * sv.idx2 +
-                           (2.0 * cospi((double)ky / sv.ny) - 2.0) * sv.idy2 +
+        const double fx = (sv.pbc & 1) ? 2.0 : 1.0, fy = (sv.pbc & 2) ? 2.0 : 1.0;
+        const double lam = (2.0 * cospi(fx * kx / sv.nx) - 2.0) * sv.idx2 +
+                           (2.0 * cospi(fy * ky / sv.ny) - 2.0) * sv.idy2 +
                            (2.0 * cospi((double)i / n) - 2.0) * sv.idz2;
         v = (kx == 0 && ky == 0 && i == 0) ? T(0) : (T)((double)v / lam);
       }
+    } else if (hart) {
+      v = (R[c * n + i].x + R[c * n + i].y) / (T)n;
     } else {
       const int p = (i & 1) ? n - 1 - (i >> 1) : (i >> 1);
       v = R[c * n + p].x / (T)n;
@@ -942,13 +964,23 @@ hipError_t launch_sor(const CubeLaunch& c, int nbox, T* phi, T* phi2, const T* r
   const size_t lds = 2 * sizeof(T) * SOR_D * SOR_D * SOR_D;
   T* cur = phi;
   T* nxt = phi2;
+  // one instantiation per sweep count and set of periodic axes
   for (int s = 0; s < sweeps; s += SOR_S) {
-    if (sweeps - s >= 2)
-      hipLaunchKernelGGL((k_sor_tile<T, 2>), grid, dim3(SOR_THREADS), lds, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz,
-                         c.pbc, (const T*)cur, nxt, r, omega, tz, N);
-    else
-      hipLaunchKernelGGL((k_sor_tile<T, 1>), grid, dim3(SOR_THREADS), lds, st, c.nx, c.ny, c.nz, c.dx, c.dy, c.dz,
-                         c.pbc, (const T*)cur, nxt, r, omega, tz, N);
+    const int two = sweeps - s >= 2;
+#define MMV_SOR_TILE(NSW, PBC)                                                                                  \
+  hipLaunchKernelGGL((k_sor_tile<T, NSW, PBC>), grid, dim3(SOR_THREADS), lds, st, c.nx, c.ny, c.nz, c.dx, c.dy, \
+                     c.dz, (const T*)cur, nxt, r, omega, tz, N)
+    switch ((c.pbc & 3) * 2 + two) {
+      case 0: MMV_SOR_TILE(1, 0); break;
+      case 1: MMV_SOR_TILE(2, 0); break;
+      case 2: MMV_SOR_TILE(1, 1); break;
+      case 3: MMV_SOR_TILE(2, 1); break;
+      case 4: MMV_SOR_TILE(1, 2); break;
+      case 5: MMV_SOR_TILE(2, 2); break;
+      case 6: MMV_SOR_TILE(1, 3); break;
+      default: MMV_SOR_TILE(2, 3); break;
+    }
+#undef MMV_SOR_TILE
     T* tmp = cur;
     cur = nxt;
     nxt = tmp;
@@ -981,7 +1013,7 @@ hipError_t launch_neumann_solve(const CubeLaunch& c, int nbox, const T* r, T* ph
                                 const void* const* tw, hipStream_t st) {
   const int nx = c.nx, ny = c.ny, nz = c.nz;
   const long long N = (long long)nx * ny * nz;
-  DctSolve sv{nx, ny, 1.0 / (c.dx * c.dx), 1.0 / (c.dy * c.dy), 1.0 / (c.dz * c.dz)};
+  DctSolve sv{nx, ny, 1.0 / (c.dx * c.dx), 1.0 / (c.dy * c.dy), 1.0 / (c.dz * c.dz), c.pbc};
   struct Ax {
     int n, inner;
     long long hs, es;
@@ -1003,15 +1035,17 @@ hipError_t launch_neumann_solve(const CubeLaunch& c, int nbox, const T* r, T* ph
       if (e != hipSuccess) return e;
     }
     const dim3 grid((x.nlines + CB - 1) / CB);
+    // axes 0 (x) and 1 (y) take the Hartley transform where periodic
+    const int hart = a < 2 && ((c.pbc >> a) & 1);
     if (inv)
       hipLaunchKernelGGL((k_dct_axis<T, true, false>), grid, dim3(CUBE_THREADS), lds, st, src, dst, x.nlines, x.n,
-                         x.inner, x.hs, x.es, CB, P[a], (const cpx<T>*)tw[a], sv);
+                         x.inner, x.hs, x.es, CB, P[a], (const cpx<T>*)tw[a], sv, hart);
     else if (solve)
       hipLaunchKernelGGL((k_dct_axis<T, false, true>), grid, dim3(CUBE_THREADS), lds, st, src, dst, x.nlines, x.n,
-                         x.inner, x.hs, x.es, CB, P[a], (const cpx<T>*)tw[a], sv);
+                         x.inner, x.hs, x.es, CB, P[a], (const cpx<T>*)tw[a], sv, hart);
     else
       hipLaunchKernelGGL((k_dct_axis<T, false, false>), grid, dim3(CUBE_THREADS), lds, st, src, dst, x.nlines, x.n,
-                         x.inner, x.hs, x.es, CB, P[a], (const cpx<T>*)tw[a], sv);
+                         x.inner, x.hs, x.es, CB, P[a], (const cpx<T>*)tw[a], sv, hart);
     return hipGetLastError();
   };
   hipError_t e = run(0, false, false, r, work);

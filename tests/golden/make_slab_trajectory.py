@@ -11,8 +11,14 @@ the slider's position and velocity, and at the end each film's eddy field:
                   x_<step>, v_<step>, eddy0, eddy1 (3, 3, 12, 16),
                   steps = (250, 500, 750, 1000)
 
-About a minute on one core.  Used by tests/test_gpu_slab.py.  Usage:
-  python tests/golden/make_slab_trajectory.py
+About a minute on one core.  With --periodic, the same films periodic in
+x and y (one image on each side), the slider driven from 15.3 cells so that
+it crosses the period (s_int 15 -> 16 = nx) near step 470:
+
+  slab_periodic_1000.npz   the same keys
+
+Used by tests/test_gpu_slab.py.  Usage:
+  python tests/golden/make_slab_trajectory.py [--periodic]
 """
 import os
 import sys
@@ -29,17 +35,20 @@ STEPS = (250, 500, 750, 1000)
 DT = 1e-13
 
 
-def case(precision=64):
+def case(precision=64, periodic=False):
     """Descriptor, drive and initial state of the stored run."""
     d = Desc(n_films=2, nx=16, ny=12, nz=3, dx=4e-9, dy=4e-9, dz=4e-9, gap_cells=1, max_travel_cells=4,
              Ms=3.5e5, Aex=5e-12, alpha=0.05, Ku=1.225e5, u=(0.0, 0.0, 1.0), sigma=1e6, precision=precision,
              halo=4, sor_sweeps=20)
     m = [stripe_state((3, 12, 16), 31 + f, width_cells=5) for f in range(2)]
+    if periodic:
+        d = d.replace(pbc=3, pbc_images=1)
+        return d, Drive(mode=1, v_d=60.0, x0=15.3 * d.dx), m
     return d, Drive(mode=1, v_d=60.0, x0=0.3 * d.dx), m
 
 
-def main():
-    d, drv, m = case()
+def main(periodic=False):
+    d, drv, m = case(periodic=periodic)
     s = SlabSystem(d, drv, m)
     out = {"steps": np.array(STEPS)}
     for n in range(STEPS[-1]):
@@ -52,8 +61,9 @@ def main():
             print("slab step", n + 1, "x/dx", s.x / d.dx, flush=True)
     out["eddy0"] = s.eddy.H[0].copy()
     out["eddy1"] = s.eddy.H[1].copy()
-    np.savez_compressed(os.path.join(HERE, "slab_1000.npz"), **out)
+    name = "slab_periodic_1000.npz" if periodic else "slab_1000.npz"
+    np.savez_compressed(os.path.join(HERE, name), **out)
 
 
 if __name__ == "__main__":
-    main()
+    main(periodic="--periodic" in sys.argv[1:])

@@ -160,14 +160,14 @@ def test_cube_size_limits_are_checked_before_any_device_call(prec, shape):
 def test_thick_films_descriptor_rules():
     """Thick films take the scalar potential only more than two cells apart
     (as one-layer films), periodic in-plane boundaries only as two films, and
-    eddy currents in periodic films with red-black sweeps over even periods."""
+    eddy currents in films periodic in y with an even period (red-black
+    sweeps)."""
     d = get_config("tiny_potential")["desc"].replace(nz=2, gap_cells=2)
     with pytest.raises(mmv.MMVError) as e:
         mmv.init_mesh(mmv.to_desc(d))
     assert e.value.code == -1 and "gap_cells >= 3" in str(e.value)
     for change, msg in ((dict(nz=2, pbc=1, n_films=1), "two thicker films"),
-                        (dict(nz=2, pbc=2, ny=31, sigma=1e6), "ny even"),
-                        (dict(nz=2, pbc=1, sigma=1e6, sor_sweeps=-1), "sor_sweeps >= 0")):
+                        (dict(nz=2, pbc=2, ny=31, sigma=1e6), "ny even")):
         d = get_config("tiny")["desc"].replace(**change)
         with pytest.raises(mmv.MMVError) as e:
             mmv.init_mesh(mmv.to_desc(d))
