@@ -19,7 +19,10 @@ summed; this module takes (reading in the design notes):
 * along an open axis the zero-padded linear convolution is kept;
 * the eddy-current sums (Eq. 9 and the field of the currents) over a
   periodic film take the same image sum of the scalar-potential kernel S of
-  Eq. 8 (FilmSWindow).
+  Eq. 8 (FilmSWindow), and so does the scalar potential of the potential
+  mode (FilmPotWindow): its window rows and columns past the period are
+  the values from the other side, the copy the paper describes for the
+  potential's extension past the domain.
 
 Pins (tests/test_oracle_periodic.py): the FFT route equals a brute-force loop
 over cell pairs and images; a uniform magnetisation gives a field that is the
@@ -107,6 +110,8 @@ class FilmWindow:
     target indices taken modulo the period.  Open axes: linear convolution
     on the displacement grid by FFT (as oracle.convolution.WindowSum)."""
 
+    nout = 3  # output channels
+
     def __init__(self, desc, x0, nwx, y0, nwy, dz_cells):
         self.desc = desc
         self.px, self.py = bool(desc.pbc & 1), bool(desc.pbc & 2)
@@ -140,13 +145,13 @@ class FilmWindow:
         x0, nwx, y0, nwy = self.box
         Ly, Lx = len(self.gy), len(self.gx)
         shat = [np.fft.fft2(m[b, 0], s=(Ly, Lx)) for b in range(3)]
-        out = np.zeros((3, 1, nwy, nwx))
+        out = np.zeros((self.nout, 1, nwy, nwx))
         xs = np.arange(x0, x0 + nwx)
         ys = np.arange(y0, y0 + nwy)
         # index of each target point in the convolution output
         ox = np.mod(xs, nx) if self.px else xs - x0 + (nx - 1)
         oy = np.mod(ys, ny) if self.py else ys - y0 + (ny - 1)
-        for a in range(3):
+        for a in range(self.nout):
             acc = 0.0
             for b in range(3):
                 if (a, b) in self.khat:
@@ -179,6 +184,33 @@ class FilmSWindow(FilmWindow):
         for (a, b, c), e in EPS.items():
             ker[(a, c)] = ker.get((a, c), 0.0) + self.sign * e * S[b]
         return ker
+
+
+class FilmPotWindow(FilmWindow):
+    """The scalar potential phi = Ms sum_j S_per(p - r_j) . m_j of a
+    one-layer source (Eqs. 7-8) on the same targets, one output channel:
+    the potential of the periodic films, whose values past the period are
+    those of the other side (the copy of Sec. III.A end)."""
+
+    nout = 1
+
+    def kernels(self, IX, IY, dz_cells):
+        return {(0, b): self.desc.Ms * periodic_s(self.desc, b, IX, IY, dz_cells) for b in range(3)}
+
+
+def brute_force_pot(desc, m, x0, nwx, y0, nwy, dz_cells):
+    """FilmPotWindow by loops over target points and source cells, the
+    kernel of each displacement taken from periodic_s."""
+    nx, ny = desc.nx, desc.ny
+    out = np.zeros((1, 1, nwy, nwx))
+    for ty in range(nwy):
+        for tx in range(nwx):
+            for j in range(ny):
+                for i in range(nx):
+                    S = np.array([float(periodic_s(desc, b, x0 + tx - i, y0 + ty - j, dz_cells))
+                                  for b in range(3)])
+                    out[0, 0, ty, tx] += desc.Ms * S @ m[:, 0, j, i]
+    return out
 
 
 def brute_force_s(desc, v, x0, nwx, y0, nwy, dz_cells, sign):
@@ -218,12 +250,14 @@ def brute_force(desc, m, x0, nwx, y0, nwy, dz_cells):
 
 
 class BoxWindow:
-    """FilmWindow over a box of layers: same call signature and output
-    layout (3, nwz, nwy, nwx) as oracle.convolution.WindowSum on that box."""
+    """FilmWindow (or, with potential=True, FilmPotWindow) over a box of
+    layers: same call signature and output layout (channels, nwz, nwy, nwx)
+    as oracle.convolution.WindowSum on that box."""
 
-    def __init__(self, desc, box):
+    def __init__(self, desc, box, potential=False):
         x0, nwx, y0, nwy, z0, nwz = box
-        self.layers = [FilmWindow(desc, x0, nwx, y0, nwy, z0 + k) for k in range(nwz)]
+        cls = FilmPotWindow if potential else FilmWindow
+        self.layers = [cls(desc, x0, nwx, y0, nwy, z0 + k) for k in range(nwz)]
 
     def __call__(self, m):
         return np.concatenate([w(m) for w in self.layers], axis=1)

@@ -117,11 +117,11 @@ class System:
         d = self.desc
         box = self.cross_box(direction, s_int)
         if d.pbc:
-            # periodic films: the window is the periodic field, its halo the
-            # copy from the other side (direct mode only)
+            # periodic films: the window is the periodic field (or potential),
+            # its halo the copy from the other side
             from .periodic import BoxWindow
-            assert d.cross_mode == 0, "periodic boundaries: direct mode only"
-            return self._op(("cross", direction, s_int, 0), lambda: BoxWindow(d, box))
+            return self._op(("cross", direction, s_int, d.cross_mode),
+                            lambda: BoxWindow(d, box, potential=d.cross_mode == 1))
         maker = (lambda: demag_window(d, box)) if d.cross_mode in (0, 2) else (
             lambda: potential_window(d, box))
         return self._op(("cross", direction, s_int, d.cross_mode), maker)

@@ -7,9 +7,10 @@ Geometry.  As in oracle.sim, but each film is nx x ny x nz cells (nz >= 1)
 and the slider's lattice origin sits z_s = nz + gap layers above the base's.
 Every cross mode: the direct field with the cubic B-spline along x
 (cross_mode 0) or linear interpolation (2), and the scalar potential (1).
-Open in-plane boundaries, or periodic ones (pbc, the direct modes): every
-layer pair's sum then takes oracle.periodic's image-summed kernel, window
-points outside the period take their image's value, and exchange wraps
+Open in-plane boundaries, or periodic ones (pbc, every cross mode): every
+layer pair's sum then takes oracle.periodic's image-summed kernel (the
+potential's too), window points outside the period take their image's
+value (for the potential, the copy of Sec. III.A end), and exchange wraps
 (the paper's friction films, Sec. IV.B; its eddy-current friction run,
 Sec. IV.C, keeps that geometry).  With eddy currents the eddy sums take the
 image-summed S kernel the same way and each film's Neumann problem is
@@ -94,7 +95,6 @@ class SlabSystem(System):
 
     def __init__(self, desc, drive=None, m_init=None):
         assert desc.n_films == 2, "two films"
-        assert desc.pbc == 0 or desc.cross_mode != 1, "periodic thick films: the direct modes"
         # the base class would set up the single-magnet eddy state
         super().__init__(desc.replace(sigma=0.0), drive, m_init)
         self.desc = desc
@@ -113,7 +113,9 @@ class SlabSystem(System):
         d = self.desc
         if d.pbc:
             box = self.cross_box(direction, s_int)
-            return self._op(("cross", direction, s_int, d.cross_mode), lambda: PeriodicLayers(d, box))
+            pot = d.cross_mode == 1
+            return self._op(("cross", direction, s_int, d.cross_mode),
+                            lambda: PeriodicLayers(d, box, potential=pot))
         return super().cross_op(direction, s_int)
 
     def cross_box(self, direction, s_int):
@@ -237,14 +239,17 @@ class PeriodicLayers:
     of target points (x0, nwx, y0, nwy, z0, nwz): target layer z0 + k takes
     the sum over source layers l of oracle.periodic.FilmWindow at the layer
     offset z0 + k - l; output (3, nwz, nwy, nwx) like WindowSum.  With a
-    sign, the eddy-current sum sign * S x v instead (FilmSWindow)."""
+    sign, the eddy-current sum sign * S x v instead (FilmSWindow); with
+    potential, the scalar potential (one channel, FilmPotWindow)."""
 
-    def __init__(self, desc, box, sign=None):
-        from .periodic import FilmWindow, FilmSWindow
+    def __init__(self, desc, box, sign=None, potential=False):
+        from .periodic import FilmWindow, FilmSWindow, FilmPotWindow
         x0, nwx, y0, nwy, z0, nwz = box
         self.nwz, self.z0, self.nz = nwz, z0, desc.nz
 
         def window(dz):
+            if potential:
+                return FilmPotWindow(desc, x0, nwx, y0, nwy, dz)
             if sign is None:
                 return FilmWindow(desc, x0, nwx, y0, nwy, dz)
             return FilmSWindow(desc, x0, nwx, y0, nwy, dz, sign)
