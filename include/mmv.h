@@ -96,10 +96,12 @@ typedef struct {
   int fft_lx, fft_ly, fft_lz; /* FFT lengths; 0 = smallest admissible       */
   int pbc;              /* periodic in-plane axes (Sec. III.A end, Sec. IV.B):
                            bit 0 = x, bit 1 = y; 0 = open.  Film meshes
-                           (nz == 1) in the direct mode without eddy
-                           currents, or two thicker films in the same mode
-                           (with eddy currents: ny even for a periodic
-                           y).  Along a
+                           (nz == 1) in every cross mode without eddy
+                           currents (the scalar potential's window rows
+                           and columns past the period are those of the
+                           other side), or two thicker films in the
+                           direct mode (with eddy currents: ny even for a
+                           periodic y).  Along a
                            periodic axis the transform length is the period (nx even and {2,3,5,7}-smooth,
                            ny {2,3,5,7}-smooth), the kernel of a displacement
                            is summed over its minimum image and pbc_images

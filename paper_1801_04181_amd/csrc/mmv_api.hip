@@ -243,7 +243,11 @@ int validate(const mmv_mesh_desc* d) {
     if (d->sigma > 0.0 && (d->pbc & 2) && d->ny % 2)
       return fail(MMV_EINVAL, "pbc: eddy currents with a periodic y need ny even (red-black colouring over the "
                               "period)");
-    if (d->cross_mode != 0) return fail(MMV_EINVAL, "pbc: periodic boundaries run in the direct mode (cross_mode 0)");
+    // one-layer films take every interpolant: the y pass writes the window
+    // rows past the period as the rows of the other side (its output row is
+    // taken modulo Ly = ny) and the row kernel's windows wrap modulo Lx = nx
+    if (d->cross_mode != 0 && d->nz != 1)
+      return fail(MMV_EINVAL, "pbc: periodic thick films run in the direct mode (cross_mode 0)");
     if ((d->pbc & 1) && (d->nx % 2 || !smooth2357(d->nx)))
       return fail(MMV_EINVAL, "pbc: a periodic x needs nx even and {2,3,5,7}-smooth (the transform length)");
     if ((d->pbc & 2) && !smooth2357(d->ny))

@@ -59,7 +59,6 @@ def test_init_rejects_bad_descriptors(field, value, msg):
     (dict(pbc=4), "pbc must be"), (dict(pbc=1, pbc_images=-1), "pbc_images"),
     (dict(pbc=1, pbc_images=1025), "pbc_images"), (dict(pbc=1, nx=31), "nx even"),
     (dict(pbc=2, ny=11), "ny {2,3,5,7}"), (dict(pbc=1, fft_lx=72), "period"),
-    (dict(pbc=1, gap_cells=3, cross_mode=1), "direct mode"),
 ])
 def test_periodic_descriptor_validation(change, msg):
     c = mmv.to_desc(get_config("tiny")["desc"])
