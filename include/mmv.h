@@ -96,12 +96,11 @@ typedef struct {
   int fft_lx, fft_ly, fft_lz; /* FFT lengths; 0 = smallest admissible       */
   int pbc;              /* periodic in-plane axes (Sec. III.A end, Sec. IV.B):
                            bit 0 = x, bit 1 = y; 0 = open.  Film meshes
-                           (nz == 1) in every cross mode without eddy
-                           currents (the scalar potential's window rows
-                           and columns past the period are those of the
-                           other side), or two thicker films in the
-                           direct mode (with eddy currents: ny even for a
-                           periodic y).  Along a
+                           (nz == 1) without eddy currents, or two
+                           thicker films (with eddy currents: ny even for
+                           a periodic y), in every cross mode (the scalar
+                           potential's window rows and columns past the
+                           period are those of the other side).  Along a
                            periodic axis the transform length is the period (nx even and {2,3,5,7}-smooth,
                            ny {2,3,5,7}-smooth), the kernel of a displacement
                            is summed over its minimum image and pbc_images
@@ -143,8 +142,8 @@ typedef struct {
  * Two films more than one cell thick (n_films 2, nz > 1; Sec. II.A end,
  * III.B, IV.C-D): the thick-film path.  Every cross mode (the scalar
  * potential's windows reach three rows and layers past the films, Ly >=
- * 2 (ny + 3)).  Periodic in-plane boundaries (pbc) in the direct mode
- * (cross_mode 0): the layer kernels summed over the images, the transform
+ * 2 (ny + 3)).  Periodic in-plane boundaries (pbc) in every cross mode:
+ * the layer kernels (and the potential's S) summed over the images, the transform
  * along a periodic axis over the period, windows unshifted along it (the
  * sampler wraps their columns and rows modulo the period) and exchange
  * wrapping; with eddy currents the S sums take the image-summed kernel and

@@ -243,11 +243,6 @@ int validate(const mmv_mesh_desc* d) {
     if (d->sigma > 0.0 && (d->pbc & 2) && d->ny % 2)
       return fail(MMV_EINVAL, "pbc: eddy currents with a periodic y need ny even (red-black colouring over the "
                               "period)");
-    // one-layer films take every interpolant: the y pass writes the window
-    // rows past the period as the rows of the other side (its output row is
-    // taken modulo Ly = ny) and the row kernel's windows wrap modulo Lx = nx
-    if (d->cross_mode != 0 && d->nz != 1)
-      return fail(MMV_EINVAL, "pbc: periodic thick films run in the direct mode (cross_mode 0)");
     if ((d->pbc & 1) && (d->nx % 2 || !smooth2357(d->nx)))
       return fail(MMV_EINVAL, "pbc: a periodic x needs nx even and {2,3,5,7}-smooth (the transform length)");
     if ((d->pbc & 2) && !smooth2357(d->ny))
@@ -962,12 +957,12 @@ int init_slab(mmv_mesh* h) {
   const long long P = (long long)plane;
   // potential mode: the films' own fields (the tensor table's first two
   // groups) and the potentials of the other film on the windows
-  h->tab_p.n = 2;
-  h->tab_p.g[0] = SlabGroup{0, zs - 3, nz + 6, 1, -hl, -3, 6LL * nz * P};
-  h->tab_p.g[1] = SlabGroup{1, -zs - 2, nz + 4, -1, -hl, -2, (6LL * nz + nz + 6) * P};
   // a periodic x keeps the windows' period unshifted (columns from 0; the
   // sampling reads them modulo nx), a periodic y the rows of the period
   const bool px = (d.pbc & 1) != 0, py = (d.pbc & 2) != 0;
+  h->tab_p.n = 2;
+  h->tab_p.g[0] = SlabGroup{0, zs - 3, nz + 6, px ? 0 : 1, px ? 0 : -hl, py ? 0 : -3, 6LL * nz * P};
+  h->tab_p.g[1] = SlabGroup{1, -zs - 2, nz + 4, px ? 0 : -1, px ? 0 : -hl, py ? 0 : -2, (6LL * nz + nz + 6) * P};
   h->tab_t.n = 4;
   h->tab_t.g[0] = SlabGroup{0, 0, nz, 0, 0, 0, 0};
   h->tab_t.g[1] = SlabGroup{1, 0, nz, 0, 0, 0, 3LL * nz * P};
@@ -1033,30 +1028,38 @@ int slab_fields(mmv_mesh* h, const T* m, bool self_on, bool cross_on, bool zee_o
     HIPCHK(launch_slab_pot<T>(h->specM, h->specP, (const T*)h->kern_s, h->tab_p, nz, h->sD, h->Lx, h->Ly, Kx,
                               h->d.Ms, h->rigid, h->st));
     const int L1 = nz + 6, R1 = ny + 6, L2 = nz + 4, R2 = ny + 4;
-    const size_t o1 = 6 * (size_t)nz * ny, o2 = o1 + (size_t)L1 * R1;
+    // periodic axes: the windows hold the period (WC columns, W1 / W2 rows
+    // per layer); the sampler reads window rows -3..ny+2 (-2..ny+1) and the
+    // columns from +-s_int - halo modulo the period, the copy of the
+    // potential from the other side
+    const bool px = (h->d.pbc & 1) != 0, py = (h->d.pbc & 2) != 0;
+    const int WC = px ? nx : M, W1 = py ? ny : R1, W2 = py ? ny : R2, hl = h->d.halo;
+    const size_t o1 = 6 * (size_t)nz * ny, o2 = o1 + (size_t)L1 * W1;
     HIPCHK(launch_fft_axis<T>(h->specP, pI, 6 * nz, Kx, 0, h->Ly, (long long)P, ny, (long long)ny * Kx, h->py, h->twy,
                               true, h->st));
-    HIPCHK(launch_fft_axis<T>((char*)h->specP + cs * 6 * nz * P, pI + cs * o1 * Kx, L1, Kx, 0, h->Ly, (long long)P, R1,
-                              (long long)R1 * Kx, h->py, h->twy, true, h->st));
+    HIPCHK(launch_fft_axis<T>((char*)h->specP + cs * 6 * nz * P, pI + cs * o1 * Kx, L1, Kx, 0, h->Ly, (long long)P, W1,
+                              (long long)W1 * Kx, h->py, h->twy, true, h->st));
     HIPCHK(launch_fft_axis<T>((char*)h->specP + cs * (6 * nz + L1) * P, pI + cs * o2 * Kx, L2, Kx, 0, h->Ly,
-                              (long long)P, R2, (long long)R2 * Kx, h->py, h->twy, true, h->st));
+                              (long long)P, W2, (long long)W2 * Kx, h->py, h->twy, true, h->st));
     HIPCHK(launch_row_inv<T>(pI, (T*)h->hd, 6 * nz * ny, R, nx, h->N2x, Kx, h->px, h->twx, h->twp, h->st));
-    HIPCHK(launch_row_inv<T>(pI + cs * o1 * Kx, (T*)h->pot_w[0], L1 * R1, R, M, h->N2x, Kx, h->px, h->twx, h->twp,
+    HIPCHK(launch_row_inv<T>(pI + cs * o1 * Kx, (T*)h->pot_w[0], L1 * W1, R, WC, h->N2x, Kx, h->px, h->twx, h->twp,
                              h->st));
-    HIPCHK(launch_row_inv<T>(pI + cs * o2 * Kx, (T*)h->pot_w[1], L2 * R2, R, M, h->N2x, Kx, h->px, h->twx, h->twp,
+    HIPCHK(launch_row_inv<T>(pI + cs * o2 * Kx, (T*)h->pot_w[1], L2 * W2, R, WC, h->N2x, Kx, h->px, h->twx, h->twp,
                              h->st));
     if (!self_on) HIPCHK(hipMemsetAsync(h->hd, 0, 2 * F * sizeof(T), h->st));
+    const SlabRows r1{1, L1 * R1, L1 * W1, R1, W1, py ? -3 : 0, M, WC, px ? 1 : 0, px ? -hl : 0, px ? nx : 0};
+    const SlabRows r2{1, L2 * R2, L2 * W2, R2, W2, py ? -2 : 0, M, WC, px ? -1 : 0, px ? -hl : 0, px ? nx : 0};
     // slider side: samples at i = -3 .. nx + 2, then H on the force stencil
     // (stencil point (l', j', i') at window layer l' + 2, row j' + 2, sample i' + 2)
-    HIPCHK(launch_slab_sample<T>((const T*)h->pot_w[0], slab_rows(1, L1 * R1, M), h->d.halo, (T*)h->pot_s[0], -3,
-                                 nx + 6, 1, 0, 0, idx, h->rigid, h->st));
+    HIPCHK(launch_slab_sample<T>((const T*)h->pot_w[0], r1, h->d.halo, (T*)h->pot_s[0], -3, nx + 6, 1, 0, 0, idx,
+                                 h->rigid, h->st));
     HIPCHK(launch_slab_potgrad<T>((const T*)h->pot_s[0], R1, nx + 6, 2, nz + 2, ny + 2, nx + 2, (T*)h->stencil, 0,
                                   h->d.dx, h->d.dy, h->d.dz, h->st));
     if (cross_on) {
       // base side: samples at i = -2 .. nx + 1; base cell (k, j, i) at window
       // layer k + 2, row j + 2, sample i + 2
-      HIPCHK(launch_slab_sample<T>((const T*)h->pot_w[1], slab_rows(1, L2 * R2, M), h->d.halo, (T*)h->pot_s[1], -2,
-                                   nx + 4, -1, 0, 0, idx, h->rigid, h->st));
+      HIPCHK(launch_slab_sample<T>((const T*)h->pot_w[1], r2, h->d.halo, (T*)h->pot_s[1], -2, nx + 4, -1, 0, 0, idx,
+                                   h->rigid, h->st));
       HIPCHK(launch_slab_potgrad<T>((const T*)h->pot_s[1], R2, nx + 4, 2, nz, ny, nx, (T*)h->hd, 1, h->d.dx, h->d.dy,
                                     h->d.dz, h->st));
     }

@@ -341,6 +341,48 @@ def test_periodic_thick_films_terms_and_force(prec, pbc, x_cells):
     print("  ", {k: f"{v:.2e}" for k, v in out.items()}, flush=True)
 
 
+@pytest.mark.parametrize("prec,pbc,x_cells,cross_mode", [(64, 3, 1.37, 1), (32, 3, 1.37, 1), (64, 1, 9.6, 1),
+                                                         (32, 2, -2.4, 1), (64, 2, 0.0, 1), (64, 3, -1.7, 2),
+                                                         (32, 1, 17.3, 2)])
+def test_periodic_thick_films_potential_and_linear(prec, pbc, x_cells, cross_mode):
+    """Periodic thick films in the scalar-potential mode (gap 3: the
+    potential's window rows and layers reach three past the films, its rows
+    and columns past the period are the other side's) and with the linear
+    interpolant; every term of both films and the force."""
+    print(f"slab periodic p{prec} pbc={pbc} x={x_cells} mode={cross_mode}", flush=True)
+    d, m = films(16, 10, 3 if cross_mode == 1 else 2, prec, gap=3 if cross_mode == 1 else 1, cross_mode=cross_mode,
+                 seed=pbc + 50, pbc=pbc, pbc_images=1)
+    mesh, s = pair(d, m, Drive(mode=0, x0=x_cells * d.dx))
+    out = check_terms(mesh, s, prec)
+    mesh.close()
+    print("  ", {k: f"{v:.2e}" for k, v in out.items()}, flush=True)
+
+
+@pytest.mark.parametrize("prec", [32, 64])
+def test_periodic_thick_potential_steps_with_eddy_currents(prec):
+    """Periodic thick films (pbc = 3) in the potential mode with eddy
+    currents in both: RK4 steps with the slider crossing a cell boundary."""
+    import torch
+    d, m = films(16, 10, 3, prec, gap=3, travel=4, sigma=1e6, cross_mode=1, state="stripes", seed=57,
+                 sor_sweeps=12, pbc=3, pbc_images=1)
+    drv = Drive(mode=1, v_d=1500.0, x0=0.91 * d.dx)
+    print(f"slab periodic potential steps p{prec}", flush=True)
+    mesh, s = pair(d, m, drv)
+    dt, n = 1e-13, 4
+    mesh.step(dt, n)
+    torch.cuda.synchronize()
+    s.run(dt, n)
+    assert s.s_int == 1, "the slider crosses a cell boundary"
+    out = {}
+    for f in range(2):
+        out[f"m{f}"] = float(np.abs(mesh.get_m(f).cpu().numpy() - s.m[f]).max())
+        assert out[f"m{f}"] < TOL_M[prec], out
+        out[f"eddy{f}"] = rel(mesh.eval_heff(f, 32).cpu().numpy(), s.eddy.H[f])
+        assert out[f"eddy{f}"] <= TOL_EDDY[prec], out
+    mesh.close()
+    print("  ", out, flush=True)
+
+
 @pytest.mark.parametrize("prec", [32, 64])
 def test_periodic_thick_films_steps(prec):
     """RK4 steps of periodic thick films (pbc = 3) with a spring-driven slider
