@@ -335,6 +335,24 @@ int profile_repeat(mmv_handle h, int kernel, int reps, double* avg_ms);
 /* Chosen FFT lengths (diagnostics). */
 int get_fft_lengths(mmv_handle h, int* lx, int* ly, int* lz);
 
+/* Transform-length autotuner (Sec. III.A: the convolutions run by FFT over
+ * padded lengths, any admissible length giving the same result up to
+ * rounding).  For each open in-plane axis whose length d leaves at 0, takes
+ * the ncand smallest admissible {2,3,5,7}-smooth lengths (Lx even, from the
+ * one init_mesh picks by itself), builds a mesh from d with each pair on
+ * hip_stream (its own initial state m = +z; two films get a 1 m/s velocity
+ * drive), times nsteps llg_step steps of size dt after one untimed step
+ * with HIP events, and returns the fastest pair in *fft_lx, *fft_ly and,
+ * if not NULL, its time per step [ms] in *ms_per_step.  A periodic axis or
+ * a length d fixes keeps that length; pairs init_mesh refuses are skipped.
+ * Set the result into d's fft_lx / fft_ly for the mesh that is kept.
+ * MMV_EINVAL for NULL d or outputs, ncand outside [1, 8], nsteps outside
+ * [1, 10000] or dt not finite and > 0; init_mesh's error for d itself;
+ * MMV_EHIP if no pair could be timed.  Synchronous; allocates and frees
+ * the candidate meshes.                                                   */
+int tune_fft_lengths(const mmv_mesh_desc* d, double dt, int nsteps, int ncand, void* hip_stream, int* fft_lx,
+                     int* fft_ly, double* ms_per_step);
+
 /* ------------------------------------------------------------------------
  * Batches: many independent two-film meshes of uneven sizes advanced
  * together, one launch per pass covering every instance (per-instance

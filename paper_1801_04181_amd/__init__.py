@@ -12,7 +12,7 @@ import os
 __all__ = ["MMVError", "lib_path", "load", "MeshDesc", "DriveDesc", "init_mesh",
            "set_m", "get_m", "set_offset", "set_drive", "set_hext_field", "eval_heff", "llg_step", "llg_run_dp",
            "spline3_prefilter", "spline3_gather", "eddy_residual",
-           "stray_force", "stray_force_noalloc", "div_curl", "get_state", "get_fft_lengths", "destroy_mesh",
+           "stray_force", "stray_force_noalloc", "div_curl", "get_state", "get_fft_lengths", "tune_fft_lengths", "destroy_mesh",
            "profile_begin", "profile_end", "profile_repeat", "init_batch", "batch_instance", "batch_step",
            "batch_tuning", "set_tune_cache", "destroy_batch", "Batch", "batch_sur_attach", "batch_sur_status", "SurDesc", "sur_create", "sur_param_count",
            "sur_param_offsets", "sur_set_params", "sur_get_params", "sur_forward", "sur_gradient",
@@ -29,7 +29,7 @@ ERRORS = {-1: "MMV_EINVAL", -2: "MMV_ENOMEM", -3: "MMV_EHIP", -4: "MMV_ERANGE",
 EXPORTS = ("init_mesh", "set_m", "get_m", "set_offset", "set_drive", "set_hext_field", "eval_heff",
            "spline3_prefilter", "spline3_gather", "eddy_residual",
            "llg_step", "llg_run_dp", "stray_force", "stray_force_noalloc", "div_curl", "get_state", "profile_begin", "profile_end",
-           "get_fft_lengths", "profile_repeat", "init_batch", "batch_instance", "batch_step", "batch_tuning",
+           "get_fft_lengths", "tune_fft_lengths", "profile_repeat", "init_batch", "batch_instance", "batch_step", "batch_tuning",
            "set_tune_cache", "destroy_batch", "destroy_mesh", "sur_create", "sur_param_count", "sur_param_offsets",
            "sur_set_params", "sur_get_params", "sur_forward", "sur_gradient", "sur_train_step",
            "sur_gemm_bf16", "sur_destroy", "sur_attach", "sur_status", "batch_sur_attach", "batch_sur_status",
@@ -101,6 +101,8 @@ def load():
         lib.div_curl.argtypes = [vp, pd, pd]
         lib.get_state.argtypes = [vp, pd, pd, pd, ctypes.POINTER(ctypes.c_long)]
         lib.get_fft_lengths.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(i)]
+        lib.tune_fft_lengths.argtypes = [ctypes.POINTER(MeshDesc), d, i, i, vp, ctypes.POINTER(i), ctypes.POINTER(i),
+                                         pd]
         lib.destroy_mesh.argtypes = [vp]
         lib.profile_begin.argtypes = [vp, i]
         lib.init_batch.argtypes = [ctypes.POINTER(MeshDesc), i, vp, i, ctypes.POINTER(vp)]
@@ -286,6 +288,16 @@ def get_state(h):
     n = ctypes.c_long()
     _check(load().get_state(h, ctypes.byref(t), ctypes.byref(x), ctypes.byref(v), ctypes.byref(n)))
     return dict(t=t.value, x=x.value, v=v.value, step=n.value)
+
+
+def tune_fft_lengths(desc, dt, nsteps=20, ncand=3, stream=None):
+    """tune_fft_lengths of the C ABI: (fft_lx, fft_ly, ms per step) of the
+    fastest candidate pair for the mesh `desc` describes."""
+    c = to_desc(desc)
+    a, b, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _check(load().tune_fft_lengths(ctypes.byref(c), float(dt), int(nsteps), int(ncand), _stream(stream),
+                                   ctypes.byref(a), ctypes.byref(b), ctypes.byref(ms)))
+    return a.value, b.value, ms.value
 
 
 def get_fft_lengths(h):

@@ -2990,6 +2990,67 @@ int get_state(mmv_handle h, double* t, double* x_s, double* v_s, long* step) {
   return report_flags(h, r);
 }
 
+int tune_fft_lengths(const mmv_mesh_desc* d, double dt, int nsteps, int ncand, void* hip_stream, int* fft_lx,
+                     int* fft_ly, double* ms_per_step) {
+  if (!d || !fft_lx || !fft_ly) return fail(MMV_EINVAL, "NULL argument");
+  if (ncand < 1 || ncand > 8) return fail(MMV_EINVAL, "ncand must be in [1, 8]");
+  if (nsteps < 1 || nsteps > 10000) return fail(MMV_EINVAL, "nsteps must be in [1, 10000]");
+  if (!(dt > 0) || !isfinite(dt)) return fail(MMV_EINVAL, "dt must be finite and > 0");
+  int rc;
+  // the smallest admissible lengths: those init_mesh picks by itself
+  mmv_handle h0 = nullptr;
+  if ((rc = init_mesh(d, hip_stream, &h0))) return rc;
+  const int lx0 = h0->Lx, ly0 = h0->Ly;
+  destroy_mesh(h0);
+  std::vector<int> cx{lx0}, cy{ly0};
+  if (!d->fft_lx && !(d->pbc & 1))
+    while ((int)cx.size() < ncand) cx.push_back(next_smooth(cx.back() + 1, true));
+  if (!d->fft_ly && !(d->pbc & 2))
+    while ((int)cy.size() < ncand) cy.push_back(next_smooth(cy.back() + 1, false));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double best = -1.0;
+  int bx = lx0, by = ly0;
+  rc = MMV_OK;
+  for (int lx : cx)
+    for (int ly : cy) {
+      mmv_mesh_desc c = *d;
+      c.fft_lx = lx;
+      c.fft_ly = ly;
+      mmv_handle h = nullptr;
+      if (init_mesh(&c, hip_stream, &h)) continue;  // e.g. beyond the LDS limits
+      if (h->nfilm == 2) {
+        // a moving slider, so that the force and re-seat work is timed
+        mmv_drive v{};
+        v.mode = MMV_DRIVE_VELOCITY;
+        v.v_d = 1.0;
+        set_drive(h, &v);
+      }
+      float ms = 0.f;
+      if ((rc = llg_step(h, dt, 1)) == MMV_OK && hipEventRecord(e0, h->st) == hipSuccess &&
+          (rc = llg_step(h, dt, nsteps)) == MMV_OK && hipEventRecord(e1, h->st) == hipSuccess &&
+          hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) {
+        const double per = ms / nsteps;
+        if (best < 0 || per < best) {
+          best = per;
+          bx = lx;
+          by = ly;
+        }
+      }
+      destroy_mesh(h);
+      if (rc) break;
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  if (best < 0) return fail(MMV_EHIP, "no candidate transform length could be timed");
+  *fft_lx = bx;
+  *fft_ly = by;
+  if (ms_per_step) *ms_per_step = best;
+  return MMV_OK;
+}
+
 int get_fft_lengths(mmv_handle h, int* lx, int* ly, int* lz) {
   int rc = check_handle(h);
   if (rc) return rc;

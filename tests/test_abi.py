@@ -238,3 +238,14 @@ def test_spline3_gather_argument_checks():
     assert lib.spline3_gather(32, None, 2, 2, 2, None, 3, None, None) == -1
     assert "NULL" in mmv.last_error()
     assert lib.spline3_gather(32, None, 2, 2, 2, None, 0, None, None) == 0   # empty: nothing launched
+
+
+def test_tune_fft_lengths_checks_arguments_before_any_device_call():
+    d = get_config("tiny")["desc"]
+    for kw, msg in ((dict(ncand=0), "ncand"), (dict(ncand=9), "ncand"), (dict(nsteps=0), "nsteps"),
+                    (dict(dt=-1.0), "dt")):
+        args = dict(dt=1e-13, nsteps=5, ncand=3)
+        args.update(kw)
+        with pytest.raises(mmv.MMVError) as e:
+            mmv.tune_fft_lengths(d, **args)
+        assert e.value.code == -1 and msg in str(e.value), (kw, str(e.value))
